@@ -1,0 +1,105 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module holds no PageRank arithmetic: it only produces inputs (edge
+lists of small hand-made graphs, personalised-PageRank seed sets, random
+start vectors, random network weights).  Both the CPU oracle and the HIP
+path receive exactly the arrays returned here.  The R-MAT edge lists are not
+made here: each side implements the counter-based R-MAT generator from its
+published definition, and the two are compared bit for bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Workload sizes of the benchmark graphs (R-MAT, edge factor 16, the seed
+# equals the scale).
+RMAT_EDGEFACTOR = 16
+DAMPING = 0.85
+
+
+def cycle(n: int):
+    """Directed cycle 0->1->...->n-1->0."""
+    src = np.arange(n, dtype=np.uint32)
+    dst = ((np.arange(n) + 1) % n).astype(np.uint32)
+    return n, src, dst
+
+
+def complete(n: int):
+    """Complete digraph without self-loops."""
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    keep = i != j
+    return n, i[keep].astype(np.uint32), j[keep].astype(np.uint32)
+
+
+def empty(n: int):
+    """n vertices, no edges."""
+    return n, np.zeros(0, np.uint32), np.zeros(0, np.uint32)
+
+
+def star_in(m: int):
+    """Leaves 1..m each point to the centre 0."""
+    leaves = np.arange(1, m + 1, dtype=np.uint32)
+    return m + 1, leaves, np.zeros(m, np.uint32)
+
+
+def star_out(m: int):
+    """Centre 0 points to each leaf 1..m."""
+    leaves = np.arange(1, m + 1, dtype=np.uint32)
+    return m + 1, np.zeros(m, np.uint32), leaves
+
+
+def star_both(m: int):
+    """Centre 0 and every leaf linked in both directions."""
+    leaves = np.arange(1, m + 1, dtype=np.uint32)
+    z = np.zeros(m, np.uint32)
+    return m + 1, np.concatenate([z, leaves]), np.concatenate([leaves, z])
+
+
+def path2():
+    """Two vertices, one edge 0->1."""
+    return 2, np.array([0], np.uint32), np.array([1], np.uint32)
+
+
+def random_edges(n: int, nedges: int, seed: int, self_loops: bool = True):
+    """Uniform random directed edges (duplicates and, optionally, self-loops
+    included) for brute-force checks of the CSR build."""
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, nedges, dtype=np.uint32)
+    dst = rng.integers(0, n, nedges, dtype=np.uint32)
+    if not self_loops:
+        keep = src != dst
+        src, dst = src[keep], dst[keep]
+    return n, src, dst
+
+
+def ppr_seed_sets(n: int, count: int, seed: int = 7, max_size: int = 16):
+    """``count`` seed sets; each has a size drawn uniformly from 1..max_size
+    and that many distinct vertices drawn uniformly from [0, n)."""
+    rng = np.random.default_rng(seed)
+    sets = []
+    for _ in range(count):
+        k = int(rng.integers(1, max_size + 1))
+        sets.append(np.sort(rng.choice(n, size=k, replace=False)).astype(np.int32))
+    return sets
+
+
+def random_distribution(n: int, seed: int) -> np.ndarray:
+    """A positive vector summing to one (a non-uniform start vector)."""
+    rng = np.random.default_rng(seed)
+    x = rng.random(n) + 0.05
+    return x / x.sum()
+
+
+def random_vector(n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return lo + (hi - lo) * rng.random(n)
+
+
+def many_graph_specs(count: int = 256, base_seed: int = 3000, smin: int = 10,
+                     smax: int = 16):
+    """(scale, seed) of each graph of the many-small-graphs workload: graph
+    i has seed base_seed + i and a scale drawn uniformly from smin..smax by a
+    numpy generator seeded with base_seed."""
+    rng = np.random.default_rng(base_seed)
+    scales = rng.integers(smin, smax + 1, count)
+    return [(int(scales[i]), base_seed + i) for i in range(count)]

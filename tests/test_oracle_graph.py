@@ -1,0 +1,119 @@
+"""Pins of the oracle's graph-input side: the counter-based RNG, the R-MAT
+generator and the CSR / out-degree / transpose construction.
+
+None of these checks reuses oracle code: the RNG is pinned by a published
+test vector, R-MAT by the quadrant probabilities it must reproduce, and the
+CSR build by brute-force set semantics in plain Python.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synthetic
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_pairs(name):
+    out = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split()
+                out.append((int(k), int(v)))
+    return out
+
+
+def test_splitmix64_published_vector(oracle_mod):
+    for k, v in _golden_pairs("splitmix64_seed1234567.txt"):
+        assert oracle_mod.splitmix64(1234567, k) == v
+
+
+@pytest.mark.parametrize("scale,seed", [(10, 10), (12, 99)])
+def test_rmat_quadrant_frequencies(oracle_mod, scale, seed):
+    """Each level picks quadrant a/b/c/d with probability .57/.19/.19/.05:
+    b sets only the destination bit, c only the source bit, d both."""
+    src, dst = oracle_mod.rmat_edges(scale, 16, seed)
+    assert len(src) == 16 << scale
+    assert src.max() < (1 << scale) and dst.max() < (1 << scale)
+    total = np.zeros(4)
+    for lev in range(scale):
+        sh = scale - 1 - lev
+        sb = (src >> sh) & 1
+        db = (dst >> sh) & 1
+        q = np.bincount(2 * sb.astype(np.int64) + db, minlength=4)
+        total += q
+        p = q / len(src)
+        sigma = np.sqrt(0.25 / len(src))
+        for got, want in zip(p, (0.57, 0.19, 0.19, 0.05)):
+            assert abs(got - want) < 6 * sigma
+    p = total / total.sum()
+    sigma = np.sqrt(0.25 / total.sum())
+    for got, want in zip(p, (0.57, 0.19, 0.19, 0.05)):
+        assert abs(got - want) < 6 * sigma
+
+
+def test_rmat_deterministic_and_seeded(oracle_mod):
+    a = oracle_mod.rmat_edges(8, 16, 5)
+    b = oracle_mod.rmat_edges(8, 16, 5)
+    c = oracle_mod.rmat_edges(8, 16, 6)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert not np.array_equal(a[0], c[0])
+
+
+def _brute_csr(n, src, dst, drop_self):
+    rows = [set() for _ in range(n)]
+    for s, d in zip(src.tolist(), dst.tolist()):
+        if drop_self and s == d:
+            continue
+        rows[s].add(d)
+    rowptr = [0]
+    col = []
+    for r in rows:
+        col.extend(sorted(r))
+        rowptr.append(len(col))
+    return np.array(rowptr, np.int32), np.array(col, np.int32)
+
+
+@pytest.mark.parametrize("n,ne,seed", [(1, 5, 1), (7, 40, 2), (33, 300, 3), (200, 5000, 4)])
+@pytest.mark.parametrize("drop_self", [True, False])
+def test_build_csr_matches_set_semantics(oracle_mod, n, ne, seed, drop_self):
+    n, src, dst = synthetic.random_edges(n, ne, seed)
+    rp, col = oracle_mod.build_csr(n, src, dst, drop_self)
+    brp, bcol = _brute_csr(n, src, dst, drop_self)
+    assert np.array_equal(rp, brp)
+    assert np.array_equal(col, bcol)
+
+
+def test_build_csr_empty_and_range(oracle_mod):
+    rp, col = oracle_mod.build_csr(5, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    assert np.array_equal(rp, np.zeros(6, np.int32)) and len(col) == 0
+    with pytest.raises(ValueError):
+        oracle_mod.build_csr(3, np.array([0], np.uint32), np.array([3], np.uint32))
+
+
+def test_transpose_brute_force_and_involution(oracle_mod):
+    n, src, dst = synthetic.random_edges(150, 3000, 11)
+    rp, col = oracle_mod.build_csr(n, src, dst, True)
+    rpT, colT = oracle_mod.transpose(n, n, rp, col)
+    # brute force: row j of the transpose = sorted sources i with i -> j
+    brpT, bcolT = _brute_csr(n, dst, src, True)
+    assert np.array_equal(rpT, brpT) and np.array_equal(colT, bcolT)
+    rp2, col2 = oracle_mod.transpose(n, n, rpT, colT)
+    assert np.array_equal(rp2, rp) and np.array_equal(col2, col)
+
+
+def test_rmat_graph_invariants(oracle_mod):
+    g = oracle_mod.rmat_graph(11)
+    assert g.n == 2048
+    assert int(g.outdeg.sum()) == g.m == int(g.indeg.sum()) == len(g.colT)
+    assert np.all(np.diff(g.rowptr) >= 0) and np.all(np.diff(g.rowptrT) >= 0)
+    for rp, col in ((g.rowptr, g.col), (g.rowptrT, g.colT)):
+        for i in range(g.n):
+            seg = col[rp[i]:rp[i + 1]]
+            assert np.all(np.diff(seg) > 0)          # ascending, no duplicates
+            assert not np.any(seg == i)              # no self-loops
+    # dedup really removed something at this density
+    assert g.m < 16 * g.n
