@@ -1,0 +1,217 @@
+"""Benchmark of the fused PageRank path on one MI355X.
+
+A step is one full PageRank solve (FP32 ranks, FP64 residual and dangling
+sums, uniform dangling redistribution, damping 0.85, L1 tolerance 1e-6) on
+an R-MAT scale-22 graph (edge factor 16, a/b/c/d = .57/.19/.19/.05, seed
+22, self-loops and duplicates removed) that is already resident in HBM,
+through GrM_pagerank in nonblocking mode, i.e. one fused kernel per
+iteration.  value = GTEPS = edges x iterations / solve time.
+
+Also reported on the same JSON line: the unfused (blocking) solve, the FP64
+fused solve and the FP32-vs-FP64 error, the roofline of the fused kernel
+(algorithmic bytes per launch over its event-timed average duration), a
+streaming-copy probe, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DAMPING = 0.85
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fused_bytes_per_pass(n: int, m: int, b: int) -> int:
+    """Algorithmic bytes of one fused pass: row pointers, column indices,
+    the gathered operand (compulsory n*b), x_old, d, and the two outputs
+    (new ranks and their pre-scaled copy)."""
+    return 4 * (n + 1) + 4 * m + 5 * n * b
+
+
+def blocking_bytes_per_pass(n: int, m: int, b: int) -> int:
+    """Unfused: mult (3n) + mxv (rowptr, col, gather n, write n) + apply (2n)
+    + absdiff (3n) + reduce (n) + masked reduce (2n)."""
+    return 4 * (n + 1) + 4 * m + 13 * n * b
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--check-every", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="time only the headline fused solve (for profiling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2509_14211_amd import api, grb
+
+    torch.cuda.init()
+    dev = torch.cuda.get_device_properties(0)
+    log("device:", dev.name, "CUs:", dev.multi_processor_count)
+    stream = torch.cuda.current_stream()
+
+    out = {}
+    with api.Context(grb.GrB_NONBLOCKING):
+        t0 = time.perf_counter()
+        g = api.rmat_graph(args.scale)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        n, m = g.n, g.m
+        log("graph: scale %d n %d m %d (setup %.2fs)" % (args.scale, n, m, setup_s))
+
+        def solve(dtype, check_every=args.check_every):
+            return api.pagerank(g, dtype, DAMPING, args.tol, 1000, grb.GrM_DANGLING_UNIFORM,
+                                None, check_every)
+
+        def timed(dtype, steps, warmup):
+            for _ in range(warmup):
+                solve(dtype)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            iters = []
+            e0.record(stream)
+            x = None
+            for _ in range(steps):
+                x, it, res = solve(dtype)
+                iters.append(it)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            return x, iters, ms, res
+
+        # ---- headline: fused FP32
+        grb.GrM_set_mode(grb.GrB_NONBLOCKING)
+        x32, iters32, ms32, res32 = timed(torch.float32, args.steps, args.warmup)
+        it32 = iters32[-1]
+        gteps = m * it32 / (ms32 * 1e-3) / 1e9
+        log("fused fp32: %d iterations, %.3f ms/solve, %.1f GTEPS" % (it32, ms32, gteps))
+
+        # ---- roofline of the fused pass (HIP events around every launch)
+        grb.GrM_timing_enable(True)
+        grb.GrM_timing_read()
+        for _ in range(3):
+            solve(torch.float32)
+        kern_ms, launches = grb.GrM_timing_read()
+        grb.GrM_timing_enable(False)
+        avg_us = kern_ms * 1e3 / max(launches, 1)
+        bpp = fused_bytes_per_pass(n, m, 4)
+        achieved = bpp / (avg_us * 1e-6) / 1e9
+        log("fused pass: %d launches, avg %.2f us, %.1f GB/s algorithmic" % (launches, avg_us, achieved))
+        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": None, "kernel": "fused_pr_kernel<float>",
+                           "bytes_per_launch": bpp, "avg_launch_us": round(avg_us, 3)}
+
+        if not args.skip_extras:
+            # ---- unfused (blocking) FP32
+            grb.GrM_set_mode(grb.GrB_BLOCKING)
+            xb, itersb, msb, _ = timed(torch.float32, max(2, args.steps // 2), 1)
+            grb.GrM_set_mode(grb.GrB_NONBLOCKING)
+            gteps_b = m * itersb[-1] / (msb * 1e-3) / 1e9
+            log("blocking fp32: %d iterations, %.3f ms/solve, %.1f GTEPS" % (itersb[-1], msb, gteps_b))
+            # ---- fused FP64 and the FP32 error against it
+            x64, iters64, ms64, _ = timed(torch.float64, 2, 1)
+            gteps64 = m * iters64[-1] / (ms64 * 1e-3) / 1e9
+            err = float((x32.double() - x64).abs().sum().item())
+            log("fused fp64: %d iterations, %.3f ms/solve; |x32-x64|_1 = %.3e" % (iters64[-1], ms64, err))
+            # ---- streaming copy probe (1 GiB)
+            nb = 1 << 30
+            a = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            grb.GrM_stream_copy(b, a, nb)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(10):
+                grb.GrM_stream_copy(b, a, nb)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            copy_gbs = 2 * nb * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+            del a, b
+            log("stream copy: %.1f GB/s" % copy_gbs)
+            out["unfused"] = {"gteps": round(gteps_b, 2), "ms_per_solve": round(msb, 4),
+                              "iterations": itersb[-1],
+                              "bytes_per_iteration": blocking_bytes_per_pass(n, m, 4)}
+            out["fused_vs_unfused_speedup"] = round(msb / ms32, 3)
+            out["fp64_fused"] = {"gteps": round(gteps64, 2), "ms_per_solve": round(ms64, 4),
+                                 "iterations": iters64[-1]}
+            out["l1_fp32_vs_fp64"] = err
+            out["stream_copy_gbs"] = round(copy_gbs, 1)
+            out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
+
+        # ---- CPU oracle on a bounded sample: the same graph, a fixed number
+        # of passes, and the GPU error against it at that pass count.
+        if not args.no_cpu_baseline:
+            import oracle
+            threads = min(16, os.cpu_count() or 1)
+            oracle.set_threads(threads)
+            t0 = time.perf_counter()
+            og = oracle.rmat_graph(args.scale)
+            build_s = time.perf_counter() - t0
+            k = args.cpu_iters
+            oracle.pagerank(og, DAMPING, fixed_iters=1)  # warm-up
+            t0 = time.perf_counter()
+            ref = oracle.pagerank(og, DAMPING, fixed_iters=k)
+            cpu_s = time.perf_counter() - t0
+            cpu_gteps = og.m * k / cpu_s / 1e9
+            xk, itk, _ = api.pagerank(g, torch.float32, DAMPING, 0.0, k, grb.GrM_DANGLING_UNIFORM, None, 8)
+            errk = float(np.abs(xk.double().cpu().numpy() - ref.x).sum())
+            log("oracle: %d passes in %.2fs on %d threads (%.3f GTEPS); graph build %.1fs; "
+                "GPU fp32 L1 error at %d passes: %.3e" % (k, cpu_s, threads, cpu_gteps, build_s, k, errk))
+            out["cpu_baseline"] = {"value": round(cpu_gteps, 4), "unit": "GTEPS", "cores": threads,
+                                   "kind": "oracle",
+                                   "sample": "%d blocking FP64 passes on the same R-MAT scale-%d graph "
+                                             "(%.1f s)" % (k, args.scale, cpu_s)}
+            out["l1_fp32_vs_oracle_fixed_passes"] = errk
+        g.free()
+
+    line = {
+        "metric": "fused PageRank GTEPS & %HBM peak vs unfused at 1e-6 L1; PPR queries/s",
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "R-MAT scale %d (n=%d, m=%d after dedup), FP32 ranks + FP64 "
+                               "reductions, damping 0.85, tol %g, uniform dangling"
+                               % (args.scale, n, m, args.tol),
+                   "iterations": it32, "graph_setup_s": round(setup_s, 3)},
+    }
+    line.update(out)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

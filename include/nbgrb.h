@@ -1,0 +1,377 @@
+/*
+ * nbgrb.h -- C ABI of a nonblocking GraphBLAS subset for AMD Instinct MI355X
+ * (gfx950), built around the fused PageRank iteration of
+ * "Julia GraphBLAS with Nonblocking Execution" (Costanza, Mattson, Kimmerer,
+ * Brock).
+ *
+ * Execution model (paper, Section II "Nonblocking execution"):
+ *   - GrB_init(GrB_BLOCKING): every operation runs as its own GPU kernel
+ *     and its output is materialised before the next operation is issued.
+ *   - GrB_init(GrB_NONBLOCKING): operations are validated and recorded as
+ *     nodes of a DAG (Section III-A, "General approach"; Fig. 3 shows the
+ *     node kept for mxv).  Nothing runs until a wait or a value read forces
+ *     it; then the pending DAG is pattern-matched onto fused kernels and
+ *     intermediates that no handle can reach any more are never written
+ *     (the "elide unneeded objects" of Section II).  Results equal blocking
+ *     mode up to floating-point reassociation.
+ *
+ * Device and stream: all work is enqueued on one HIP stream (GrM_set_stream;
+ * the null stream by default).  "Complete" means complete in stream order:
+ * later work on that stream sees the result.  Calls that hand a value to
+ * the host (GrB_Scalar_extractElement_FP64, GrB_Vector_reduce_FP64, the
+ * *_export_* calls into host memory, GrM_pagerank's iteration count)
+ * synchronise the stream.
+ *
+ * Memory: every pointer argument documented as "device" must be device
+ * memory on the current HIP device; "host" pointers are ordinary host
+ * memory.  Imports copy the caller's data; exports copy out.  The library
+ * owns all storage behind its handles and frees it in *_free or
+ * GrB_finalize.  Device memory comes from the allocator installed with
+ * GrM_set_allocator (hipMalloc/hipFree when none is installed), cached by
+ * exact size and reused in stream order.
+ *
+ * Errors: every call returns a GrB_Info.  API errors (null pointers,
+ * uninitialised handles, size or type mismatches, unsupported operator
+ * combinations) are detected eagerly in both modes and leave all objects
+ * unchanged.  Execution errors (GrB_OUT_OF_MEMORY, GrB_PANIC on a HIP
+ * failure) surface at the call that executes the work: the operation itself
+ * in blocking mode, the forcing call in nonblocking mode.  GrM_error()
+ * returns a text describing the last error of the calling thread.
+ * Non-convergence of an iterative algorithm is not an error.
+ *
+ * Threads: one context per process; the library is not thread-safe.
+ */
+#ifndef NBGRB_H
+#define NBGRB_H
+
+#include <stdbool.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef uint64_t GrB_Index;
+
+/* Return codes, numbered as in the GraphBLAS C API specification 2.x. */
+typedef enum {
+  GrB_SUCCESS = 0,
+  GrB_NO_VALUE = 1,
+  GrB_UNINITIALIZED_OBJECT = -1,
+  GrB_NULL_POINTER = -2,
+  GrB_INVALID_VALUE = -3,
+  GrB_INVALID_INDEX = -4,
+  GrB_DOMAIN_MISMATCH = -5,
+  GrB_DIMENSION_MISMATCH = -6,
+  GrB_OUTPUT_NOT_EMPTY = -7,
+  GrB_NOT_IMPLEMENTED = -8,
+  GrB_PANIC = -101,
+  GrB_OUT_OF_MEMORY = -102,
+  GrB_INSUFFICIENT_SPACE = -103,
+  GrB_INVALID_OBJECT = -104,
+  GrB_INDEX_OUT_OF_BOUNDS = -105,
+  GrB_EMPTY_OBJECT = -106
+} GrB_Info;
+
+/* Execution modes (Section II of the paper). */
+typedef enum { GrB_NONBLOCKING = 0, GrB_BLOCKING = 1 } GrB_Mode;
+
+/* GrB_COMPLETE: the object's value is computed (in stream order).
+ * GrB_MATERIALIZE: additionally it is held in storage, not as a pending
+ * node.  Both force the pending DAG in nonblocking mode. */
+typedef enum { GrB_COMPLETE = 0, GrB_MATERIALIZE = 1 } GrB_WaitMode;
+
+/* Opaque handles. */
+typedef struct GB_Type_opaque *GrB_Type;
+typedef struct GB_UnaryOp_opaque *GrB_UnaryOp;
+typedef struct GB_BinaryOp_opaque *GrB_BinaryOp;
+typedef struct GB_Monoid_opaque *GrB_Monoid;
+typedef struct GB_Semiring_opaque *GrB_Semiring;
+typedef struct GB_Descriptor_opaque *GrB_Descriptor;
+typedef struct GB_Vector_opaque *GrB_Vector;
+typedef struct GB_Matrix_opaque *GrB_Matrix;
+typedef struct GB_Scalar_opaque *GrB_Scalar;
+
+/* ------------------------------------------------------------------------
+ * Built-in types and operators.  User-defined (host) functions cannot run
+ * in a GPU kernel, so the operator set is closed; the paper's anonymous
+ * functions map onto it as follows (Fig. 6):
+ *   (x, y) -> abs(x - y)            GrM_ABSDIFF_*
+ *   (_, x) -> x  (mxv multiply)     GrM_PLUS_SECOND_SEMIRING_*
+ *   x / d with d = max(outdeg,1)/damping   GrB_DIV_* (eWiseMult)
+ * ---------------------------------------------------------------------- */
+extern GrB_Type GrB_BOOL, GrB_INT32, GrB_FP32, GrB_FP64;
+
+extern GrB_UnaryOp GrB_IDENTITY_FP32, GrB_IDENTITY_FP64;
+extern GrB_UnaryOp GrB_ABS_FP32, GrB_ABS_FP64;
+extern GrB_UnaryOp GrB_AINV_FP32, GrB_AINV_FP64; /* -x */
+extern GrB_UnaryOp GrB_MINV_FP32, GrB_MINV_FP64; /* 1/x */
+/* 1/x where x != 0, else 0: the inverse out-degree with dangling -> 0. */
+extern GrB_UnaryOp GrM_MINV_OR_ZERO_FP32, GrM_MINV_OR_ZERO_FP64;
+
+extern GrB_BinaryOp GrB_PLUS_FP32, GrB_PLUS_FP64;
+extern GrB_BinaryOp GrB_MINUS_FP32, GrB_MINUS_FP64;
+extern GrB_BinaryOp GrB_TIMES_FP32, GrB_TIMES_FP64;
+extern GrB_BinaryOp GrB_DIV_FP32, GrB_DIV_FP64;
+extern GrB_BinaryOp GrB_MAX_FP32, GrB_MAX_FP64;
+extern GrB_BinaryOp GrB_MIN_FP32, GrB_MIN_FP64;
+extern GrB_BinaryOp GrB_FIRST_FP32, GrB_FIRST_FP64;
+extern GrB_BinaryOp GrB_SECOND_FP32, GrB_SECOND_FP64;
+extern GrB_BinaryOp GrM_ABSDIFF_FP32, GrM_ABSDIFF_FP64; /* |x - y| */
+
+extern GrB_Monoid GrB_PLUS_MONOID_FP32, GrB_PLUS_MONOID_FP64;
+
+/* Semirings accepted by GrB_mxv / GrB_mxm.  The matrices built by this
+ * library are patterns whose stored values are all 1 (iso-valued), so
+ * plus-times and plus-second compute the same product. */
+extern GrB_Semiring GrB_PLUS_TIMES_SEMIRING_FP32, GrB_PLUS_TIMES_SEMIRING_FP64;
+extern GrB_Semiring GrM_PLUS_SECOND_SEMIRING_FP32, GrM_PLUS_SECOND_SEMIRING_FP64;
+
+/* Descriptors: NULL (defaults) or GrB_DESC_C (complement the mask). */
+extern GrB_Descriptor GrB_DESC_C;
+
+/* ------------------------------------------------------------------------
+ * Context
+ * ---------------------------------------------------------------------- */
+
+/* Start the library in the given mode.  GrB_INVALID_VALUE for an unknown
+ * mode; GrB_INVALID_VALUE if already initialised; GrB_PANIC if no HIP
+ * device is usable. */
+GrB_Info GrB_init(GrB_Mode mode);
+
+/* Wait for all queued work, free every object and cached buffer. */
+GrB_Info GrB_finalize(void);
+
+GrB_Info GrM_get_mode(GrB_Mode *mode);
+
+/* Switch the execution mode of the running context (project extension):
+ * pending work is forced first.  Lets one process compare blocking and
+ * nonblocking execution on the same objects. */
+GrB_Info GrM_set_mode(GrB_Mode mode);
+
+/* Text of the last error (never NULL; empty when there was none). */
+const char *GrM_error(void);
+
+/* Stream all work is enqueued on (a hipStream_t).  The previous stream is
+ * synchronised first, so cached buffers are never shared across streams
+ * without ordering. */
+GrB_Info GrM_set_stream(void *hip_stream);
+
+/* Device allocator callbacks: alloc(bytes, ctx) returns device memory or
+ * NULL; release(ptr, ctx) frees it.  Pass NULLs to return to hipMalloc /
+ * hipFree.  Only allowed while no object holds device memory
+ * (GrB_INVALID_VALUE otherwise). */
+GrB_Info GrM_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                           void (*release)(void *ptr, void *ctx), void *ctx);
+
+/* Test hook: make the k-th device allocation from now on fail (k >= 1);
+ * k = 0 disables.  The failure surfaces as GrB_OUT_OF_MEMORY at the call
+ * that executes the work. */
+GrB_Info GrM_fail_allocation_after(int64_t k);
+
+/* Counters since GrB_init or the last reset: kernels launched, fused
+ * PageRank-iteration launches, plan-cache hits and misses, number of
+ * intermediates that were never materialised. */
+typedef struct {
+  int64_t kernels;
+  int64_t fused_launches;
+  int64_t plan_hits;
+  int64_t plan_misses;
+  int64_t elided_nodes;
+  int64_t forced_waits;
+} GrM_Stats;
+GrB_Info GrM_get_stats(GrM_Stats *stats);
+GrB_Info GrM_reset_stats(void);
+
+/* ------------------------------------------------------------------------
+ * Scalars.  Values live on the device as FP64 whatever the declared type.
+ * ---------------------------------------------------------------------- */
+GrB_Info GrB_Scalar_new(GrB_Scalar *s, GrB_Type type);
+GrB_Info GrB_Scalar_free(GrB_Scalar *s);
+GrB_Info GrB_Scalar_setElement_FP64(GrB_Scalar s, double x);
+/* Forces the scalar and copies its value to *x (synchronises).
+ * GrB_NO_VALUE if the scalar has never been assigned. */
+GrB_Info GrB_Scalar_extractElement_FP64(double *x, GrB_Scalar s);
+GrB_Info GrB_Scalar_wait(GrB_Scalar s, GrB_WaitMode mode);
+/* out = alpha * in + beta, recorded like any other operation (project
+ * extension: it expresses the teleport constant (1-d)/n + d*D/n from the
+ * dangling mass D without a host round trip). */
+GrB_Info GrM_Scalar_affine(GrB_Scalar out, double alpha, GrB_Scalar in, double beta);
+
+/* ------------------------------------------------------------------------
+ * Vectors.  All vectors are full (dense): every index holds a value, as the
+ * FullVector of the paper (Section III-A, Fig. 4).
+ * ---------------------------------------------------------------------- */
+
+/* New vector of length n (n >= 1) holding zeros.  type FP32, FP64 or INT32. */
+GrB_Info GrB_Vector_new(GrB_Vector *v, GrB_Type type, GrB_Index n);
+GrB_Info GrB_Vector_free(GrB_Vector *v);
+/* w = u (a new reference to u's value; no copy is made). */
+GrB_Info GrB_Vector_dup(GrB_Vector *w, GrB_Vector u);
+GrB_Info GrB_Vector_size(GrB_Index *n, GrB_Vector v);
+GrB_Info GrM_Vector_type(GrB_Type *t, GrB_Vector v);
+GrB_Info GrB_Vector_wait(GrB_Vector v, GrB_WaitMode mode);
+
+/* Every entry := value (the paper's GrBVector(n, value) constructor,
+ * Fig. 6).  Kept iso-valued -- one value, no storage -- until an operation
+ * needs it stored. */
+GrB_Info GrM_Vector_fill(GrB_Vector v, double value);
+
+/* Copy n entries of the vector's type from device memory src_dev. */
+GrB_Info GrM_Vector_import_dense(GrB_Vector v, const void *src_dev, GrB_Index n);
+/* Force v and copy its n entries (vector's type) to device memory dst_dev. */
+GrB_Info GrM_Vector_export_dense(void *dst_dev, GrB_Index n, GrB_Vector v);
+/* Force and materialise v; *ptr receives the device address of its
+ * storage, valid until v is next modified or freed.  Read-only. */
+GrB_Info GrM_Vector_device_pointer(const void **ptr, GrB_Vector v);
+
+/* ------------------------------------------------------------------------
+ * Matrices: CSR patterns with int32 row pointers and column indices (the
+ * paper uses 32-bit indices throughout its experiments, Section IV), so
+ * nnz < 2^31 and dimensions < 2^31.  Stored values are all 1.
+ * ---------------------------------------------------------------------- */
+
+GrB_Info GrB_Matrix_new(GrB_Matrix *A, GrB_Type type, GrB_Index nrows, GrB_Index ncols);
+GrB_Info GrB_Matrix_free(GrB_Matrix *A);
+GrB_Info GrB_Matrix_nrows(GrB_Index *n, GrB_Matrix A);
+GrB_Info GrB_Matrix_ncols(GrB_Index *n, GrB_Matrix A);
+GrB_Info GrB_Matrix_nvals(GrB_Index *nvals, GrB_Matrix A);
+GrB_Info GrB_Matrix_wait(GrB_Matrix A, GrB_WaitMode mode);
+
+/* Replace A's content by the CSR pattern (rowptr_dev[nrows+1],
+ * col_dev[nnz], device, int32).  rowptr must start at 0, be
+ * non-decreasing and end at nnz; columns must lie in [0, ncols), with no
+ * column repeated within a row (any order).  The arrays are copied.
+ * GrB_INVALID_VALUE on a malformed pattern (checked on the device). */
+GrB_Info GrM_Matrix_import_CSR(GrB_Matrix A, const int32_t *rowptr_dev,
+                               const int32_t *col_dev, GrB_Index nnz);
+
+/* Copy A's CSR pattern to device memory (rowptr_dev[nrows+1], col_dev[nnz]). */
+GrB_Info GrM_Matrix_export_CSR(int32_t *rowptr_dev, int32_t *col_dev, GrB_Matrix A);
+
+/* A := the n x n pattern with an entry (src[e], dst[e]) for every edge e
+ * (device arrays of length nedges).  Duplicate edges are merged; self-loops
+ * are dropped when drop_self is true.  Rows are sources, each row's columns
+ * ascending.  GrB_INDEX_OUT_OF_BOUNDS if an endpoint is >= n. */
+GrB_Info GrM_Matrix_build_edges(GrB_Matrix A, const uint32_t *src_dev,
+                                const uint32_t *dst_dev, GrB_Index nedges,
+                                bool drop_self);
+
+/* C := A^T (GraphBLAS transpose with no mask and no accumulator; mask and
+ * accum must be NULL).  C must be ncols(A) x nrows(A).  Each row of C lists
+ * its columns in ascending order. */
+GrB_Info GrB_transpose(GrB_Matrix C, GrB_Matrix Mask, GrB_BinaryOp accum,
+                       GrB_Matrix A, GrB_Descriptor desc);
+
+/* deg := number of stored entries in each row of A (deg has nrows(A)
+ * entries; type INT32, FP32 or FP64).  With A the adjacency pattern this is
+ * the out-degree vector the paper's PageRank takes as input (Fig. 6). */
+GrB_Info GrM_Matrix_row_degree(GrB_Vector deg, GrB_Matrix A);
+
+/* R-MAT edge list (Chakrabarti, Zhan & Faloutsos 2004) written to device
+ * arrays src_dev[nedges], dst_dev[nedges].  Edge e chooses a quadrant at
+ * each of `scale` levels, most significant bit first, from draw
+ * k = e*scale + level of a SplitMix64 stream (Steele, Lea & Flood 2014)
+ * seeded with `seed`, as u = (draw >> 11) * 2^-53: u < t_a -> no bit,
+ * u < t_ab -> destination bit, u < t_abc -> source bit, else both.  The
+ * library only uses this to produce inputs; it is not part of any
+ * GraphBLAS operation.  GrB_INVALID_VALUE unless 1 <= scale <= 31. */
+GrB_Info GrM_rmat_edges(uint32_t *src_dev, uint32_t *dst_dev, int scale,
+                        GrB_Index nedges, uint64_t seed, double t_a,
+                        double t_ab, double t_abc);
+
+/* ------------------------------------------------------------------------
+ * Operations (GraphBLAS C API forms, destructive output as in the C
+ * specification; the paper's Julia methods return new nodes instead,
+ * Section III-A).  mask and accum must be NULL unless stated.  Output
+ * vectors are overwritten entirely.  Operand types must equal the
+ * operator's type (INT32 inputs are accepted and converted by the unary
+ * apply forms).
+ * ---------------------------------------------------------------------- */
+
+/* w = A (+.*) u.  A is nrows x ncols, u has ncols entries, w nrows.  An
+ * empty row gives the monoid identity 0. */
+GrB_Info GrB_mxv(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
+                 GrB_Semiring op, GrB_Matrix A, GrB_Vector u, GrB_Descriptor desc);
+
+/* w(i) = op(u(i), v(i)).  For full vectors the union (eWiseAdd) and the
+ * intersection (eWiseMult) of the patterns coincide. */
+GrB_Info GrB_Vector_eWiseMult_BinaryOp(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
+                                       GrB_BinaryOp op, GrB_Vector u, GrB_Vector v,
+                                       GrB_Descriptor desc);
+GrB_Info GrB_Vector_eWiseAdd_BinaryOp(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
+                                      GrB_BinaryOp op, GrB_Vector u, GrB_Vector v,
+                                      GrB_Descriptor desc);
+
+/* w(i) = op(u(i)). */
+GrB_Info GrB_Vector_apply(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
+                          GrB_UnaryOp op, GrB_Vector u, GrB_Descriptor desc);
+/* w(i) = op(s, u(i)) and w(i) = op(u(i), s) with a host scalar s. */
+GrB_Info GrB_Vector_apply_BinaryOp1st_FP64(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
+                                           GrB_BinaryOp op, double s, GrB_Vector u,
+                                           GrB_Descriptor desc);
+GrB_Info GrB_Vector_apply_BinaryOp2nd_FP64(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
+                                           GrB_BinaryOp op, GrB_Vector u, double s,
+                                           GrB_Descriptor desc);
+/* w(i) = op(u(i), s) with s a (possibly pending) GrB_Scalar. */
+GrB_Info GrB_Vector_apply_BinaryOp2nd_Scalar(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
+                                             GrB_BinaryOp op, GrB_Vector u, GrB_Scalar s,
+                                             GrB_Descriptor desc);
+
+/* s = sum of u (plus monoid only), accumulated in FP64.  The _Scalar form
+ * is recorded lazily; the _FP64 form forces and synchronises. */
+GrB_Info GrB_Vector_reduce_Monoid_Scalar(GrB_Scalar s, GrB_BinaryOp accum, GrB_Monoid monoid,
+                                         GrB_Vector u, GrB_Descriptor desc);
+GrB_Info GrB_Vector_reduce_FP64(double *s, GrB_BinaryOp accum, GrB_Monoid monoid,
+                                GrB_Vector u, GrB_Descriptor desc);
+
+/* s = sum of u(i) over the i selected by the value mask `mask` (mask(i) !=
+ * 0), or by its complement when desc is GrB_DESC_C.  Project extension: the
+ * C API's reduce takes no mask.  With mask = the inverse out-degree vector
+ * and GrB_DESC_C this is the dangling mass sum_{outdeg(j)=0} u(j). */
+GrB_Info GrM_Vector_reduce_masked_Scalar(GrB_Scalar s, GrB_Vector mask, GrB_Monoid monoid,
+                                         GrB_Vector u, GrB_Descriptor desc);
+
+/* ------------------------------------------------------------------------
+ * PageRank drivers.  They issue the operations above (so the nonblocking
+ * matcher and the plan cache are on their path) and add device-side loop
+ * control so the host reads the residual only every `check_every`
+ * iterations; iterations past convergence are skipped on the device, so
+ * the iteration count is the same as with a check after every pass.
+ * ---------------------------------------------------------------------- */
+
+typedef enum { GrM_DANGLING_DROP = 0, GrM_DANGLING_UNIFORM = 1 } GrM_Dangling;
+
+/* PageRank of the graph whose transposed adjacency pattern is AT (n x n),
+ * with out-degrees outdeg (n entries, any numeric type), following the loop
+ * of Fig. 6: w = x .* (damping ./ outdeg); s = AT (+.second) w;
+ * r = c + s; rho = sum |x - r|; repeat while iterations < itermax and
+ * rho > tol (rho = 1 before the first pass).  GrM_DANGLING_DROP uses
+ * c = (1-damping)/n as the paper does; GrM_DANGLING_UNIFORM uses
+ * c = (1-damping)/n + damping * D/n with D the rank held by vertices of
+ * out-degree 0, so the ranks sum to one.  r (FP32 or FP64, n entries)
+ * receives the result and fixes the arithmetic type; the residual and D
+ * are accumulated in FP64.  x0 is the start vector (NULL: every entry 1/n).
+ * *iters = passes performed, *resid = last rho.  check_every >= 1. */
+GrB_Info GrM_pagerank(GrB_Vector r, int *iters, double *resid, GrB_Matrix AT,
+                      GrB_Vector outdeg, double damping, double tol, int itermax,
+                      GrM_Dangling dangling, GrB_Vector x0, int check_every);
+
+/* ------------------------------------------------------------------------
+ * Bandwidth probe: dst_dev[0:bytes) = src_dev[0:bytes) with a streaming
+ * copy kernel (bytes a multiple of 16, pointers 16-byte aligned).
+ * ---------------------------------------------------------------------- */
+GrB_Info GrM_stream_copy(void *dst_dev, const void *src_dev, size_t bytes);
+
+/* Per-launch timing of fused PageRank kernels (HIP events recorded around
+ * every fused launch on the library stream while enabled).  Reading the
+ * total synchronises. */
+GrB_Info GrM_timing_enable(bool on);
+GrB_Info GrM_timing_read(double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBGRB_H */

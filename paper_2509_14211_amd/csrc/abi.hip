@@ -1,0 +1,1093 @@
+// C ABI entry points (declared in include/nbgrb.h).  Each call validates
+// its arguments eagerly, then records (nonblocking) or runs (blocking) the
+// operation through the runtime.  Internal errors are C++ exceptions that
+// are turned into GrB_Info codes here.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "runtime.h"
+
+using namespace nbgrb;
+
+// ------------------------------------------------------------ built-ins
+
+static GB_Type_opaque t_bool{T_BOOL}, t_int32{T_INT32}, t_fp32{T_FP32}, t_fp64{T_FP64};
+GrB_Type GrB_BOOL = &t_bool, GrB_INT32 = &t_int32, GrB_FP32 = &t_fp32, GrB_FP64 = &t_fp64;
+
+#define UNOP(NAME, OP, T)                  \
+  static GB_UnaryOp_opaque u_##NAME{OP, T}; \
+  GrB_UnaryOp NAME = &u_##NAME;
+UNOP(GrB_IDENTITY_FP32, U_IDENTITY, T_FP32)
+UNOP(GrB_IDENTITY_FP64, U_IDENTITY, T_FP64)
+UNOP(GrB_ABS_FP32, U_ABS, T_FP32)
+UNOP(GrB_ABS_FP64, U_ABS, T_FP64)
+UNOP(GrB_AINV_FP32, U_AINV, T_FP32)
+UNOP(GrB_AINV_FP64, U_AINV, T_FP64)
+UNOP(GrB_MINV_FP32, U_MINV, T_FP32)
+UNOP(GrB_MINV_FP64, U_MINV, T_FP64)
+UNOP(GrM_MINV_OR_ZERO_FP32, U_MINV_OR_ZERO, T_FP32)
+UNOP(GrM_MINV_OR_ZERO_FP64, U_MINV_OR_ZERO, T_FP64)
+
+#define BINOP(NAME, OP, T)                   \
+  static GB_BinaryOp_opaque b_##NAME{OP, T}; \
+  GrB_BinaryOp NAME = &b_##NAME;
+BINOP(GrB_PLUS_FP32, B_PLUS, T_FP32)
+BINOP(GrB_PLUS_FP64, B_PLUS, T_FP64)
+BINOP(GrB_MINUS_FP32, B_MINUS, T_FP32)
+BINOP(GrB_MINUS_FP64, B_MINUS, T_FP64)
+BINOP(GrB_TIMES_FP32, B_TIMES, T_FP32)
+BINOP(GrB_TIMES_FP64, B_TIMES, T_FP64)
+BINOP(GrB_DIV_FP32, B_DIV, T_FP32)
+BINOP(GrB_DIV_FP64, B_DIV, T_FP64)
+BINOP(GrB_MAX_FP32, B_MAX, T_FP32)
+BINOP(GrB_MAX_FP64, B_MAX, T_FP64)
+BINOP(GrB_MIN_FP32, B_MIN, T_FP32)
+BINOP(GrB_MIN_FP64, B_MIN, T_FP64)
+BINOP(GrB_FIRST_FP32, B_FIRST, T_FP32)
+BINOP(GrB_FIRST_FP64, B_FIRST, T_FP64)
+BINOP(GrB_SECOND_FP32, B_SECOND, T_FP32)
+BINOP(GrB_SECOND_FP64, B_SECOND, T_FP64)
+BINOP(GrM_ABSDIFF_FP32, B_ABSDIFF, T_FP32)
+BINOP(GrM_ABSDIFF_FP64, B_ABSDIFF, T_FP64)
+
+static GB_Monoid_opaque m_plus32{B_PLUS, T_FP32}, m_plus64{B_PLUS, T_FP64};
+GrB_Monoid GrB_PLUS_MONOID_FP32 = &m_plus32, GrB_PLUS_MONOID_FP64 = &m_plus64;
+
+static GB_Semiring_opaque s_pt32{B_PLUS, B_TIMES, T_FP32}, s_pt64{B_PLUS, B_TIMES, T_FP64};
+static GB_Semiring_opaque s_ps32{B_PLUS, B_SECOND, T_FP32}, s_ps64{B_PLUS, B_SECOND, T_FP64};
+GrB_Semiring GrB_PLUS_TIMES_SEMIRING_FP32 = &s_pt32, GrB_PLUS_TIMES_SEMIRING_FP64 = &s_pt64;
+GrB_Semiring GrM_PLUS_SECOND_SEMIRING_FP32 = &s_ps32, GrM_PLUS_SECOND_SEMIRING_FP64 = &s_ps64;
+
+static GB_Descriptor_opaque d_comp{true};
+GrB_Descriptor GrB_DESC_C = &d_comp;
+
+// ------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+#define API_BEGIN \
+  try {           \
+    g_err.clear();
+#define API_END                                      \
+  }                                                  \
+  catch (const GrbError& e) {                        \
+    g_err = e.msg;                                   \
+    return e.info;                                   \
+  }                                                  \
+  catch (const std::bad_alloc&) {                    \
+    g_err = "host allocation failed";                \
+    return GrB_OUT_OF_MEMORY;                        \
+  }                                                  \
+  catch (const std::exception& e) {                  \
+    g_err = e.what();                                \
+    return GrB_PANIC;                                \
+  }                                                  \
+  return GrB_SUCCESS;
+
+static void need(const void* p, const char* what) {
+  if (!p) fail(GrB_NULL_POINTER, std::string(what) + " is NULL");
+}
+
+static GB_Vector_opaque* vec(GrB_Vector v, const char* what) {
+  need(v, what);
+  if (v->magic != MAGIC_VEC) fail(GrB_UNINITIALIZED_OBJECT, std::string(what) + " is not a vector");
+  return v;
+}
+
+static GB_Scalar_opaque* sca(GrB_Scalar s, const char* what) {
+  need(s, what);
+  if (s->magic != MAGIC_SCA) fail(GrB_UNINITIALIZED_OBJECT, std::string(what) + " is not a scalar");
+  return s;
+}
+
+static GB_Matrix_opaque* mat(GrB_Matrix A, const char* what) {
+  need(A, what);
+  if (A->magic != MAGIC_MAT) fail(GrB_UNINITIALIZED_OBJECT, std::string(what) + " is not a matrix");
+  return A;
+}
+
+static void no_mask_accum(const void* mask, const void* accum) {
+  if (mask) fail(GrB_NOT_IMPLEMENTED, "masks are not supported by this operation");
+  if (accum) fail(GrB_NOT_IMPLEMENTED, "accumulators are not supported");
+}
+
+static void float_type(int t, const char* what) {
+  if (t != T_FP32 && t != T_FP64) fail(GrB_DOMAIN_MISMATCH, std::string(what) + " must be FP32 or FP64");
+}
+
+static bool desc_comp(GrB_Descriptor d) { return d && d->mask_comp; }
+
+// ------------------------------------------------------------ recording
+
+namespace {
+
+NodeP iso_node(int type, int64_t n, double v) {
+  NodeP p = new_node(N_DENSE, type, n, false);
+  p->done = true;
+  p->iso = true;
+  p->iso_val = v;
+  return p;
+}
+
+void rec_ewise(GB_Vector_opaque* w, int op, GB_Vector_opaque* u, GB_Vector_opaque* v) {
+  NodeP p = new_node(N_EWISE, w->type, w->n, false);
+  p->a = u->node;
+  p->b = v->node;
+  p->op = op;
+  submit(p);
+  set_vec(w, p);
+}
+
+void rec_unop(GB_Vector_opaque* w, int op, GB_Vector_opaque* u) {
+  NodeP p = new_node(N_APPLY_U, w->type, w->n, false);
+  p->a = u->node;
+  p->op = op;
+  submit(p);
+  set_vec(w, p);
+}
+
+void rec_bind(GB_Vector_opaque* w, int op, GB_Vector_opaque* u, double k, bool first) {
+  NodeP p = new_node(first ? N_APPLY_B1 : N_APPLY_B2, w->type, w->n, false);
+  p->a = u->node;
+  p->op = op;
+  p->k = k;
+  submit(p);
+  set_vec(w, p);
+}
+
+void rec_bind_scalar(GB_Vector_opaque* w, int op, GB_Vector_opaque* u, GB_Scalar_opaque* s) {
+  NodeP p = new_node(N_APPLY_B2S, w->type, w->n, false);
+  p->a = u->node;
+  p->s = s->node;
+  p->op = op;
+  submit(p);
+  set_vec(w, p);
+}
+
+void rec_mxv(GB_Vector_opaque* w, GB_Matrix_opaque* A, GB_Vector_opaque* u) {
+  NodeP p = new_node(N_MXV, w->type, w->n, false);
+  p->A = A->data;
+  p->a = u->node;
+  submit(p);
+  set_vec(w, p);
+}
+
+void rec_reduce(GB_Scalar_opaque* s, GB_Vector_opaque* u, GB_Vector_opaque* mask, bool comp,
+                bool watch) {
+  NodeP p = new_node(mask ? N_REDUCE_MASK : N_REDUCE, T_FP64, 0, true);
+  p->a = u->node;
+  if (mask) {
+    p->mask = mask->node;
+    p->mask_comp = comp;
+  }
+  p->guard_watch = watch;
+  submit(p);
+  set_sca(s, p);
+}
+
+void rec_affine(GB_Scalar_opaque* out, double alpha, GB_Scalar_opaque* in, double beta) {
+  NodeP p = new_node(N_AFFINE, T_FP64, 0, true);
+  p->s = in->node;
+  p->alpha = alpha;
+  p->beta = beta;
+  submit(p);
+  set_sca(out, p);
+}
+
+void store_if_iso(const NodeP& v) {
+  if (!v->iso) return;
+  BufP b = dev_alloc(type_size(v->type) * (size_t)v->n);
+  hip_check(launch_fill(b->p, v->type, v->n, v->iso_val, ctx().stream), "fill");
+  launch_mark(false);
+  v->buf = b;
+  v->iso = false;
+}
+
+MatP new_matdata(int64_t nrows, int64_t ncols) {
+  auto m = std::make_shared<MatData>();
+  m->id = ctx().next_id++;
+  m->nrows = nrows;
+  m->ncols = ncols;
+  m->nnz = 0;
+  m->rowptr = dev_alloc(sizeof(int) * (size_t)(nrows + 1));
+  hip_check(launch_fill(m->rowptr->p, T_INT32, nrows + 1, 0.0, ctx().stream), "fill");
+  launch_mark(false);
+  return m;
+}
+
+// Temporary buffers of the graph builder come from the buffer cache.
+std::map<void*, BufP>& tmp_bufs() {
+  static std::map<void*, BufP> m;
+  return m;
+}
+void* tmp_alloc(size_t bytes, void*) {
+  try {
+    BufP b = dev_alloc(bytes);
+    void* p = b->p;
+    tmp_bufs()[p] = b;
+    return p;
+  } catch (const GrbError&) {
+    return nullptr;
+  }
+}
+void tmp_release(void* p, void*) { tmp_bufs().erase(p); }
+
+int read_flag(const BufP& f) {
+  int h = 0;
+  hip_check(hipMemcpyAsync(&h, f->p, sizeof(int), hipMemcpyDeviceToHost, ctx().stream), "copy flag");
+  hip_check(hipStreamSynchronize(ctx().stream), "sync");
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+// ------------------------------------------------------------ context
+
+GrB_Info GrB_init(GrB_Mode mode) {
+  API_BEGIN
+  Ctx& c = ctx();
+  if (c.init) fail(GrB_INVALID_VALUE, "already initialised");
+  if (mode != GrB_BLOCKING && mode != GrB_NONBLOCKING) fail(GrB_INVALID_VALUE, "unknown mode");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    fail(GrB_PANIC, "no HIP device");
+  }
+  hip_check(hipGetDevice(&c.device), "get device");
+  hipDeviceProp_t prop;
+  hip_check(hipGetDeviceProperties(&prop, c.device), "device properties");
+  c.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c.mode = mode;
+  c.stream = nullptr;
+  c.stats = Stats{};
+  c.init = true;
+  API_END
+}
+
+GrB_Info GrB_finalize(void) {
+  API_BEGIN
+  Ctx& c = ctx();
+  if (!c.init) return GrB_SUCCESS;
+  (void)hipStreamSynchronize(c.stream);
+  c.pending.clear();
+  c.red_part.reset();
+  c.red_ticket.reset();
+  c.fused_part.reset();
+  c.fused_ticket.reset();
+  c.fused_part_cap = 0;
+  c.guard = nullptr;
+  for (auto& e : c.events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  c.events.clear();
+  for (auto e : c.event_pool) (void)hipEventDestroy(e);
+  c.event_pool.clear();
+  c.tuned.clear();
+  c.init = false;
+  for (auto& kv : c.cache)
+    for (void* p : kv.second) raw_release(p);
+  c.cache.clear();
+  API_END
+}
+
+GrB_Info GrM_get_mode(GrB_Mode* mode) {
+  API_BEGIN
+  require_init();
+  need(mode, "mode");
+  *mode = ctx().mode;
+  API_END
+}
+
+GrB_Info GrM_set_mode(GrB_Mode mode) {
+  API_BEGIN
+  require_init();
+  if (mode != GrB_BLOCKING && mode != GrB_NONBLOCKING) fail(GrB_INVALID_VALUE, "unknown mode");
+  force_all();
+  ctx().mode = mode;
+  API_END
+}
+
+const char* GrM_error(void) { return g_err.c_str(); }
+
+GrB_Info GrM_set_stream(void* hip_stream) {
+  API_BEGIN
+  require_init();
+  Ctx& c = ctx();
+  force_all();
+  hip_check(hipStreamSynchronize(c.stream), "sync old stream");
+  c.stream = (hipStream_t)hip_stream;
+  API_END
+}
+
+GrB_Info GrM_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* actx) {
+  API_BEGIN
+  require_init();
+  Ctx& c = ctx();
+  if ((alloc == nullptr) != (release == nullptr)) fail(GrB_NULL_POINTER, "give both callbacks or neither");
+  force_all();
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+  for (auto& kv : c.cache)
+    for (void* p : kv.second) raw_release(p);
+  c.cache.clear();
+  if (c.live_bytes != 0) fail(GrB_INVALID_VALUE, "objects still hold device memory");
+  c.alloc = alloc;
+  c.release = release;
+  c.actx = actx;
+  API_END
+}
+
+GrB_Info GrM_fail_allocation_after(int64_t k) {
+  API_BEGIN
+  require_init();
+  if (k < 0) fail(GrB_INVALID_VALUE, "k < 0");
+  Ctx& c = ctx();
+  c.fail_after = k;
+  if (k > 0) {
+    // force fresh allocations so the countdown is seen
+    for (auto& kv : c.cache)
+      for (void* p : kv.second) raw_release(p);
+    c.cache.clear();
+  }
+  API_END
+}
+
+GrB_Info GrM_get_stats(GrM_Stats* s) {
+  API_BEGIN
+  require_init();
+  need(s, "stats");
+  const Stats& t = ctx().stats;
+  s->kernels = t.kernels;
+  s->fused_launches = t.fused;
+  s->plan_hits = t.plan_hits;
+  s->plan_misses = t.plan_misses;
+  s->elided_nodes = t.elided;
+  s->forced_waits = t.waits;
+  API_END
+}
+
+GrB_Info GrM_reset_stats(void) {
+  API_BEGIN
+  require_init();
+  ctx().stats = Stats{};
+  API_END
+}
+
+// ------------------------------------------------------------ scalars
+
+GrB_Info GrB_Scalar_new(GrB_Scalar* s, GrB_Type type) {
+  API_BEGIN
+  require_init();
+  need(s, "scalar");
+  need(type, "type");
+  auto* o = new GB_Scalar_opaque{MAGIC_SCA, type->code, nullptr};
+  NodeP p = new_node(N_SCALAR, T_FP64, 0, true);
+  p->done = true;
+  p->has_value = false;
+  set_sca(o, p);
+  *s = o;
+  API_END
+}
+
+GrB_Info GrB_Scalar_free(GrB_Scalar* s) {
+  API_BEGIN
+  if (!s || !*s) return GrB_SUCCESS;
+  GB_Scalar_opaque* o = sca(*s, "scalar");
+  set_sca(o, nullptr);
+  o->magic = MAGIC_FREED;
+  delete o;
+  *s = nullptr;
+  API_END
+}
+
+GrB_Info GrB_Scalar_setElement_FP64(GrB_Scalar s, double x) {
+  API_BEGIN
+  require_init();
+  GB_Scalar_opaque* o = sca(s, "scalar");
+  NodeP p = new_node(N_SCALAR, T_FP64, 0, true);
+  p->buf = dev_alloc(sizeof(double));
+  hip_check(launch_set_scalar((double*)p->buf->p, x, ctx().stream), "set scalar");
+  launch_mark(false);
+  p->done = true;
+  set_sca(o, p);
+  API_END
+}
+
+GrB_Info GrB_Scalar_extractElement_FP64(double* x, GrB_Scalar s) {
+  API_BEGIN
+  require_init();
+  need(x, "x");
+  GB_Scalar_opaque* o = sca(s, "scalar");
+  materialize(o->node);
+  if (!o->node->has_value) return GrB_NO_VALUE;
+  double h = 0.0;
+  hip_check(hipMemcpyAsync(&h, o->node->buf->p, sizeof(double), hipMemcpyDeviceToHost, ctx().stream),
+            "copy scalar");
+  hip_check(hipStreamSynchronize(ctx().stream), "sync");
+  *x = h;
+  API_END
+}
+
+GrB_Info GrB_Scalar_wait(GrB_Scalar s, GrB_WaitMode mode) {
+  API_BEGIN
+  require_init();
+  GB_Scalar_opaque* o = sca(s, "scalar");
+  if (mode != GrB_COMPLETE && mode != GrB_MATERIALIZE) fail(GrB_INVALID_VALUE, "wait mode");
+  materialize(o->node);
+  API_END
+}
+
+GrB_Info GrM_Scalar_affine(GrB_Scalar out, double alpha, GrB_Scalar in, double beta) {
+  API_BEGIN
+  require_init();
+  GB_Scalar_opaque* o = sca(out, "out");
+  GB_Scalar_opaque* i = sca(in, "in");
+  rec_affine(o, alpha, i, beta);
+  API_END
+}
+
+// ------------------------------------------------------------ vectors
+
+GrB_Info GrB_Vector_new(GrB_Vector* v, GrB_Type type, GrB_Index n) {
+  API_BEGIN
+  require_init();
+  need(v, "vector");
+  need(type, "type");
+  if (n < 1 || n > (GrB_Index)INT32_MAX) fail(GrB_INVALID_VALUE, "vector length must be in [1, 2^31)");
+  if (type->code == T_BOOL) fail(GrB_NOT_IMPLEMENTED, "BOOL vectors are not supported");
+  auto* o = new GB_Vector_opaque{MAGIC_VEC, type->code, (int64_t)n, nullptr};
+  set_vec(o, iso_node(type->code, (int64_t)n, 0.0));
+  *v = o;
+  API_END
+}
+
+GrB_Info GrB_Vector_free(GrB_Vector* v) {
+  API_BEGIN
+  if (!v || !*v) return GrB_SUCCESS;
+  GB_Vector_opaque* o = vec(*v, "vector");
+  set_vec(o, nullptr);
+  o->magic = MAGIC_FREED;
+  delete o;
+  *v = nullptr;
+  API_END
+}
+
+GrB_Info GrB_Vector_dup(GrB_Vector* w, GrB_Vector u) {
+  API_BEGIN
+  require_init();
+  need(w, "w");
+  GB_Vector_opaque* uo = vec(u, "u");
+  auto* o = new GB_Vector_opaque{MAGIC_VEC, uo->type, uo->n, nullptr};
+  set_vec(o, uo->node);
+  *w = o;
+  API_END
+}
+
+GrB_Info GrB_Vector_size(GrB_Index* n, GrB_Vector v) {
+  API_BEGIN
+  need(n, "n");
+  *n = (GrB_Index)vec(v, "vector")->n;
+  API_END
+}
+
+GrB_Info GrM_Vector_type(GrB_Type* t, GrB_Vector v) {
+  API_BEGIN
+  need(t, "t");
+  switch (vec(v, "vector")->type) {
+    case T_INT32: *t = GrB_INT32; break;
+    case T_FP32: *t = GrB_FP32; break;
+    case T_FP64: *t = GrB_FP64; break;
+    default: *t = GrB_BOOL; break;
+  }
+  API_END
+}
+
+GrB_Info GrB_Vector_wait(GrB_Vector v, GrB_WaitMode mode) {
+  API_BEGIN
+  require_init();
+  GB_Vector_opaque* o = vec(v, "vector");
+  if (mode != GrB_COMPLETE && mode != GrB_MATERIALIZE) fail(GrB_INVALID_VALUE, "wait mode");
+  materialize(o->node);
+  API_END
+}
+
+GrB_Info GrM_Vector_fill(GrB_Vector v, double value) {
+  API_BEGIN
+  require_init();
+  GB_Vector_opaque* o = vec(v, "vector");
+  set_vec(o, iso_node(o->type, o->n, value));
+  API_END
+}
+
+GrB_Info GrM_Vector_import_dense(GrB_Vector v, const void* src, GrB_Index n) {
+  API_BEGIN
+  require_init();
+  GB_Vector_opaque* o = vec(v, "vector");
+  need(src, "src");
+  if ((int64_t)n != o->n) fail(GrB_DIMENSION_MISMATCH, "length differs from the vector's");
+  NodeP p = new_node(N_DENSE, o->type, o->n, false);
+  p->buf = dev_alloc(type_size(o->type) * (size_t)o->n);
+  hip_check(hipMemcpyAsync(p->buf->p, src, type_size(o->type) * (size_t)o->n,
+                           hipMemcpyDeviceToDevice, ctx().stream),
+            "import");
+  p->done = true;
+  set_vec(o, p);
+  API_END
+}
+
+GrB_Info GrM_Vector_export_dense(void* dst, GrB_Index n, GrB_Vector v) {
+  API_BEGIN
+  require_init();
+  GB_Vector_opaque* o = vec(v, "vector");
+  need(dst, "dst");
+  if ((int64_t)n != o->n) fail(GrB_DIMENSION_MISMATCH, "length differs from the vector's");
+  materialize(o->node);
+  const NodeP& p = o->node;
+  if (p->iso) {
+    hip_check(launch_fill(dst, o->type, o->n, p->iso_val, ctx().stream), "export fill");
+    launch_mark(false);
+  } else {
+    hip_check(hipMemcpyAsync(dst, p->buf->p, type_size(o->type) * (size_t)o->n,
+                             hipMemcpyDeviceToDevice, ctx().stream),
+              "export");
+  }
+  API_END
+}
+
+GrB_Info GrM_Vector_device_pointer(const void** ptr, GrB_Vector v) {
+  API_BEGIN
+  require_init();
+  need(ptr, "ptr");
+  GB_Vector_opaque* o = vec(v, "vector");
+  materialize(o->node);
+  store_if_iso(o->node);
+  *ptr = o->node->buf->p;
+  API_END
+}
+
+// ------------------------------------------------------------ matrices
+
+GrB_Info GrB_Matrix_new(GrB_Matrix* A, GrB_Type type, GrB_Index nrows, GrB_Index ncols) {
+  API_BEGIN
+  require_init();
+  need(A, "matrix");
+  need(type, "type");
+  if (nrows < 1 || ncols < 1 || nrows > (GrB_Index)INT32_MAX - 1 || ncols > (GrB_Index)INT32_MAX - 1)
+    fail(GrB_INVALID_VALUE, "dimensions must be in [1, 2^31-1)");
+  auto* o = new GB_Matrix_opaque{MAGIC_MAT, type->code, (int64_t)nrows, (int64_t)ncols, nullptr};
+  o->data = new_matdata((int64_t)nrows, (int64_t)ncols);
+  *A = o;
+  API_END
+}
+
+GrB_Info GrB_Matrix_free(GrB_Matrix* A) {
+  API_BEGIN
+  if (!A || !*A) return GrB_SUCCESS;
+  GB_Matrix_opaque* o = mat(*A, "matrix");
+  o->data.reset();
+  o->magic = MAGIC_FREED;
+  delete o;
+  *A = nullptr;
+  API_END
+}
+
+GrB_Info GrB_Matrix_nrows(GrB_Index* n, GrB_Matrix A) {
+  API_BEGIN
+  need(n, "n");
+  *n = (GrB_Index)mat(A, "A")->nrows;
+  API_END
+}
+
+GrB_Info GrB_Matrix_ncols(GrB_Index* n, GrB_Matrix A) {
+  API_BEGIN
+  need(n, "n");
+  *n = (GrB_Index)mat(A, "A")->ncols;
+  API_END
+}
+
+GrB_Info GrB_Matrix_nvals(GrB_Index* nvals, GrB_Matrix A) {
+  API_BEGIN
+  need(nvals, "nvals");
+  *nvals = (GrB_Index)mat(A, "A")->data->nnz;
+  API_END
+}
+
+GrB_Info GrB_Matrix_wait(GrB_Matrix A, GrB_WaitMode mode) {
+  API_BEGIN
+  require_init();
+  mat(A, "A");
+  if (mode != GrB_COMPLETE && mode != GrB_MATERIALIZE) fail(GrB_INVALID_VALUE, "wait mode");
+  API_END
+}
+
+GrB_Info GrM_Matrix_import_CSR(GrB_Matrix A, const int32_t* rowptr, const int32_t* col, GrB_Index nnz) {
+  API_BEGIN
+  require_init();
+  GB_Matrix_opaque* o = mat(A, "A");
+  need(rowptr, "rowptr");
+  if (nnz > 0) need(col, "col");
+  if (nnz > (GrB_Index)INT32_MAX) fail(GrB_INVALID_VALUE, "nnz must be < 2^31");
+  Ctx& c = ctx();
+  auto m = std::make_shared<MatData>();
+  m->id = c.next_id++;
+  m->nrows = o->nrows;
+  m->ncols = o->ncols;
+  m->nnz = (int64_t)nnz;
+  m->rowptr = dev_alloc(sizeof(int) * (size_t)(o->nrows + 1));
+  hip_check(hipMemcpyAsync(m->rowptr->p, rowptr, sizeof(int) * (size_t)(o->nrows + 1),
+                           hipMemcpyDeviceToDevice, c.stream),
+            "import rowptr");
+  if (nnz > 0) {
+    m->col = dev_alloc(sizeof(int) * (size_t)nnz);
+    hip_check(hipMemcpyAsync(m->col->p, col, sizeof(int) * (size_t)nnz, hipMemcpyDeviceToDevice, c.stream),
+              "import col");
+  }
+  BufP flag = dev_alloc(sizeof(int));
+  hip_check(launch_fill(flag->p, T_INT32, 1, 0.0, c.stream), "fill");
+  hip_check(launch_check_csr((const int*)m->rowptr->p, m->nrows, m->col ? (const int*)m->col->p : nullptr,
+                             m->nnz, m->ncols, (int*)flag->p, c.stream),
+            "check csr");
+  launch_mark(false);
+  launch_mark(false);
+  if (read_flag(flag) != 0) fail(GrB_INVALID_VALUE, "malformed CSR pattern");
+  o->data = m;
+  API_END
+}
+
+GrB_Info GrM_Matrix_export_CSR(int32_t* rowptr, int32_t* col, GrB_Matrix A) {
+  API_BEGIN
+  require_init();
+  GB_Matrix_opaque* o = mat(A, "A");
+  need(rowptr, "rowptr");
+  const MatP& m = o->data;
+  if (m->nnz > 0) need(col, "col");
+  Ctx& c = ctx();
+  hip_check(hipMemcpyAsync(rowptr, m->rowptr->p, sizeof(int) * (size_t)(m->nrows + 1),
+                           hipMemcpyDeviceToDevice, c.stream),
+            "export rowptr");
+  if (m->nnz > 0)
+    hip_check(hipMemcpyAsync(col, m->col->p, sizeof(int) * (size_t)m->nnz, hipMemcpyDeviceToDevice, c.stream),
+              "export col");
+  API_END
+}
+
+GrB_Info GrM_Matrix_build_edges(GrB_Matrix A, const uint32_t* src, const uint32_t* dst, GrB_Index nedges,
+                                bool drop_self) {
+  API_BEGIN
+  require_init();
+  GB_Matrix_opaque* o = mat(A, "A");
+  if (o->nrows != o->ncols) fail(GrB_DIMENSION_MISMATCH, "edge lists build square matrices");
+  if (nedges > 0) {
+    need(src, "src");
+    need(dst, "dst");
+  }
+  if (nedges > (GrB_Index)INT32_MAX) fail(GrB_INVALID_VALUE, "at most 2^31-1 edges");
+  Ctx& c = ctx();
+  const int64_t n = o->nrows;
+  auto m = std::make_shared<MatData>();
+  m->id = c.next_id++;
+  m->nrows = n;
+  m->ncols = n;
+  m->rowptr = dev_alloc(sizeof(int) * (size_t)(n + 1));
+  BufP colbuf = nedges > 0 ? dev_alloc(sizeof(int) * (size_t)nedges) : nullptr;
+  BufP flag = dev_alloc(sizeof(int));
+  hip_check(launch_fill(flag->p, T_INT32, 1, 0.0, c.stream), "fill");
+  int64_t nnz = 0;
+  hip_check(build_csr_from_edges(n, src, dst, (int64_t)nedges, drop_self, (int*)m->rowptr->p,
+                                 colbuf ? (int*)colbuf->p : nullptr, &nnz, (int*)flag->p, tmp_alloc,
+                                 tmp_release, nullptr, c.stream),
+            "build CSR");
+  launch_mark(false);
+  if (read_flag(flag) != 0) fail(GrB_INDEX_OUT_OF_BOUNDS, "edge endpoint >= n");
+  m->nnz = nnz;
+  if (nnz > 0) {
+    // shrink the column array to nnz
+    m->col = dev_alloc(sizeof(int) * (size_t)nnz);
+    hip_check(hipMemcpyAsync(m->col->p, colbuf->p, sizeof(int) * (size_t)nnz, hipMemcpyDeviceToDevice,
+                             c.stream),
+              "copy col");
+  }
+  o->data = m;
+  API_END
+}
+
+GrB_Info GrB_transpose(GrB_Matrix C, GrB_Matrix Mask, GrB_BinaryOp accum, GrB_Matrix A, GrB_Descriptor desc) {
+  API_BEGIN
+  require_init();
+  (void)desc;
+  GB_Matrix_opaque* co = mat(C, "C");
+  GB_Matrix_opaque* ao = mat(A, "A");
+  no_mask_accum(Mask, accum);
+  if (co->nrows != ao->ncols || co->ncols != ao->nrows) fail(GrB_DIMENSION_MISMATCH, "C must be ncols(A) x nrows(A)");
+  Ctx& c = ctx();
+  const MatP& a = ao->data;
+  auto m = std::make_shared<MatData>();
+  m->id = c.next_id++;
+  m->nrows = a->ncols;
+  m->ncols = a->nrows;
+  m->nnz = a->nnz;
+  m->rowptr = dev_alloc(sizeof(int) * (size_t)(m->nrows + 1));
+  if (a->nnz > 0) m->col = dev_alloc(sizeof(int) * (size_t)a->nnz);
+  hip_check(transpose_csr(a->nrows, a->ncols, (const int*)a->rowptr->p, a->col ? (const int*)a->col->p : nullptr,
+                          a->nnz, (int*)m->rowptr->p, m->col ? (int*)m->col->p : nullptr, tmp_alloc,
+                          tmp_release, nullptr, c.stream),
+            "transpose");
+  launch_mark(false);
+  co->data = m;
+  API_END
+}
+
+GrB_Info GrM_Matrix_row_degree(GrB_Vector deg, GrB_Matrix A) {
+  API_BEGIN
+  require_init();
+  GB_Vector_opaque* d = vec(deg, "deg");
+  GB_Matrix_opaque* a = mat(A, "A");
+  if (d->n != a->nrows) fail(GrB_DIMENSION_MISMATCH, "deg must have nrows(A) entries");
+  NodeP p = new_node(N_DENSE, d->type, d->n, false);
+  p->buf = dev_alloc(type_size(d->type) * (size_t)d->n);
+  hip_check(launch_row_degree((const int*)a->data->rowptr->p, a->nrows, p->buf->p, d->type, ctx().stream),
+            "row degree");
+  launch_mark(false);
+  p->done = true;
+  set_vec(d, p);
+  API_END
+}
+
+GrB_Info GrM_rmat_edges(uint32_t* src, uint32_t* dst, int scale, GrB_Index nedges, uint64_t seed, double ta,
+                        double tab, double tabc) {
+  API_BEGIN
+  require_init();
+  if (scale < 1 || scale > 31) fail(GrB_INVALID_VALUE, "scale must be in [1, 31]");
+  if (nedges > 0) {
+    need(src, "src");
+    need(dst, "dst");
+  }
+  hip_check(launch_rmat(src, dst, scale, (int64_t)nedges, seed, ta, tab, tabc, ctx().stream), "rmat");
+  launch_mark(false);
+  API_END
+}
+
+// ------------------------------------------------------------ operations
+
+GrB_Info GrB_mxv(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_Semiring op, GrB_Matrix A, GrB_Vector u,
+                 GrB_Descriptor desc) {
+  API_BEGIN
+  require_init();
+  (void)desc;
+  GB_Vector_opaque* wo = vec(w, "w");
+  GB_Vector_opaque* uo = vec(u, "u");
+  GB_Matrix_opaque* ao = mat(A, "A");
+  need(op, "semiring");
+  no_mask_accum(mask, accum);
+  if (ao->ncols != uo->n || ao->nrows != wo->n) fail(GrB_DIMENSION_MISMATCH, "mxv dimensions");
+  if (op->add != B_PLUS || (op->mul != B_TIMES && op->mul != B_SECOND))
+    fail(GrB_NOT_IMPLEMENTED, "only plus-times / plus-second semirings");
+  if (op->type != wo->type || op->type != uo->type) fail(GrB_DOMAIN_MISMATCH, "mxv types");
+  rec_mxv(wo, ao, uo);
+  API_END
+}
+
+static GrB_Info ewise_common(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_BinaryOp op, GrB_Vector u,
+                             GrB_Vector v) {
+  API_BEGIN
+  require_init();
+  GB_Vector_opaque* wo = vec(w, "w");
+  GB_Vector_opaque* uo = vec(u, "u");
+  GB_Vector_opaque* vo = vec(v, "v");
+  need(op, "op");
+  no_mask_accum(mask, accum);
+  if (uo->n != wo->n || vo->n != wo->n) fail(GrB_DIMENSION_MISMATCH, "vector lengths differ");
+  float_type(op->type, "operator");
+  if (op->type != wo->type || op->type != uo->type || op->type != vo->type)
+    fail(GrB_DOMAIN_MISMATCH, "operand types differ from the operator's");
+  rec_ewise(wo, op->op, uo, vo);
+  API_END
+}
+
+GrB_Info GrB_Vector_eWiseMult_BinaryOp(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_BinaryOp op,
+                                       GrB_Vector u, GrB_Vector v, GrB_Descriptor desc) {
+  (void)desc;
+  return ewise_common(w, mask, accum, op, u, v);
+}
+
+GrB_Info GrB_Vector_eWiseAdd_BinaryOp(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_BinaryOp op,
+                                      GrB_Vector u, GrB_Vector v, GrB_Descriptor desc) {
+  (void)desc;
+  return ewise_common(w, mask, accum, op, u, v);
+}
+
+GrB_Info GrB_Vector_apply(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_UnaryOp op, GrB_Vector u,
+                          GrB_Descriptor desc) {
+  API_BEGIN
+  require_init();
+  (void)desc;
+  GB_Vector_opaque* wo = vec(w, "w");
+  GB_Vector_opaque* uo = vec(u, "u");
+  need(op, "op");
+  no_mask_accum(mask, accum);
+  if (uo->n != wo->n) fail(GrB_DIMENSION_MISMATCH, "vector lengths differ");
+  if (op->type != wo->type) fail(GrB_DOMAIN_MISMATCH, "output type differs from the operator's");
+  rec_unop(wo, op->op, uo);
+  API_END
+}
+
+static GrB_Info bind_common(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_BinaryOp op, GrB_Vector u,
+                            double s, bool first) {
+  API_BEGIN
+  require_init();
+  GB_Vector_opaque* wo = vec(w, "w");
+  GB_Vector_opaque* uo = vec(u, "u");
+  need(op, "op");
+  no_mask_accum(mask, accum);
+  if (uo->n != wo->n) fail(GrB_DIMENSION_MISMATCH, "vector lengths differ");
+  float_type(op->type, "operator");
+  if (op->type != wo->type || op->type != uo->type) fail(GrB_DOMAIN_MISMATCH, "operand types");
+  rec_bind(wo, op->op, uo, s, first);
+  API_END
+}
+
+GrB_Info GrB_Vector_apply_BinaryOp1st_FP64(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_BinaryOp op,
+                                           double s, GrB_Vector u, GrB_Descriptor desc) {
+  (void)desc;
+  return bind_common(w, mask, accum, op, u, s, true);
+}
+
+GrB_Info GrB_Vector_apply_BinaryOp2nd_FP64(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_BinaryOp op,
+                                           GrB_Vector u, double s, GrB_Descriptor desc) {
+  (void)desc;
+  return bind_common(w, mask, accum, op, u, s, false);
+}
+
+GrB_Info GrB_Vector_apply_BinaryOp2nd_Scalar(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_BinaryOp op,
+                                             GrB_Vector u, GrB_Scalar s, GrB_Descriptor desc) {
+  API_BEGIN
+  require_init();
+  (void)desc;
+  GB_Vector_opaque* wo = vec(w, "w");
+  GB_Vector_opaque* uo = vec(u, "u");
+  GB_Scalar_opaque* so = sca(s, "s");
+  need(op, "op");
+  no_mask_accum(mask, accum);
+  if (uo->n != wo->n) fail(GrB_DIMENSION_MISMATCH, "vector lengths differ");
+  float_type(op->type, "operator");
+  if (op->type != wo->type || op->type != uo->type) fail(GrB_DOMAIN_MISMATCH, "operand types");
+  if (so->node->done && !so->node->has_value) fail(GrB_EMPTY_OBJECT, "scalar has no value");
+  rec_bind_scalar(wo, op->op, uo, so);
+  API_END
+}
+
+GrB_Info GrB_Vector_reduce_Monoid_Scalar(GrB_Scalar s, GrB_BinaryOp accum, GrB_Monoid monoid, GrB_Vector u,
+                                         GrB_Descriptor desc) {
+  API_BEGIN
+  require_init();
+  (void)desc;
+  GB_Scalar_opaque* so = sca(s, "s");
+  GB_Vector_opaque* uo = vec(u, "u");
+  need(monoid, "monoid");
+  if (accum) fail(GrB_NOT_IMPLEMENTED, "accumulators are not supported");
+  if (monoid->op != B_PLUS) fail(GrB_NOT_IMPLEMENTED, "only the plus monoid");
+  float_type(uo->type, "u");
+  rec_reduce(so, uo, nullptr, false, false);
+  API_END
+}
+
+GrB_Info GrB_Vector_reduce_FP64(double* s, GrB_BinaryOp accum, GrB_Monoid monoid, GrB_Vector u,
+                                GrB_Descriptor desc) {
+  API_BEGIN
+  require_init();
+  (void)desc;
+  need(s, "s");
+  GB_Vector_opaque* uo = vec(u, "u");
+  need(monoid, "monoid");
+  if (accum) fail(GrB_NOT_IMPLEMENTED, "accumulators are not supported");
+  if (monoid->op != B_PLUS) fail(GrB_NOT_IMPLEMENTED, "only the plus monoid");
+  float_type(uo->type, "u");
+  GB_Scalar_opaque tmp{MAGIC_SCA, T_FP64, nullptr};
+  rec_reduce(&tmp, uo, nullptr, false, false);
+  NodeP node = tmp.node;
+  materialize(node);
+  double h = 0.0;
+  hip_check(hipMemcpyAsync(&h, node->buf->p, sizeof(double), hipMemcpyDeviceToHost, ctx().stream), "copy");
+  hip_check(hipStreamSynchronize(ctx().stream), "sync");
+  set_sca(&tmp, nullptr);
+  *s = h;
+  API_END
+}
+
+GrB_Info GrM_Vector_reduce_masked_Scalar(GrB_Scalar s, GrB_Vector mask, GrB_Monoid monoid, GrB_Vector u,
+                                         GrB_Descriptor desc) {
+  API_BEGIN
+  require_init();
+  GB_Scalar_opaque* so = sca(s, "s");
+  GB_Vector_opaque* uo = vec(u, "u");
+  GB_Vector_opaque* mo = vec(mask, "mask");
+  need(monoid, "monoid");
+  if (monoid->op != B_PLUS) fail(GrB_NOT_IMPLEMENTED, "only the plus monoid");
+  if (mo->n != uo->n) fail(GrB_DIMENSION_MISMATCH, "mask length");
+  float_type(uo->type, "u");
+  rec_reduce(so, uo, mo, desc_comp(desc), false);
+  API_END
+}
+
+// ------------------------------------------------------------ PageRank
+
+GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, GrB_Vector outdeg, double damping,
+                      double tol, int itermax, GrM_Dangling dangling, GrB_Vector x0, int check_every) {
+  Ctx& c = ctx();
+  GuardDev* saved_guard = c.guard;
+  BufP gbuf;
+  API_BEGIN
+  require_init();
+  GB_Vector_opaque* ro = vec(r, "r");
+  need(iters, "iters");
+  need(resid, "resid");
+  GB_Matrix_opaque* ao = mat(AT, "AT");
+  GB_Vector_opaque* dego = vec(outdeg, "outdeg");
+  GB_Vector_opaque* xo = x0 ? vec(x0, "x0") : nullptr;
+  float_type(ro->type, "r");
+  const int T = ro->type;
+  const int64_t n = ao->nrows;
+  if (ao->ncols != n || ro->n != n || dego->n != n || (xo && xo->n != n))
+    fail(GrB_DIMENSION_MISMATCH, "pagerank dimensions");
+  if (dangling != GrM_DANGLING_DROP && dangling != GrM_DANGLING_UNIFORM) fail(GrB_INVALID_VALUE, "dangling mode");
+  if (check_every < 1 || itermax < 0 || !(damping >= 0.0 && damping < 1.0) || std::isnan(tol))
+    fail(GrB_INVALID_VALUE, "pagerank parameters");
+  if (c.guard) fail(GrB_INVALID_VALUE, "an iterative driver is already running");
+  const bool uniform = dangling == GrM_DANGLING_UNIFORM;
+  const double tele = (1.0 - damping) / (double)n;
+
+  // d = damping ./ outdeg (0 where outdeg = 0)
+  GB_Vector_opaque dinv{MAGIC_VEC, T, n, nullptr};
+  rec_unop(&dinv, U_MINV_OR_ZERO, dego);
+  rec_bind(&dinv, B_TIMES, &dinv, damping, true);
+  materialize(dinv.node);
+  store_if_iso(dinv.node);
+
+  GB_Vector_opaque x{MAGIC_VEC, T, n, nullptr};
+  if (xo) {
+    if (xo->type == T)
+      set_vec(&x, xo->node);
+    else
+      rec_unop(&x, U_IDENTITY, xo);
+  } else {
+    set_vec(&x, iso_node(T, n, 1.0 / (double)n));
+  }
+  materialize(x.node);
+  store_if_iso(x.node);
+
+  GB_Scalar_opaque D{MAGIC_SCA, T_FP64, nullptr};
+  if (uniform) rec_reduce(&D, &x, &dinv, true, false);
+
+  gbuf = dev_alloc(sizeof(GuardDev));
+  hip_check(launch_guard_init((GuardDev*)gbuf->p, (1.0 > tol && itermax > 0) ? 1 : 0, tol, itermax, c.stream),
+            "guard init");
+  launch_mark(false);
+  c.guard = (GuardDev*)gbuf->p;
+
+  std::vector<NodeP> hist{x.node};
+  int64_t base = 0;
+  GuardDev hg{};
+  for (;;) {
+    for (int j = 0; j < check_every; ++j) {
+      GB_Vector_opaque w{MAGIC_VEC, T, n, nullptr}, s{MAGIC_VEC, T, n, nullptr};
+      GB_Vector_opaque rn{MAGIC_VEC, T, n, nullptr}, t{MAGIC_VEC, T, n, nullptr};
+      GB_Scalar_opaque cs{MAGIC_SCA, T_FP64, nullptr}, rho{MAGIC_SCA, T_FP64, nullptr};
+      GB_Scalar_opaque Dn{MAGIC_SCA, T_FP64, nullptr};
+      rec_ewise(&w, B_TIMES, &x, &dinv);            // w = x .* d
+      rec_mxv(&s, ao, &w);                          // s = AT (+.second) w
+      if (uniform) {                                // r = c + s
+        rec_affine(&cs, damping / (double)n, &D, tele);
+        rec_bind_scalar(&rn, B_PLUS, &s, &cs);
+      } else {
+        rec_bind(&rn, B_PLUS, &s, tele, false);
+      }
+      rec_ewise(&t, B_ABSDIFF, &x, &rn);            // t = |x - r|
+      rec_reduce(&rho, &t, nullptr, false, true);   // rho = sum t  (advances the guard)
+      if (uniform) rec_reduce(&Dn, &rn, &dinv, true, false);  // D = sum r(outdeg = 0)
+      // only r, rho and D stay reachable: w, s, t and c become intermediates
+      set_vec(&w, nullptr);
+      set_vec(&s, nullptr);
+      set_vec(&t, nullptr);
+      set_sca(&cs, nullptr);
+      materialize(rn.node);
+      set_vec(&x, rn.node);
+      if (uniform) set_sca(&D, Dn.node);
+      hist.push_back(rn.node);
+      set_vec(&rn, nullptr);
+      set_sca(&rho, nullptr);
+      set_sca(&Dn, nullptr);
+    }
+    hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    if (!hg.active) break;
+    base += (int64_t)hist.size() - 1;
+    NodeP last = hist.back();
+    hist.assign(1, last);
+  }
+  const int64_t idx = (int64_t)hg.iters - base;
+  if (idx < 0 || idx >= (int64_t)hist.size()) fail(GrB_PANIC, "loop guard out of step");
+  c.guard = saved_guard;
+  set_vec(ro, hist[(size_t)idx]);
+  set_vec(&x, nullptr);
+  set_vec(&dinv, nullptr);
+  set_sca(&D, nullptr);
+  *iters = hg.iters;
+  *resid = hg.rho;
+  }
+  catch (const GrbError& e) {
+    c.guard = saved_guard;
+    g_err = e.msg;
+    return e.info;
+  }
+  catch (const std::exception& e) {
+    c.guard = saved_guard;
+    g_err = e.what();
+    return GrB_PANIC;
+  }
+  return GrB_SUCCESS;
+}
+
+// ------------------------------------------------------------ probe / timing
+
+GrB_Info GrM_stream_copy(void* dst, const void* src, size_t bytes) {
+  API_BEGIN
+  require_init();
+  need(dst, "dst");
+  need(src, "src");
+  hip_check(launch_stream_copy(dst, src, bytes, ctx().stream), "stream copy");
+  launch_mark(false);
+  API_END
+}
+
+GrB_Info GrM_timing_enable(bool on) {
+  API_BEGIN
+  require_init();
+  ctx().timing = on;
+  API_END
+}
+
+GrB_Info GrM_timing_read(double* total_ms, int64_t* launches) {
+  API_BEGIN
+  require_init();
+  need(total_ms, "total_ms");
+  need(launches, "launches");
+  Ctx& c = ctx();
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+  double tot = 0.0;
+  for (auto& e : c.events) {
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, e.first, e.second), "elapsed");
+    tot += ms;
+    c.event_pool.push_back(e.first);
+    c.event_pool.push_back(e.second);
+  }
+  *launches = (int64_t)c.events.size();
+  c.events.clear();
+  *total_ms = tot;
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+// Internal interface between the runtime (DAG, matcher, plans) and the
+// gfx950 kernels.  Nothing here is part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nbgrb {
+
+// Value type codes of dense vector storage.
+enum TypeCode : int { T_BOOL = 0, T_INT32 = 1, T_FP32 = 2, T_FP64 = 3 };
+
+inline size_t type_size(int t) {
+  switch (t) {
+    case T_BOOL: return 1;
+    case T_INT32: return 4;
+    case T_FP32: return 4;
+    default: return 8;
+  }
+}
+
+// Closed operator set.
+enum UnOp : int { U_IDENTITY = 0, U_ABS, U_AINV, U_MINV, U_MINV_OR_ZERO };
+enum BinOp : int {
+  B_PLUS = 0, B_MINUS, B_TIMES, B_DIV, B_MAX, B_MIN, B_FIRST, B_SECOND, B_ABSDIFF
+};
+
+// Device-side loop control of an iterative driver.  Kernels launched while
+// a guard is installed return at once when `active` is 0; the reduction
+// that produces the guarded residual updates it.
+struct GuardDev {
+  int active;     // 1 while another pass is wanted
+  int iters;      // passes completed
+  double rho;     // last residual
+  double tol;
+  int itermax;
+  int pad;
+};
+
+// Scalar operand: value = dev ? alpha * (*dev) + beta : beta.
+struct ScalarArg {
+  const double* dev;
+  double alpha;
+  double beta;
+};
+
+// Dense operand of an elementwise kernel: storage of type `type`, or an
+// iso value when p == nullptr.
+struct Operand {
+  const void* p;
+  int type;
+  double iso;
+};
+
+// Reduction target: the result goes to *out (FP64); if `guard` is set the
+// reduction also advances the guard with its result.
+struct ReduceOut {
+  double* out;
+  GuardDev* guard;
+};
+
+// Scratch of a deterministic two-level reduction (per-block partials + a
+// ticket for the last block).  `partials` holds 2 * nblocks doubles.
+struct RedScratch {
+  double* partials;
+  unsigned* ticket;  // zero before the launch; the last block resets it
+};
+
+// ------------------------------------------------------------------ tiles
+// Row tiles of a CSR pattern for the row-parallel kernels (built once per
+// matrix and tile geometry on the host).
+//   STREAM tile  : {row0, nrows > 0, e0, ne}  rows [row0,row0+nrows), their
+//                  ne entries start at e0; staged through LDS.
+//   LONG tile    : {row, 0, e0, ne} one row, reduced by the whole block.
+//   CHUNK tile   : {row, -(h+1), e0, ne} one chunk of hub row h; the block
+//                  that completes the last chunk finishes the row.
+// HubInfo h: {row, nchunks, first partial slot, first entry}.
+struct TilePlanDev {
+  const int4* tiles;
+  int ntiles;
+  const int4* hubs;
+  int nhubs;
+  int nparts;  // total chunk partial slots
+};
+
+// Epilogue of the fused PageRank pass, per row i with row sum s:
+//   mode PLAIN : s_out[i] = s
+//   mode PR    : r = tele(i) + s, tele(i) = tele_vec ? tele_vec[i] : c,
+//                c = (T)(c.alpha * (*c.dev) + c.beta) or (T)c.beta;
+//                r_out[i] = r; rho += |x_old[i] - r| (FP64);
+//                w_out[i] = memo_div ? r / dvec[i] : r * dvec[i];
+//                D += r where the mask selects i (FP64).
+enum EpiMode : int { EPI_PLAIN = 0, EPI_PR = 1 };
+
+template <typename T>
+struct FusedArgs {
+  const int* rowptr;
+  const int* col;
+  const T* w;  // gathered vector
+  int nrows;
+  int mode;
+  T* s_out;
+  T* r_out;
+  const T* x_old;     // residual against this vector (nullptr: none)
+  const T* dvec;      // prescale vector for the memo / the dvec mask
+  T* w_out;           // memo output (nullptr: none)
+  int memo_div;
+  int do_D;
+  int mask_is_dvec;   // mask = dvec (value mask)
+  Operand mask;       // otherwise this vector
+  int mask_comp;      // complement the mask
+  const T* tele_vec;  // per-row teleport (nullptr: scalar c)
+  ScalarArg c;
+  ReduceOut rho_out;
+  ReduceOut D_out;
+};
+
+struct FusedScratch {
+  double* wg_part;    // 2 per workgroup: (rho, D) partials
+  double* hub_sum;    // one slot per hub chunk: chunk row sums
+  int* hub_cnt;       // per hub: chunks finished (zero; the finisher resets)
+  double* hub_red;    // 2 per hub: (rho, D) of the hub row
+  unsigned* ticket;   // zero; the last workgroup resets it
+};
+
+// Geometry of the row-parallel kernels.
+constexpr int FUSED_BLOCK = 256;
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `s` and return the launch status.
+
+// Fused PageRank pass / plain SpMV over a tile plan.  grid = persistent
+// workgroup count; tiles are assigned round-robin, so the per-workgroup
+// partials are summed in a fixed order.  lds_entries = STREAM tile entry
+// budget the plan was built for; lds_rows = its row budget.
+hipError_t launch_fused_f32(const TilePlanDev& plan, const FusedArgs<float>& a,
+                            const FusedScratch& scr, int grid, int lds_entries, int lds_rows,
+                            const GuardDev* guard, hipStream_t s);
+hipError_t launch_fused_f64(const TilePlanDev& plan, const FusedArgs<double>& a,
+                            const FusedScratch& scr, int grid, int lds_entries, int lds_rows,
+                            const GuardDev* guard, hipStream_t s);
+
+// Elementwise: out[i] = f(a[i], b[i]) computed in `ct` (T_FP32 / T_FP64).
+//   kind 0: binary op(a, b); 1: unary op(a); 2: op(s, a); 3: op(a, s)
+enum EwKind : int { EW_BINARY = 0, EW_UNARY = 1, EW_BIND1ST = 2, EW_BIND2ND = 3 };
+hipError_t launch_ewise(int64_t n, int ct, int kind, int op, Operand a, Operand b,
+                        ScalarArg sc, void* out, int out_type, const GuardDev* guard,
+                        hipStream_t s);
+
+// Deterministic sum of x (selected by mask when use_mask) into out.out.
+constexpr int REDUCE_BLOCK = 256;
+constexpr int REDUCE_GRID = 1024;
+hipError_t launch_reduce(int64_t n, Operand x, int use_mask, Operand mask, int mask_comp,
+                         ReduceOut out, RedScratch scr, const GuardDev* guard, hipStream_t s);
+
+// out[0:n) = v converted to `type`.
+hipError_t launch_fill(void* out, int type, int64_t n, double v, hipStream_t s);
+// *dst = v (one double).
+hipError_t launch_set_scalar(double* dst, double v, hipStream_t s);
+// Copy with conversion between storage types.
+hipError_t launch_convert(const void* src, int src_type, void* dst, int dst_type, int64_t n,
+                          hipStream_t s);
+// Guard := {active, 0 iterations, rho, tol, itermax}.
+hipError_t launch_guard_init(GuardDev* g, int active, double tol, int itermax, hipStream_t s);
+// Zero n bytes with a kernel (no memset node, safe under graph capture).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// R-MAT edges, one thread per edge.
+hipError_t launch_rmat(uint32_t* src, uint32_t* dst, int scale, int64_t nedges, uint64_t seed,
+                       double ta, double tab, double tabc, hipStream_t s);
+
+// Streaming copy probe (bytes multiple of 16).
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// Row degree deg[i] = rowptr[i+1] - rowptr[i] written as `type`.
+hipError_t launch_row_degree(const int* rowptr, int64_t n, void* deg, int type, hipStream_t s);
+
+// CSR validity check: flag[0] != 0 afterwards if rowptr is not a valid
+// non-decreasing 0..nnz sequence or a column is outside [0, ncols).
+hipError_t launch_check_csr(const int* rowptr, int64_t nrows, const int* col, int64_t nnz,
+                            int64_t ncols, int* flag, hipStream_t s);
+
+// ------------------------------------------------------------ graph build
+// (graph_build.hip) Sort-based construction of a CSR pattern from an edge
+// list.  Temporary device memory comes from `alloc` / `release`.
+typedef void* (*AllocFn)(size_t bytes, void* ctx);
+typedef void (*ReleaseFn)(void* p, void* ctx);
+
+// Builds rowptr (n+1) and col (capacity nedges) from (src,dst); *nnz gets
+// the number of distinct edges.  bad_flag[0] is set if an endpoint >= n.
+// Synchronises `s` once to read the count back.
+hipError_t build_csr_from_edges(int64_t n, const uint32_t* src, const uint32_t* dst,
+                                int64_t nedges, bool drop_self, int* rowptr, int* col,
+                                int64_t* nnz, int* bad_flag, AllocFn alloc, ReleaseFn release,
+                                void* actx, hipStream_t s);
+
+// Transpose of an nrows x ncols pattern: rowptrT (ncols+1), colT (nnz).
+hipError_t transpose_csr(int64_t nrows, int64_t ncols, const int* rowptr, const int* col,
+                         int64_t nnz, int* rowptrT, int* colT, AllocFn alloc,
+                         ReleaseFn release, void* actx, hipStream_t s);
+
+}  // namespace nbgrb

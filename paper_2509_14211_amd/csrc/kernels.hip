@@ -1,0 +1,682 @@
+// gfx950 kernels of the nonblocking GraphBLAS PageRank path.
+//
+// The central kernel is the fused PageRank pass (paper, Fig. 6: the
+// ewise_mult, mxv and ewise_add that the nonblocking DAG materialises at
+// wait(r), plus the absdiff/reduce pair behind rdiff(), here also the
+// dangling-mass reduction), run over a tile plan of the transposed
+// adjacency pattern:
+//   * STREAM tiles (runs of short rows) gather their entries' operand
+//     values into LDS with coalesced, non-temporal column reads, then reduce
+//     each row from LDS with a power-of-two group of lanes per row chosen
+//     from the tile's row count, finishing with cross-lane shuffles;
+//   * LONG tiles (one row) are summed by the whole workgroup;
+//   * CHUNK tiles split a hub row over several workgroups; the workgroup
+//     that completes the last chunk adds the chunk sums in chunk order and
+//     finishes the row.
+// The per-row epilogue applies the teleport/dangling constant, writes the
+// new rank, the pre-scaled copy the next pass gathers, and accumulates the
+// L1 residual and the dangling mass in FP64.  Partials are combined in a
+// fixed order by the last workgroup, so results are bitwise reproducible.
+//
+// Cross-workgroup hand-off (hub chunks, workgroup partials) publishes values
+// with device-scope atomic stores, waits for their completion, then bumps a
+// counter; readers use device-scope atomic loads.  This avoids L2
+// write-back / invalidate fences in the middle of the pass.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace nbgrb {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ void wait_stores() {
+  // s_waitcnt vmcnt(0): every vector memory operation of this wave is done.
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
+template <typename V>
+__device__ __forceinline__ void publish(V* p, V v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename V>
+__device__ __forceinline__ V consume(const V* p) {
+  return __hip_atomic_load(const_cast<V*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned ticket_add(unsigned* p) {
+  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int counter_add(int* p) {
+  return __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename V>
+__device__ __forceinline__ V wave_sum(V v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the block in a fixed tree; the result is valid in thread 0.
+template <typename V, int B>
+__device__ __forceinline__ V block_sum(V v, V* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  V r = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < B / 64; ++i) r += red[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T load_as(const Operand& o, int64_t i) {
+  if (!o.p) return (T)o.iso;
+  switch (o.type) {
+    case T_BOOL: return (T)(((const uint8_t*)o.p)[i]);
+    case T_INT32: return (T)(((const int*)o.p)[i]);
+    case T_FP32: return (T)(((const float*)o.p)[i]);
+    default: return (T)(((const double*)o.p)[i]);
+  }
+}
+
+__device__ __forceinline__ bool nonzero_at(const Operand& o, int64_t i) {
+  if (!o.p) return o.iso != 0.0;
+  switch (o.type) {
+    case T_BOOL: return ((const uint8_t*)o.p)[i] != 0;
+    case T_INT32: return ((const int*)o.p)[i] != 0;
+    case T_FP32: return ((const float*)o.p)[i] != 0.0f;
+    default: return ((const double*)o.p)[i] != 0.0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_as(void* p, int type, int64_t i, T v) {
+  switch (type) {
+    case T_BOOL: ((uint8_t*)p)[i] = (uint8_t)(v != (T)0); break;
+    case T_INT32: ((int*)p)[i] = (int)v; break;
+    case T_FP32: ((float*)p)[i] = (float)v; break;
+    default: ((double*)p)[i] = (double)v; break;
+  }
+}
+
+__device__ __forceinline__ double scalar_value(const ScalarArg& s) {
+  return s.dev ? s.alpha * (*s.dev) + s.beta : s.beta;
+}
+
+template <typename T>
+__device__ __forceinline__ T apply_binop(int op, T x, T y) {
+  switch (op) {
+    case B_PLUS: return x + y;
+    case B_MINUS: return x - y;
+    case B_TIMES: return x * y;
+    case B_DIV: return x / y;
+    case B_MAX: return x > y ? x : y;
+    case B_MIN: return x < y ? x : y;
+    case B_FIRST: return x;
+    case B_SECOND: return y;
+    default: return fabs(x - y);  // B_ABSDIFF
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T apply_unop(int op, T x) {
+  switch (op) {
+    case U_IDENTITY: return x;
+    case U_ABS: return fabs(x);
+    case U_AINV: return -x;
+    case U_MINV: return (T)1 / x;
+    default: return x != (T)0 ? (T)1 / x : (T)0;  // U_MINV_OR_ZERO
+  }
+}
+
+// Called by thread 0 of the block that produced a guarded residual.
+__device__ __forceinline__ void guard_advance(GuardDev* g, double rho) {
+  g->rho = rho;
+  const int it = g->iters + 1;
+  g->iters = it;
+  g->active = (rho > g->tol && it < g->itermax) ? 1 : 0;
+}
+
+// ---------------------------------------------------------- fused PR pass
+
+template <typename T>
+__device__ __forceinline__ void pr_epilogue(const FusedArgs<T>& a, int i, T s, T c, double& rho,
+                                            double& dm) {
+  if (a.mode == EPI_PLAIN) {
+    a.s_out[i] = s;
+    return;
+  }
+  const T tele = a.tele_vec ? a.tele_vec[i] : c;
+  const T r = tele + s;
+  if (a.r_out) __builtin_nontemporal_store(r, a.r_out + i);
+  if (a.x_old) rho += fabs((double)__builtin_nontemporal_load(a.x_old + i) - (double)r);
+  T dv = (T)0;
+  if (a.dvec) dv = __builtin_nontemporal_load(a.dvec + i);
+  if (a.w_out) a.w_out[i] = a.memo_div ? r / dv : r * dv;
+  if (a.do_D) {
+    const bool m = a.mask_is_dvec ? (dv != (T)0) : nonzero_at(a.mask, i);
+    if (m != (a.mask_comp != 0)) dm += (double)r;
+  }
+}
+
+// Gather w[col[k]] for k in [0, ne) into sval, eight loads in flight per
+// thread.  Column indices are streamed once, so they are read non-temporal.
+template <typename T, int B>
+__device__ __forceinline__ void gather_to_lds(const int* __restrict__ col, const T* __restrict__ w,
+                                              int ne, T* __restrict__ sval) {
+  int k = threadIdx.x;
+  for (; k + 7 * B < ne; k += 8 * B) {
+    int c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = __builtin_nontemporal_load(col + k + u * B);
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = w[c[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sval[k + u * B] = v[u];
+  }
+  for (; k < ne; k += B) sval[k] = w[__builtin_nontemporal_load(col + k)];
+}
+
+// Per-thread partial sum of w[col[k]], k in [0, ne), in a fixed order.
+template <typename T, int B>
+__device__ __forceinline__ T gather_sum(const int* __restrict__ col, const T* __restrict__ w,
+                                        int ne) {
+  T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+  int k = threadIdx.x;
+  for (; k + 7 * B < ne; k += 8 * B) {
+    int c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = __builtin_nontemporal_load(col + k + u * B);
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = w[c[u]];
+    acc0 += v[0] + v[4];
+    acc1 += v[1] + v[5];
+    acc2 += v[2] + v[6];
+    acc3 += v[3] + v[7];
+  }
+  for (; k < ne; k += B) acc0 += w[__builtin_nontemporal_load(col + k)];
+  return (acc0 + acc1) + (acc2 + acc3);
+}
+
+template <typename T, int ET, int RT>
+__global__ __launch_bounds__(FUSED_BLOCK) void fused_pr_kernel(TilePlanDev plan, FusedArgs<T> a,
+                                                               FusedScratch scr,
+                                                               const GuardDev* guard) {
+  constexpr int B = FUSED_BLOCK;
+  if (guard && guard->active == 0) return;
+
+  __shared__ T sval[ET];
+  __shared__ int srp[RT + 1];
+  __shared__ T sres[RT];
+  __shared__ double sred[B / 64];
+  __shared__ T sredT[B / 64];
+  __shared__ int sflag;
+
+  const int tid = threadIdx.x;
+  T c = (T)0;
+  if (a.mode == EPI_PR) c = (T)scalar_value(a.c);
+  double rho = 0.0, dm = 0.0;
+
+  for (int t = blockIdx.x; t < plan.ntiles; t += gridDim.x) {
+    const int4 td = plan.tiles[t];
+    if (td.y > 0) {
+      // ---- STREAM tile
+      const int row0 = td.x, nr = td.y, e0 = td.z, ne = td.w;
+      for (int k = tid; k <= nr; k += B) srp[k] = a.rowptr[row0 + k] - e0;
+      gather_to_lds<T, B>(a.col + e0, a.w, ne, sval);
+      __syncthreads();
+      const int q = B / nr;
+      const int lpr = q >= 64 ? 64 : q >= 32 ? 32 : q >= 16 ? 16 : q >= 8 ? 8 : q >= 4 ? 4 : q >= 2 ? 2 : 1;
+      const int slots = B / lpr;
+      const int grp = tid / lpr, lane = tid & (lpr - 1);
+      const int rounds = (nr + slots - 1) / slots;
+      for (int rd = 0; rd < rounds; ++rd) {
+        const int rr = rd * slots + grp;
+        T v = 0;
+        if (rr < nr) {
+          const int hi = srp[rr + 1];
+          for (int k = srp[rr] + lane; k < hi; k += lpr) v += sval[k];
+        }
+        for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0 && rr < nr) sres[rr] = v;
+      }
+      __syncthreads();
+      for (int k = tid; k < nr; k += B) pr_epilogue(a, row0 + k, sres[k], c, rho, dm);
+      __syncthreads();
+    } else {
+      // ---- LONG or CHUNK tile
+      const int e0 = td.z, ne = td.w;
+      const T part = gather_sum<T, B>(a.col + e0, a.w, ne);
+      const T tot = block_sum<T, B>(part, sredT);
+      if (td.y == 0) {
+        if (tid == 0) pr_epilogue(a, td.x, tot, c, rho, dm);
+      } else {
+        const int h = -td.y - 1;
+        const int4 hub = plan.hubs[h];  // {row, nchunks, slot0, -}
+        if (tid == 0) {
+          publish(&scr.hub_sum[hub.z + td.x], (double)tot);
+          wait_stores();
+          sflag = counter_add(&scr.hub_cnt[h]) == hub.y - 1;
+        }
+        __syncthreads();
+        if (sflag) {
+          // This block finished the hub's last chunk: add the chunk sums
+          // (fixed tree over chunk order) and finish the row.
+          T s = 0;
+          for (int k = tid; k < hub.y; k += B) s += (T)consume(&scr.hub_sum[hub.z + k]);
+          s = block_sum<T, B>(s, sredT);
+          if (tid == 0) {
+            double hr = 0.0, hd = 0.0;
+            pr_epilogue(a, hub.x, s, c, hr, hd);
+            publish(&scr.hub_red[2 * h], hr);
+            publish(&scr.hub_red[2 * h + 1], hd);
+            publish(&scr.hub_cnt[h], 0);
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  const bool reduce = a.mode == EPI_PR && (a.rho_out.out || a.D_out.out || a.rho_out.guard);
+  if (!reduce) return;
+
+  const double br = block_sum<double, B>(rho, sred);
+  const double bd = block_sum<double, B>(dm, sred);
+  if (tid == 0) {
+    publish(&scr.wg_part[2 * blockIdx.x], br);
+    publish(&scr.wg_part[2 * blockIdx.x + 1], bd);
+    wait_stores();
+    const unsigned prev = ticket_add(scr.ticket);
+    sflag = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!sflag) return;
+
+  // Last workgroup: partials in workgroup order, then hub rows in order.
+  double pr = 0.0, pd = 0.0;
+  for (int k = tid; k < (int)gridDim.x; k += B) {
+    pr += consume(&scr.wg_part[2 * k]);
+    pd += consume(&scr.wg_part[2 * k + 1]);
+  }
+  for (int h = tid; h < plan.nhubs; h += B) {
+    pr += consume(&scr.hub_red[2 * h]);
+    pd += consume(&scr.hub_red[2 * h + 1]);
+  }
+  const double tr = block_sum<double, B>(pr, sred);
+  const double tdm = block_sum<double, B>(pd, sred);
+  if (tid == 0) {
+    if (a.rho_out.out) *a.rho_out.out = tr;
+    if (a.D_out.out) *a.D_out.out = tdm;
+    if (a.rho_out.guard) guard_advance(a.rho_out.guard, tr);
+    publish(scr.ticket, 0u);
+  }
+}
+
+template <typename T, int ET, int RT>
+static hipError_t launch_fused_t(const TilePlanDev& plan, const FusedArgs<T>& a,
+                                 const FusedScratch& scr, int grid, const GuardDev* guard,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL((fused_pr_kernel<T, ET, RT>), dim3(grid), dim3(FUSED_BLOCK), 0, s, plan, a,
+                     scr, guard);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_fused_dispatch(const TilePlanDev& plan, const FusedArgs<T>& a,
+                                        const FusedScratch& scr, int grid, int lds_entries,
+                                        int lds_rows, const GuardDev* guard, hipStream_t s) {
+  if (grid <= 0) return hipErrorInvalidValue;
+  if (lds_entries == 1024 && lds_rows == 512)
+    return launch_fused_t<T, 1024, 512>(plan, a, scr, grid, guard, s);
+  if (lds_entries == 2048 && lds_rows == 1024)
+    return launch_fused_t<T, 2048, 1024>(plan, a, scr, grid, guard, s);
+  if (lds_entries == 4096 && lds_rows == 1024)
+    return launch_fused_t<T, 4096, 1024>(plan, a, scr, grid, guard, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused_f32(const TilePlanDev& plan, const FusedArgs<float>& a,
+                            const FusedScratch& scr, int grid, int lds_entries, int lds_rows,
+                            const GuardDev* guard, hipStream_t s) {
+  return launch_fused_dispatch<float>(plan, a, scr, grid, lds_entries, lds_rows, guard, s);
+}
+
+hipError_t launch_fused_f64(const TilePlanDev& plan, const FusedArgs<double>& a,
+                            const FusedScratch& scr, int grid, int lds_entries, int lds_rows,
+                            const GuardDev* guard, hipStream_t s) {
+  return launch_fused_dispatch<double>(plan, a, scr, grid, lds_entries, lds_rows, guard, s);
+}
+
+// ---------------------------------------------------------- elementwise
+
+constexpr int EW_BLOCK = 256;
+
+template <typename T>
+__global__ __launch_bounds__(EW_BLOCK) void ewise_kernel(int64_t n, int kind, int op, Operand a,
+                                                         Operand b, ScalarArg sc, void* out,
+                                                         int out_type, const GuardDev* guard) {
+  if (guard && guard->active == 0) return;
+  const T sv = (T)scalar_value(sc);
+  const int64_t stride = (int64_t)gridDim.x * EW_BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * EW_BLOCK + threadIdx.x; i < n; i += stride) {
+    const T x = load_as<T>(a, i);
+    T r;
+    switch (kind) {
+      case EW_BINARY: r = apply_binop<T>(op, x, load_as<T>(b, i)); break;
+      case EW_UNARY: r = apply_unop<T>(op, x); break;
+      case EW_BIND1ST: r = apply_binop<T>(op, sv, x); break;
+      default: r = apply_binop<T>(op, x, sv); break;
+    }
+    store_as<T>(out, out_type, i, r);
+  }
+}
+
+// Dense same-type fast path: four elements in flight per thread.
+template <typename T>
+__global__ __launch_bounds__(EW_BLOCK) void ewise_fast_kernel(int64_t n, int kind, int op,
+                                                              const T* __restrict__ a, T aiso,
+                                                              const T* __restrict__ b, T biso,
+                                                              ScalarArg sc, T* __restrict__ out,
+                                                              const GuardDev* guard) {
+  if (guard && guard->active == 0) return;
+  const T sv = (T)scalar_value(sc);
+  const int64_t stride = (int64_t)gridDim.x * EW_BLOCK;
+  int64_t i = (int64_t)blockIdx.x * EW_BLOCK + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    T x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = a ? a[i + u * stride] : aiso;
+    if (kind == EW_BINARY) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] = b ? b[i + u * stride] : biso;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      T r;
+      switch (kind) {
+        case EW_BINARY: r = apply_binop<T>(op, x[u], y[u]); break;
+        case EW_UNARY: r = apply_unop<T>(op, x[u]); break;
+        case EW_BIND1ST: r = apply_binop<T>(op, sv, x[u]); break;
+        default: r = apply_binop<T>(op, x[u], sv); break;
+      }
+      out[i + u * stride] = r;
+    }
+  }
+  for (; i < n; i += stride) {
+    const T x = a ? a[i] : aiso;
+    T r;
+    switch (kind) {
+      case EW_BINARY: r = apply_binop<T>(op, x, b ? b[i] : biso); break;
+      case EW_UNARY: r = apply_unop<T>(op, x); break;
+      case EW_BIND1ST: r = apply_binop<T>(op, sv, x); break;
+      default: r = apply_binop<T>(op, x, sv); break;
+    }
+    out[i] = r;
+  }
+}
+
+static int ew_grid(int64_t n, int per_thread) {
+  int64_t g = (n + (int64_t)EW_BLOCK * per_thread - 1) / ((int64_t)EW_BLOCK * per_thread);
+  if (g < 1) g = 1;
+  if (g > 16384) g = 16384;
+  return (int)g;
+}
+
+hipError_t launch_ewise(int64_t n, int ct, int kind, int op, Operand a, Operand b, ScalarArg sc,
+                        void* out, int out_type, const GuardDev* guard, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const bool a_ok = !a.p || a.type == ct;
+  const bool b_ok = kind != EW_BINARY || !b.p || b.type == ct;
+  if (a_ok && b_ok && out_type == ct && (ct == T_FP32 || ct == T_FP64)) {
+    const int g = ew_grid(n, 4);
+    if (ct == T_FP32)
+      hipLaunchKernelGGL(ewise_fast_kernel<float>, dim3(g), dim3(EW_BLOCK), 0, s, n, kind, op,
+                         (const float*)a.p, (float)a.iso, (const float*)b.p, (float)b.iso, sc,
+                         (float*)out, guard);
+    else
+      hipLaunchKernelGGL(ewise_fast_kernel<double>, dim3(g), dim3(EW_BLOCK), 0, s, n, kind, op,
+                         (const double*)a.p, a.iso, (const double*)b.p, b.iso, sc,
+                         (double*)out, guard);
+    return hipGetLastError();
+  }
+  const int g = ew_grid(n, 2);
+  if (ct == T_FP32)
+    hipLaunchKernelGGL(ewise_kernel<float>, dim3(g), dim3(EW_BLOCK), 0, s, n, kind, op, a, b, sc,
+                       out, out_type, guard);
+  else
+    hipLaunchKernelGGL(ewise_kernel<double>, dim3(g), dim3(EW_BLOCK), 0, s, n, kind, op, a, b,
+                       sc, out, out_type, guard);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- reduction
+
+__global__ __launch_bounds__(REDUCE_BLOCK) void reduce_kernel(int64_t n, Operand x, int use_mask,
+                                                              Operand mask, int mask_comp,
+                                                              ReduceOut out, RedScratch scr,
+                                                              const GuardDev* guard) {
+  constexpr int B = REDUCE_BLOCK;
+  if (guard && guard->active == 0) return;
+  __shared__ double sred[B / 64];
+  __shared__ int sflag;
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * B;
+  for (int64_t i = (int64_t)blockIdx.x * B + tid; i < n; i += stride) {
+    if (use_mask && (nonzero_at(mask, i) == (mask_comp != 0))) continue;
+    acc += load_as<double>(x, i);
+  }
+  const double b = block_sum<double, B>(acc, sred);
+  if (tid == 0) {
+    publish(&scr.partials[blockIdx.x], b);
+    wait_stores();
+    sflag = ticket_add(scr.ticket) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!sflag) return;
+  double p = 0.0;
+  for (int k = tid; k < (int)gridDim.x; k += B) p += consume(&scr.partials[k]);
+  const double tot = block_sum<double, B>(p, sred);
+  if (tid == 0) {
+    if (out.out) *out.out = tot;
+    if (out.guard) guard_advance(out.guard, tot);
+    publish(scr.ticket, 0u);
+  }
+}
+
+hipError_t launch_reduce(int64_t n, Operand x, int use_mask, Operand mask, int mask_comp,
+                         ReduceOut out, RedScratch scr, const GuardDev* guard, hipStream_t s) {
+  int64_t g = (n + REDUCE_BLOCK * 4 - 1) / (REDUCE_BLOCK * 4);
+  if (g < 1) g = 1;
+  if (g > REDUCE_GRID) g = REDUCE_GRID;
+  hipLaunchKernelGGL(reduce_kernel, dim3((int)g), dim3(REDUCE_BLOCK), 0, s, n, x, use_mask, mask,
+                     mask_comp, out, scr, guard);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- small kernels
+
+__global__ void fill_kernel(void* out, int type, int64_t n, double v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    store_as<double>(out, type, i, v);
+}
+
+hipError_t launch_fill(void* out, int type, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(ew_grid(n, 4)), dim3(EW_BLOCK), 0, s, out, type, n, v);
+  return hipGetLastError();
+}
+
+__global__ void set_scalar_kernel(double* dst, double v) { *dst = v; }
+
+hipError_t launch_set_scalar(double* dst, double v, hipStream_t s) {
+  hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, s, dst, v);
+  return hipGetLastError();
+}
+
+__global__ void convert_kernel(Operand src, void* dst, int dst_type, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (dst_type == T_FP32)
+      ((float*)dst)[i] = load_as<float>(src, i);
+    else
+      store_as<double>(dst, dst_type, i, load_as<double>(src, i));
+  }
+}
+
+hipError_t launch_convert(const void* src, int src_type, void* dst, int dst_type, int64_t n,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  Operand o{src, src_type, 0.0};
+  hipLaunchKernelGGL(convert_kernel, dim3(ew_grid(n, 4)), dim3(EW_BLOCK), 0, s, o, dst, dst_type,
+                     n);
+  return hipGetLastError();
+}
+
+__global__ void guard_init_kernel(GuardDev* g, int active, double tol, int itermax) {
+  g->active = active;
+  g->iters = 0;
+  g->rho = 1.0;
+  g->tol = tol;
+  g->itermax = itermax;
+  g->pad = 0;
+}
+
+hipError_t launch_guard_init(GuardDev* g, int active, double tol, int itermax, hipStream_t s) {
+  hipLaunchKernelGGL(guard_init_kernel, dim3(1), dim3(1), 0, s, g, active, tol, itermax);
+  return hipGetLastError();
+}
+
+__global__ void zero_kernel(uint8_t* p, size_t bytes) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t words = bytes / 4;
+  uint32_t* w = (uint32_t*)p;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) w[i] = 0u;
+  for (size_t i = words * 4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < bytes;
+       i += stride)
+    p[i] = 0;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (((uintptr_t)p & 3u) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zero_kernel, dim3(ew_grid((int64_t)(bytes / 4 + 1), 4)), dim3(EW_BLOCK), 0, s,
+                     (uint8_t*)p, bytes);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- R-MAT
+
+// SplitMix64 as a counter-based generator: draw k of the stream seeded
+// with `seed` is the output after k+1 increments of the state.
+__device__ __forceinline__ uint64_t splitmix_draw(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void rmat_kernel(uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int scale,
+                            int64_t nedges, uint64_t seed, double ta, double tab, double tabc) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nedges; e += stride) {
+    uint32_t su = 0, dv = 0;
+    uint64_t k = (uint64_t)e * (uint64_t)scale;
+    for (int l = 0; l < scale; ++l, ++k) {
+      const double u = (double)(splitmix_draw(seed, k) >> 11) * 0x1.0p-53;
+      const uint32_t bs = u >= tab ? 1u : 0u;                       // c or d
+      const uint32_t bd = (u >= ta && u < tab) || u >= tabc ? 1u : 0u;  // b or d
+      su = (su << 1) | bs;
+      dv = (dv << 1) | bd;
+    }
+    src[e] = su;
+    dst[e] = dv;
+  }
+}
+
+hipError_t launch_rmat(uint32_t* src, uint32_t* dst, int scale, int64_t nedges, uint64_t seed,
+                       double ta, double tab, double tabc, hipStream_t s) {
+  if (nedges <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rmat_kernel, dim3(ew_grid(nedges, 4)), dim3(EW_BLOCK), 0, s, src, dst, scale,
+                     nedges, seed, ta, tab, tabc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- probes / misc
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void stream_copy_kernel(u32x4* __restrict__ dst,
+                                                          const u32x4* __restrict__ src,
+                                                          int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+  }
+  for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if ((bytes & 15u) || ((uintptr_t)dst & 15u) || ((uintptr_t)src & 15u)) return hipErrorInvalidValue;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  int64_t g = (n16 + 256 * 4 - 1) / (256 * 4);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(stream_copy_kernel, dim3((int)g), dim3(256), 0, s, (u32x4*)dst,
+                     (const u32x4*)src, n16);
+  return hipGetLastError();
+}
+
+__global__ void row_degree_kernel(const int* rowptr, int64_t n, void* deg, int type) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    store_as<double>(deg, type, i, (double)(rowptr[i + 1] - rowptr[i]));
+}
+
+hipError_t launch_row_degree(const int* rowptr, int64_t n, void* deg, int type, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(row_degree_kernel, dim3(ew_grid(n, 4)), dim3(EW_BLOCK), 0, s, rowptr, n, deg,
+                     type);
+  return hipGetLastError();
+}
+
+__global__ void check_csr_kernel(const int* rowptr, int64_t nrows, const int* col, int64_t nnz,
+                                 int64_t ncols, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0 && (rowptr[0] != 0 || (int64_t)rowptr[nrows] != nnz)) atomicOr(flag, 1);
+  for (int64_t i = tid; i < nrows; i += stride)
+    if (rowptr[i + 1] < rowptr[i]) atomicOr(flag, 1);
+  for (int64_t e = tid; e < nnz; e += stride)
+    if (col[e] < 0 || (int64_t)col[e] >= ncols) atomicOr(flag, 2);
+}
+
+hipError_t launch_check_csr(const int* rowptr, int64_t nrows, const int* col, int64_t nnz,
+                            int64_t ncols, int* flag, hipStream_t s) {
+  const int64_t work = nrows > nnz ? nrows : nnz;
+  hipLaunchKernelGGL(check_csr_kernel, dim3(ew_grid(work + 1, 4)), dim3(EW_BLOCK), 0, s, rowptr,
+                     nrows, col, nnz, ncols, flag);
+  return hipGetLastError();
+}
+
+}  // namespace nbgrb

@@ -1,0 +1,241 @@
+// Host-side runtime of the nonblocking GraphBLAS library: device memory,
+// versioned objects, the DAG of pending operations and its scheduler.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.h"
+#include "../../include/nbgrb.h"
+
+namespace nbgrb {
+
+// Internal error carrying a GraphBLAS return code; caught at the C ABI.
+struct GrbError {
+  GrB_Info info;
+  std::string msg;
+};
+
+[[noreturn]] void fail(GrB_Info info, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+
+// ------------------------------------------------------------ device memory
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf();
+};
+using BufP = std::shared_ptr<DevBuf>;
+
+// Allocate from the size-keyed cache (or the allocator on a miss).
+BufP dev_alloc(size_t bytes);
+
+// ------------------------------------------------------------ operators
+
+struct OpInfo {
+  int kind;  // 0 unary, 1 binary
+  int op;
+  int type;
+};
+
+// ------------------------------------------------------------ matrices
+
+struct Plan;
+
+struct MatData {
+  uint64_t id = 0;
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  BufP rowptr, col;
+  std::map<std::tuple<int, int, int, int, int>, std::shared_ptr<Plan>> plans;
+};
+using MatP = std::shared_ptr<MatData>;
+
+// Tile plan of one matrix for the row-parallel kernels.
+struct PlanConfig {
+  int lds_entries = 2048;  // STREAM tile entry budget
+  int lds_rows = 1024;     // STREAM tile row budget
+  int long_row = 512;      // rows longer than this get their own tile
+  int chunk = 8192;        // rows longer than this are split in chunks
+  int grid = 0;            // persistent workgroups (0: from the device)
+  bool operator<(const PlanConfig& o) const {
+    return std::tie(lds_entries, lds_rows, long_row, chunk, grid) <
+           std::tie(o.lds_entries, o.lds_rows, o.long_row, o.chunk, o.grid);
+  }
+};
+
+struct Plan {
+  PlanConfig cfg;
+  int ntiles = 0, nhubs = 0, nparts = 0;
+  int nstream = 0, nlong = 0, nchunk = 0;
+  BufP tiles, hubs, hub_sum, hub_cnt, hub_red;
+  TilePlanDev dev{};
+};
+
+std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg);
+PlanConfig default_plan_config(const MatP& A, int value_type);
+
+// ------------------------------------------------------------ DAG nodes
+
+enum NodeKind : int {
+  N_DENSE = 0,   // materialised vector (storage or iso value)
+  N_EWISE,       // w = op(a, b)
+  N_APPLY_U,     // w = op(a)
+  N_APPLY_B1,    // w = op(k, a)
+  N_APPLY_B2,    // w = op(a, k)
+  N_APPLY_B2S,   // w = op(a, scalar s)
+  N_MXV,         // w = A (+.*) a
+  N_REDUCE,      // scalar = sum a
+  N_REDUCE_MASK, // scalar = sum a(mask)
+  N_SCALAR,      // materialised scalar
+  N_AFFINE,      // scalar = alpha * s + beta
+};
+
+struct Node;
+using NodeP = std::shared_ptr<Node>;
+
+struct Node {
+  uint64_t id = 0;
+  NodeKind kind = N_DENSE;
+  int type = T_FP64;   // value type
+  int64_t n = 0;       // vector length (0 for scalars)
+  bool scalar = false;
+  NodeP a, b, s, mask;
+  bool mask_comp = false;
+  MatP A;
+  int op = 0;
+  double k = 0.0, alpha = 1.0, beta = 0.0;
+
+  bool done = false;
+  bool pending = false;    // recorded in nonblocking mode, not yet run
+  BufP buf;                // storage (vectors) / one double (scalars)
+  bool iso = false;        // materialised vector with one value, no storage
+  double iso_val = 0.0;
+  bool has_value = true;   // scalars: false until assigned
+  int handles = 0;         // user handles pointing here
+  bool guard_watch = false;  // this scalar advances the loop guard
+
+  // Pre-scaled copy of this vector (value .* dvec or ./ dvec) produced as a
+  // side output by the fused pass, keyed by operator and dvec node id.
+  BufP memo;
+  int memo_op = -1;
+  uint64_t memo_dvec = 0;
+
+  ~Node();
+};
+
+// ------------------------------------------------------------ handles
+
+constexpr uint32_t MAGIC_VEC = 0x56454331u;
+constexpr uint32_t MAGIC_SCA = 0x53434131u;
+constexpr uint32_t MAGIC_MAT = 0x4d415431u;
+constexpr uint32_t MAGIC_FREED = 0xdeadbeefu;
+
+}  // namespace nbgrb
+
+struct GB_Type_opaque {
+  int code;
+};
+struct GB_UnaryOp_opaque {
+  int op;
+  int type;
+};
+struct GB_BinaryOp_opaque {
+  int op;
+  int type;
+};
+struct GB_Monoid_opaque {
+  int op;
+  int type;
+};
+struct GB_Semiring_opaque {
+  int add;
+  int mul;
+  int type;
+};
+struct GB_Descriptor_opaque {
+  bool mask_comp;
+};
+struct GB_Vector_opaque {
+  uint32_t magic;
+  int type;
+  int64_t n;
+  nbgrb::NodeP node;
+};
+struct GB_Scalar_opaque {
+  uint32_t magic;
+  int type;
+  nbgrb::NodeP node;
+};
+struct GB_Matrix_opaque {
+  uint32_t magic;
+  int type;
+  int64_t nrows, ncols;
+  nbgrb::MatP data;
+};
+
+namespace nbgrb {
+
+// ------------------------------------------------------------ context
+
+struct Stats {
+  int64_t kernels = 0, fused = 0, plan_hits = 0, plan_misses = 0, elided = 0, waits = 0;
+};
+
+struct Ctx {
+  bool init = false;
+  GrB_Mode mode = GrB_NONBLOCKING;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int cus = 256;
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*release)(void*, void*) = nullptr;
+  void* actx = nullptr;
+  int64_t fail_after = 0;  // 0: off
+  int64_t live_bytes = 0;
+  std::map<size_t, std::vector<void*>> cache;
+  std::vector<std::weak_ptr<Node>> pending;
+  uint64_t next_id = 1;
+  Stats stats;
+  // scratch shared by all reductions / fused passes on the stream
+  BufP red_part, red_ticket, fused_part, fused_ticket;
+  int fused_part_cap = 0;
+  GuardDev* guard = nullptr;  // installed loop guard (device)
+  // timing of fused launches
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  std::vector<hipEvent_t> event_pool;
+  // plan configuration override chosen by the autotuner (per matrix id)
+  std::map<std::pair<uint64_t, int>, PlanConfig> tuned;
+};
+
+Ctx& ctx();
+void require_init();
+void* raw_alloc(size_t bytes);
+void raw_release(void* p);
+
+NodeP new_node(NodeKind k, int type, int64_t n, bool scalar);
+void set_vec(GB_Vector_opaque* v, NodeP node);
+void set_sca(GB_Scalar_opaque* s, NodeP node);
+
+// Record (nonblocking) or run (blocking) a node.
+void submit(const NodeP& node);
+// Run all pending work of the DAG (nonblocking mode).
+void force_all();
+// Make sure `node` is computed and (for vectors) held in storage.
+void materialize(const NodeP& node);
+
+// Scalar operand of a kernel for a scalar node (folds a pending affine).
+ScalarArg scalar_arg(const NodeP& s);
+Operand operand_of(const NodeP& v);
+
+void launch_mark(bool fused);
+
+}  // namespace nbgrb

@@ -1,0 +1,456 @@
+"""Python binding of libnbgrb.so (include/nbgrb.h).
+
+The functions keep the C names and argument order; output handles that C
+returns through a pointer are returned instead, and GrB_Info codes other
+than success (and GrB_NO_VALUE where documented) raise GrBError.  Device
+buffers are passed as torch tensors on the current CUDA (HIP) device or as
+raw integer addresses.  No arithmetic happens here: every step runs in the
+library's kernels.  The library must be built; nothing falls back to
+another implementation when it is not.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnbgrb.so")
+
+GrB_SUCCESS = 0
+GrB_NO_VALUE = 1
+GrB_NONBLOCKING = 0
+GrB_BLOCKING = 1
+GrB_COMPLETE = 0
+GrB_MATERIALIZE = 1
+GrM_DANGLING_DROP = 0
+GrM_DANGLING_UNIFORM = 1
+
+_INFO_NAMES = {
+    0: "GrB_SUCCESS", 1: "GrB_NO_VALUE", -1: "GrB_UNINITIALIZED_OBJECT", -2: "GrB_NULL_POINTER",
+    -3: "GrB_INVALID_VALUE", -4: "GrB_INVALID_INDEX", -5: "GrB_DOMAIN_MISMATCH",
+    -6: "GrB_DIMENSION_MISMATCH", -7: "GrB_OUTPUT_NOT_EMPTY", -8: "GrB_NOT_IMPLEMENTED",
+    -101: "GrB_PANIC", -102: "GrB_OUT_OF_MEMORY", -103: "GrB_INSUFFICIENT_SPACE",
+    -104: "GrB_INVALID_OBJECT", -105: "GrB_INDEX_OUT_OF_BOUNDS", -106: "GrB_EMPTY_OBJECT",
+}
+
+# Data symbols exported by the library (types, operators, descriptors).
+DATA_SYMBOLS = [
+    "GrB_BOOL", "GrB_INT32", "GrB_FP32", "GrB_FP64",
+    "GrB_IDENTITY_FP32", "GrB_IDENTITY_FP64", "GrB_ABS_FP32", "GrB_ABS_FP64",
+    "GrB_AINV_FP32", "GrB_AINV_FP64", "GrB_MINV_FP32", "GrB_MINV_FP64",
+    "GrM_MINV_OR_ZERO_FP32", "GrM_MINV_OR_ZERO_FP64",
+    "GrB_PLUS_FP32", "GrB_PLUS_FP64", "GrB_MINUS_FP32", "GrB_MINUS_FP64",
+    "GrB_TIMES_FP32", "GrB_TIMES_FP64", "GrB_DIV_FP32", "GrB_DIV_FP64",
+    "GrB_MAX_FP32", "GrB_MAX_FP64", "GrB_MIN_FP32", "GrB_MIN_FP64",
+    "GrB_FIRST_FP32", "GrB_FIRST_FP64", "GrB_SECOND_FP32", "GrB_SECOND_FP64",
+    "GrM_ABSDIFF_FP32", "GrM_ABSDIFF_FP64",
+    "GrB_PLUS_MONOID_FP32", "GrB_PLUS_MONOID_FP64",
+    "GrB_PLUS_TIMES_SEMIRING_FP32", "GrB_PLUS_TIMES_SEMIRING_FP64",
+    "GrM_PLUS_SECOND_SEMIRING_FP32", "GrM_PLUS_SECOND_SEMIRING_FP64",
+    "GrB_DESC_C",
+]
+
+vp = ctypes.c_void_p
+u64 = ctypes.c_uint64
+i64 = ctypes.c_int64
+i32 = ctypes.c_int
+dbl = ctypes.c_double
+PV = ctypes.POINTER(ctypes.c_void_p)
+
+
+class GrM_Stats(ctypes.Structure):
+    _fields_ = [("kernels", i64), ("fused_launches", i64), ("plan_hits", i64),
+                ("plan_misses", i64), ("elided_nodes", i64), ("forced_waits", i64)]
+
+
+# name -> (restype, argtypes).  All return GrB_Info unless noted.
+_FUNCS = {
+    "GrB_init": [i32],
+    "GrB_finalize": [],
+    "GrM_get_mode": [ctypes.POINTER(i32)],
+    "GrM_set_mode": [i32],
+    "GrM_set_stream": [vp],
+    "GrM_set_allocator": [vp, vp, vp],
+    "GrM_fail_allocation_after": [i64],
+    "GrM_get_stats": [ctypes.POINTER(GrM_Stats)],
+    "GrM_reset_stats": [],
+    "GrB_Scalar_new": [PV, vp],
+    "GrB_Scalar_free": [PV],
+    "GrB_Scalar_setElement_FP64": [vp, dbl],
+    "GrB_Scalar_extractElement_FP64": [ctypes.POINTER(dbl), vp],
+    "GrB_Scalar_wait": [vp, i32],
+    "GrM_Scalar_affine": [vp, dbl, vp, dbl],
+    "GrB_Vector_new": [PV, vp, u64],
+    "GrB_Vector_free": [PV],
+    "GrB_Vector_dup": [PV, vp],
+    "GrB_Vector_size": [ctypes.POINTER(u64), vp],
+    "GrM_Vector_type": [PV, vp],
+    "GrB_Vector_wait": [vp, i32],
+    "GrM_Vector_fill": [vp, dbl],
+    "GrM_Vector_import_dense": [vp, vp, u64],
+    "GrM_Vector_export_dense": [vp, u64, vp],
+    "GrM_Vector_device_pointer": [PV, vp],
+    "GrB_Matrix_new": [PV, vp, u64, u64],
+    "GrB_Matrix_free": [PV],
+    "GrB_Matrix_nrows": [ctypes.POINTER(u64), vp],
+    "GrB_Matrix_ncols": [ctypes.POINTER(u64), vp],
+    "GrB_Matrix_nvals": [ctypes.POINTER(u64), vp],
+    "GrB_Matrix_wait": [vp, i32],
+    "GrM_Matrix_import_CSR": [vp, vp, vp, u64],
+    "GrM_Matrix_export_CSR": [vp, vp, vp],
+    "GrM_Matrix_build_edges": [vp, vp, vp, u64, ctypes.c_bool],
+    "GrB_transpose": [vp, vp, vp, vp, vp],
+    "GrM_Matrix_row_degree": [vp, vp],
+    "GrM_rmat_edges": [vp, vp, i32, u64, u64, dbl, dbl, dbl],
+    "GrB_mxv": [vp, vp, vp, vp, vp, vp, vp],
+    "GrB_Vector_eWiseMult_BinaryOp": [vp, vp, vp, vp, vp, vp, vp],
+    "GrB_Vector_eWiseAdd_BinaryOp": [vp, vp, vp, vp, vp, vp, vp],
+    "GrB_Vector_apply": [vp, vp, vp, vp, vp, vp],
+    "GrB_Vector_apply_BinaryOp1st_FP64": [vp, vp, vp, vp, dbl, vp, vp],
+    "GrB_Vector_apply_BinaryOp2nd_FP64": [vp, vp, vp, vp, vp, dbl, vp],
+    "GrB_Vector_apply_BinaryOp2nd_Scalar": [vp, vp, vp, vp, vp, vp, vp],
+    "GrB_Vector_reduce_Monoid_Scalar": [vp, vp, vp, vp, vp],
+    "GrB_Vector_reduce_FP64": [ctypes.POINTER(dbl), vp, vp, vp, vp],
+    "GrM_Vector_reduce_masked_Scalar": [vp, vp, vp, vp, vp],
+    "GrM_pagerank": [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, vp, dbl, dbl, i32, i32,
+                     vp, i32],
+    "GrM_stream_copy": [vp, vp, ctypes.c_size_t],
+    "GrM_timing_enable": [ctypes.c_bool],
+    "GrM_timing_read": [ctypes.POINTER(dbl), ctypes.POINTER(i64)],
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+class GrBError(RuntimeError):
+    def __init__(self, info: int, where: str, msg: str):
+        self.info = info
+        super().__init__("%s returned %s (%d): %s" % (where, _INFO_NAMES.get(info, "?"), info, msg))
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load():
+    """Load libnbgrb.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libnbgrb.so is not built (expected at %s); run "
+                "`python paper_2509_14211_amd/build.py` or __graft_entry__.build()" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, args in _FUNCS.items():
+            f = getattr(lib, name)
+            f.restype = i32
+            f.argtypes = args
+        lib.GrM_error.restype = ctypes.c_char_p
+        lib.GrM_error.argtypes = []
+        _lib = lib
+        return lib
+
+
+def builtin(name: str) -> int:
+    """Address value held by an exported data symbol (a type or operator)."""
+    return vp.in_dll(load(), name).value
+
+
+def __getattr__(name):  # module-level access to GrB_FP32, GrB_PLUS_FP64, ...
+    if name in DATA_SYMBOLS:
+        return builtin(name)
+    raise AttributeError(name)
+
+
+def _call(name, *args, ok=(GrB_SUCCESS,)):
+    lib = load()
+    info = getattr(lib, name)(*args)
+    if info not in ok:
+        raise GrBError(info, name, lib.GrM_error().decode(errors="replace"))
+    return info
+
+
+def _addr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+# ---------------------------------------------------------------- context
+
+def GrB_init(mode=GrB_NONBLOCKING):
+    _call("GrB_init", mode)
+
+
+def GrB_finalize():
+    _call("GrB_finalize")
+
+
+def GrM_get_mode() -> int:
+    m = i32()
+    _call("GrM_get_mode", ctypes.byref(m))
+    return m.value
+
+
+def GrM_set_mode(mode):
+    _call("GrM_set_mode", mode)
+
+
+def GrM_set_stream(stream_handle: int):
+    _call("GrM_set_stream", stream_handle)
+
+
+_ALLOC_T = ctypes.CFUNCTYPE(vp, ctypes.c_size_t, vp)
+_FREE_T = ctypes.CFUNCTYPE(None, vp, vp)
+_keep = []
+
+
+def GrM_set_allocator(alloc=None, release=None):
+    """alloc(nbytes) -> int address, release(address) -> None (Python
+    callables), or both None for hipMalloc / hipFree."""
+    if alloc is None:
+        _call("GrM_set_allocator", None, None, None)
+        return
+    ca = _ALLOC_T(lambda n, ctx: alloc(n) or None)
+    cf = _FREE_T(lambda p, ctx: release(p))
+    _keep.append((ca, cf))
+    _call("GrM_set_allocator", ctypes.cast(ca, vp), ctypes.cast(cf, vp), None)
+
+
+def GrM_fail_allocation_after(k: int):
+    _call("GrM_fail_allocation_after", k)
+
+
+def GrM_get_stats() -> dict:
+    s = GrM_Stats()
+    _call("GrM_get_stats", ctypes.byref(s))
+    return {f: getattr(s, f) for f, _ in GrM_Stats._fields_}
+
+
+def GrM_reset_stats():
+    _call("GrM_reset_stats")
+
+
+def GrM_error() -> str:
+    return load().GrM_error().decode(errors="replace")
+
+
+# ---------------------------------------------------------------- scalars
+
+def GrB_Scalar_new(type_) -> int:
+    h = vp()
+    _call("GrB_Scalar_new", ctypes.byref(h), type_)
+    return h.value
+
+
+def GrB_Scalar_free(s):
+    h = vp(s)
+    _call("GrB_Scalar_free", ctypes.byref(h))
+
+
+def GrB_Scalar_setElement_FP64(s, x: float):
+    _call("GrB_Scalar_setElement_FP64", s, x)
+
+
+def GrB_Scalar_extractElement_FP64(s):
+    """Value of the scalar, or None when it has no value (GrB_NO_VALUE)."""
+    x = dbl()
+    info = _call("GrB_Scalar_extractElement_FP64", ctypes.byref(x), s, ok=(0, 1))
+    return None if info == GrB_NO_VALUE else x.value
+
+
+def GrB_Scalar_wait(s, mode=GrB_MATERIALIZE):
+    _call("GrB_Scalar_wait", s, mode)
+
+
+def GrM_Scalar_affine(out, alpha, in_, beta):
+    _call("GrM_Scalar_affine", out, alpha, in_, beta)
+
+
+# ---------------------------------------------------------------- vectors
+
+def GrB_Vector_new(type_, n: int) -> int:
+    h = vp()
+    _call("GrB_Vector_new", ctypes.byref(h), type_, n)
+    return h.value
+
+
+def GrB_Vector_free(v):
+    h = vp(v)
+    _call("GrB_Vector_free", ctypes.byref(h))
+
+
+def GrB_Vector_dup(u) -> int:
+    h = vp()
+    _call("GrB_Vector_dup", ctypes.byref(h), u)
+    return h.value
+
+
+def GrB_Vector_size(v) -> int:
+    n = u64()
+    _call("GrB_Vector_size", ctypes.byref(n), v)
+    return n.value
+
+
+def GrM_Vector_type(v) -> int:
+    t = vp()
+    _call("GrM_Vector_type", ctypes.byref(t), v)
+    return t.value
+
+
+def GrB_Vector_wait(v, mode=GrB_MATERIALIZE):
+    _call("GrB_Vector_wait", v, mode)
+
+
+def GrM_Vector_fill(v, value: float):
+    _call("GrM_Vector_fill", v, value)
+
+
+def GrM_Vector_import_dense(v, src, n: int):
+    _call("GrM_Vector_import_dense", v, _addr(src), n)
+
+
+def GrM_Vector_export_dense(dst, n: int, v):
+    _call("GrM_Vector_export_dense", _addr(dst), n, v)
+
+
+def GrM_Vector_device_pointer(v) -> int:
+    p = vp()
+    _call("GrM_Vector_device_pointer", ctypes.byref(p), v)
+    return p.value
+
+
+# ---------------------------------------------------------------- matrices
+
+def GrB_Matrix_new(type_, nrows: int, ncols: int) -> int:
+    h = vp()
+    _call("GrB_Matrix_new", ctypes.byref(h), type_, nrows, ncols)
+    return h.value
+
+
+def GrB_Matrix_free(A):
+    h = vp(A)
+    _call("GrB_Matrix_free", ctypes.byref(h))
+
+
+def GrB_Matrix_nrows(A) -> int:
+    n = u64()
+    _call("GrB_Matrix_nrows", ctypes.byref(n), A)
+    return n.value
+
+
+def GrB_Matrix_ncols(A) -> int:
+    n = u64()
+    _call("GrB_Matrix_ncols", ctypes.byref(n), A)
+    return n.value
+
+
+def GrB_Matrix_nvals(A) -> int:
+    n = u64()
+    _call("GrB_Matrix_nvals", ctypes.byref(n), A)
+    return n.value
+
+
+def GrB_Matrix_wait(A, mode=GrB_MATERIALIZE):
+    _call("GrB_Matrix_wait", A, mode)
+
+
+def GrM_Matrix_import_CSR(A, rowptr, col, nnz: int):
+    _call("GrM_Matrix_import_CSR", A, _addr(rowptr), _addr(col), nnz)
+
+
+def GrM_Matrix_export_CSR(rowptr, col, A):
+    _call("GrM_Matrix_export_CSR", _addr(rowptr), _addr(col), A)
+
+
+def GrM_Matrix_build_edges(A, src, dst, nedges: int, drop_self: bool = True):
+    _call("GrM_Matrix_build_edges", A, _addr(src), _addr(dst), nedges, drop_self)
+
+
+def GrB_transpose(C, Mask, accum, A, desc=None):
+    _call("GrB_transpose", C, Mask, accum, A, desc)
+
+
+def GrM_Matrix_row_degree(deg, A):
+    _call("GrM_Matrix_row_degree", deg, A)
+
+
+def GrM_rmat_edges(src, dst, scale, nedges, seed, t_a, t_ab, t_abc):
+    _call("GrM_rmat_edges", _addr(src), _addr(dst), scale, nedges, seed & (2**64 - 1),
+          t_a, t_ab, t_abc)
+
+
+# ---------------------------------------------------------------- operations
+
+def GrB_mxv(w, mask, accum, op, A, u, desc=None):
+    _call("GrB_mxv", w, mask, accum, op, A, u, desc)
+
+
+def GrB_Vector_eWiseMult_BinaryOp(w, mask, accum, op, u, v, desc=None):
+    _call("GrB_Vector_eWiseMult_BinaryOp", w, mask, accum, op, u, v, desc)
+
+
+def GrB_Vector_eWiseAdd_BinaryOp(w, mask, accum, op, u, v, desc=None):
+    _call("GrB_Vector_eWiseAdd_BinaryOp", w, mask, accum, op, u, v, desc)
+
+
+def GrB_Vector_apply(w, mask, accum, op, u, desc=None):
+    _call("GrB_Vector_apply", w, mask, accum, op, u, desc)
+
+
+def GrB_Vector_apply_BinaryOp1st_FP64(w, mask, accum, op, s, u, desc=None):
+    _call("GrB_Vector_apply_BinaryOp1st_FP64", w, mask, accum, op, s, u, desc)
+
+
+def GrB_Vector_apply_BinaryOp2nd_FP64(w, mask, accum, op, u, s, desc=None):
+    _call("GrB_Vector_apply_BinaryOp2nd_FP64", w, mask, accum, op, u, s, desc)
+
+
+def GrB_Vector_apply_BinaryOp2nd_Scalar(w, mask, accum, op, u, s, desc=None):
+    _call("GrB_Vector_apply_BinaryOp2nd_Scalar", w, mask, accum, op, u, s, desc)
+
+
+def GrB_Vector_reduce_Monoid_Scalar(s, accum, monoid, u, desc=None):
+    _call("GrB_Vector_reduce_Monoid_Scalar", s, accum, monoid, u, desc)
+
+
+def GrB_Vector_reduce_FP64(accum, monoid, u, desc=None) -> float:
+    x = dbl()
+    _call("GrB_Vector_reduce_FP64", ctypes.byref(x), accum, monoid, u, desc)
+    return x.value
+
+
+def GrM_Vector_reduce_masked_Scalar(s, mask, monoid, u, desc=None):
+    _call("GrM_Vector_reduce_masked_Scalar", s, mask, monoid, u, desc)
+
+
+def GrM_pagerank(r, AT, outdeg, damping, tol, itermax, dangling=GrM_DANGLING_UNIFORM, x0=None,
+                 check_every=8):
+    """Returns (iterations, residual); the ranks are left in vector r."""
+    it = i32()
+    res = dbl()
+    _call("GrM_pagerank", r, ctypes.byref(it), ctypes.byref(res), AT, outdeg, damping, tol,
+          itermax, dangling, x0, check_every)
+    return it.value, res.value
+
+
+def GrM_stream_copy(dst, src, nbytes: int):
+    _call("GrM_stream_copy", _addr(dst), _addr(src), nbytes)
+
+
+def GrM_timing_enable(on: bool):
+    _call("GrM_timing_enable", bool(on))
+
+
+def GrM_timing_read():
+    """(total milliseconds, launches) of timed fused passes since the last read."""
+    t = dbl()
+    n = i64()
+    _call("GrM_timing_read", ctypes.byref(t), ctypes.byref(n))
+    return t.value, n.value
