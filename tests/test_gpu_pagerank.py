@@ -36,7 +36,9 @@ def test_fp64_fused_matches_oracle(nonblocking, oracle_mod, scale, mode):
     x, it, res = _pr(g, torch.float64, tol=1e-9, dangling=mode)
     ref = oracle_mod.pagerank(og, D, fixed_iters=it, mode=mode)
     assert _rel_l1(x, ref.x) <= 1e-12
-    assert abs(res - ref.resid) <= 1e-12 * max(ref.resid, 1e-300) + 1e-18
+    # rho_k = |x_k - x_{k-1}|_1, so by the triangle inequality it can differ
+    # from the oracle's by at most the iterates' errors (~ twice the last).
+    assert abs(res - ref.resid) <= 4 * np.abs(x - ref.x).sum() + 1e-16
     free = oracle_mod.pagerank(og, D, tol=1e-9, itermax=1000, mode=mode)
     assert abs(it - free.iters) <= 1
     g.free()
@@ -50,8 +52,9 @@ def test_fp32_fused_matches_fp64_oracle(nonblocking, oracle_mod, scale):
     og = oracle_mod.rmat_graph(scale)
     x, it, res = _pr(g, torch.float32, tol=1e-6)
     ref = oracle_mod.pagerank(og, D, fixed_iters=it, mode=1)
-    assert np.abs(x - ref.x).sum() <= 1e-5
-    assert abs(res - ref.resid) <= 1e-6
+    err = np.abs(x - ref.x).sum()
+    assert err <= 1e-5
+    assert abs(res - ref.resid) <= 4 * err + 1e-7
     g.free()
 
 
@@ -241,7 +244,7 @@ def test_fig6_call_sequence(gpu, oracle_mod, mode):
     gpu.GrB_Vector_free(r)
     ref = oracle_mod.pagerank(og, D, fixed_iters=it)
     assert _rel_l1(x, ref.x) <= 1e-12
-    assert abs(rd - ref.resid) <= 1e-12 * ref.resid
+    assert abs(rd - ref.resid) <= 4 * np.abs(x - ref.x).sum() + 1e-16
     if mode == "nonblocking":
         # one fused pass per iteration; the pre-scale runs on its own only in
         # the first iteration (later ones gather the pass's side output)
