@@ -359,6 +359,58 @@ GrB_Info GrM_pagerank(GrB_Vector r, int *iters, double *resid, GrB_Matrix AT,
                       GrM_Dangling dangling, GrB_Vector x0, int check_every);
 
 /* ------------------------------------------------------------------------
+ * Tile plans.  The row-parallel kernels (mxv and the fused PageRank pass)
+ * walk a plan of row tiles built once per matrix and configuration on the
+ * host (the analogue of the paper's compiled-kernel cache keyed by a method
+ * signature, Section III-C):
+ *   kernel       0: one workgroup per tile; 1: one wavefront per tile
+ *   lds_entries  entries a tile stages in LDS (kernel 0: 1024, 2048 or 4096;
+ *                kernel 1: 512)
+ *   lds_rows     rows per tile (kernel 0: 512 with 1024 entries, else 1024;
+ *                kernel 1: 256)
+ *   long_row     rows with more entries get a tile of their own
+ *                (1 <= long_row <= chunk)
+ *   chunk        rows with more entries than this are split into chunks
+ *                of this size reduced by several workgroups
+ *                (long_row <= chunk <= lds_entries)
+ *   grid         persistent workgroups (0: 8 per compute unit)
+ * The choice never changes results beyond floating-point reassociation.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t kernel;   /* 0: workgroup tiles; 1: wavefront tiles (lds_entries 512,
+                       lds_rows 256, 1024-thread workgroups) */
+  int32_t lds_entries;
+  int32_t lds_rows;
+  int32_t long_row;
+  int32_t chunk;
+  int32_t grid;
+  int32_t hot;      /* kernel 1: leading entries of the gathered vector kept in
+                       LDS (clamped to what fits) */
+  int32_t relabel;  /* GrM_pagerank: 1 runs on a copy of the matrix with the
+                       vertices renumbered by decreasing out-degree (built once
+                       and cached with the matrix), so the most gathered values
+                       come first; 0 runs on the matrix as given */
+} GrM_PlanConfig;
+
+/* Use cfg for A's kernels computing in `type` (FP32 or FP64); NULL goes
+ * back to the default.  GrB_INVALID_VALUE for an unsupported geometry. */
+GrB_Info GrM_Matrix_plan_set(GrB_Matrix A, GrB_Type type, const GrM_PlanConfig *cfg);
+/* The configuration A's kernels computing in `type` would use now. */
+GrB_Info GrM_Matrix_plan_get(GrM_PlanConfig *cfg, GrB_Matrix A, GrB_Type type);
+
+/* Autotuner: time candidate plan configurations of the fused PageRank pass
+ * on AT (a few fixed-length GrM_pagerank runs each, with outdeg as its
+ * out-degree vector, computing in `type`), install the fastest for AT and
+ * return it in *chosen (and its time per pass in *us_per_pass, or -1 when
+ * it came from the cache).  cache_path (may be NULL) names a text file of
+ * earlier choices keyed by the matrix signature (dimension, entries,
+ * longest row, value type, compute units): a hit installs the stored
+ * choice without timing; a miss appends the new choice.  Candidates only
+ * differ in speed, never beyond rounding in results. */
+GrB_Info GrM_autotune_pagerank(GrM_PlanConfig *chosen, double *us_per_pass, GrB_Matrix AT,
+                               GrB_Vector outdeg, GrB_Type type, const char *cache_path);
+
+/* ------------------------------------------------------------------------
  * Bandwidth probe: dst_dev[0:bytes) = src_dev[0:bytes) with a streaming
  * copy kernel (bytes a multiple of 16, pointers 16-byte aligned).
  * ---------------------------------------------------------------------- */

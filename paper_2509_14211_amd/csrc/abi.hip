@@ -66,6 +66,8 @@ GrB_Descriptor GrB_DESC_C = &d_comp;
 
 static thread_local std::string g_err;
 
+void nbgrb::set_error_text(const std::string& msg) { g_err = msg; }
+
 #define API_BEGIN \
   try {           \
     g_err.clear();
@@ -216,22 +218,17 @@ MatP new_matdata(int64_t nrows, int64_t ncols) {
   return m;
 }
 
-// Temporary buffers of the graph builder come from the buffer cache.
-std::map<void*, BufP>& tmp_bufs() {
-  static std::map<void*, BufP> m;
-  return m;
+// out[k] = v[idx[k]] as a new materialised node (iso vectors stay iso).
+NodeP permuted(const NodeP& v, const BufP& idx) {
+  materialize(v);
+  if (v->iso) return iso_node(v->type, v->n, v->iso_val);
+  NodeP p = new_node(N_DENSE, v->type, v->n, false);
+  p->buf = dev_alloc(type_size(v->type) * (size_t)v->n);
+  hip_check(launch_permute(v->buf->p, v->type, (const int*)idx->p, p->buf->p, v->n, ctx().stream), "permute");
+  launch_mark(false);
+  p->done = true;
+  return p;
 }
-void* tmp_alloc(size_t bytes, void*) {
-  try {
-    BufP b = dev_alloc(bytes);
-    void* p = b->p;
-    tmp_bufs()[p] = b;
-    return p;
-  } catch (const GrbError&) {
-    return nullptr;
-  }
-}
-void tmp_release(void* p, void*) { tmp_bufs().erase(p); }
 
 int read_flag(const BufP& f) {
   int h = 0;
@@ -697,8 +694,8 @@ GrB_Info GrM_Matrix_build_edges(GrB_Matrix A, const uint32_t* src, const uint32_
   hip_check(launch_fill(flag->p, T_INT32, 1, 0.0, c.stream), "fill");
   int64_t nnz = 0;
   hip_check(build_csr_from_edges(n, src, dst, (int64_t)nedges, drop_self, (int*)m->rowptr->p,
-                                 colbuf ? (int*)colbuf->p : nullptr, &nnz, (int*)flag->p, tmp_alloc,
-                                 tmp_release, nullptr, c.stream),
+                                 colbuf ? (int*)colbuf->p : nullptr, &nnz, (int*)flag->p, cache_alloc,
+                                 cache_release, nullptr, c.stream),
             "build CSR");
   launch_mark(false);
   if (read_flag(flag) != 0) fail(GrB_INDEX_OUT_OF_BOUNDS, "edge endpoint >= n");
@@ -732,8 +729,8 @@ GrB_Info GrB_transpose(GrB_Matrix C, GrB_Matrix Mask, GrB_BinaryOp accum, GrB_Ma
   m->rowptr = dev_alloc(sizeof(int) * (size_t)(m->nrows + 1));
   if (a->nnz > 0) m->col = dev_alloc(sizeof(int) * (size_t)a->nnz);
   hip_check(transpose_csr(a->nrows, a->ncols, (const int*)a->rowptr->p, a->col ? (const int*)a->col->p : nullptr,
-                          a->nnz, (int*)m->rowptr->p, m->col ? (int*)m->col->p : nullptr, tmp_alloc,
-                          tmp_release, nullptr, c.stream),
+                          a->nnz, (int*)m->rowptr->p, m->col ? (int*)m->col->p : nullptr, cache_alloc,
+                          cache_release, nullptr, c.stream),
             "transpose");
   launch_mark(false);
   co->data = m;
@@ -959,10 +956,28 @@ GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, Gr
   const bool uniform = dangling == GrM_DANGLING_UNIFORM;
   const double tele = (1.0 - damping) / (double)n;
 
+  // Execution matrix: AT itself, or its copy with vertices renumbered by
+  // decreasing out-degree (the teleport vector is uniform, so the method is
+  // unchanged; vectors are permuted in and out).
+  const PlanConfig pc = default_plan_config(ao->data, T);
+  std::shared_ptr<Relabeled> rl;
+  GB_Matrix_opaque A_exec{MAGIC_MAT, ao->type, n, n, ao->data};
+  if (pc.relabel) {
+    rl = get_relabeled(ao->data);
+    A_exec.data = rl->A;
+    PlanConfig sub = pc;
+    sub.relabel = 0;
+    c.tuned[{rl->A->id, T}] = sub;
+  }
+
+  GB_Vector_opaque deg_exec{MAGIC_VEC, dego->type, n, nullptr};
+  set_vec(&deg_exec, rl ? permuted(dego->node, rl->order) : dego->node);
+
   // d = damping ./ outdeg (0 where outdeg = 0)
   GB_Vector_opaque dinv{MAGIC_VEC, T, n, nullptr};
-  rec_unop(&dinv, U_MINV_OR_ZERO, dego);
+  rec_unop(&dinv, U_MINV_OR_ZERO, &deg_exec);
   rec_bind(&dinv, B_TIMES, &dinv, damping, true);
+  set_vec(&deg_exec, nullptr);
   materialize(dinv.node);
   store_if_iso(dinv.node);
 
@@ -972,6 +987,8 @@ GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, Gr
       set_vec(&x, xo->node);
     else
       rec_unop(&x, U_IDENTITY, xo);
+    materialize(x.node);
+    if (rl) set_vec(&x, permuted(x.node, rl->order));
   } else {
     set_vec(&x, iso_node(T, n, 1.0 / (double)n));
   }
@@ -990,14 +1007,16 @@ GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, Gr
   std::vector<NodeP> hist{x.node};
   int64_t base = 0;
   GuardDev hg{};
+  int batch = check_every;
+  int issued = 0;
   for (;;) {
-    for (int j = 0; j < check_every; ++j) {
+    for (int j = 0; j < batch; ++j) {
       GB_Vector_opaque w{MAGIC_VEC, T, n, nullptr}, s{MAGIC_VEC, T, n, nullptr};
       GB_Vector_opaque rn{MAGIC_VEC, T, n, nullptr}, t{MAGIC_VEC, T, n, nullptr};
       GB_Scalar_opaque cs{MAGIC_SCA, T_FP64, nullptr}, rho{MAGIC_SCA, T_FP64, nullptr};
       GB_Scalar_opaque Dn{MAGIC_SCA, T_FP64, nullptr};
       rec_ewise(&w, B_TIMES, &x, &dinv);            // w = x .* d
-      rec_mxv(&s, ao, &w);                          // s = AT (+.second) w
+      rec_mxv(&s, &A_exec, &w);                     // s = AT (+.second) w
       if (uniform) {                                // r = c + s
         rec_affine(&cs, damping / (double)n, &D, tele);
         rec_bind_scalar(&rn, B_PLUS, &s, &cs);
@@ -1020,17 +1039,33 @@ GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, Gr
       set_sca(&rho, nullptr);
       set_sca(&Dn, nullptr);
     }
+    issued += batch;
     hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
     hip_check(hipStreamSynchronize(c.stream), "sync");
     if (!hg.active) break;
     base += (int64_t)hist.size() - 1;
     NodeP last = hist.back();
     hist.assign(1, last);
+    // The residual contracts about geometrically: predict the passes still
+    // needed from the last two residuals (at least 1, at most what itermax
+    // allows); an underestimate only costs one more check.
+    int next = check_every;
+    if (hg.rho_prev > 0.0 && hg.rho > 0.0 && hg.rho < hg.rho_prev && tol > 0.0) {
+      const double q = hg.rho / hg.rho_prev;
+      const double need = std::log(tol / hg.rho) / std::log(q);
+      if (need > 0.0 && need < 1e6) next = (int)std::ceil(need);
+      if (next < 1) next = 1;
+    }
+    if (next > itermax - hg.iters) next = itermax - hg.iters;
+    if (next < 1) next = 1;
+    batch = next;
   }
   const int64_t idx = (int64_t)hg.iters - base;
   if (idx < 0 || idx >= (int64_t)hist.size()) fail(GrB_PANIC, "loop guard out of step");
   c.guard = saved_guard;
-  set_vec(ro, hist[(size_t)idx]);
+  NodeP result = hist[(size_t)idx];
+  set_vec(ro, rl ? permuted(result, rl->inv) : result);
+  hist.clear();
   set_vec(&x, nullptr);
   set_vec(&dinv, nullptr);
   set_sca(&D, nullptr);
@@ -1048,6 +1083,64 @@ GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, Gr
     return GrB_PANIC;
   }
   return GrB_SUCCESS;
+}
+
+// ------------------------------------------------------------ plans
+
+static bool plan_geometry_ok(const GrM_PlanConfig& c) {
+  if (c.kernel != K_BLOCK && c.kernel != K_WAVE) return false;
+  if (c.hot < 0 || (c.relabel != 0 && c.relabel != 1)) return false;
+  const bool lds_ok = c.kernel == K_WAVE
+                          ? (c.lds_entries == WAVE_TILE_ENTRIES && c.lds_rows == WAVE_TILE_ROWS)
+                          : ((c.lds_entries == 1024 && c.lds_rows == 512) ||
+                             (c.lds_entries == 2048 && c.lds_rows == 1024) ||
+                             (c.lds_entries == 4096 && c.lds_rows == 1024));
+  return lds_ok && c.long_row >= 1 && c.long_row <= c.chunk && c.chunk <= c.lds_entries &&
+         c.grid >= 0 && c.grid <= (1 << 20);
+}
+
+GrB_Info GrM_Matrix_plan_set(GrB_Matrix A, GrB_Type type, const GrM_PlanConfig* cfg) {
+  API_BEGIN
+  require_init();
+  GB_Matrix_opaque* ao = mat(A, "A");
+  need(type, "type");
+  float_type(type->code, "type");
+  auto key = std::make_pair(ao->data->id, type->code);
+  if (!cfg) {
+    ctx().tuned.erase(key);
+  } else {
+    if (!plan_geometry_ok(*cfg)) fail(GrB_INVALID_VALUE, "unsupported tile plan geometry");
+    PlanConfig pc;
+    pc.kernel = cfg->kernel;
+    pc.hot = cfg->hot;
+    pc.relabel = cfg->relabel;
+    pc.lds_entries = cfg->lds_entries;
+    pc.lds_rows = cfg->lds_rows;
+    pc.long_row = cfg->long_row;
+    pc.chunk = cfg->chunk;
+    pc.grid = cfg->grid;
+    ctx().tuned[key] = pc;
+  }
+  API_END
+}
+
+GrB_Info GrM_Matrix_plan_get(GrM_PlanConfig* cfg, GrB_Matrix A, GrB_Type type) {
+  API_BEGIN
+  require_init();
+  need(cfg, "cfg");
+  GB_Matrix_opaque* ao = mat(A, "A");
+  need(type, "type");
+  float_type(type->code, "type");
+  PlanConfig pc = default_plan_config(ao->data, type->code);
+  cfg->kernel = pc.kernel;
+  cfg->hot = pc.hot;
+  cfg->relabel = pc.relabel;
+  cfg->lds_entries = pc.lds_entries;
+  cfg->lds_rows = pc.lds_rows;
+  cfg->long_row = pc.long_row;
+  cfg->chunk = pc.chunk;
+  cfg->grid = pc.grid;
+  API_END
 }
 
 // ------------------------------------------------------------ probe / timing

@@ -192,4 +192,98 @@ hipError_t transpose_csr(int64_t nrows, int64_t ncols, const int* rowptr, const 
   return hipGetLastError();
 }
 
+namespace {
+
+__global__ void column_count_kernel(const int* __restrict__ col, int64_t nnz, int* __restrict__ cnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride)
+    atomicAdd(&cnt[col[e]], 1);
+}
+
+// key = (2^32 - 1 - count) << 32 | v: ascending keys = decreasing count,
+// ties by increasing vertex id.
+__global__ void degree_keys_kernel(const int* __restrict__ cnt, int64_t n, uint64_t* __restrict__ keys) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    keys[v] = ((uint64_t)(0xFFFFFFFFu - (uint32_t)cnt[v]) << 32) | (uint64_t)v;
+}
+
+__global__ void order_from_keys_kernel(const uint64_t* __restrict__ keys, int64_t n, int* __restrict__ order,
+                                       int* __restrict__ inv) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    const int v = (int)(uint32_t)(keys[k] & 0xFFFFFFFFull);
+    order[k] = v;
+    inv[v] = (int)k;
+  }
+}
+
+// key = inv[row] << 32 | inv[col] for every entry of a square pattern.
+__global__ void permute_keys_kernel(const int* __restrict__ rowptr, int64_t n, const int* __restrict__ col,
+                                    int64_t nnz, const int* __restrict__ inv, uint64_t* __restrict__ keys) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    int64_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)rowptr[mid] <= e) lo = mid; else hi = mid;
+    }
+    keys[e] = ((uint64_t)(uint32_t)inv[lo] << 32) | (uint64_t)(uint32_t)inv[col[e]];
+  }
+}
+
+}  // namespace
+
+hipError_t degree_order(int64_t n, const int* col, int64_t nnz, int* order, int* inv, AllocFn alloc,
+                        ReleaseFn release, void* actx, hipStream_t s) {
+  Scoped cbuf(alloc, release, actx, (size_t)n * sizeof(int));
+  Scoped kbuf(alloc, release, actx, (size_t)n * 16);
+  if (!cbuf.ok(1) || !kbuf.ok(1)) return hipErrorOutOfMemory;
+  int* cnt = (int*)cbuf.p;
+  uint64_t* keys = (uint64_t*)kbuf.p;
+  uint64_t* out = keys + n;
+  hipError_t e = launch_fill(cnt, T_INT32, n, 0.0, s);
+  if (e != hipSuccess) return e;
+  if (nnz > 0) {
+    hipLaunchKernelGGL(column_count_kernel, dim3(gb_grid(nnz)), dim3(GB_BLOCK), 0, s, col, nnz, cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(degree_keys_kernel, dim3(gb_grid(n)), dim3(GB_BLOCK), 0, s, cnt, n, keys);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  size_t tb = 0;
+  e = rocprim::radix_sort_keys(nullptr, tb, keys, out, (size_t)n, 0u, 64u, s);
+  if (e != hipSuccess) return e;
+  Scoped tmp(alloc, release, actx, tb + 256);
+  if (!tmp.ok(1)) return hipErrorOutOfMemory;
+  e = rocprim::radix_sort_keys(tmp.p, tb, keys, out, (size_t)n, 0u, 64u, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(order_from_keys_kernel, dim3(gb_grid(n)), dim3(GB_BLOCK), 0, s, out, n, order, inv);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipStreamSynchronize(s);  // scoped temporaries are released on return
+}
+
+hipError_t permute_csr(int64_t n, const int* rowptr, const int* col, int64_t nnz, const int* inv,
+                       int* rowptr2, int* col2, AllocFn alloc, ReleaseFn release, void* actx,
+                       hipStream_t s) {
+  if (nnz == 0) return launch_fill(rowptr2, T_INT32, n + 1, 0.0, s);
+  Scoped kbuf(alloc, release, actx, (size_t)nnz * 16);
+  if (!kbuf.ok(1)) return hipErrorOutOfMemory;
+  uint64_t* keys = (uint64_t*)kbuf.p;
+  uint64_t* out = keys + nnz;
+  hipLaunchKernelGGL(permute_keys_kernel, dim3(gb_grid(nnz)), dim3(GB_BLOCK), 0, s, rowptr, n, col, nnz,
+                     inv, keys);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned end_bit = 32u + (unsigned)bit_width_u64((uint64_t)n);
+  int64_t u = 0;
+  e = sort_unique(keys, out, nnz, end_bit, &u, alloc, release, actx, s);
+  if (e != hipSuccess) return e;
+  if (u != nnz) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(keys_to_csr_kernel, dim3(gb_grid(n + 1 > nnz ? n + 1 : nnz)), dim3(GB_BLOCK), 0, s,
+                     keys, nnz, n, rowptr2, col2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
 }  // namespace nbgrb

@@ -29,9 +29,10 @@ enum BinOp : int {
 // a guard is installed return at once when `active` is 0; the reduction
 // that produces the guarded residual updates it.
 struct GuardDev {
-  int active;     // 1 while another pass is wanted
-  int iters;      // passes completed
-  double rho;     // last residual
+  int active;       // 1 while another pass is wanted
+  int iters;        // passes completed
+  double rho;       // last residual
+  double rho_prev;  // the one before (lets the host predict how many more)
   double tol;
   int itermax;
   int pad;
@@ -71,9 +72,9 @@ struct RedScratch {
 // matrix and tile geometry on the host).
 //   STREAM tile  : {row0, nrows > 0, e0, ne}  rows [row0,row0+nrows), their
 //                  ne entries start at e0; staged through LDS.
-//   LONG tile    : {row, 0, e0, ne} one row, reduced by the whole block.
-//   CHUNK tile   : {row, -(h+1), e0, ne} one chunk of hub row h; the block
+//   CHUNK tile   : {k, -(h+1), e0, ne} chunk k of hub row h; the block
 //                  that completes the last chunk finishes the row.
+// Every tile holds at most the kernel's LDS entry budget of entries.
 // HubInfo h: {row, nchunks, first partial slot, first entry}.
 struct TilePlanDev {
   const int4* tiles;
@@ -140,6 +141,20 @@ hipError_t launch_fused_f64(const TilePlanDev& plan, const FusedArgs<double>& a,
                             const FusedScratch& scr, int grid, int lds_entries, int lds_rows,
                             const GuardDev* guard, hipStream_t s);
 
+// Wave-tiled fused pass: tiles of at most 512 entries and 256 rows, one
+// wavefront each, 1024-thread workgroups (grid = persistent workgroups),
+// the first hot_n entries of the gathered vector held in LDS (clamped to
+// wave_hot_max(type)).
+constexpr int WAVE_TILE_ENTRIES = 512;
+constexpr int WAVE_TILE_ROWS = 256;
+hipError_t launch_fused_wave_f32(const TilePlanDev& plan, const FusedArgs<float>& a,
+                                 const FusedScratch& scr, int grid, int hot_n,
+                                 const GuardDev* guard, hipStream_t s);
+hipError_t launch_fused_wave_f64(const TilePlanDev& plan, const FusedArgs<double>& a,
+                                 const FusedScratch& scr, int grid, int hot_n,
+                                 const GuardDev* guard, hipStream_t s);
+int wave_hot_max(int type);
+
 // Elementwise: out[i] = f(a[i], b[i]) computed in `ct` (T_FP32 / T_FP64).
 //   kind 0: binary op(a, b); 1: unary op(a); 2: op(s, a); 3: op(a, s)
 enum EwKind : int { EW_BINARY = 0, EW_UNARY = 1, EW_BIND1ST = 2, EW_BIND2ND = 3 };
@@ -198,5 +213,16 @@ hipError_t build_csr_from_edges(int64_t n, const uint32_t* src, const uint32_t* 
 hipError_t transpose_csr(int64_t nrows, int64_t ncols, const int* rowptr, const int* col,
                          int64_t nnz, int* rowptrT, int* colT, AllocFn alloc,
                          ReleaseFn release, void* actx, hipStream_t s);
+
+// Vertex order by decreasing column count of an n x n pattern (ties by
+// increasing id): order[k] = vertex at position k, inv[v] = position of v.
+hipError_t degree_order(int64_t n, const int* col, int64_t nnz, int* order, int* inv, AllocFn alloc,
+                        ReleaseFn release, void* actx, hipStream_t s);
+// The pattern with rows and columns renumbered by inv (both sorted again).
+hipError_t permute_csr(int64_t n, const int* rowptr, const int* col, int64_t nnz, const int* inv,
+                       int* rowptr2, int* col2, AllocFn alloc, ReleaseFn release, void* actx,
+                       hipStream_t s);
+// out[k] = in[idx[k]] for k < n, storage type `type`.
+hipError_t launch_permute(const void* in, int type, const int* idx, void* out, int64_t n, hipStream_t s);
 
 }  // namespace nbgrb

@@ -9,7 +9,6 @@
 //     values into LDS with coalesced, non-temporal column reads, then reduce
 //     each row from LDS with a power-of-two group of lanes per row chosen
 //     from the tile's row count, finishing with cross-lane shuffles;
-//   * LONG tiles (one row) are summed by the whole workgroup;
 //   * CHUNK tiles split a hub row over several workgroups; the workgroup
 //     that completes the last chunk adds the chunk sums in chunk order and
 //     finishes the row.
@@ -141,6 +140,7 @@ __device__ __forceinline__ T apply_unop(int op, T x) {
 
 // Called by thread 0 of the block that produced a guarded residual.
 __device__ __forceinline__ void guard_advance(GuardDev* g, double rho) {
+  g->rho_prev = g->rho;
   g->rho = rho;
   const int it = g->iters + 1;
   g->iters = it;
@@ -169,45 +169,65 @@ __device__ __forceinline__ void pr_epilogue(const FusedArgs<T>& a, int i, T s, T
   }
 }
 
-// Gather w[col[k]] for k in [0, ne) into sval, eight loads in flight per
-// thread.  Column indices are streamed once, so they are read non-temporal.
-template <typename T, int B>
-__device__ __forceinline__ void gather_to_lds(const int* __restrict__ col, const T* __restrict__ w,
-                                              int ne, T* __restrict__ sval) {
-  int k = threadIdx.x;
-  for (; k + 7 * B < ne; k += 8 * B) {
-    int c[8];
+// Registers a thread holds for one tile before its gathers: column indices
+// of its entries, the tile's row pointers and, for the PageRank epilogue,
+// x_old and d of its rows.  Loading them for the next tile while the
+// current one is reduced hides one memory round trip per tile.
+template <typename T, int KE, int KP, int KR>
+struct TileRegs {
+  int4 td;
+  int ci[KE];
+  int rp[KP];
+  T xo[KR];
+  T dv[KR];
+};
+
+template <typename T, int B, int KE, int KP, int KR>
+__device__ __forceinline__ void tile_prefetch(const TilePlanDev& plan, const FusedArgs<T>& a,
+                                              int t, bool pr, TileRegs<T, KE, KP, KR>& R) {
+  const int tid = threadIdx.x;
+  R.td = plan.tiles[t];
+  const int4 d = R.td;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) c[u] = __builtin_nontemporal_load(col + k + u * B);
-    T v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = w[c[u]];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) sval[k + u * B] = v[u];
+  for (int k = 0; k < KE; ++k) {
+    const int e = tid + k * B;
+    R.ci[k] = e < d.w ? __builtin_nontemporal_load(a.col + d.z + e) : 0;
   }
-  for (; k < ne; k += B) sval[k] = w[__builtin_nontemporal_load(col + k)];
+  if (d.y > 0) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int r = tid + k * B;
+      R.rp[k] = r <= d.y ? a.rowptr[d.x + r] : 0;
+    }
+    if (pr) {
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int r = tid + k * B;
+        const bool ok = r < d.y;
+        R.xo[k] = (ok && a.x_old) ? __builtin_nontemporal_load(a.x_old + d.x + r) : (T)0;
+        R.dv[k] = (ok && a.dvec) ? __builtin_nontemporal_load(a.dvec + d.x + r) : (T)0;
+      }
+    }
+  }
 }
 
-// Per-thread partial sum of w[col[k]], k in [0, ne), in a fixed order.
-template <typename T, int B>
-__device__ __forceinline__ T gather_sum(const int* __restrict__ col, const T* __restrict__ w,
-                                        int ne) {
-  T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-  int k = threadIdx.x;
-  for (; k + 7 * B < ne; k += 8 * B) {
-    int c[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) c[u] = __builtin_nontemporal_load(col + k + u * B);
-    T v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = w[c[u]];
-    acc0 += v[0] + v[4];
-    acc1 += v[1] + v[5];
-    acc2 += v[2] + v[6];
-    acc3 += v[3] + v[7];
+// Epilogue with x_old and d already loaded.
+template <typename T>
+__device__ __forceinline__ void pr_epilogue_pre(const FusedArgs<T>& a, int i, T s, T c, T xo, T dv,
+                                                double& rho, double& dm) {
+  if (a.mode == EPI_PLAIN) {
+    a.s_out[i] = s;
+    return;
   }
-  for (; k < ne; k += B) acc0 += w[__builtin_nontemporal_load(col + k)];
-  return (acc0 + acc1) + (acc2 + acc3);
+  const T tele = a.tele_vec ? a.tele_vec[i] : c;
+  const T r = tele + s;
+  if (a.r_out) __builtin_nontemporal_store(r, a.r_out + i);
+  if (a.x_old) rho += fabs((double)xo - (double)r);
+  if (a.w_out) a.w_out[i] = a.memo_div ? r / dv : r * dv;
+  if (a.do_D) {
+    const bool m = a.mask_is_dvec ? (dv != (T)0) : nonzero_at(a.mask, i);
+    if (m != (a.mask_comp != 0)) dm += (double)r;
+  }
 }
 
 template <typename T, int ET, int RT>
@@ -215,6 +235,9 @@ __global__ __launch_bounds__(FUSED_BLOCK) void fused_pr_kernel(TilePlanDev plan,
                                                                FusedScratch scr,
                                                                const GuardDev* guard) {
   constexpr int B = FUSED_BLOCK;
+  constexpr int KE = ET / B;                 // entries per thread
+  constexpr int KP = (RT + 1 + B - 1) / B;   // row pointers per thread
+  constexpr int KR = (RT + B - 1) / B;       // epilogue rows per thread
   if (guard && guard->active == 0) return;
 
   __shared__ T sval[ET];
@@ -225,17 +248,42 @@ __global__ __launch_bounds__(FUSED_BLOCK) void fused_pr_kernel(TilePlanDev plan,
   __shared__ int sflag;
 
   const int tid = threadIdx.x;
+  const bool pr = a.mode == EPI_PR;
   T c = (T)0;
-  if (a.mode == EPI_PR) c = (T)scalar_value(a.c);
+  if (pr) c = (T)scalar_value(a.c);
   double rho = 0.0, dm = 0.0;
 
-  for (int t = blockIdx.x; t < plan.ntiles; t += gridDim.x) {
-    const int4 td = plan.tiles[t];
-    if (td.y > 0) {
-      // ---- STREAM tile
-      const int row0 = td.x, nr = td.y, e0 = td.z, ne = td.w;
-      for (int k = tid; k <= nr; k += B) srp[k] = a.rowptr[row0 + k] - e0;
-      gather_to_lds<T, B>(a.col + e0, a.w, ne, sval);
+  TileRegs<T, KE, KP, KR> R;
+  int t = blockIdx.x;
+  if (t < plan.ntiles) tile_prefetch<T, B>(plan, a, t, pr, R);
+  for (; t < plan.ntiles; t += gridDim.x) {
+    // gathers of the current tile
+    const int4 cur = R.td;
+    T val[KE];
+#pragma unroll
+    for (int k = 0; k < KE; ++k) val[k] = (tid + k * B < cur.w) ? a.w[R.ci[k]] : (T)0;
+    int crp[KP];
+    T cxo[KR], cdv[KR];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) crp[k] = R.rp[k];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      cxo[k] = R.xo[k];
+      cdv[k] = R.dv[k];
+    }
+    // next tile's independent loads go out while this one is reduced
+    const int tn = t + (int)gridDim.x;
+    if (tn < plan.ntiles) tile_prefetch<T, B>(plan, a, tn, pr, R);
+
+    if (cur.y > 0) {
+      // ---- rows [row0, row0 + nr) staged through LDS
+      const int row0 = cur.x, nr = cur.y, e0 = cur.z, ne = cur.w;
+#pragma unroll
+      for (int k = 0; k < KE; ++k)
+        if (tid + k * B < ne) sval[tid + k * B] = val[k];
+#pragma unroll
+      for (int k = 0; k < KP; ++k)
+        if (tid + k * B <= nr) srp[tid + k * B] = crp[k] - e0;
       __syncthreads();
       const int q = B / nr;
       const int lpr = q >= 64 ? 64 : q >= 32 ? 32 : q >= 16 ? 16 : q >= 8 ? 8 : q >= 4 ? 4 : q >= 2 ? 2 : 1;
@@ -253,44 +301,46 @@ __global__ __launch_bounds__(FUSED_BLOCK) void fused_pr_kernel(TilePlanDev plan,
         if (lane == 0 && rr < nr) sres[rr] = v;
       }
       __syncthreads();
-      for (int k = tid; k < nr; k += B) pr_epilogue(a, row0 + k, sres[k], c, rho, dm);
-      __syncthreads();
-    } else {
-      // ---- LONG or CHUNK tile
-      const int e0 = td.z, ne = td.w;
-      const T part = gather_sum<T, B>(a.col + e0, a.w, ne);
-      const T tot = block_sum<T, B>(part, sredT);
-      if (td.y == 0) {
-        if (tid == 0) pr_epilogue(a, td.x, tot, c, rho, dm);
-      } else {
-        const int h = -td.y - 1;
-        const int4 hub = plan.hubs[h];  // {row, nchunks, slot0, -}
-        if (tid == 0) {
-          publish(&scr.hub_sum[hub.z + td.x], (double)tot);
-          wait_stores();
-          sflag = counter_add(&scr.hub_cnt[h]) == hub.y - 1;
-        }
-        __syncthreads();
-        if (sflag) {
-          // This block finished the hub's last chunk: add the chunk sums
-          // (fixed tree over chunk order) and finish the row.
-          T s = 0;
-          for (int k = tid; k < hub.y; k += B) s += (T)consume(&scr.hub_sum[hub.z + k]);
-          s = block_sum<T, B>(s, sredT);
-          if (tid == 0) {
-            double hr = 0.0, hd = 0.0;
-            pr_epilogue(a, hub.x, s, c, hr, hd);
-            publish(&scr.hub_red[2 * h], hr);
-            publish(&scr.hub_red[2 * h + 1], hd);
-            publish(&scr.hub_cnt[h], 0);
-          }
-        }
-        __syncthreads();
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int r = tid + k * B;
+        if (r < nr) pr_epilogue_pre(a, row0 + r, sres[r], c, cxo[k], cdv[k], rho, dm);
       }
+      // the next tile writes sval/srp before its first barrier and sres only
+      // after it, so no barrier is needed here
+    } else {
+      // ---- one chunk of hub row h
+      T part = 0;
+#pragma unroll
+      for (int k = 0; k < KE; ++k) part += val[k];
+      const T tot = block_sum<T, B>(part, sredT);
+      const int h = -cur.y - 1;
+      const int4 hub = plan.hubs[h];  // {row, nchunks, slot0, -}
+      if (tid == 0) {
+        publish(&scr.hub_sum[hub.z + cur.x], (double)tot);
+        wait_stores();
+        sflag = counter_add(&scr.hub_cnt[h]) == hub.y - 1;
+      }
+      __syncthreads();
+      if (sflag) {
+        // This block finished the hub's last chunk: add the chunk sums
+        // (fixed tree over chunk order) and finish the row.
+        T s = 0;
+        for (int k = tid; k < hub.y; k += B) s += (T)consume(&scr.hub_sum[hub.z + k]);
+        s = block_sum<T, B>(s, sredT);
+        if (tid == 0) {
+          double hr = 0.0, hd = 0.0;
+          pr_epilogue(a, hub.x, s, c, hr, hd);
+          publish(&scr.hub_red[2 * h], hr);
+          publish(&scr.hub_red[2 * h + 1], hd);
+          publish(&scr.hub_cnt[h], 0);
+        }
+      }
+      __syncthreads();
     }
   }
 
-  const bool reduce = a.mode == EPI_PR && (a.rho_out.out || a.D_out.out || a.rho_out.guard);
+  const bool reduce = pr && (a.rho_out.out || a.D_out.out || a.rho_out.guard);
   if (!reduce) return;
 
   const double br = block_sum<double, B>(rho, sred);
@@ -306,16 +356,16 @@ __global__ __launch_bounds__(FUSED_BLOCK) void fused_pr_kernel(TilePlanDev plan,
   if (!sflag) return;
 
   // Last workgroup: partials in workgroup order, then hub rows in order.
-  double pr = 0.0, pd = 0.0;
+  double pr_ = 0.0, pd = 0.0;
   for (int k = tid; k < (int)gridDim.x; k += B) {
-    pr += consume(&scr.wg_part[2 * k]);
+    pr_ += consume(&scr.wg_part[2 * k]);
     pd += consume(&scr.wg_part[2 * k + 1]);
   }
   for (int h = tid; h < plan.nhubs; h += B) {
-    pr += consume(&scr.hub_red[2 * h]);
+    pr_ += consume(&scr.hub_red[2 * h]);
     pd += consume(&scr.hub_red[2 * h + 1]);
   }
-  const double tr = block_sum<double, B>(pr, sred);
+  const double tr = block_sum<double, B>(pr_, sred);
   const double tdm = block_sum<double, B>(pd, sred);
   if (tid == 0) {
     if (a.rho_out.out) *a.rho_out.out = tr;
@@ -359,6 +409,235 @@ hipError_t launch_fused_f64(const TilePlanDev& plan, const FusedArgs<double>& a,
                             const GuardDev* guard, hipStream_t s) {
   return launch_fused_dispatch<double>(plan, a, scr, grid, lds_entries, lds_rows, guard, s);
 }
+
+// ---------------------------------------------------------- wave-tiled pass
+//
+// Same pass over a plan of smaller tiles (at most WE entries and WR rows),
+// each processed by one wavefront on its own: no workgroup barrier inside
+// the tile loop, so the 16 wavefronts of a workgroup overlap each other's
+// memory and LDS phases freely.  One 1024-thread workgroup per compute unit
+// also keeps the first `hot` entries of the gathered vector in LDS for all
+// its wavefronts; with vertices numbered by decreasing out-degree those are
+// the most gathered values, served from LDS instead of the L2.
+
+template <typename T>
+struct WaveLds;
+template <>
+struct WaveLds<float> {
+  static constexpr int HMAX = 23552;  // 92 KiB: with the tile staging, 156 KiB of LDS
+};
+template <>
+struct WaveLds<double> {
+  static constexpr int HMAX = 5632;   // 44 KiB: with the tile staging, 157 KiB of LDS
+};
+
+constexpr int WAVE_BLOCK = 1024;
+constexpr int WAVE_WE = 512;
+constexpr int WAVE_WR = 256;
+
+template <typename T, int KE, int KP, int KR>
+__device__ __forceinline__ void wave_prefetch(const TilePlanDev& plan, const FusedArgs<T>& a, int t,
+                                              bool pr, int lane, TileRegs<T, KE, KP, KR>& R) {
+  R.td = plan.tiles[t];
+  const int4 d = R.td;
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int e = lane + 64 * k;
+    R.ci[k] = e < d.w ? __builtin_nontemporal_load(a.col + d.z + e) : 0;
+  }
+  if (d.y > 0) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int r = lane + 64 * k;
+      R.rp[k] = r <= d.y ? a.rowptr[d.x + r] : 0;
+    }
+    if (pr) {
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int r = lane + 64 * k;
+        const bool ok = r < d.y;
+        R.xo[k] = (ok && a.x_old) ? __builtin_nontemporal_load(a.x_old + d.x + r) : (T)0;
+        R.dv[k] = (ok && a.dvec) ? __builtin_nontemporal_load(a.dvec + d.x + r) : (T)0;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+  // order this wavefront's LDS writes before its later LDS reads by other lanes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan, FusedArgs<T> a,
+                                                                FusedScratch scr, int hot_n,
+                                                                const GuardDev* guard) {
+  constexpr int B = WAVE_BLOCK;
+  constexpr int NW = B / 64;
+  constexpr int WE = WAVE_WE, WR = WAVE_WR;
+  constexpr int KE = WE / 64, KP = (WR + 1 + 63) / 64, KR = WR / 64;
+  constexpr int HMAX = WaveLds<T>::HMAX;
+  if (guard && guard->active == 0) return;
+
+  __shared__ T hot[HMAX];
+  __shared__ T sval[NW][WE];
+  __shared__ int srp[NW][WR + 1];
+  __shared__ T sres[NW][WR];
+  __shared__ double sred[B / 64];
+  __shared__ int sflag;
+
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, lane = tid & 63;
+  const bool pr = a.mode == EPI_PR;
+  T c = (T)0;
+  if (pr) c = (T)scalar_value(a.c);
+  double rho = 0.0, dm = 0.0;
+
+  const int H = hot_n < HMAX ? hot_n : HMAX;
+  for (int k = tid; k < H; k += B) hot[k] = a.w[k];
+  __syncthreads();
+
+  const int nwaves = (int)gridDim.x * NW;
+  TileRegs<T, KE, KP, KR> R;
+  int t = (int)blockIdx.x * NW + wv;
+  if (t < plan.ntiles) wave_prefetch<T>(plan, a, t, pr, lane, R);
+  for (; t < plan.ntiles; t += nwaves) {
+    const int4 cur = R.td;
+    T val[KE];
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      const int ci = R.ci[k];
+      val[k] = (lane + 64 * k < cur.w) ? (ci < H ? hot[ci] : a.w[ci]) : (T)0;
+    }
+    int crp[KP];
+    T cxo[KR], cdv[KR];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) crp[k] = R.rp[k];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      cxo[k] = R.xo[k];
+      cdv[k] = R.dv[k];
+    }
+    const int tn = t + nwaves;
+    if (tn < plan.ntiles) wave_prefetch<T>(plan, a, tn, pr, lane, R);
+
+    if (cur.y > 0) {
+      const int row0 = cur.x, nr = cur.y, e0 = cur.z, ne = cur.w;
+      T* wval = sval[wv];
+      int* wrp = srp[wv];
+      T* wres = sres[wv];
+#pragma unroll
+      for (int k = 0; k < KE; ++k)
+        if (lane + 64 * k < ne) wval[lane + 64 * k] = val[k];
+#pragma unroll
+      for (int k = 0; k < KP; ++k)
+        if (lane + 64 * k <= nr) wrp[lane + 64 * k] = crp[k] - e0;
+      wave_lds_fence();
+      const int q = 64 / nr;
+      const int lpr = q >= 64 ? 64 : q >= 32 ? 32 : q >= 16 ? 16 : q >= 8 ? 8 : q >= 4 ? 4 : q >= 2 ? 2 : 1;
+      const int slots = 64 / lpr;
+      const int grp = lane / lpr, sub = lane & (lpr - 1);
+      const int rounds = (nr + slots - 1) / slots;
+      for (int rd = 0; rd < rounds; ++rd) {
+        const int rr = rd * slots + grp;
+        T v = 0;
+        if (rr < nr) {
+          const int hi = wrp[rr + 1];
+          for (int k = wrp[rr] + sub; k < hi; k += lpr) v += wval[k];
+        }
+        for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (sub == 0 && rr < nr) wres[rr] = v;
+      }
+      wave_lds_fence();
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int r = lane + 64 * k;
+        if (r < nr) pr_epilogue_pre(a, row0 + r, wres[r], c, cxo[k], cdv[k], rho, dm);
+      }
+      wave_lds_fence();  // wres / wval / wrp are rewritten by the next tile
+    } else {
+      // one chunk of hub row h
+      T part = 0;
+#pragma unroll
+      for (int k = 0; k < KE; ++k) part += val[k];
+      part = wave_sum(part);
+      const int h = -cur.y - 1;
+      const int4 hub = plan.hubs[h];  // {row, nchunks, slot0, -}
+      int last = 0;
+      if (lane == 0) {
+        publish(&scr.hub_sum[hub.z + cur.x], (double)part);
+        wait_stores();
+        last = counter_add(&scr.hub_cnt[h]) == hub.y - 1;
+      }
+      last = __shfl(last, 0, 64);
+      if (last) {
+        T s = 0;
+        for (int k = lane; k < hub.y; k += 64) s += (T)consume(&scr.hub_sum[hub.z + k]);
+        s = wave_sum(s);
+        if (lane == 0) {
+          double hr = 0.0, hd = 0.0;
+          pr_epilogue(a, hub.x, s, c, hr, hd);
+          publish(&scr.hub_red[2 * h], hr);
+          publish(&scr.hub_red[2 * h + 1], hd);
+          publish(&scr.hub_cnt[h], 0);
+        }
+      }
+    }
+  }
+
+  const bool reduce = pr && (a.rho_out.out || a.D_out.out || a.rho_out.guard);
+  if (!reduce) return;
+
+  const double br = block_sum<double, B>(rho, sred);
+  const double bd = block_sum<double, B>(dm, sred);
+  if (tid == 0) {
+    publish(&scr.wg_part[2 * blockIdx.x], br);
+    publish(&scr.wg_part[2 * blockIdx.x + 1], bd);
+    wait_stores();
+    sflag = ticket_add(scr.ticket) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!sflag) return;
+  double pr_ = 0.0, pd = 0.0;
+  for (int k = tid; k < (int)gridDim.x; k += B) {
+    pr_ += consume(&scr.wg_part[2 * k]);
+    pd += consume(&scr.wg_part[2 * k + 1]);
+  }
+  for (int h = tid; h < plan.nhubs; h += B) {
+    pr_ += consume(&scr.hub_red[2 * h]);
+    pd += consume(&scr.hub_red[2 * h + 1]);
+  }
+  const double tr = block_sum<double, B>(pr_, sred);
+  const double tdm = block_sum<double, B>(pd, sred);
+  if (tid == 0) {
+    if (a.rho_out.out) *a.rho_out.out = tr;
+    if (a.D_out.out) *a.D_out.out = tdm;
+    if (a.rho_out.guard) guard_advance(a.rho_out.guard, tr);
+    publish(scr.ticket, 0u);
+  }
+}
+
+hipError_t launch_fused_wave_f32(const TilePlanDev& plan, const FusedArgs<float>& a,
+                                 const FusedScratch& scr, int grid, int hot_n,
+                                 const GuardDev* guard, hipStream_t s) {
+  if (grid <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fused_wave_kernel<float>, dim3(grid), dim3(WAVE_BLOCK), 0, s, plan, a, scr,
+                     hot_n, guard);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_wave_f64(const TilePlanDev& plan, const FusedArgs<double>& a,
+                                 const FusedScratch& scr, int grid, int hot_n,
+                                 const GuardDev* guard, hipStream_t s) {
+  if (grid <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fused_wave_kernel<double>, dim3(grid), dim3(WAVE_BLOCK), 0, s, plan, a, scr,
+                     hot_n, guard);
+  return hipGetLastError();
+}
+
+int wave_hot_max(int type) { return type == T_FP32 ? WaveLds<float>::HMAX : WaveLds<double>::HMAX; }
 
 // ---------------------------------------------------------- elementwise
 
@@ -551,6 +830,7 @@ __global__ void guard_init_kernel(GuardDev* g, int active, double tol, int iterm
   g->active = active;
   g->iters = 0;
   g->rho = 1.0;
+  g->rho_prev = 0.0;
   g->tol = tol;
   g->itermax = itermax;
   g->pad = 0;
@@ -644,6 +924,26 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
   if (g < 1) g = 1;
   hipLaunchKernelGGL(stream_copy_kernel, dim3((int)g), dim3(256), 0, s, (u32x4*)dst,
                      (const u32x4*)src, n16);
+  return hipGetLastError();
+}
+
+__global__ void permute_kernel(const void* __restrict__ in, int type, const int* __restrict__ idx,
+                               void* __restrict__ out, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    const int64_t j = idx[k];
+    switch (type) {
+      case T_BOOL: ((uint8_t*)out)[k] = ((const uint8_t*)in)[j]; break;
+      case T_INT32: ((int*)out)[k] = ((const int*)in)[j]; break;
+      case T_FP32: ((float*)out)[k] = ((const float*)in)[j]; break;
+      default: ((double*)out)[k] = ((const double*)in)[j]; break;
+    }
+  }
+}
+
+hipError_t launch_permute(const void* in, int type, const int* idx, void* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(permute_kernel, dim3(ew_grid(n, 4)), dim3(EW_BLOCK), 0, s, in, type, idx, out, n);
   return hipGetLastError();
 }
 

@@ -49,26 +49,38 @@ struct OpInfo {
 // ------------------------------------------------------------ matrices
 
 struct Plan;
+struct MatData;
+using MatP = std::shared_ptr<MatData>;
+
+// The same pattern with vertices renumbered by decreasing out-degree
+// (column count): order[k] = old vertex at position k, inv[v] = position
+// of old vertex v.
+struct Relabeled {
+  MatP A;
+  BufP order, inv;
+};
 
 struct MatData {
   uint64_t id = 0;
   int64_t nrows = 0, ncols = 0, nnz = 0;
   BufP rowptr, col;
-  std::map<std::tuple<int, int, int, int, int>, std::shared_ptr<Plan>> plans;
+  std::map<std::tuple<int, int, int, int, int, int>, std::shared_ptr<Plan>> plans;
+  std::shared_ptr<Relabeled> relabeled;
 };
-using MatP = std::shared_ptr<MatData>;
+
+// Kernel family of a plan.
+enum KernelKind : int { K_BLOCK = 0, K_WAVE = 1 };
 
 // Tile plan of one matrix for the row-parallel kernels.
 struct PlanConfig {
+  int kernel = K_BLOCK;    // block-tiled or wave-tiled pass
   int lds_entries = 2048;  // STREAM tile entry budget
   int lds_rows = 1024;     // STREAM tile row budget
-  int long_row = 512;      // rows longer than this get their own tile
-  int chunk = 8192;        // rows longer than this are split in chunks
+  int long_row = 2048;     // rows longer than this get a tile of their own
+  int chunk = 2048;        // rows longer than this are split in chunks (<= lds_entries)
   int grid = 0;            // persistent workgroups (0: from the device)
-  bool operator<(const PlanConfig& o) const {
-    return std::tie(lds_entries, lds_rows, long_row, chunk, grid) <
-           std::tie(o.lds_entries, o.lds_rows, o.long_row, o.chunk, o.grid);
-  }
+  int hot = 0;             // wave kernel: leading gathered entries kept in LDS
+  int relabel = 0;         // drivers: run on the degree-renumbered copy
 };
 
 struct Plan {
@@ -237,5 +249,15 @@ ScalarArg scalar_arg(const NodeP& s);
 Operand operand_of(const NodeP& v);
 
 void launch_mark(bool fused);
+
+// Text returned by GrM_error() for the calling thread.
+void set_error_text(const std::string& msg);
+
+// Cache-backed allocator callbacks for the graph builders.
+void* cache_alloc(size_t bytes, void* ctx);
+void cache_release(void* p, void* ctx);
+
+// Degree-renumbered copy of a square pattern (built once, then cached).
+std::shared_ptr<Relabeled> get_relabeled(const MatP& A);
 
 }  // namespace nbgrb

@@ -196,6 +196,55 @@ static void fused_scratch_ensure(int grid) {
   }
 }
 
+// ------------------------------------------------------------ temporaries
+
+// Temporary buffers of the graph builders come from the buffer cache.
+static std::map<void*, BufP>& tmp_bufs() {
+  static std::map<void*, BufP> m;
+  return m;
+}
+
+void* cache_alloc(size_t bytes, void*) {
+  try {
+    BufP b = dev_alloc(bytes);
+    void* p = b->p;
+    tmp_bufs()[p] = b;
+    return p;
+  } catch (const GrbError&) {
+    return nullptr;
+  }
+}
+
+void cache_release(void* p, void*) { tmp_bufs().erase(p); }
+
+std::shared_ptr<Relabeled> get_relabeled(const MatP& A) {
+  if (A->relabeled) return A->relabeled;
+  if (A->nrows != A->ncols) fail(GrB_DIMENSION_MISMATCH, "relabeling needs a square matrix");
+  Ctx& c = g_ctx;
+  const int64_t n = A->nrows;
+  auto r = std::make_shared<Relabeled>();
+  r->order = dev_alloc(sizeof(int) * (size_t)n);
+  r->inv = dev_alloc(sizeof(int) * (size_t)n);
+  hip_check(degree_order(n, A->col ? (const int*)A->col->p : nullptr, A->nnz, (int*)r->order->p,
+                         (int*)r->inv->p, cache_alloc, cache_release, nullptr, c.stream),
+            "degree order");
+  auto m = std::make_shared<MatData>();
+  m->id = c.next_id++;
+  m->nrows = n;
+  m->ncols = n;
+  m->nnz = A->nnz;
+  m->rowptr = dev_alloc(sizeof(int) * (size_t)(n + 1));
+  if (A->nnz > 0) m->col = dev_alloc(sizeof(int) * (size_t)A->nnz);
+  hip_check(permute_csr(n, (const int*)A->rowptr->p, A->col ? (const int*)A->col->p : nullptr, A->nnz,
+                        (const int*)r->inv->p, (int*)m->rowptr->p, m->col ? (int*)m->col->p : nullptr,
+                        cache_alloc, cache_release, nullptr, c.stream),
+            "relabel");
+  launch_mark(false);
+  r->A = m;
+  A->relabeled = r;
+  return r;
+}
+
 // ------------------------------------------------------------ plans
 
 static int device_cus() { return g_ctx.cus; }
@@ -206,23 +255,28 @@ PlanConfig default_plan_config(const MatP& A, int value_type) {
   PlanConfig c;
   c.lds_entries = 2048;
   c.lds_rows = 1024;
-  c.long_row = 512;
-  c.chunk = 8192;
+  c.long_row = 2048;
+  c.chunk = 2048;
   c.grid = device_cus() * 8;
   return c;
 }
 
 std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
   PlanConfig cfg = cfg0;
-  if (cfg.grid <= 0) cfg.grid = device_cus() * 8;
-  auto key = std::make_tuple(cfg.lds_entries, cfg.lds_rows, cfg.long_row, cfg.chunk, cfg.grid);
+  if (cfg.kernel == K_WAVE) {
+    cfg.lds_entries = WAVE_TILE_ENTRIES;
+    cfg.lds_rows = WAVE_TILE_ROWS;
+  }
+  if (cfg.grid <= 0) cfg.grid = cfg.kernel == K_WAVE ? device_cus() : device_cus() * 8;
+  auto key = std::make_tuple(cfg.kernel, cfg.lds_entries, cfg.lds_rows, cfg.long_row, cfg.chunk,
+                             cfg.grid);
   auto it = A->plans.find(key);
   if (it != A->plans.end()) {
     g_ctx.stats.plan_hits++;
     return it->second;
   }
   g_ctx.stats.plan_misses++;
-  if (cfg.long_row < 1 || cfg.long_row > cfg.lds_entries || cfg.chunk < cfg.long_row ||
+  if (cfg.long_row < 1 || cfg.chunk < cfg.long_row || cfg.chunk > cfg.lds_entries ||
       cfg.lds_rows < 1)
     fail(GrB_INVALID_VALUE, "bad tile plan configuration");
   Ctx& c = g_ctx;
@@ -251,7 +305,8 @@ std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
     if (len > cfg.long_row) {
       flush(i);
       if (len <= cfg.chunk) {
-        tiles.push_back(make_int4((int)i, 0, rp[i], len));
+        // a STREAM tile of its own
+        tiles.push_back(make_int4((int)i, 1, rp[i], len));
         plan->nlong++;
       } else {
         const int h = (int)hubs.size();
@@ -341,6 +396,11 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
   Ctx& c = g_ctx;
   const PlanConfig cfg = cfg_override ? *cfg_override : default_plan_config(A, f.type);
   auto plan = get_plan(A, cfg);
+  // the hot slice is w[0, hot): never more than the gathered vector holds
+  int64_t hot = cfg.hot < 0 ? 0 : cfg.hot;
+  if (hot > A->ncols) hot = A->ncols;
+  if (hot > wave_hot_max(f.type)) hot = wave_hot_max(f.type);
+  plan->cfg.hot = (int)hot;
   fused_scratch_ensure(plan->cfg.grid);
   FusedScratch scr{};
   scr.wg_part = (double*)c.fused_part->p;
@@ -356,6 +416,7 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     hip_check(hipEventRecord(e0, c.stream), "event record");
   }
   hipError_t e;
+  const bool wave = plan->cfg.kernel == K_WAVE;
   if (f.type == T_FP32) {
     FusedArgs<float> a{};
     a.rowptr = (const int*)A->rowptr->p;
@@ -377,8 +438,9 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     a.c = f.c;
     a.rho_out = f.rho;
     a.D_out = f.D;
-    e = launch_fused_f32(plan->dev, a, scr, plan->cfg.grid, plan->cfg.lds_entries,
-                         plan->cfg.lds_rows, c.guard, c.stream);
+    e = wave ? launch_fused_wave_f32(plan->dev, a, scr, plan->cfg.grid, plan->cfg.hot, c.guard, c.stream)
+             : launch_fused_f32(plan->dev, a, scr, plan->cfg.grid, plan->cfg.lds_entries,
+                                plan->cfg.lds_rows, c.guard, c.stream);
   } else {
     FusedArgs<double> a{};
     a.rowptr = (const int*)A->rowptr->p;
@@ -400,8 +462,9 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     a.c = f.c;
     a.rho_out = f.rho;
     a.D_out = f.D;
-    e = launch_fused_f64(plan->dev, a, scr, plan->cfg.grid, plan->cfg.lds_entries,
-                         plan->cfg.lds_rows, c.guard, c.stream);
+    e = wave ? launch_fused_wave_f64(plan->dev, a, scr, plan->cfg.grid, plan->cfg.hot, c.guard, c.stream)
+             : launch_fused_f64(plan->dev, a, scr, plan->cfg.grid, plan->cfg.lds_entries,
+                                plan->cfg.lds_rows, c.guard, c.stream);
   }
   hip_check(e, "fused pass launch");
   if (timed) {

@@ -59,6 +59,11 @@ dbl = ctypes.c_double
 PV = ctypes.POINTER(ctypes.c_void_p)
 
 
+class GrM_PlanConfig(ctypes.Structure):
+    _fields_ = [("kernel", i32), ("lds_entries", i32), ("lds_rows", i32), ("long_row", i32),
+                ("chunk", i32), ("grid", i32), ("hot", i32), ("relabel", i32)]
+
+
 class GrM_Stats(ctypes.Structure):
     _fields_ = [("kernels", i64), ("fused_launches", i64), ("plan_hits", i64),
                 ("plan_misses", i64), ("elided_nodes", i64), ("forced_waits", i64)]
@@ -115,6 +120,9 @@ _FUNCS = {
     "GrM_Vector_reduce_masked_Scalar": [vp, vp, vp, vp, vp],
     "GrM_pagerank": [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, vp, dbl, dbl, i32, i32,
                      vp, i32],
+    "GrM_Matrix_plan_set": [vp, vp, ctypes.c_void_p],
+    "GrM_Matrix_plan_get": [ctypes.c_void_p, vp, vp],
+    "GrM_autotune_pagerank": [ctypes.c_void_p, ctypes.POINTER(dbl), vp, vp, vp, ctypes.c_char_p],
     "GrM_stream_copy": [vp, vp, ctypes.c_size_t],
     "GrM_timing_enable": [ctypes.c_bool],
     "GrM_timing_read": [ctypes.POINTER(dbl), ctypes.POINTER(i64)],
@@ -438,6 +446,30 @@ def GrM_pagerank(r, AT, outdeg, damping, tol, itermax, dangling=GrM_DANGLING_UNI
     _call("GrM_pagerank", r, ctypes.byref(it), ctypes.byref(res), AT, outdeg, damping, tol,
           itermax, dangling, x0, check_every)
     return it.value, res.value
+
+
+def GrM_Matrix_plan_set(A, type_, cfg: dict | None):
+    """cfg: dict with the GrM_PlanConfig fields (missing ones are 0), or None."""
+    if cfg is None:
+        _call("GrM_Matrix_plan_set", A, type_, None)
+        return
+    c = GrM_PlanConfig(**cfg)
+    _call("GrM_Matrix_plan_set", A, type_, ctypes.addressof(c))
+
+
+def GrM_Matrix_plan_get(A, type_) -> dict:
+    c = GrM_PlanConfig()
+    _call("GrM_Matrix_plan_get", ctypes.addressof(c), A, type_)
+    return {f: getattr(c, f) for f, _ in GrM_PlanConfig._fields_}
+
+
+def GrM_autotune_pagerank(AT, outdeg, type_, cache_path: str | None = None):
+    """Returns (chosen plan config dict, microseconds per pass or -1 if cached)."""
+    c = GrM_PlanConfig()
+    us = dbl()
+    _call("GrM_autotune_pagerank", ctypes.addressof(c), ctypes.byref(us), AT, outdeg, type_,
+          cache_path.encode() if cache_path else None)
+    return {f: getattr(c, f) for f, _ in GrM_PlanConfig._fields_}, us.value
 
 
 def GrM_stream_copy(dst, src, nbytes: int):
