@@ -358,6 +358,32 @@ GrB_Info GrM_pagerank(GrB_Vector r, int *iters, double *resid, GrB_Matrix AT,
                       GrB_Vector outdeg, double damping, double tol, int itermax,
                       GrM_Dangling dangling, GrB_Vector x0, int check_every);
 
+/* Personalised PageRank: as GrM_pagerank with the uniform 1/n teleport
+ * replaced by the distribution `teleport` (r's type, entries summing to
+ * one, typically 1/|S| on a seed set S):  r = s + (1-damping) v, plus, in
+ * GrM_DANGLING_UNIFORM, damping * D * v (the dangling mass returns to the
+ * seeds).  x0 = NULL starts from the teleport vector. */
+GrB_Info GrM_ppr(GrB_Vector r, int *iters, double *resid, GrB_Matrix AT, GrB_Vector outdeg,
+                 GrB_Vector teleport, double damping, double tol, int itermax,
+                 GrM_Dangling dangling, GrB_Vector x0, int check_every);
+
+/* Batched personalised PageRank of k seed sets (1 <= k <= 64), iterated
+ * together as one sparse x dense product per pass.  Seed set q is
+ * seed_vtx[seed_ptr[q] : seed_ptr[q+1]] (host int32 arrays; non-empty,
+ * distinct vertices in [0, n)); its teleport vector is 1/|S_q| on the set.
+ * Column q follows GrM_ppr exactly (start = teleport vector, the dangling
+ * mass returns to the seeds in GrM_DANGLING_UNIFORM), with the residual and
+ * dangling mass of every column in FP64.  All columns iterate until the
+ * largest column residual is <= tol (or itermax passes).  X (device,
+ * n x k row-major, `type` FP32 or FP64) receives the ranks; *iters the
+ * passes performed; col_iters[q] (host, may be NULL) the first pass at
+ * which column q's residual was <= tol (-1 if never); col_resid[q] (host,
+ * may be NULL) its last residual. */
+GrB_Info GrM_ppr_batch(void *X, GrB_Type type, int k, const int32_t *seed_ptr,
+                       const int32_t *seed_vtx, GrB_Matrix AT, GrB_Vector outdeg, double damping,
+                       double tol, int itermax, GrM_Dangling dangling, int check_every, int *iters,
+                       int *col_iters, double *col_resid);
+
 /* ------------------------------------------------------------------------
  * Tile plans.  The row-parallel kernels (mxv and the fused PageRank pass)
  * walk a plan of row tiles built once per matrix and configuration on the

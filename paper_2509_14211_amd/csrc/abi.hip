@@ -2,6 +2,7 @@
 // its arguments eagerly, then records (nonblocking) or runs (blocking) the
 // operation through the runtime.  Internal errors are C++ exceptions that
 // are turned into GrB_Info codes here.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -931,8 +932,9 @@ GrB_Info GrM_Vector_reduce_masked_Scalar(GrB_Scalar s, GrB_Vector mask, GrB_Mono
 
 // ------------------------------------------------------------ PageRank
 
-GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, GrB_Vector outdeg, double damping,
-                      double tol, int itermax, GrM_Dangling dangling, GrB_Vector x0, int check_every) {
+static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, GrB_Vector outdeg,
+                              GrB_Vector teleport, double damping, double tol, int itermax,
+                              GrM_Dangling dangling, GrB_Vector x0, int check_every) {
   Ctx& c = ctx();
   GuardDev* saved_guard = c.guard;
   BufP gbuf;
@@ -944,11 +946,13 @@ GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, Gr
   GB_Matrix_opaque* ao = mat(AT, "AT");
   GB_Vector_opaque* dego = vec(outdeg, "outdeg");
   GB_Vector_opaque* xo = x0 ? vec(x0, "x0") : nullptr;
+  GB_Vector_opaque* vo = teleport ? vec(teleport, "teleport") : nullptr;
   float_type(ro->type, "r");
   const int T = ro->type;
   const int64_t n = ao->nrows;
-  if (ao->ncols != n || ro->n != n || dego->n != n || (xo && xo->n != n))
+  if (ao->ncols != n || ro->n != n || dego->n != n || (xo && xo->n != n) || (vo && vo->n != n))
     fail(GrB_DIMENSION_MISMATCH, "pagerank dimensions");
+  if (vo && vo->type != T) fail(GrB_DOMAIN_MISMATCH, "teleport vector must have r's type");
   if (dangling != GrM_DANGLING_DROP && dangling != GrM_DANGLING_UNIFORM) fail(GrB_INVALID_VALUE, "dangling mode");
   if (check_every < 1 || itermax < 0 || !(damping >= 0.0 && damping < 1.0) || std::isnan(tol))
     fail(GrB_INVALID_VALUE, "pagerank parameters");
@@ -981,8 +985,18 @@ GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, Gr
   materialize(dinv.node);
   store_if_iso(dinv.node);
 
+  // personalised teleport distribution (permuted like every vector)
+  GB_Vector_opaque v{MAGIC_VEC, T, n, nullptr};
+  if (vo) {
+    set_vec(&v, rl ? permuted(vo->node, rl->order) : vo->node);
+    materialize(v.node);
+    store_if_iso(v.node);
+  }
+
   GB_Vector_opaque x{MAGIC_VEC, T, n, nullptr};
-  if (xo) {
+  if (!xo && vo) {
+    set_vec(&x, v.node);
+  } else if (xo) {
     if (xo->type == T)
       set_vec(&x, xo->node);
     else
@@ -1017,7 +1031,17 @@ GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, Gr
       GB_Scalar_opaque Dn{MAGIC_SCA, T_FP64, nullptr};
       rec_ewise(&w, B_TIMES, &x, &dinv);            // w = x .* d
       rec_mxv(&s, &A_exec, &w);                     // s = AT (+.second) w
-      if (uniform) {                                // r = c + s
+      GB_Vector_opaque vt{MAGIC_VEC, T, n, nullptr};
+      if (vo) {                                     // r = s + v .* c
+        if (uniform) {                              //   c = (1-d) + d D
+          rec_affine(&cs, damping, &D, 1.0 - damping);
+          rec_bind_scalar(&vt, B_TIMES, &v, &cs);
+        } else {                                    //   c = 1-d
+          rec_bind(&vt, B_TIMES, &v, 1.0 - damping, false);
+        }
+        rec_ewise(&rn, B_PLUS, &s, &vt);
+        set_vec(&vt, nullptr);
+      } else if (uniform) {                         // r = c + s, c = (1-d)/n + d D/n
         rec_affine(&cs, damping / (double)n, &D, tele);
         rec_bind_scalar(&rn, B_PLUS, &s, &cs);
       } else {
@@ -1067,10 +1091,238 @@ GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, Gr
   set_vec(ro, rl ? permuted(result, rl->inv) : result);
   hist.clear();
   set_vec(&x, nullptr);
+  set_vec(&v, nullptr);
   set_vec(&dinv, nullptr);
   set_sca(&D, nullptr);
   *iters = hg.iters;
   *resid = hg.rho;
+  }
+  catch (const GrbError& e) {
+    c.guard = saved_guard;
+    g_err = e.msg;
+    return e.info;
+  }
+  catch (const std::exception& e) {
+    c.guard = saved_guard;
+    g_err = e.what();
+    return GrB_PANIC;
+  }
+  return GrB_SUCCESS;
+}
+
+GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, GrB_Vector outdeg, double damping,
+                      double tol, int itermax, GrM_Dangling dangling, GrB_Vector x0, int check_every) {
+  return pagerank_impl(r, iters, resid, AT, outdeg, nullptr, damping, tol, itermax, dangling, x0, check_every);
+}
+
+GrB_Info GrM_ppr(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, GrB_Vector outdeg, GrB_Vector teleport,
+                 double damping, double tol, int itermax, GrM_Dangling dangling, GrB_Vector x0, int check_every) {
+  if (!teleport) {
+    g_err = "teleport is NULL";
+    return GrB_NULL_POINTER;
+  }
+  return pagerank_impl(r, iters, resid, AT, outdeg, teleport, damping, tol, itermax, dangling, x0, check_every);
+}
+
+GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, const int32_t* seed_vtx,
+                       GrB_Matrix AT, GrB_Vector outdeg, double damping, double tol, int itermax,
+                       GrM_Dangling dangling, int check_every, int* iters, int* col_iters, double* col_resid) {
+  Ctx& c = ctx();
+  GuardDev* saved_guard = c.guard;
+  API_BEGIN
+  require_init();
+  need(X, "X");
+  need(type, "type");
+  need(seed_ptr, "seed_ptr");
+  need(iters, "iters");
+  GB_Matrix_opaque* ao = mat(AT, "AT");
+  GB_Vector_opaque* dego = vec(outdeg, "outdeg");
+  const int T = type->code;
+  float_type(T, "type");
+  const int64_t n = ao->nrows;
+  if (ao->ncols != n || dego->n != n) fail(GrB_DIMENSION_MISMATCH, "ppr_batch dimensions");
+  if (k < 1 || k > 64) fail(GrB_INVALID_VALUE, "k must be in [1, 64]");
+  if (dangling != GrM_DANGLING_DROP && dangling != GrM_DANGLING_UNIFORM) fail(GrB_INVALID_VALUE, "dangling mode");
+  if (check_every < 1 || itermax < 0 || !(damping >= 0.0 && damping < 1.0) || std::isnan(tol))
+    fail(GrB_INVALID_VALUE, "ppr_batch parameters");
+  if (c.guard) fail(GrB_INVALID_VALUE, "an iterative driver is already running");
+  if (seed_ptr[0] != 0) fail(GrB_INVALID_VALUE, "seed_ptr[0] must be 0");
+  for (int q = 0; q < k; ++q)
+    if (seed_ptr[q + 1] <= seed_ptr[q]) fail(GrB_INVALID_VALUE, "every seed set must be non-empty");
+  const int ns = seed_ptr[k];
+  need(seed_vtx, "seed_vtx");
+  for (int q = 0; q < k; ++q) {
+    std::vector<int> s(seed_vtx + seed_ptr[q], seed_vtx + seed_ptr[q + 1]);
+    std::sort(s.begin(), s.end());
+    for (size_t i = 0; i < s.size(); ++i) {
+      if (s[i] < 0 || s[i] >= n) fail(GrB_INDEX_OUT_OF_BOUNDS, "seed vertex out of range");
+      if (i > 0 && s[i] == s[i - 1]) fail(GrB_INVALID_VALUE, "repeated seed vertex in a set");
+    }
+  }
+  const bool uniform = dangling == GrM_DANGLING_UNIFORM;
+
+  // execution matrix (degree-renumbered copy if the plan asks for it)
+  const PlanConfig pc = default_plan_config(ao->data, T);
+  std::shared_ptr<Relabeled> rl;
+  MatP A_exec = ao->data;
+  std::vector<int> inv_host;
+  if (pc.relabel) {
+    rl = get_relabeled(ao->data);
+    A_exec = rl->A;
+    inv_host.resize((size_t)n);
+    hip_check(hipMemcpyAsync(inv_host.data(), rl->inv->p, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost, c.stream),
+              "copy permutation");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+  }
+  PlanConfig wp;
+  wp.kernel = K_WAVE;
+  wp.lds_entries = WAVE_TILE_ENTRIES;
+  wp.lds_rows = WAVE_TILE_ROWS;
+  wp.long_row = (pc.kernel == K_WAVE) ? pc.long_row : WAVE_TILE_ENTRIES;
+  wp.chunk = WAVE_TILE_ENTRIES;
+  wp.grid = c.cus * 2;
+  auto plan = get_plan(A_exec, wp);
+
+  // d = damping ./ outdeg (0 for dangling), in execution order
+  GB_Vector_opaque deg_exec{MAGIC_VEC, dego->type, n, nullptr};
+  set_vec(&deg_exec, rl ? permuted(dego->node, rl->order) : dego->node);
+  GB_Vector_opaque dinv{MAGIC_VEC, T, n, nullptr};
+  rec_unop(&dinv, U_MINV_OR_ZERO, &deg_exec);
+  rec_bind(&dinv, B_TIMES, &dinv, damping, true);
+  set_vec(&deg_exec, nullptr);
+  materialize(dinv.node);
+  store_if_iso(dinv.node);
+
+  // seed tables: by column (initial vectors) and sorted by vertex (teleport)
+  struct Seed {
+    int v, c;
+    double w;
+  };
+  std::vector<Seed> seeds;
+  std::vector<int> bc_ptr(k + 1), bc_v(ns);
+  std::vector<double> bc_w(ns);
+  for (int q = 0; q < k; ++q) {
+    bc_ptr[q] = seed_ptr[q];
+    const double w = 1.0 / (double)(seed_ptr[q + 1] - seed_ptr[q]);
+    for (int e = seed_ptr[q]; e < seed_ptr[q + 1]; ++e) {
+      const int v = rl ? inv_host[(size_t)seed_vtx[e]] : seed_vtx[e];
+      bc_v[e] = v;
+      bc_w[e] = w;
+      seeds.push_back({v, q, w});
+    }
+  }
+  bc_ptr[k] = ns;
+  std::sort(seeds.begin(), seeds.end(), [](const Seed& a, const Seed& b) { return a.v != b.v ? a.v < b.v : a.c < b.c; });
+  std::vector<int> sv(ns), sc(ns);
+  std::vector<double> sw(ns);
+  for (int i = 0; i < ns; ++i) {
+    sv[i] = seeds[i].v;
+    sc[i] = seeds[i].c;
+    sw[i] = seeds[i].w;
+  }
+  auto upload = [&](const void* h, size_t bytes) {
+    BufP b = dev_alloc(bytes);
+    hip_check(hipMemcpyAsync(b->p, h, bytes, hipMemcpyHostToDevice, c.stream), "upload");
+    return b;
+  };
+  BufP d_sv = upload(sv.data(), sizeof(int) * ns), d_sc = upload(sc.data(), sizeof(int) * ns);
+  BufP d_sw = upload(sw.data(), sizeof(double) * ns);
+  BufP d_bcp = upload(bc_ptr.data(), sizeof(int) * (k + 1)), d_bcv = upload(bc_v.data(), sizeof(int) * ns);
+  BufP d_bcw = upload(bc_w.data(), sizeof(double) * ns);
+
+  const size_t vbytes = type_size(T) * (size_t)n * (size_t)k;
+  BufP Xb[2] = {dev_alloc(vbytes), dev_alloc(vbytes)};
+  BufP Wb[2] = {dev_alloc(vbytes), dev_alloc(vbytes)};
+  BufP Db[2] = {dev_alloc(sizeof(double) * 64), dev_alloc(sizeof(double) * 64)};
+  BufP rho = dev_alloc(sizeof(double) * 64), hit = dev_alloc(sizeof(int) * 64);
+  const int grid = plan->cfg.grid;
+  BufP hub_sum = dev_alloc(sizeof(double) * 64 * (size_t)std::max(plan->nparts, 1));
+  BufP hub_cnt = dev_alloc(sizeof(int) * (size_t)std::max(plan->nhubs, 1));
+  BufP hub_red = dev_alloc(sizeof(double) * 128 * (size_t)std::max(plan->nhubs, 1));
+  BufP wg_part = dev_alloc(sizeof(double) * 128 * (size_t)grid);
+  BufP ticket = dev_alloc(256);
+  BufP gbuf = dev_alloc(sizeof(GuardDev));
+  hip_check(launch_zero(hub_cnt->p, sizeof(int) * (size_t)std::max(plan->nhubs, 1), c.stream), "zero");
+  hip_check(launch_zero(ticket->p, 256, c.stream), "zero");
+  hip_check(launch_zero(Xb[0]->p, vbytes, c.stream), "zero");
+  hip_check(launch_zero(Wb[0]->p, vbytes, c.stream), "zero");
+  for (int i = 0; i < 4; ++i) launch_mark(false);
+
+  SpmmArgs a{};
+  a.rowptr = (const int*)A_exec->rowptr->p;
+  a.col = A_exec->col ? (const int*)A_exec->col->p : nullptr;
+  a.k = k;
+  a.dvec = dinv.node->buf->p;
+  a.seed_v = (const int*)d_sv->p;
+  a.seed_c = (const int*)d_sc->p;
+  a.seed_w = (const double*)d_sw->p;
+  a.nseeds = ns;
+  a.c_alpha = damping;
+  a.c_beta = 1.0 - damping;
+  a.rho_out = (double*)rho->p;
+  a.hit = (int*)hit->p;
+  a.hub_sum = (double*)hub_sum->p;
+  a.hub_cnt = (int*)hub_cnt->p;
+  a.hub_red = (double*)hub_red->p;
+  a.wg_part = (double*)wg_part->p;
+  a.ticket = (unsigned*)ticket->p;
+  // initial vectors
+  a.x_new = Xb[0]->p;
+  a.w_new = Wb[0]->p;
+  a.d_out = (double*)Db[0]->p;
+  hip_check(launch_spmm_init(a, T, (const int*)d_bcp->p, (const int*)d_bcv->p, (const double*)d_bcw->p, c.stream),
+            "ppr init");
+  launch_mark(false);
+  hip_check(launch_guard_init((GuardDev*)gbuf->p, (1.0 > tol && itermax > 0) ? 1 : 0, tol, itermax, c.stream),
+            "guard init");
+  launch_mark(false);
+  c.guard = (GuardDev*)gbuf->p;
+  a.guard = c.guard;
+
+  GuardDev hg{};
+  int pass = 0, batch = check_every;
+  for (;;) {
+    for (int j = 0; j < batch; ++j) {
+      ++pass;
+      const int in = (pass - 1) & 1, out = pass & 1;
+      a.w = Wb[in]->p;
+      a.x_old = Xb[in]->p;
+      a.x_new = Xb[out]->p;
+      a.w_new = Wb[out]->p;
+      a.d_prev = uniform ? (const double*)Db[in]->p : nullptr;
+      a.d_out = (double*)Db[out]->p;
+      hip_check(launch_spmm_ppr(plan->dev, a, T, grid, c.guard, c.stream), "ppr pass");
+      launch_mark(true);
+    }
+    hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    if (!hg.active) break;
+    int next = check_every;
+    if (hg.rho_prev > 0.0 && hg.rho > 0.0 && hg.rho < hg.rho_prev && tol > 0.0) {
+      const double need_passes = std::log(tol / hg.rho) / std::log(hg.rho / hg.rho_prev);
+      if (need_passes > 0.0 && need_passes < 1e6) next = (int)std::ceil(need_passes);
+    }
+    if (next > itermax - hg.iters) next = itermax - hg.iters;
+    if (next < 1) next = 1;
+    batch = next;
+  }
+  c.guard = saved_guard;
+  const BufP& res = Xb[hg.iters & 1];
+  if (rl)
+    hip_check(launch_rows_permute(res->p, T, (const int*)rl->inv->p, X, n, k, c.stream), "unpermute");
+  else
+    hip_check(hipMemcpyAsync(X, res->p, vbytes, hipMemcpyDeviceToDevice, c.stream), "copy out");
+  std::vector<int> hh(64);
+  std::vector<double> rr(64);
+  hip_check(hipMemcpyAsync(hh.data(), hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+  hip_check(hipMemcpyAsync(rr.data(), rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+  if (col_iters)
+    for (int q = 0; q < k; ++q) col_iters[q] = hg.iters == 0 ? -1 : hh[q];
+  if (col_resid)
+    for (int q = 0; q < k; ++q) col_resid[q] = hg.iters == 0 ? 1.0 : rr[q];
+  set_vec(&dinv, nullptr);
+  *iters = hg.iters;
   }
   catch (const GrbError& e) {
     c.guard = saved_guard;

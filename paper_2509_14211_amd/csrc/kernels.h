@@ -86,7 +86,8 @@ struct TilePlanDev {
 
 // Epilogue of the fused PageRank pass, per row i with row sum s:
 //   mode PLAIN : s_out[i] = s
-//   mode PR    : r = tele(i) + s, tele(i) = tele_vec ? tele_vec[i] : c,
+//   mode PR    : r = tele(i) + s, tele(i) = tele_vec ? tele_vec[i] (* c when
+//                tele_scaled) : c,
 //                c = (T)(c.alpha * (*c.dev) + c.beta) or (T)c.beta;
 //                r_out[i] = r; rho += |x_old[i] - r| (FP64);
 //                w_out[i] = memo_div ? r / dvec[i] : r * dvec[i];
@@ -111,6 +112,7 @@ struct FusedArgs {
   Operand mask;       // otherwise this vector
   int mask_comp;      // complement the mask
   const T* tele_vec;  // per-row teleport (nullptr: scalar c)
+  int tele_scaled;    // teleport = tele_vec[i] * c instead of tele_vec[i]
   ScalarArg c;
   ReduceOut rho_out;
   ReduceOut D_out;
@@ -194,6 +196,49 @@ hipError_t launch_row_degree(const int* rowptr, int64_t n, void* deg, int type, 
 // non-decreasing 0..nnz sequence or a column is outside [0, ncols).
 hipError_t launch_check_csr(const int* rowptr, int64_t nrows, const int* col, int64_t nnz,
                             int64_t ncols, int* flag, hipStream_t s);
+
+// ------------------------------------------------------------ batched PPR
+// One pass of k-column personalised PageRank over the wavefront-tile plan
+// (spmm.hip).  x_old / w / x_new / w_new are n x k row-major.  Seeds are
+// given sorted by vertex (seed_v ascending; seed_c its column, seed_w its
+// weight 1/|S_c|).  d_prev[c] is the previous dangling mass of column c
+// (nullptr: no redistribution); the teleport factor of column c is
+// c_beta + c_alpha * d_prev[c].  hub_sum holds 64 slots per chunk,
+// hub_red and wg_part 128 per hub / workgroup.
+struct SpmmArgs {
+  const int* rowptr;
+  const int* col;
+  int k;
+  const void* w;
+  const void* x_old;
+  const void* dvec;
+  void* x_new;
+  void* w_new;
+  const int* seed_v;
+  const int* seed_c;
+  const double* seed_w;
+  int nseeds;
+  const double* d_prev;
+  double c_alpha, c_beta;
+  double* rho_out;  // k
+  double* d_out;    // k
+  int* hit;         // k: first pass with rho_c <= tol (-1 before)
+  GuardDev* guard;
+  double* hub_sum;
+  int* hub_cnt;
+  double* hub_red;
+  double* wg_part;
+  unsigned* ticket;
+};
+constexpr int SPMM_BLOCK = 1024;
+hipError_t launch_spmm_ppr(const TilePlanDev& plan, const SpmmArgs& a, int type, int grid,
+                           const GuardDev* guard, hipStream_t s);
+// x_new = V, w_new = V .* d (both must be zero beforehand), d_out = D0, hit = -1.
+hipError_t launch_spmm_init(const SpmmArgs& a, int type, const int* by_col_ptr, const int* by_col_v,
+                            const double* by_col_w, hipStream_t s);
+// out row i = in row idx[i] (n rows of k values).
+hipError_t launch_rows_permute(const void* in, int type, const int* idx, void* out, int64_t n, int k,
+                               hipStream_t s);
 
 // ------------------------------------------------------------ graph build
 // (graph_build.hip) Sort-based construction of a CSR pattern from an edge

@@ -156,7 +156,7 @@ __device__ __forceinline__ void pr_epilogue(const FusedArgs<T>& a, int i, T s, T
     a.s_out[i] = s;
     return;
   }
-  const T tele = a.tele_vec ? a.tele_vec[i] : c;
+  const T tele = a.tele_vec ? (a.tele_scaled ? a.tele_vec[i] * c : a.tele_vec[i]) : c;
   const T r = tele + s;
   if (a.r_out) __builtin_nontemporal_store(r, a.r_out + i);
   if (a.x_old) rho += fabs((double)__builtin_nontemporal_load(a.x_old + i) - (double)r);
@@ -219,7 +219,7 @@ __device__ __forceinline__ void pr_epilogue_pre(const FusedArgs<T>& a, int i, T 
     a.s_out[i] = s;
     return;
   }
-  const T tele = a.tele_vec ? a.tele_vec[i] : c;
+  const T tele = a.tele_vec ? (a.tele_scaled ? a.tele_vec[i] * c : a.tele_vec[i]) : c;
   const T r = tele + s;
   if (a.r_out) __builtin_nontemporal_store(r, a.r_out + i);
   if (a.x_old) rho += fabs((double)xo - (double)r);

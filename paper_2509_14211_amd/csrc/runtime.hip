@@ -375,6 +375,7 @@ struct FusedSpec {
   Operand mask{};
   int mask_comp = 0;
   const void* tele_vec = nullptr;
+  int tele_scaled = 0;
   ScalarArg c{nullptr, 0.0, 0.0};
   ReduceOut rho{nullptr, nullptr};
   ReduceOut D{nullptr, nullptr};
@@ -435,6 +436,7 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     a.mask = f.mask;
     a.mask_comp = f.mask_comp;
     a.tele_vec = (const float*)f.tele_vec;
+    a.tele_scaled = f.tele_scaled;
     a.c = f.c;
     a.rho_out = f.rho;
     a.D_out = f.D;
@@ -459,6 +461,7 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     a.mask = f.mask;
     a.mask_comp = f.mask_comp;
     a.tele_vec = (const double*)f.tele_vec;
+    a.tele_scaled = f.tele_scaled;
     a.c = f.c;
     a.rho_out = f.rho;
     a.D_out = f.D;
@@ -602,7 +605,7 @@ bool is_dense_of(const NodeP& v, int type) { return v && v->done && !v->iso && v
 
 // The mxv anchor of a PageRank-iteration group and the nodes it absorbs.
 struct PRMatch {
-  NodeP M, E, T, R, DR;
+  NodeP M, E, T, R, DR, RT;
   NodeP W;
   NodeP X;        // vector whose memo the pass gathers (W = X op DV)
   NodeP DV;       // pre-scale vector
@@ -637,11 +640,22 @@ bool match_pr(const NodeP& M, const Consumers& cons, PRMatch& m) {
     f.c = ScalarArg{nullptr, 0.0, E->k};
   } else if (E->kind == N_EWISE && E->op == B_PLUS && (E->a == M || E->b == M)) {
     NodeP RT = E->a == M ? E->b : E->a;
-    if (!RT->done || RT->type != T) return false;
-    if (RT->iso)
-      f.c = ScalarArg{nullptr, 0.0, RT->iso_val};
-    else
-      f.tele_vec = RT->buf->p;
+    if (RT->type != T) return false;
+    if (RT->done) {
+      if (RT->iso)
+        f.c = ScalarArg{nullptr, 0.0, RT->iso_val};
+      else
+        f.tele_vec = RT->buf->p;
+    } else if ((RT->kind == N_APPLY_B2S || RT->kind == N_APPLY_B2) && RT->op == B_TIMES &&
+               RT->handles == 0 && only_consumer(cons, RT.get(), E.get()) && is_dense_of(RT->a, T)) {
+      // teleport v .* c with a (possibly pending) scalar c: folded per row
+      f.tele_vec = RT->a->buf->p;
+      f.tele_scaled = 1;
+      f.c = RT->kind == N_APPLY_B2S ? scalar_arg(RT->s) : ScalarArg{nullptr, 0.0, RT->k};
+      m.RT = RT;
+    } else {
+      return false;
+    }
   } else {
     return false;
   }
@@ -746,6 +760,10 @@ static void run_pr_group(PRMatch& m, const Consumers& cons) {
   if (m.T) {
     m.T->done = true;
     release_inputs(*m.T);
+  }
+  if (m.RT) {
+    m.RT->done = true;  // folded into the pass, never stored
+    release_inputs(*m.RT);
   }
   if (m.R) {
     m.R->done = true;

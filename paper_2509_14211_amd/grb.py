@@ -120,6 +120,10 @@ _FUNCS = {
     "GrM_Vector_reduce_masked_Scalar": [vp, vp, vp, vp, vp],
     "GrM_pagerank": [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, vp, dbl, dbl, i32, i32,
                      vp, i32],
+    "GrM_ppr": [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, vp, vp, dbl, dbl, i32, i32,
+                vp, i32],
+    "GrM_ppr_batch": [vp, vp, i32, vp, vp, vp, vp, dbl, dbl, i32, i32, i32, ctypes.POINTER(i32),
+                      vp, vp],
     "GrM_Matrix_plan_set": [vp, vp, ctypes.c_void_p],
     "GrM_Matrix_plan_get": [ctypes.c_void_p, vp, vp],
     "GrM_autotune_pagerank": [ctypes.c_void_p, ctypes.POINTER(dbl), vp, vp, vp, ctypes.c_char_p],
@@ -470,6 +474,37 @@ def GrM_autotune_pagerank(AT, outdeg, type_, cache_path: str | None = None):
     _call("GrM_autotune_pagerank", ctypes.addressof(c), ctypes.byref(us), AT, outdeg, type_,
           cache_path.encode() if cache_path else None)
     return {f: getattr(c, f) for f, _ in GrM_PlanConfig._fields_}, us.value
+
+
+def GrM_ppr(r, AT, outdeg, teleport, damping, tol, itermax, dangling=GrM_DANGLING_UNIFORM,
+            x0=None, check_every=8):
+    """Personalised PageRank; returns (iterations, residual), ranks in r."""
+    it = i32()
+    res = dbl()
+    _call("GrM_ppr", r, ctypes.byref(it), ctypes.byref(res), AT, outdeg, teleport, damping, tol,
+          itermax, dangling, x0, check_every)
+    return it.value, res.value
+
+
+def GrM_ppr_batch(X, type_, seed_sets, AT, outdeg, damping, tol, itermax,
+                  dangling=GrM_DANGLING_UNIFORM, check_every=8):
+    """seed_sets: list of k integer sequences.  X: device buffer (tensor or
+    address) of n*k entries of type_.  Returns (passes, per-column first
+    converged pass, per-column last residual)."""
+    import numpy as np
+    k = len(seed_sets)
+    ptr = np.zeros(k + 1, dtype=np.int32)
+    for q, s in enumerate(seed_sets):
+        ptr[q + 1] = ptr[q] + len(s)
+    vtx = np.ascontiguousarray(np.concatenate([np.asarray(s, dtype=np.int32) for s in seed_sets])
+                               if k else np.zeros(0, np.int32), dtype=np.int32)
+    it = i32()
+    col_it = np.zeros(max(k, 1), dtype=np.int32)
+    col_res = np.zeros(max(k, 1), dtype=np.float64)
+    _call("GrM_ppr_batch", _addr(X), type_, k, ptr.ctypes.data, vtx.ctypes.data, AT, outdeg,
+          damping, tol, itermax, dangling, check_every, ctypes.byref(it), col_it.ctypes.data,
+          col_res.ctypes.data)
+    return it.value, col_it[:k].copy(), col_res[:k].copy()
 
 
 def GrM_stream_copy(dst, src, nbytes: int):

@@ -1,0 +1,139 @@
+"""Personalised PageRank on the GPU: the single-vector driver (GrM_ppr) and
+the batched SpMM driver (GrM_ppr_batch), each column against the FP64
+oracle at the same pass count."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+D = 0.85
+
+
+def _tcode(grb, dtype):
+    return grb.builtin("GrB_FP32" if dtype == torch.float32 else "GrB_FP64")
+
+
+def _ppr_single(grb, g, seeds, dtype, **kw):
+    from paper_2509_14211_amd import api
+    n = g.n
+    v = torch.zeros(n, dtype=dtype, device="cuda")
+    v[torch.as_tensor(seeds, dtype=torch.long)] = 1.0 / len(seeds)
+    vv = api.vector_from_tensor(v)
+    r = grb.GrB_Vector_new(_tcode(grb, dtype), n)
+    it, res = grb.GrM_ppr(r, g.AT, g.outdeg, vv, D, kw.get("tol", 1e-9), kw.get("itermax", 1000),
+                          kw.get("dangling", 1), None, 8)
+    x = api.tensor_from_vector(r, dtype).cpu().numpy().astype(np.float64)
+    grb.GrB_Vector_free(r)
+    grb.GrB_Vector_free(vv)
+    return x, it, res
+
+
+def _batch(grb, g, sets, dtype, tol, itermax=1000, dangling=1):
+    X = torch.empty(g.n * len(sets), dtype=dtype, device="cuda")
+    it, col_it, col_res = grb.GrM_ppr_batch(X, _tcode(grb, dtype), sets, g.AT, g.outdeg, D, tol,
+                                            itermax, dangling)
+    return X.view(g.n, len(sets)).cpu().numpy().astype(np.float64), it, col_it, col_res
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_ppr_single_matches_oracle(nonblocking, oracle_mod, mode, relabel):
+    from paper_2509_14211_amd import api
+    grb = nonblocking
+    g = api.rmat_graph(12)
+    og = oracle_mod.rmat_graph(12)
+    for dtype in (torch.float64, torch.float32):
+        grb.GrM_Matrix_plan_set(g.AT, _tcode(grb, dtype),
+                                dict(kernel=1, lds_entries=512, lds_rows=256, long_row=512, chunk=512,
+                                     grid=0, hot=1 << 20, relabel=relabel))
+    for seeds in synthetic.ppr_seed_sets(g.n, 3, seed=11):
+        x, it, res = _ppr_single(grb, g, seeds, torch.float64, dangling=mode)
+        ref = oracle_mod.ppr(og, seeds, D, fixed_iters=it, mode=mode)
+        assert np.abs(x - ref.x).sum() / np.abs(ref.x).sum() <= 1e-12
+        free = oracle_mod.ppr(og, seeds, D, tol=1e-9, mode=mode)
+        assert abs(it - free.iters) <= 1
+        x, it, res = _ppr_single(grb, g, seeds, torch.float32, tol=1e-6, dangling=mode)
+        ref = oracle_mod.ppr(og, seeds, D, fixed_iters=it, mode=mode)
+        assert np.abs(x - ref.x).sum() <= 1e-5
+    g.free()
+
+
+@pytest.mark.parametrize("relabel", [0, 1])
+@pytest.mark.parametrize("k", [1, 7, 64])
+def test_ppr_batch_matches_oracle(nonblocking, oracle_mod, k, relabel):
+    from paper_2509_14211_amd import api
+    grb = nonblocking
+    print("ppr batch k", k, "relabel", relabel, flush=True)
+    g = api.rmat_graph(11)
+    og = oracle_mod.rmat_graph(11)
+    for dtype in (torch.float64, torch.float32):
+        grb.GrM_Matrix_plan_set(g.AT, _tcode(grb, dtype),
+                                dict(kernel=1, lds_entries=512, lds_rows=256, long_row=512, chunk=512,
+                                     grid=0, hot=0, relabel=relabel))
+    sets = synthetic.ppr_seed_sets(g.n, k, seed=7)
+    X, it, col_it, col_res = _batch(grb, g, sets, torch.float64, tol=1e-9)
+    assert it >= 1 and col_res.max() <= 1e-9
+    for q, s in enumerate(sets):
+        ref = oracle_mod.ppr(og, s, D, fixed_iters=it)
+        assert np.abs(X[:, q] - ref.x).sum() / np.abs(ref.x).sum() <= 1e-12, q
+        free = oracle_mod.ppr(og, s, D, tol=1e-9)
+        assert abs(int(col_it[q]) - free.iters) <= 1, (q, col_it[q], free.iters)
+    X, it, _, _ = _batch(grb, g, sets, torch.float32, tol=1e-6)
+    for q, s in enumerate(sets):
+        ref = oracle_mod.ppr(og, s, D, fixed_iters=it)
+        assert np.abs(X[:, q] - ref.x).sum() <= 1e-5, q
+    g.free()
+
+
+def test_ppr_batch_drop_mode_and_hubs(nonblocking, oracle_mod):
+    """DROP mode, and a hub row longer than a chunk (split across wavefronts)."""
+    from paper_2509_14211_amd import api
+    grb = nonblocking
+    n, src, dst = synthetic.star_both(3000)
+    g = api.graph_from_edges(n, src, dst)
+    og = oracle_mod.graph_from_edges(n, src, dst)
+    sets = [[0], [1, 2, 3], list(range(5, 21))]
+    X, it, _, _ = _batch(grb, g, sets, torch.float64, tol=1e-12, dangling=0)
+    for q, s in enumerate(sets):
+        ref = oracle_mod.ppr(og, s, D, fixed_iters=it, mode=0)
+        assert np.abs(X[:, q] - ref.x).sum() / np.abs(ref.x).sum() <= 1e-12
+    g.free()
+
+
+def test_ppr_batch_all_vertices_is_global_pagerank(nonblocking):
+    from paper_2509_14211_amd import api
+    grb = nonblocking
+    g = api.rmat_graph(10)
+    X, it, _, _ = _batch(grb, g, [list(range(g.n))], torch.float64, tol=1e-10)
+    x, it2, _ = api.pagerank(g, torch.float64, tol=1e-10)
+    assert it == it2
+    assert np.abs(X[:, 0] - x.cpu().numpy()).sum() <= 1e-13
+    g.free()
+
+
+def test_ppr_batch_invariants_and_errors(nonblocking):
+    from paper_2509_14211_amd import api
+    grb = nonblocking
+    g = api.rmat_graph(10)
+    sets = synthetic.ppr_seed_sets(g.n, 5, seed=3)
+    X, it, _, _ = _batch(grb, g, sets, torch.float64, tol=1e-8)
+    rp, _ = api.csr_of(g.AT)
+    indeg = np.diff(rp.cpu().numpy())
+    for q, s in enumerate(sets):
+        assert abs(X[:, q].sum() - 1.0) < 1e-12
+        zero = indeg == 0
+        zero[s] = False
+        assert np.all(X[zero, q] == 0.0)
+    Xb = torch.empty(g.n * 2, dtype=torch.float64, device="cuda")
+    t = grb.builtin("GrB_FP64")
+    for bad in ([[1], []], [[1, 1]], [[g.n]], [[-1]]):
+        with pytest.raises(grb.GrBError):
+            grb.GrM_ppr_batch(Xb, t, bad, g.AT, g.outdeg, D, 1e-6, 100)
+    with pytest.raises(grb.GrBError):
+        grb.GrM_ppr_batch(Xb, t, [[0]] * 65, g.AT, g.outdeg, D, 1e-6, 100)
+    X, it, col_it, _ = _batch(grb, g, sets, torch.float64, tol=2.0)
+    assert it == 0 and np.all(col_it == -1)
+    g.free()
