@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--ppr-k", type=int, default=64, help="seed sets of the batched PPR leg")
     ap.add_argument("--skip-extras", action="store_true",
                     help="time only the headline fused solve (for profiling)")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
@@ -237,6 +238,54 @@ def main():
             out["fp64_fused"] = {"gteps": round(gteps64, 2), "ms_per_solve": round(ms64, 4),
                                  "iterations": iters64[-1]}
             out["l1_fp32_vs_fp64"] = err
+
+        # ---- batched personalised PageRank: 64 seed sets (sizes 1..16) as one
+        # SpMM solve vs 64 sequential single-vector solves, same tolerance
+        if not args.skip_extras and args.ppr_k > 0:
+            import synthetic
+            sets = [s.tolist() for s in synthetic.ppr_seed_sets(n, args.ppr_k, seed=7)]
+            f32 = grb.builtin("GrB_FP32")
+            X = torch.empty(n * len(sets), dtype=torch.float32, device="cuda")
+            grb.GrM_ppr_batch(X, f32, sets, g.AT, g.outdeg, DAMPING, args.tol, 1000)  # warm-up
+            torch.cuda.synchronize()
+            reps = 3
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                pit, col_it, col_res = grb.GrM_ppr_batch(X, f32, sets, g.AT, g.outdeg, DAMPING,
+                                                         args.tol, 1000)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            batch_ms = e0.elapsed_time(e1) / reps
+            # sequential single-vector solves of the first few sets, scaled
+            nseq = min(8, len(sets))
+            r = grb.GrB_Vector_new(f32, n)
+            seq_ms = 0.0
+            for s_ in sets[:nseq]:
+                v = torch.zeros(n, dtype=torch.float32, device="cuda")
+                v[torch.as_tensor(s_, dtype=torch.long)] = 1.0 / len(s_)
+                vv = api.vector_from_tensor(v)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                grb.GrM_ppr(r, g.AT, g.outdeg, vv, DAMPING, args.tol, 1000)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                seq_ms += e0.elapsed_time(e1)
+                grb.GrB_Vector_free(vv)
+            grb.GrB_Vector_free(r)
+            seq_per_query = seq_ms / nseq
+            bpp = 4 * (n + 1) + 4 * m + 4 * n + 4 * n * len(sets) * 4
+            del X
+            log("ppr batch: %d sets, %d passes, %.2f ms -> %.1f queries/s; sequential %.2f ms/query "
+                "(%.1f queries/s)" % (len(sets), pit, batch_ms, len(sets) / batch_ms * 1e3,
+                                      seq_per_query, 1e3 / seq_per_query))
+            out["ppr"] = {"queries_per_s": round(len(sets) / batch_ms * 1e3, 1), "k": len(sets),
+                          "passes": pit, "ms_per_batch": round(batch_ms, 3),
+                          "sequential_queries_per_s": round(1e3 / seq_per_query, 1),
+                          "batch_vs_sequential_speedup": round(seq_per_query * len(sets) / batch_ms, 2),
+                          "algorithmic_gbs": round(bpp * pit / (batch_ms * 1e-3) / 1e9, 1),
+                          "max_col_resid": float(col_res.max())}
 
         # ---- CPU oracle on a bounded sample: the same graph, a fixed number
         # of passes, and the GPU error against it at that pass count.

@@ -385,6 +385,28 @@ GrB_Info GrM_ppr_batch(void *X, GrB_Type type, int k, const int32_t *seed_ptr,
                        int *col_iters, double *col_resid);
 
 /* ------------------------------------------------------------------------
+ * Many independent graphs in one launch.  A multigraph packs copies of
+ * ngraphs transposed adjacency patterns AT[g] (square; each graph's
+ * out-degrees are the column counts of its AT) with their vertices
+ * renumbered by decreasing out-degree.  GrM_pagerank_many then solves the
+ * global PageRank of every graph (the loop of GrM_pagerank, uniform start,
+ * each graph stopping at its own residual <= tol or itermax passes) in one
+ * persistent kernel, captured in a HIP graph on first use for a given
+ * (type, damping, tol, itermax, dangling, X) and replayed afterwards.
+ * X (device, total vertices entries of `type`) receives the ranks of graph
+ * g at offsets voff[g] .. voff[g+1] in the graph's original numbering;
+ * iters / resid (host arrays of ngraphs, may be NULL) receive each graph's
+ * passes and last residual (reading them synchronises).
+ * ---------------------------------------------------------------------- */
+typedef struct GB_Multigraph_opaque *GrM_Multigraph;
+GrB_Info GrM_Multigraph_new(GrM_Multigraph *mg, int ngraphs, const GrB_Matrix *AT);
+GrB_Info GrM_Multigraph_free(GrM_Multigraph *mg);
+/* voff: host array of ngraphs + 1 vertex offsets. */
+GrB_Info GrM_Multigraph_offsets(int64_t *voff, GrM_Multigraph mg);
+GrB_Info GrM_pagerank_many(void *X, GrB_Type type, GrM_Multigraph mg, double damping, double tol,
+                           int itermax, GrM_Dangling dangling, int *iters, double *resid);
+
+/* ------------------------------------------------------------------------
  * Tile plans.  The row-parallel kernels (mxv and the fused PageRank pass)
  * walk a plan of row tiles built once per matrix and configuration on the
  * host (the analogue of the paper's compiled-kernel cache keyed by a method

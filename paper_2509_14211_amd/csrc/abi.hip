@@ -1337,6 +1337,249 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
   return GrB_SUCCESS;
 }
 
+// ------------------------------------------------------------ many graphs
+
+struct GB_Multigraph_opaque {
+  uint32_t magic;
+  int ngraphs;
+  int64_t nv, ne;
+  std::vector<int64_t> voff;
+  BufP graphs, queue, qnext, rowptr, col, deg, inv, longrows, xa, xb, wa, wb, iters, resid;
+  std::vector<std::shared_ptr<MatData>> keep;  // relabeled copies stay alive
+  struct Exec {
+    int type;
+    double damping, tol;
+    int itermax, uniform;
+    void* out;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<Exec> execs;
+  hipStream_t aux = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+static constexpr uint32_t MAGIC_MULTI = 0x4d554c54u;
+
+static void multigraph_release(GB_Multigraph_opaque* m) {
+  for (auto& e : m->execs) {
+    (void)hipGraphExecDestroy(e.exec);
+    (void)hipGraphDestroy(e.graph);
+  }
+  m->execs.clear();
+  if (m->ev0) (void)hipEventDestroy(m->ev0);
+  if (m->ev1) (void)hipEventDestroy(m->ev1);
+  if (m->aux) (void)hipStreamDestroy(m->aux);
+}
+
+GrB_Info GrM_Multigraph_new(GrM_Multigraph* mg, int ngraphs, const GrB_Matrix* AT) {
+  GB_Multigraph_opaque* m = nullptr;
+  API_BEGIN
+  require_init();
+  need(mg, "mg");
+  need(AT, "AT");
+  if (ngraphs < 1) fail(GrB_INVALID_VALUE, "ngraphs must be >= 1");
+  Ctx& c = ctx();
+  std::vector<std::shared_ptr<Relabeled>> rls;
+  std::vector<ManyGraph> gs((size_t)ngraphs);
+  int64_t nv = 0, ne = 0, nr = 0;
+  for (int g = 0; g < ngraphs; ++g) {
+    GB_Matrix_opaque* a = mat(AT[g], "AT[g]");
+    if (a->nrows != a->ncols) fail(GrB_DIMENSION_MISMATCH, "graphs must be square");
+    rls.push_back(get_relabeled(a->data));
+    const MatData& r = *rls.back()->A;
+    ManyGraph& G = gs[(size_t)g];
+    G.n = (int)r.nrows;
+    G.m = (int)r.nnz;
+    const double avg = r.nrows > 0 ? (double)r.nnz / (double)r.nrows : 0.0;
+    int lpr = 1;
+    while (lpr * 2 <= avg && lpr < 32) lpr *= 2;
+    G.lpr = lpr;
+    G.nlong = 0;
+    G.loff = 0;
+    G.voff = nv;
+    G.eoff = ne;
+    G.roff = nr;
+    nv += r.nrows;
+    ne += r.nnz;
+    nr += r.nrows + 1;
+  }
+  if (ne > (int64_t)INT32_MAX * 4) fail(GrB_INVALID_VALUE, "too many entries");
+  // rows too long for one lane group, per graph
+  std::vector<int> longrows;
+  for (int g = 0; g < ngraphs; ++g) {
+    const MatData& r = *rls[(size_t)g]->A;
+    std::vector<int> rp((size_t)r.nrows + 1);
+    hip_check(hipMemcpyAsync(rp.data(), r.rowptr->p, sizeof(int) * rp.size(), hipMemcpyDeviceToHost, c.stream),
+              "copy row pointers");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    ManyGraph& G = gs[(size_t)g];
+    G.loff = (int64_t)longrows.size();
+    for (int64_t i = 0; i < r.nrows; ++i)
+      if (rp[(size_t)i + 1] - rp[(size_t)i] > MANY_LONG_ROW) longrows.push_back((int)i);
+    G.nlong = (int)((int64_t)longrows.size() - G.loff);
+  }
+  m = new GB_Multigraph_opaque();
+  m->magic = MAGIC_MULTI;
+  m->ngraphs = ngraphs;
+  m->nv = nv;
+  m->ne = ne;
+  m->graphs = dev_alloc(sizeof(ManyGraph) * gs.size());
+  m->rowptr = dev_alloc(sizeof(int) * (size_t)nr);
+  m->col = dev_alloc(sizeof(int) * (size_t)std::max<int64_t>(ne, 1));
+  m->deg = dev_alloc(sizeof(int) * (size_t)nv);
+  m->inv = dev_alloc(sizeof(int) * (size_t)nv);
+  for (BufP* b : {&m->xa, &m->xb, &m->wa, &m->wb}) *b = dev_alloc(sizeof(double) * (size_t)nv);
+  m->iters = dev_alloc(sizeof(int) * (size_t)ngraphs);
+  m->resid = dev_alloc(sizeof(double) * (size_t)ngraphs);
+  m->qnext = dev_alloc(256);
+  hip_check(launch_fill(m->deg->p, T_INT32, nv, 0.0, c.stream), "fill");
+  launch_mark(false);
+  for (int g = 0; g < ngraphs; ++g) {
+    const ManyGraph& G = gs[(size_t)g];
+    const MatData& r = *rls[(size_t)g]->A;
+    hip_check(hipMemcpyAsync((int*)m->rowptr->p + G.roff, r.rowptr->p, sizeof(int) * (size_t)(G.n + 1),
+                             hipMemcpyDeviceToDevice, c.stream), "pack");
+    if (G.m > 0) {
+      hip_check(hipMemcpyAsync((int*)m->col->p + G.eoff, r.col->p, sizeof(int) * (size_t)G.m,
+                               hipMemcpyDeviceToDevice, c.stream), "pack");
+      hip_check(launch_column_count((const int*)r.col->p, G.m, (int*)m->deg->p + G.voff, c.stream), "degrees");
+      launch_mark(false);
+    }
+    hip_check(hipMemcpyAsync((int*)m->inv->p + G.voff, rls[(size_t)g]->inv->p, sizeof(int) * (size_t)G.n,
+                             hipMemcpyDeviceToDevice, c.stream), "pack");
+    m->voff.push_back(G.voff);
+    m->keep.push_back(rls[(size_t)g]->A);
+  }
+  m->voff.push_back(nv);
+  std::vector<int> order((size_t)ngraphs);
+  for (int g = 0; g < ngraphs; ++g) order[(size_t)g] = g;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return gs[(size_t)a].m > gs[(size_t)b].m; });
+  m->queue = dev_alloc(sizeof(int) * order.size());
+  m->longrows = dev_alloc(sizeof(int) * std::max<size_t>(longrows.size(), 1));
+  if (!longrows.empty())
+    hip_check(hipMemcpyAsync(m->longrows->p, longrows.data(), sizeof(int) * longrows.size(), hipMemcpyHostToDevice,
+                             c.stream), "upload");
+  hip_check(hipMemcpyAsync(m->graphs->p, gs.data(), sizeof(ManyGraph) * gs.size(), hipMemcpyHostToDevice, c.stream),
+            "upload");
+  hip_check(hipMemcpyAsync(m->queue->p, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, c.stream),
+            "upload");
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+  hip_check(hipStreamCreateWithFlags(&m->aux, hipStreamNonBlocking), "stream");
+  hip_check(hipEventCreateWithFlags(&m->ev0, hipEventDisableTiming), "event");
+  hip_check(hipEventCreateWithFlags(&m->ev1, hipEventDisableTiming), "event");
+  *mg = m;
+  m = nullptr;
+  }
+  catch (const GrbError& e) {
+    if (m) {
+      multigraph_release(m);
+      delete m;
+    }
+    g_err = e.msg;
+    return e.info;
+  }
+  catch (const std::exception& e) {
+    g_err = e.what();
+    return GrB_PANIC;
+  }
+  return GrB_SUCCESS;
+}
+
+GrB_Info GrM_Multigraph_free(GrM_Multigraph* mg) {
+  API_BEGIN
+  if (!mg || !*mg) return GrB_SUCCESS;
+  GB_Multigraph_opaque* m = *mg;
+  if (m->magic != MAGIC_MULTI) fail(GrB_UNINITIALIZED_OBJECT, "not a multigraph");
+  (void)hipStreamSynchronize(ctx().stream);
+  if (m->aux) (void)hipStreamSynchronize(m->aux);
+  multigraph_release(m);
+  m->magic = MAGIC_FREED;
+  delete m;
+  *mg = nullptr;
+  API_END
+}
+
+GrB_Info GrM_Multigraph_offsets(int64_t* voff, GrM_Multigraph mg) {
+  API_BEGIN
+  need(voff, "voff");
+  need(mg, "mg");
+  if (mg->magic != MAGIC_MULTI) fail(GrB_UNINITIALIZED_OBJECT, "not a multigraph");
+  for (size_t i = 0; i < mg->voff.size(); ++i) voff[i] = mg->voff[i];
+  API_END
+}
+
+GrB_Info GrM_pagerank_many(void* X, GrB_Type type, GrM_Multigraph mg, double damping, double tol, int itermax,
+                           GrM_Dangling dangling, int* iters, double* resid) {
+  API_BEGIN
+  require_init();
+  need(X, "X");
+  need(type, "type");
+  need(mg, "mg");
+  if (mg->magic != MAGIC_MULTI) fail(GrB_UNINITIALIZED_OBJECT, "not a multigraph");
+  const int T = type->code;
+  float_type(T, "type");
+  if (dangling != GrM_DANGLING_DROP && dangling != GrM_DANGLING_UNIFORM) fail(GrB_INVALID_VALUE, "dangling mode");
+  if (itermax < 0 || !(damping >= 0.0 && damping < 1.0) || std::isnan(tol))
+    fail(GrB_INVALID_VALUE, "pagerank parameters");
+  Ctx& c = ctx();
+  const int uniform = dangling == GrM_DANGLING_UNIFORM ? 1 : 0;
+  GB_Multigraph_opaque::Exec* ex = nullptr;
+  for (auto& e : mg->execs)
+    if (e.type == T && e.damping == damping && e.tol == tol && e.itermax == itermax && e.uniform == uniform &&
+        e.out == X)
+      ex = &e;
+  if (!ex) {
+    ManyArgs a{};
+    a.graphs = (const ManyGraph*)mg->graphs->p;
+    a.queue = (const int*)mg->queue->p;
+    a.queue_next = (int*)mg->qnext->p;
+    a.ngraphs = mg->ngraphs;
+    a.rowptr = (const int*)mg->rowptr->p;
+    a.col = (const int*)mg->col->p;
+    a.deg = (const int*)mg->deg->p;
+    a.inv = (const int*)mg->inv->p;
+    a.longrows = (const int*)mg->longrows->p;
+    a.xa = mg->xa->p;
+    a.xb = mg->xb->p;
+    a.wa = mg->wa->p;
+    a.wb = mg->wb->p;
+    a.out = X;
+    a.iters = (int*)mg->iters->p;
+    a.resid = (double*)mg->resid->p;
+    a.damping = damping;
+    a.tol = tol;
+    a.itermax = itermax;
+    a.uniform = uniform;
+    GB_Multigraph_opaque::Exec e{T, damping, tol, itermax, uniform, X, nullptr, nullptr};
+    hip_check(hipStreamBeginCapture(mg->aux, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t le = launch_pr_many(a, T, c.cus, mg->aux);
+    hipGraph_t gph = nullptr;
+    hipError_t ce = hipStreamEndCapture(mg->aux, &gph);
+    hip_check(le, "many-graph launch");
+    hip_check(ce, "end capture");
+    e.graph = gph;
+    hip_check(hipGraphInstantiate(&e.exec, gph, nullptr, nullptr, 0), "instantiate");
+    mg->execs.push_back(e);
+    ex = &mg->execs.back();
+  }
+  // order the replay after the library stream's work, and later work after it
+  hip_check(hipEventRecord(mg->ev0, c.stream), "record");
+  hip_check(hipStreamWaitEvent(mg->aux, mg->ev0, 0), "wait");
+  hip_check(hipGraphLaunch(ex->exec, mg->aux), "graph launch");
+  hip_check(hipEventRecord(mg->ev1, mg->aux), "record");
+  hip_check(hipStreamWaitEvent(c.stream, mg->ev1, 0), "wait");
+  launch_mark(true);
+  if (iters)
+    hip_check(hipMemcpyAsync(iters, mg->iters->p, sizeof(int) * (size_t)mg->ngraphs, hipMemcpyDeviceToHost, c.stream),
+              "copy");
+  if (resid)
+    hip_check(hipMemcpyAsync(resid, mg->resid->p, sizeof(double) * (size_t)mg->ngraphs, hipMemcpyDeviceToHost,
+                             c.stream),
+              "copy");
+  if (iters || resid) hip_check(hipStreamSynchronize(c.stream), "sync");
+  API_END
+}
+
 // ------------------------------------------------------------ plans
 
 static bool plan_geometry_ok(const GrM_PlanConfig& c) {

@@ -234,6 +234,12 @@ __global__ void permute_keys_kernel(const int* __restrict__ rowptr, int64_t n, c
 
 }  // namespace
 
+hipError_t launch_column_count(const int* col, int64_t nnz, int* cnt, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  hipLaunchKernelGGL(column_count_kernel, dim3(gb_grid(nnz)), dim3(GB_BLOCK), 0, s, col, nnz, cnt);
+  return hipGetLastError();
+}
+
 hipError_t degree_order(int64_t n, const int* col, int64_t nnz, int* order, int* inv, AllocFn alloc,
                         ReleaseFn release, void* actx, hipStream_t s) {
   Scoped cbuf(alloc, release, actx, (size_t)n * sizeof(int));

@@ -240,6 +240,40 @@ hipError_t launch_spmm_init(const SpmmArgs& a, int type, const int* by_col_ptr, 
 hipError_t launch_rows_permute(const void* in, int type, const int* idx, void* out, int64_t n, int k,
                                hipStream_t s);
 
+// ------------------------------------------------------------ many graphs
+// One problem of the persistent many-graph launch (many.hip): n vertices,
+// row pointers at rowptr + roff (n + 1 local offsets), columns at
+// col + eoff, vertex arrays at + voff; lpr lanes reduce one row.
+struct ManyGraph {
+  int n, m, lpr, nlong;   // nlong rows longer than MANY_LONG_ROW entries
+  int64_t voff, eoff, roff, loff;
+};
+// Rows with more entries are summed by the whole workgroup, not by one
+// lane group, so no lane accumulates more than this many terms serially.
+constexpr int MANY_LONG_ROW = 256;
+struct ManyArgs {
+  const ManyGraph* graphs;
+  const int* queue;   // graph indices, largest first
+  int* queue_next;    // reset to 0 by the launch
+  int ngraphs;
+  const int* rowptr;
+  const int* col;
+  const int* deg;     // out-degree per vertex (execution numbering)
+  const int* inv;     // per graph: position of original vertex v
+  const int* longrows;  // per graph at loff: its long rows, ascending
+  void* xa;
+  void* xb;
+  void* wa;
+  void* wb;
+  void* out;          // ranks in the original numbering
+  int* iters;
+  double* resid;
+  double damping, tol;
+  int itermax, uniform;
+};
+// Queue reset + the persistent kernel (grid workgroups of 1024 threads).
+hipError_t launch_pr_many(const ManyArgs& a, int type, int grid, hipStream_t s);
+
 // ------------------------------------------------------------ graph build
 // (graph_build.hip) Sort-based construction of a CSR pattern from an edge
 // list.  Temporary device memory comes from `alloc` / `release`.
@@ -259,6 +293,8 @@ hipError_t transpose_csr(int64_t nrows, int64_t ncols, const int* rowptr, const 
                          int64_t nnz, int* rowptrT, int* colT, AllocFn alloc,
                          ReleaseFn release, void* actx, hipStream_t s);
 
+// cnt[col[e]] += 1 for every entry (cnt zeroed by the caller).
+hipError_t launch_column_count(const int* col, int64_t nnz, int* cnt, hipStream_t s);
 // Vertex order by decreasing column count of an n x n pattern (ties by
 // increasing id): order[k] = vertex at position k, inv[v] = position of v.
 hipError_t degree_order(int64_t n, const int* col, int64_t nnz, int* order, int* inv, AllocFn alloc,

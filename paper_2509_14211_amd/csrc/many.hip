@@ -1,0 +1,207 @@
+// Many independent PageRank problems in one persistent launch.
+//
+// Every workgroup (1024 threads, one per compute unit) takes whole graphs
+// from a queue ordered by decreasing size and runs the fused pass on each
+// until its own residual reaches the tolerance: no workgroup ever waits for
+// another, and each exits when the queue is empty.  Inside a graph the
+// vertices are numbered by decreasing out-degree, so the leading slice of
+// the gathered vector -- all of it for graphs up to the LDS capacity -- is
+// kept in LDS and refreshed after every pass.  Rows are reduced by groups of
+// lanes (a power of two per graph from its mean degree) with shuffles; the
+// residual and the dangling mass are summed in FP64 in a fixed order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace nbgrb {
+
+namespace {
+
+constexpr int MB = 1024;
+constexpr int MNW = MB / 64;
+
+template <typename T>
+struct ManyLds;
+template <>
+struct ManyLds<float> {
+  static constexpr int H = 36864;  // 144 KiB
+};
+template <>
+struct ManyLds<double> {
+  static constexpr int H = 18432;  // 144 KiB
+};
+
+template <typename V>
+__device__ __forceinline__ V wsum(V v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fixed-tree sum over the workgroup, returned to every thread.
+__device__ __forceinline__ double bsum(double v, double* red, double* out) {
+  v = wsum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < MNW; ++i) s += red[i];
+    *out = s;
+  }
+  __syncthreads();
+  const double r = *out;
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
+  constexpr int HM = ManyLds<T>::H;
+  __shared__ T hot[HM];
+  __shared__ double red[MNW];
+  __shared__ T redT[MNW];
+  __shared__ double bcast;
+  __shared__ int sq;
+  const int tid = threadIdx.x;
+
+  for (;;) {
+    if (tid == 0) sq = __hip_atomic_fetch_add(p.queue_next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int q = sq;
+    __syncthreads();
+    if (q >= p.ngraphs) break;
+    const ManyGraph G = p.graphs[p.queue[q]];
+    const int n = G.n;
+    const int* rp = p.rowptr + G.roff;
+    const int* col = p.col + G.eoff;
+    const int* deg = p.deg + G.voff;
+    T* xa = (T*)p.xa + G.voff;
+    T* xb = (T*)p.xb + G.voff;
+    T* wa = (T*)p.wa + G.voff;
+    T* wb = (T*)p.wb + G.voff;
+    const int H = n < HM ? n : HM;
+    const int lpr = G.lpr;
+    const int groups = MB / lpr;
+    const int grp = tid / lpr, sub = tid & (lpr - 1);
+    const T dmp = (T)p.damping;
+
+    // start: x = 1/n, w = x .* d, D = mass on dangling vertices
+    double dl = 0.0;
+    const T x0 = (T)(1.0 / (double)n);
+    for (int i = tid; i < n; i += MB) {
+      const int dg = deg[i];
+      const T dv = dg > 0 ? dmp * ((T)1 / (T)dg) : (T)0;
+      xa[i] = x0;
+      const T wv = x0 * dv;
+      wa[i] = wv;
+      if (i < H) hot[i] = wv;
+      if (dg == 0) dl += (double)x0;
+    }
+    double D = bsum(dl, red, &bcast);
+    double rho = 1.0;
+    int it = 0;
+    T* xc = xa;
+    T* xn = xb;
+    T* wc = wa;
+    T* wn = wb;
+    while (it < p.itermax && rho > p.tol) {
+      const double cd = (1.0 - p.damping) / (double)n + (p.uniform ? p.damping * D / (double)n : 0.0);
+      const T c = (T)cd;
+      double rl = 0.0, dn = 0.0;
+      for (int base = 0; base < n; base += groups) {
+        const int row = base + grp;
+        T s = 0;
+        bool mine = row < n;
+        if (mine) {
+          const int e0 = rp[row], e1 = rp[row + 1];
+          mine = e1 - e0 <= MANY_LONG_ROW;  // long rows: second phase
+          if (mine)
+            for (int e = e0 + sub; e < e1; e += lpr) {
+              const int j = col[e];
+              s += j < H ? hot[j] : wc[j];
+            }
+        }
+        for (int o = lpr >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (sub == 0 && mine) {
+          const T r = c + s;
+          const T xo = xc[row];
+          const int dg = deg[row];
+          const T dv = dg > 0 ? dmp * ((T)1 / (T)dg) : (T)0;
+          xn[row] = r;
+          wn[row] = r * dv;
+          rl += fabs((double)xo - (double)r);
+          if (dg == 0) dn += (double)r;
+        }
+      }
+      // long rows: every thread takes a strided share, fixed tree after
+      for (int q = 0; q < G.nlong; ++q) {
+        const int row = p.longrows[G.loff + q];
+        const int e1 = rp[row + 1];
+        T s = 0;
+        for (int e = rp[row] + tid; e < e1; e += MB) {
+          const int j = col[e];
+          s += j < H ? hot[j] : wc[j];
+        }
+        s = wsum(s);
+        if ((tid & 63) == 0) redT[tid >> 6] = s;
+        __syncthreads();
+        if (tid == 0) {
+          T t = 0;
+          for (int w = 0; w < MNW; ++w) t += redT[w];
+          const T r = c + t;
+          const T xo = xc[row];
+          const int dg = deg[row];
+          const T dv = dg > 0 ? dmp * ((T)1 / (T)dg) : (T)0;
+          xn[row] = r;
+          wn[row] = r * dv;
+          rl += fabs((double)xo - (double)r);
+          if (dg == 0) dn += (double)r;
+        }
+        __syncthreads();
+      }
+      __syncthreads();  // every row of the pass is written
+      rho = bsum(rl, red, &bcast);
+      D = bsum(dn, red, &bcast);
+      ++it;
+      // the next pass gathers the new pre-scaled vector
+      for (int i = tid; i < H; i += MB) hot[i] = wn[i];
+      __syncthreads();
+      T* t = xc;
+      xc = xn;
+      xn = t;
+      t = wc;
+      wc = wn;
+      wn = t;
+    }
+    // ranks back in the graph's original numbering
+    T* out = (T*)p.out + G.voff;
+    const int* inv = p.inv + G.voff;
+    for (int v = tid; v < n; v += MB) out[v] = xc[inv[v]];
+    if (tid == 0) {
+      p.iters[p.queue[q]] = it;
+      p.resid[p.queue[q]] = rho;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void queue_reset_kernel(int* q) { *q = 0; }
+
+}  // namespace
+
+hipError_t launch_pr_many(const ManyArgs& a, int type, int grid, hipStream_t s) {
+  if (grid <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, s, a.queue_next);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (type == T_FP32)
+    hipLaunchKernelGGL(pr_many_kernel<float>, dim3(grid), dim3(MB), 0, s, a);
+  else
+    hipLaunchKernelGGL(pr_many_kernel<double>, dim3(grid), dim3(MB), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace nbgrb

@@ -124,6 +124,10 @@ _FUNCS = {
                 vp, i32],
     "GrM_ppr_batch": [vp, vp, i32, vp, vp, vp, vp, dbl, dbl, i32, i32, i32, ctypes.POINTER(i32),
                       vp, vp],
+    "GrM_Multigraph_new": [PV, i32, vp],
+    "GrM_Multigraph_free": [PV],
+    "GrM_Multigraph_offsets": [vp, vp],
+    "GrM_pagerank_many": [vp, vp, vp, dbl, dbl, i32, i32, vp, vp],
     "GrM_Matrix_plan_set": [vp, vp, ctypes.c_void_p],
     "GrM_Matrix_plan_get": [ctypes.c_void_p, vp, vp],
     "GrM_autotune_pagerank": [ctypes.c_void_p, ctypes.POINTER(dbl), vp, vp, vp, ctypes.c_char_p],
@@ -505,6 +509,36 @@ def GrM_ppr_batch(X, type_, seed_sets, AT, outdeg, damping, tol, itermax,
           damping, tol, itermax, dangling, check_every, ctypes.byref(it), col_it.ctypes.data,
           col_res.ctypes.data)
     return it.value, col_it[:k].copy(), col_res[:k].copy()
+
+
+def GrM_Multigraph_new(ATs) -> int:
+    arr = (ctypes.c_void_p * len(ATs))(*ATs)
+    h = vp()
+    _call("GrM_Multigraph_new", ctypes.byref(h), len(ATs), ctypes.cast(arr, vp))
+    return h.value
+
+
+def GrM_Multigraph_free(mg):
+    h = vp(mg)
+    _call("GrM_Multigraph_free", ctypes.byref(h))
+
+
+def GrM_Multigraph_offsets(mg, ngraphs: int):
+    import numpy as np
+    off = np.zeros(ngraphs + 1, dtype=np.int64)
+    _call("GrM_Multigraph_offsets", off.ctypes.data, mg)
+    return off
+
+
+def GrM_pagerank_many(X, type_, mg, ngraphs: int, damping, tol, itermax,
+                      dangling=GrM_DANGLING_UNIFORM):
+    """Returns (per-graph passes, per-graph last residual) as numpy arrays."""
+    import numpy as np
+    it = np.zeros(ngraphs, dtype=np.int32)
+    res = np.zeros(ngraphs, dtype=np.float64)
+    _call("GrM_pagerank_many", _addr(X), type_, mg, damping, tol, itermax, dangling,
+          it.ctypes.data, res.ctypes.data)
+    return it, res
 
 
 def GrM_stream_copy(dst, src, nbytes: int):
