@@ -100,6 +100,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--ppr-k", type=int, default=64, help="seed sets of the batched PPR leg")
+    ap.add_argument("--many", type=int, default=256, help="graphs of the many-graph leg")
     ap.add_argument("--skip-extras", action="store_true",
                     help="time only the headline fused solve (for profiling)")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
@@ -286,6 +287,61 @@ def main():
                           "batch_vs_sequential_speedup": round(seq_per_query * len(sets) / batch_ms, 2),
                           "algorithmic_gbs": round(bpp * pit / (batch_ms * 1e-3) / 1e9, 1),
                           "max_col_resid": float(col_res.max())}
+
+        # ---- many small graphs: one persistent, graph-captured launch vs the
+        # same graphs solved one after another
+        if not args.skip_extras and args.many > 0:
+            import synthetic
+            specs = synthetic.many_graph_specs(args.many)
+            t0 = time.perf_counter()
+            mgs = [api.rmat_graph(sc, 16, sd) for sc, sd in specs]
+            mg = grb.GrM_Multigraph_new([x.AT for x in mgs])
+            torch.cuda.synchronize()
+            pack_s = time.perf_counter() - t0
+            off = grb.GrM_Multigraph_offsets(mg, len(mgs))
+            f32 = grb.builtin("GrB_FP32")
+            Xm = torch.empty(int(off[-1]), dtype=torch.float32, device="cuda")
+            grb.GrM_pagerank_many(Xm, f32, mg, len(mgs), DAMPING, args.tol, 1000)  # capture
+            reps = 5
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                grb.GrM_pagerank_many(Xm, f32, mg, len(mgs), DAMPING, args.tol, 1000)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            many_ms = e0.elapsed_time(e1) / reps
+            its, res = grb.GrM_pagerank_many(Xm, f32, mg, len(mgs), DAMPING, args.tol, 1000)
+            edges = sum(x.m for x in mgs)
+            for x in mgs:  # sequential baseline: warm every plan first
+                api.pagerank(x, torch.float32, DAMPING, args.tol, 1000)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            seq_it = 0
+            for x in mgs:
+                _, it_, _ = api.pagerank(x, torch.float32, DAMPING, args.tol, 1000)
+                seq_it += it_
+            e1.record(stream)
+            torch.cuda.synchronize()
+            seq_ms = e0.elapsed_time(e1)
+            log("many graphs: %d graphs, %d vertices, %d edges; one launch %.3f ms (%.0f graphs/s, "
+                "%.1f GTEPS); sequential %.2f ms; pack %.1fs" % (
+                    len(mgs), int(off[-1]), edges, many_ms, len(mgs) / many_ms * 1e3,
+                    float((its.astype(np.int64) * np.array([x.m for x in mgs])).sum()) / (many_ms * 1e-3) / 1e9,
+                    seq_ms, pack_s))
+            out["many_graphs"] = {"graphs": len(mgs), "vertices": int(off[-1]), "edges": int(edges),
+                                  "ms_per_launch": round(many_ms, 4),
+                                  "graphs_per_s": round(len(mgs) / many_ms * 1e3, 1),
+                                  "gteps": round(float((its.astype(np.int64) * np.array(
+                                      [x.m for x in mgs])).sum()) / (many_ms * 1e-3) / 1e9, 2),
+                                  "sequential_ms": round(seq_ms, 3),
+                                  "speedup_vs_sequential": round(seq_ms / many_ms, 2),
+                                  "max_resid": float(res.max()), "max_iters": int(its.max())}
+            grb.GrM_Multigraph_free(mg)
+            for x in mgs:
+                x.free()
+            del Xm
 
         # ---- CPU oracle on a bounded sample: the same graph, a fixed number
         # of passes, and the GPU error against it at that pass count.

@@ -1252,6 +1252,7 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
   a.rowptr = (const int*)A_exec->rowptr->p;
   a.col = A_exec->col ? (const int*)A_exec->col->p : nullptr;
   a.k = k;
+  a.w_bytes = vbytes < 0xFFFFFF00ull ? (unsigned)vbytes : 0u;
   a.dvec = dinv.node->buf->p;
   a.seed_v = (const int*)d_sv->p;
   a.seed_c = (const int*)d_sc->p;
@@ -1266,6 +1267,10 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
   a.hub_red = (double*)hub_red->p;
   a.wg_part = (double*)wg_part->p;
   a.ticket = (unsigned*)ticket->p;
+  BufP tile_seed = dev_alloc(sizeof(int) * (size_t)std::max(plan->dev.ntiles, 1));
+  hip_check(launch_spmm_tile_seed(plan->dev, a.seed_v, ns, (int*)tile_seed->p, c.stream), "tile seeds");
+  launch_mark(false);
+  a.tile_seed = (const int*)tile_seed->p;
   // initial vectors
   a.x_new = Xb[0]->p;
   a.w_new = Wb[0]->p;

@@ -210,6 +210,8 @@ struct SpmmArgs {
   const int* col;
   int k;
   const void* w;
+  unsigned w_bytes;       // size of w in bytes when below 4 GiB (buffer-addressed pass), else 0
+  const int* tile_seed;   // per tile: first vertex-sorted seed at or after the tile's first row
   const void* x_old;
   const void* dvec;
   void* x_new;
@@ -233,6 +235,7 @@ struct SpmmArgs {
 constexpr int SPMM_BLOCK = 1024;
 hipError_t launch_spmm_ppr(const TilePlanDev& plan, const SpmmArgs& a, int type, int grid,
                            const GuardDev* guard, hipStream_t s);
+hipError_t launch_spmm_tile_seed(const TilePlanDev& plan, const int* seed_v, int nseeds, int* out, hipStream_t s);
 // x_new = V, w_new = V .* d (both must be zero beforehand), d_out = D0, hit = -1.
 hipError_t launch_spmm_init(const SpmmArgs& a, int type, const int* by_col_ptr, const int* by_col_v,
                             const double* by_col_w, hipStream_t s);

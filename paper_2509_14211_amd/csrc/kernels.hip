@@ -54,6 +54,13 @@ __device__ __forceinline__ int counter_add(int* p) {
   return __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Values that are the same in every lane of the wavefront, moved to scalar
+// registers so that branches on them are uniform.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int4 wave_uniform(int4 v) {
+  return make_int4(wave_uniform(v.x), wave_uniform(v.y), wave_uniform(v.z), wave_uniform(v.w));
+}
+
 template <typename V>
 __device__ __forceinline__ V wave_sum(V v) {
 #pragma unroll
@@ -438,7 +445,7 @@ constexpr int WAVE_WR = 256;
 template <typename T, int KE, int KP, int KR>
 __device__ __forceinline__ void wave_prefetch(const TilePlanDev& plan, const FusedArgs<T>& a, int t,
                                               bool pr, int lane, TileRegs<T, KE, KP, KR>& R) {
-  R.td = plan.tiles[t];
+  R.td = wave_uniform(plan.tiles[t]);
   const int4 d = R.td;
 #pragma unroll
   for (int k = 0; k < KE; ++k) {
@@ -489,7 +496,7 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
   __shared__ int sflag;
 
   const int tid = threadIdx.x;
-  const int wv = tid >> 6, lane = tid & 63;
+  const int wv = wave_uniform(tid >> 6), lane = tid & 63;
   const bool pr = a.mode == EPI_PR;
   T c = (T)0;
   if (pr) c = (T)scalar_value(a.c);
@@ -564,7 +571,7 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
       for (int k = 0; k < KE; ++k) part += val[k];
       part = wave_sum(part);
       const int h = -cur.y - 1;
-      const int4 hub = plan.hubs[h];  // {row, nchunks, slot0, -}
+      const int4 hub = wave_uniform(plan.hubs[h]);  // {row, nchunks, slot0, -}
       int last = 0;
       if (lane == 0) {
         publish(&scr.hub_sum[hub.z + cur.x], (double)part);

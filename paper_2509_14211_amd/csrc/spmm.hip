@@ -33,54 +33,21 @@ __device__ __forceinline__ V get(const V* p) {
 }
 __device__ __forceinline__ void drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// Row sum of row entries [e0, e1) for this lane's column.
+// Epilogue of row i with its inputs already loaded (xo = x_old row entry,
+// dv = d_i).  Seeds are consumed in vertex order: sp is the next unread
+// seed, nsv its vertex.
 template <typename T>
-__device__ __forceinline__ T row_gather(const int* __restrict__ col, const T* __restrict__ W, int k,
-                                        int lane, bool on, int e0, int e1) {
-  T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-  int e = e0;
-  for (; e + 7 < e1; e += 8) {
-    int j[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) j[u] = col[e + u];
-    T v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = on ? W[(int64_t)j[u] * k + lane] : (T)0;
-    a0 += v[0] + v[4];
-    a1 += v[1] + v[5];
-    a2 += v[2] + v[6];
-    a3 += v[3] + v[7];
-  }
-  for (; e < e1; ++e) {
-    const int j = col[e];
-    a0 += on ? W[(int64_t)j * k + lane] : (T)0;
-  }
-  return (a0 + a1) + (a2 + a3);
-}
-
-// First index in the vertex-sorted seed list with vertex >= v.
-__device__ __forceinline__ int seed_lower_bound(const SpmmArgs& p, int v) {
-  int lo = 0, hi = p.nseeds;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (p.seed_v[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-template <typename T>
-__device__ __forceinline__ void spmm_epilogue(const SpmmArgs& p, int i, T s, int lane, bool on, T cfac,
-                                              int& sp, double& rho, double& dm) {
+__device__ __forceinline__ void spmm_finish(const SpmmArgs& p, int i, T s, int lane, bool on, T cfac, T xo,
+                                            T dv, int& sp, int& nsv, double& rho, double& dm) {
   T tele = 0;
-  while (sp < p.nseeds && p.seed_v[sp] == i) {
+  while (nsv == i) {
     if (p.seed_c[sp] == lane) tele += (T)p.seed_w[sp] * cfac;
     ++sp;
+    nsv = sp < p.nseeds ? p.seed_v[sp] : 0x7fffffff;
   }
   if (!on) return;
   const int64_t at = (int64_t)i * p.k + lane;
   const T r = s + tele;
-  const T xo = __builtin_nontemporal_load((const T*)p.x_old + at);
-  const T dv = ((const T*)p.dvec)[i];
   __builtin_nontemporal_store(r, (T*)p.x_new + at);
   ((T*)p.w_new)[at] = r * dv;
   rho += fabs((double)xo - (double)r);
@@ -88,56 +55,50 @@ __device__ __forceinline__ void spmm_epilogue(const SpmmArgs& p, int i, T s, int
 }
 
 template <typename T>
-__global__ __launch_bounds__(SB) void spmm_ppr_kernel(TilePlanDev plan, SpmmArgs p, const GuardDev* guard) {
-  if (guard && guard->active == 0) return;
-  __shared__ double sr[SNW][64];
-  __shared__ double sd[SNW][64];
-  __shared__ int sflag;
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const bool on = lane < p.k;
-  const T* W = (const T*)p.w;
-  // teleport factor of this lane's column: (1-d) + d D_c, or (1-d)
-  T cfac = (T)0;
-  if (on) cfac = (T)(p.c_beta + (p.d_prev ? p.c_alpha * p.d_prev[lane] : 0.0));
-  double rho = 0.0, dm = 0.0;
+__device__ __forceinline__ T load_xo(const SpmmArgs& p, int i, int lane, bool on) {
+  return on ? __builtin_nontemporal_load((const T*)p.x_old + (int64_t)i * p.k + lane) : (T)0;
+}
 
-  const int nwaves = (int)gridDim.x * SNW;
-  for (int t = (int)blockIdx.x * SNW + wv; t < plan.ntiles; t += nwaves) {
-    const int4 td = plan.tiles[t];
-    if (td.y > 0) {
-      const int row0 = td.x, nr = td.y;
-      int sp = seed_lower_bound(p, row0);
-      int e = p.rowptr[row0];
-      for (int r = 0; r < nr; ++r) {
-        const int e1 = p.rowptr[row0 + r + 1];
-        const T s = row_gather<T>(p.col, W, p.k, lane, on, e, e1);
-        spmm_epilogue<T>(p, row0 + r, s, lane, on, cfac, sp, rho, dm);
-        e = e1;
-      }
-    } else {
-      const int h = -td.y - 1;
-      const int4 hub = plan.hubs[h];  // {row, nchunks, slot0, -}
-      const T part = row_gather<T>(p.col, W, p.k, lane, on, td.z, td.z + td.w);
-      if (on) put(&p.hub_sum[(int64_t)(hub.z + td.x) * 64 + lane], (double)part);
-      drain();
-      int last = 0;
-      if (lane == 0) last = __hip_atomic_fetch_add(&p.hub_cnt[h], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                            hub.y - 1;
-      last = __shfl(last, 0, 64);
-      if (last) {
-        T s = 0;
-        for (int q = 0; q < hub.y; ++q) s += on ? (T)get(&p.hub_sum[(int64_t)(hub.z + q) * 64 + lane]) : (T)0;
-        int sp = seed_lower_bound(p, hub.x);
-        double hr = 0.0, hd = 0.0;
-        spmm_epilogue<T>(p, hub.x, s, lane, on, cfac, sp, hr, hd);
-        put(&p.hub_red[(int64_t)h * 128 + lane], hr);
-        put(&p.hub_red[(int64_t)h * 128 + 64 + lane], hd);
-        if (lane == 0) put(&p.hub_cnt[h], 0);
-      }
-    }
+// Hub row h: once every chunk has published its k-wide partial sum, the
+// wavefront that finished last adds them in chunk order and runs the
+// epilogue; the row's residual and dangling terms go to hub_red[h].
+template <typename T>
+__device__ void spmm_hub_finish(const SpmmArgs& p, int4 hub, int h, int chunk, int sp0, T acc, int lane, bool on,
+                                T cfac) {
+  if (on) put(&p.hub_sum[(int64_t)(hub.z + chunk) * 64 + lane], (double)acc);
+  drain();
+  int last = 0;
+  if (lane == 0)
+    last = __hip_atomic_fetch_add(&p.hub_cnt[h], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == hub.y - 1;
+  last = __shfl(last, 0, 64);
+  if (!last) return;
+  T s = 0;
+  int q = 0;
+  for (; q + 8 <= hub.y; q += 8) {  // eight loads in flight
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = on ? get(&p.hub_sum[(int64_t)(hub.z + q + u) * 64 + lane]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += (T)v[u];
   }
+  for (; q < hub.y; ++q) s += on ? (T)get(&p.hub_sum[(int64_t)(hub.z + q) * 64 + lane]) : (T)0;
+  int sp = sp0;
+  int nsv = sp < p.nseeds ? p.seed_v[sp] : 0x7fffffff;
+  double hr = 0.0, hd = 0.0;
+  spmm_finish<T>(p, hub.x, s, lane, on, cfac, load_xo<T>(p, hub.x, lane, on), ((const T*)p.dvec)[hub.x], sp, nsv,
+                 hr, hd);
+  put(&p.hub_red[(int64_t)h * 128 + lane], hr);
+  put(&p.hub_red[(int64_t)h * 128 + 64 + lane], hd);
+  if (lane == 0) put(&p.hub_cnt[h], 0);
+}
 
-  // per-column partials: wavefronts in order, then workgroups in order
+// Per-column residual and dangling mass of the pass: wavefronts in order,
+// then workgroups in order, then hub rows; the last workgroup to arrive
+// writes rho_out / d_out and advances the loop guard on the largest column
+// residual.
+__device__ void spmm_reduce(const TilePlanDev& plan, const SpmmArgs& p, double rho, double dm,
+                            double (*sr)[64], double (*sd)[64], int* sflag) {
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   sr[wv][lane] = rho;
   sd[wv][lane] = dm;
   __syncthreads();
@@ -152,22 +113,38 @@ __global__ __launch_bounds__(SB) void spmm_ppr_kernel(TilePlanDev plan, SpmmArgs
   }
   drain();
   __syncthreads();
-  if (tid == 0) sflag = __hip_atomic_fetch_add(p.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                        gridDim.x - 1;
+  if (tid == 0)
+    *sflag = __hip_atomic_fetch_add(p.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
   __syncthreads();
-  if (!sflag) return;
-  if (tid < 64) {
+  if (!*sflag) return;
+  {
+    // thread (slice, column): slice sl of the workgroup partials and of the
+    // hub rows, then the slices of a column in slice order
+    const int cc = tid & 63, sl = tid >> 6;
     double a = 0.0, b = 0.0;
-    for (int g = 0; g < (int)gridDim.x; ++g) {
-      a += get(&p.wg_part[(int64_t)g * 128 + tid]);
-      b += get(&p.wg_part[(int64_t)g * 128 + 64 + tid]);
+    for (int g = sl; g < (int)gridDim.x; g += SNW) {
+      a += get(&p.wg_part[(int64_t)g * 128 + cc]);
+      b += get(&p.wg_part[(int64_t)g * 128 + 64 + cc]);
     }
-    for (int h = 0; h < plan.nhubs; ++h) {
-      a += get(&p.hub_red[(int64_t)h * 128 + tid]);
-      b += get(&p.hub_red[(int64_t)h * 128 + 64 + tid]);
+    for (int h = sl; h < plan.nhubs; h += SNW) {
+      a += get(&p.hub_red[(int64_t)h * 128 + cc]);
+      b += get(&p.hub_red[(int64_t)h * 128 + 64 + cc]);
     }
-    sr[0][tid] = tid < p.k ? a : 0.0;
-    sd[0][tid] = b;
+    sr[sl][cc] = a;
+    sd[sl][cc] = b;
+  }
+  __syncthreads();
+  double fa = 0.0, fb = 0.0;
+  if (tid < 64) {
+    for (int w = 0; w < SNW; ++w) {
+      fa += sr[w][tid];
+      fb += sd[w][tid];
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    sr[0][tid] = tid < p.k ? fa : 0.0;
+    sd[0][tid] = fb;
   }
   __syncthreads();
   if (tid == 0) {
@@ -188,6 +165,287 @@ __global__ __launch_bounds__(SB) void spmm_ppr_kernel(TilePlanDev plan, SpmmArgs
     }
     put(p.ticket, 0u);
   }
+}
+
+// k-wide rows of the n x k operands, addressed through buffer resources:
+// the row's byte offset is a wave-uniform scalar, the lane's column a
+// per-lane offset (lanes past k use column 0 and never store).
+struct RowBufs {
+  __amdgpu_buffer_rsrc_t w, xo, xn, wn;
+  int voff;
+  unsigned row_bytes;
+};
+constexpr int CP_NT = 2;  // nontemporal cache policy of buffer loads / stores
+
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+template <typename T, int AUX>
+__device__ __forceinline__ T row_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
+}
+template <typename T, int AUX>
+__device__ __forceinline__ void row_store(__amdgpu_buffer_rsrc_t r, T v, int voff, int soff) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, AUX);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
+}
+// A value every lane reads from the same address, kept in scalar registers.
+__device__ __forceinline__ float uniform_load(const float* a) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, *a)));
+}
+__device__ __forceinline__ double uniform_load(const double* a) {
+  const int2 v = __builtin_bit_cast(int2, *a);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y)));
+}
+__device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int4 sgpr(int4 v) { return make_int4(sgpr(v.x), sgpr(v.y), sgpr(v.z), sgpr(v.w)); }
+__device__ __forceinline__ double sgpr(double v) {
+  const int2 h = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(sgpr(h.x), sgpr(h.y)));
+}
+__device__ __forceinline__ int row_off(const RowBufs& b, int i) { return (int)((unsigned)i * b.row_bytes); }
+
+// spmm_finish with buffer-addressed rows.
+template <typename T>
+__device__ __forceinline__ void spmm_finish_b(const SpmmArgs& p, const RowBufs& b, int i, T s, int lane, bool on,
+                                              T cfac, T xo, T dv, int& sp, int& nsv, double& rho, double& dm) {
+  T tele = 0;
+  while (nsv == i) {
+    if (sgpr(p.seed_c[sp]) == lane) tele += (T)sgpr(p.seed_w[sp]) * cfac;
+    ++sp;
+    nsv = sp < p.nseeds ? sgpr(p.seed_v[sp]) : 0x7fffffff;
+  }
+  if (!on) return;
+  const T r = s + tele;
+  const int so = row_off(b, i);
+  row_store<T, CP_NT>(b.xn, r, b.voff, so);
+  row_store<T, 0>(b.wn, r * dv, b.voff, so);
+  rho += fabs((double)xo - (double)r);
+  if (dv == (T)0) dm += (double)r;
+}
+
+template <typename T>
+struct GatherDepth {
+  static constexpr int U = 32;
+};
+template <>
+struct GatherDepth<double> {
+  static constexpr int U = 8;
+};
+
+// The pass for operands below 4 GiB.  Each wavefront takes one tile at a
+// time; the tile's column indices are read 64 at a time into one register
+// (lane q holds entry q of the chunk) and broadcast with readlane, so every
+// gathered row costs one scalar offset and one vector load, with U rows in
+// flight.  The tile's row pointers sit in wave-private LDS.
+template <typename T>
+__global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void spmm_ppr_kernel(
+    TilePlanDev plan, SpmmArgs p, const GuardDev* guard) {
+  constexpr int TR = WAVE_TILE_ROWS, U = GatherDepth<T>::U;
+  static_assert(64 % U == 0, "gather depth divides the chunk");
+  if (guard && guard->active == 0) return;
+  __shared__ double sr[SNW][64];
+  __shared__ double sd[SNW][64];
+  __shared__ int srp[SNW][TR + 1];
+  __shared__ int sflag;
+  const int tid = threadIdx.x, wv = sgpr(tid >> 6), lane = tid & 63;
+  const bool on = lane < p.k;
+  RowBufs b;
+  b.row_bytes = (unsigned)p.k * (unsigned)sizeof(T);
+  b.voff = on ? lane * (int)sizeof(T) : 0;
+  b.w = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.w), (short)0, (int)p.w_bytes, 0x00020000);
+  b.xo = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.x_old), (short)0, (int)p.w_bytes, 0x00020000);
+  b.xn = __builtin_amdgcn_make_buffer_rsrc(p.x_new, (short)0, (int)p.w_bytes, 0x00020000);
+  b.wn = __builtin_amdgcn_make_buffer_rsrc(p.w_new, (short)0, (int)p.w_bytes, 0x00020000);
+  T cfac = (T)0;
+  if (on) cfac = (T)(p.c_beta + (p.d_prev ? p.c_alpha * p.d_prev[lane] : 0.0));
+  double rho = 0.0, dm = 0.0;
+  int* wrp = srp[wv];
+
+  const int nwaves = (int)gridDim.x * SNW;
+  for (int t = (int)blockIdx.x * SNW + wv; t < plan.ntiles; t += nwaves) {
+    const int4 td = sgpr(plan.tiles[t]);
+    const int e0 = td.z, ne = td.w;
+    int colv = lane < ne ? p.col[e0 + lane] : 0;
+    if (td.y > 0) {
+      const int row0 = td.x, nr = td.y;
+      for (int q = lane; q <= nr; q += 64) wrp[q] = p.rowptr[row0 + q] - e0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      int sp = sgpr(p.tile_seed[t]);
+      int nsv = sp < p.nseeds ? sgpr(p.seed_v[sp]) : 0x7fffffff;
+      int r = 0;
+      int rend = sgpr(wrp[1]);
+      T acc = 0;
+      T xo = row_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0));
+      T dv = uniform_load((const T*)p.dvec + row0);
+      for (int c0 = 0; c0 < ne; c0 += 64) {
+        const int cn = c0 + 64 + lane;
+        const int coln = cn < ne ? p.col[e0 + cn] : 0;
+#pragma unroll
+        for (int h = 0; h < 64; h += U) {
+          const int base = c0 + h;
+          if (base >= ne) break;
+          T v[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) v[u] = row_load<T, 0>(b.w, b.voff, row_off(b, __builtin_amdgcn_readlane(colv, h + u)));
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = base + u;
+            if (e < ne) {
+              while (e == rend) {
+                spmm_finish_b<T>(p, b, row0 + r, acc, lane, on, cfac, xo, dv, sp, nsv, rho, dm);
+                acc = 0;
+                ++r;
+                rend = sgpr(wrp[r + 1]);
+                xo = row_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
+                dv = uniform_load((const T*)p.dvec + row0 + r);
+              }
+              acc += v[u];
+            }
+          }
+        }
+        colv = coln;
+      }
+      while (r < nr) {  // last row with entries, then empty rows
+        spmm_finish_b<T>(p, b, row0 + r, acc, lane, on, cfac, xo, dv, sp, nsv, rho, dm);
+        acc = 0;
+        ++r;
+        if (r < nr) {
+          xo = row_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
+          dv = uniform_load((const T*)p.dvec + row0 + r);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();  // the next tile rewrites wrp
+    } else {
+      const int h = -td.y - 1;
+      T acc = 0;
+      for (int c0 = 0; c0 < ne; c0 += 64) {
+        const int cn = c0 + 64 + lane;
+        const int coln = cn < ne ? p.col[e0 + cn] : 0;
+#pragma unroll
+        for (int hh = 0; hh < 64; hh += U) {
+          const int base = c0 + hh;
+          if (base >= ne) break;
+          T v[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) v[u] = row_load<T, 0>(b.w, b.voff, row_off(b, __builtin_amdgcn_readlane(colv, hh + u)));
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (base + u < ne) acc += v[u];
+        }
+        colv = coln;
+      }
+      spmm_hub_finish<T>(p, sgpr(plan.hubs[h]), h, td.x, sgpr(p.tile_seed[t]), acc, lane, on, cfac);
+    }
+  }
+  spmm_reduce(plan, p, rho, dm, sr, sd, &sflag);
+}
+
+// The same pass with 64-bit addressing, for operands of 4 GiB or more: the
+// tile's column indices are staged in wave-private LDS.
+template <typename T>
+__global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArgs p, const GuardDev* guard) {
+  constexpr int TE = WAVE_TILE_ENTRIES, TR = WAVE_TILE_ROWS, U = 16;
+  if (guard && guard->active == 0) return;
+  __shared__ double sr[SNW][64];
+  __shared__ double sd[SNW][64];
+  __shared__ __align__(16) int scol[SNW][TE + 16];  // padded: 16-entry reads past ne stay inside
+  __shared__ int srp[SNW][TR + 1];
+  __shared__ int sflag;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const bool on = lane < p.k;
+  const T* W = (const T*)p.w;
+  T cfac = (T)0;
+  if (on) cfac = (T)(p.c_beta + (p.d_prev ? p.c_alpha * p.d_prev[lane] : 0.0));
+  double rho = 0.0, dm = 0.0;
+  int* wcol = scol[wv];
+  int* wrp = srp[wv];
+
+  const int nwaves = (int)gridDim.x * SNW;
+  for (int t = (int)blockIdx.x * SNW + wv; t < plan.ntiles; t += nwaves) {
+    const int4 td = plan.tiles[t];
+    const int e0 = td.z, ne = td.w;
+    for (int q = lane; q < ne; q += 64) wcol[q] = p.col[e0 + q];
+    if (td.y > 0)
+      for (int q = lane; q <= td.y; q += 64) wrp[q] = p.rowptr[td.x + q] - e0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    T acc = 0;
+    int r = 0, sp = p.tile_seed[t];
+    int nsv = sp < p.nseeds ? p.seed_v[sp] : 0x7fffffff;
+    const int row0 = td.x, nr = td.y;
+    int rend = td.y > 0 ? wrp[1] : 0x7fffffff;
+    T xo = td.y > 0 ? load_xo<T>(p, row0, lane, on) : (T)0;
+    T dv = td.y > 0 ? ((const T*)p.dvec)[row0] : (T)0;
+    for (int base = 0; base < ne; base += U) {
+      int cj[U];
+#pragma unroll
+      for (int u = 0; u < U; u += 4) {
+        const int4 c4 = *reinterpret_cast<const int4*>(wcol + base + u);
+        cj[u] = c4.x;
+        cj[u + 1] = c4.y;
+        cj[u + 2] = c4.z;
+        cj[u + 3] = c4.w;
+      }
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = (on && base + u < ne) ? W[(int64_t)cj[u] * p.k + lane] : (T)0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = base + u;
+        if (e < ne) {
+          while (e == rend) {
+            spmm_finish<T>(p, row0 + r, acc, lane, on, cfac, xo, dv, sp, nsv, rho, dm);
+            acc = 0;
+            ++r;
+            rend = wrp[r + 1];
+            xo = load_xo<T>(p, row0 + r, lane, on);
+            dv = ((const T*)p.dvec)[row0 + r];
+          }
+          acc += v[u];
+        }
+      }
+    }
+    if (td.y > 0) {
+      while (r < nr) {
+        spmm_finish<T>(p, row0 + r, acc, lane, on, cfac, xo, dv, sp, nsv, rho, dm);
+        acc = 0;
+        ++r;
+        if (r < nr) {
+          xo = load_xo<T>(p, row0 + r, lane, on);
+          dv = ((const T*)p.dvec)[row0 + r];
+        }
+      }
+    } else {
+      const int h = -td.y - 1;
+      spmm_hub_finish<T>(p, plan.hubs[h], h, td.x, sp, acc, lane, on, cfac);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // the next tile rewrites wcol / wrp
+  }
+  spmm_reduce(plan, p, rho, dm, sr, sd, &sflag);
+}
+
+// First seed (in vertex order) at or after the first row of each tile.
+__global__ void spmm_tile_seed_kernel(TilePlanDev plan, const int* __restrict__ seed_v, int nseeds,
+                                      int* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= plan.ntiles) return;
+  const int4 td = plan.tiles[t];
+  const int v = td.y > 0 ? td.x : plan.hubs[-td.y - 1].x;
+  int lo = 0, hi = nseeds;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (seed_v[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  out[t] = lo;
 }
 
 // x0 / w0 / D0 of the batch: x0 = V (seed weights), w0 = V .* d,
@@ -228,11 +486,26 @@ __global__ void rows_permute_kernel(const void* __restrict__ in, int type, const
 
 hipError_t launch_spmm_ppr(const TilePlanDev& plan, const SpmmArgs& a, int type, int grid,
                            const GuardDev* guard, hipStream_t s) {
-  if (grid <= 0 || a.k < 1 || a.k > 64) return hipErrorInvalidValue;
-  if (type == T_FP32)
-    hipLaunchKernelGGL(spmm_ppr_kernel<float>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
-  else
-    hipLaunchKernelGGL(spmm_ppr_kernel<double>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
+  if (grid <= 0 || a.k < 1 || a.k > 64 || !a.tile_seed) return hipErrorInvalidValue;
+  const bool wide = a.w_bytes == 0;  // operand of 4 GiB or more
+  if (type == T_FP32) {
+    if (wide)
+      hipLaunchKernelGGL(spmm_wide_kernel<float>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
+    else
+      hipLaunchKernelGGL(spmm_ppr_kernel<float>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
+  } else {
+    if (wide)
+      hipLaunchKernelGGL(spmm_wide_kernel<double>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
+    else
+      hipLaunchKernelGGL(spmm_ppr_kernel<double>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_tile_seed(const TilePlanDev& plan, const int* seed_v, int nseeds, int* out, hipStream_t s) {
+  if (plan.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(spmm_tile_seed_kernel, dim3((plan.ntiles + 255) / 256), dim3(256), 0, s, plan, seed_v, nseeds,
+                     out);
   return hipGetLastError();
 }
 
