@@ -45,47 +45,112 @@ def blocking_bytes_per_pass(n: int, m: int, b: int) -> int:
     return 4 * (n + 1) + 4 * m + 13 * n * b
 
 
-def summarize_rocprof(d: str) -> None:
+COPY_BYTES = 1 << 30  # bytes read and written by one launch of the copy probe
+PROFILE_MD = os.path.join(ROOT, "profiles", "fused_wave_kernel_rmat22.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_14211_amd", "csrc", f) for f in ("kernels.hip", "kernels.h")]
+
+
+def kernel_source_sha() -> str:
+    """sha256 over the sources that define the fused kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM-side bytes per launch of the fused FP32 kernel as recorded in the
+    committed profile summary, or None when the summary is missing or the
+    kernel sources changed since the counters were taken."""
+    try:
+        text = open(PROFILE_MD).read()
+    except OSError:
+        return None
+    kv = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_sha():
+        return None
+    try:
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def summarize_rocprof(dirs) -> None:
     """Kernel statistics (from --kernel-trace --stats) and per-dispatch PMC
-    counters (from --pmc runs) found under d, as Markdown tables."""
+    counters (from --pmc runs) found under the given directories, as
+    Markdown tables; with FETCH_SIZE and WRITE_SIZE runs that include the
+    copy probe, also the calibrated traffic per launch of the fused kernels."""
     import collections
     import csv
     import glob
-    stats = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
-    for p in stats:
-        print("### kernel statistics (%s)\n" % os.path.relpath(p, d))
-        print("| kernel | calls | average (us) | min (us) | max (us) | share |")
-        print("|---|---|---|---|---|---|")
-        for r in list(csv.DictReader(open(p)))[:15]:
-            print("| %s | %s | %.2f | %.2f | %.2f | %.2f%% |" % (
-                r["Name"][:90], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
-                float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
-        print()
-    traces = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
-    for p in traces:
-        dur = collections.defaultdict(list)
-        for r in csv.DictReader(open(p)):
-            dur[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-        print("### launches of the fused kernels (%s)\n" % os.path.relpath(p, d))
-        print("| kernel | launches | mean (us) | launches > 20 us | their mean (us) |")
-        print("|---|---|---|---|---|")
-        for k, v in dur.items():
-            if "fused" in k:
-                act = [x for x in v if x > 20.0]
-                print("| %s | %d | %.2f | %d | %.2f |" % (k[:90], len(v), sum(v) / len(v), len(act),
-                                                        sum(act) / max(len(act), 1)))
-        print()
-    pmcs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-    for p in pmcs:
-        vals = collections.defaultdict(list)
-        for r in csv.DictReader(open(p)):
-            vals[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
-        print("### counters per dispatch (%s)\n" % os.path.relpath(p, d))
-        print("| kernel | counter | dispatches | mean | max |")
-        print("|---|---|---|---|---|")
-        for (k, c), v in sorted(vals.items()):
-            if "fused" in k or "stream_copy" in k:
-                print("| %s | %s | %d | %.1f | %.1f |" % (k[:90], c, len(v), sum(v) / len(v), max(v)))
+    counters = collections.defaultdict(list)
+    for d in dirs:
+        stats = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+        for p in stats:
+            print("### kernel statistics (%s)\n" % os.path.basename(p))
+            print("| kernel | calls | average (us) | min (us) | max (us) | share |")
+            print("|---|---|---|---|---|---|")
+            for r in list(csv.DictReader(open(p)))[:15]:
+                print("| %s | %s | %.2f | %.2f | %.2f | %.2f%% |" % (
+                    r["Name"][:90], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+                    float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+            print()
+        traces = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+        for p in traces:
+            dur = collections.defaultdict(list)
+            for r in csv.DictReader(open(p)):
+                dur[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            print("### launches of the fused kernels (%s)\n" % os.path.basename(p))
+            print("| kernel | launches | mean (us) | launches > 20 us | their mean (us) |")
+            print("|---|---|---|---|---|")
+            for k, v in dur.items():
+                if "fused" in k:
+                    act = [x for x in v if x > 20.0]
+                    print("| %s | %d | %.2f | %d | %.2f |" % (k[:90], len(v), sum(v) / len(v), len(act),
+                                                            sum(act) / max(len(act), 1)))
+            print()
+        pmcs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        for p in pmcs:
+            vals = collections.defaultdict(list)
+            for r in csv.DictReader(open(p)):
+                vals[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+            print("### counters per dispatch (%s)\n" % os.path.basename(p))
+            print("| kernel | counter | dispatches | mean | max |")
+            print("|---|---|---|---|---|")
+            for (k, c), v in sorted(vals.items()):
+                if "fused" in k or "stream_copy" in k:
+                    print("| %s | %s | %d | %.1f | %.1f |" % (k[:90], c, len(v), sum(v) / len(v), max(v)))
+                    counters[(k, c)] = v
+            print()
+    copy = [k for (k, c) in counters if "stream_copy" in k]
+    fused = sorted({k for (k, c) in counters if "fused_wave_kernel<float>" in k})
+    if copy and fused:
+        ck = copy[0]
+        f_copy = sum(counters[(ck, "FETCH_SIZE")]) / len(counters[(ck, "FETCH_SIZE")])
+        w_copy = sum(counters[(ck, "WRITE_SIZE")]) / len(counters[(ck, "WRITE_SIZE")])
+        f_scale = COPY_BYTES / (f_copy * 1024.0)
+        w_scale = COPY_BYTES / (w_copy * 1024.0)
+        k = fused[0]
+        f_k = sum(counters[(k, "FETCH_SIZE")]) / len(counters[(k, "FETCH_SIZE")])
+        w_k = sum(counters[(k, "WRITE_SIZE")]) / len(counters[(k, "WRITE_SIZE")])
+        traffic = f_k * 1024.0 * f_scale + w_k * 1024.0 * w_scale
+        print("### calibrated traffic of the fused FP32 kernel\n")
+        print("The copy probe reads and writes %d bytes per launch; its counters give the scale of each "
+              "counter (bytes per KiB reported).\n" % COPY_BYTES)
+        print("- copy_fetch_kib: %.1f" % f_copy)
+        print("- copy_write_kib: %.1f" % w_copy)
+        print("- fetch_scale: %.4f" % (f_scale * 1.0))
+        print("- write_scale: %.4f" % (w_scale * 1.0))
+        print("- kernel_fetch_kib_per_launch: %.1f" % f_k)
+        print("- kernel_write_kib_per_launch: %.1f" % w_k)
+        print("- traffic_bytes_per_launch: %d" % int(round(traffic)))
+        print("- source_sha256: %s" % kernel_source_sha())
         print()
 
 
@@ -103,8 +168,8 @@ def main():
     ap.add_argument("--many", type=int, default=256, help="graphs of the many-graph leg")
     ap.add_argument("--skip-extras", action="store_true",
                     help="time only the headline fused solve (for profiling)")
-    ap.add_argument("--summarize-rocprof", metavar="DIR",
-                    help="print a text summary of the rocprofv3 CSV files under DIR and exit")
+    ap.add_argument("--summarize-rocprof", metavar="DIR", nargs="+",
+                    help="print a text summary of the rocprofv3 CSV files under the DIRs and exit")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(args.summarize_rocprof)
@@ -196,7 +261,7 @@ def main():
         log("fused pass: %.2f us, %.1f GB/s algorithmic" % (avg_us, achieved))
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                           "traffic": None,
+                           "traffic": recorded_traffic(),
                            "kernel": "fused_wave_kernel<float>" if tuned["GrB_FP32"]["kernel"] == 1
                            else "fused_pr_kernel<float, ...>",
                            "bytes_per_launch": bpp, "avg_launch_us": round(avg_us, 3)}

@@ -100,6 +100,7 @@ struct FusedArgs {
   const int* col;
   const T* w;  // gathered vector
   int nrows;
+  int ncols;   // length of w
   int mode;
   T* s_out;
   T* r_out;

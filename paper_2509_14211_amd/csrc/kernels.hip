@@ -61,6 +61,34 @@ __device__ __forceinline__ int4 wave_uniform(int4 v) {
   return make_int4(wave_uniform(v.x), wave_uniform(v.y), wave_uniform(v.z), wave_uniform(v.w));
 }
 
+// Tile descriptor t (t wave-uniform) through the scalar cache: the plan is
+// read-only during a pass, and a scalar load does not wait behind the
+// wavefront's outstanding vector loads.
+__device__ __forceinline__ int4 tile_desc(const int4* tiles, int t) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef const __attribute__((address_space(4))) int4* const_int4_ptr;
+  return ((const_int4_ptr)tiles)[wave_uniform(t)];
+#else
+  return tiles[t];
+#endif
+}
+
+// Buffer resources: loads at byte offsets at or past `bytes` return zero
+// without touching memory, which keeps per-lane bounds out of the control
+// flow.
+constexpr unsigned BUF_SKIP = 0xFFFFFFF0u;  // offset of a lane that must not load
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename V, int AUX>
+__device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(V) == 4)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX));
+}
+constexpr int CP_NT = 2;  // nontemporal
+
 template <typename V>
 __device__ __forceinline__ V wave_sum(V v) {
 #pragma unroll
@@ -445,26 +473,24 @@ constexpr int WAVE_WR = 256;
 template <typename T, int KE, int KP, int KR>
 __device__ __forceinline__ void wave_prefetch(const TilePlanDev& plan, const FusedArgs<T>& a, int t,
                                               bool pr, int lane, TileRegs<T, KE, KP, KR>& R) {
-  R.td = wave_uniform(plan.tiles[t]);
+  R.td = tile_desc(plan.tiles, t);
   const int4 d = R.td;
+  const __amdgpu_buffer_rsrc_t rc = buf_rsrc(a.col + d.z, (unsigned)d.w * 4u);
 #pragma unroll
-  for (int k = 0; k < KE; ++k) {
-    const int e = lane + 64 * k;
-    R.ci[k] = e < d.w ? __builtin_nontemporal_load(a.col + d.z + e) : 0;
-  }
+  for (int k = 0; k < KE; ++k) R.ci[k] = buf_load<int, CP_NT>(rc, (unsigned)(lane + 64 * k) * 4u);
   if (d.y > 0) {
+    const __amdgpu_buffer_rsrc_t rr = buf_rsrc(a.rowptr + d.x, (unsigned)(d.y + 1) * 4u);
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const int r = lane + 64 * k;
-      R.rp[k] = r <= d.y ? a.rowptr[d.x + r] : 0;
-    }
+    for (int k = 0; k < KP; ++k) R.rp[k] = buf_load<int, 0>(rr, (unsigned)(lane + 64 * k) * 4u);
     if (pr) {
+      const unsigned rows = (unsigned)d.y * (unsigned)sizeof(T);
+      const __amdgpu_buffer_rsrc_t rx = buf_rsrc(a.x_old ? a.x_old + d.x : nullptr, a.x_old ? rows : 0u);
+      const __amdgpu_buffer_rsrc_t rd = buf_rsrc(a.dvec ? a.dvec + d.x : nullptr, a.dvec ? rows : 0u);
 #pragma unroll
       for (int k = 0; k < KR; ++k) {
-        const int r = lane + 64 * k;
-        const bool ok = r < d.y;
-        R.xo[k] = (ok && a.x_old) ? __builtin_nontemporal_load(a.x_old + d.x + r) : (T)0;
-        R.dv[k] = (ok && a.dvec) ? __builtin_nontemporal_load(a.dvec + d.x + r) : (T)0;
+        const unsigned off = (unsigned)(lane + 64 * k) * (unsigned)sizeof(T);
+        R.xo[k] = buf_load<T, CP_NT>(rx, off);
+        R.dv[k] = buf_load<T, CP_NT>(rd, off);
       }
     }
   }
@@ -477,6 +503,97 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Entries of the tile whose column indices R holds: hot-slice hits from LDS,
+// the rest gathered from memory.
+// Entries past the tile's end hold column 0 (the index loads return zero
+// there) and their values are never used.
+template <typename T, int KE>
+__device__ __forceinline__ void wave_gather(__amdgpu_buffer_rsrc_t rw, const T* hot, int H,
+                                            const int (&ci)[KE], T (&val)[KE]) {
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int c = ci[k];
+    const bool h = c < H;
+    const T g = buf_load<T, 0>(rw, h ? BUF_SKIP : (unsigned)c * (unsigned)sizeof(T));
+    const T hv = hot[h ? c : 0];
+    val[k] = h ? hv : g;
+  }
+}
+
+// Row sums and epilogues of one tile whose entries are in val.
+template <typename T, int KE, int KP, int KR>
+__device__ __forceinline__ void wave_process(const TilePlanDev& plan, const FusedArgs<T>& a,
+                                             const FusedScratch& scr, int lane, T c, const int4 cur,
+                                             const T (&val)[KE], const int (&crp)[KP], const T (&cxo)[KR],
+                                             const T (&cdv)[KR], T* wval, int* wrp, T* wres, double& rho,
+                                             double& dm) {
+  if (cur.y > 0) {
+    const int row0 = cur.x, nr = cur.y, e0 = cur.z, ne = cur.w;
+#pragma unroll
+    for (int k = 0; k < KE; ++k)
+      if (lane + 64 * k < ne) wval[lane + 64 * k] = val[k];
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+      if (lane + 64 * k <= nr) wrp[lane + 64 * k] = crp[k] - e0;
+    wave_lds_fence();
+    const int q = 64 / nr;
+    const int lpr = q >= 64 ? 64 : q >= 32 ? 32 : q >= 16 ? 16 : q >= 8 ? 8 : q >= 4 ? 4 : q >= 2 ? 2 : 1;
+    const int slots = 64 / lpr;
+    const int grp = lane / lpr, sub = lane & (lpr - 1);
+    const int rounds = (nr + slots - 1) / slots;
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int rr = rd * slots + grp;
+      T v = 0;
+      if (rr < nr) {
+        const int hi = wrp[rr + 1];
+        for (int k = wrp[rr] + sub; k < hi; k += lpr) v += wval[k];
+      }
+      for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (sub == 0 && rr < nr) wres[rr] = v;
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int r = lane + 64 * k;
+      if (r < nr) pr_epilogue_pre(a, row0 + r, wres[r], c, cxo[k], cdv[k], rho, dm);
+    }
+    wave_lds_fence();  // wres / wval / wrp are rewritten by the next tile
+  } else {
+    // one chunk of hub row h
+    T part = 0;
+#pragma unroll
+    for (int k = 0; k < KE; ++k)
+      if (lane + 64 * k < cur.w) part += val[k];
+    part = wave_sum(part);
+    const int h = -cur.y - 1;
+    const int4 hub = tile_desc(plan.hubs, h);  // {row, nchunks, slot0, -}
+    int last = 0;
+    if (lane == 0) {
+      publish(&scr.hub_sum[hub.z + cur.x], (double)part);
+      wait_stores();
+      last = counter_add(&scr.hub_cnt[h]) == hub.y - 1;
+    }
+    last = __shfl(last, 0, 64);
+    if (last) {
+      T s = 0;
+      for (int k = lane; k < hub.y; k += 64) s += (T)consume(&scr.hub_sum[hub.z + k]);
+      s = wave_sum(s);
+      if (lane == 0) {
+        double hr = 0.0, hd = 0.0;
+        pr_epilogue(a, hub.x, s, c, hr, hd);
+        publish(&scr.hub_red[2 * h], hr);
+        publish(&scr.hub_red[2 * h + 1], hd);
+        publish(&scr.hub_cnt[h], 0);
+      }
+    }
+  }
+}
+
+// Tiles of one wavefront are software-pipelined: while tile i is reduced,
+// the gathers of tile i+1 and the column indices (and row pointers and
+// epilogue inputs) of tile i+2 are in flight.  Loads are issued in the
+// order [indices of i+2][gathers of i+1], so waiting for either never waits
+// for the other.  FP64 keeps one tile in flight (register budget).
 template <typename T>
 __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan, FusedArgs<T> a,
                                                                 FusedScratch scr, int hot_n,
@@ -486,6 +603,7 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
   constexpr int WE = WAVE_WE, WR = WAVE_WR;
   constexpr int KE = WE / 64, KP = (WR + 1 + 63) / 64, KR = WR / 64;
   constexpr int HMAX = WaveLds<T>::HMAX;
+  constexpr bool PIPE = sizeof(T) == 4;
   if (guard && guard->active == 0) return;
 
   __shared__ T hot[HMAX];
@@ -505,92 +623,61 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
   const int H = hot_n < HMAX ? hot_n : HMAX;
   for (int k = tid; k < H; k += B) hot[k] = a.w[k];
   __syncthreads();
+  const __amdgpu_buffer_rsrc_t rw = buf_rsrc(a.w, (unsigned)a.ncols * (unsigned)sizeof(T));
 
   const int nwaves = (int)gridDim.x * NW;
-  TileRegs<T, KE, KP, KR> R;
+  T* wval = sval[wv];
+  int* wrp = srp[wv];
+  T* wres = sres[wv];
   int t = (int)blockIdx.x * NW + wv;
-  if (t < plan.ntiles) wave_prefetch<T>(plan, a, t, pr, lane, R);
-  for (; t < plan.ntiles; t += nwaves) {
-    const int4 cur = R.td;
-    T val[KE];
-#pragma unroll
-    for (int k = 0; k < KE; ++k) {
-      const int ci = R.ci[k];
-      val[k] = (lane + 64 * k < cur.w) ? (ci < H ? hot[ci] : a.w[ci]) : (T)0;
-    }
-    int crp[KP];
-    T cxo[KR], cdv[KR];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) crp[k] = R.rp[k];
-#pragma unroll
-    for (int k = 0; k < KR; ++k) {
-      cxo[k] = R.xo[k];
-      cdv[k] = R.dv[k];
-    }
-    const int tn = t + nwaves;
-    if (tn < plan.ntiles) wave_prefetch<T>(plan, a, tn, pr, lane, R);
-
-    if (cur.y > 0) {
-      const int row0 = cur.x, nr = cur.y, e0 = cur.z, ne = cur.w;
-      T* wval = sval[wv];
-      int* wrp = srp[wv];
-      T* wres = sres[wv];
-#pragma unroll
-      for (int k = 0; k < KE; ++k)
-        if (lane + 64 * k < ne) wval[lane + 64 * k] = val[k];
-#pragma unroll
-      for (int k = 0; k < KP; ++k)
-        if (lane + 64 * k <= nr) wrp[lane + 64 * k] = crp[k] - e0;
-      wave_lds_fence();
-      const int q = 64 / nr;
-      const int lpr = q >= 64 ? 64 : q >= 32 ? 32 : q >= 16 ? 16 : q >= 8 ? 8 : q >= 4 ? 4 : q >= 2 ? 2 : 1;
-      const int slots = 64 / lpr;
-      const int grp = lane / lpr, sub = lane & (lpr - 1);
-      const int rounds = (nr + slots - 1) / slots;
-      for (int rd = 0; rd < rounds; ++rd) {
-        const int rr = rd * slots + grp;
-        T v = 0;
-        if (rr < nr) {
-          const int hi = wrp[rr + 1];
-          for (int k = wrp[rr] + sub; k < hi; k += lpr) v += wval[k];
-        }
-        for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (sub == 0 && rr < nr) wres[rr] = v;
+  if (PIPE) {
+    if (t < plan.ntiles) {
+      // three register sets rotate through the roles (reduce, gather,
+      // prefetch), unrolled by three so no set is ever copied: a copy of a
+      // register with a load in flight would wait for every older load.
+      TileRegs<T, KE, KP, KR> X, Y, Z;
+      T vX[KE], vY[KE], vZ[KE];
+      const int last = plan.ntiles - 1;
+      wave_prefetch<T>(plan, a, t, pr, lane, X);
+      wave_prefetch<T>(plan, a, min(t + nwaves, last), pr, lane, Y);
+      wave_gather<T, KE>(rw, hot, H, X.ci, vX);
+      auto step = [&](int tt, TileRegs<T, KE, KP, KR>& P, T (&vP)[KE], TileRegs<T, KE, KP, KR>& G, T (&vG)[KE],
+                      TileRegs<T, KE, KP, KR>& F) {
+        wave_prefetch<T>(plan, a, min(tt + 2 * nwaves, last), pr, lane, F);
+        wave_gather<T, KE>(rw, hot, H, G.ci, vG);
+        wave_process<T>(plan, a, scr, lane, c, P.td, vP, P.rp, P.xo, P.dv, wval, wrp, wres, rho, dm);
+      };
+      for (;;) {
+        step(t, X, vX, Y, vY, Z);
+        t += nwaves;
+        if (t >= plan.ntiles) break;
+        step(t, Y, vY, Z, vZ, X);
+        t += nwaves;
+        if (t >= plan.ntiles) break;
+        step(t, Z, vZ, X, vX, Y);
+        t += nwaves;
+        if (t >= plan.ntiles) break;
       }
-      wave_lds_fence();
+    }
+  } else {
+    TileRegs<T, KE, KP, KR> R;
+    if (t < plan.ntiles) wave_prefetch<T>(plan, a, t, pr, lane, R);
+    for (; t < plan.ntiles; t += nwaves) {
+      T val[KE];
+      wave_gather<T, KE>(rw, hot, H, R.ci, val);
+      const int4 cur = R.td;
+      int crp[KP];
+      T cxo[KR], cdv[KR];
+#pragma unroll
+      for (int k = 0; k < KP; ++k) crp[k] = R.rp[k];
 #pragma unroll
       for (int k = 0; k < KR; ++k) {
-        const int r = lane + 64 * k;
-        if (r < nr) pr_epilogue_pre(a, row0 + r, wres[r], c, cxo[k], cdv[k], rho, dm);
+        cxo[k] = R.xo[k];
+        cdv[k] = R.dv[k];
       }
-      wave_lds_fence();  // wres / wval / wrp are rewritten by the next tile
-    } else {
-      // one chunk of hub row h
-      T part = 0;
-#pragma unroll
-      for (int k = 0; k < KE; ++k) part += val[k];
-      part = wave_sum(part);
-      const int h = -cur.y - 1;
-      const int4 hub = wave_uniform(plan.hubs[h]);  // {row, nchunks, slot0, -}
-      int last = 0;
-      if (lane == 0) {
-        publish(&scr.hub_sum[hub.z + cur.x], (double)part);
-        wait_stores();
-        last = counter_add(&scr.hub_cnt[h]) == hub.y - 1;
-      }
-      last = __shfl(last, 0, 64);
-      if (last) {
-        T s = 0;
-        for (int k = lane; k < hub.y; k += 64) s += (T)consume(&scr.hub_sum[hub.z + k]);
-        s = wave_sum(s);
-        if (lane == 0) {
-          double hr = 0.0, hd = 0.0;
-          pr_epilogue(a, hub.x, s, c, hr, hd);
-          publish(&scr.hub_red[2 * h], hr);
-          publish(&scr.hub_red[2 * h + 1], hd);
-          publish(&scr.hub_cnt[h], 0);
-        }
-      }
+      const int tn = t + nwaves;
+      if (tn < plan.ntiles) wave_prefetch<T>(plan, a, tn, pr, lane, R);
+      wave_process<T>(plan, a, scr, lane, c, cur, val, crp, cxo, cdv, wval, wrp, wres, rho, dm);
     }
   }
 

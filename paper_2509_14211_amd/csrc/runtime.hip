@@ -424,6 +424,7 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     a.col = A->col ? (const int*)A->col->p : nullptr;
     a.w = (const float*)f.w;
     a.nrows = (int)A->nrows;
+    a.ncols = (int)A->ncols;
     a.mode = f.mode;
     a.s_out = (float*)f.s_out;
     a.r_out = (float*)f.r_out;
@@ -449,6 +450,7 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     a.col = A->col ? (const int*)A->col->p : nullptr;
     a.w = (const double*)f.w;
     a.nrows = (int)A->nrows;
+    a.ncols = (int)A->ncols;
     a.mode = f.mode;
     a.s_out = (double*)f.s_out;
     a.r_out = (double*)f.r_out;
