@@ -163,7 +163,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target length of the CPU oracle sample (whole passes)")
     ap.add_argument("--ppr-k", type=int, default=64, help="seed sets of the batched PPR leg")
     ap.add_argument("--many", type=int, default=256, help="graphs of the many-graph leg")
     ap.add_argument("--skip-extras", action="store_true",
@@ -417,8 +418,10 @@ def main():
             t0 = time.perf_counter()
             og = oracle.rmat_graph(args.scale)
             build_s = time.perf_counter() - t0
-            k = args.cpu_iters
-            oracle.pagerank(og, DAMPING, fixed_iters=1)  # warm-up
+            t0 = time.perf_counter()
+            oracle.pagerank(og, DAMPING, fixed_iters=2)  # warm-up, and the pass time estimate
+            per_pass = (time.perf_counter() - t0) / 2
+            k = max(8, int(args.cpu_seconds / max(per_pass, 1e-6)))
             t0 = time.perf_counter()
             ref = oracle.pagerank(og, DAMPING, fixed_iters=k)
             cpu_s = time.perf_counter() - t0
