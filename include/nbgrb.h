@@ -102,6 +102,9 @@ typedef struct GB_Scalar_opaque *GrB_Scalar;
  *   x / d with d = max(outdeg,1)/damping   GrB_DIV_* (eWiseMult)
  * ---------------------------------------------------------------------- */
 extern GrB_Type GrB_BOOL, GrB_INT32, GrB_FP32, GrB_FP64;
+/* bfloat16 (upper half of binary32, rounded to nearest even): storage type
+ * of network activations only (GrM_GNN_new); not a vector type. */
+extern GrB_Type GrM_BF16;
 
 extern GrB_UnaryOp GrB_IDENTITY_FP32, GrB_IDENTITY_FP64;
 extern GrB_UnaryOp GrB_ABS_FP32, GrB_ABS_FP64;
@@ -457,6 +460,71 @@ GrB_Info GrM_Matrix_plan_get(GrM_PlanConfig *cfg, GrB_Matrix A, GrB_Type type);
  * differ in speed, never beyond rounding in results. */
 GrB_Info GrM_autotune_pagerank(GrM_PlanConfig *chosen, double *us_per_pass, GrB_Matrix AT,
                                GrB_Vector outdeg, GrB_Type type, const char *cache_path);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start for personalised PageRank.  A network predicts the
+ * start vector x0 of GrM_ppr for one seed set S on a graph given as A
+ * (rows = sources) and A^T (both square n x n, the same pattern), from 11
+ * features per vertex v:
+ *   x[0] = 1 if v in S, x[1] = log(1 + indeg v), x[2] = log(1 + outdeg v),
+ *   x[2+t] = log(1 + n c_t(v) / W), t = 1..8,
+ * where c_t(v) counts the W random walkers at v after step t: walker w
+ * starts at S[w mod |S|]; at step t, with u from draw 4(8w + t - 1) of the
+ * SplitMix64 stream of `seed` (top 53 bits, scaled to [0,1)), it restarts at
+ * S[r mod |S|] (r = the next draw) when u < 1 - damping or its vertex has no
+ * out-edge, else follows out-edge r mod outdeg (r = the draw after that).
+ * The walkers' distribution after t steps is the t-th personalised
+ * PageRank iterate from the teleport start.  Network (parameter vector
+ * theta of GRM_GNN_NPARAMS FP32 values in this order: W1s[64][11],
+ * W1n[64][11], b1[64], w2s[64], w2n[64], b2):
+ *   m_v = mean of x over in-neighbours (0 without any)
+ *   h_v = ReLU(W1s x_v + W1n m_v + b1)
+ *   z_v = w2s . h_v + b2 + mean over in-neighbours u of w2n . h_u
+ *   x0  = softmax(z), or the teleport vector (1/|S| on S) when z has a
+ *         non-finite value or the normaliser is not finite and positive.
+ * Training minimises KL(x* || x0) for target ranks x*.  Activations (x, m,
+ * h) are stored in the network's activation type (GrB_FP32 or GrM_BF16),
+ * weights in FP32, sums accumulated in FP32, weight gradients and the
+ * softmax normaliser in FP64.  The calls enqueue on the library stream; a
+ * network keeps work space for the graph it was last used with.
+ * ---------------------------------------------------------------------- */
+#define GRM_GNN_FEATURES 11
+#define GRM_GNN_HIDDEN 64
+#define GRM_GNN_NPARAMS 1601
+typedef struct GB_GNN_opaque *GrM_GNN;
+/* New network: Glorot-uniform weights from the SplitMix64 stream of
+ * init_seed (draw i for parameter i), zero biases, Adam state cleared. */
+GrB_Info GrM_GNN_new(GrM_GNN *net, GrB_Type act, uint64_t init_seed);
+GrB_Info GrM_GNN_free(GrM_GNN *net);
+/* theta: host array of GRM_GNN_NPARAMS floats (set also clears Adam). */
+GrB_Info GrM_GNN_set_params(GrM_GNN net, const float *theta);
+GrB_Info GrM_GNN_get_params(GrM_GNN net, float *theta);
+/* grad: host array of GRM_GNN_NPARAMS doubles, the accumulated gradient. */
+GrB_Info GrM_GNN_get_grad(GrM_GNN net, double *grad);
+/* Device pointer and element count of a work buffer of the last graph
+ * (synchronises): 0 walk counts (INT32, 8 x n), 1 features x, 2 means m
+ * (activation type, n x 16 row-major, columns 11..15 zero), 3 hidden h (n
+ * x 64), 4 a = w2s.h + b2, 5 q = w2n.h, 6 z, 7 x0, 8 dL/dq (FP32, n). */
+GrB_Info GrM_GNN_buffer(GrM_GNN net, int which, void **ptr, int64_t *count);
+/* Features of seed set seeds[0:nseeds) (host, distinct, in [0, n)) with
+ * `walkers` walks (1 <= walkers <= 2^26) at `damping`. */
+GrB_Info GrM_gnn_features(GrM_GNN net, GrB_Matrix A, GrB_Matrix AT, const int32_t *seeds, int nseeds,
+                          int walkers, double damping, uint64_t seed);
+/* z and x0 from the current features; *fell_back (may be NULL; reading it
+ * synchronises) is 1 when x0 is the teleport vector. */
+GrB_Info GrM_gnn_forward(GrM_GNN net, GrB_Matrix A, GrB_Matrix AT, int *fell_back);
+/* Gradient of KL(x* || x0) after GrM_gnn_forward: x_star (device FP32,
+ * element v at x_star[v * stride]) is the target; the gradient replaces
+ * (accumulate 0) or adds to (1) the network's gradient; *loss (may be
+ * NULL; reading it synchronises) receives the KL value. */
+GrB_Info GrM_gnn_backward(GrM_GNN net, GrB_Matrix A, GrB_Matrix AT, const float *x_star, int64_t stride,
+                          int accumulate, double *loss);
+/* Adam step (Kingma & Ba, 2015, with bias correction) on grad * grad_scale. */
+GrB_Info GrM_gnn_adam_step(GrM_GNN net, double lr, double beta1, double beta2, double eps, double grad_scale);
+/* Features + forward, then x0 (FP32 or FP64 vector of length n) = the
+ * prediction: a start vector for GrM_ppr. */
+GrB_Info GrM_gnn_predict_x0(GrB_Vector x0, GrM_GNN net, GrB_Matrix A, GrB_Matrix AT, const int32_t *seeds,
+                            int nseeds, int walkers, double damping, uint64_t seed, int *fell_back);
 
 /* ------------------------------------------------------------------------
  * Bandwidth probe: dst_dev[0:bytes) = src_dev[0:bytes) with a streaming

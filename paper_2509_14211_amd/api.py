@@ -157,3 +157,37 @@ def pagerank(g: Graph, dtype=torch.float32, damping=0.85, tol=1e-9, itermax=1000
         if xv:
             grb.GrB_Vector_free(xv)
     return x, it, res
+
+
+def teleport_tensor(n: int, seeds, dtype=torch.float32) -> torch.Tensor:
+    """1/|S| on the seed set S, 0 elsewhere."""
+    v = torch.zeros(n, dtype=dtype, device="cuda")
+    v[torch.as_tensor(list(seeds), dtype=torch.long, device="cuda")] = 1.0 / len(seeds)
+    return v
+
+
+def ppr(g: Graph, seeds, dtype=torch.float32, damping=0.85, tol=1e-6, itermax=1000,
+        dangling=grb.GrM_DANGLING_UNIFORM, x0: int | None = None, check_every=8):
+    """(ranks tensor, iterations, residual) of GrM_ppr for one seed set;
+    x0 is an optional start vector handle (default: the teleport vector)."""
+    tv = vector_from_tensor(teleport_tensor(g.n, seeds, dtype))
+    r = grb.GrB_Vector_new(dtype_code(dtype), g.n)
+    try:
+        it, res = grb.GrM_ppr(r, g.AT, g.outdeg, tv, damping, tol, itermax, dangling, x0, check_every)
+        x = tensor_from_vector(r, dtype)
+    finally:
+        grb.GrB_Vector_free(r)
+        grb.GrB_Vector_free(tv)
+    return x, it, res
+
+
+def device_copy(ptr: int, count: int, dtype) -> torch.Tensor:
+    """Copy of `count` elements of a library work buffer at device address
+    ptr (the size must be a multiple of 16 bytes)."""
+    out = torch.empty(count, dtype=dtype, device="cuda")
+    nbytes = count * out.element_size()
+    if nbytes % 16:
+        raise ValueError("buffer size must be a multiple of 16 bytes")
+    if nbytes:
+        grb.GrM_stream_copy(out, ptr, nbytes)
+    return out

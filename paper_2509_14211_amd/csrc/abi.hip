@@ -13,8 +13,8 @@ using namespace nbgrb;
 
 // ------------------------------------------------------------ built-ins
 
-static GB_Type_opaque t_bool{T_BOOL}, t_int32{T_INT32}, t_fp32{T_FP32}, t_fp64{T_FP64};
-GrB_Type GrB_BOOL = &t_bool, GrB_INT32 = &t_int32, GrB_FP32 = &t_fp32, GrB_FP64 = &t_fp64;
+static GB_Type_opaque t_bool{T_BOOL}, t_int32{T_INT32}, t_fp32{T_FP32}, t_fp64{T_FP64}, t_bf16{T_BF16};
+GrB_Type GrB_BOOL = &t_bool, GrB_INT32 = &t_int32, GrB_FP32 = &t_fp32, GrB_FP64 = &t_fp64, GrM_BF16 = &t_bf16;
 
 #define UNOP(NAME, OP, T)                  \
   static GB_UnaryOp_opaque u_##NAME{OP, T}; \
@@ -455,7 +455,8 @@ GrB_Info GrB_Vector_new(GrB_Vector* v, GrB_Type type, GrB_Index n) {
   need(v, "vector");
   need(type, "type");
   if (n < 1 || n > (GrB_Index)INT32_MAX) fail(GrB_INVALID_VALUE, "vector length must be in [1, 2^31)");
-  if (type->code == T_BOOL) fail(GrB_NOT_IMPLEMENTED, "BOOL vectors are not supported");
+  if (type->code == T_BOOL || type->code == T_BF16)
+    fail(GrB_NOT_IMPLEMENTED, "BOOL and BF16 vectors are not supported");
   auto* o = new GB_Vector_opaque{MAGIC_VEC, type->code, (int64_t)n, nullptr};
   set_vec(o, iso_node(type->code, (int64_t)n, 0.0));
   *v = o;

@@ -8,11 +8,13 @@
 namespace nbgrb {
 
 // Value type codes of dense vector storage.
-enum TypeCode : int { T_BOOL = 0, T_INT32 = 1, T_FP32 = 2, T_FP64 = 3 };
+// T_BF16 is a storage type of network activations only.
+enum TypeCode : int { T_BOOL = 0, T_INT32 = 1, T_FP32 = 2, T_FP64 = 3, T_BF16 = 4 };
 
 inline size_t type_size(int t) {
   switch (t) {
     case T_BOOL: return 1;
+    case T_BF16: return 2;
     case T_INT32: return 4;
     case T_FP32: return 4;
     default: return 8;

@@ -25,69 +25,12 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "device_util.h"
 #include "kernels.h"
 
 namespace nbgrb {
 
 // ------------------------------------------------------------------ helpers
-
-__device__ __forceinline__ void wait_stores() {
-  // s_waitcnt vmcnt(0): every vector memory operation of this wave is done.
-  __builtin_amdgcn_s_waitcnt(0x0F70);
-}
-
-template <typename V>
-__device__ __forceinline__ void publish(V* p, V v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename V>
-__device__ __forceinline__ V consume(const V* p) {
-  return __hip_atomic_load(const_cast<V*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ unsigned ticket_add(unsigned* p) {
-  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ int counter_add(int* p) {
-  return __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Values that are the same in every lane of the wavefront, moved to scalar
-// registers so that branches on them are uniform.
-__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int4 wave_uniform(int4 v) {
-  return make_int4(wave_uniform(v.x), wave_uniform(v.y), wave_uniform(v.z), wave_uniform(v.w));
-}
-
-// Tile descriptor t (t wave-uniform) through the scalar cache: the plan is
-// read-only during a pass, and a scalar load does not wait behind the
-// wavefront's outstanding vector loads.
-__device__ __forceinline__ int4 tile_desc(const int4* tiles, int t) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  typedef const __attribute__((address_space(4))) int4* const_int4_ptr;
-  return ((const_int4_ptr)tiles)[wave_uniform(t)];
-#else
-  return tiles[t];
-#endif
-}
-
-// Buffer resources: loads at byte offsets at or past `bytes` return zero
-// without touching memory, which keeps per-lane bounds out of the control
-// flow.
-constexpr unsigned BUF_SKIP = 0xFFFFFFF0u;  // offset of a lane that must not load
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
-}
-template <typename V, int AUX>
-__device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  if constexpr (sizeof(V) == 4)
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX));
-  else
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX));
-}
-constexpr int CP_NT = 2;  // nontemporal
 
 template <typename V>
 __device__ __forceinline__ V wave_sum(V v) {
@@ -955,15 +898,6 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 
 // ---------------------------------------------------------- R-MAT
 
-// SplitMix64 as a counter-based generator: draw k of the stream seeded
-// with `seed` is the output after k+1 increments of the state.
-__device__ __forceinline__ uint64_t splitmix_draw(uint64_t seed, uint64_t k) {
-  uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 __global__ void rmat_kernel(uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int scale,
                             int64_t nedges, uint64_t seed, double ta, double tab, double tabc) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -971,7 +905,7 @@ __global__ void rmat_kernel(uint32_t* __restrict__ src, uint32_t* __restrict__ d
     uint32_t su = 0, dv = 0;
     uint64_t k = (uint64_t)e * (uint64_t)scale;
     for (int l = 0; l < scale; ++l, ++k) {
-      const double u = (double)(splitmix_draw(seed, k) >> 11) * 0x1.0p-53;
+      const double u = draw_unit(splitmix_draw(seed, k));
       const uint32_t bs = u >= tab ? 1u : 0u;                       // c or d
       const uint32_t bd = (u >= ta && u < tab) || u >= tabc ? 1u : 0u;  // b or d
       su = (su << 1) | bs;

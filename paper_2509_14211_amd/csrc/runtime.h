@@ -257,6 +257,10 @@ void set_error_text(const std::string& msg);
 void* cache_alloc(size_t bytes, void* ctx);
 void cache_release(void* p, void* ctx);
 
+// s = A (+.second) w over the pattern of A (dense FP32/FP64 w and s of the
+// same type), run now on the context stream with the matrix's plan.
+void mxv_now(const MatP& A, int type, const void* w, void* s_out);
+
 // Degree-renumbered copy of a square pattern (built once, then cached).
 std::shared_ptr<Relabeled> get_relabeled(const MatP& A);
 

@@ -489,6 +489,8 @@ static void run_mxv_plain(const MatP& A, int type, const void* w, void* s_out) {
   run_fused(A, f);
 }
 
+void mxv_now(const MatP& A, int type, const void* w, void* s_out) { run_mxv_plain(A, type, w, s_out); }
+
 // Public hook for the autotuner and tests: one fused pass with an explicit
 // plan configuration.
 void run_fused_with(const MatP& A, const FusedSpec& f, const PlanConfig& cfg) {

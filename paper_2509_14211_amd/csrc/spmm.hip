@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device_util.h"
 #include "kernels.h"
 
 namespace nbgrb {
@@ -22,16 +23,6 @@ namespace {
 
 constexpr int SB = 1024;   // threads per workgroup
 constexpr int SNW = SB / 64;
-
-template <typename V>
-__device__ __forceinline__ void put(V* p, V v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename V>
-__device__ __forceinline__ V get(const V* p) {
-  return __hip_atomic_load(const_cast<V*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Epilogue of row i with its inputs already loaded (xo = x_old row entry,
 // dv = d_i).  Seeds are consumed in vertex order: sp is the next unread
@@ -65,8 +56,8 @@ __device__ __forceinline__ T load_xo(const SpmmArgs& p, int i, int lane, bool on
 template <typename T>
 __device__ void spmm_hub_finish(const SpmmArgs& p, int4 hub, int h, int chunk, int sp0, T acc, int lane, bool on,
                                 T cfac) {
-  if (on) put(&p.hub_sum[(int64_t)(hub.z + chunk) * 64 + lane], (double)acc);
-  drain();
+  if (on) publish(&p.hub_sum[(int64_t)(hub.z + chunk) * 64 + lane], (double)acc);
+  wait_stores();
   int last = 0;
   if (lane == 0)
     last = __hip_atomic_fetch_add(&p.hub_cnt[h], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == hub.y - 1;
@@ -77,19 +68,19 @@ __device__ void spmm_hub_finish(const SpmmArgs& p, int4 hub, int h, int chunk, i
   for (; q + 8 <= hub.y; q += 8) {  // eight loads in flight
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = on ? get(&p.hub_sum[(int64_t)(hub.z + q + u) * 64 + lane]) : 0.0;
+    for (int u = 0; u < 8; ++u) v[u] = on ? consume(&p.hub_sum[(int64_t)(hub.z + q + u) * 64 + lane]) : 0.0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) s += (T)v[u];
   }
-  for (; q < hub.y; ++q) s += on ? (T)get(&p.hub_sum[(int64_t)(hub.z + q) * 64 + lane]) : (T)0;
+  for (; q < hub.y; ++q) s += on ? (T)consume(&p.hub_sum[(int64_t)(hub.z + q) * 64 + lane]) : (T)0;
   int sp = sp0;
   int nsv = sp < p.nseeds ? p.seed_v[sp] : 0x7fffffff;
   double hr = 0.0, hd = 0.0;
   spmm_finish<T>(p, hub.x, s, lane, on, cfac, load_xo<T>(p, hub.x, lane, on), ((const T*)p.dvec)[hub.x], sp, nsv,
                  hr, hd);
-  put(&p.hub_red[(int64_t)h * 128 + lane], hr);
-  put(&p.hub_red[(int64_t)h * 128 + 64 + lane], hd);
-  if (lane == 0) put(&p.hub_cnt[h], 0);
+  publish(&p.hub_red[(int64_t)h * 128 + lane], hr);
+  publish(&p.hub_red[(int64_t)h * 128 + 64 + lane], hd);
+  if (lane == 0) publish(&p.hub_cnt[h], 0);
 }
 
 // Per-column residual and dangling mass of the pass: wavefronts in order,
@@ -108,10 +99,10 @@ __device__ void spmm_reduce(const TilePlanDev& plan, const SpmmArgs& p, double r
       a += sr[w][tid];
       b += sd[w][tid];
     }
-    put(&p.wg_part[(int64_t)blockIdx.x * 128 + tid], a);
-    put(&p.wg_part[(int64_t)blockIdx.x * 128 + 64 + tid], b);
+    publish(&p.wg_part[(int64_t)blockIdx.x * 128 + tid], a);
+    publish(&p.wg_part[(int64_t)blockIdx.x * 128 + 64 + tid], b);
   }
-  drain();
+  wait_stores();
   __syncthreads();
   if (tid == 0)
     *sflag = __hip_atomic_fetch_add(p.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
@@ -123,12 +114,12 @@ __device__ void spmm_reduce(const TilePlanDev& plan, const SpmmArgs& p, double r
     const int cc = tid & 63, sl = tid >> 6;
     double a = 0.0, b = 0.0;
     for (int g = sl; g < (int)gridDim.x; g += SNW) {
-      a += get(&p.wg_part[(int64_t)g * 128 + cc]);
-      b += get(&p.wg_part[(int64_t)g * 128 + 64 + cc]);
+      a += consume(&p.wg_part[(int64_t)g * 128 + cc]);
+      b += consume(&p.wg_part[(int64_t)g * 128 + 64 + cc]);
     }
     for (int h = sl; h < plan.nhubs; h += SNW) {
-      a += get(&p.hub_red[(int64_t)h * 128 + cc]);
-      b += get(&p.hub_red[(int64_t)h * 128 + 64 + cc]);
+      a += consume(&p.hub_red[(int64_t)h * 128 + cc]);
+      b += consume(&p.hub_red[(int64_t)h * 128 + 64 + cc]);
     }
     sr[sl][cc] = a;
     sd[sl][cc] = b;
@@ -163,7 +154,7 @@ __device__ void spmm_reduce(const TilePlanDev& plan, const SpmmArgs& p, double r
       g->iters = it;
       g->active = (mx > g->tol && it < g->itermax) ? 1 : 0;
     }
-    put(p.ticket, 0u);
+    publish(p.ticket, 0u);
   }
 }
 
@@ -175,37 +166,6 @@ struct RowBufs {
   int voff;
   unsigned row_bytes;
 };
-constexpr int CP_NT = 2;  // nontemporal cache policy of buffer loads / stores
-
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-template <typename T, int AUX>
-__device__ __forceinline__ T row_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  if constexpr (sizeof(T) == 4)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
-  else
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
-}
-template <typename T, int AUX>
-__device__ __forceinline__ void row_store(__amdgpu_buffer_rsrc_t r, T v, int voff, int soff) {
-  if constexpr (sizeof(T) == 4)
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, AUX);
-  else
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
-}
-// A value every lane reads from the same address, kept in scalar registers.
-__device__ __forceinline__ float uniform_load(const float* a) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, *a)));
-}
-__device__ __forceinline__ double uniform_load(const double* a) {
-  const int2 v = __builtin_bit_cast(int2, *a);
-  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y)));
-}
-__device__ __forceinline__ int sgpr(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int4 sgpr(int4 v) { return make_int4(sgpr(v.x), sgpr(v.y), sgpr(v.z), sgpr(v.w)); }
-__device__ __forceinline__ double sgpr(double v) {
-  const int2 h = __builtin_bit_cast(int2, v);
-  return __builtin_bit_cast(double, make_int2(sgpr(h.x), sgpr(h.y)));
-}
 __device__ __forceinline__ int row_off(const RowBufs& b, int i) { return (int)((unsigned)i * b.row_bytes); }
 
 // spmm_finish with buffer-addressed rows.
@@ -214,15 +174,15 @@ __device__ __forceinline__ void spmm_finish_b(const SpmmArgs& p, const RowBufs& 
                                               T cfac, T xo, T dv, int& sp, int& nsv, double& rho, double& dm) {
   T tele = 0;
   while (nsv == i) {
-    if (sgpr(p.seed_c[sp]) == lane) tele += (T)sgpr(p.seed_w[sp]) * cfac;
+    if (wave_uniform(p.seed_c[sp]) == lane) tele += (T)wave_uniform(p.seed_w[sp]) * cfac;
     ++sp;
-    nsv = sp < p.nseeds ? sgpr(p.seed_v[sp]) : 0x7fffffff;
+    nsv = sp < p.nseeds ? wave_uniform(p.seed_v[sp]) : 0x7fffffff;
   }
   if (!on) return;
   const T r = s + tele;
   const int so = row_off(b, i);
-  row_store<T, CP_NT>(b.xn, r, b.voff, so);
-  row_store<T, 0>(b.wn, r * dv, b.voff, so);
+  buf_store<T, CP_NT>(b.xn, r, b.voff, so);
+  buf_store<T, 0>(b.wn, r * dv, b.voff, so);
   rho += fabs((double)xo - (double)r);
   if (dv == (T)0) dm += (double)r;
 }
@@ -251,7 +211,7 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
   __shared__ double sd[SNW][64];
   __shared__ int srp[SNW][TR + 1];
   __shared__ int sflag;
-  const int tid = threadIdx.x, wv = sgpr(tid >> 6), lane = tid & 63;
+  const int tid = threadIdx.x, wv = wave_uniform(tid >> 6), lane = tid & 63;
   const bool on = lane < p.k;
   RowBufs b;
   b.row_bytes = (unsigned)p.k * (unsigned)sizeof(T);
@@ -267,7 +227,7 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
 
   const int nwaves = (int)gridDim.x * SNW;
   for (int t = (int)blockIdx.x * SNW + wv; t < plan.ntiles; t += nwaves) {
-    const int4 td = sgpr(plan.tiles[t]);
+    const int4 td = wave_uniform(plan.tiles[t]);
     const int e0 = td.z, ne = td.w;
     int colv = lane < ne ? p.col[e0 + lane] : 0;
     if (td.y > 0) {
@@ -276,13 +236,13 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      int sp = sgpr(p.tile_seed[t]);
-      int nsv = sp < p.nseeds ? sgpr(p.seed_v[sp]) : 0x7fffffff;
+      int sp = wave_uniform(p.tile_seed[t]);
+      int nsv = sp < p.nseeds ? wave_uniform(p.seed_v[sp]) : 0x7fffffff;
       int r = 0;
-      int rend = sgpr(wrp[1]);
+      int rend = wave_uniform(wrp[1]);
       T acc = 0;
-      T xo = row_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0));
-      T dv = uniform_load((const T*)p.dvec + row0);
+      T xo = buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0));
+      T dv = wave_uniform(((const T*)p.dvec)[row0]);
       for (int c0 = 0; c0 < ne; c0 += 64) {
         const int cn = c0 + 64 + lane;
         const int coln = cn < ne ? p.col[e0 + cn] : 0;
@@ -292,7 +252,7 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
           if (base >= ne) break;
           T v[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) v[u] = row_load<T, 0>(b.w, b.voff, row_off(b, __builtin_amdgcn_readlane(colv, h + u)));
+          for (int u = 0; u < U; ++u) v[u] = buf_load<T, 0>(b.w, b.voff, row_off(b, __builtin_amdgcn_readlane(colv, h + u)));
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int e = base + u;
@@ -301,9 +261,9 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
                 spmm_finish_b<T>(p, b, row0 + r, acc, lane, on, cfac, xo, dv, sp, nsv, rho, dm);
                 acc = 0;
                 ++r;
-                rend = sgpr(wrp[r + 1]);
-                xo = row_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
-                dv = uniform_load((const T*)p.dvec + row0 + r);
+                rend = wave_uniform(wrp[r + 1]);
+                xo = buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
+                dv = wave_uniform(((const T*)p.dvec)[row0 + r]);
               }
               acc += v[u];
             }
@@ -316,8 +276,8 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
         acc = 0;
         ++r;
         if (r < nr) {
-          xo = row_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
-          dv = uniform_load((const T*)p.dvec + row0 + r);
+          xo = buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
+          dv = wave_uniform(((const T*)p.dvec)[row0 + r]);
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -334,14 +294,14 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
           if (base >= ne) break;
           T v[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) v[u] = row_load<T, 0>(b.w, b.voff, row_off(b, __builtin_amdgcn_readlane(colv, hh + u)));
+          for (int u = 0; u < U; ++u) v[u] = buf_load<T, 0>(b.w, b.voff, row_off(b, __builtin_amdgcn_readlane(colv, hh + u)));
 #pragma unroll
           for (int u = 0; u < U; ++u)
             if (base + u < ne) acc += v[u];
         }
         colv = coln;
       }
-      spmm_hub_finish<T>(p, sgpr(plan.hubs[h]), h, td.x, sgpr(p.tile_seed[t]), acc, lane, on, cfac);
+      spmm_hub_finish<T>(p, wave_uniform(plan.hubs[h]), h, td.x, wave_uniform(p.tile_seed[t]), acc, lane, on, cfac);
     }
   }
   spmm_reduce(plan, p, rho, dm, sr, sd, &sflag);

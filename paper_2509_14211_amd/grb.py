@@ -34,6 +34,9 @@ _INFO_NAMES = {
     -104: "GrB_INVALID_OBJECT", -105: "GrB_INDEX_OUT_OF_BOUNDS", -106: "GrB_EMPTY_OBJECT",
 }
 
+# The info codes as module constants (GrB_INVALID_VALUE, ...).
+globals().update({name: code for code, name in _INFO_NAMES.items()})
+
 # Data symbols exported by the library (types, operators, descriptors).
 DATA_SYMBOLS = [
     "GrB_BOOL", "GrB_INT32", "GrB_FP32", "GrB_FP64",
@@ -48,7 +51,7 @@ DATA_SYMBOLS = [
     "GrB_PLUS_MONOID_FP32", "GrB_PLUS_MONOID_FP64",
     "GrB_PLUS_TIMES_SEMIRING_FP32", "GrB_PLUS_TIMES_SEMIRING_FP64",
     "GrM_PLUS_SECOND_SEMIRING_FP32", "GrM_PLUS_SECOND_SEMIRING_FP64",
-    "GrB_DESC_C",
+    "GrB_DESC_C", "GrM_BF16",
 ]
 
 vp = ctypes.c_void_p
@@ -131,6 +134,17 @@ _FUNCS = {
     "GrM_Matrix_plan_set": [vp, vp, ctypes.c_void_p],
     "GrM_Matrix_plan_get": [ctypes.c_void_p, vp, vp],
     "GrM_autotune_pagerank": [ctypes.c_void_p, ctypes.POINTER(dbl), vp, vp, vp, ctypes.c_char_p],
+    "GrM_GNN_new": [PV, vp, u64],
+    "GrM_GNN_free": [PV],
+    "GrM_GNN_set_params": [vp, vp],
+    "GrM_GNN_get_params": [vp, vp],
+    "GrM_GNN_get_grad": [vp, vp],
+    "GrM_GNN_buffer": [vp, i32, PV, ctypes.POINTER(i64)],
+    "GrM_gnn_features": [vp, vp, vp, vp, i32, i32, dbl, u64],
+    "GrM_gnn_forward": [vp, vp, vp, ctypes.POINTER(i32)],
+    "GrM_gnn_backward": [vp, vp, vp, vp, i64, i32, ctypes.POINTER(dbl)],
+    "GrM_gnn_adam_step": [vp, dbl, dbl, dbl, dbl, dbl],
+    "GrM_gnn_predict_x0": [vp, vp, vp, vp, vp, i32, i32, dbl, u64, ctypes.POINTER(i32)],
     "GrM_stream_copy": [vp, vp, ctypes.c_size_t],
     "GrM_timing_enable": [ctypes.c_bool],
     "GrM_timing_read": [ctypes.POINTER(dbl), ctypes.POINTER(i64)],
@@ -555,3 +569,88 @@ def GrM_timing_read():
     n = i64()
     _call("GrM_timing_read", ctypes.byref(t), ctypes.byref(n))
     return t.value, n.value
+
+
+# ------------------------------------------------------------ warm start
+
+GRM_GNN_NPARAMS = 1601
+GNN_BUFFERS = {"counts": 0, "X": 1, "M": 2, "H": 3, "a": 4, "q": 5, "z": 6, "x0": 7, "gq": 8}
+
+
+def _seeds_i32(seeds):
+    import numpy as np
+    return np.ascontiguousarray(np.asarray(seeds, dtype=np.int32))
+
+
+def GrM_GNN_new(act_type, init_seed: int = 0) -> int:
+    h = vp()
+    _call("GrM_GNN_new", ctypes.byref(h), act_type, init_seed & (2**64 - 1))
+    return h.value
+
+
+def GrM_GNN_free(net):
+    h = vp(net)
+    _call("GrM_GNN_free", ctypes.byref(h))
+
+
+def GrM_GNN_set_params(net, theta):
+    import numpy as np
+    t = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+    assert t.size == GRM_GNN_NPARAMS
+    _call("GrM_GNN_set_params", net, t.ctypes.data)
+
+
+def GrM_GNN_get_params(net):
+    import numpy as np
+    t = np.zeros(GRM_GNN_NPARAMS, dtype=np.float32)
+    _call("GrM_GNN_get_params", net, t.ctypes.data)
+    return t
+
+
+def GrM_GNN_get_grad(net):
+    import numpy as np
+    g = np.zeros(GRM_GNN_NPARAMS, dtype=np.float64)
+    _call("GrM_GNN_get_grad", net, g.ctypes.data)
+    return g
+
+
+def GrM_GNN_buffer(net, which):
+    """(device address, element count) of a work buffer (name or index)."""
+    w = GNN_BUFFERS[which] if isinstance(which, str) else int(which)
+    p = vp()
+    c = i64()
+    _call("GrM_GNN_buffer", net, w, ctypes.byref(p), ctypes.byref(c))
+    return p.value, c.value
+
+
+def GrM_gnn_features(net, A, AT, seeds, walkers: int, damping: float, seed: int):
+    s = _seeds_i32(seeds)
+    _call("GrM_gnn_features", net, A, AT, s.ctypes.data, s.size, walkers, damping, seed & (2**64 - 1))
+
+
+def GrM_gnn_forward(net, A, AT) -> int:
+    """Returns 1 if the prediction fell back to the teleport vector."""
+    fb = i32()
+    _call("GrM_gnn_forward", net, A, AT, ctypes.byref(fb))
+    return fb.value
+
+
+def GrM_gnn_backward(net, A, AT, x_star, stride: int = 1, accumulate: bool = False) -> float:
+    """Gradient of KL(x* || x0) into the network; returns the loss."""
+    loss = dbl()
+    _call("GrM_gnn_backward", net, A, AT, _addr(x_star), stride, 1 if accumulate else 0, ctypes.byref(loss))
+    return loss.value
+
+
+def GrM_gnn_adam_step(net, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                      grad_scale: float = 1.0):
+    _call("GrM_gnn_adam_step", net, lr, beta1, beta2, eps, grad_scale)
+
+
+def GrM_gnn_predict_x0(x0, net, A, AT, seeds, walkers: int, damping: float, seed: int) -> int:
+    """x0 (a GrB_Vector) = predicted start vector; returns the fallback flag."""
+    s = _seeds_i32(seeds)
+    fb = i32()
+    _call("GrM_gnn_predict_x0", x0, net, A, AT, s.ctypes.data, s.size, walkers, damping, seed & (2**64 - 1),
+          ctypes.byref(fb))
+    return fb.value

@@ -1,0 +1,202 @@
+"""Training and evaluation driver of the learned warm start.
+
+Host-side loops over the C entry points of the library (every step --
+walk features, the network's forward and backward passes, Adam, the
+personalised PageRank solves that provide the targets and the
+comparison -- runs in its kernels).
+
+Training: for each graph, the targets x* of its seed sets come from one
+batched personalised PageRank solve per 64 seed sets (GrM_ppr_batch,
+FP32, tolerance `target_tol`); each seed set is one sample: features,
+forward, backward into the accumulated gradient, and an Adam step every
+`batch` samples on the mean gradient.
+
+Evaluation: for every seed set of a graph, GrM_ppr from the teleport start
+and from the predicted start, both to the same tolerance; the warm-start
+time counts the features and the network's prediction as well as the
+iterations.
+
+Run as ``python -m paper_2509_14211_amd.warmstart`` for the full-size
+experiment (10 scale-20 training graphs x 1000 seed sets, 5 scale-22
+evaluation graphs x 200 seed sets; ``--quick`` for a small one).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import api, grb
+
+DAMPING = 0.85
+FEATURE_SEED_STRIDE = 1_000_003
+
+
+def feature_seed(graph_seed: int, index: int) -> int:
+    """Random-walk stream of seed set `index` on the graph of `graph_seed`."""
+    return graph_seed * FEATURE_SEED_STRIDE + index
+
+
+class WarmStart:
+    def __init__(self, act: str = "bf16", walkers: int = 1 << 14, init_seed: int = 0, damping: float = DAMPING):
+        self.act = act
+        t = grb.builtin("GrM_BF16" if act == "bf16" else "GrB_FP32")
+        self.net = grb.GrM_GNN_new(t, init_seed)
+        self.walkers = walkers
+        self.damping = damping
+
+    def close(self):
+        if self.net:
+            grb.GrM_GNN_free(self.net)
+            self.net = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ training
+    def targets(self, g: api.Graph, seed_sets, tol: float) -> torch.Tensor:
+        """n x k FP32 ranks of up to 64 seed sets (row-major)."""
+        k = len(seed_sets)
+        X = torch.empty(g.n * k, dtype=torch.float32, device="cuda")
+        grb.GrM_ppr_batch(X, grb.builtin("GrB_FP32"), seed_sets, g.AT, g.outdeg, self.damping, tol, 1000)
+        return X
+
+    def train(self, graphs, seed_sets_per_graph, epochs: int = 3, lr: float = 3e-3, batch: int = 8,
+              graph_seeds=None, target_tol: float = 1e-6, log=None) -> list:
+        """Returns the mean loss of every epoch."""
+        graph_seeds = graph_seeds or list(range(len(graphs)))
+        targets = []
+        for g, sets in zip(graphs, seed_sets_per_graph):
+            targets.append([(c, self.targets(g, sets[c:c + 64], target_tol)) for c in range(0, len(sets), 64)])
+        history = []
+        pending = 0
+        for ep in range(epochs):
+            total, count = 0.0, 0
+            for gi, (g, sets) in enumerate(zip(graphs, seed_sets_per_graph)):
+                for c0, X in targets[gi]:
+                    k = min(64, len(sets) - c0)
+                    for q in range(k):
+                        i = c0 + q
+                        grb.GrM_gnn_features(self.net, g.A, g.AT, sets[i], self.walkers, self.damping,
+                                             feature_seed(graph_seeds[gi], i))
+                        grb.GrM_gnn_forward(self.net, g.A, g.AT)
+                        loss = grb.GrM_gnn_backward(self.net, g.A, g.AT, X[q:], stride=k, accumulate=pending > 0)
+                        pending += 1
+                        total += loss
+                        count += 1
+                        if pending == batch:
+                            grb.GrM_gnn_adam_step(self.net, lr, grad_scale=1.0 / pending)
+                            pending = 0
+            if pending:
+                grb.GrM_gnn_adam_step(self.net, lr, grad_scale=1.0 / pending)
+                pending = 0
+            history.append(total / max(count, 1))
+            if log:
+                log("epoch %d: mean KL %.5f over %d samples" % (ep, history[-1], count))
+        return history
+
+    # ------------------------------------------------------------ inference
+    def predict_vector(self, g: api.Graph, seeds, graph_seed: int, index: int) -> int:
+        """A new FP32 GrB_Vector holding the predicted start (caller frees)."""
+        v = grb.GrB_Vector_new(grb.builtin("GrB_FP32"), g.n)
+        try:
+            self.last_fallback = grb.GrM_gnn_predict_x0(v, self.net, g.A, g.AT, seeds, self.walkers, self.damping,
+                                                        feature_seed(graph_seed, index))
+        except Exception:
+            grb.GrB_Vector_free(v)
+            raise
+        return v
+
+    def evaluate(self, g: api.Graph, seed_sets, tol: float = 1e-6, graph_seed: int = 0) -> dict:
+        stream = torch.cuda.current_stream()
+        it_t, it_w, t_t, t_w, fb = [], [], 0.0, 0.0, 0
+        tele = []
+        for seeds in seed_sets:
+            tele.append(api.vector_from_tensor(api.teleport_tensor(g.n, seeds, torch.float32)))
+        r = grb.GrB_Vector_new(grb.builtin("GrB_FP32"), g.n)
+        try:
+            for i, seeds in enumerate(seed_sets):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                it, _ = grb.GrM_ppr(r, g.AT, g.outdeg, tele[i], self.damping, tol, 1000)
+                torch.cuda.synchronize()
+                t_t += time.perf_counter() - t0
+                it_t.append(it)
+                t0 = time.perf_counter()
+                x0 = self.predict_vector(g, seeds, graph_seed, i)
+                try:
+                    it, _ = grb.GrM_ppr(r, g.AT, g.outdeg, tele[i], self.damping, tol, 1000, x0=x0)
+                    torch.cuda.synchronize()
+                finally:
+                    grb.GrB_Vector_free(x0)
+                t_w += time.perf_counter() - t0
+                it_w.append(it)
+                fb += self.last_fallback
+        finally:
+            grb.GrB_Vector_free(r)
+            for v in tele:
+                grb.GrB_Vector_free(v)
+        del stream
+        n = len(seed_sets)
+        return {"sets": n, "mean_iters_teleport": float(np.mean(it_t)), "mean_iters_warm": float(np.mean(it_w)),
+                "ms_teleport": 1e3 * t_t / n, "ms_warm": 1e3 * t_w / n, "fallbacks": int(fb),
+                "iters_teleport": it_t, "iters_warm": it_w}
+
+
+def seed_sets(n: int, count: int, seed: int):
+    import synthetic
+    return [list(map(int, s)) for s in synthetic.ppr_seed_sets(n, count, seed=seed)]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--quick", action="store_true", help="scale-14 training / scale-16 evaluation, few sets")
+    ap.add_argument("--act", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--epochs", type=int, default=2)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    args = ap.parse_args()
+    if args.quick:
+        tr_scale, tr_graphs, tr_sets, ev_scale, ev_graphs, ev_sets = 14, 2, 128, 16, 1, 64
+    else:
+        tr_scale, tr_graphs, tr_sets, ev_scale, ev_graphs, ev_sets = 20, 10, 1000, 22, 5, 200
+
+    def log(*a):
+        print(*a, flush=True)
+
+    with api.Context(grb.GrB_NONBLOCKING):
+        ws = WarmStart(args.act)
+        train_seeds = [1000 + i for i in range(tr_graphs)]
+        t0 = time.perf_counter()
+        out = {"train": {"scale": tr_scale, "graphs": tr_graphs, "sets_per_graph": tr_sets}, "eval": []}
+        hist = []
+        for ep in range(args.epochs):
+            for gs in train_seeds:
+                g = api.rmat_graph(tr_scale, seed=gs)
+                hist += ws.train([g], [seed_sets(g.n, tr_sets, gs)], epochs=1, lr=args.lr, graph_seeds=[gs])
+                g.free()
+            log("epoch %d done (%.1f s), last mean KL %.5f" % (ep, time.perf_counter() - t0, hist[-1]))
+        out["train"]["seconds"] = time.perf_counter() - t0
+        out["train"]["loss_history"] = hist
+        for i in range(ev_graphs):
+            gs = 2000 + i
+            g = api.rmat_graph(ev_scale, seed=gs)
+            res = ws.evaluate(g, seed_sets(g.n, ev_sets, 5000 + i), tol=1e-6, graph_seed=gs)
+            g.free()
+            res.pop("iters_teleport")
+            res.pop("iters_warm")
+            res["scale"] = ev_scale
+            res["graph_seed"] = gs
+            log(json.dumps(res))
+            out["eval"].append(res)
+        ws.close()
+        print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
