@@ -81,7 +81,7 @@ def recorded_traffic():
         return None
 
 
-def summarize_rocprof(dirs) -> None:
+def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float>") -> None:
     """Kernel statistics (from --kernel-trace --stats) and per-dispatch PMC
     counters (from --pmc runs) found under the given directories, as
     Markdown tables; with FETCH_SIZE and WRITE_SIZE runs that include the
@@ -110,7 +110,7 @@ def summarize_rocprof(dirs) -> None:
             print("| kernel | launches | mean (us) | launches > 20 us | their mean (us) |")
             print("|---|---|---|---|---|")
             for k, v in dur.items():
-                if "fused" in k:
+                if "fused" in k or traffic_kernel in k:
                     act = [x for x in v if x > 20.0]
                     print("| %s | %d | %.2f | %d | %.2f |" % (k[:90], len(v), sum(v) / len(v), len(act),
                                                             sum(act) / max(len(act), 1)))
@@ -124,12 +124,12 @@ def summarize_rocprof(dirs) -> None:
             print("| kernel | counter | dispatches | mean | max |")
             print("|---|---|---|---|---|")
             for (k, c), v in sorted(vals.items()):
-                if "fused" in k or "stream_copy" in k:
+                if "fused" in k or "stream_copy" in k or traffic_kernel in k:
                     print("| %s | %s | %d | %.1f | %.1f |" % (k[:90], c, len(v), sum(v) / len(v), max(v)))
                     counters[(k, c)] = v
             print()
     copy = [k for (k, c) in counters if "stream_copy" in k]
-    fused = sorted({k for (k, c) in counters if "fused_wave_kernel<float>" in k})
+    fused = sorted({k for (k, c) in counters if traffic_kernel in k})
     if copy and fused:
         ck = copy[0]
         f_copy = sum(counters[(ck, "FETCH_SIZE")]) / len(counters[(ck, "FETCH_SIZE")])
@@ -140,7 +140,7 @@ def summarize_rocprof(dirs) -> None:
         f_k = sum(counters[(k, "FETCH_SIZE")]) / len(counters[(k, "FETCH_SIZE")])
         w_k = sum(counters[(k, "WRITE_SIZE")]) / len(counters[(k, "WRITE_SIZE")])
         traffic = f_k * 1024.0 * f_scale + w_k * 1024.0 * w_scale
-        print("### calibrated traffic of the fused FP32 kernel\n")
+        print("### calibrated traffic of %s\n" % traffic_kernel)
         print("The copy probe reads and writes %d bytes per launch; its counters give the scale of each "
               "counter (bytes per KiB reported).\n" % COPY_BYTES)
         print("- copy_fetch_kib: %.1f" % f_copy)
@@ -150,7 +150,8 @@ def summarize_rocprof(dirs) -> None:
         print("- kernel_fetch_kib_per_launch: %.1f" % f_k)
         print("- kernel_write_kib_per_launch: %.1f" % w_k)
         print("- traffic_bytes_per_launch: %d" % int(round(traffic)))
-        print("- source_sha256: %s" % kernel_source_sha())
+        if traffic_kernel == "fused_wave_kernel<float>":
+            print("- source_sha256: %s" % kernel_source_sha())
         print()
 
 
@@ -167,14 +168,28 @@ def main():
                     help="target length of the CPU oracle sample (whole passes)")
     ap.add_argument("--ppr-k", type=int, default=64, help="seed sets of the batched PPR leg")
     ap.add_argument("--many", type=int, default=256, help="graphs of the many-graph leg")
+    ap.add_argument("--warm-train-sets", type=int, default=256,
+                    help="seed sets per training graph of the warm-start leg (0: skip it)")
     ap.add_argument("--skip-extras", action="store_true",
-                    help="time only the headline fused solve (for profiling)")
+                    help="time only the headline fused solve (for profiling); same as --legs none")
+    ap.add_argument("--legs", default="all",
+                    help="comma list of extra legs to run: blocking (also FP64), ppr, many, warm; or all / none")
+    ap.add_argument("--traffic-kernel", default="fused_wave_kernel<float>",
+                    help="kernel (name substring) whose calibrated traffic --summarize-rocprof reports")
     ap.add_argument("--summarize-rocprof", metavar="DIR", nargs="+",
                     help="print a text summary of the rocprofv3 CSV files under the DIRs and exit")
     args = ap.parse_args()
     if args.summarize_rocprof:
-        summarize_rocprof(args.summarize_rocprof)
+        summarize_rocprof(args.summarize_rocprof, args.traffic_kernel)
         return
+
+    legs = {"blocking", "ppr", "many", "warm"} if args.legs == "all" else (
+        set() if args.legs == "none" else set(args.legs.split(",")))
+    if args.skip_extras:
+        legs = set()
+
+    def leg(name):
+        return name in legs
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -286,7 +301,7 @@ def main():
         out["stream_copy_gbs"] = round(copy_gbs, 1)
         out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
 
-        if not args.skip_extras:
+        if leg("blocking"):
             # ---- unfused (blocking) FP32
             grb.GrM_set_mode(grb.GrB_BLOCKING)
             xb, itersb, msb, _ = timed(torch.float32, max(2, args.steps // 2), 1)
@@ -308,7 +323,7 @@ def main():
 
         # ---- batched personalised PageRank: 64 seed sets (sizes 1..16) as one
         # SpMM solve vs 64 sequential single-vector solves, same tolerance
-        if not args.skip_extras and args.ppr_k > 0:
+        if leg("ppr") and args.ppr_k > 0:
             import synthetic
             sets = [s.tolist() for s in synthetic.ppr_seed_sets(n, args.ppr_k, seed=7)]
             f32 = grb.builtin("GrB_FP32")
@@ -356,7 +371,7 @@ def main():
 
         # ---- many small graphs: one persistent, graph-captured launch vs the
         # same graphs solved one after another
-        if not args.skip_extras and args.many > 0:
+        if leg("many") and args.many > 0:
             import synthetic
             specs = synthetic.many_graph_specs(args.many)
             t0 = time.perf_counter()
@@ -409,6 +424,34 @@ def main():
                 x.free()
             del Xm
 
+        # ---- learned warm start (reduced size): train on scale-20 graphs,
+        # then warm vs teleport start on the headline graph, both to tol;
+        # the warm time includes the walk features and the prediction.
+        if leg("warm") and args.warm_train_sets > 0:
+            from paper_2509_14211_amd import warmstart
+            t0 = time.perf_counter()
+            ws = warmstart.WarmStart("bf16")
+            tr = []
+            for gs in (1000, 1001):
+                gt = api.rmat_graph(20, seed=gs)
+                tr += ws.train([gt], [warmstart.seed_sets(gt.n, args.warm_train_sets, gs)], epochs=1,
+                               lr=3e-3, graph_seeds=[gs])
+                gt.free()
+            train_s = time.perf_counter() - t0
+            ev = ws.evaluate(g, warmstart.seed_sets(n, 64, 5000), tol=args.tol, graph_seed=args.scale)
+            ws.close()
+            log("warm start: trained in %.1fs (KL %.4f); iterations warm %.2f vs teleport %.2f; "
+                "%.2f vs %.2f ms per query" % (train_s, tr[-1], ev["mean_iters_warm"], ev["mean_iters_teleport"],
+                                               ev["ms_warm"], ev["ms_teleport"]))
+            out["warm_start"] = {"train": "2 R-MAT scale-20 graphs x %d seed sets, 1 epoch, BF16 activations" %
+                                          args.warm_train_sets,
+                                 "train_s": round(train_s, 2), "final_kl": round(tr[-1], 5),
+                                 "eval_sets": ev["sets"], "mean_iters_warm": ev["mean_iters_warm"],
+                                 "mean_iters_teleport": ev["mean_iters_teleport"],
+                                 "ms_per_query_warm": round(ev["ms_warm"], 3),
+                                 "ms_per_query_teleport": round(ev["ms_teleport"], 3),
+                                 "fallbacks": ev["fallbacks"]}
+
         # ---- CPU oracle on a bounded sample: the same graph, a fixed number
         # of passes, and the GPU error against it at that pass count.
         if not args.no_cpu_baseline:
@@ -418,9 +461,10 @@ def main():
             t0 = time.perf_counter()
             og = oracle.rmat_graph(args.scale)
             build_s = time.perf_counter() - t0
+            oracle.pagerank(og, DAMPING, fixed_iters=2)  # warm-up
             t0 = time.perf_counter()
-            oracle.pagerank(og, DAMPING, fixed_iters=2)  # warm-up, and the pass time estimate
-            per_pass = (time.perf_counter() - t0) / 2
+            oracle.pagerank(og, DAMPING, fixed_iters=8)  # pass time estimate
+            per_pass = (time.perf_counter() - t0) / 8
             k = max(8, int(args.cpu_seconds / max(per_pass, 1e-6)))
             t0 = time.perf_counter()
             ref = oracle.pagerank(og, DAMPING, fixed_iters=k)
