@@ -167,6 +167,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target length of the CPU oracle sample (whole passes)")
     ap.add_argument("--ppr-k", type=int, default=64, help="seed sets of the batched PPR leg")
+    ap.add_argument("--ppr-stream", type=int, default=512,
+                    help="seed sets streamed through the ppr-k column slots (0: skip)")
     ap.add_argument("--many", type=int, default=256, help="graphs of the many-graph leg")
     ap.add_argument("--warm-train-sets", type=int, default=256,
                     help="seed sets per training graph of the warm-start leg (0: skip it)")
@@ -368,6 +370,29 @@ def main():
                           "batch_vs_sequential_speedup": round(seq_per_query * len(sets) / batch_ms, 2),
                           "algorithmic_gbs": round(bpp * pit / (batch_ms * 1e-3) / 1e9, 1),
                           "max_col_resid": float(col_res.max())}
+            # a stream of seed sets through the same 64 column slots: a
+            # converged column is written out and restarts with the next set
+            if args.ppr_stream > 0:
+                ssets = [s_.tolist() for s_ in synthetic.ppr_seed_sets(n, args.ppr_stream, seed=8)]
+                Xs = torch.empty(n * len(ssets), dtype=torch.float32, device="cuda")
+                torch.cuda.synchronize()
+                e0.record(stream)
+                s_it, s_ps, s_res = grb.GrM_ppr_stream(Xs, f32, ssets, g.AT, g.outdeg, DAMPING, args.tol, 1000,
+                                                       grb.GrM_DANGLING_UNIFORM, len(sets), 2)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                stream_ms = e0.elapsed_time(e1)
+                del Xs
+                log("ppr stream: %d sets through %d slots, %.1f ms -> %.1f queries/s (mean %.1f passes per set, "
+                    "first converged at %.1f)" % (len(ssets), len(sets), stream_ms, len(ssets) / stream_ms * 1e3,
+                                                  s_ps.mean(), s_it.mean()))
+                out["ppr"]["stream"] = {"sets": len(ssets), "slots": len(sets), "ms": round(stream_ms, 2),
+                                        "queries_per_s": round(len(ssets) / stream_ms * 1e3, 1),
+                                        "mean_passes_per_set": round(float(s_ps.mean()), 2),
+                                        "mean_first_converged_pass": round(float(s_it.mean()), 2),
+                                        "max_resid": float(s_res.max())}
+                out["ppr"]["queries_per_s_batch64"] = out["ppr"]["queries_per_s"]
+                out["ppr"]["queries_per_s"] = out["ppr"]["stream"]["queries_per_s"]
 
         # ---- many small graphs: one persistent, graph-captured launch vs the
         # same graphs solved one after another

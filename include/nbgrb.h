@@ -387,6 +387,22 @@ GrB_Info GrM_ppr_batch(void *X, GrB_Type type, int k, const int32_t *seed_ptr,
                        double tol, int itermax, GrM_Dangling dangling, int check_every, int *iters,
                        int *col_iters, double *col_resid);
 
+/* Personalised PageRank of nsets seed sets through k column slots
+ * (1 <= k <= 64) of the batched pass: the first k sets start together, and
+ * whenever a column's residual has reached tol (checked every check_every
+ * passes) or it has run itermax passes, its ranks are written out and the
+ * column restarts with the next set, so one pass always serves k queries.
+ * Seed sets as in GrM_ppr_batch.  X (device, nsets x n of `type` FP32 or
+ * FP64) receives set q's ranks at X + q n in the original numbering;
+ * set_iters[q] (host, may be NULL) the first pass at which its residual was
+ * <= tol (-1 if never), set_passes[q] the passes it ran (its ranks are that
+ * iterate), set_resid[q] its last residual.  Each set's ranks equal
+ * GrM_ppr's after set_passes[q] passes. */
+GrB_Info GrM_ppr_stream(void *X, GrB_Type type, int nsets, const int32_t *seed_ptr,
+                        const int32_t *seed_vtx, GrB_Matrix AT, GrB_Vector outdeg, double damping,
+                        double tol, int itermax, GrM_Dangling dangling, int k, int check_every,
+                        int *set_iters, int *set_passes, double *set_resid);
+
 /* ------------------------------------------------------------------------
  * Many independent graphs in one launch.  A multigraph packs copies of
  * ngraphs transposed adjacency patterns AT[g] (square; each graph's

@@ -1023,7 +1023,6 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
   int64_t base = 0;
   GuardDev hg{};
   int batch = check_every;
-  int issued = 0;
   for (;;) {
     for (int j = 0; j < batch; ++j) {
       GB_Vector_opaque w{MAGIC_VEC, T, n, nullptr}, s{MAGIC_VEC, T, n, nullptr};
@@ -1064,7 +1063,6 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
       set_sca(&rho, nullptr);
       set_sca(&Dn, nullptr);
     }
-    issued += batch;
     hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
     hip_check(hipStreamSynchronize(c.stream), "sync");
     if (!hg.active) break;
@@ -1125,6 +1123,210 @@ GrB_Info GrM_ppr(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, GrB_Vec
   return pagerank_impl(r, iters, resid, AT, outdeg, teleport, damping, tol, itermax, dangling, x0, check_every);
 }
 
+// ------------------------------------------------------------ batched PPR
+
+namespace {
+
+struct PprSeed {
+  int v, c;
+  double w;
+};
+
+// Seed sets seed_vtx[seed_ptr[q] : seed_ptr[q+1]], q < nsets: non-empty,
+// distinct vertices in [0, n).
+void check_seed_sets(int nsets, const int32_t* seed_ptr, const int32_t* seed_vtx, int64_t n) {
+  need(seed_ptr, "seed_ptr");
+  need(seed_vtx, "seed_vtx");
+  if (seed_ptr[0] != 0) fail(GrB_INVALID_VALUE, "seed_ptr[0] must be 0");
+  for (int q = 0; q < nsets; ++q)
+    if (seed_ptr[q + 1] <= seed_ptr[q]) fail(GrB_INVALID_VALUE, "every seed set must be non-empty");
+  for (int q = 0; q < nsets; ++q) {
+    std::vector<int> s(seed_vtx + seed_ptr[q], seed_vtx + seed_ptr[q + 1]);
+    std::sort(s.begin(), s.end());
+    for (size_t i = 0; i < s.size(); ++i) {
+      if (s[i] < 0 || s[i] >= n) fail(GrB_INDEX_OUT_OF_BOUNDS, "seed vertex out of range");
+      if (i > 0 && s[i] == s[i - 1]) fail(GrB_INVALID_VALUE, "repeated seed vertex in a set");
+    }
+  }
+}
+
+// Device state of k personalised PageRank columns iterated together by the
+// SpMM pass: the execution matrix (degree-renumbered copy when the plan
+// asks for it), its wave tile plan, d = damping ./ outdeg, the two
+// alternating n x k iterate / pre-scaled buffers, the per-column FP64
+// residual and dangling mass, and the vertex-sorted seed table.
+struct PprColumns {
+  int64_t n = 0;
+  int T = T_FP32, k = 0;
+  std::shared_ptr<Relabeled> rl;
+  MatP A_exec;
+  std::vector<int> inv_host;
+  std::shared_ptr<Plan> plan;
+  GB_Vector_opaque dinv{MAGIC_VEC, T_FP32, 0, nullptr};
+  size_t vbytes = 0;
+  BufP Xb[2], Wb[2], Db[2], rho, hit, hub_sum, hub_cnt, hub_red, wg_part, ticket, gbuf, tile_seed, sv, sc, sw;
+  SpmmArgs a{};
+  int grid = 0;
+  bool uniform = true;
+
+  ~PprColumns() { set_vec(&dinv, nullptr); }
+
+  void setup(GB_Matrix_opaque* ao, GB_Vector_opaque* dego, int type, int kk, double damping, double tol,
+             bool unif) {
+    Ctx& c = ctx();
+    n = ao->nrows;
+    T = type;
+    k = kk;
+    uniform = unif;
+    const PlanConfig pc = default_plan_config(ao->data, T);
+    A_exec = ao->data;
+    if (pc.relabel) {
+      rl = get_relabeled(ao->data);
+      A_exec = rl->A;
+      inv_host.resize((size_t)n);
+      hip_check(hipMemcpyAsync(inv_host.data(), rl->inv->p, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost,
+                               c.stream),
+                "copy permutation");
+      hip_check(hipStreamSynchronize(c.stream), "sync");
+    }
+    PlanConfig wp;
+    wp.kernel = K_WAVE;
+    wp.lds_entries = WAVE_TILE_ENTRIES;
+    wp.lds_rows = WAVE_TILE_ROWS;
+    wp.long_row = (pc.kernel == K_WAVE) ? pc.long_row : WAVE_TILE_ENTRIES;
+    wp.chunk = WAVE_TILE_ENTRIES;
+    wp.grid = c.cus * 2;
+    plan = get_plan(A_exec, wp);
+    grid = plan->cfg.grid;
+
+    // d = damping ./ outdeg (0 for dangling), in execution order
+    GB_Vector_opaque deg_exec{MAGIC_VEC, dego->type, n, nullptr};
+    set_vec(&deg_exec, rl ? permuted(dego->node, rl->order) : dego->node);
+    dinv.type = T;
+    dinv.n = n;
+    rec_unop(&dinv, U_MINV_OR_ZERO, &deg_exec);
+    rec_bind(&dinv, B_TIMES, &dinv, damping, true);
+    set_vec(&deg_exec, nullptr);
+    materialize(dinv.node);
+    store_if_iso(dinv.node);
+
+    vbytes = type_size(T) * (size_t)n * (size_t)k;
+    for (int i = 0; i < 2; ++i) {
+      Xb[i] = dev_alloc(vbytes);
+      Wb[i] = dev_alloc(vbytes);
+      Db[i] = dev_alloc(sizeof(double) * 64);
+    }
+    rho = dev_alloc(sizeof(double) * 64);
+    hit = dev_alloc(sizeof(int) * 64);
+    hub_sum = dev_alloc(sizeof(double) * 64 * (size_t)std::max(plan->nparts, 1));
+    hub_cnt = dev_alloc(sizeof(int) * (size_t)std::max(plan->nhubs, 1));
+    hub_red = dev_alloc(sizeof(double) * 128 * (size_t)std::max(plan->nhubs, 1));
+    wg_part = dev_alloc(sizeof(double) * 128 * (size_t)grid);
+    ticket = dev_alloc(256);
+    gbuf = dev_alloc(sizeof(GuardDev));
+    tile_seed = dev_alloc(sizeof(int) * (size_t)std::max(plan->dev.ntiles, 1));
+    hip_check(launch_zero(hub_cnt->p, sizeof(int) * (size_t)std::max(plan->nhubs, 1), c.stream), "zero");
+    hip_check(launch_zero(ticket->p, 256, c.stream), "zero");
+    hip_check(launch_zero(Xb[0]->p, vbytes, c.stream), "zero");
+    hip_check(launch_zero(Wb[0]->p, vbytes, c.stream), "zero");
+    hip_check(launch_zero(Db[0]->p, sizeof(double) * 64, c.stream), "zero");
+    hip_check(launch_zero(rho->p, sizeof(double) * 64, c.stream), "zero");
+    for (int i = 0; i < 6; ++i) launch_mark(false);
+
+    a.rowptr = (const int*)A_exec->rowptr->p;
+    a.col = A_exec->col ? (const int*)A_exec->col->p : nullptr;
+    a.k = k;
+    a.w_bytes = vbytes < 0xFFFFFF00ull ? (unsigned)vbytes : 0u;
+    a.dvec = dinv.node->buf->p;
+    a.c_alpha = damping;
+    a.c_beta = 1.0 - damping;
+    a.rho_out = (double*)rho->p;
+    a.hit = (int*)hit->p;
+    a.hit_tol = tol;
+    a.hub_sum = (double*)hub_sum->p;
+    a.hub_cnt = (int*)hub_cnt->p;
+    a.hub_red = (double*)hub_red->p;
+    a.wg_part = (double*)wg_part->p;
+    a.ticket = (unsigned*)ticket->p;
+    a.tile_seed = (const int*)tile_seed->p;
+  }
+
+  int exec_vertex(int v) const { return rl ? inv_host[(size_t)v] : v; }
+
+  BufP upload(const void* h, size_t bytes) {
+    BufP b = dev_alloc(std::max<size_t>(bytes, 16));
+    if (bytes) hip_check(hipMemcpyAsync(b->p, h, bytes, hipMemcpyHostToDevice, ctx().stream), "upload");
+    return b;
+  }
+
+  // Teleport table of the columns in use: seeds (execution numbering)
+  // sorted by vertex, then column; each tile's first seed.
+  void set_seeds(std::vector<PprSeed> seeds) {
+    std::sort(seeds.begin(), seeds.end(),
+              [](const PprSeed& x, const PprSeed& y) { return x.v != y.v ? x.v < y.v : x.c < y.c; });
+    const int ns = (int)seeds.size();
+    std::vector<int> v(ns), cc(ns);
+    std::vector<double> w(ns);
+    for (int i = 0; i < ns; ++i) {
+      v[i] = seeds[i].v;
+      cc[i] = seeds[i].c;
+      w[i] = seeds[i].w;
+    }
+    sv = upload(v.data(), sizeof(int) * ns);
+    sc = upload(cc.data(), sizeof(int) * ns);
+    sw = upload(w.data(), sizeof(double) * ns);
+    a.seed_v = (const int*)sv->p;
+    a.seed_c = (const int*)sc->p;
+    a.seed_w = (const double*)sw->p;
+    a.nseeds = ns;
+    hip_check(launch_spmm_tile_seed(plan->dev, a.seed_v, ns, (int*)tile_seed->p, ctx().stream), "tile seeds");
+    launch_mark(false);
+  }
+
+  // Start columns `cols` (their seeds listed by column in seeds_by_col) in
+  // buffer set `cur`: x = v, w = v .* d, D = dangling seed mass, hit = -1.
+  void start_columns(uint64_t cols, int cur, const std::vector<PprSeed>& seeds_by_col) {
+    Ctx& c = ctx();
+    hip_check(launch_spmm_zero_columns(Xb[cur]->p, Wb[cur]->p, T, n, k, cols, c.stream), "zero columns");
+    std::vector<int> ptr(k + 1, 0), v;
+    std::vector<double> w;
+    for (int col = 0; col < k; ++col) {
+      for (const PprSeed& s : seeds_by_col)
+        if (s.c == col) {
+          v.push_back(s.v);
+          w.push_back(s.w);
+        }
+      ptr[col + 1] = (int)v.size();
+    }
+    BufP dp = upload(ptr.data(), sizeof(int) * (k + 1)), dv = upload(v.data(), sizeof(int) * v.size());
+    BufP dw = upload(w.data(), sizeof(double) * w.size());
+    SpmmArgs ia = a;
+    ia.x_new = Xb[cur]->p;
+    ia.w_new = Wb[cur]->p;
+    ia.d_out = (double*)Db[cur]->p;
+    hip_check(launch_spmm_init(ia, T, (const int*)dp->p, (const int*)dv->p, (const double*)dw->p, cols, c.stream),
+              "ppr init");
+    launch_mark(false);
+    launch_mark(false);
+  }
+
+  // One pass from buffer set (pass-1)&1 into pass&1.
+  void run_pass(int pass) {
+    Ctx& c = ctx();
+    const int in = (pass - 1) & 1, out = pass & 1;
+    a.w = Wb[in]->p;
+    a.x_old = Xb[in]->p;
+    a.x_new = Xb[out]->p;
+    a.w_new = Wb[out]->p;
+    a.d_prev = uniform ? (const double*)Db[in]->p : nullptr;
+    a.d_out = (double*)Db[out]->p;
+    hip_check(launch_spmm_ppr(plan->dev, a, T, grid, a.guard, c.stream), "ppr pass");
+    launch_mark(true);
+  }
+};
+
+}  // namespace
+
 GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, const int32_t* seed_vtx,
                        GrB_Matrix AT, GrB_Vector outdeg, double damping, double tol, int itermax,
                        GrM_Dangling dangling, int check_every, int* iters, int* col_iters, double* col_resid) {
@@ -1134,7 +1336,6 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
   require_init();
   need(X, "X");
   need(type, "type");
-  need(seed_ptr, "seed_ptr");
   need(iters, "iters");
   GB_Matrix_opaque* ao = mat(AT, "AT");
   GB_Vector_opaque* dego = vec(outdeg, "outdeg");
@@ -1147,159 +1348,27 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
   if (check_every < 1 || itermax < 0 || !(damping >= 0.0 && damping < 1.0) || std::isnan(tol))
     fail(GrB_INVALID_VALUE, "ppr_batch parameters");
   if (c.guard) fail(GrB_INVALID_VALUE, "an iterative driver is already running");
-  if (seed_ptr[0] != 0) fail(GrB_INVALID_VALUE, "seed_ptr[0] must be 0");
-  for (int q = 0; q < k; ++q)
-    if (seed_ptr[q + 1] <= seed_ptr[q]) fail(GrB_INVALID_VALUE, "every seed set must be non-empty");
-  const int ns = seed_ptr[k];
-  need(seed_vtx, "seed_vtx");
+  check_seed_sets(k, seed_ptr, seed_vtx, n);
+
+  PprColumns pc;
+  pc.setup(ao, dego, T, k, damping, tol, dangling == GrM_DANGLING_UNIFORM);
+  std::vector<PprSeed> seeds;
   for (int q = 0; q < k; ++q) {
-    std::vector<int> s(seed_vtx + seed_ptr[q], seed_vtx + seed_ptr[q + 1]);
-    std::sort(s.begin(), s.end());
-    for (size_t i = 0; i < s.size(); ++i) {
-      if (s[i] < 0 || s[i] >= n) fail(GrB_INDEX_OUT_OF_BOUNDS, "seed vertex out of range");
-      if (i > 0 && s[i] == s[i - 1]) fail(GrB_INVALID_VALUE, "repeated seed vertex in a set");
-    }
-  }
-  const bool uniform = dangling == GrM_DANGLING_UNIFORM;
-
-  // execution matrix (degree-renumbered copy if the plan asks for it)
-  const PlanConfig pc = default_plan_config(ao->data, T);
-  std::shared_ptr<Relabeled> rl;
-  MatP A_exec = ao->data;
-  std::vector<int> inv_host;
-  if (pc.relabel) {
-    rl = get_relabeled(ao->data);
-    A_exec = rl->A;
-    inv_host.resize((size_t)n);
-    hip_check(hipMemcpyAsync(inv_host.data(), rl->inv->p, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost, c.stream),
-              "copy permutation");
-    hip_check(hipStreamSynchronize(c.stream), "sync");
-  }
-  PlanConfig wp;
-  wp.kernel = K_WAVE;
-  wp.lds_entries = WAVE_TILE_ENTRIES;
-  wp.lds_rows = WAVE_TILE_ROWS;
-  wp.long_row = (pc.kernel == K_WAVE) ? pc.long_row : WAVE_TILE_ENTRIES;
-  wp.chunk = WAVE_TILE_ENTRIES;
-  wp.grid = c.cus * 2;
-  auto plan = get_plan(A_exec, wp);
-
-  // d = damping ./ outdeg (0 for dangling), in execution order
-  GB_Vector_opaque deg_exec{MAGIC_VEC, dego->type, n, nullptr};
-  set_vec(&deg_exec, rl ? permuted(dego->node, rl->order) : dego->node);
-  GB_Vector_opaque dinv{MAGIC_VEC, T, n, nullptr};
-  rec_unop(&dinv, U_MINV_OR_ZERO, &deg_exec);
-  rec_bind(&dinv, B_TIMES, &dinv, damping, true);
-  set_vec(&deg_exec, nullptr);
-  materialize(dinv.node);
-  store_if_iso(dinv.node);
-
-  // seed tables: by column (initial vectors) and sorted by vertex (teleport)
-  struct Seed {
-    int v, c;
-    double w;
-  };
-  std::vector<Seed> seeds;
-  std::vector<int> bc_ptr(k + 1), bc_v(ns);
-  std::vector<double> bc_w(ns);
-  for (int q = 0; q < k; ++q) {
-    bc_ptr[q] = seed_ptr[q];
     const double w = 1.0 / (double)(seed_ptr[q + 1] - seed_ptr[q]);
-    for (int e = seed_ptr[q]; e < seed_ptr[q + 1]; ++e) {
-      const int v = rl ? inv_host[(size_t)seed_vtx[e]] : seed_vtx[e];
-      bc_v[e] = v;
-      bc_w[e] = w;
-      seeds.push_back({v, q, w});
-    }
+    for (int e = seed_ptr[q]; e < seed_ptr[q + 1]; ++e) seeds.push_back({pc.exec_vertex(seed_vtx[e]), q, w});
   }
-  bc_ptr[k] = ns;
-  std::sort(seeds.begin(), seeds.end(), [](const Seed& a, const Seed& b) { return a.v != b.v ? a.v < b.v : a.c < b.c; });
-  std::vector<int> sv(ns), sc(ns);
-  std::vector<double> sw(ns);
-  for (int i = 0; i < ns; ++i) {
-    sv[i] = seeds[i].v;
-    sc[i] = seeds[i].c;
-    sw[i] = seeds[i].w;
-  }
-  auto upload = [&](const void* h, size_t bytes) {
-    BufP b = dev_alloc(bytes);
-    hip_check(hipMemcpyAsync(b->p, h, bytes, hipMemcpyHostToDevice, c.stream), "upload");
-    return b;
-  };
-  BufP d_sv = upload(sv.data(), sizeof(int) * ns), d_sc = upload(sc.data(), sizeof(int) * ns);
-  BufP d_sw = upload(sw.data(), sizeof(double) * ns);
-  BufP d_bcp = upload(bc_ptr.data(), sizeof(int) * (k + 1)), d_bcv = upload(bc_v.data(), sizeof(int) * ns);
-  BufP d_bcw = upload(bc_w.data(), sizeof(double) * ns);
-
-  const size_t vbytes = type_size(T) * (size_t)n * (size_t)k;
-  BufP Xb[2] = {dev_alloc(vbytes), dev_alloc(vbytes)};
-  BufP Wb[2] = {dev_alloc(vbytes), dev_alloc(vbytes)};
-  BufP Db[2] = {dev_alloc(sizeof(double) * 64), dev_alloc(sizeof(double) * 64)};
-  BufP rho = dev_alloc(sizeof(double) * 64), hit = dev_alloc(sizeof(int) * 64);
-  const int grid = plan->cfg.grid;
-  BufP hub_sum = dev_alloc(sizeof(double) * 64 * (size_t)std::max(plan->nparts, 1));
-  BufP hub_cnt = dev_alloc(sizeof(int) * (size_t)std::max(plan->nhubs, 1));
-  BufP hub_red = dev_alloc(sizeof(double) * 128 * (size_t)std::max(plan->nhubs, 1));
-  BufP wg_part = dev_alloc(sizeof(double) * 128 * (size_t)grid);
-  BufP ticket = dev_alloc(256);
-  BufP gbuf = dev_alloc(sizeof(GuardDev));
-  hip_check(launch_zero(hub_cnt->p, sizeof(int) * (size_t)std::max(plan->nhubs, 1), c.stream), "zero");
-  hip_check(launch_zero(ticket->p, 256, c.stream), "zero");
-  hip_check(launch_zero(Xb[0]->p, vbytes, c.stream), "zero");
-  hip_check(launch_zero(Wb[0]->p, vbytes, c.stream), "zero");
-  for (int i = 0; i < 4; ++i) launch_mark(false);
-
-  SpmmArgs a{};
-  a.rowptr = (const int*)A_exec->rowptr->p;
-  a.col = A_exec->col ? (const int*)A_exec->col->p : nullptr;
-  a.k = k;
-  a.w_bytes = vbytes < 0xFFFFFF00ull ? (unsigned)vbytes : 0u;
-  a.dvec = dinv.node->buf->p;
-  a.seed_v = (const int*)d_sv->p;
-  a.seed_c = (const int*)d_sc->p;
-  a.seed_w = (const double*)d_sw->p;
-  a.nseeds = ns;
-  a.c_alpha = damping;
-  a.c_beta = 1.0 - damping;
-  a.rho_out = (double*)rho->p;
-  a.hit = (int*)hit->p;
-  a.hub_sum = (double*)hub_sum->p;
-  a.hub_cnt = (int*)hub_cnt->p;
-  a.hub_red = (double*)hub_red->p;
-  a.wg_part = (double*)wg_part->p;
-  a.ticket = (unsigned*)ticket->p;
-  BufP tile_seed = dev_alloc(sizeof(int) * (size_t)std::max(plan->dev.ntiles, 1));
-  hip_check(launch_spmm_tile_seed(plan->dev, a.seed_v, ns, (int*)tile_seed->p, c.stream), "tile seeds");
-  launch_mark(false);
-  a.tile_seed = (const int*)tile_seed->p;
-  // initial vectors
-  a.x_new = Xb[0]->p;
-  a.w_new = Wb[0]->p;
-  a.d_out = (double*)Db[0]->p;
-  hip_check(launch_spmm_init(a, T, (const int*)d_bcp->p, (const int*)d_bcv->p, (const double*)d_bcw->p, c.stream),
-            "ppr init");
-  launch_mark(false);
-  hip_check(launch_guard_init((GuardDev*)gbuf->p, (1.0 > tol && itermax > 0) ? 1 : 0, tol, itermax, c.stream),
+  pc.set_seeds(seeds);
+  pc.start_columns(k == 64 ? ~0ull : ((1ull << k) - 1ull), 0, seeds);
+  hip_check(launch_guard_init((GuardDev*)pc.gbuf->p, (1.0 > tol && itermax > 0) ? 1 : 0, tol, itermax, c.stream),
             "guard init");
   launch_mark(false);
-  c.guard = (GuardDev*)gbuf->p;
-  a.guard = c.guard;
+  c.guard = (GuardDev*)pc.gbuf->p;
+  pc.a.guard = c.guard;
 
   GuardDev hg{};
   int pass = 0, batch = check_every;
   for (;;) {
-    for (int j = 0; j < batch; ++j) {
-      ++pass;
-      const int in = (pass - 1) & 1, out = pass & 1;
-      a.w = Wb[in]->p;
-      a.x_old = Xb[in]->p;
-      a.x_new = Xb[out]->p;
-      a.w_new = Wb[out]->p;
-      a.d_prev = uniform ? (const double*)Db[in]->p : nullptr;
-      a.d_out = (double*)Db[out]->p;
-      hip_check(launch_spmm_ppr(plan->dev, a, T, grid, c.guard, c.stream), "ppr pass");
-      launch_mark(true);
-    }
+    for (int j = 0; j < batch; ++j) pc.run_pass(++pass);
     hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
     hip_check(hipStreamSynchronize(c.stream), "sync");
     if (!hg.active) break;
@@ -1313,22 +1382,139 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
     batch = next;
   }
   c.guard = saved_guard;
-  const BufP& res = Xb[hg.iters & 1];
-  if (rl)
-    hip_check(launch_rows_permute(res->p, T, (const int*)rl->inv->p, X, n, k, c.stream), "unpermute");
+  const BufP& res = pc.Xb[hg.iters & 1];
+  if (pc.rl)
+    hip_check(launch_rows_permute(res->p, T, (const int*)pc.rl->inv->p, X, n, k, c.stream), "unpermute");
   else
-    hip_check(hipMemcpyAsync(X, res->p, vbytes, hipMemcpyDeviceToDevice, c.stream), "copy out");
+    hip_check(hipMemcpyAsync(X, res->p, pc.vbytes, hipMemcpyDeviceToDevice, c.stream), "copy out");
   std::vector<int> hh(64);
   std::vector<double> rr(64);
-  hip_check(hipMemcpyAsync(hh.data(), hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
-  hip_check(hipMemcpyAsync(rr.data(), rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+  hip_check(hipMemcpyAsync(hh.data(), pc.hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+  hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
   hip_check(hipStreamSynchronize(c.stream), "sync");
   if (col_iters)
     for (int q = 0; q < k; ++q) col_iters[q] = hg.iters == 0 ? -1 : hh[q];
   if (col_resid)
     for (int q = 0; q < k; ++q) col_resid[q] = hg.iters == 0 ? 1.0 : rr[q];
-  set_vec(&dinv, nullptr);
   *iters = hg.iters;
+  }
+  catch (const GrbError& e) {
+    c.guard = saved_guard;
+    g_err = e.msg;
+    return e.info;
+  }
+  catch (const std::exception& e) {
+    c.guard = saved_guard;
+    g_err = e.what();
+    return GrB_PANIC;
+  }
+  return GrB_SUCCESS;
+}
+
+GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_ptr, const int32_t* seed_vtx,
+                        GrB_Matrix AT, GrB_Vector outdeg, double damping, double tol, int itermax,
+                        GrM_Dangling dangling, int k, int check_every, int* set_iters, int* set_passes,
+                        double* set_resid) {
+  Ctx& c = ctx();
+  GuardDev* saved_guard = c.guard;
+  API_BEGIN
+  require_init();
+  need(X, "X");
+  need(type, "type");
+  GB_Matrix_opaque* ao = mat(AT, "AT");
+  GB_Vector_opaque* dego = vec(outdeg, "outdeg");
+  const int T = type->code;
+  float_type(T, "type");
+  const int64_t n = ao->nrows;
+  if (ao->ncols != n || dego->n != n) fail(GrB_DIMENSION_MISMATCH, "ppr_stream dimensions");
+  if (nsets < 1) fail(GrB_INVALID_VALUE, "nsets must be >= 1");
+  if (k < 1 || k > 64) fail(GrB_INVALID_VALUE, "k must be in [1, 64]");
+  if (dangling != GrM_DANGLING_DROP && dangling != GrM_DANGLING_UNIFORM) fail(GrB_INVALID_VALUE, "dangling mode");
+  if (check_every < 1 || itermax < 1 || !(damping >= 0.0 && damping < 1.0) || std::isnan(tol))
+    fail(GrB_INVALID_VALUE, "ppr_stream parameters");
+  if (c.guard) fail(GrB_INVALID_VALUE, "an iterative driver is already running");
+  check_seed_sets(nsets, seed_ptr, seed_vtx, n);
+  if (k > nsets) k = nsets;
+
+  PprColumns pc;
+  pc.setup(ao, dego, T, k, damping, tol, dangling == GrM_DANGLING_UNIFORM);
+  // the device guard only counts passes here (it never stops them)
+  hip_check(launch_guard_init((GuardDev*)pc.gbuf->p, 1, -1.0, INT32_MAX, c.stream), "guard init");
+  launch_mark(false);
+  c.guard = (GuardDev*)pc.gbuf->p;
+  pc.a.guard = c.guard;
+
+  std::vector<int> slot_set(k, -1), slot_start(k, 0);
+  std::vector<PprSeed> active;  // seeds of the columns in use
+  int next_set = 0, pass = 0, live = 0;
+  auto set_seeds_of = [&](int q, int col, std::vector<PprSeed>& out) {
+    const double w = 1.0 / (double)(seed_ptr[q + 1] - seed_ptr[q]);
+    for (int e = seed_ptr[q]; e < seed_ptr[q + 1]; ++e) out.push_back({pc.exec_vertex(seed_vtx[e]), col, w});
+  };
+  // fill the free slots with the next sets, starting them in buffer set `cur`
+  auto refill = [&](int cur) {
+    // drop the seeds of retired columns, then hand free columns the next sets
+    active.erase(std::remove_if(active.begin(), active.end(), [&](const PprSeed& s) { return slot_set[s.c] < 0; }),
+                 active.end());
+    uint64_t cols = 0;
+    std::vector<PprSeed> fresh;
+    for (int col = 0; col < k && next_set < nsets; ++col) {
+      if (slot_set[col] >= 0) continue;
+      slot_set[col] = next_set;
+      slot_start[col] = pass;
+      set_seeds_of(next_set, col, fresh);
+      cols |= 1ull << col;
+      ++next_set;
+      ++live;
+    }
+    active.insert(active.end(), fresh.begin(), fresh.end());
+    pc.set_seeds(active);
+    if (cols) pc.start_columns(cols, cur, fresh);
+  };
+  refill(0);
+  std::vector<int> hh(64);
+  std::vector<double> rr(64);
+  while (live > 0) {
+    // up to check_every passes, never past a column's itermax
+    int batch = check_every;
+    for (int col = 0; col < k; ++col)
+      if (slot_set[col] >= 0) batch = std::min(batch, itermax - (pass - slot_start[col]));
+    for (int j = 0; j < std::max(batch, 1); ++j) pc.run_pass(++pass);
+    hip_check(hipMemcpyAsync(hh.data(), pc.hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+    hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    const int cur = pass & 1;
+    bool freed = false;
+    for (int col = 0; col < k; ++col) {
+      const int q = slot_set[col];
+      if (q < 0) continue;
+      const int done = pass - slot_start[col];
+      const bool conv = hh[col] >= 0;
+      if (!conv && done < itermax) continue;
+      // retire: the column's current iterate, in the original numbering
+      hip_check(launch_spmm_column_out(pc.Xb[cur]->p, T, pc.rl ? (const int*)pc.rl->inv->p : nullptr, n, k, col,
+                                       (char*)X + type_size(T) * (size_t)n * (size_t)q, c.stream),
+                "column out");
+      launch_mark(false);
+      if (set_iters) set_iters[q] = conv ? hh[col] - slot_start[col] : -1;
+      if (set_passes) set_passes[q] = done;
+      if (set_resid) set_resid[q] = rr[col];
+      slot_set[col] = -1;
+      --live;
+      freed = true;
+    }
+    if (freed) {
+      // a freed column stops contributing: zero it; then refill
+      uint64_t dead = 0;
+      for (int col = 0; col < k; ++col)
+        if (slot_set[col] < 0) dead |= 1ull << col;
+      hip_check(launch_spmm_zero_columns(pc.Xb[cur]->p, pc.Wb[cur]->p, T, n, k, dead, c.stream), "zero columns");
+      launch_mark(false);
+      refill(cur);
+    }
+  }
+  c.guard = saved_guard;
+  hip_check(hipStreamSynchronize(c.stream), "sync");
   }
   catch (const GrbError& e) {
     c.guard = saved_guard;

@@ -227,7 +227,8 @@ struct SpmmArgs {
   double c_alpha, c_beta;
   double* rho_out;  // k
   double* d_out;    // k
-  int* hit;         // k: first pass with rho_c <= tol (-1 before)
+  int* hit;         // k: first pass with rho_c <= hit_tol (-1 before)
+  double hit_tol;
   GuardDev* guard;
   double* hub_sum;
   int* hub_cnt;
@@ -239,9 +240,15 @@ constexpr int SPMM_BLOCK = 1024;
 hipError_t launch_spmm_ppr(const TilePlanDev& plan, const SpmmArgs& a, int type, int grid,
                            const GuardDev* guard, hipStream_t s);
 hipError_t launch_spmm_tile_seed(const TilePlanDev& plan, const int* seed_v, int nseeds, int* out, hipStream_t s);
-// x_new = V, w_new = V .* d (both must be zero beforehand), d_out = D0, hit = -1.
+// Columns c with bit c of `cols` set: x_new = V, w_new = V .* d (both must
+// be zero there beforehand), d_out = D0, hit = -1; other columns untouched.
 hipError_t launch_spmm_init(const SpmmArgs& a, int type, const int* by_col_ptr, const int* by_col_v,
-                            const double* by_col_w, hipStream_t s);
+                            const double* by_col_w, uint64_t cols, hipStream_t s);
+// Zero columns `cols` (bit mask) of the n x k arrays x and w.
+hipError_t launch_spmm_zero_columns(void* x, void* w, int type, int64_t n, int k, uint64_t cols, hipStream_t s);
+// out[i] = in[(idx ? idx[i] : i) * k + c], i < n: one column in vertex order.
+hipError_t launch_spmm_column_out(const void* in, int type, const int* idx, int64_t n, int k, int c, void* out,
+                                  hipStream_t s);
 // out row i = in row idx[i] (n rows of k values).
 hipError_t launch_rows_permute(const void* in, int type, const int* idx, void* out, int64_t n, int k,
                                hipStream_t s);

@@ -145,7 +145,7 @@ __device__ void spmm_reduce(const TilePlanDev& plan, const SpmmArgs& p, double r
       p.rho_out[c] = sr[0][c];
       p.d_out[c] = sd[0][c];
       if (sr[0][c] > mx) mx = sr[0][c];
-      if (p.hit && p.hit[c] < 0 && p.guard && sr[0][c] <= p.guard->tol) p.hit[c] = it;
+      if (p.hit && p.hit[c] < 0 && p.guard && sr[0][c] <= p.hit_tol) p.hit[c] = it;
     }
     if (p.guard) {
       GuardDev* g = p.guard;
@@ -412,9 +412,10 @@ __global__ void spmm_tile_seed_kernel(TilePlanDev plan, const int* __restrict__ 
 // D0_c = sum of the seed weights of column c on dangling vertices.
 template <typename T>
 __global__ void spmm_init_kernel(SpmmArgs p, const int* __restrict__ by_col_ptr,
-                                 const int* __restrict__ by_col_v, const double* __restrict__ by_col_w) {
+                                 const int* __restrict__ by_col_v, const double* __restrict__ by_col_w,
+                                 uint64_t cols) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= p.k) return;
+  if (c >= p.k || !((cols >> c) & 1ull)) return;
   double D = 0.0;
   for (int q = by_col_ptr[c]; q < by_col_ptr[c + 1]; ++q) {
     const int v = by_col_v[q];
@@ -426,6 +427,35 @@ __global__ void spmm_init_kernel(SpmmArgs p, const int* __restrict__ by_col_ptr,
   }
   p.d_out[c] = D;
   if (p.hit) p.hit[c] = -1;
+}
+
+__global__ void zero_columns_kernel(void* __restrict__ x, void* __restrict__ w, int type, int64_t n, int k,
+                                    uint64_t cols) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t total = n * k;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
+    const int c = (int)(q % k);
+    if (!((cols >> c) & 1ull)) continue;
+    if (type == T_FP32) {
+      ((float*)x)[q] = 0.f;
+      ((float*)w)[q] = 0.f;
+    } else {
+      ((double*)x)[q] = 0.0;
+      ((double*)w)[q] = 0.0;
+    }
+  }
+}
+
+__global__ void column_out_kernel(const void* __restrict__ in, int type, const int* __restrict__ idx, int64_t n,
+                                  int k, int c, void* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t src = (idx ? (int64_t)idx[i] : i) * k + c;
+    if (type == T_FP32)
+      ((float*)out)[i] = ((const float*)in)[src];
+    else
+      ((double*)out)[i] = ((const double*)in)[src];
+  }
 }
 
 __global__ void rows_permute_kernel(const void* __restrict__ in, int type, const int* __restrict__ idx,
@@ -470,11 +500,28 @@ hipError_t launch_spmm_tile_seed(const TilePlanDev& plan, const int* seed_v, int
 }
 
 hipError_t launch_spmm_init(const SpmmArgs& a, int type, const int* by_col_ptr, const int* by_col_v,
-                            const double* by_col_w, hipStream_t s) {
+                            const double* by_col_w, uint64_t cols, hipStream_t s) {
   if (type == T_FP32)
-    hipLaunchKernelGGL(spmm_init_kernel<float>, dim3(1), dim3(64), 0, s, a, by_col_ptr, by_col_v, by_col_w);
+    hipLaunchKernelGGL(spmm_init_kernel<float>, dim3(1), dim3(64), 0, s, a, by_col_ptr, by_col_v, by_col_w, cols);
   else
-    hipLaunchKernelGGL(spmm_init_kernel<double>, dim3(1), dim3(64), 0, s, a, by_col_ptr, by_col_v, by_col_w);
+    hipLaunchKernelGGL(spmm_init_kernel<double>, dim3(1), dim3(64), 0, s, a, by_col_ptr, by_col_v, by_col_w, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_zero_columns(void* x, void* w, int type, int64_t n, int k, uint64_t cols, hipStream_t s) {
+  if (n <= 0 || !cols) return hipSuccess;
+  int64_t g = (n * k + 1023) / 1024;
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(zero_columns_kernel, dim3((int)g), dim3(256), 0, s, x, w, type, n, k, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_column_out(const void* in, int type, const int* idx, int64_t n, int k, int c, void* out,
+                                  hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + 1023) / 1024;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(column_out_kernel, dim3((int)g), dim3(256), 0, s, in, type, idx, n, k, c, out);
   return hipGetLastError();
 }
 

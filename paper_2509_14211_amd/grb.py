@@ -127,6 +127,7 @@ _FUNCS = {
                 vp, i32],
     "GrM_ppr_batch": [vp, vp, i32, vp, vp, vp, vp, dbl, dbl, i32, i32, i32, ctypes.POINTER(i32),
                       vp, vp],
+    "GrM_ppr_stream": [vp, vp, i32, vp, vp, vp, vp, dbl, dbl, i32, i32, i32, i32, vp, vp, vp],
     "GrM_Multigraph_new": [PV, i32, vp],
     "GrM_Multigraph_free": [PV],
     "GrM_Multigraph_offsets": [vp, vp],
@@ -523,6 +524,26 @@ def GrM_ppr_batch(X, type_, seed_sets, AT, outdeg, damping, tol, itermax,
           damping, tol, itermax, dangling, check_every, ctypes.byref(it), col_it.ctypes.data,
           col_res.ctypes.data)
     return it.value, col_it[:k].copy(), col_res[:k].copy()
+
+
+def GrM_ppr_stream(X, type_, seed_sets, AT, outdeg, damping, tol, itermax, dangling=GrM_DANGLING_UNIFORM,
+                   k=64, check_every=2):
+    """seed_sets: list of integer sequences.  X: device buffer of
+    len(seed_sets) * n entries of type_ (set q at offset q * n).  Returns
+    per-set (first converged pass, passes run, last residual) numpy arrays."""
+    import numpy as np
+    q = len(seed_sets)
+    ptr = np.zeros(q + 1, dtype=np.int32)
+    for i, s in enumerate(seed_sets):
+        ptr[i + 1] = ptr[i] + len(s)
+    vtx = np.ascontiguousarray(np.concatenate([np.asarray(s, dtype=np.int32) for s in seed_sets])
+                               if q else np.zeros(0, np.int32), dtype=np.int32)
+    it = np.zeros(max(q, 1), dtype=np.int32)
+    ps = np.zeros(max(q, 1), dtype=np.int32)
+    res = np.zeros(max(q, 1), dtype=np.float64)
+    _call("GrM_ppr_stream", _addr(X), type_, q, ptr.ctypes.data, vtx.ctypes.data, AT, outdeg, damping, tol,
+          itermax, dangling, k, check_every, it.ctypes.data, ps.ctypes.data, res.ctypes.data)
+    return it[:q].copy(), ps[:q].copy(), res[:q].copy()
 
 
 def GrM_Multigraph_new(ATs) -> int:

@@ -137,3 +137,57 @@ def test_ppr_batch_invariants_and_errors(nonblocking):
     X, it, col_it, _ = _batch(grb, g, sets, torch.float64, tol=2.0)
     assert it == 0 and np.all(col_it == -1)
     g.free()
+
+
+def _stream(grb, g, sets, dtype, tol, k, check_every=2, itermax=1000, dangling=1):
+    X = torch.zeros(len(sets) * g.n, dtype=dtype, device="cuda")
+    it, ps, res = grb.GrM_ppr_stream(X, _tcode(grb, dtype), [list(map(int, s)) for s in sets], g.AT, g.outdeg, D,
+                                     tol, itermax, dangling, k, check_every)
+    return X.reshape(len(sets), g.n).cpu().numpy().astype(np.float64), it, ps, res
+
+
+@pytest.mark.parametrize("k,relabel", [(64, 1), (7, 0)])
+def test_ppr_stream_matches_oracle(nonblocking, oracle_mod, k, relabel):
+    """More seed sets than column slots: each set's ranks equal the oracle's
+    after the passes it ran, its first converged pass matches a free oracle
+    solve, and slots are reused (sets > k)."""
+    from paper_2509_14211_amd import api
+    grb = nonblocking
+    print("ppr stream k", k, "relabel", relabel, flush=True)
+    g = api.rmat_graph(11)
+    og = oracle_mod.rmat_graph(11)
+    for dtype in (torch.float64, torch.float32):
+        grb.GrM_Matrix_plan_set(g.AT, _tcode(grb, dtype),
+                                dict(kernel=1, lds_entries=512, lds_rows=256, long_row=512, chunk=512,
+                                     grid=0, hot=0, relabel=relabel))
+    sets = synthetic.ppr_seed_sets(g.n, 150, seed=21)
+    X, it, ps, res = _stream(grb, g, sets, torch.float64, 1e-9, k, check_every=3)
+    assert np.all(it >= 1) and np.all(it <= ps) and np.all(ps - it < 3) and res.max() <= 1e-9
+    for q, s in enumerate(sets):
+        ref = oracle_mod.ppr(og, s, D, fixed_iters=int(ps[q]))
+        assert np.abs(X[q] - ref.x).sum() / np.abs(ref.x).sum() <= 1e-12, q
+        free = oracle_mod.ppr(og, s, D, tol=1e-9)
+        assert abs(int(it[q]) - free.iters) <= 1, (q, it[q], free.iters)
+    X, it, ps, res = _stream(grb, g, sets, torch.float32, 1e-6, k)
+    for q, s in enumerate(sets):
+        ref = oracle_mod.ppr(og, s, D, fixed_iters=int(ps[q]))
+        assert np.abs(X[q] - ref.x).sum() <= 1e-5, q
+    g.free()
+
+
+def test_ppr_stream_itermax_and_drop_mode(nonblocking, oracle_mod):
+    """Sets that cannot converge retire after exactly itermax passes."""
+    from paper_2509_14211_amd import api
+    grb = nonblocking
+    n, src, dst = synthetic.star_both(3000)
+    g = api.graph_from_edges(n, src, dst)
+    og = oracle_mod.graph_from_edges(n, src, dst)
+    sets = [[0], [1, 2, 3], list(range(5, 21)), [7], [2999]]
+    X, it, ps, res = _stream(grb, g, sets, torch.float64, 1e-14, 2, check_every=4, itermax=5, dangling=0)
+    assert np.all(ps == 5) and np.all(it == -1)
+    for q, s in enumerate(sets):
+        ref = oracle_mod.ppr(og, s, D, fixed_iters=5, mode=0)
+        assert np.abs(X[q] - ref.x).sum() / np.abs(ref.x).sum() <= 1e-12
+    with pytest.raises(grb.GrBError):
+        _stream(grb, g, [[1, 1]], torch.float64, 1e-9, 2)
+    g.free()
