@@ -1452,7 +1452,7 @@ GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_p
     for (int e = seed_ptr[q]; e < seed_ptr[q + 1]; ++e) out.push_back({pc.exec_vertex(seed_vtx[e]), col, w});
   };
   // fill the free slots with the next sets, starting them in buffer set `cur`
-  auto refill = [&](int cur) {
+  auto refill = [&](int cur, uint64_t freed) {
     // drop the seeds of retired columns, then hand free columns the next sets
     active.erase(std::remove_if(active.begin(), active.end(), [&](const PprSeed& s) { return slot_set[s.c] < 0; }),
                  active.end());
@@ -1469,9 +1469,9 @@ GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_p
     }
     active.insert(active.end(), fresh.begin(), fresh.end());
     pc.set_seeds(active);
-    if (cols) pc.start_columns(cols, cur, fresh);
+    pc.start_columns(cols | freed, cur, fresh);
   };
-  refill(0);
+  refill(0, 0);
   std::vector<int> hh(64);
   std::vector<double> rr(64);
   while (live > 0) {
@@ -1484,33 +1484,30 @@ GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_p
     hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
     hip_check(hipStreamSynchronize(c.stream), "sync");
     const int cur = pass & 1;
-    bool freed = false;
+    uint64_t retired = 0;
+    ColumnOutputs outs{};
     for (int col = 0; col < k; ++col) {
       const int q = slot_set[col];
       if (q < 0) continue;
       const int done = pass - slot_start[col];
       const bool conv = hh[col] >= 0;
       if (!conv && done < itermax) continue;
-      // retire: the column's current iterate, in the original numbering
-      hip_check(launch_spmm_column_out(pc.Xb[cur]->p, T, pc.rl ? (const int*)pc.rl->inv->p : nullptr, n, k, col,
-                                       (char*)X + type_size(T) * (size_t)n * (size_t)q, c.stream),
-                "column out");
-      launch_mark(false);
+      // retire: the column's current iterate goes to set q's output
+      retired |= 1ull << col;
+      outs.out[col] = (char*)X + type_size(T) * (size_t)n * (size_t)q;
       if (set_iters) set_iters[q] = conv ? hh[col] - slot_start[col] : -1;
       if (set_passes) set_passes[q] = done;
       if (set_resid) set_resid[q] = rr[col];
       slot_set[col] = -1;
       --live;
-      freed = true;
     }
-    if (freed) {
-      // a freed column stops contributing: zero it; then refill
-      uint64_t dead = 0;
-      for (int col = 0; col < k; ++col)
-        if (slot_set[col] < 0) dead |= 1ull << col;
-      hip_check(launch_spmm_zero_columns(pc.Xb[cur]->p, pc.Wb[cur]->p, T, n, k, dead, c.stream), "zero columns");
+    if (retired) {
+      hip_check(launch_spmm_columns_out(pc.Xb[cur]->p, T, pc.rl ? (const int*)pc.rl->inv->p : nullptr, n, k, retired,
+                                        outs, c.stream),
+                "columns out");
       launch_mark(false);
-      refill(cur);
+      // freed columns stop contributing (zeroed) or restart with new sets
+      refill(cur, retired);
     }
   }
   c.guard = saved_guard;

@@ -246,9 +246,13 @@ hipError_t launch_spmm_init(const SpmmArgs& a, int type, const int* by_col_ptr, 
                             const double* by_col_w, uint64_t cols, hipStream_t s);
 // Zero columns `cols` (bit mask) of the n x k arrays x and w.
 hipError_t launch_spmm_zero_columns(void* x, void* w, int type, int64_t n, int k, uint64_t cols, hipStream_t s);
-// out[i] = in[(idx ? idx[i] : i) * k + c], i < n: one column in vertex order.
-hipError_t launch_spmm_column_out(const void* in, int type, const int* idx, int64_t n, int k, int c, void* out,
-                                  hipStream_t s);
+// For every column c with bit c of `cols` set: out[c][i] = in[(idx ? idx[i]
+// : i) * k + c], i < n (columns of the n x k array in vertex order).
+struct ColumnOutputs {
+  void* out[64];
+};
+hipError_t launch_spmm_columns_out(const void* in, int type, const int* idx, int64_t n, int k, uint64_t cols,
+                                   const ColumnOutputs& outs, hipStream_t s);
 // out row i = in row idx[i] (n rows of k values).
 hipError_t launch_rows_permute(const void* in, int type, const int* idx, void* out, int64_t n, int k,
                                hipStream_t s);

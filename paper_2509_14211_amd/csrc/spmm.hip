@@ -446,15 +446,23 @@ __global__ void zero_columns_kernel(void* __restrict__ x, void* __restrict__ w, 
   }
 }
 
-__global__ void column_out_kernel(const void* __restrict__ in, int type, const int* __restrict__ idx, int64_t n,
-                                  int k, int c, void* __restrict__ out) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const int64_t src = (idx ? (int64_t)idx[i] : i) * k + c;
-    if (type == T_FP32)
-      ((float*)out)[i] = ((const float*)in)[src];
-    else
-      ((double*)out)[i] = ((const double*)in)[src];
+// 64 rows per workgroup: the rows (k values each, read whole) go through
+// LDS, then each selected column leaves as 64 consecutive values.
+template <typename T>
+__global__ __launch_bounds__(256) void columns_out_kernel(const T* __restrict__ in, const int* __restrict__ idx,
+                                                          int64_t n, int k, uint64_t cols, ColumnOutputs outs) {
+  __shared__ T tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  for (int q = threadIdx.x; q < 64 * 64; q += 256) {
+    const int r = q >> 6, c = q & 63;
+    const int64_t i = r0 + r;
+    if (i < n && c < k) tile[r][c] = in[(idx ? (int64_t)idx[i] : i) * k + c];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 64 * 64; q += 256) {
+    const int c = q >> 6, r = q & 63;
+    const int64_t i = r0 + r;
+    if (i < n && c < k && ((cols >> c) & 1ull)) ((T*)outs.out[c])[i] = tile[r][c];
   }
 }
 
@@ -516,12 +524,15 @@ hipError_t launch_spmm_zero_columns(void* x, void* w, int type, int64_t n, int k
   return hipGetLastError();
 }
 
-hipError_t launch_spmm_column_out(const void* in, int type, const int* idx, int64_t n, int k, int c, void* out,
-                                  hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int64_t g = (n + 1023) / 1024;
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(column_out_kernel, dim3((int)g), dim3(256), 0, s, in, type, idx, n, k, c, out);
+hipError_t launch_spmm_columns_out(const void* in, int type, const int* idx, int64_t n, int k, uint64_t cols,
+                                   const ColumnOutputs& outs, hipStream_t s) {
+  if (n <= 0 || !cols) return hipSuccess;
+  const int g = (int)((n + 63) / 64);
+  if (type == T_FP32)
+    hipLaunchKernelGGL(columns_out_kernel<float>, dim3(g), dim3(256), 0, s, (const float*)in, idx, n, k, cols, outs);
+  else
+    hipLaunchKernelGGL(columns_out_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)in, idx, n, k, cols,
+                       outs);
   return hipGetLastError();
 }
 
