@@ -170,6 +170,33 @@ def forward(g, theta: np.ndarray, X: np.ndarray) -> dict:
     return {"M": M, "pre": pre, "H": H, "a": a, "q": q, "z": z}
 
 
+def z_at(g, theta: np.ndarray, feat, vertices) -> np.ndarray:
+    """z of the given vertices only, each computed from its two-hop
+    in-neighbourhood (for spot checks on graphs too large for ``forward``).
+    ``feat(u)`` returns the 11 features of vertex u."""
+    p = unpack(theta)
+    rp = np.asarray(g.rowptrT, dtype=np.int64)
+    colT = np.asarray(g.colT, dtype=np.int64)
+
+    def mean_feat(u):
+        nb = colT[rp[u]:rp[u + 1]]
+        if len(nb) == 0:
+            return np.zeros(NF)
+        return np.sum([feat(int(w)) for w in nb], axis=0) / len(nb)
+
+    def hidden(u):
+        pre = p["W1s"] @ feat(u) + p["W1n"] @ mean_feat(u) + p["b1"]
+        return np.maximum(pre, 0.0)
+
+    out = np.empty(len(vertices))
+    for i, v in enumerate(vertices):
+        a = hidden(v) @ p["w2s"] + p["b2"][0]
+        nb = colT[rp[v]:rp[v + 1]]
+        mq = np.mean([hidden(int(u)) @ p["w2n"] for u in nb]) if len(nb) else 0.0
+        out[i] = a + mq
+    return out
+
+
 def softmax(z: np.ndarray) -> np.ndarray:
     e = np.exp(z - z.max())
     return e / e.sum()

@@ -1,0 +1,167 @@
+"""Parity at the workload sizes, in the launch configuration the benchmark
+times (autotuned plan: wave tiles, LDS hot slice, degree relabeling): the
+R-MAT scale-22 and scale-25 solves against the full FP64 oracle, the 64-set
+batched PPR on sampled columns, all 256 graphs of the many-graph workload,
+and the warm-start network on sampled vertices of the scale-22 graph."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+D = 0.85
+
+
+def _threads():
+    return min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def g22(gpu, oracle_mod):
+    from paper_2509_14211_amd import api
+    print("scale-22 graph, GPU and oracle", flush=True)
+    oracle_mod.set_threads(_threads())
+    g = api.rmat_graph(22)
+    for t in ("GrB_FP32", "GrB_FP64"):
+        gpu.GrM_autotune_pagerank(g.AT, g.outdeg, gpu.builtin(t), None)
+    og = oracle_mod.rmat_graph(22)
+    yield g, og
+    g.free()
+
+
+def test_scale22_graph_is_bit_exact(gpu, g22):
+    from paper_2509_14211_amd import api
+    g, og = g22
+    assert g.m == og.m
+    rp, col = api.csr_of(g.AT)
+    assert np.array_equal(rp.cpu().numpy(), og.rowptrT)
+    assert np.array_equal(col.cpu().numpy(), og.colT)
+    deg = api.tensor_from_vector(g.outdeg, torch.int32).cpu().numpy()
+    assert np.array_equal(deg, og.outdeg)
+
+
+def test_scale22_fp32_fused_matches_oracle(gpu, oracle_mod, g22):
+    """The headline solve: FP32 ranks with FP64 reductions to L1 1e-6."""
+    from paper_2509_14211_amd import api
+    g, og = g22
+    x, it, res = api.pagerank(g, torch.float32, D, 1e-6)
+    x = x.cpu().numpy().astype(np.float64)
+    ref = oracle_mod.pagerank(og, D, fixed_iters=it)
+    err = np.abs(x - ref.x).sum()
+    print("scale 22 fp32: %d passes, L1 error %.3e" % (it, err), flush=True)
+    assert err <= 1e-5
+    assert res <= 1e-6 and abs(res - ref.resid) <= 4 * err + 1e-7
+    assert abs(x.sum() - 1.0) <= 1e-5
+    free = oracle_mod.pagerank(og, D, tol=1e-6)
+    assert abs(it - free.iters) <= 1
+
+
+def test_scale22_fp64_fused_matches_oracle(gpu, oracle_mod, g22):
+    from paper_2509_14211_amd import api
+    g, og = g22
+    x, it, res = api.pagerank(g, torch.float64, D, 1e-9)
+    x = x.cpu().numpy()
+    ref = oracle_mod.pagerank(og, D, fixed_iters=it)
+    assert np.abs(x - ref.x).sum() / np.abs(ref.x).sum() <= 1e-12
+    assert abs(res - ref.resid) <= 4 * np.abs(x - ref.x).sum() + 1e-16
+
+
+def test_scale22_ppr_batch_sampled_columns(gpu, oracle_mod, g22):
+    """64 seed sets (sizes 1..16, seed 7) as one SpMM solve to 1e-6."""
+    g, og = g22
+    sets = [s.tolist() for s in synthetic.ppr_seed_sets(g.n, 64, seed=7)]
+    X = torch.empty(g.n * 64, dtype=torch.float32, device="cuda")
+    it, col_it, col_res = gpu.GrM_ppr_batch(X, gpu.builtin("GrB_FP32"), sets, g.AT, g.outdeg, D, 1e-6, 1000)
+    X = X.reshape(g.n, 64).cpu().numpy().astype(np.float64)
+    assert col_res.max() <= 1e-6
+    assert np.all(np.abs(X.sum(axis=0) - 1.0) <= 1e-5)
+    for q in (0, 17, 40, 63):
+        ref = oracle_mod.ppr(og, sets[q], D, fixed_iters=it)
+        assert np.abs(X[:, q] - ref.x).sum() <= 1e-5, q
+
+
+def test_scale22_warm_start_sampled_vertices(gpu, oracle_mod, g22):
+    """Walk counts of the whole graph bit-exact; z of sampled vertices
+    (small two-hop in-neighbourhoods) against the oracle's one-by-one
+    evaluation, FP32 activations."""
+    from oracle import gnn
+    from paper_2509_14211_amd import api
+    g, og = g22
+    seeds = [int(v) for v in synthetic.ppr_seed_sets(g.n, 1, seed=77)[0]]
+    rng = np.random.default_rng(3)
+    theta = (gnn.init_params(3) + 0.05 * rng.normal(size=gnn.NPARAMS)).astype(np.float32)
+    W = 1 << 14
+    net = gpu.GrM_GNN_new(gpu.builtin("GrB_FP32"), 0)
+    try:
+        gpu.GrM_GNN_set_params(net, theta)
+        gpu.GrM_gnn_features(net, g.A, g.AT, seeds, W, D, 2024)
+        gpu.GrM_gnn_forward(net, g.A, g.AT)
+        p, c = gpu.GrM_GNN_buffer(net, "counts")
+        counts = api.device_copy(p, c, torch.int32).cpu().numpy().reshape(gnn.STEPS, g.n)
+        assert np.array_equal(counts, gnn.walk_counts(og, seeds, W, D, 2024))
+        p, c = gpu.GrM_GNN_buffer(net, "z")
+        z = api.device_copy(p, c, torch.float32).cpu().numpy().astype(np.float64)
+    finally:
+        gpu.GrM_GNN_free(net)
+    X = gnn.features(og, seeds, W, D, 2024)
+    indeg = np.diff(og.rowptrT)
+    cand = [v for v in rng.choice(g.n, 4000, replace=False)
+            if indeg[v] <= 64 and indeg[og.colT[og.rowptrT[v]:og.rowptrT[v + 1]]].sum() <= 4000]
+    vs = [int(v) for v in cand[:48]] + [int(s) for s in seeds]
+    want = gnn.z_at(og, theta.astype(np.float64), lambda u: X[u], vs)
+    assert np.abs(z[vs] - want).max() <= 1e-5 * max(np.abs(want).max(), 1.0)
+
+
+def test_many_graphs_full_workload(gpu, oracle_mod):
+    """All 256 graphs (scales 10..16) in one persistent launch, each against
+    the oracle at its own pass count."""
+    from paper_2509_14211_amd import api
+    specs = synthetic.many_graph_specs(256)
+    gs = [api.rmat_graph(s, 16, seed) for s, seed in specs]
+    mg = gpu.GrM_Multigraph_new([x.AT for x in gs])
+    try:
+        off = gpu.GrM_Multigraph_offsets(mg, len(gs))
+        X = torch.empty(int(off[-1]), dtype=torch.float32, device="cuda")
+        its, res = gpu.GrM_pagerank_many(X, gpu.builtin("GrB_FP32"), mg, len(gs), D, 1e-6, 1000)
+        x = X.cpu().numpy().astype(np.float64)
+        assert np.all(res <= 1e-6)
+        for i, (s, seed) in enumerate(specs):
+            og = oracle_mod.rmat_graph(s, 16, seed)
+            ref = oracle_mod.pagerank(og, D, fixed_iters=int(its[i]))
+            assert np.abs(x[off[i]:off[i + 1]] - ref.x).sum() <= 1e-5, (i, s)
+    finally:
+        gpu.GrM_Multigraph_free(mg)
+        for x_ in gs:
+            x_.free()
+
+
+def test_scale25_fp32_fused_matches_oracle(gpu, oracle_mod):
+    """The HBM-bound size: graph bit-exact and the FP32 solve within 1e-5 L1
+    of the full FP64 oracle (about a minute of oracle work)."""
+    from paper_2509_14211_amd import api
+    oracle_mod.set_threads(_threads())
+    print("scale-25 graph on the GPU", flush=True)
+    g = api.rmat_graph(25)
+    try:
+        gpu.GrM_autotune_pagerank(g.AT, g.outdeg, gpu.builtin("GrB_FP32"), None)
+        x, it, res = api.pagerank(g, torch.float32, D, 1e-6)
+        x = x.cpu().numpy().astype(np.float64)
+        rp, col = api.csr_of(g.AT)
+        rp = rp.cpu().numpy()
+        col = col.cpu().numpy()
+        print("scale-25 graph in the oracle", flush=True)
+        og = oracle_mod.rmat_graph(25)
+        assert g.m == og.m
+        assert np.array_equal(rp, og.rowptrT) and np.array_equal(col, og.colT)
+        del rp, col
+        ref = oracle_mod.pagerank(og, D, fixed_iters=it)
+        err = np.abs(x - ref.x).sum()
+        print("scale 25 fp32: %d passes, L1 error %.3e" % (it, err), flush=True)
+        assert err <= 1e-5 and res <= 1e-6
+        assert abs(x.sum() - 1.0) <= 1e-5
+    finally:
+        g.free()

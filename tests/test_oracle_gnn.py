@@ -113,6 +113,17 @@ def test_forward_is_permutation_equivariant():
     assert np.allclose(zp[perm], z, rtol=1e-12, atol=1e-12)
 
 
+def test_z_at_matches_forward():
+    n, src, dst = synthetic.random_edges(40, 160, seed=12)
+    g = oracle.graph_from_edges(n, src, dst)
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(n, gnn.NF))
+    theta = gnn.init_params(5) + 0.05 * rng.normal(size=gnn.NPARAMS)
+    z = gnn.forward(g, theta, X)["z"]
+    vs = [0, 3, 17, 39]
+    assert np.allclose(gnn.z_at(g, theta, lambda u: X[u], vs), z[vs], rtol=1e-12, atol=1e-12)
+
+
 def test_softmax_kl_gradient_identity():
     rng = np.random.default_rng(2)
     z = rng.normal(size=9)
