@@ -175,7 +175,8 @@ def main():
     ap.add_argument("--skip-extras", action="store_true",
                     help="time only the headline fused solve (for profiling); same as --legs none")
     ap.add_argument("--legs", default="all",
-                    help="comma list of extra legs to run: blocking (also FP64), ppr, many, warm; or all / none")
+                    help="comma list of extra legs to run: blocking (also FP64), ppr, many, scale25, warm; "
+                         "or all / none")
     ap.add_argument("--traffic-kernel", default="fused_wave_kernel<float>",
                     help="kernel (name substring) whose calibrated traffic --summarize-rocprof reports")
     ap.add_argument("--summarize-rocprof", metavar="DIR", nargs="+",
@@ -185,7 +186,7 @@ def main():
         summarize_rocprof(args.summarize_rocprof, args.traffic_kernel)
         return
 
-    legs = {"blocking", "ppr", "many", "warm"} if args.legs == "all" else (
+    legs = {"blocking", "ppr", "many", "scale25", "warm"} if args.legs == "all" else (
         set() if args.legs == "none" else set(args.legs.split(",")))
     if args.skip_extras:
         legs = set()
@@ -448,6 +449,59 @@ def main():
             for x in mgs:
                 x.free()
             del Xm
+
+        # ---- the HBM-bound size: R-MAT scale 25, fused vs blocking (FP32)
+        if leg("scale25"):
+            t0 = time.perf_counter()
+            g25 = api.rmat_graph(25)
+            torch.cuda.synchronize()
+            setup25 = time.perf_counter() - t0
+            n25, m25 = g25.n, g25.m
+            f32 = grb.builtin("GrB_FP32")
+            cfg25, _ = grb.GrM_autotune_pagerank(g25.AT, g25.outdeg, f32, os.environ.get("NBGRB_TUNE_CACHE"))
+
+            def solve25():
+                return api.pagerank(g25, torch.float32, DAMPING, args.tol, 1000, grb.GrM_DANGLING_UNIFORM, None,
+                                    args.check_every)
+
+            def time25(reps):
+                solve25()
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    _, it_, _ = solve25()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / reps, it_
+
+            ms25, it25 = time25(3)
+            t = []
+            for k in (4, 20, 4, 20):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                api.pagerank(g25, torch.float32, DAMPING, 0.0, k, grb.GrM_DANGLING_UNIFORM, None, k)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t.append(e0.elapsed_time(e1))
+            us25 = ((t[1] - t[0]) + (t[3] - t[2])) / 2 * 1e3 / 16
+            bpp25 = fused_bytes_per_pass(n25, m25, 4)
+            grb.GrM_set_mode(grb.GrB_BLOCKING)
+            msb25, itb25 = time25(2)
+            grb.GrM_set_mode(grb.GrB_NONBLOCKING)
+            g25.free()
+            log("scale 25: n %d m %d (setup %.1fs); fused %d passes %.2f ms (%.1f GTEPS), pass %.1f us = %.1f GB/s; "
+                "blocking %.2f ms" % (n25, m25, setup25, it25, ms25, m25 * it25 / (ms25 * 1e-3) / 1e9, us25,
+                                      bpp25 / (us25 * 1e-6) / 1e9, msb25))
+            out["scale25"] = {"n": n25, "m": m25, "plan": cfg25, "iterations": it25, "ms_per_solve": round(ms25, 3),
+                              "gteps": round(m25 * it25 / (ms25 * 1e-3) / 1e9, 2),
+                              "pass_us": round(us25, 2), "bytes_per_pass": bpp25,
+                              "achieved_gbs": round(bpp25 / (us25 * 1e-6) / 1e9, 1),
+                              "frac": round(bpp25 / (us25 * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                              "blocking_ms_per_solve": round(msb25, 3), "blocking_iterations": itb25,
+                              "fused_vs_unfused_speedup": round(msb25 / ms25, 3)}
 
         # ---- learned warm start (reduced size): train on scale-20 graphs,
         # then warm vs teleport start on the headline graph, both to tol;
