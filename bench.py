@@ -175,7 +175,7 @@ def main():
     ap.add_argument("--skip-extras", action="store_true",
                     help="time only the headline fused solve (for profiling); same as --legs none")
     ap.add_argument("--legs", default="all",
-                    help="comma list of extra legs to run: blocking (also FP64), ppr, many, scale25, warm; "
+                    help="comma list of extra legs to run: blocking (also FP64), ppr, many, fusion, scale25, warm; "
                          "or all / none")
     ap.add_argument("--traffic-kernel", default="fused_wave_kernel<float>",
                     help="kernel (name substring) whose calibrated traffic --summarize-rocprof reports")
@@ -186,7 +186,7 @@ def main():
         summarize_rocprof(args.summarize_rocprof, args.traffic_kernel)
         return
 
-    legs = {"blocking", "ppr", "many", "scale25", "warm"} if args.legs == "all" else (
+    legs = {"blocking", "ppr", "many", "fusion", "scale25", "warm"} if args.legs == "all" else (
         set() if args.legs == "none" else set(args.legs.split(",")))
     if args.skip_extras:
         legs = set()
@@ -449,6 +449,58 @@ def main():
             for x in mgs:
                 x.free()
             del Xm
+
+        # ---- generated elementwise fusion: w = |x .* (y + 1) - 2 z| / 3 over
+        # 2^26 FP32 entries, one generated kernel vs five per-op kernels
+        if leg("fusion"):
+            ne = 1 << 26
+            f = grb.builtin
+            xs = [torch.rand(ne, device="cuda") for _ in range(3)]
+            vx, vy, vz = (api.vector_from_tensor(t_) for t_ in xs)
+            w = grb.GrB_Vector_new(f("GrB_FP32"), ne)
+
+            def chain():
+                t1 = grb.GrB_Vector_new(f("GrB_FP32"), ne)
+                grb.GrB_Vector_apply_BinaryOp2nd_FP64(t1, None, None, f("GrB_PLUS_FP32"), vy, 1.0)
+                t2 = grb.GrB_Vector_new(f("GrB_FP32"), ne)
+                grb.GrB_Vector_eWiseMult_BinaryOp(t2, None, None, f("GrB_TIMES_FP32"), vx, t1)
+                t3 = grb.GrB_Vector_new(f("GrB_FP32"), ne)
+                grb.GrB_Vector_apply_BinaryOp1st_FP64(t3, None, None, f("GrB_TIMES_FP32"), 2.0, vz)
+                t4 = grb.GrB_Vector_new(f("GrB_FP32"), ne)
+                grb.GrB_Vector_eWiseAdd_BinaryOp(t4, None, None, f("GrM_ABSDIFF_FP32"), t2, t3)
+                grb.GrB_Vector_apply_BinaryOp2nd_FP64(w, None, None, f("GrB_DIV_FP32"), t4, 3.0)
+                for h in (t1, t2, t3, t4):
+                    grb.GrB_Vector_free(h)
+                grb.GrB_Vector_wait(w)
+
+            res_f = {}
+            for level in (1, 0):
+                grb.GrM_set_fusion(level)
+                t0 = time.perf_counter()
+                chain()
+                torch.cuda.synchronize()
+                first_s = time.perf_counter() - t0
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(10):
+                    chain()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                res_f[level] = (e0.elapsed_time(e1) / 10, first_s)
+            grb.GrM_set_fusion(1)
+            for h in (vx, vy, vz, w):
+                grb.GrB_Vector_free(h)
+            del xs
+            fused_b, perop_b = 16 * ne, 48 * ne
+            log("elementwise chain over %d: generated %.3f ms (%.1f GB/s), per-op %.3f ms; first call %.2fs" % (
+                ne, res_f[1][0], fused_b / (res_f[1][0] * 1e-3) / 1e9, res_f[0][0], res_f[1][1]))
+            out["ewise_fusion"] = {"n": ne, "ops": 5, "generated_ms": round(res_f[1][0], 4),
+                                   "per_op_ms": round(res_f[0][0], 4),
+                                   "speedup": round(res_f[0][0] / res_f[1][0], 2),
+                                   "generated_gbs": round(fused_b / (res_f[1][0] * 1e-3) / 1e9, 1),
+                                   "per_op_gbs": round(perop_b / (res_f[0][0] * 1e-3) / 1e9, 1),
+                                   "first_call_s": round(res_f[1][1], 3)}
 
         # ---- the HBM-bound size: R-MAT scale 25, fused vs blocking (FP32)
         if leg("scale25"):

@@ -183,9 +183,28 @@ typedef struct {
   int64_t plan_misses;
   int64_t elided_nodes;
   int64_t forced_waits;
+  int64_t ewise_fused;      /* generated elementwise-tree launches */
+  int64_t ewise_ops;        /* operations those launches covered */
+  int64_t jit_compiles;     /* generated kernels compiled */
+  int64_t jit_disk_hits;    /* ... loaded from the code cache directory */
+  int64_t jit_memory_hits;  /* ... found already loaded */
 } GrM_Stats;
 GrB_Info GrM_get_stats(GrM_Stats *stats);
 GrB_Info GrM_reset_stats(void);
+
+/* Nonblocking fusion level: 0 fuses only the PageRank-iteration pattern;
+ * 1 (default) also runs every needed elementwise result together with the
+ * pending elementwise intermediates below it (eWiseAdd, eWiseMult, apply
+ * with or without a bound scalar; FP32/FP64 results, FP32/FP64/INT32
+ * inputs; up to 24 operations, 12 input vectors and 6 scalars) as one
+ * kernel generated for the tree's signature.  Generated kernels are
+ * compiled with hipRTC once per process and their code objects kept in the
+ * directory NBGRB_CODE_CACHE (default $HOME/.cache/nbgrb), keyed by the
+ * source they were compiled from.  Results equal the per-operation
+ * kernels' bit for bit. */
+GrB_Info GrM_set_fusion(int level);
+/* Unload every generated kernel of this process (the directory stays). */
+GrB_Info GrM_code_cache_clear(void);
 
 /* ------------------------------------------------------------------------
  * Scalars.  Values live on the device as FP64 whatever the declared type.

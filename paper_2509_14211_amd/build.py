@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnbgrb.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "graph_build.hip", "runtime.hip", "abi.hip", "autotune.hip", "spmm.hip", "many.hip", "gnn.hip"]
+SOURCES = ["kernels.hip", "graph_build.hip", "runtime.hip", "abi.hip", "autotune.hip", "spmm.hip", "many.hip", "gnn.hip", "jit.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -47,7 +47,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lhiprtc"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))

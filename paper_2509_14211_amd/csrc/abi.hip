@@ -364,6 +364,28 @@ GrB_Info GrM_get_stats(GrM_Stats* s) {
   s->plan_misses = t.plan_misses;
   s->elided_nodes = t.elided;
   s->forced_waits = t.waits;
+  s->ewise_fused = t.ewise_fused;
+  s->ewise_ops = t.ewise_ops;
+  s->jit_compiles = t.jit_compiles;
+  s->jit_disk_hits = t.jit_disk_hits;
+  s->jit_memory_hits = t.jit_memory_hits;
+  API_END
+}
+
+GrB_Info GrM_set_fusion(int level) {
+  API_BEGIN
+  require_init();
+  if (level < 0 || level > 1) fail(GrB_INVALID_VALUE, "fusion level must be 0 or 1");
+  force_all();
+  ctx().fusion = level;
+  API_END
+}
+
+GrB_Info GrM_code_cache_clear(void) {
+  API_BEGIN
+  require_init();
+  hip_check(hipStreamSynchronize(ctx().stream), "sync");
+  jit_clear();
   API_END
 }
 

@@ -86,8 +86,9 @@ __device__ __forceinline__ void store_as(void* p, int type, int64_t i, T v) {
   }
 }
 
+// alpha * s + beta with one rounding (generated kernels use the same form).
 __device__ __forceinline__ double scalar_value(const ScalarArg& s) {
-  return s.dev ? s.alpha * (*s.dev) + s.beta : s.beta;
+  return s.dev ? fma(s.alpha, *s.dev, s.beta) : s.beta;
 }
 
 template <typename T>

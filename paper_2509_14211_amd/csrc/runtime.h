@@ -199,6 +199,9 @@ namespace nbgrb {
 
 struct Stats {
   int64_t kernels = 0, fused = 0, plan_hits = 0, plan_misses = 0, elided = 0, waits = 0;
+  int64_t ewise_fused = 0;   // generated elementwise-tree launches
+  int64_t ewise_ops = 0;     // operations they covered
+  int64_t jit_compiles = 0, jit_disk_hits = 0, jit_memory_hits = 0;
 };
 
 struct Ctx {
@@ -224,6 +227,9 @@ struct Ctx {
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   std::vector<hipEvent_t> event_pool;
+  // 0: only the PageRank pattern is fused; 1: pending elementwise trees are
+  // also fused into generated kernels
+  int fusion = 1;
   // plan configuration override chosen by the autotuner (per matrix id)
   std::map<std::pair<uint64_t, int>, PlanConfig> tuned;
 };
@@ -260,6 +266,12 @@ void cache_release(void* p, void* ctx);
 // s = A (+.second) w over the pattern of A (dense FP32/FP64 w and s of the
 // same type), run now on the context stream with the matrix's plan.
 void mxv_now(const MatP& A, int type, const void* w, void* s_out);
+
+// Kernel `name` of a generated HIP source, compiled for the device once per
+// process (and cached on disk across processes).
+hipFunction_t jit_kernel(const std::string& key, const std::string& source, const char* name);
+// Unload every generated module (the disk cache stays).
+void jit_clear();
 
 // Degree-renumbered copy of a square pattern (built once, then cached).
 std::shared_ptr<Relabeled> get_relabeled(const MatP& A);

@@ -9,14 +9,17 @@
 // the rest, the matcher looks for the PageRank-iteration shape
 //     mxv(A, w)  ->  + teleport  ->  { |x - r| -> sum ,  masked sum }
 // and runs it as one fused pass; intermediates that only feed the pass are
-// never written.  Everything else runs one kernel per node, which is also
-// exactly what blocking mode does at every call.
+// never written.  A needed elementwise result and the elementwise
+// intermediates below it run as one generated kernel.  Everything else runs
+// one kernel per node, which is also exactly what blocking mode does at
+// every call.
 #include "runtime.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <sstream>
 
 namespace nbgrb {
 
@@ -688,6 +691,216 @@ bool match_pr(const NodeP& M, const Consumers& cons, PRMatch& m) {
 
 }  // namespace
 
+// ------------------------------------------------------------ generated elementwise fusion
+//
+// A pending elementwise operation whose result is needed, together with the
+// pending elementwise intermediates below it that nothing else uses, runs as
+// one generated kernel: the tree is printed as HIP source (one statement per
+// operation, each result rounded to its node's type exactly as the per-op
+// kernel would store it, no contraction), compiled once per signature and
+// launched over the vector.  Leaves are the vectors and scalars the tree
+// reads.
+
+namespace {
+
+constexpr int EW_MAX_LEAVES = 12, EW_MAX_SCALARS = 6, EW_MAX_OPS = 24;
+
+// Argument block of every generated elementwise kernel (the generated
+// source declares the same struct).
+struct EwArgs {
+  const void* in[EW_MAX_LEAVES];
+  double iso[EW_MAX_LEAVES];
+  const double* sdev[EW_MAX_SCALARS];
+  double salpha[EW_MAX_SCALARS];
+  double sbeta[EW_MAX_SCALARS];
+  const int* active;
+  void* out;
+  long long n;
+};
+
+bool ew_kind(const Node& n) {
+  return (n.kind == N_EWISE || n.kind == N_APPLY_U || n.kind == N_APPLY_B1 || n.kind == N_APPLY_B2 ||
+          n.kind == N_APPLY_B2S) &&
+         (n.type == T_FP32 || n.type == T_FP64);
+}
+
+const char* ctype(int t) { return t == T_FP32 ? "float" : t == T_FP64 ? "double" : "int"; }
+
+struct EwTree {
+  std::vector<NodeP> ops;      // post-order, root last
+  std::vector<NodeP> leaves;   // vectors read
+  std::vector<NodeP> scalars;  // scalar operands
+  std::map<const Node*, std::string> var;
+  bool ok = true;
+};
+
+// Add x (an operation of the tree) and, below it, the pending elementwise
+// intermediates used only by it; everything else becomes a leaf.
+void ew_collect(const NodeP& x, const Consumers& cons, EwTree& t) {
+  auto operand = [&](const NodeP& v) {
+    if (!t.ok || t.var.count(v.get())) return;
+    const bool inner = !v->done && v->handles == 0 && ew_kind(*v) && v->n == x->n &&
+                       only_consumer(cons, v.get(), x.get());
+    if (inner) {
+      ew_collect(v, cons, t);
+      return;
+    }
+    if (v->type != T_FP32 && v->type != T_FP64 && v->type != T_INT32) {
+      t.ok = false;
+      return;
+    }
+    t.var[v.get()] = "l" + std::to_string(t.leaves.size());
+    t.leaves.push_back(v);
+  };
+  operand(x->a);
+  if (x->kind == N_EWISE) operand(x->b);
+  if (x->kind == N_APPLY_B2S && !t.var.count(x->s.get())) {
+    t.var[x->s.get()] = "s" + std::to_string(t.scalars.size());
+    t.scalars.push_back(x->s);
+  }
+  t.var[x.get()] = "v" + std::to_string(t.ops.size());
+  t.ops.push_back(x);
+  if ((int)t.leaves.size() > EW_MAX_LEAVES || (int)t.scalars.size() > EW_MAX_SCALARS ||
+      (int)t.ops.size() > EW_MAX_OPS)
+    t.ok = false;
+}
+
+std::string binop_expr(int op, const std::string& x, const std::string& y) {
+  switch (op) {
+    case B_PLUS: return "(" + x + " + " + y + ")";
+    case B_MINUS: return "(" + x + " - " + y + ")";
+    case B_TIMES: return "(" + x + " * " + y + ")";
+    case B_DIV: return "(" + x + " / " + y + ")";
+    case B_MAX: return "(" + x + " > " + y + " ? " + x + " : " + y + ")";
+    case B_MIN: return "(" + x + " < " + y + " ? " + x + " : " + y + ")";
+    case B_FIRST: return x;
+    case B_SECOND: return y;
+    default: return "fabs(" + x + " - " + y + ")";  // B_ABSDIFF
+  }
+}
+
+std::string unop_expr(int op, const std::string& T, const std::string& x) {
+  switch (op) {
+    case U_IDENTITY: return x;
+    case U_ABS: return "fabs(" + x + ")";
+    case U_AINV: return "(-" + x + ")";
+    case U_MINV: return "((" + T + ")1 / " + x + ")";
+    default: return "(" + x + " != (" + T + ")0 ? (" + T + ")1 / " + x + " : (" + T + ")0)";  // U_MINV_OR_ZERO
+  }
+}
+
+// HIP source of the tree; operands of each operation are first converted
+// to its type, as the per-op kernel converts what it loads.
+std::string ew_source(const EwTree& t) {
+  std::ostringstream s;
+  s << "struct EwArgs { const void* in[" << EW_MAX_LEAVES << "]; double iso[" << EW_MAX_LEAVES
+    << "]; const double* sdev[" << EW_MAX_SCALARS << "]; double salpha[" << EW_MAX_SCALARS << "]; double sbeta["
+    << EW_MAX_SCALARS << "]; const int* active; void* out; long long n; };\n";
+  s << "__device__ __forceinline__ void elem(const EwArgs& a, long long i";
+  for (size_t j = 0; j < t.scalars.size(); ++j) s << ", double s" << j;
+  s << ") {\n";
+  for (size_t j = 0; j < t.leaves.size(); ++j) {
+    const Node& v = *t.leaves[j];
+    if (v.done && v.iso)
+      s << "  const double l" << j << " = a.iso[" << j << "];\n";
+    else
+      s << "  const " << ctype(v.type) << " l" << j << " = ((const " << ctype(v.type) << "*)a.in[" << j
+        << "])[i];\n";
+  }
+  for (const NodeP& o : t.ops) {
+    const std::string T = ctype(o->type);
+    auto cv = [&](const NodeP& x) { return "(" + T + ")" + t.var.at(x.get()); };
+    std::string e;
+    switch (o->kind) {
+      case N_EWISE: e = binop_expr(o->op, cv(o->a), cv(o->b)); break;
+      case N_APPLY_U: e = unop_expr(o->op, T, cv(o->a)); break;
+      case N_APPLY_B1: {
+        std::ostringstream k;
+        k.precision(17);
+        k << "(" << T << ")" << std::scientific << o->k;
+        e = binop_expr(o->op, k.str(), cv(o->a));
+        break;
+      }
+      case N_APPLY_B2: {
+        std::ostringstream k;
+        k.precision(17);
+        k << "(" << T << ")" << std::scientific << o->k;
+        e = binop_expr(o->op, cv(o->a), k.str());
+        break;
+      }
+      default: e = binop_expr(o->op, cv(o->a), "(" + T + ")" + t.var.at(o->s.get())); break;  // N_APPLY_B2S
+    }
+    s << "  const " << T << " " << t.var.at(o.get()) << " = " << e << ";\n";
+  }
+  const NodeP& root = t.ops.back();
+  s << "  ((" << ctype(root->type) << "*)a.out)[i] = " << t.var.at(root.get()) << ";\n}\n";
+  s << "extern \"C\" __global__ void __launch_bounds__(256) nbgrb_ewise(EwArgs a) {\n";
+  s << "  if (a.active && *a.active == 0) return;\n";
+  for (size_t j = 0; j < t.scalars.size(); ++j)
+    s << "  const double s" << j << " = a.sdev[" << j << "] ? __builtin_fma(a.salpha[" << j << "], *a.sdev[" << j
+      << "], a.sbeta[" << j << "]) : a.sbeta[" << j << "];\n";
+  std::string sargs;
+  for (size_t j = 0; j < t.scalars.size(); ++j) sargs += ", s" + std::to_string(j);
+  s << "  const long long stride = (long long)gridDim.x * 256;\n";
+  s << "  long long i = (long long)blockIdx.x * 256 + threadIdx.x;\n";
+  s << "  for (; i + 3 * stride < a.n; i += 4 * stride) {\n";
+  for (int u = 0; u < 4; ++u) s << "    elem(a, i + " << u << " * stride" << sargs << ");\n";
+  s << "  }\n  for (; i < a.n; i += stride) elem(a, i" << sargs << ");\n}\n";
+  return s.str();
+}
+
+void run_ew_tree(EwTree& t) {
+  Ctx& c = g_ctx;
+  const NodeP root = t.ops.back();
+  for (const NodeP& v : t.leaves) ensure_done(v);
+  EwArgs args{};
+  for (size_t j = 0; j < t.leaves.size(); ++j) {
+    const Node& v = *t.leaves[j];
+    args.in[j] = v.iso ? nullptr : v.buf->p;
+    args.iso[j] = v.iso ? v.iso_val : 0.0;
+  }
+  for (size_t j = 0; j < t.scalars.size(); ++j) {
+    const ScalarArg sa = scalar_arg(t.scalars[j]);
+    args.sdev[j] = sa.dev;
+    args.salpha[j] = sa.alpha;
+    args.sbeta[j] = sa.beta;
+  }
+  const std::string src = ew_source(t);
+  hipFunction_t fn = jit_kernel(src, src, "nbgrb_ewise");
+  BufP out = vec_storage(*root);
+  args.active = c.guard ? &c.guard->active : nullptr;
+  args.out = out->p;
+  args.n = root->n;
+  if (root->n > 0) {
+    int64_t g = (root->n + 1023) / 1024;
+    if (g > 16384) g = 16384;
+    void* params[] = {&args};
+    hip_check(hipModuleLaunchKernel(fn, (unsigned)g, 1, 1, 256, 1, 1, 0, c.stream, params, nullptr),
+              "generated elementwise kernel");
+    launch_mark(false);
+  }
+  c.stats.ewise_fused++;
+  c.stats.ewise_ops += (int64_t)t.ops.size();
+  for (const NodeP& o : t.ops) {
+    o->done = true;
+    if (o != root) release_inputs(*o);
+  }
+  root->buf = out;
+  release_inputs(*root);
+}
+
+// Fuse the elementwise tree rooted at r if it has two operations or more.
+bool try_ew_fusion(const NodeP& r, const Consumers& cons) {
+  if (g_ctx.fusion < 1 || r->done || !ew_kind(*r)) return false;
+  EwTree t;
+  ew_collect(r, cons, t);
+  if (!t.ok || t.ops.size() < 2) return false;
+  run_ew_tree(t);
+  return true;
+}
+
+}  // namespace
+
 // Run the matched group as one fused pass.
 static void run_pr_group(PRMatch& m, const Consumers& cons) {
   Ctx& c = g_ctx;
@@ -822,6 +1035,11 @@ void force_all() {
     // a consumer needs it, is absorbed by a fused group, or (a scalar
     // affine) is folded into its consumer -- or it is never needed.
     if (p->handles == 0) continue;
+    if (try_ew_fusion(p, cons)) continue;
+    // a reduction of an elementwise tree: the tree as one kernel first
+    if ((p->kind == N_REDUCE || p->kind == N_REDUCE_MASK) && p->a && !p->a->done && p->a->handles == 0 &&
+        only_consumer(cons, p->a.get(), p.get()))
+      try_ew_fusion(p->a, cons);
     exec_node(p);
   }
 }

@@ -69,7 +69,9 @@ class GrM_PlanConfig(ctypes.Structure):
 
 class GrM_Stats(ctypes.Structure):
     _fields_ = [("kernels", i64), ("fused_launches", i64), ("plan_hits", i64),
-                ("plan_misses", i64), ("elided_nodes", i64), ("forced_waits", i64)]
+                ("plan_misses", i64), ("elided_nodes", i64), ("forced_waits", i64),
+                ("ewise_fused", i64), ("ewise_ops", i64), ("jit_compiles", i64),
+                ("jit_disk_hits", i64), ("jit_memory_hits", i64)]
 
 
 # name -> (restype, argtypes).  All return GrB_Info unless noted.
@@ -83,6 +85,8 @@ _FUNCS = {
     "GrM_fail_allocation_after": [i64],
     "GrM_get_stats": [ctypes.POINTER(GrM_Stats)],
     "GrM_reset_stats": [],
+    "GrM_set_fusion": [i32],
+    "GrM_code_cache_clear": [],
     "GrB_Scalar_new": [PV, vp],
     "GrB_Scalar_free": [PV],
     "GrB_Scalar_setElement_FP64": [vp, dbl],
@@ -266,6 +270,14 @@ def GrM_get_stats() -> dict:
 
 def GrM_reset_stats():
     _call("GrM_reset_stats")
+
+
+def GrM_set_fusion(level: int):
+    _call("GrM_set_fusion", level)
+
+
+def GrM_code_cache_clear():
+    _call("GrM_code_cache_clear")
 
 
 def GrM_error() -> str:
