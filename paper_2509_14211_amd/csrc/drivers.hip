@@ -1,0 +1,857 @@
+// C entry points of the iterative drivers (declared in include/nbgrb.h):
+// PageRank and personalised PageRank as recorded GraphBLAS loops
+// (GrM_pagerank, GrM_ppr), the batched and streamed personalised solvers
+// over the SpMM pass (GrM_ppr_batch, GrM_ppr_stream), and many graphs in one
+// persistent launch (GrM_Multigraph_*, GrM_pagerank_many).
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "abi_util.h"
+
+using namespace nbgrb;
+
+extern "C" {
+
+// ------------------------------------------------------------ PageRank
+
+static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, GrB_Vector outdeg,
+                              GrB_Vector teleport, double damping, double tol, int itermax,
+                              GrM_Dangling dangling, GrB_Vector x0, int check_every) {
+  Ctx& c = ctx();
+  GuardDev* saved_guard = c.guard;
+  BufP gbuf;
+  API_BEGIN
+  require_init();
+  GB_Vector_opaque* ro = vec(r, "r");
+  need(iters, "iters");
+  need(resid, "resid");
+  GB_Matrix_opaque* ao = mat(AT, "AT");
+  GB_Vector_opaque* dego = vec(outdeg, "outdeg");
+  GB_Vector_opaque* xo = x0 ? vec(x0, "x0") : nullptr;
+  GB_Vector_opaque* vo = teleport ? vec(teleport, "teleport") : nullptr;
+  float_type(ro->type, "r");
+  const int T = ro->type;
+  const int64_t n = ao->nrows;
+  if (ao->ncols != n || ro->n != n || dego->n != n || (xo && xo->n != n) || (vo && vo->n != n))
+    fail(GrB_DIMENSION_MISMATCH, "pagerank dimensions");
+  if (vo && vo->type != T) fail(GrB_DOMAIN_MISMATCH, "teleport vector must have r's type");
+  if (dangling != GrM_DANGLING_DROP && dangling != GrM_DANGLING_UNIFORM) fail(GrB_INVALID_VALUE, "dangling mode");
+  if (check_every < 1 || itermax < 0 || !(damping >= 0.0 && damping < 1.0) || std::isnan(tol))
+    fail(GrB_INVALID_VALUE, "pagerank parameters");
+  if (c.guard) fail(GrB_INVALID_VALUE, "an iterative driver is already running");
+  const bool uniform = dangling == GrM_DANGLING_UNIFORM;
+  const double tele = (1.0 - damping) / (double)n;
+
+  // Execution matrix: AT itself, or its copy with vertices renumbered by
+  // decreasing out-degree (the teleport vector is uniform, so the method is
+  // unchanged; vectors are permuted in and out).
+  const PlanConfig pc = default_plan_config(ao->data, T);
+  std::shared_ptr<Relabeled> rl;
+  GB_Matrix_opaque A_exec{MAGIC_MAT, ao->type, n, n, ao->data};
+  if (pc.relabel) {
+    rl = get_relabeled(ao->data);
+    A_exec.data = rl->A;
+    PlanConfig sub = pc;
+    sub.relabel = 0;
+    c.tuned[{rl->A->id, T}] = sub;
+  }
+
+  GB_Vector_opaque deg_exec{MAGIC_VEC, dego->type, n, nullptr};
+  set_vec(&deg_exec, rl ? permuted(dego->node, rl->order) : dego->node);
+
+  // d = damping ./ outdeg (0 where outdeg = 0)
+  GB_Vector_opaque dinv{MAGIC_VEC, T, n, nullptr};
+  rec_unop(&dinv, U_MINV_OR_ZERO, &deg_exec);
+  rec_bind(&dinv, B_TIMES, &dinv, damping, true);
+  set_vec(&deg_exec, nullptr);
+  materialize(dinv.node);
+  store_if_iso(dinv.node);
+
+  // personalised teleport distribution (permuted like every vector)
+  GB_Vector_opaque v{MAGIC_VEC, T, n, nullptr};
+  if (vo) {
+    set_vec(&v, rl ? permuted(vo->node, rl->order) : vo->node);
+    materialize(v.node);
+    store_if_iso(v.node);
+  }
+
+  GB_Vector_opaque x{MAGIC_VEC, T, n, nullptr};
+  if (!xo && vo) {
+    set_vec(&x, v.node);
+  } else if (xo) {
+    if (xo->type == T)
+      set_vec(&x, xo->node);
+    else
+      rec_unop(&x, U_IDENTITY, xo);
+    materialize(x.node);
+    if (rl) set_vec(&x, permuted(x.node, rl->order));
+  } else {
+    set_vec(&x, iso_node(T, n, 1.0 / (double)n));
+  }
+  materialize(x.node);
+  store_if_iso(x.node);
+
+  GB_Scalar_opaque D{MAGIC_SCA, T_FP64, nullptr};
+  if (uniform) rec_reduce(&D, &x, &dinv, true, false);
+
+  gbuf = dev_alloc(sizeof(GuardDev));
+  hip_check(launch_guard_init((GuardDev*)gbuf->p, (1.0 > tol && itermax > 0) ? 1 : 0, tol, itermax, c.stream),
+            "guard init");
+  launch_mark(false);
+  c.guard = (GuardDev*)gbuf->p;
+
+  std::vector<NodeP> hist{x.node};
+  int64_t base = 0;
+  GuardDev hg{};
+  int batch = check_every;
+  for (;;) {
+    for (int j = 0; j < batch; ++j) {
+      GB_Vector_opaque w{MAGIC_VEC, T, n, nullptr}, s{MAGIC_VEC, T, n, nullptr};
+      GB_Vector_opaque rn{MAGIC_VEC, T, n, nullptr}, t{MAGIC_VEC, T, n, nullptr};
+      GB_Scalar_opaque cs{MAGIC_SCA, T_FP64, nullptr}, rho{MAGIC_SCA, T_FP64, nullptr};
+      GB_Scalar_opaque Dn{MAGIC_SCA, T_FP64, nullptr};
+      rec_ewise(&w, B_TIMES, &x, &dinv);            // w = x .* d
+      rec_mxv(&s, &A_exec, &w);                     // s = AT (+.second) w
+      GB_Vector_opaque vt{MAGIC_VEC, T, n, nullptr};
+      if (vo) {                                     // r = s + v .* c
+        if (uniform) {                              //   c = (1-d) + d D
+          rec_affine(&cs, damping, &D, 1.0 - damping);
+          rec_bind_scalar(&vt, B_TIMES, &v, &cs);
+        } else {                                    //   c = 1-d
+          rec_bind(&vt, B_TIMES, &v, 1.0 - damping, false);
+        }
+        rec_ewise(&rn, B_PLUS, &s, &vt);
+        set_vec(&vt, nullptr);
+      } else if (uniform) {                         // r = c + s, c = (1-d)/n + d D/n
+        rec_affine(&cs, damping / (double)n, &D, tele);
+        rec_bind_scalar(&rn, B_PLUS, &s, &cs);
+      } else {
+        rec_bind(&rn, B_PLUS, &s, tele, false);
+      }
+      rec_ewise(&t, B_ABSDIFF, &x, &rn);            // t = |x - r|
+      rec_reduce(&rho, &t, nullptr, false, true);   // rho = sum t  (advances the guard)
+      if (uniform) rec_reduce(&Dn, &rn, &dinv, true, false);  // D = sum r(outdeg = 0)
+      // only r, rho and D stay reachable: w, s, t and c become intermediates
+      set_vec(&w, nullptr);
+      set_vec(&s, nullptr);
+      set_vec(&t, nullptr);
+      set_sca(&cs, nullptr);
+      materialize(rn.node);
+      set_vec(&x, rn.node);
+      if (uniform) set_sca(&D, Dn.node);
+      hist.push_back(rn.node);
+      set_vec(&rn, nullptr);
+      set_sca(&rho, nullptr);
+      set_sca(&Dn, nullptr);
+    }
+    hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    if (!hg.active) break;
+    base += (int64_t)hist.size() - 1;
+    NodeP last = hist.back();
+    hist.assign(1, last);
+    // The residual contracts about geometrically: predict the passes still
+    // needed from the last two residuals (at least 1, at most what itermax
+    // allows); an underestimate only costs one more check.
+    int next = check_every;
+    if (hg.rho_prev > 0.0 && hg.rho > 0.0 && hg.rho < hg.rho_prev && tol > 0.0) {
+      const double q = hg.rho / hg.rho_prev;
+      const double need = std::log(tol / hg.rho) / std::log(q);
+      if (need > 0.0 && need < 1e6) next = (int)std::ceil(need);
+      if (next < 1) next = 1;
+    }
+    if (next > itermax - hg.iters) next = itermax - hg.iters;
+    if (next < 1) next = 1;
+    batch = next;
+  }
+  const int64_t idx = (int64_t)hg.iters - base;
+  if (idx < 0 || idx >= (int64_t)hist.size()) fail(GrB_PANIC, "loop guard out of step");
+  c.guard = saved_guard;
+  NodeP result = hist[(size_t)idx];
+  set_vec(ro, rl ? permuted(result, rl->inv) : result);
+  hist.clear();
+  set_vec(&x, nullptr);
+  set_vec(&v, nullptr);
+  set_vec(&dinv, nullptr);
+  set_sca(&D, nullptr);
+  *iters = hg.iters;
+  *resid = hg.rho;
+  }
+  catch (const GrbError& e) {
+    c.guard = saved_guard;
+    api_error() = e.msg;
+    return e.info;
+  }
+  catch (const std::exception& e) {
+    c.guard = saved_guard;
+    api_error() = e.what();
+    return GrB_PANIC;
+  }
+  return GrB_SUCCESS;
+}
+
+GrB_Info GrM_pagerank(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, GrB_Vector outdeg, double damping,
+                      double tol, int itermax, GrM_Dangling dangling, GrB_Vector x0, int check_every) {
+  return pagerank_impl(r, iters, resid, AT, outdeg, nullptr, damping, tol, itermax, dangling, x0, check_every);
+}
+
+GrB_Info GrM_ppr(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, GrB_Vector outdeg, GrB_Vector teleport,
+                 double damping, double tol, int itermax, GrM_Dangling dangling, GrB_Vector x0, int check_every) {
+  if (!teleport) {
+    api_error() = "teleport is NULL";
+    return GrB_NULL_POINTER;
+  }
+  return pagerank_impl(r, iters, resid, AT, outdeg, teleport, damping, tol, itermax, dangling, x0, check_every);
+}
+
+// ------------------------------------------------------------ batched PPR
+
+namespace {
+
+struct PprSeed {
+  int v, c;
+  double w;
+};
+
+// Seed sets seed_vtx[seed_ptr[q] : seed_ptr[q+1]], q < nsets: non-empty,
+// distinct vertices in [0, n).
+void check_seed_sets(int nsets, const int32_t* seed_ptr, const int32_t* seed_vtx, int64_t n) {
+  need(seed_ptr, "seed_ptr");
+  need(seed_vtx, "seed_vtx");
+  if (seed_ptr[0] != 0) fail(GrB_INVALID_VALUE, "seed_ptr[0] must be 0");
+  for (int q = 0; q < nsets; ++q)
+    if (seed_ptr[q + 1] <= seed_ptr[q]) fail(GrB_INVALID_VALUE, "every seed set must be non-empty");
+  for (int q = 0; q < nsets; ++q) {
+    std::vector<int> s(seed_vtx + seed_ptr[q], seed_vtx + seed_ptr[q + 1]);
+    std::sort(s.begin(), s.end());
+    for (size_t i = 0; i < s.size(); ++i) {
+      if (s[i] < 0 || s[i] >= n) fail(GrB_INDEX_OUT_OF_BOUNDS, "seed vertex out of range");
+      if (i > 0 && s[i] == s[i - 1]) fail(GrB_INVALID_VALUE, "repeated seed vertex in a set");
+    }
+  }
+}
+
+// Device state of k personalised PageRank columns iterated together by the
+// SpMM pass: the execution matrix (degree-renumbered copy when the plan
+// asks for it), its wave tile plan, d = damping ./ outdeg, the two
+// alternating n x k iterate / pre-scaled buffers, the per-column FP64
+// residual and dangling mass, and the vertex-sorted seed table.
+struct PprColumns {
+  int64_t n = 0;
+  int T = T_FP32, k = 0;
+  std::shared_ptr<Relabeled> rl;
+  MatP A_exec;
+  std::vector<int> inv_host;
+  std::shared_ptr<Plan> plan;
+  GB_Vector_opaque dinv{MAGIC_VEC, T_FP32, 0, nullptr};
+  size_t vbytes = 0;
+  BufP Xb[2], Wb[2], Db[2], rho, hit, hub_sum, hub_cnt, hub_red, wg_part, ticket, gbuf, tile_seed, sv, sc, sw;
+  SpmmArgs a{};
+  int grid = 0;
+  bool uniform = true;
+
+  ~PprColumns() { set_vec(&dinv, nullptr); }
+
+  void setup(GB_Matrix_opaque* ao, GB_Vector_opaque* dego, int type, int kk, double damping, double tol,
+             bool unif) {
+    Ctx& c = ctx();
+    n = ao->nrows;
+    T = type;
+    k = kk;
+    uniform = unif;
+    const PlanConfig pc = default_plan_config(ao->data, T);
+    A_exec = ao->data;
+    if (pc.relabel) {
+      rl = get_relabeled(ao->data);
+      A_exec = rl->A;
+      inv_host.resize((size_t)n);
+      hip_check(hipMemcpyAsync(inv_host.data(), rl->inv->p, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost,
+                               c.stream),
+                "copy permutation");
+      hip_check(hipStreamSynchronize(c.stream), "sync");
+    }
+    PlanConfig wp;
+    wp.kernel = K_WAVE;
+    wp.lds_entries = WAVE_TILE_ENTRIES;
+    wp.lds_rows = WAVE_TILE_ROWS;
+    wp.long_row = (pc.kernel == K_WAVE) ? pc.long_row : WAVE_TILE_ENTRIES;
+    wp.chunk = WAVE_TILE_ENTRIES;
+    wp.grid = c.cus * 2;
+    plan = get_plan(A_exec, wp);
+    grid = plan->cfg.grid;
+
+    // d = damping ./ outdeg (0 for dangling), in execution order
+    GB_Vector_opaque deg_exec{MAGIC_VEC, dego->type, n, nullptr};
+    set_vec(&deg_exec, rl ? permuted(dego->node, rl->order) : dego->node);
+    dinv.type = T;
+    dinv.n = n;
+    rec_unop(&dinv, U_MINV_OR_ZERO, &deg_exec);
+    rec_bind(&dinv, B_TIMES, &dinv, damping, true);
+    set_vec(&deg_exec, nullptr);
+    materialize(dinv.node);
+    store_if_iso(dinv.node);
+
+    vbytes = type_size(T) * (size_t)n * (size_t)k;
+    for (int i = 0; i < 2; ++i) {
+      Xb[i] = dev_alloc(vbytes);
+      Wb[i] = dev_alloc(vbytes);
+      Db[i] = dev_alloc(sizeof(double) * 64);
+    }
+    rho = dev_alloc(sizeof(double) * 64);
+    hit = dev_alloc(sizeof(int) * 64);
+    hub_sum = dev_alloc(sizeof(double) * 64 * (size_t)std::max(plan->nparts, 1));
+    hub_cnt = dev_alloc(sizeof(int) * (size_t)std::max(plan->nhubs, 1));
+    hub_red = dev_alloc(sizeof(double) * 128 * (size_t)std::max(plan->nhubs, 1));
+    wg_part = dev_alloc(sizeof(double) * 128 * (size_t)grid);
+    ticket = dev_alloc(256);
+    gbuf = dev_alloc(sizeof(GuardDev));
+    tile_seed = dev_alloc(sizeof(int) * (size_t)std::max(plan->dev.ntiles, 1));
+    hip_check(launch_zero(hub_cnt->p, sizeof(int) * (size_t)std::max(plan->nhubs, 1), c.stream), "zero");
+    hip_check(launch_zero(ticket->p, 256, c.stream), "zero");
+    hip_check(launch_zero(Xb[0]->p, vbytes, c.stream), "zero");
+    hip_check(launch_zero(Wb[0]->p, vbytes, c.stream), "zero");
+    hip_check(launch_zero(Db[0]->p, sizeof(double) * 64, c.stream), "zero");
+    hip_check(launch_zero(rho->p, sizeof(double) * 64, c.stream), "zero");
+    for (int i = 0; i < 6; ++i) launch_mark(false);
+
+    a.rowptr = (const int*)A_exec->rowptr->p;
+    a.col = A_exec->col ? (const int*)A_exec->col->p : nullptr;
+    a.k = k;
+    a.w_bytes = vbytes < 0xFFFFFF00ull ? (unsigned)vbytes : 0u;
+    a.dvec = dinv.node->buf->p;
+    a.c_alpha = damping;
+    a.c_beta = 1.0 - damping;
+    a.rho_out = (double*)rho->p;
+    a.hit = (int*)hit->p;
+    a.hit_tol = tol;
+    a.hub_sum = (double*)hub_sum->p;
+    a.hub_cnt = (int*)hub_cnt->p;
+    a.hub_red = (double*)hub_red->p;
+    a.wg_part = (double*)wg_part->p;
+    a.ticket = (unsigned*)ticket->p;
+    a.tile_seed = (const int*)tile_seed->p;
+  }
+
+  int exec_vertex(int v) const { return rl ? inv_host[(size_t)v] : v; }
+
+  BufP upload(const void* h, size_t bytes) {
+    BufP b = dev_alloc(std::max<size_t>(bytes, 16));
+    if (bytes) hip_check(hipMemcpyAsync(b->p, h, bytes, hipMemcpyHostToDevice, ctx().stream), "upload");
+    return b;
+  }
+
+  // Teleport table of the columns in use: seeds (execution numbering)
+  // sorted by vertex, then column; each tile's first seed.
+  void set_seeds(std::vector<PprSeed> seeds) {
+    std::sort(seeds.begin(), seeds.end(),
+              [](const PprSeed& x, const PprSeed& y) { return x.v != y.v ? x.v < y.v : x.c < y.c; });
+    const int ns = (int)seeds.size();
+    std::vector<int> v(ns), cc(ns);
+    std::vector<double> w(ns);
+    for (int i = 0; i < ns; ++i) {
+      v[i] = seeds[i].v;
+      cc[i] = seeds[i].c;
+      w[i] = seeds[i].w;
+    }
+    sv = upload(v.data(), sizeof(int) * ns);
+    sc = upload(cc.data(), sizeof(int) * ns);
+    sw = upload(w.data(), sizeof(double) * ns);
+    a.seed_v = (const int*)sv->p;
+    a.seed_c = (const int*)sc->p;
+    a.seed_w = (const double*)sw->p;
+    a.nseeds = ns;
+    hip_check(launch_spmm_tile_seed(plan->dev, a.seed_v, ns, (int*)tile_seed->p, ctx().stream), "tile seeds");
+    launch_mark(false);
+  }
+
+  // Start columns `cols` (their seeds listed by column in seeds_by_col) in
+  // buffer set `cur`: x = v, w = v .* d, D = dangling seed mass, hit = -1.
+  void start_columns(uint64_t cols, int cur, const std::vector<PprSeed>& seeds_by_col) {
+    Ctx& c = ctx();
+    hip_check(launch_spmm_zero_columns(Xb[cur]->p, Wb[cur]->p, T, n, k, cols, c.stream), "zero columns");
+    std::vector<int> ptr(k + 1, 0), v;
+    std::vector<double> w;
+    for (int col = 0; col < k; ++col) {
+      for (const PprSeed& s : seeds_by_col)
+        if (s.c == col) {
+          v.push_back(s.v);
+          w.push_back(s.w);
+        }
+      ptr[col + 1] = (int)v.size();
+    }
+    BufP dp = upload(ptr.data(), sizeof(int) * (k + 1)), dv = upload(v.data(), sizeof(int) * v.size());
+    BufP dw = upload(w.data(), sizeof(double) * w.size());
+    SpmmArgs ia = a;
+    ia.x_new = Xb[cur]->p;
+    ia.w_new = Wb[cur]->p;
+    ia.d_out = (double*)Db[cur]->p;
+    hip_check(launch_spmm_init(ia, T, (const int*)dp->p, (const int*)dv->p, (const double*)dw->p, cols, c.stream),
+              "ppr init");
+    launch_mark(false);
+    launch_mark(false);
+  }
+
+  // One pass from buffer set (pass-1)&1 into pass&1.
+  void run_pass(int pass) {
+    Ctx& c = ctx();
+    const int in = (pass - 1) & 1, out = pass & 1;
+    a.w = Wb[in]->p;
+    a.x_old = Xb[in]->p;
+    a.x_new = Xb[out]->p;
+    a.w_new = Wb[out]->p;
+    a.d_prev = uniform ? (const double*)Db[in]->p : nullptr;
+    a.d_out = (double*)Db[out]->p;
+    hip_check(launch_spmm_ppr(plan->dev, a, T, grid, a.guard, c.stream), "ppr pass");
+    launch_mark(true);
+  }
+};
+
+}  // namespace
+
+GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, const int32_t* seed_vtx,
+                       GrB_Matrix AT, GrB_Vector outdeg, double damping, double tol, int itermax,
+                       GrM_Dangling dangling, int check_every, int* iters, int* col_iters, double* col_resid) {
+  Ctx& c = ctx();
+  GuardDev* saved_guard = c.guard;
+  API_BEGIN
+  require_init();
+  need(X, "X");
+  need(type, "type");
+  need(iters, "iters");
+  GB_Matrix_opaque* ao = mat(AT, "AT");
+  GB_Vector_opaque* dego = vec(outdeg, "outdeg");
+  const int T = type->code;
+  float_type(T, "type");
+  const int64_t n = ao->nrows;
+  if (ao->ncols != n || dego->n != n) fail(GrB_DIMENSION_MISMATCH, "ppr_batch dimensions");
+  if (k < 1 || k > 64) fail(GrB_INVALID_VALUE, "k must be in [1, 64]");
+  if (dangling != GrM_DANGLING_DROP && dangling != GrM_DANGLING_UNIFORM) fail(GrB_INVALID_VALUE, "dangling mode");
+  if (check_every < 1 || itermax < 0 || !(damping >= 0.0 && damping < 1.0) || std::isnan(tol))
+    fail(GrB_INVALID_VALUE, "ppr_batch parameters");
+  if (c.guard) fail(GrB_INVALID_VALUE, "an iterative driver is already running");
+  check_seed_sets(k, seed_ptr, seed_vtx, n);
+
+  PprColumns pc;
+  pc.setup(ao, dego, T, k, damping, tol, dangling == GrM_DANGLING_UNIFORM);
+  std::vector<PprSeed> seeds;
+  for (int q = 0; q < k; ++q) {
+    const double w = 1.0 / (double)(seed_ptr[q + 1] - seed_ptr[q]);
+    for (int e = seed_ptr[q]; e < seed_ptr[q + 1]; ++e) seeds.push_back({pc.exec_vertex(seed_vtx[e]), q, w});
+  }
+  pc.set_seeds(seeds);
+  pc.start_columns(k == 64 ? ~0ull : ((1ull << k) - 1ull), 0, seeds);
+  hip_check(launch_guard_init((GuardDev*)pc.gbuf->p, (1.0 > tol && itermax > 0) ? 1 : 0, tol, itermax, c.stream),
+            "guard init");
+  launch_mark(false);
+  c.guard = (GuardDev*)pc.gbuf->p;
+  pc.a.guard = c.guard;
+
+  GuardDev hg{};
+  int pass = 0, batch = check_every;
+  for (;;) {
+    for (int j = 0; j < batch; ++j) pc.run_pass(++pass);
+    hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    if (!hg.active) break;
+    int next = check_every;
+    if (hg.rho_prev > 0.0 && hg.rho > 0.0 && hg.rho < hg.rho_prev && tol > 0.0) {
+      const double need_passes = std::log(tol / hg.rho) / std::log(hg.rho / hg.rho_prev);
+      if (need_passes > 0.0 && need_passes < 1e6) next = (int)std::ceil(need_passes);
+    }
+    if (next > itermax - hg.iters) next = itermax - hg.iters;
+    if (next < 1) next = 1;
+    batch = next;
+  }
+  c.guard = saved_guard;
+  const BufP& res = pc.Xb[hg.iters & 1];
+  if (pc.rl)
+    hip_check(launch_rows_permute(res->p, T, (const int*)pc.rl->inv->p, X, n, k, c.stream), "unpermute");
+  else
+    hip_check(hipMemcpyAsync(X, res->p, pc.vbytes, hipMemcpyDeviceToDevice, c.stream), "copy out");
+  std::vector<int> hh(64);
+  std::vector<double> rr(64);
+  hip_check(hipMemcpyAsync(hh.data(), pc.hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+  hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+  if (col_iters)
+    for (int q = 0; q < k; ++q) col_iters[q] = hg.iters == 0 ? -1 : hh[q];
+  if (col_resid)
+    for (int q = 0; q < k; ++q) col_resid[q] = hg.iters == 0 ? 1.0 : rr[q];
+  *iters = hg.iters;
+  }
+  catch (const GrbError& e) {
+    c.guard = saved_guard;
+    api_error() = e.msg;
+    return e.info;
+  }
+  catch (const std::exception& e) {
+    c.guard = saved_guard;
+    api_error() = e.what();
+    return GrB_PANIC;
+  }
+  return GrB_SUCCESS;
+}
+
+GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_ptr, const int32_t* seed_vtx,
+                        GrB_Matrix AT, GrB_Vector outdeg, double damping, double tol, int itermax,
+                        GrM_Dangling dangling, int k, int check_every, int* set_iters, int* set_passes,
+                        double* set_resid) {
+  Ctx& c = ctx();
+  GuardDev* saved_guard = c.guard;
+  API_BEGIN
+  require_init();
+  need(X, "X");
+  need(type, "type");
+  GB_Matrix_opaque* ao = mat(AT, "AT");
+  GB_Vector_opaque* dego = vec(outdeg, "outdeg");
+  const int T = type->code;
+  float_type(T, "type");
+  const int64_t n = ao->nrows;
+  if (ao->ncols != n || dego->n != n) fail(GrB_DIMENSION_MISMATCH, "ppr_stream dimensions");
+  if (nsets < 1) fail(GrB_INVALID_VALUE, "nsets must be >= 1");
+  if (k < 1 || k > 64) fail(GrB_INVALID_VALUE, "k must be in [1, 64]");
+  if (dangling != GrM_DANGLING_DROP && dangling != GrM_DANGLING_UNIFORM) fail(GrB_INVALID_VALUE, "dangling mode");
+  if (check_every < 1 || itermax < 1 || !(damping >= 0.0 && damping < 1.0) || std::isnan(tol))
+    fail(GrB_INVALID_VALUE, "ppr_stream parameters");
+  if (c.guard) fail(GrB_INVALID_VALUE, "an iterative driver is already running");
+  check_seed_sets(nsets, seed_ptr, seed_vtx, n);
+  if (k > nsets) k = nsets;
+
+  PprColumns pc;
+  pc.setup(ao, dego, T, k, damping, tol, dangling == GrM_DANGLING_UNIFORM);
+  // the device guard only counts passes here (it never stops them)
+  hip_check(launch_guard_init((GuardDev*)pc.gbuf->p, 1, -1.0, INT32_MAX, c.stream), "guard init");
+  launch_mark(false);
+  c.guard = (GuardDev*)pc.gbuf->p;
+  pc.a.guard = c.guard;
+
+  std::vector<int> slot_set(k, -1), slot_start(k, 0);
+  std::vector<PprSeed> active;  // seeds of the columns in use
+  int next_set = 0, pass = 0, live = 0;
+  auto set_seeds_of = [&](int q, int col, std::vector<PprSeed>& out) {
+    const double w = 1.0 / (double)(seed_ptr[q + 1] - seed_ptr[q]);
+    for (int e = seed_ptr[q]; e < seed_ptr[q + 1]; ++e) out.push_back({pc.exec_vertex(seed_vtx[e]), col, w});
+  };
+  // fill the free slots with the next sets, starting them in buffer set `cur`
+  auto refill = [&](int cur, uint64_t freed) {
+    // drop the seeds of retired columns, then hand free columns the next sets
+    active.erase(std::remove_if(active.begin(), active.end(), [&](const PprSeed& s) { return slot_set[s.c] < 0; }),
+                 active.end());
+    uint64_t cols = 0;
+    std::vector<PprSeed> fresh;
+    for (int col = 0; col < k && next_set < nsets; ++col) {
+      if (slot_set[col] >= 0) continue;
+      slot_set[col] = next_set;
+      slot_start[col] = pass;
+      set_seeds_of(next_set, col, fresh);
+      cols |= 1ull << col;
+      ++next_set;
+      ++live;
+    }
+    active.insert(active.end(), fresh.begin(), fresh.end());
+    pc.set_seeds(active);
+    pc.start_columns(cols | freed, cur, fresh);
+  };
+  refill(0, 0);
+  std::vector<int> hh(64);
+  std::vector<double> rr(64);
+  while (live > 0) {
+    // up to check_every passes, never past a column's itermax
+    int batch = check_every;
+    for (int col = 0; col < k; ++col)
+      if (slot_set[col] >= 0) batch = std::min(batch, itermax - (pass - slot_start[col]));
+    for (int j = 0; j < std::max(batch, 1); ++j) pc.run_pass(++pass);
+    hip_check(hipMemcpyAsync(hh.data(), pc.hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+    hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    const int cur = pass & 1;
+    uint64_t retired = 0;
+    ColumnOutputs outs{};
+    for (int col = 0; col < k; ++col) {
+      const int q = slot_set[col];
+      if (q < 0) continue;
+      const int done = pass - slot_start[col];
+      const bool conv = hh[col] >= 0;
+      if (!conv && done < itermax) continue;
+      // retire: the column's current iterate goes to set q's output
+      retired |= 1ull << col;
+      outs.out[col] = (char*)X + type_size(T) * (size_t)n * (size_t)q;
+      if (set_iters) set_iters[q] = conv ? hh[col] - slot_start[col] : -1;
+      if (set_passes) set_passes[q] = done;
+      if (set_resid) set_resid[q] = rr[col];
+      slot_set[col] = -1;
+      --live;
+    }
+    if (retired) {
+      hip_check(launch_spmm_columns_out(pc.Xb[cur]->p, T, pc.rl ? (const int*)pc.rl->inv->p : nullptr, n, k, retired,
+                                        outs, c.stream),
+                "columns out");
+      launch_mark(false);
+      // freed columns stop contributing (zeroed) or restart with new sets
+      refill(cur, retired);
+    }
+  }
+  c.guard = saved_guard;
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+  }
+  catch (const GrbError& e) {
+    c.guard = saved_guard;
+    api_error() = e.msg;
+    return e.info;
+  }
+  catch (const std::exception& e) {
+    c.guard = saved_guard;
+    api_error() = e.what();
+    return GrB_PANIC;
+  }
+  return GrB_SUCCESS;
+}
+
+// ------------------------------------------------------------ many graphs
+
+struct GB_Multigraph_opaque {
+  uint32_t magic;
+  int ngraphs;
+  int64_t nv, ne;
+  std::vector<int64_t> voff;
+  BufP graphs, queue, qnext, rowptr, col, deg, inv, longrows, xa, xb, wa, wb, iters, resid;
+  std::vector<std::shared_ptr<MatData>> keep;  // relabeled copies stay alive
+  struct Exec {
+    int type;
+    double damping, tol;
+    int itermax, uniform;
+    void* out;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<Exec> execs;
+  hipStream_t aux = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+static constexpr uint32_t MAGIC_MULTI = 0x4d554c54u;
+
+static void multigraph_release(GB_Multigraph_opaque* m) {
+  for (auto& e : m->execs) {
+    (void)hipGraphExecDestroy(e.exec);
+    (void)hipGraphDestroy(e.graph);
+  }
+  m->execs.clear();
+  if (m->ev0) (void)hipEventDestroy(m->ev0);
+  if (m->ev1) (void)hipEventDestroy(m->ev1);
+  if (m->aux) (void)hipStreamDestroy(m->aux);
+}
+
+GrB_Info GrM_Multigraph_new(GrM_Multigraph* mg, int ngraphs, const GrB_Matrix* AT) {
+  GB_Multigraph_opaque* m = nullptr;
+  API_BEGIN
+  require_init();
+  need(mg, "mg");
+  need(AT, "AT");
+  if (ngraphs < 1) fail(GrB_INVALID_VALUE, "ngraphs must be >= 1");
+  Ctx& c = ctx();
+  std::vector<std::shared_ptr<Relabeled>> rls;
+  std::vector<ManyGraph> gs((size_t)ngraphs);
+  int64_t nv = 0, ne = 0, nr = 0;
+  for (int g = 0; g < ngraphs; ++g) {
+    GB_Matrix_opaque* a = mat(AT[g], "AT[g]");
+    if (a->nrows != a->ncols) fail(GrB_DIMENSION_MISMATCH, "graphs must be square");
+    rls.push_back(get_relabeled(a->data));
+    const MatData& r = *rls.back()->A;
+    ManyGraph& G = gs[(size_t)g];
+    G.n = (int)r.nrows;
+    G.m = (int)r.nnz;
+    const double avg = r.nrows > 0 ? (double)r.nnz / (double)r.nrows : 0.0;
+    int lpr = 1;
+    while (lpr * 2 <= avg && lpr < 32) lpr *= 2;
+    G.lpr = lpr;
+    G.nlong = 0;
+    G.loff = 0;
+    G.voff = nv;
+    G.eoff = ne;
+    G.roff = nr;
+    nv += r.nrows;
+    ne += r.nnz;
+    nr += r.nrows + 1;
+  }
+  if (ne > (int64_t)INT32_MAX * 4) fail(GrB_INVALID_VALUE, "too many entries");
+  // rows too long for one lane group, per graph
+  std::vector<int> longrows;
+  for (int g = 0; g < ngraphs; ++g) {
+    const MatData& r = *rls[(size_t)g]->A;
+    std::vector<int> rp((size_t)r.nrows + 1);
+    hip_check(hipMemcpyAsync(rp.data(), r.rowptr->p, sizeof(int) * rp.size(), hipMemcpyDeviceToHost, c.stream),
+              "copy row pointers");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    ManyGraph& G = gs[(size_t)g];
+    G.loff = (int64_t)longrows.size();
+    for (int64_t i = 0; i < r.nrows; ++i)
+      if (rp[(size_t)i + 1] - rp[(size_t)i] > MANY_LONG_ROW) longrows.push_back((int)i);
+    G.nlong = (int)((int64_t)longrows.size() - G.loff);
+  }
+  m = new GB_Multigraph_opaque();
+  m->magic = MAGIC_MULTI;
+  m->ngraphs = ngraphs;
+  m->nv = nv;
+  m->ne = ne;
+  m->graphs = dev_alloc(sizeof(ManyGraph) * gs.size());
+  m->rowptr = dev_alloc(sizeof(int) * (size_t)nr);
+  m->col = dev_alloc(sizeof(int) * (size_t)std::max<int64_t>(ne, 1));
+  m->deg = dev_alloc(sizeof(int) * (size_t)nv);
+  m->inv = dev_alloc(sizeof(int) * (size_t)nv);
+  for (BufP* b : {&m->xa, &m->xb, &m->wa, &m->wb}) *b = dev_alloc(sizeof(double) * (size_t)nv);
+  m->iters = dev_alloc(sizeof(int) * (size_t)ngraphs);
+  m->resid = dev_alloc(sizeof(double) * (size_t)ngraphs);
+  m->qnext = dev_alloc(256);
+  hip_check(launch_fill(m->deg->p, T_INT32, nv, 0.0, c.stream), "fill");
+  launch_mark(false);
+  for (int g = 0; g < ngraphs; ++g) {
+    const ManyGraph& G = gs[(size_t)g];
+    const MatData& r = *rls[(size_t)g]->A;
+    hip_check(hipMemcpyAsync((int*)m->rowptr->p + G.roff, r.rowptr->p, sizeof(int) * (size_t)(G.n + 1),
+                             hipMemcpyDeviceToDevice, c.stream), "pack");
+    if (G.m > 0) {
+      hip_check(hipMemcpyAsync((int*)m->col->p + G.eoff, r.col->p, sizeof(int) * (size_t)G.m,
+                               hipMemcpyDeviceToDevice, c.stream), "pack");
+      hip_check(launch_column_count((const int*)r.col->p, G.m, (int*)m->deg->p + G.voff, c.stream), "degrees");
+      launch_mark(false);
+    }
+    hip_check(hipMemcpyAsync((int*)m->inv->p + G.voff, rls[(size_t)g]->inv->p, sizeof(int) * (size_t)G.n,
+                             hipMemcpyDeviceToDevice, c.stream), "pack");
+    m->voff.push_back(G.voff);
+    m->keep.push_back(rls[(size_t)g]->A);
+  }
+  m->voff.push_back(nv);
+  std::vector<int> order((size_t)ngraphs);
+  for (int g = 0; g < ngraphs; ++g) order[(size_t)g] = g;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return gs[(size_t)a].m > gs[(size_t)b].m; });
+  m->queue = dev_alloc(sizeof(int) * order.size());
+  m->longrows = dev_alloc(sizeof(int) * std::max<size_t>(longrows.size(), 1));
+  if (!longrows.empty())
+    hip_check(hipMemcpyAsync(m->longrows->p, longrows.data(), sizeof(int) * longrows.size(), hipMemcpyHostToDevice,
+                             c.stream), "upload");
+  hip_check(hipMemcpyAsync(m->graphs->p, gs.data(), sizeof(ManyGraph) * gs.size(), hipMemcpyHostToDevice, c.stream),
+            "upload");
+  hip_check(hipMemcpyAsync(m->queue->p, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, c.stream),
+            "upload");
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+  hip_check(hipStreamCreateWithFlags(&m->aux, hipStreamNonBlocking), "stream");
+  hip_check(hipEventCreateWithFlags(&m->ev0, hipEventDisableTiming), "event");
+  hip_check(hipEventCreateWithFlags(&m->ev1, hipEventDisableTiming), "event");
+  *mg = m;
+  m = nullptr;
+  }
+  catch (const GrbError& e) {
+    if (m) {
+      multigraph_release(m);
+      delete m;
+    }
+    api_error() = e.msg;
+    return e.info;
+  }
+  catch (const std::exception& e) {
+    api_error() = e.what();
+    return GrB_PANIC;
+  }
+  return GrB_SUCCESS;
+}
+
+GrB_Info GrM_Multigraph_free(GrM_Multigraph* mg) {
+  API_BEGIN
+  if (!mg || !*mg) return GrB_SUCCESS;
+  GB_Multigraph_opaque* m = *mg;
+  if (m->magic != MAGIC_MULTI) fail(GrB_UNINITIALIZED_OBJECT, "not a multigraph");
+  (void)hipStreamSynchronize(ctx().stream);
+  if (m->aux) (void)hipStreamSynchronize(m->aux);
+  multigraph_release(m);
+  m->magic = MAGIC_FREED;
+  delete m;
+  *mg = nullptr;
+  API_END
+}
+
+GrB_Info GrM_Multigraph_offsets(int64_t* voff, GrM_Multigraph mg) {
+  API_BEGIN
+  need(voff, "voff");
+  need(mg, "mg");
+  if (mg->magic != MAGIC_MULTI) fail(GrB_UNINITIALIZED_OBJECT, "not a multigraph");
+  for (size_t i = 0; i < mg->voff.size(); ++i) voff[i] = mg->voff[i];
+  API_END
+}
+
+GrB_Info GrM_pagerank_many(void* X, GrB_Type type, GrM_Multigraph mg, double damping, double tol, int itermax,
+                           GrM_Dangling dangling, int* iters, double* resid) {
+  API_BEGIN
+  require_init();
+  need(X, "X");
+  need(type, "type");
+  need(mg, "mg");
+  if (mg->magic != MAGIC_MULTI) fail(GrB_UNINITIALIZED_OBJECT, "not a multigraph");
+  const int T = type->code;
+  float_type(T, "type");
+  if (dangling != GrM_DANGLING_DROP && dangling != GrM_DANGLING_UNIFORM) fail(GrB_INVALID_VALUE, "dangling mode");
+  if (itermax < 0 || !(damping >= 0.0 && damping < 1.0) || std::isnan(tol))
+    fail(GrB_INVALID_VALUE, "pagerank parameters");
+  Ctx& c = ctx();
+  const int uniform = dangling == GrM_DANGLING_UNIFORM ? 1 : 0;
+  GB_Multigraph_opaque::Exec* ex = nullptr;
+  for (auto& e : mg->execs)
+    if (e.type == T && e.damping == damping && e.tol == tol && e.itermax == itermax && e.uniform == uniform &&
+        e.out == X)
+      ex = &e;
+  if (!ex) {
+    ManyArgs a{};
+    a.graphs = (const ManyGraph*)mg->graphs->p;
+    a.queue = (const int*)mg->queue->p;
+    a.queue_next = (int*)mg->qnext->p;
+    a.ngraphs = mg->ngraphs;
+    a.rowptr = (const int*)mg->rowptr->p;
+    a.col = (const int*)mg->col->p;
+    a.deg = (const int*)mg->deg->p;
+    a.inv = (const int*)mg->inv->p;
+    a.longrows = (const int*)mg->longrows->p;
+    a.xa = mg->xa->p;
+    a.xb = mg->xb->p;
+    a.wa = mg->wa->p;
+    a.wb = mg->wb->p;
+    a.out = X;
+    a.iters = (int*)mg->iters->p;
+    a.resid = (double*)mg->resid->p;
+    a.damping = damping;
+    a.tol = tol;
+    a.itermax = itermax;
+    a.uniform = uniform;
+    GB_Multigraph_opaque::Exec e{T, damping, tol, itermax, uniform, X, nullptr, nullptr};
+    hip_check(hipStreamBeginCapture(mg->aux, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t le = launch_pr_many(a, T, c.cus, mg->aux);
+    hipGraph_t gph = nullptr;
+    hipError_t ce = hipStreamEndCapture(mg->aux, &gph);
+    hip_check(le, "many-graph launch");
+    hip_check(ce, "end capture");
+    e.graph = gph;
+    hip_check(hipGraphInstantiate(&e.exec, gph, nullptr, nullptr, 0), "instantiate");
+    mg->execs.push_back(e);
+    ex = &mg->execs.back();
+  }
+  // order the replay after the library stream's work, and later work after it
+  hip_check(hipEventRecord(mg->ev0, c.stream), "record");
+  hip_check(hipStreamWaitEvent(mg->aux, mg->ev0, 0), "wait");
+  hip_check(hipGraphLaunch(ex->exec, mg->aux), "graph launch");
+  hip_check(hipEventRecord(mg->ev1, mg->aux), "record");
+  hip_check(hipStreamWaitEvent(c.stream, mg->ev1, 0), "wait");
+  launch_mark(true);
+  if (iters)
+    hip_check(hipMemcpyAsync(iters, mg->iters->p, sizeof(int) * (size_t)mg->ngraphs, hipMemcpyDeviceToHost, c.stream),
+              "copy");
+  if (resid)
+    hip_check(hipMemcpyAsync(resid, mg->resid->p, sizeof(double) * (size_t)mg->ngraphs, hipMemcpyDeviceToHost,
+                             c.stream),
+              "copy");
+  if (iters || resid) hip_check(hipStreamSynchronize(c.stream), "sync");
+  API_END
+}
+
+}  // extern "C"
