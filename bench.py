@@ -175,7 +175,8 @@ def main():
     ap.add_argument("--skip-extras", action="store_true",
                     help="time only the headline fused solve (for profiling); same as --legs none")
     ap.add_argument("--legs", default="all",
-                    help="comma list of extra legs to run: blocking (also FP64), ppr, many, fusion, scale25, warm; "
+                    help="comma list of extra legs to run: blocking (also FP64), m0, ppr, many, fusion, scale25, "
+                         "warm; "
                          "or all / none")
     ap.add_argument("--traffic-kernel", default="fused_wave_kernel<float>",
                     help="kernel (name substring) whose calibrated traffic --summarize-rocprof reports")
@@ -186,7 +187,7 @@ def main():
         summarize_rocprof(args.summarize_rocprof, args.traffic_kernel)
         return
 
-    legs = {"blocking", "ppr", "many", "fusion", "scale25", "warm"} if args.legs == "all" else (
+    legs = {"blocking", "m0", "ppr", "many", "fusion", "scale25", "warm"} if args.legs == "all" else (
         set() if args.legs == "none" else set(args.legs.split(",")))
     if args.skip_extras:
         legs = set()
@@ -449,6 +450,37 @@ def main():
             for x in mgs:
                 x.free()
             del Xm
+
+        # ---- the smallest configuration: R-MAT scale 10, FP64 to 1e-9, the
+        # fused nonblocking loop vs the blocking one (time and launches)
+        if leg("m0"):
+            g10 = api.rmat_graph(10)
+            res0 = {}
+            for mode in (grb.GrB_NONBLOCKING, grb.GrB_BLOCKING):
+                grb.GrM_set_mode(mode)
+                api.pagerank(g10, torch.float64, DAMPING, 1e-9, 1000, grb.GrM_DANGLING_UNIFORM, None, 8)
+                torch.cuda.synchronize()
+                grb.GrM_reset_stats()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                reps = 20
+                for _ in range(reps):
+                    _, it10, _ = api.pagerank(g10, torch.float64, DAMPING, 1e-9, 1000, grb.GrM_DANGLING_UNIFORM,
+                                              None, 8)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                st = grb.GrM_get_stats()
+                res0[mode] = (e0.elapsed_time(e1) / reps, it10, st["kernels"] / reps, st["fused_launches"] / reps)
+            grb.GrM_set_mode(grb.GrB_NONBLOCKING)
+            g10.free()
+            fz, bl = res0[grb.GrB_NONBLOCKING], res0[grb.GrB_BLOCKING]
+            log("scale 10 fp64: fused %.3f ms (%d passes, %.1f kernels/solve), blocking %.3f ms (%.1f kernels/solve)" % (
+                fz[0], fz[1], fz[2], bl[0], bl[2]))
+            out["scale10_fp64"] = {"iterations": fz[1], "fused_ms": round(fz[0], 4), "blocking_ms": round(bl[0], 4),
+                                   "fused_kernels_per_solve": fz[2], "blocking_kernels_per_solve": bl[2],
+                                   "fused_passes_per_solve": fz[3],
+                                   "fused_vs_unfused_speedup": round(bl[0] / fz[0], 2)}
 
         # ---- generated elementwise fusion: w = |x .* (y + 1) - 2 z| / 3 over
         # 2^26 FP32 entries, one generated kernel vs five per-op kernels
