@@ -164,7 +164,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=16.0,
                     help="target length of the CPU oracle sample (whole passes)")
     ap.add_argument("--ppr-k", type=int, default=64, help="seed sets of the batched PPR leg")
     ap.add_argument("--ppr-stream", type=int, default=512,
