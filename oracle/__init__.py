@@ -77,6 +77,14 @@ def _load():
         lib.oracle_pagerank.restype = i32
         lib.oracle_pagerank.argtypes = [i64, vp, vp, vp, dbl, dbl, i32, i32, i32,
                                         vp, vp, vp, vp, vp, vp]
+        lib.oracle_web_degrees.restype = None
+        lib.oracle_web_degrees.argtypes = [u64, u64, vp, vp]
+        lib.oracle_web_edges.restype = None
+        lib.oracle_web_edges.argtypes = [u64, u64, vp, vp, vp, vp]
+        lib.oracle_web_row.restype = i64
+        lib.oracle_web_row.argtypes = [u64, u64, vp, u64, vp]
+        lib.oracle_web_links_into.restype = i64
+        lib.oracle_web_links_into.argtypes = [u64, u64, vp, vp, i64, vp, vp]
         lib.oracle_set_threads.restype = None
         lib.oracle_set_threads.argtypes = [i32]
         lib.oracle_get_threads.restype = i32
@@ -116,6 +124,79 @@ def rmat_edges(scale: int, edgefactor: int, seed: int):
     _load().oracle_rmat_edges(int(scale), m, seed & (2**64 - 1), ta, tab, tabc,
                               _ptr(src), _ptr(dst))
     return src, dst
+
+
+# --------------------------------------------------------------------------
+# Web-shaped generator (stand-in for the web crawl of Section IV)
+# --------------------------------------------------------------------------
+
+WEB_FIELDS = ("kmin", "kmax", "p_zero", "p_home", "p_local", "local_min", "hub",
+              "perm_a", "perm_b")
+
+
+def _web_model(model) -> np.ndarray:
+    return np.array([int(model[f]) for f in WEB_FIELDS], dtype=np.int64)
+
+
+def web_degrees(n: int, seed: int, model) -> np.ndarray:
+    """Number of generated links of every vertex (before self-loop removal
+    and merging of repeats)."""
+    deg = np.empty(n, dtype=np.int64)
+    _load().oracle_web_degrees(int(n), seed & (2**64 - 1), _ptr(_web_model(model)), _ptr(deg))
+    return deg
+
+
+def web_edges(n: int, seed: int, model):
+    """The generated link list (src, dst) as uint32 arrays, in order of the
+    source vertex, then of the link number."""
+    deg = web_degrees(n, seed, model)
+    off = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(deg, out=off[1:])
+    m = int(off[-1])
+    src = np.empty(max(m, 1), dtype=np.uint32)
+    dst = np.empty(max(m, 1), dtype=np.uint32)
+    _load().oracle_web_edges(int(n), seed & (2**64 - 1), _ptr(_web_model(model)), _ptr(off),
+                             _ptr(src), _ptr(dst))
+    return src[:m], dst[:m]
+
+
+def web_graph(n: int, seed: int, model) -> "Graph":
+    src, dst = web_edges(n, seed, model)
+    return graph_from_edges(n, src, dst, True)
+
+
+def web_row_links(n: int, seed: int, model, u: int) -> np.ndarray:
+    """The generated targets of vertex u in link order (repeats and a
+    self-loop included)."""
+    mdl = _web_model(model)
+    out = np.empty(int(mdl[1]), dtype=np.uint32)
+    k = _load().oracle_web_row(int(n), seed & (2**64 - 1), _ptr(mdl), int(u), _ptr(out))
+    return out[:k].copy()
+
+
+def web_out_row(n: int, seed: int, model, u: int) -> np.ndarray:
+    """Row u of the graph's CSR(A): distinct targets other than u, ascending."""
+    t = np.unique(web_row_links(n, seed, model, u))
+    return t[t != u].astype(np.int32)
+
+
+def web_in_rows(n: int, seed: int, model, vertices, cap: int = 1 << 26) -> dict:
+    """Rows of CSR(A^T) for the given vertices: for each v, its distinct
+    in-neighbours other than v, ascending.  One scan over every link."""
+    want = np.zeros(n, dtype=np.uint8)
+    want[np.asarray(vertices, dtype=np.int64)] = 1
+    src = np.empty(cap, dtype=np.uint32)
+    dst = np.empty(cap, dtype=np.uint32)
+    cnt = _load().oracle_web_links_into(int(n), seed & (2**64 - 1), _ptr(_web_model(model)),
+                                        _ptr(want), int(cap), _ptr(src), _ptr(dst))
+    if cnt < 0:
+        raise ValueError("more than %d links into the requested vertices" % cap)
+    src, dst = src[:cnt], dst[:cnt]
+    rows = {}
+    for v in np.unique(np.asarray(vertices, dtype=np.int64)):
+        s = np.unique(src[dst == v])
+        rows[int(v)] = s[s != v].astype(np.int32)
+    return rows
 
 
 # --------------------------------------------------------------------------

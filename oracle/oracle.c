@@ -102,6 +102,119 @@ void oracle_rmat_edges(int scale, int64_t nedges, uint64_t seed, double t_a,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Web-shaped generator: a synthetic stand-in for the web crawl of the       */
+/* paper's evaluation (Section IV: many pages, a high mean degree, strong    */
+/* locality).  Every quantity is an unsigned 64-bit integer.                 */
+/*                                                                           */
+/* model[] = {kmin, kmax, p_zero, p_home, p_local, local_min, hub, perm_a,   */
+/* perm_b}; probabilities in units of 2^-16.  The draw with key k is draw k  */
+/* of the SplitMix64 stream above.                                           */
+/*                                                                           */
+/* Heavy-tailed helper: D(c, r) = floor(c * 2^52 / X) with X = (r >> 12)+1  */
+/* uniform on 1..2^52, so D >= c and P(D >= x) is about c/x.                 */
+/*                                                                           */
+/* Vertex u: a page without out-links when the top 16 bits of draw           */
+/* (u<<18 | 0x3FFFC) fall below p_zero; otherwise its number of links is    */
+/* k_u = min(kmax, D(kmin, draw(u<<18 | 0x3FFFD))).                          */
+/*                                                                           */
+/* Link j of u, with r = draw(u<<18 | j<<2), q = draw(u<<18 | j<<2 | 1) and  */
+/* t = the top 16 bits of r:                                                 */
+/*   t < p_home           -> home link: clear the low h = 6 + (r mod 16)     */
+/*                           bits of u;                                      */
+/*   t < p_home + p_local -> local link at distance                          */
+/*                           d = min(n-1, D(max(local_min, k_u), q)),        */
+/*                           backwards when bit 4 of r is set, modulo n;     */
+/*   otherwise            -> global link to vertex (perm_a*i + perm_b) mod n */
+/*                           with i = (D(hub, q) - hub) mod n.               */
+/* ------------------------------------------------------------------------ */
+
+static uint64_t web_heavy(uint64_t c, uint64_t r) {
+  uint64_t x = (r >> 12) + 1u;        /* 1 .. 2^52 */
+  return (c << 52) / x;
+}
+
+static uint64_t web_links_of(uint64_t seed, const int64_t *model, uint64_t u) {
+  uint64_t kmin = (uint64_t)model[0], kmax = (uint64_t)model[1], p_zero = (uint64_t)model[2];
+  uint64_t a = oracle_splitmix64(seed, (u << 18) | 0x3FFFCu);
+  if ((a >> 48) < p_zero) return 0;
+  uint64_t k = web_heavy(kmin, oracle_splitmix64(seed, (u << 18) | 0x3FFFDu));
+  return k < kmax ? k : kmax;
+}
+
+static uint64_t web_link(uint64_t n, uint64_t seed, const int64_t *model, uint64_t u,
+                         uint64_t j, uint64_t k_u) {
+  uint64_t p_home = (uint64_t)model[3], p_local = (uint64_t)model[4];
+  uint64_t local_min = (uint64_t)model[5], hub = (uint64_t)model[6];
+  uint64_t perm_a = (uint64_t)model[7], perm_b = (uint64_t)model[8];
+  uint64_t r = oracle_splitmix64(seed, (u << 18) | (j << 2));
+  uint64_t q = oracle_splitmix64(seed, (u << 18) | (j << 2) | 1u);
+  uint64_t t = r >> 48;
+  if (t < p_home) {
+    uint64_t h = 6 + r % 16;
+    return (u >> h) << h;
+  }
+  if (t < p_home + p_local) {
+    uint64_t scale = local_min > k_u ? local_min : k_u;
+    uint64_t d = web_heavy(scale, q);
+    if (d > n - 1) d = n - 1;
+    if ((r >> 4) & 1u) return (u + (n - d)) % n; /* u - d modulo n */
+    return (u + d) % n;
+  }
+  uint64_t i = (web_heavy(hub, q) - hub) % n;
+  return (perm_a * i + perm_b) % n;
+}
+
+/* Number of links of every vertex. */
+void oracle_web_degrees(uint64_t n, uint64_t seed, const int64_t *model, int64_t *deg) {
+#pragma omp parallel for schedule(static)
+  for (int64_t u = 0; u < (int64_t)n; ++u) deg[u] = (int64_t)web_links_of(seed, model, (uint64_t)u);
+}
+
+/* All links in order of u then j; off[u] = first link of u (n+1 entries). */
+void oracle_web_edges(uint64_t n, uint64_t seed, const int64_t *model, const int64_t *off,
+                      uint32_t *src, uint32_t *dst) {
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t u = 0; u < (int64_t)n; ++u) {
+    uint64_t k = (uint64_t)(off[u + 1] - off[u]);
+    for (uint64_t j = 0; j < k; ++j) {
+      src[off[u] + (int64_t)j] = (uint32_t)u;
+      dst[off[u] + (int64_t)j] = (uint32_t)web_link(n, seed, model, (uint64_t)u, j, k);
+    }
+  }
+}
+
+/* The links of one vertex (k_u targets in order of j); returns k_u. */
+int64_t oracle_web_row(uint64_t n, uint64_t seed, const int64_t *model, uint64_t u, uint32_t *out) {
+  uint64_t k = web_links_of(seed, model, u);
+  for (uint64_t j = 0; j < k; ++j) out[j] = (uint32_t)web_link(n, seed, model, u, j, k);
+  return (int64_t)k;
+}
+
+/* Every link (u, v) whose target v has want[v] != 0, in no particular
+ * order; returns their number, or -1 when more than cap were found (the
+ * arrays then hold the first cap in no particular order). */
+int64_t oracle_web_links_into(uint64_t n, uint64_t seed, const int64_t *model, const uint8_t *want,
+                              int64_t cap, uint32_t *src, uint32_t *dst) {
+  int64_t found = 0;
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t u = 0; u < (int64_t)n; ++u) {
+    uint64_t k = web_links_of(seed, model, (uint64_t)u);
+    for (uint64_t j = 0; j < k; ++j) {
+      uint64_t v = web_link(n, seed, model, (uint64_t)u, j, k);
+      if (!want[v]) continue;
+      int64_t slot;
+#pragma omp atomic capture
+      slot = found++;
+      if (slot < cap) {
+        src[slot] = (uint32_t)u;
+        dst[slot] = (uint32_t)v;
+      }
+    }
+  }
+  return found > cap ? -1 : found;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Graph construction                                                        */
 /* ------------------------------------------------------------------------ */
 

@@ -16,6 +16,26 @@ import numpy as np
 RMAT_EDGEFACTOR = 16
 DAMPING = 0.85
 
+# Web-shaped stand-in for the paper's web crawl (Section IV: 50.6 million
+# pages, 1.9494 billion links, strong locality, high mean degree).  The
+# parameters of the web-shaped generator (see GrM_web_edges): out-degrees
+# min(4000, D(7)) with 17.75 % of pages without links; 5 % home links,
+# 60 % local links at distance >= max(16, k_u), 35 % global links with
+# popularity scale 1024.  At WEB_N vertices this generates 2,120,533,943
+# links, about 1.93 billion after merging repeats (38.2 per vertex).
+WEB_N = 50_600_000
+WEB_SEED = 50
+WEB_MODEL = {
+    "kmin": 7, "kmax": 4000,
+    "p_zero": 11633, "p_home": 3277, "p_local": 39322,
+    "local_min": 16, "hub": 1024,
+    "perm_a": 2654435761, "perm_b": 12345,
+}
+# The paper does not state its PageRank settings for the crawl; these are
+# the GAP benchmark's (damping 0.85, tolerance 1e-4 on the L1 change).
+WEB_TOL = 1e-4
+WEB_ITERMAX = 100
+
 
 def cycle(n: int):
     """Directed cycle 0->1->...->n-1->0."""
