@@ -176,7 +176,7 @@ def main():
                     help="time only the headline fused solve (for profiling); same as --legs none")
     ap.add_argument("--legs", default="all",
                     help="comma list of extra legs to run: blocking (also FP64), m0, ppr, many, fusion, scale25, "
-                         "warm; "
+                         "web, warm; "
                          "or all / none")
     ap.add_argument("--traffic-kernel", default="fused_wave_kernel<float>",
                     help="kernel (name substring) whose calibrated traffic --summarize-rocprof reports")
@@ -187,7 +187,7 @@ def main():
         summarize_rocprof(args.summarize_rocprof, args.traffic_kernel)
         return
 
-    legs = {"blocking", "m0", "ppr", "many", "fusion", "scale25", "warm"} if args.legs == "all" else (
+    legs = {"blocking", "m0", "ppr", "many", "fusion", "scale25", "web", "warm"} if args.legs == "all" else (
         set() if args.legs == "none" else set(args.legs.split(",")))
     if args.skip_extras:
         legs = set()
@@ -534,58 +534,86 @@ def main():
                                    "per_op_gbs": round(perop_b / (res_f[0][0] * 1e-3) / 1e9, 1),
                                    "first_call_s": round(res_f[1][1], 3)}
 
+        def big_graph_leg(gx, dang, tol, itermax, reps):
+            """Fused solve to tolerance (autotuned plan), the pass time from
+            two fixed-length runs, and the blocking solve, all FP32."""
+            f32 = grb.builtin("GrB_FP32")
+            cfg, _ = grb.GrM_autotune_pagerank(gx.AT, gx.outdeg, f32, os.environ.get("NBGRB_TUNE_CACHE"))
+
+            def solve_x():
+                return api.pagerank(gx, torch.float32, DAMPING, tol, itermax, dang, None, args.check_every)
+
+            def time_x(k):
+                solve_x()
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(k):
+                    xx, it_, res_ = solve_x()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / k, it_, res_, xx
+
+            ms_x, it_x, res_x, xx = time_x(reps)
+            t = []
+            for k in (4, 20, 4, 20):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                api.pagerank(gx, torch.float32, DAMPING, 0.0, k, dang, None, k)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t.append(e0.elapsed_time(e1))
+            us_x = ((t[1] - t[0]) + (t[3] - t[2])) / 2 * 1e3 / 16
+            bpp_x = fused_bytes_per_pass(gx.n, gx.m, 4)
+            grb.GrM_set_mode(grb.GrB_BLOCKING)
+            msb_x, itb_x, _, _ = time_x(max(1, reps - 1))
+            grb.GrM_set_mode(grb.GrB_NONBLOCKING)
+            gbs = bpp_x / (us_x * 1e-6) / 1e9
+            return {"n": gx.n, "m": gx.m, "plan": cfg, "iterations": it_x, "resid": res_x,
+                    "rank_sum": float(xx.double().sum().item()), "ms_per_solve": round(ms_x, 3),
+                    "gteps": round(gx.m * it_x / (ms_x * 1e-3) / 1e9, 2),
+                    "pass_us": round(us_x, 2), "bytes_per_pass": bpp_x,
+                    "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "blocking_ms_per_solve": round(msb_x, 3), "blocking_iterations": itb_x,
+                    "fused_vs_unfused_speedup": round(msb_x / ms_x, 3)}
+
         # ---- the HBM-bound size: R-MAT scale 25, fused vs blocking (FP32)
         if leg("scale25"):
             t0 = time.perf_counter()
             g25 = api.rmat_graph(25)
             torch.cuda.synchronize()
             setup25 = time.perf_counter() - t0
-            n25, m25 = g25.n, g25.m
-            f32 = grb.builtin("GrB_FP32")
-            cfg25, _ = grb.GrM_autotune_pagerank(g25.AT, g25.outdeg, f32, os.environ.get("NBGRB_TUNE_CACHE"))
-
-            def solve25():
-                return api.pagerank(g25, torch.float32, DAMPING, args.tol, 1000, grb.GrM_DANGLING_UNIFORM, None,
-                                    args.check_every)
-
-            def time25(reps):
-                solve25()
-                torch.cuda.synchronize()
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for _ in range(reps):
-                    _, it_, _ = solve25()
-                e1.record(stream)
-                torch.cuda.synchronize()
-                return e0.elapsed_time(e1) / reps, it_
-
-            ms25, it25 = time25(3)
-            t = []
-            for k in (4, 20, 4, 20):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                api.pagerank(g25, torch.float32, DAMPING, 0.0, k, grb.GrM_DANGLING_UNIFORM, None, k)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                t.append(e0.elapsed_time(e1))
-            us25 = ((t[1] - t[0]) + (t[3] - t[2])) / 2 * 1e3 / 16
-            bpp25 = fused_bytes_per_pass(n25, m25, 4)
-            grb.GrM_set_mode(grb.GrB_BLOCKING)
-            msb25, itb25 = time25(2)
-            grb.GrM_set_mode(grb.GrB_NONBLOCKING)
+            r25 = big_graph_leg(g25, grb.GrM_DANGLING_UNIFORM, args.tol, 1000, 3)
             g25.free()
-            log("scale 25: n %d m %d (setup %.1fs); fused %d passes %.2f ms (%.1f GTEPS), pass %.1f us = %.1f GB/s; "
-                "blocking %.2f ms" % (n25, m25, setup25, it25, ms25, m25 * it25 / (ms25 * 1e-3) / 1e9, us25,
-                                      bpp25 / (us25 * 1e-6) / 1e9, msb25))
-            out["scale25"] = {"n": n25, "m": m25, "plan": cfg25, "iterations": it25, "ms_per_solve": round(ms25, 3),
-                              "gteps": round(m25 * it25 / (ms25 * 1e-3) / 1e9, 2),
-                              "pass_us": round(us25, 2), "bytes_per_pass": bpp25,
-                              "achieved_gbs": round(bpp25 / (us25 * 1e-6) / 1e9, 1),
-                              "frac": round(bpp25 / (us25 * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                              "blocking_ms_per_solve": round(msb25, 3), "blocking_iterations": itb25,
-                              "fused_vs_unfused_speedup": round(msb25 / ms25, 3)}
+            r25.pop("rank_sum")
+            r25.pop("resid")
+            log("scale 25: n %d m %d (setup %.1fs); fused %d passes %.2f ms (%.1f GTEPS), pass %.1f us = "
+                "%.1f GB/s; blocking %.2f ms" % (r25["n"], r25["m"], setup25, r25["iterations"],
+                                                 r25["ms_per_solve"], r25["gteps"], r25["pass_us"],
+                                                 r25["achieved_gbs"], r25["blocking_ms_per_solve"]))
+            out["scale25"] = r25
+
+        # ---- the web-crawl-shaped graph at the size of the paper's data set
+        # (50.6M pages, about 1.93B links after merging repeats), in the
+        # paper's dangling-drop mode with the GAP benchmark's tolerance
+        if leg("web"):
+            import synthetic
+            t0 = time.perf_counter()
+            gw = api.web_graph(synthetic.WEB_N, synthetic.WEB_SEED, synthetic.WEB_MODEL)
+            torch.cuda.synchronize()
+            setupw = time.perf_counter() - t0
+            rw = big_graph_leg(gw, grb.GrM_DANGLING_DROP, synthetic.WEB_TOL, synthetic.WEB_ITERMAX, 3)
+            gw.free()
+            rw["setup_s"] = round(setupw, 2)
+            rw["dangling"] = "drop"
+            rw["tol"] = synthetic.WEB_TOL
+            log("web: n %d m %d (setup %.1fs); fused %d passes %.2f ms (%.1f GTEPS), pass %.1f us = %.1f GB/s; "
+                "blocking %.2f ms" % (rw["n"], rw["m"], setupw, rw["iterations"], rw["ms_per_solve"],
+                                      rw["gteps"], rw["pass_us"], rw["achieved_gbs"],
+                                      rw["blocking_ms_per_solve"]))
+            out["web"] = rw
 
         # ---- learned warm start (reduced size): train on scale-20 graphs,
         # then warm vs teleport start on the headline graph, both to tol;

@@ -303,6 +303,46 @@ GrB_Info GrM_rmat_edges(uint32_t *src_dev, uint32_t *dst_dev, int scale,
                         GrB_Index nedges, uint64_t seed, double t_a,
                         double t_ab, double t_abc);
 
+/* Web-shaped synthetic graph: a stand-in for the crawl the paper measures
+ * on (Section IV: 50.6M pages, 1.95B links, with strong locality and a
+ * high mean degree), generated vertex by vertex from a SplitMix64 stream
+ * seeded with `seed`.  All arithmetic is on unsigned 64-bit integers.
+ * With D(c, r) = (c << 52) / ((r >> 12) + 1) (a Pareto-like draw:
+ * P(D >= x) ~ c / x for x >= c) and draw(key) the stream's draw number key:
+ *   vertex u: a = draw(u<<18 | 0x3FFFC), b = draw(u<<18 | 0x3FFFD);
+ *     out-degree k_u = 0 if (a >> 48) < p_zero,
+ *     else min(kmax, D(kmin, b));
+ *   link j < k_u of u: r = draw(u<<18 | j<<2), q = draw(u<<18 | j<<2 | 1),
+ *     t = r >> 48;
+ *     t < p_home:            v = u & ~(2^h - 1), h = 6 + (r & 15)
+ *                            (the first page of an enclosing aligned block);
+ *     t < p_home + p_local:  d = min(n - 1, D(max(local_min, k_u), q)),
+ *                            v = (u - d) mod n if bit 4 of r is set,
+ *                            else (u + d) mod n;
+ *     otherwise:             i = (D(hub, q) - hub) mod n,
+ *                            v = (perm_a * i + perm_b) mod n.
+ * Links are emitted as (u, v) in order of u, then j; self-loops and repeats
+ * are kept (GrM_Matrix_build_edges drops and merges them).
+ * Probabilities p_* are in units of 2^-16.  Requirements (else
+ * GrB_INVALID_VALUE): 1 <= n < 2^32; 1 <= kmin <= kmax <= 4095;
+ * 1 <= local_min, hub <= 4095; p_zero + p_home + p_local <= 65536;
+ * perm_a coprime with n (so that i -> v is a bijection).
+ * Call with src_dev == NULL to get the number of links in *nedges; then
+ * with device arrays of at least `capacity` entries each
+ * (GrB_INSUFFICIENT_SPACE if capacity < the count).  Temporary device
+ * memory: 16 bytes per vertex plus the scan's workspace. */
+typedef struct {
+  int32_t kmin, kmax;               /* out-degree draw */
+  int32_t p_zero, p_home, p_local;  /* units of 2^-16 */
+  int32_t local_min;                /* smallest local link distance scale */
+  int32_t hub;                      /* popularity scale of global links */
+  uint32_t perm_a, perm_b;          /* vertex permutation of global links */
+} GrM_WebModel;
+
+GrB_Info GrM_web_edges(uint32_t *src_dev, uint32_t *dst_dev, GrB_Index capacity,
+                       GrB_Index *nedges, GrB_Index n, uint64_t seed,
+                       const GrM_WebModel *model);
+
 /* ------------------------------------------------------------------------
  * Operations (GraphBLAS C API forms, destructive output as in the C
  * specification; the paper's Julia methods return new nodes instead,

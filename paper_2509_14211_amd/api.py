@@ -119,6 +119,26 @@ def rmat_graph(scale: int, edgefactor: int = 16, seed: int | None = None) -> Gra
     return g
 
 
+def web_device_edges(n: int, seed: int, model):
+    """The web-shaped generator's links as device int32 tensors (the bits
+    of uint32 vertex ids)."""
+    m = grb.GrM_web_edges(None, None, 0, n, seed, model)
+    src = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+    dst = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+    grb.GrM_web_edges(src, dst, src.numel(), n, seed, model)
+    return src[:m], dst[:m]
+
+
+def web_graph(n: int, seed: int, model) -> Graph:
+    """Web-shaped graph (self-loops dropped, repeated links merged)."""
+    src, dst = web_device_edges(n, seed, model)
+    if src.numel() == 0:
+        return _graph_no_edges(n)
+    g = graph_from_device_edges(n, src, dst, True)
+    del src, dst
+    return g
+
+
 def csr_of(A: int):
     """(rowptr, col) int32 tensors copied from matrix A."""
     n = grb.GrB_Matrix_nrows(A)

@@ -266,6 +266,16 @@ PlanConfig default_plan_config(const MatP& A, int value_type) {
 
 std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
   PlanConfig cfg = cfg0;
+  if (cfg.kernel == K_WAVE && (uint64_t)A->ncols * sizeof(double) > 0xFFFFFFFFull) {
+    // the wave kernel addresses the gathered vector with 32-bit byte offsets
+    cfg.kernel = K_BLOCK;
+    cfg.lds_entries = 2048;
+    cfg.lds_rows = 1024;
+    cfg.long_row = 2048;
+    cfg.chunk = 2048;
+    cfg.grid = 0;
+    cfg.hot = 0;
+  }
   if (cfg.kernel == K_WAVE) {
     cfg.lds_entries = WAVE_TILE_ENTRIES;
     cfg.lds_rows = WAVE_TILE_ROWS;

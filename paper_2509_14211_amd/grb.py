@@ -67,6 +67,11 @@ class GrM_PlanConfig(ctypes.Structure):
                 ("chunk", i32), ("grid", i32), ("hot", i32), ("relabel", i32)]
 
 
+class GrM_WebModel(ctypes.Structure):
+    _fields_ = [("kmin", i32), ("kmax", i32), ("p_zero", i32), ("p_home", i32), ("p_local", i32),
+                ("local_min", i32), ("hub", i32), ("perm_a", ctypes.c_uint32), ("perm_b", ctypes.c_uint32)]
+
+
 class GrM_Stats(ctypes.Structure):
     _fields_ = [("kernels", i64), ("fused_launches", i64), ("plan_hits", i64),
                 ("plan_misses", i64), ("elided_nodes", i64), ("forced_waits", i64),
@@ -115,6 +120,7 @@ _FUNCS = {
     "GrB_transpose": [vp, vp, vp, vp, vp],
     "GrM_Matrix_row_degree": [vp, vp],
     "GrM_rmat_edges": [vp, vp, i32, u64, u64, dbl, dbl, dbl],
+    "GrM_web_edges": [vp, vp, u64, ctypes.POINTER(u64), u64, u64, ctypes.c_void_p],
     "GrB_mxv": [vp, vp, vp, vp, vp, vp, vp],
     "GrB_Vector_eWiseMult_BinaryOp": [vp, vp, vp, vp, vp, vp, vp],
     "GrB_Vector_eWiseAdd_BinaryOp": [vp, vp, vp, vp, vp, vp, vp],
@@ -427,6 +433,18 @@ def GrM_Matrix_row_degree(deg, A):
 def GrM_rmat_edges(src, dst, scale, nedges, seed, t_a, t_ab, t_abc):
     _call("GrM_rmat_edges", _addr(src), _addr(dst), scale, nedges, seed & (2**64 - 1),
           t_a, t_ab, t_abc)
+
+
+def GrM_web_edges(src, dst, capacity, n, seed, model) -> int:
+    """Web-shaped link list into device arrays src/dst (None, None: only
+    count); model is a mapping with the GrM_WebModel fields.  Returns the
+    number of links."""
+    m = GrM_WebModel(**{f: int(model[f]) for f, _ in GrM_WebModel._fields_})
+    cnt = u64()
+    _call("GrM_web_edges", _addr(src) if src is not None else None,
+          _addr(dst) if dst is not None else None, capacity, ctypes.byref(cnt), n,
+          seed & (2**64 - 1), ctypes.addressof(m))
+    return int(cnt.value)
 
 
 # ---------------------------------------------------------------- operations
