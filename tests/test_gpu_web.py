@@ -35,7 +35,7 @@ def test_web_edges_bitwise(gpu, oracle_mod, n, seed):
 
 def test_web_degenerate_and_invalid_models(gpu):
     from paper_2509_14211_amd import api, grb
-    none = dict(MODEL, p_zero=65536)
+    none = dict(MODEL, p_zero=65536, p_home=0, p_local=0)
     assert grb.GrM_web_edges(None, None, 0, 1000, 1, none) == 0
     g = api.web_graph(1000, 1, none)
     assert g.m == 0
