@@ -47,7 +47,8 @@ def blocking_bytes_per_pass(n: int, m: int, b: int) -> int:
 
 COPY_BYTES = 1 << 30  # bytes read and written by one launch of the copy probe
 PROFILE_MD = os.path.join(ROOT, "profiles", "fused_wave_kernel_rmat22.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_14211_amd", "csrc", f) for f in ("kernels.hip", "kernels.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_14211_amd", "csrc", f)
+                  for f in ("kernels.hip", "kernels.h", "device_util.h", "ops_device.h")]
 
 
 def kernel_source_sha() -> str:
@@ -175,8 +176,8 @@ def main():
     ap.add_argument("--skip-extras", action="store_true",
                     help="time only the headline fused solve (for profiling); same as --legs none")
     ap.add_argument("--legs", default="all",
-                    help="comma list of extra legs to run: blocking (also FP64), m0, ppr, many, fusion, scale25, "
-                         "web, warm; "
+                    help="comma list of extra legs to run: blocking (also FP64), m0, ppr, many, fusion, bfs, "
+                         "scale25, web, warm; "
                          "or all / none")
     ap.add_argument("--traffic-kernel", default="fused_wave_kernel<float>",
                     help="kernel (name substring) whose calibrated traffic --summarize-rocprof reports")
@@ -187,7 +188,7 @@ def main():
         summarize_rocprof(args.summarize_rocprof, args.traffic_kernel)
         return
 
-    legs = {"blocking", "m0", "ppr", "many", "fusion", "scale25", "web", "warm"} if args.legs == "all" else (
+    legs = {"blocking", "m0", "ppr", "many", "fusion", "bfs", "scale25", "web", "warm"} if args.legs == "all" else (
         set() if args.legs == "none" else set(args.legs.split(",")))
     if args.skip_extras:
         legs = set()
@@ -616,6 +617,51 @@ def main():
                                       rw["gteps"], rw["pass_us"], rw["achieved_gbs"],
                                       rw["blocking_ms_per_solve"]))
             out["web"] = rw
+
+        # ---- vectors with missing entries: breadth-first search on the
+        # headline graph, loop drivers chosen by the fill estimates (push for
+        # sparse frontiers, pull for dense ones) vs pull at every level
+        if leg("bfs"):
+            rp_a, _ = api.csr_of(g.A)
+            outdeg_h = np.diff(rp_a.cpu().numpy().astype(np.int64))
+            del rp_a
+            rng_b = np.random.default_rng(17)
+            cands = np.nonzero(outdeg_h > 0)[0]
+            sources = [int(s_) for s_ in rng_b.choice(cands, 4, replace=False)]
+
+            def run_bfs(policy):
+                grb.GrM_set_format_policy(policy)
+                lv, _ = api.bfs_levels(g, sources[0])  # warm-up (transposed pattern, plans)
+                grb.GrB_Vector_free(lv)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                traversed, depths = 0, []
+                stats0 = grb.GrM_get_stats()
+                for s_ in sources:
+                    lv, depth = api.bfs_levels(g, s_)
+                    idx_b, _ = grb.GrB_Vector_extractTuples(lv)
+                    grb.GrB_Vector_free(lv)
+                    traversed += int(outdeg_h[idx_b].sum())
+                    depths.append(depth)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / len(sources)
+                st = grb.GrM_get_stats()
+                grb.GrM_set_format_policy(0)
+                return dt, traversed / len(sources), depths, st["mxv_push"] - stats0["mxv_push"], \
+                    st["mxv_pull"] - stats0["mxv_pull"]
+
+            dt_e, tr_e, depths, push_e, pull_e = run_bfs(0)
+            dt_p, tr_p, _, push_p, pull_p = run_bfs(1)
+            log("bfs: %.2f ms per search (push %d / pull %d levels), pull only %.2f ms; %.2f GTEPS" %
+                (dt_e * 1e3, push_e, pull_e, dt_p * 1e3, tr_e / dt_e / 1e9))
+            out["bfs"] = {"sources": len(sources), "depths": depths,
+                          "ms_per_search": round(dt_e * 1e3, 3), "gteps": round(tr_e / dt_e / 1e9, 2),
+                          "push_levels": push_e, "pull_levels": pull_e,
+                          "pull_only_ms_per_search": round(dt_p * 1e3, 3),
+                          "speedup_vs_pull_only": round(dt_p / dt_e, 2),
+                          "edges_per_search": int(tr_e),
+                          "timing": "host clock around whole searches, including the per-level "
+                                    "count read-back and the levels' extraction"}
 
         # ---- learned warm start (reduced size): train on scale-20 graphs,
         # then warm vs teleport start on the headline graph, both to tol;

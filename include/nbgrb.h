@@ -131,8 +131,13 @@ extern GrB_Monoid GrB_PLUS_MONOID_FP32, GrB_PLUS_MONOID_FP64;
 extern GrB_Semiring GrB_PLUS_TIMES_SEMIRING_FP32, GrB_PLUS_TIMES_SEMIRING_FP64;
 extern GrB_Semiring GrM_PLUS_SECOND_SEMIRING_FP32, GrM_PLUS_SECOND_SEMIRING_FP64;
 
-/* Descriptors: NULL (defaults) or GrB_DESC_C (complement the mask). */
-extern GrB_Descriptor GrB_DESC_C;
+/* Descriptors: NULL (defaults), or any combination of R (replace: positions
+ * the mask does not allow lose their entry instead of keeping the output's
+ * old one), S (structural mask: a present mask entry allows its position
+ * whatever its value; otherwise the value must be nonzero) and C
+ * (complement the mask). */
+extern GrB_Descriptor GrB_DESC_C, GrB_DESC_S, GrB_DESC_SC, GrB_DESC_R, GrB_DESC_RC, GrB_DESC_RS,
+    GrB_DESC_RSC;
 
 /* ------------------------------------------------------------------------
  * Context
@@ -188,6 +193,13 @@ typedef struct {
   int64_t jit_compiles;     /* generated kernels compiled */
   int64_t jit_disk_hits;    /* ... loaded from the code cache directory */
   int64_t jit_memory_hits;  /* ... found already loaded */
+  int64_t mxv_push;         /* mxv with missing entries driven by u's entries */
+  int64_t mxv_pull;         /* ... driven by the rows of A */
+  int64_t out_full;         /* results with missing entries possible, stored full */
+  int64_t out_bitset;       /* ... stored as bitsets */
+  int64_t out_sparse;       /* ... stored sparse */
+  int64_t index_loops;      /* elementwise loops driven by a sparse input's entries */
+  int64_t range_loops;      /* ... over the whole index range */
 } GrM_Stats;
 GrB_Info GrM_get_stats(GrM_Stats *stats);
 GrB_Info GrM_reset_stats(void);
@@ -344,6 +356,65 @@ GrB_Info GrM_web_edges(uint32_t *src_dev, uint32_t *dst_dev, GrB_Index capacity,
                        const GrM_WebModel *model);
 
 /* ------------------------------------------------------------------------
+ * Vectors with missing entries (Section III-A: a vector is stored full,
+ * as a bitset or sparse).  A vector made by GrB_Vector_new, the import and
+ * fill calls is full.  Operations on vectors with missing entries follow
+ * the GraphBLAS meaning: eWiseMult keeps the positions present in both
+ * inputs, eWiseAdd those present in either (op where both are, else the
+ * present value), apply keeps the input's positions, reduce sums the
+ * present values, and mxv gives w(i) where row i of A meets at least one
+ * present u(j) -- except that a u with every entry present gives a w with
+ * every entry present (an empty row holds 0, as the paper's mxv with the
+ * initial value 0).  A mask restricts the positions an mxv or assign
+ * writes (see the descriptors).  How a result is stored and which loop
+ * computes it are chosen by naive fill-ratio estimates made when the
+ * operation is recorded (Section III-D): the product of the inputs' fills
+ * for eWiseMult, their union for eWiseAdd, 1 - (1 - f)^L for mxv with mean
+ * row length L, times the mask's allowed share.  The choice never changes a
+ * result beyond the order of a floating-point sum.  Calls that need every
+ * entry present (the dense import/export calls, the PageRank drivers and
+ * their vectors, fused PageRank passes) fail with GrB_INVALID_VALUE on a
+ * vector that has missing entries.
+ * ---------------------------------------------------------------------- */
+
+typedef enum { GrM_FULL = 0, GrM_BITSET = 1, GrM_SPARSE = 2 } GrM_Format;
+
+/* Number of present entries (forces the vector). */
+GrB_Info GrB_Vector_nvals(GrB_Index *nvals, GrB_Vector v);
+/* Remove every entry. */
+GrB_Info GrB_Vector_clear(GrB_Vector v);
+/* w := the entries (indices[k], values[k]), k < nvals, from host arrays;
+ * repeated indices are combined with dup (GrB_INVALID_VALUE if dup is
+ * NULL), GrB_INDEX_OUT_OF_BOUNDS for an index >= size(w).  The type of the
+ * values must be w's. */
+GrB_Info GrB_Vector_build_FP32(GrB_Vector w, const GrB_Index *indices, const float *values,
+                               GrB_Index nvals, GrB_BinaryOp dup);
+GrB_Info GrB_Vector_build_FP64(GrB_Vector w, const GrB_Index *indices, const double *values,
+                               GrB_Index nvals, GrB_BinaryOp dup);
+GrB_Info GrB_Vector_build_INT32(GrB_Vector w, const GrB_Index *indices, const int32_t *values,
+                                GrB_Index nvals, GrB_BinaryOp dup);
+/* The present entries into host arrays in ascending index order; *n holds
+ * their capacity on entry (GrB_INSUFFICIENT_SPACE if below nvals) and the
+ * count on return.  Values are converted to the function's type. */
+GrB_Info GrB_Vector_extractTuples_FP32(GrB_Index *indices, float *values, GrB_Index *n, GrB_Vector v);
+GrB_Info GrB_Vector_extractTuples_FP64(GrB_Index *indices, double *values, GrB_Index *n, GrB_Vector v);
+GrB_Info GrB_Vector_extractTuples_INT32(GrB_Index *indices, int32_t *values, GrB_Index *n, GrB_Vector v);
+/* w<mask> = x at every position (indices must be NULL, i.e. GrB_ALL, and
+ * ni = size(w)); positions the mask does not allow keep w's old entries
+ * unless the descriptor says replace.  accum must be NULL. */
+GrB_Info GrB_Vector_assign_FP32(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, float x,
+                                const GrB_Index *indices, GrB_Index ni, GrB_Descriptor desc);
+GrB_Info GrB_Vector_assign_FP64(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, double x,
+                                const GrB_Index *indices, GrB_Index ni, GrB_Descriptor desc);
+GrB_Info GrB_Vector_assign_INT32(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, int32_t x,
+                                 const GrB_Index *indices, GrB_Index ni, GrB_Descriptor desc);
+/* How v is stored now (forces it). */
+GrB_Info GrM_Vector_format(GrM_Format *fmt, GrB_Vector v);
+/* 0 (default): estimates choose the storage of results with missing
+ * entries; 1: always bitset; 2: always sparse.  Results are the same. */
+GrB_Info GrM_set_format_policy(int policy);
+
+/* ------------------------------------------------------------------------
  * Operations (GraphBLAS C API forms, destructive output as in the C
  * specification; the paper's Julia methods return new nodes instead,
  * Section III-A).  mask and accum must be NULL unless stated.  Output
@@ -352,8 +423,10 @@ GrB_Info GrM_web_edges(uint32_t *src_dev, uint32_t *dst_dev, GrB_Index capacity,
  * apply forms).
  * ---------------------------------------------------------------------- */
 
-/* w = A (+.*) u.  A is nrows x ncols, u has ncols entries, w nrows.  An
- * empty row gives the monoid identity 0. */
+/* w<mask> = A (+.*) u.  A is nrows x ncols, u has ncols entries, w nrows.
+ * With every entry of u present an empty row gives the monoid identity 0;
+ * otherwise see "Vectors with missing entries".  mask may be NULL; accum
+ * must be NULL. */
 GrB_Info GrB_mxv(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
                  GrB_Semiring op, GrB_Matrix A, GrB_Vector u, GrB_Descriptor desc);
 
@@ -516,6 +589,11 @@ typedef struct {
                        vertices renumbered by decreasing out-degree (built once
                        and cached with the matrix), so the most gathered values
                        come first; 0 runs on the matrix as given */
+  int32_t xcd_split; /* 1: the tile list is cut into 8 contiguous ranges and
+                       workgroup b works only in range b mod 8 (the XCD the
+                       hardware places it on), so each XCD's L2 serves one
+                       region of the matrix; 0: tiles interleaved over all
+                       workgroups.  Ignored when grid is not a multiple of 8 */
 } GrM_PlanConfig;
 
 /* Use cfg for A's kernels computing in `type` (FP32 or FP64); NULL goes

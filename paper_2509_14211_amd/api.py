@@ -211,3 +211,34 @@ def device_copy(ptr: int, count: int, dtype) -> torch.Tensor:
     if nbytes:
         grb.GrM_stream_copy(out, ptr, nbytes)
     return out
+
+
+def bfs_levels(g: Graph, source: int):
+    """Breadth-first levels from `source` written with GraphBLAS operations
+    on vectors with missing entries: the frontier's successors are
+    A^T (+.second) frontier under the complement of the visited set
+    (structural mask, replace), and levels<frontier> = depth.  Returns
+    (levels handle (INT32, unreached vertices have no entry), depth count).
+    Which operations run push (driven by the frontier's entries) or pull
+    (driven by the rows of A^T), and how each vector is stored, is left to
+    the library's fill estimates."""
+    n = g.n
+    levels = grb.GrB_Vector_new(grb.builtin("GrB_INT32"), n)
+    frontier = grb.GrB_Vector_new(grb.builtin("GrB_FP32"), n)
+    sem = grb.builtin("GrM_PLUS_SECOND_SEMIRING_FP32")
+    second = grb.builtin("GrB_SECOND_FP32")
+    try:
+        grb.GrB_Vector_clear(levels)
+        grb.GrB_Vector_build(frontier, [source], [1.0])
+        depth = 0
+        while True:
+            grb.GrB_Vector_assign(levels, frontier, depth, grb.builtin("GrB_DESC_S"))
+            grb.GrB_mxv(frontier, levels, None, sem, g.AT, frontier, grb.builtin("GrB_DESC_RSC"))
+            # keep the frontier's values at 1 (only its pattern matters)
+            grb.GrB_Vector_apply_BinaryOp2nd_FP64(frontier, None, None, second, frontier, 1.0)
+            depth += 1
+            if grb.GrB_Vector_nvals(frontier) == 0:
+                break
+    finally:
+        grb.GrB_Vector_free(frontier)
+    return levels, depth

@@ -61,8 +61,15 @@ static GB_Semiring_opaque s_ps32{B_PLUS, B_SECOND, T_FP32}, s_ps64{B_PLUS, B_SEC
 GrB_Semiring GrB_PLUS_TIMES_SEMIRING_FP32 = &s_pt32, GrB_PLUS_TIMES_SEMIRING_FP64 = &s_pt64;
 GrB_Semiring GrM_PLUS_SECOND_SEMIRING_FP32 = &s_ps32, GrM_PLUS_SECOND_SEMIRING_FP64 = &s_ps64;
 
-static GB_Descriptor_opaque d_comp{true};
+static GB_Descriptor_opaque d_comp{true, false, false}, d_s{false, true, false}, d_sc{true, true, false},
+    d_r{false, false, true}, d_rc{true, false, true}, d_rs{false, true, true}, d_rsc{true, true, true};
 GrB_Descriptor GrB_DESC_C = &d_comp;
+GrB_Descriptor GrB_DESC_S = &d_s;
+GrB_Descriptor GrB_DESC_SC = &d_sc;
+GrB_Descriptor GrB_DESC_R = &d_r;
+GrB_Descriptor GrB_DESC_RC = &d_rc;
+GrB_Descriptor GrB_DESC_RS = &d_rs;
+GrB_Descriptor GrB_DESC_RSC = &d_rsc;
 
 // ------------------------------------------------------------ errors
 
@@ -110,6 +117,8 @@ void nbgrb::float_type(int t, const char* what) {
 }
 
 bool nbgrb::desc_comp(GrB_Descriptor d) { return d && d->mask_comp; }
+bool nbgrb::desc_struct(GrB_Descriptor d) { return d && d->mask_struct; }
+bool nbgrb::desc_replace(GrB_Descriptor d) { return d && d->replace; }
 
 // ------------------------------------------------------------ recording
 
@@ -123,11 +132,12 @@ NodeP iso_node(int type, int64_t n, double v) {
   return p;
 }
 
-void rec_ewise(GB_Vector_opaque* w, int op, GB_Vector_opaque* u, GB_Vector_opaque* v) {
+void rec_ewise(GB_Vector_opaque* w, int op, GB_Vector_opaque* u, GB_Vector_opaque* v, bool set_union) {
   NodeP p = new_node(N_EWISE, w->type, w->n, false);
   p->a = u->node;
   p->b = v->node;
   p->op = op;
+  p->set_union = set_union;
   submit(p);
   set_vec(w, p);
 }
@@ -158,10 +168,32 @@ void rec_bind_scalar(GB_Vector_opaque* w, int op, GB_Vector_opaque* u, GB_Scalar
   set_vec(w, p);
 }
 
-void rec_mxv(GB_Vector_opaque* w, GB_Matrix_opaque* A, GB_Vector_opaque* u) {
+void rec_mxv(GB_Vector_opaque* w, GB_Matrix_opaque* A, GB_Vector_opaque* u, GB_Vector_opaque* mask,
+             GrB_Descriptor desc) {
   NodeP p = new_node(N_MXV, w->type, w->n, false);
   p->A = A->data;
   p->a = u->node;
+  if (mask) {
+    p->mask = mask->node;
+    p->mask_comp = desc_comp(desc);
+    p->mask_struct = desc_struct(desc);
+    p->replace = desc_replace(desc);
+    if (!p->replace) p->b = w->node;  // positions the mask forbids keep w's entries
+  }
+  submit(p);
+  set_vec(w, p);
+}
+
+void rec_assign(GB_Vector_opaque* w, GB_Vector_opaque* mask, double x, GrB_Descriptor desc) {
+  NodeP p = new_node(N_ASSIGN, w->type, w->n, false);
+  p->k = x;
+  if (mask) {
+    p->mask = mask->node;
+    p->mask_comp = desc_comp(desc);
+    p->mask_struct = desc_struct(desc);
+  }
+  p->replace = desc_replace(desc);
+  if (!p->replace && mask) p->b = w->node;
   submit(p);
   set_vec(w, p);
 }
@@ -212,6 +244,7 @@ MatP new_matdata(int64_t nrows, int64_t ncols) {
 // out[k] = v[idx[k]] as a new materialised node (iso vectors stay iso).
 NodeP permuted(const NodeP& v, const BufP& idx) {
   materialize(v);
+  require_full(v, "a relabeled run");
   if (v->iso) return iso_node(v->type, v->n, v->iso_val);
   NodeP p = new_node(N_DENSE, v->type, v->n, false);
   p->buf = dev_alloc(type_size(v->type) * (size_t)v->n);
@@ -359,6 +392,13 @@ GrB_Info GrM_get_stats(GrM_Stats* s) {
   s->jit_compiles = t.jit_compiles;
   s->jit_disk_hits = t.jit_disk_hits;
   s->jit_memory_hits = t.jit_memory_hits;
+  s->mxv_push = t.mxv_push;
+  s->mxv_pull = t.mxv_pull;
+  s->out_full = t.out_full;
+  s->out_bitset = t.out_bitset;
+  s->out_sparse = t.out_sparse;
+  s->index_loops = t.index_loops;
+  s->range_loops = t.range_loops;
   API_END
 }
 
@@ -557,6 +597,7 @@ GrB_Info GrM_Vector_export_dense(void* dst, GrB_Index n, GrB_Vector v) {
   if ((int64_t)n != o->n) fail(GrB_DIMENSION_MISMATCH, "length differs from the vector's");
   materialize(o->node);
   const NodeP& p = o->node;
+  require_full(p, "the dense export");
   if (p->iso) {
     hip_check(launch_fill(dst, o->type, o->n, p->iso_val, ctx().stream), "export fill");
     launch_mark(false);
@@ -574,6 +615,7 @@ GrB_Info GrM_Vector_device_pointer(const void** ptr, GrB_Vector v) {
   need(ptr, "ptr");
   GB_Vector_opaque* o = vec(v, "vector");
   materialize(o->node);
+  require_full(o->node, "a device pointer");
   store_if_iso(o->node);
   *ptr = o->node->buf->p;
   API_END
@@ -792,17 +834,19 @@ GrB_Info GrB_mxv(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_Semiring
   GB_Vector_opaque* uo = vec(u, "u");
   GB_Matrix_opaque* ao = mat(A, "A");
   need(op, "semiring");
-  no_mask_accum(mask, accum);
+  if (accum) fail(GrB_NOT_IMPLEMENTED, "accumulators are not supported");
+  GB_Vector_opaque* mo = mask ? vec(mask, "mask") : nullptr;
+  if (mo && mo->n != wo->n) fail(GrB_DIMENSION_MISMATCH, "mask length");
   if (ao->ncols != uo->n || ao->nrows != wo->n) fail(GrB_DIMENSION_MISMATCH, "mxv dimensions");
   if (op->add != B_PLUS || (op->mul != B_TIMES && op->mul != B_SECOND))
     fail(GrB_NOT_IMPLEMENTED, "only plus-times / plus-second semirings");
   if (op->type != wo->type || op->type != uo->type) fail(GrB_DOMAIN_MISMATCH, "mxv types");
-  rec_mxv(wo, ao, uo);
+  rec_mxv(wo, ao, uo, mo, desc);
   API_END
 }
 
 static GrB_Info ewise_common(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_BinaryOp op, GrB_Vector u,
-                             GrB_Vector v) {
+                             GrB_Vector v, bool set_union) {
   API_BEGIN
   require_init();
   GB_Vector_opaque* wo = vec(w, "w");
@@ -814,20 +858,20 @@ static GrB_Info ewise_common(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, 
   float_type(op->type, "operator");
   if (op->type != wo->type || op->type != uo->type || op->type != vo->type)
     fail(GrB_DOMAIN_MISMATCH, "operand types differ from the operator's");
-  rec_ewise(wo, op->op, uo, vo);
+  rec_ewise(wo, op->op, uo, vo, set_union);
   API_END
 }
 
 GrB_Info GrB_Vector_eWiseMult_BinaryOp(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_BinaryOp op,
                                        GrB_Vector u, GrB_Vector v, GrB_Descriptor desc) {
   (void)desc;
-  return ewise_common(w, mask, accum, op, u, v);
+  return ewise_common(w, mask, accum, op, u, v, false);
 }
 
 GrB_Info GrB_Vector_eWiseAdd_BinaryOp(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_BinaryOp op,
                                       GrB_Vector u, GrB_Vector v, GrB_Descriptor desc) {
   (void)desc;
-  return ewise_common(w, mask, accum, op, u, v);
+  return ewise_common(w, mask, accum, op, u, v, true);
 }
 
 GrB_Info GrB_Vector_apply(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum, GrB_UnaryOp op, GrB_Vector u,
@@ -947,7 +991,7 @@ GrB_Info GrM_Vector_reduce_masked_Scalar(GrB_Scalar s, GrB_Vector mask, GrB_Mono
 
 static bool plan_geometry_ok(const GrM_PlanConfig& c) {
   if (c.kernel != K_BLOCK && c.kernel != K_WAVE) return false;
-  if (c.hot < 0 || (c.relabel != 0 && c.relabel != 1)) return false;
+  if (c.hot < 0 || (c.relabel != 0 && c.relabel != 1) || (c.xcd_split != 0 && c.xcd_split != 1)) return false;
   const bool lds_ok = c.kernel == K_WAVE
                           ? (c.lds_entries == WAVE_TILE_ENTRIES && c.lds_rows == WAVE_TILE_ROWS)
                           : ((c.lds_entries == 1024 && c.lds_rows == 512) ||
@@ -972,6 +1016,7 @@ GrB_Info GrM_Matrix_plan_set(GrB_Matrix A, GrB_Type type, const GrM_PlanConfig* 
     pc.kernel = cfg->kernel;
     pc.hot = cfg->hot;
     pc.relabel = cfg->relabel;
+    pc.xcd = cfg->xcd_split;
     pc.lds_entries = cfg->lds_entries;
     pc.lds_rows = cfg->lds_rows;
     pc.long_row = cfg->long_row;
@@ -993,6 +1038,7 @@ GrB_Info GrM_Matrix_plan_get(GrM_PlanConfig* cfg, GrB_Matrix A, GrB_Type type) {
   cfg->kernel = pc.kernel;
   cfg->hot = pc.hot;
   cfg->relabel = pc.relabel;
+  cfg->xcd_split = pc.xcd;
   cfg->lds_entries = pc.lds_entries;
   cfg->lds_rows = pc.lds_rows;
   cfg->long_row = pc.long_row;

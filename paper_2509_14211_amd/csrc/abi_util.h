@@ -19,14 +19,18 @@ GB_Matrix_opaque* mat(GrB_Matrix A, const char* what);
 void no_mask_accum(const void* mask, const void* accum);
 void float_type(int t, const char* what);
 bool desc_comp(GrB_Descriptor d);
+bool desc_struct(GrB_Descriptor d);
+bool desc_replace(GrB_Descriptor d);
 
 // Record (nonblocking) or run (blocking) one operation into its output.
 NodeP iso_node(int type, int64_t n, double v);
-void rec_ewise(GB_Vector_opaque* w, int op, GB_Vector_opaque* u, GB_Vector_opaque* v);
+void rec_ewise(GB_Vector_opaque* w, int op, GB_Vector_opaque* u, GB_Vector_opaque* v, bool set_union);
 void rec_unop(GB_Vector_opaque* w, int op, GB_Vector_opaque* u);
 void rec_bind(GB_Vector_opaque* w, int op, GB_Vector_opaque* u, double k, bool first);
 void rec_bind_scalar(GB_Vector_opaque* w, int op, GB_Vector_opaque* u, GB_Scalar_opaque* s);
-void rec_mxv(GB_Vector_opaque* w, GB_Matrix_opaque* A, GB_Vector_opaque* u);
+void rec_mxv(GB_Vector_opaque* w, GB_Matrix_opaque* A, GB_Vector_opaque* u, GB_Vector_opaque* mask,
+             GrB_Descriptor desc);
+void rec_assign(GB_Vector_opaque* w, GB_Vector_opaque* mask, double x, GrB_Descriptor desc);
 void rec_reduce(GB_Scalar_opaque* s, GB_Vector_opaque* u, GB_Vector_opaque* mask, bool comp, bool watch);
 void rec_affine(GB_Scalar_opaque* out, double alpha, GB_Scalar_opaque* in, double beta);
 // Give an iso vector storage.

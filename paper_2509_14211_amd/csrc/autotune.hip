@@ -45,7 +45,7 @@ bool read_cache(const std::string& path, const std::string& key, GrM_PlanConfig*
   std::string line;
   bool found = false;
   while (std::getline(f, line)) {
-    // key|kernel lds_entries lds_rows long_row chunk grid hot relabel|us
+    // key|kernel lds_entries lds_rows long_row chunk grid hot relabel xcd_split|us
     const size_t a = line.find('|');
     const size_t b = line.rfind('|');
     if (a == std::string::npos || b == a) continue;
@@ -53,6 +53,7 @@ bool read_cache(const std::string& path, const std::string& key, GrM_PlanConfig*
     std::istringstream v(line.substr(a + 1, b - a - 1));
     GrM_PlanConfig c{};
     if (v >> c.kernel >> c.lds_entries >> c.lds_rows >> c.long_row >> c.chunk >> c.grid >> c.hot >> c.relabel) {
+      if (!(v >> c.xcd_split)) c.xcd_split = 0;  // entries written before the field existed
       *out = c;
       found = true;  // the last entry for a key wins
     }
@@ -64,7 +65,7 @@ void append_cache(const std::string& path, const std::string& key, const GrM_Pla
   std::ofstream f(path, std::ios::app);
   if (!f) return;
   f << key << "|" << c.kernel << " " << c.lds_entries << " " << c.lds_rows << " " << c.long_row << " " << c.chunk
-    << " " << c.grid << " " << c.hot << " " << c.relabel << "|" << us << "\n";
+    << " " << c.grid << " " << c.hot << " " << c.relabel << " " << c.xcd_split << "|" << us << "\n";
 }
 
 PlanConfig to_plan(const GrM_PlanConfig& g) {
@@ -77,6 +78,7 @@ PlanConfig to_plan(const GrM_PlanConfig& g) {
   p.grid = g.grid;
   p.hot = g.hot;
   p.relabel = g.relabel;
+  p.xcd = g.xcd_split;
   return p;
 }
 
@@ -105,11 +107,13 @@ GrB_Info GrM_autotune_pagerank(GrM_PlanConfig* chosen, double* us_per_pass, GrB_
     const int hmax = wave_hot_max(T);
     std::vector<GrM_PlanConfig> cands;
     for (int relabel = 0; relabel < 2; ++relabel) {
-      cands.push_back({0, 2048, 1024, 2048, 2048, 0, 0, relabel});
-      cands.push_back({0, 2048, 1024, 2048, 2048, c.cus * 16, 0, relabel});
-      cands.push_back({1, 512, 256, 512, 512, 0, 0, relabel});
-      cands.push_back({1, 512, 256, 512, 512, 0, hmax, relabel});
-      cands.push_back({1, 512, 256, 128, 512, 0, hmax, relabel});
+      cands.push_back({0, 2048, 1024, 2048, 2048, 0, 0, relabel, 0});
+      cands.push_back({0, 2048, 1024, 2048, 2048, c.cus * 16, 0, relabel, 0});
+      cands.push_back({0, 2048, 1024, 2048, 2048, c.cus * 16, 0, relabel, 1});
+      cands.push_back({1, 512, 256, 512, 512, 0, 0, relabel, 0});
+      cands.push_back({1, 512, 256, 512, 512, 0, hmax, relabel, 0});
+      cands.push_back({1, 512, 256, 512, 512, 0, hmax, relabel, 1});
+      cands.push_back({1, 512, 256, 128, 512, 0, hmax, relabel, 0});
     }
     // Time k1 and k2 fused passes in one batch each (tol 0, no early stop);
     // the difference divided by k2 - k1 is the time of one pass.

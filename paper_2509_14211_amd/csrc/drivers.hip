@@ -69,6 +69,7 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
   rec_bind(&dinv, B_TIMES, &dinv, damping, true);
   set_vec(&deg_exec, nullptr);
   materialize(dinv.node);
+  require_full(dinv.node, "the PageRank out-degree vector");
   store_if_iso(dinv.node);
 
   // personalised teleport distribution (permuted like every vector)
@@ -76,6 +77,7 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
   if (vo) {
     set_vec(&v, rl ? permuted(vo->node, rl->order) : vo->node);
     materialize(v.node);
+    require_full(v.node, "the teleport vector");
     store_if_iso(v.node);
   }
 
@@ -93,6 +95,7 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
     set_vec(&x, iso_node(T, n, 1.0 / (double)n));
   }
   materialize(x.node);
+  require_full(x.node, "the start vector");
   store_if_iso(x.node);
 
   GB_Scalar_opaque D{MAGIC_SCA, T_FP64, nullptr};
@@ -114,8 +117,8 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
       GB_Vector_opaque rn{MAGIC_VEC, T, n, nullptr}, t{MAGIC_VEC, T, n, nullptr};
       GB_Scalar_opaque cs{MAGIC_SCA, T_FP64, nullptr}, rho{MAGIC_SCA, T_FP64, nullptr};
       GB_Scalar_opaque Dn{MAGIC_SCA, T_FP64, nullptr};
-      rec_ewise(&w, B_TIMES, &x, &dinv);            // w = x .* d
-      rec_mxv(&s, &A_exec, &w);                     // s = AT (+.second) w
+      rec_ewise(&w, B_TIMES, &x, &dinv, false);     // w = x .* d
+      rec_mxv(&s, &A_exec, &w, nullptr, nullptr); // s = AT (+.second) w
       GB_Vector_opaque vt{MAGIC_VEC, T, n, nullptr};
       if (vo) {                                     // r = s + v .* c
         if (uniform) {                              //   c = (1-d) + d D
@@ -124,7 +127,7 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
         } else {                                    //   c = 1-d
           rec_bind(&vt, B_TIMES, &v, 1.0 - damping, false);
         }
-        rec_ewise(&rn, B_PLUS, &s, &vt);
+        rec_ewise(&rn, B_PLUS, &s, &vt, true);
         set_vec(&vt, nullptr);
       } else if (uniform) {                         // r = c + s, c = (1-d)/n + d D/n
         rec_affine(&cs, damping / (double)n, &D, tele);
@@ -132,7 +135,7 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
       } else {
         rec_bind(&rn, B_PLUS, &s, tele, false);
       }
-      rec_ewise(&t, B_ABSDIFF, &x, &rn);            // t = |x - r|
+      rec_ewise(&t, B_ABSDIFF, &x, &rn, true);      // t = |x - r|
       rec_reduce(&rho, &t, nullptr, false, true);   // rho = sum t  (advances the guard)
       if (uniform) rec_reduce(&Dn, &rn, &dinv, true, false);  // D = sum r(outdeg = 0)
       // only r, rho and D stay reachable: w, s, t and c become intermediates
@@ -293,6 +296,7 @@ struct PprColumns {
     rec_bind(&dinv, B_TIMES, &dinv, damping, true);
     set_vec(&deg_exec, nullptr);
     materialize(dinv.node);
+    require_full(dinv.node, "the PageRank out-degree vector");
     store_if_iso(dinv.node);
 
     vbytes = type_size(T) * (size_t)n * (size_t)k;

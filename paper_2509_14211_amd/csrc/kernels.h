@@ -84,6 +84,7 @@ struct TilePlanDev {
   const int4* hubs;
   int nhubs;
   int nparts;  // total chunk partial slots
+  int xcd;     // 1: one contiguous tile range per XCD (workgroup b on XCD b mod 8)
 };
 
 // Epilogue of the fused PageRank pass, per row i with row sum s:

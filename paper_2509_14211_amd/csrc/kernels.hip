@@ -27,6 +27,7 @@
 
 #include "device_util.h"
 #include "kernels.h"
+#include "ops_device.h"
 
 namespace nbgrb {
 
@@ -53,68 +54,6 @@ __device__ __forceinline__ V block_sum(V v, V* red) {
   }
   __syncthreads();
   return r;
-}
-
-template <typename T>
-__device__ __forceinline__ T load_as(const Operand& o, int64_t i) {
-  if (!o.p) return (T)o.iso;
-  switch (o.type) {
-    case T_BOOL: return (T)(((const uint8_t*)o.p)[i]);
-    case T_INT32: return (T)(((const int*)o.p)[i]);
-    case T_FP32: return (T)(((const float*)o.p)[i]);
-    default: return (T)(((const double*)o.p)[i]);
-  }
-}
-
-__device__ __forceinline__ bool nonzero_at(const Operand& o, int64_t i) {
-  if (!o.p) return o.iso != 0.0;
-  switch (o.type) {
-    case T_BOOL: return ((const uint8_t*)o.p)[i] != 0;
-    case T_INT32: return ((const int*)o.p)[i] != 0;
-    case T_FP32: return ((const float*)o.p)[i] != 0.0f;
-    default: return ((const double*)o.p)[i] != 0.0;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void store_as(void* p, int type, int64_t i, T v) {
-  switch (type) {
-    case T_BOOL: ((uint8_t*)p)[i] = (uint8_t)(v != (T)0); break;
-    case T_INT32: ((int*)p)[i] = (int)v; break;
-    case T_FP32: ((float*)p)[i] = (float)v; break;
-    default: ((double*)p)[i] = (double)v; break;
-  }
-}
-
-// alpha * s + beta with one rounding (generated kernels use the same form).
-__device__ __forceinline__ double scalar_value(const ScalarArg& s) {
-  return s.dev ? fma(s.alpha, *s.dev, s.beta) : s.beta;
-}
-
-template <typename T>
-__device__ __forceinline__ T apply_binop(int op, T x, T y) {
-  switch (op) {
-    case B_PLUS: return x + y;
-    case B_MINUS: return x - y;
-    case B_TIMES: return x * y;
-    case B_DIV: return x / y;
-    case B_MAX: return x > y ? x : y;
-    case B_MIN: return x < y ? x : y;
-    case B_FIRST: return x;
-    case B_SECOND: return y;
-    default: return fabs(x - y);  // B_ABSDIFF
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ T apply_unop(int op, T x) {
-  switch (op) {
-    case U_IDENTITY: return x;
-    case U_ABS: return fabs(x);
-    case U_AINV: return -x;
-    case U_MINV: return (T)1 / x;
-    default: return x != (T)0 ? (T)1 / x : (T)0;  // U_MINV_OR_ZERO
-  }
 }
 
 // Called by thread 0 of the block that produced a guarded residual.
@@ -209,6 +148,27 @@ __device__ __forceinline__ void pr_epilogue_pre(const FusedArgs<T>& a, int i, T 
   }
 }
 
+// Tiles a worker runs: first, end and stride.  Workers are workgroups
+// (per_wg = 1) or the per_wg wavefronts of each workgroup (slot = wavefront).
+// With plan.xcd the tile list is cut into 8 contiguous ranges and workgroup
+// b works in range b mod 8 -- the XCD that workgroup is dispatched to -- so
+// the rows, and with them the neighbouring columns, that one XCD's L2 sees
+// stay in one region of the matrix.
+struct TileWalk {
+  int t, end, step;
+};
+
+__device__ __forceinline__ TileWalk tile_walk(const TilePlanDev& plan, int slot, int per_wg) {
+  const int G = (int)gridDim.x, b = (int)blockIdx.x;
+  if (plan.xcd && (G & 7) == 0) {
+    const int x = b & 7, j = b >> 3;
+    const int lo = (int)((int64_t)plan.ntiles * x / 8);
+    const int hi = (int)((int64_t)plan.ntiles * (x + 1) / 8);
+    return {lo + j * per_wg + slot, hi, (G >> 3) * per_wg};
+  }
+  return {b * per_wg + slot, plan.ntiles, G * per_wg};
+}
+
 template <typename T, int ET, int RT>
 __global__ __launch_bounds__(FUSED_BLOCK) void fused_pr_kernel(TilePlanDev plan, FusedArgs<T> a,
                                                                FusedScratch scr,
@@ -233,9 +193,10 @@ __global__ __launch_bounds__(FUSED_BLOCK) void fused_pr_kernel(TilePlanDev plan,
   double rho = 0.0, dm = 0.0;
 
   TileRegs<T, KE, KP, KR> R;
-  int t = blockIdx.x;
-  if (t < plan.ntiles) tile_prefetch<T, B>(plan, a, t, pr, R);
-  for (; t < plan.ntiles; t += gridDim.x) {
+  const TileWalk tw = tile_walk(plan, 0, 1);
+  int t = tw.t;
+  if (t < tw.end) tile_prefetch<T, B>(plan, a, t, pr, R);
+  for (; t < tw.end; t += tw.step) {
     // gathers of the current tile
     const int4 cur = R.td;
     T val[KE];
@@ -251,8 +212,8 @@ __global__ __launch_bounds__(FUSED_BLOCK) void fused_pr_kernel(TilePlanDev plan,
       cdv[k] = R.dv[k];
     }
     // next tile's independent loads go out while this one is reduced
-    const int tn = t + (int)gridDim.x;
-    if (tn < plan.ntiles) tile_prefetch<T, B>(plan, a, tn, pr, R);
+    const int tn = t + tw.step;
+    if (tn < tw.end) tile_prefetch<T, B>(plan, a, tn, pr, R);
 
     if (cur.y > 0) {
       // ---- rows [row0, row0 + nr) staged through LDS
@@ -569,19 +530,20 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
   __syncthreads();
   const __amdgpu_buffer_rsrc_t rw = buf_rsrc(a.w, (unsigned)a.ncols * (unsigned)sizeof(T));
 
-  const int nwaves = (int)gridDim.x * NW;
   T* wval = sval[wv];
   int* wrp = srp[wv];
   T* wres = sres[wv];
-  int t = (int)blockIdx.x * NW + wv;
+  const TileWalk tw = tile_walk(plan, wv, NW);
+  const int nwaves = tw.step, tend = tw.end;
+  int t = tw.t;
   if (PIPE) {
-    if (t < plan.ntiles) {
+    if (t < tend) {
       // three register sets rotate through the roles (reduce, gather,
       // prefetch), unrolled by three so no set is ever copied: a copy of a
       // register with a load in flight would wait for every older load.
       TileRegs<T, KE, KP, KR> X, Y, Z;
       T vX[KE], vY[KE], vZ[KE];
-      const int last = plan.ntiles - 1;
+      const int last = tend - 1;
       wave_prefetch<T>(plan, a, t, pr, lane, X);
       wave_prefetch<T>(plan, a, min(t + nwaves, last), pr, lane, Y);
       wave_gather<T, KE>(rw, hot, H, X.ci, vX);
@@ -594,19 +556,19 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
       for (;;) {
         step(t, X, vX, Y, vY, Z);
         t += nwaves;
-        if (t >= plan.ntiles) break;
+        if (t >= tend) break;
         step(t, Y, vY, Z, vZ, X);
         t += nwaves;
-        if (t >= plan.ntiles) break;
+        if (t >= tend) break;
         step(t, Z, vZ, X, vX, Y);
         t += nwaves;
-        if (t >= plan.ntiles) break;
+        if (t >= tend) break;
       }
     }
   } else {
     TileRegs<T, KE, KP, KR> R;
-    if (t < plan.ntiles) wave_prefetch<T>(plan, a, t, pr, lane, R);
-    for (; t < plan.ntiles; t += nwaves) {
+    if (t < tend) wave_prefetch<T>(plan, a, t, pr, lane, R);
+    for (; t < tend; t += nwaves) {
       T val[KE];
       wave_gather<T, KE>(rw, hot, H, R.ci, val);
       const int4 cur = R.td;
@@ -620,7 +582,7 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
         cdv[k] = R.dv[k];
       }
       const int tn = t + nwaves;
-      if (tn < plan.ntiles) wave_prefetch<T>(plan, a, tn, pr, lane, R);
+      if (tn < tend) wave_prefetch<T>(plan, a, tn, pr, lane, R);
       wave_process<T>(plan, a, scr, lane, c, cur, val, crp, cxo, cdv, wval, wrp, wres, rho, dm);
     }
   }

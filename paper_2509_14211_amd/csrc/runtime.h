@@ -64,8 +64,9 @@ struct MatData {
   uint64_t id = 0;
   int64_t nrows = 0, ncols = 0, nnz = 0;
   BufP rowptr, col;
-  std::map<std::tuple<int, int, int, int, int, int>, std::shared_ptr<Plan>> plans;
+  std::map<std::tuple<int, int, int, int, int, int, int>, std::shared_ptr<Plan>> plans;
   std::shared_ptr<Relabeled> relabeled;
+  std::shared_ptr<MatData> transposed;  // built on demand for push-style mxv
 };
 
 // Kernel family of a plan.
@@ -81,6 +82,7 @@ struct PlanConfig {
   int grid = 0;            // persistent workgroups (0: from the device)
   int hot = 0;             // wave kernel: leading gathered entries kept in LDS
   int relabel = 0;         // drivers: run on the degree-renumbered copy
+  int xcd = 0;             // tiles split into one contiguous range per XCD
 };
 
 struct Plan {
@@ -108,7 +110,20 @@ enum NodeKind : int {
   N_REDUCE_MASK, // scalar = sum a(mask)
   N_SCALAR,      // materialised scalar
   N_AFFINE,      // scalar = alpha * s + beta
+  N_ASSIGN,      // w<mask> = k (GrB_ALL), old value in b
 };
+
+// Storage of a materialised vector (Section III-A: full, bitset and sparse
+// vectors).  FULL: every entry present, values in buf (or iso).  BITSET:
+// values in buf (n entries, 0 where absent) and one presence byte per entry
+// in bits.  SPARSE: nvals ascending int32 positions in idx, their values in
+// buf.
+enum VecFormat : int { F_FULL = 0, F_BITSET = 1, F_SPARSE = 2 };
+
+// Output format policy: estimates choose (default), or every vector with a
+// missing entry is stored as a bitset / sparse vector (results are the same
+// either way; the policy only exists to show it).
+enum FormatPolicy : int { FP_ESTIMATE = 0, FP_BITSET = 1, FP_SPARSE = 2 };
 
 struct Node;
 using NodeP = std::shared_ptr<Node>;
@@ -133,6 +148,20 @@ struct Node {
   bool has_value = true;   // scalars: false until assigned
   int handles = 0;         // user handles pointing here
   bool guard_watch = false;  // this scalar advances the loop guard
+
+  // Vectors with missing entries.  `sparse_path` is decided when the node
+  // is recorded: set when an input may have missing entries or a mask
+  // restricts the output; such nodes run on the kernels of
+  // vectors-with-missing-entries and never join a fused dense group.
+  // `est` is the naive metadata estimate of the fraction of present
+  // entries (Section III-D).
+  int fmt = F_FULL;
+  BufP bits, idx;
+  int64_t nvals = -1;
+  bool sparse_path = false;
+  double est = 1.0;
+  bool mask_struct = false, replace = false;
+  bool set_union = false;  // N_EWISE: eWiseAdd (union of the entries) rather than eWiseMult
 
   // Pre-scaled copy of this vector (value .* dvec or ./ dvec) produced as a
   // side output by the fused pass, keyed by operator and dvec node id.
@@ -174,6 +203,8 @@ struct GB_Semiring_opaque {
 };
 struct GB_Descriptor_opaque {
   bool mask_comp;
+  bool mask_struct;
+  bool replace;
 };
 struct GB_Vector_opaque {
   uint32_t magic;
@@ -202,6 +233,9 @@ struct Stats {
   int64_t ewise_fused = 0;   // generated elementwise-tree launches
   int64_t ewise_ops = 0;     // operations they covered
   int64_t jit_compiles = 0, jit_disk_hits = 0, jit_memory_hits = 0;
+  int64_t mxv_push = 0, mxv_pull = 0;        // sparse-path mxv by loop driver
+  int64_t out_full = 0, out_bitset = 0, out_sparse = 0;  // sparse-path output formats
+  int64_t index_loops = 0, range_loops = 0;  // sparse-path elementwise loop drivers
 };
 
 struct Ctx {
@@ -230,6 +264,7 @@ struct Ctx {
   // 0: only the PageRank pattern is fused; 1: pending elementwise trees are
   // also fused into generated kernels
   int fusion = 1;
+  int format_policy = FP_ESTIMATE;
   // plan configuration override chosen by the autotuner (per matrix id)
   std::map<std::pair<uint64_t, int>, PlanConfig> tuned;
 };
@@ -256,6 +291,9 @@ Operand operand_of(const NodeP& v);
 
 void launch_mark(bool fused);
 
+// Scratch of the deterministic reduction kernel on the context stream.
+RedScratch reduce_scratch();
+
 // Text returned by GrM_error() for the calling thread.
 void set_error_text(const std::string& msg);
 
@@ -275,5 +313,19 @@ void jit_clear();
 
 // Degree-renumbered copy of a square pattern (built once, then cached).
 std::shared_ptr<Relabeled> get_relabeled(const MatP& A);
+
+// Transposed pattern of A (built once, then cached with A).
+MatP get_transposed(const MatP& A);
+
+// Vectors with missing entries: decide the sparse path and the fill
+// estimate of a node from its inputs (called when it is recorded), run such
+// a node, and the checks of the dense paths.
+void annotate(const NodeP& node);
+void exec_sparse_node(const NodeP& node);
+// Fail unless the done vector has every entry present.
+void require_full(const NodeP& v, const char* what);
+// Present entries of a done vector: count, then host copies.
+int64_t vec_nvals(const NodeP& v);
+void vec_tuples(const NodeP& v, int64_t* idx, void* vals, int out_type);
 
 }  // namespace nbgrb

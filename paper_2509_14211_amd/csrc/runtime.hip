@@ -139,6 +139,7 @@ void launch_mark(bool fused) {
 }
 
 Operand operand_of(const NodeP& v) {
+  require_full(v, "this operation");
   Operand o{};
   if (v->iso) {
     o.p = nullptr;
@@ -175,7 +176,7 @@ ScalarArg scalar_arg(const NodeP& s) {
 
 // ------------------------------------------------------------ scratch
 
-static RedScratch reduce_scratch() {
+RedScratch reduce_scratch() {
   Ctx& c = g_ctx;
   if (!c.red_part) {
     c.red_part = dev_alloc(sizeof(double) * REDUCE_GRID);
@@ -281,8 +282,9 @@ std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
     cfg.lds_rows = WAVE_TILE_ROWS;
   }
   if (cfg.grid <= 0) cfg.grid = cfg.kernel == K_WAVE ? device_cus() : device_cus() * 8;
+  if (cfg.grid % 8 != 0) cfg.xcd = 0;
   auto key = std::make_tuple(cfg.kernel, cfg.lds_entries, cfg.lds_rows, cfg.long_row, cfg.chunk,
-                             cfg.grid);
+                             cfg.grid, cfg.xcd);
   auto it = A->plans.find(key);
   if (it != A->plans.end()) {
     g_ctx.stats.plan_hits++;
@@ -367,6 +369,7 @@ std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
   plan->dev.hubs = plan->hubs ? (const int4*)plan->hubs->p : nullptr;
   plan->dev.nhubs = plan->nhubs;
   plan->dev.nparts = nparts;
+  plan->dev.xcd = cfg.xcd;
   A->plans[key] = plan;
   return plan;
 }
@@ -545,6 +548,12 @@ static void exec_node(const NodeP& np) {
   ensure_done(n.b);
   if (n.kind != N_APPLY_B2S) ensure_done(n.s);
   ensure_done(n.mask);
+  if (n.sparse_path) {
+    exec_sparse_node(np);
+    n.done = true;
+    release_inputs(n);
+    return;
+  }
   switch (n.kind) {
     case N_EWISE: {
       BufP out = vec_storage(n);
@@ -618,7 +627,9 @@ namespace {
 
 using Consumers = std::map<const Node*, std::vector<NodeP>>;
 
-bool is_dense_of(const NodeP& v, int type) { return v && v->done && !v->iso && v->type == type; }
+bool is_dense_of(const NodeP& v, int type) {
+  return v && v->done && !v->iso && v->fmt == F_FULL && v->type == type;
+}
 
 // The mxv anchor of a PageRank-iteration group and the nodes it absorbs.
 struct PRMatch {
@@ -644,7 +655,7 @@ bool match_pr(const NodeP& M, const Consumers& cons, PRMatch& m) {
   auto cit = cons.find(M.get());
   if (cit == cons.end() || cit->second.size() != 1) return false;
   NodeP E = cit->second[0];
-  if (E->type != T || E->done) return false;
+  if (E->type != T || E->done || E->sparse_path) return false;
   m.M = M;
   m.E = E;
   FusedSpec& f = m.spec;
@@ -659,6 +670,7 @@ bool match_pr(const NodeP& M, const Consumers& cons, PRMatch& m) {
     NodeP RT = E->a == M ? E->b : E->a;
     if (RT->type != T) return false;
     if (RT->done) {
+      if (RT->fmt != F_FULL) return false;
       if (RT->iso)
         f.c = ScalarArg{nullptr, 0.0, RT->iso_val};
       else
@@ -680,13 +692,14 @@ bool match_pr(const NodeP& M, const Consumers& cons, PRMatch& m) {
   auto eit = cons.find(E.get());
   if (eit != cons.end()) {
     for (const NodeP& u : eit->second) {
+      if (u->sparse_path) continue;
       if (!m.T && u->kind == N_EWISE && u->op == B_ABSDIFF && u->handles == 0 && !u->done) {
         NodeP X = u->a == E ? u->b : u->a;
         if (!(u->a == E || u->b == E) || !is_dense_of(X, T)) continue;
         auto tit = cons.find(u.get());
         if (tit == cons.end() || tit->second.size() != 1) continue;
         NodeP R = tit->second[0];
-        if (R->kind != N_REDUCE || R->a != u || R->done) continue;
+        if (R->kind != N_REDUCE || R->a != u || R->done || R->sparse_path) continue;
         m.T = u;
         m.R = R;
         f.x_old = X->buf->p;
@@ -1028,7 +1041,7 @@ void force_all() {
   }
   for (const NodeP& p : live) {
     if (p->done) continue;
-    if (p->kind == N_MXV) {
+    if (p->kind == N_MXV && !p->sparse_path) {
       PRMatch m;
       bool ok = false;
       try {
@@ -1045,10 +1058,10 @@ void force_all() {
     // a consumer needs it, is absorbed by a fused group, or (a scalar
     // affine) is folded into its consumer -- or it is never needed.
     if (p->handles == 0) continue;
-    if (try_ew_fusion(p, cons)) continue;
+    if (!p->sparse_path && try_ew_fusion(p, cons)) continue;
     // a reduction of an elementwise tree: the tree as one kernel first
-    if ((p->kind == N_REDUCE || p->kind == N_REDUCE_MASK) && p->a && !p->a->done && p->a->handles == 0 &&
-        only_consumer(cons, p->a.get(), p.get()))
+    if ((p->kind == N_REDUCE || p->kind == N_REDUCE_MASK) && !p->sparse_path && p->a && !p->a->done &&
+        p->a->handles == 0 && only_consumer(cons, p->a.get(), p.get()))
       try_ew_fusion(p->a, cons);
     exec_node(p);
   }
@@ -1056,6 +1069,7 @@ void force_all() {
 
 void submit(const NodeP& node) {
   Ctx& c = g_ctx;
+  annotate(node);
   if (c.mode == GrB_BLOCKING) {
     exec_node(node);
   } else {

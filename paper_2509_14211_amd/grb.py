@@ -14,6 +14,8 @@ import ctypes
 import os
 import threading
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnbgrb.so")
 
@@ -51,7 +53,8 @@ DATA_SYMBOLS = [
     "GrB_PLUS_MONOID_FP32", "GrB_PLUS_MONOID_FP64",
     "GrB_PLUS_TIMES_SEMIRING_FP32", "GrB_PLUS_TIMES_SEMIRING_FP64",
     "GrM_PLUS_SECOND_SEMIRING_FP32", "GrM_PLUS_SECOND_SEMIRING_FP64",
-    "GrB_DESC_C", "GrM_BF16",
+    "GrB_DESC_C", "GrB_DESC_S", "GrB_DESC_SC", "GrB_DESC_R", "GrB_DESC_RC", "GrB_DESC_RS", "GrB_DESC_RSC",
+    "GrM_BF16",
 ]
 
 vp = ctypes.c_void_p
@@ -64,7 +67,7 @@ PV = ctypes.POINTER(ctypes.c_void_p)
 
 class GrM_PlanConfig(ctypes.Structure):
     _fields_ = [("kernel", i32), ("lds_entries", i32), ("lds_rows", i32), ("long_row", i32),
-                ("chunk", i32), ("grid", i32), ("hot", i32), ("relabel", i32)]
+                ("chunk", i32), ("grid", i32), ("hot", i32), ("relabel", i32), ("xcd_split", i32)]
 
 
 class GrM_WebModel(ctypes.Structure):
@@ -76,7 +79,9 @@ class GrM_Stats(ctypes.Structure):
     _fields_ = [("kernels", i64), ("fused_launches", i64), ("plan_hits", i64),
                 ("plan_misses", i64), ("elided_nodes", i64), ("forced_waits", i64),
                 ("ewise_fused", i64), ("ewise_ops", i64), ("jit_compiles", i64),
-                ("jit_disk_hits", i64), ("jit_memory_hits", i64)]
+                ("jit_disk_hits", i64), ("jit_memory_hits", i64), ("mxv_push", i64), ("mxv_pull", i64),
+                ("out_full", i64), ("out_bitset", i64), ("out_sparse", i64), ("index_loops", i64),
+                ("range_loops", i64)]
 
 
 # name -> (restype, argtypes).  All return GrB_Info unless noted.
@@ -91,6 +96,19 @@ _FUNCS = {
     "GrM_get_stats": [ctypes.POINTER(GrM_Stats)],
     "GrM_reset_stats": [],
     "GrM_set_fusion": [i32],
+    "GrB_Vector_nvals": [ctypes.POINTER(u64), vp],
+    "GrB_Vector_clear": [vp],
+    "GrB_Vector_build_FP32": [vp, vp, vp, u64, vp],
+    "GrB_Vector_build_FP64": [vp, vp, vp, u64, vp],
+    "GrB_Vector_build_INT32": [vp, vp, vp, u64, vp],
+    "GrB_Vector_extractTuples_FP32": [vp, vp, ctypes.POINTER(u64), vp],
+    "GrB_Vector_extractTuples_FP64": [vp, vp, ctypes.POINTER(u64), vp],
+    "GrB_Vector_extractTuples_INT32": [vp, vp, ctypes.POINTER(u64), vp],
+    "GrB_Vector_assign_FP32": [vp, vp, vp, ctypes.c_float, vp, u64, vp],
+    "GrB_Vector_assign_FP64": [vp, vp, vp, dbl, vp, u64, vp],
+    "GrB_Vector_assign_INT32": [vp, vp, vp, i32, vp, u64, vp],
+    "GrM_Vector_format": [ctypes.POINTER(i32), vp],
+    "GrM_set_format_policy": [i32],
     "GrM_code_cache_clear": [],
     "GrB_Scalar_new": [PV, vp],
     "GrB_Scalar_free": [PV],
@@ -284,6 +302,67 @@ def GrM_set_fusion(level: int):
 
 def GrM_code_cache_clear():
     _call("GrM_code_cache_clear")
+
+
+# ---------------------------------------------------------------- vectors with missing entries
+
+GrM_FULL, GrM_BITSET, GrM_SPARSE = 0, 1, 2
+_TYPE_SUFFIX = {"FP32": (np.float32, "FP32"), "FP64": (np.float64, "FP64"), "INT32": (np.int32, "INT32")}
+
+
+def _suffix_of(v) -> str:
+    t = GrM_Vector_type(v)
+    for name in ("GrB_FP32", "GrB_FP64", "GrB_INT32"):
+        if builtin(name) == t:
+            return name[4:]
+    raise ValueError("vector type has no tuple form")
+
+
+def GrB_Vector_nvals(v) -> int:
+    n = u64()
+    _call("GrB_Vector_nvals", ctypes.byref(n), v)
+    return int(n.value)
+
+
+def GrB_Vector_clear(v):
+    _call("GrB_Vector_clear", v)
+
+
+def GrB_Vector_build(w, indices, values, dup=None):
+    """w := entries (indices[k], values[k]) from host arrays (w's type)."""
+    suf = _suffix_of(w)
+    idx = np.ascontiguousarray(indices, dtype=np.uint64)
+    val = np.ascontiguousarray(values, dtype=_TYPE_SUFFIX[suf][0])
+    if idx.shape != val.shape:
+        raise ValueError("indices and values differ in length")
+    _call("GrB_Vector_build_" + suf, w, idx.ctypes.data_as(vp), val.ctypes.data_as(vp), len(idx), dup)
+
+
+def GrB_Vector_extractTuples(v):
+    """(indices int64, values) of the present entries, ascending."""
+    suf = _suffix_of(v)
+    nv = GrB_Vector_nvals(v)
+    idx = np.empty(max(nv, 1), dtype=np.uint64)
+    val = np.empty(max(nv, 1), dtype=_TYPE_SUFFIX[suf][0])
+    n = u64(len(idx))
+    _call("GrB_Vector_extractTuples_" + suf, idx.ctypes.data_as(vp), val.ctypes.data_as(vp), ctypes.byref(n), v)
+    return idx[:n.value].astype(np.int64), val[:n.value]
+
+
+def GrB_Vector_assign(w, mask, x, desc=None):
+    """w<mask> = x at every position (GrB_ALL)."""
+    suf = _suffix_of(w)
+    _call("GrB_Vector_assign_" + suf, w, mask, None, x, None, GrB_Vector_size(w), desc)
+
+
+def GrM_Vector_format(v) -> int:
+    f = i32()
+    _call("GrM_Vector_format", ctypes.byref(f), v)
+    return int(f.value)
+
+
+def GrM_set_format_policy(policy: int):
+    _call("GrM_set_format_policy", policy)
 
 
 def GrM_error() -> str:

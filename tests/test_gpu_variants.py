@@ -20,12 +20,24 @@ VARIANTS = [
     dict(kernel=1, lds_entries=512, lds_rows=256, long_row=512, chunk=512, grid=0, hot=1 << 20, relabel=0),
     dict(kernel=1, lds_entries=512, lds_rows=256, long_row=64, chunk=512, grid=0, hot=1 << 20, relabel=1),
     dict(kernel=1, lds_entries=512, lds_rows=256, long_row=128, chunk=256, grid=5, hot=1000, relabel=1),
+    # tiles split into one contiguous range per XCD (grid a multiple of 8;
+    # with grid 5 the split is ignored)
+    dict(kernel=0, lds_entries=2048, lds_rows=1024, long_row=2048, chunk=2048, grid=16, hot=0, relabel=0,
+         xcd_split=1),
+    dict(kernel=0, lds_entries=1024, lds_rows=512, long_row=256, chunk=1024, grid=4096, hot=0, relabel=1,
+         xcd_split=1),
+    dict(kernel=1, lds_entries=512, lds_rows=256, long_row=512, chunk=512, grid=0, hot=1 << 20, relabel=1,
+         xcd_split=1),
+    dict(kernel=1, lds_entries=512, lds_rows=256, long_row=64, chunk=512, grid=8, hot=0, relabel=0,
+         xcd_split=1),
+    dict(kernel=1, lds_entries=512, lds_rows=256, long_row=128, chunk=256, grid=5, hot=1000, relabel=1,
+         xcd_split=1),
 ]
 
 
 def _ids(v):
-    return "k%d-e%d-l%d-c%d-g%d-h%d-r%d" % (v["kernel"], v["lds_entries"], v["long_row"], v["chunk"],
-                                          v["grid"], v["hot"], v["relabel"])
+    return "k%d-e%d-l%d-c%d-g%d-h%d-r%d-x%d" % (v["kernel"], v["lds_entries"], v["long_row"], v["chunk"],
+                                              v["grid"], v["hot"], v["relabel"], v.get("xcd_split", 0))
 
 
 def _run(grb, g, dtype, cfg, **kw):
@@ -101,7 +113,8 @@ def test_plan_config_validation(nonblocking):
            dict(kernel=0, lds_entries=3000, lds_rows=1024, long_row=2048, chunk=2048),
            dict(kernel=1, lds_entries=2048, lds_rows=1024, long_row=512, chunk=512),
            dict(kernel=0, lds_entries=2048, lds_rows=1024, long_row=4096, chunk=2048),
-           dict(kernel=1, lds_entries=512, lds_rows=256, long_row=512, chunk=1024)]
+           dict(kernel=1, lds_entries=512, lds_rows=256, long_row=512, chunk=1024),
+           dict(kernel=1, lds_entries=512, lds_rows=256, long_row=512, chunk=512, xcd_split=2)]
     for cfg in bad:
         with pytest.raises(grb.GrBError) as e:
             grb.GrM_Matrix_plan_set(g.AT, t, cfg)
