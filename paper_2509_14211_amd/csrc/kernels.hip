@@ -364,11 +364,11 @@ template <typename T>
 struct WaveLds;
 template <>
 struct WaveLds<float> {
-  static constexpr int HMAX = 23552;  // 92 KiB: with the tile staging, 156 KiB of LDS
+  static constexpr int HMAX = 32704;  // 127.75 KiB: with the entry staging, 159.9 KiB of LDS
 };
 template <>
 struct WaveLds<double> {
-  static constexpr int HMAX = 5632;   // 44 KiB: with the tile staging, 157 KiB of LDS
+  static constexpr int HMAX = 12224;  // 95.5 KiB: with the entry staging, 159.6 KiB of LDS
 };
 
 constexpr int WAVE_BLOCK = 1024;
@@ -425,44 +425,62 @@ __device__ __forceinline__ void wave_gather(__amdgpu_buffer_rsrc_t rw, const T* 
   }
 }
 
-// Row sums and epilogues of one tile whose entries are in val.
+// Row sums and epilogues of one tile whose entries are in val.  Only the
+// entries go through LDS: row bounds come from the row-pointer registers
+// by cross-lane reads, and row sums stay in registers (at most four
+// rounds), so the LDS left over holds a larger slice of the gathered
+// vector.
 template <typename T, int KE, int KP, int KR>
 __device__ __forceinline__ void wave_process(const TilePlanDev& plan, const FusedArgs<T>& a,
                                              const FusedScratch& scr, int lane, T c, const int4 cur,
                                              const T (&val)[KE], const int (&crp)[KP], const T (&cxo)[KR],
-                                             const T (&cdv)[KR], T* wval, int* wrp, T* wres, double& rho,
-                                             double& dm) {
+                                             const T (&cdv)[KR], T* wval, double& rho, double& dm) {
+  static_assert(KR <= 4, "row sums are held in four registers");
   if (cur.y > 0) {
     const int row0 = cur.x, nr = cur.y, e0 = cur.z, ne = cur.w;
 #pragma unroll
     for (int k = 0; k < KE; ++k)
       if (lane + 64 * k < ne) wval[lane + 64 * k] = val[k];
-#pragma unroll
-    for (int k = 0; k < KP; ++k)
-      if (lane + 64 * k <= nr) wrp[lane + 64 * k] = crp[k] - e0;
     wave_lds_fence();
+    // rows of up to 64/nr entries get a power-of-two group of lanes each;
+    // with more than 64 rows one lane sums row lane + 64 rd in round rd
     const int q = 64 / nr;
     const int lpr = q >= 64 ? 64 : q >= 32 ? 32 : q >= 16 ? 16 : q >= 8 ? 8 : q >= 4 ? 4 : q >= 2 ? 2 : 1;
     const int slots = 64 / lpr;
     const int grp = lane / lpr, sub = lane & (lpr - 1);
     const int rounds = (nr + slots - 1) / slots;
-    for (int rd = 0; rd < rounds; ++rd) {
-      const int rr = rd * slots + grp;
-      T v = 0;
-      if (rr < nr) {
-        const int hi = wrp[rr + 1];
-        for (int k = wrp[rr] + sub; k < hi; k += lpr) v += wval[k];
+    T res[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+    for (int rd = 0; rd < 4; ++rd) {
+      if (rd < rounds) {
+        // rows rd*slots .. rd*slots+slots-1 lie in one register of row
+        // pointers: crp[rd] when lpr == 1, else (one round) crp[0].  Only
+        // constant indices, so the register arrays are never addressed.
+        const int rr = rd * slots + grp;
+        const int k = lpr == 1 ? rd : 0;
+        const int here = lpr == 1 ? crp[rd] : crp[0];
+        const int next = lpr == 1 ? crp[rd + 1 < KP ? rd + 1 : KP - 1] : crp[1];
+        const int lo = __shfl(here, rr & 63, 64) - e0;
+        const int hiA = __shfl(here, (rr + 1) & 63, 64);
+        const int hiB = __shfl(next, (rr + 1) & 63, 64);
+        const int hi = (((rr + 1) >> 6) != k ? hiB : hiA) - e0;
+        T v = 0;
+        if (rr < nr)
+          for (int e = lo + sub; e < hi; e += lpr) v += wval[e];
+        for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        res[rd] = v;
       }
-      for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      if (sub == 0 && rr < nr) wres[rr] = v;
     }
-    wave_lds_fence();
+    // with one round the sum of row r sits in lane r*lpr; with several
+    // (lpr == 1) row lane + 64k is in this lane's res[k]
+    const T first = __shfl(res[0], (lane * lpr) & 63, 64);
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
       const int r = lane + 64 * k;
-      if (r < nr) pr_epilogue_pre(a, row0 + r, wres[r], c, cxo[k], cdv[k], rho, dm);
+      const T s = lpr == 1 ? res[k] : first;
+      if (r < nr) pr_epilogue_pre(a, row0 + r, s, c, cxo[k], cdv[k], rho, dm);
     }
-    wave_lds_fence();  // wres / wval / wrp are rewritten by the next tile
+    wave_lds_fence();  // wval is rewritten by the next tile
   } else {
     // one chunk of hub row h
     T part = 0;
@@ -513,8 +531,6 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
 
   __shared__ T hot[HMAX];
   __shared__ T sval[NW][WE];
-  __shared__ int srp[NW][WR + 1];
-  __shared__ T sres[NW][WR];
   __shared__ double sred[B / 64];
   __shared__ int sflag;
 
@@ -531,8 +547,6 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
   const __amdgpu_buffer_rsrc_t rw = buf_rsrc(a.w, (unsigned)a.ncols * (unsigned)sizeof(T));
 
   T* wval = sval[wv];
-  int* wrp = srp[wv];
-  T* wres = sres[wv];
   const TileWalk tw = tile_walk(plan, wv, NW);
   const int nwaves = tw.step, tend = tw.end;
   int t = tw.t;
@@ -551,7 +565,7 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
                       TileRegs<T, KE, KP, KR>& F) {
         wave_prefetch<T>(plan, a, min(tt + 2 * nwaves, last), pr, lane, F);
         wave_gather<T, KE>(rw, hot, H, G.ci, vG);
-        wave_process<T>(plan, a, scr, lane, c, P.td, vP, P.rp, P.xo, P.dv, wval, wrp, wres, rho, dm);
+        wave_process<T>(plan, a, scr, lane, c, P.td, vP, P.rp, P.xo, P.dv, wval, rho, dm);
       };
       for (;;) {
         step(t, X, vX, Y, vY, Z);
@@ -583,7 +597,7 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
       }
       const int tn = t + nwaves;
       if (tn < tend) wave_prefetch<T>(plan, a, tn, pr, lane, R);
-      wave_process<T>(plan, a, scr, lane, c, cur, val, crp, cxo, cdv, wval, wrp, wres, rho, dm);
+      wave_process<T>(plan, a, scr, lane, c, cur, val, crp, cxo, cdv, wval, rho, dm);
     }
   }
 
