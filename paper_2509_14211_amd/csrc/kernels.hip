@@ -529,7 +529,7 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
   constexpr bool PIPE = sizeof(T) == 4;
   if (guard && guard->active == 0) return;
 
-  __shared__ T hot[HMAX];
+  __shared__ __attribute__((aligned(16))) T hot[HMAX];
   __shared__ T sval[NW][WE];
   __shared__ double sred[B / 64];
   __shared__ int sflag;
@@ -542,7 +542,22 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
   double rho = 0.0, dm = 0.0;
 
   const int H = hot_n < HMAX ? hot_n : HMAX;
-  for (int k = tid; k < H; k += B) hot[k] = a.w[k];
+  {
+    // the slice in 16-byte pieces, every load issued before the first LDS
+    // store, so the fill costs about one memory latency
+    constexpr int HV = (int)((HMAX * sizeof(T) + 16 * B - 1) / (16 * B));
+    const int nvec = (int)((H * sizeof(T)) / 16);
+    const uint4* src = (const uint4*)a.w;
+    if (nvec > 0) {
+      uint4 tmp[HV];
+#pragma unroll
+      for (int j = 0; j < HV; ++j) tmp[j] = src[min(tid + j * B, nvec - 1)];
+#pragma unroll
+      for (int j = 0; j < HV; ++j)
+        if (tid + j * B < nvec) ((uint4*)hot)[tid + j * B] = tmp[j];
+    }
+    for (int k = (int)(nvec * 16 / sizeof(T)) + tid; k < H; k += B) hot[k] = a.w[k];
+  }
   __syncthreads();
   const __amdgpu_buffer_rsrc_t rw = buf_rsrc(a.w, (unsigned)a.ncols * (unsigned)sizeof(T));
 
