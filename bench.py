@@ -82,11 +82,15 @@ def recorded_traffic():
         return None
 
 
-def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float>") -> None:
+def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float>", min_write_kib: float = 0.0) -> None:
     """Kernel statistics (from --kernel-trace --stats) and per-dispatch PMC
     counters (from --pmc runs) found under the given directories, as
     Markdown tables; with FETCH_SIZE and WRITE_SIZE runs that include the
-    copy probe, also the calibrated traffic per launch of the fused kernels."""
+    copy probe, also the calibrated traffic per launch of the fused kernels.
+    With min_write_kib, only the traffic kernel's launches whose WRITE_SIZE
+    reaches it are counted (matched by launch order between the two runs):
+    the fused passes, when plain mxv launches of the same kernel (blocking
+    mode) share the profile."""
     import collections
     import csv
     import glob
@@ -119,7 +123,7 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float>") ->
         pmcs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
         for p in pmcs:
             vals = collections.defaultdict(list)
-            for r in csv.DictReader(open(p)):
+            for r in sorted(csv.DictReader(open(p)), key=lambda r: int(r["Dispatch_Id"])):
                 vals[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
             print("### counters per dispatch (%s)\n" % os.path.basename(p))
             print("| kernel | counter | dispatches | mean | max |")
@@ -138,8 +142,12 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float>") ->
         f_scale = COPY_BYTES / (f_copy * 1024.0)
         w_scale = COPY_BYTES / (w_copy * 1024.0)
         k = fused[0]
-        f_k = sum(counters[(k, "FETCH_SIZE")]) / len(counters[(k, "FETCH_SIZE")])
-        w_k = sum(counters[(k, "WRITE_SIZE")]) / len(counters[(k, "WRITE_SIZE")])
+        fv, wv = counters[(k, "FETCH_SIZE")], counters[(k, "WRITE_SIZE")]
+        keep = list(range(len(wv)))
+        if min_write_kib > 0 and len(fv) == len(wv):
+            keep = [i for i, w in enumerate(wv) if w >= min_write_kib]
+        f_k = sum(fv[i] for i in keep) / len(keep)
+        w_k = sum(wv[i] for i in keep) / len(keep)
         traffic = f_k * 1024.0 * f_scale + w_k * 1024.0 * w_scale
         print("### calibrated traffic of %s\n" % traffic_kernel)
         print("The copy probe reads and writes %d bytes per launch; its counters give the scale of each "
@@ -150,6 +158,8 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float>") ->
         print("- write_scale: %.4f" % (w_scale * 1.0))
         print("- kernel_fetch_kib_per_launch: %.1f" % f_k)
         print("- kernel_write_kib_per_launch: %.1f" % w_k)
+        if len(keep) != len(wv):
+            print("- launches_counted: %d of %d (WRITE_SIZE >= %.0f KiB)" % (len(keep), len(wv), min_write_kib))
         print("- traffic_bytes_per_launch: %d" % int(round(traffic)))
         if traffic_kernel == "fused_wave_kernel<float>":
             print("- source_sha256: %s" % kernel_source_sha())
@@ -181,11 +191,13 @@ def main():
                          "or all / none")
     ap.add_argument("--traffic-kernel", default="fused_wave_kernel<float>",
                     help="kernel (name substring) whose calibrated traffic --summarize-rocprof reports")
+    ap.add_argument("--min-write-kib", type=float, default=0.0,
+                    help="with --summarize-rocprof: count only traffic-kernel launches writing at least this")
     ap.add_argument("--summarize-rocprof", metavar="DIR", nargs="+",
                     help="print a text summary of the rocprofv3 CSV files under the DIRs and exit")
     args = ap.parse_args()
     if args.summarize_rocprof:
-        summarize_rocprof(args.summarize_rocprof, args.traffic_kernel)
+        summarize_rocprof(args.summarize_rocprof, args.traffic_kernel, args.min_write_kib)
         return
 
     legs = {"blocking", "m0", "ppr", "many", "fusion", "bfs", "scale25", "web", "warm"} if args.legs == "all" else (
