@@ -326,3 +326,61 @@ def test_bfs_scale22_properties(policy):
                 assert st["mxv_push"] >= 1 and st["mxv_pull"] >= 1
     finally:
         g.free()
+
+
+def test_empty_and_tiny_vectors(policy, g10):
+    """Vectors with no entries through every operation, a size-1 vector, and
+    assign without a mask (every position, stored full)."""
+    grb = policy
+    g, og = g10
+    n = g.n
+    e = _new(grb, "FP64", n)
+    grb.GrB_Vector_clear(e)
+    u = _from_svec(grb, _rand(np.random.default_rng(2), n, 0.1))
+    w = _new(grb, "FP64", n)
+    grb.GrB_Vector_eWiseMult_BinaryOp(w, None, None, _op(grb, "plus"), e, u)
+    assert grb.GrB_Vector_nvals(w) == 0
+    grb.GrB_Vector_eWiseAdd_BinaryOp(w, None, None, _op(grb, "plus"), e, u)
+    assert _same(_to_svec(grb, w, n), _to_svec(grb, u, n))
+    grb.GrB_Vector_apply(w, None, None, grb.builtin("GrB_ABS_FP64"), e)
+    assert grb.GrB_Vector_nvals(w) == 0
+    assert grb.GrB_Vector_reduce_FP64(None, grb.builtin("GrB_PLUS_MONOID_FP64"), e) == 0.0
+    grb.GrB_mxv(w, None, None, grb.builtin("GrM_PLUS_SECOND_SEMIRING_FP64"), g.AT, e)
+    assert grb.GrB_Vector_nvals(w) == 0
+    grb.GrB_Vector_assign(w, None, 2.5)
+    assert grb.GrM_Vector_format(w) == grb.GrM_FULL and grb.GrB_Vector_nvals(w) == n
+    grb.GrB_Vector_assign(w, e, 1.0, grb.builtin("GrB_DESC_R"))   # empty mask + replace: nothing left
+    assert grb.GrB_Vector_nvals(w) == 0
+    one = _new(grb, "FP32", 1)
+    grb.GrB_Vector_build(one, [0], [3.0])
+    assert grb.GrM_Vector_format(one) == grb.GrM_FULL
+    i, x = grb.GrB_Vector_extractTuples(one)
+    assert i.tolist() == [0] and x.tolist() == [3.0]
+    for h in (e, u, w, one):
+        grb.GrB_Vector_free(h)
+
+
+def test_push_through_hub_and_empty_rows(policy, oracle_mod):
+    """Push from the centre of an out-star (one frontier entry, one long
+    column) and from a leaf without out-edges (no entry at all)."""
+    from paper_2509_14211_amd import api
+    grb = policy
+    n, src, dst = synthetic.star_out(5000)
+    g = api.graph_from_edges(n, src, dst)
+    og = oracle_mod.graph_from_edges(n, src, dst)
+    try:
+        u = S.SVec(n, [0], [2.0])
+        gu = _from_svec(grb, u)
+        w = _new(grb, "FP64", n)
+        grb.GrM_reset_stats()
+        grb.GrB_mxv(w, None, None, grb.builtin("GrM_PLUS_SECOND_SEMIRING_FP64"), g.AT, gu)
+        assert _same(_to_svec(grb, w, n), S.mxv(og.rowptrT, og.colT, u))
+        assert grb.GrM_get_stats()["mxv_push"] == 1
+        v = S.SVec(n, [7], [1.0])                  # a leaf: nothing points out of it
+        gv = _from_svec(grb, v)
+        grb.GrB_mxv(w, None, None, grb.builtin("GrM_PLUS_SECOND_SEMIRING_FP64"), g.AT, gv)
+        assert grb.GrB_Vector_nvals(w) == 0
+        for h in (gu, gv, w):
+            grb.GrB_Vector_free(h)
+    finally:
+        g.free()
