@@ -82,7 +82,7 @@ def recorded_traffic():
         return None
 
 
-def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float>", min_write_kib: float = 0.0) -> None:
+def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float", min_write_kib: float = 0.0) -> None:
     """Kernel statistics (from --kernel-trace --stats) and per-dispatch PMC
     counters (from --pmc runs) found under the given directories, as
     Markdown tables; with FETCH_SIZE and WRITE_SIZE runs that include the
@@ -161,7 +161,7 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float>", mi
         if len(keep) != len(wv):
             print("- launches_counted: %d of %d (WRITE_SIZE >= %.0f KiB)" % (len(keep), len(wv), min_write_kib))
         print("- traffic_bytes_per_launch: %d" % int(round(traffic)))
-        if traffic_kernel == "fused_wave_kernel<float>":
+        if traffic_kernel == "fused_wave_kernel<float":
             print("- source_sha256: %s" % kernel_source_sha())
         print()
 
@@ -189,7 +189,7 @@ def main():
                     help="comma list of extra legs to run: blocking (also FP64), m0, ppr, many, fusion, bfs, "
                          "scale25, web, warm; "
                          "or all / none")
-    ap.add_argument("--traffic-kernel", default="fused_wave_kernel<float>",
+    ap.add_argument("--traffic-kernel", default="fused_wave_kernel<float",
                     help="kernel (name substring) whose calibrated traffic --summarize-rocprof reports")
     ap.add_argument("--min-write-kib", type=float, default=0.0,
                     help="with --summarize-rocprof: count only traffic-kernel launches writing at least this")
@@ -299,7 +299,7 @@ def main():
                            # the committed counters cover the wave kernel on the scale-22 graph only
                            "traffic": recorded_traffic() if args.scale == 22 and tuned["GrB_FP32"]["kernel"] == 1
                            else None,
-                           "kernel": "fused_wave_kernel<float>" if tuned["GrB_FP32"]["kernel"] == 1
+                           "kernel": "fused_wave_kernel<float, ...>" if tuned["GrB_FP32"]["kernel"] == 1
                            else "fused_pr_kernel<float, ...>",
                            "bytes_per_launch": bpp, "avg_launch_us": round(avg_us, 3)}
         if out["roofline"]["traffic"]:

@@ -375,14 +375,17 @@ constexpr int WAVE_BLOCK = 1024;
 constexpr int WAVE_WE = 512;
 constexpr int WAVE_WR = 256;
 
-template <typename T, int KE, int KP, int KR>
+template <typename T, int POL, int KE, int KP, int KR>
 __device__ __forceinline__ void wave_prefetch(const TilePlanDev& plan, const FusedArgs<T>& a, int t,
                                               bool pr, int lane, TileRegs<T, KE, KP, KR>& R) {
   R.td = tile_desc(plan.tiles, t);
   const int4 d = R.td;
+  // cache policy POL of these streams: the nontemporal hint keeps them out
+  // of the gathered vector's way in L2 but slows the loads themselves; it
+  // pays once the gathered vector is much larger than L2
   const __amdgpu_buffer_rsrc_t rc = buf_rsrc(a.col + d.z, (unsigned)d.w * 4u);
 #pragma unroll
-  for (int k = 0; k < KE; ++k) R.ci[k] = buf_load<int, CP_NT>(rc, (unsigned)(lane + 64 * k) * 4u);
+  for (int k = 0; k < KE; ++k) R.ci[k] = buf_load<int, POL>(rc, (unsigned)(lane + 64 * k) * 4u);
   if (d.y > 0) {
     const __amdgpu_buffer_rsrc_t rr = buf_rsrc(a.rowptr + d.x, (unsigned)(d.y + 1) * 4u);
 #pragma unroll
@@ -394,8 +397,8 @@ __device__ __forceinline__ void wave_prefetch(const TilePlanDev& plan, const Fus
 #pragma unroll
       for (int k = 0; k < KR; ++k) {
         const unsigned off = (unsigned)(lane + 64 * k) * (unsigned)sizeof(T);
-        R.xo[k] = buf_load<T, CP_NT>(rx, off);
-        R.dv[k] = buf_load<T, CP_NT>(rd, off);
+        R.xo[k] = buf_load<T, POL>(rx, off);
+        R.dv[k] = buf_load<T, POL>(rd, off);
       }
     }
   }
@@ -517,7 +520,7 @@ __device__ __forceinline__ void wave_process(const TilePlanDev& plan, const Fuse
 // epilogue inputs) of tile i+2 are in flight.  Loads are issued in the
 // order [indices of i+2][gathers of i+1], so waiting for either never waits
 // for the other.  FP64 keeps one tile in flight (register budget).
-template <typename T>
+template <typename T, int POL>
 __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan, FusedArgs<T> a,
                                                                 FusedScratch scr, int hot_n,
                                                                 const GuardDev* guard) {
@@ -573,12 +576,12 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
       TileRegs<T, KE, KP, KR> X, Y, Z;
       T vX[KE], vY[KE], vZ[KE];
       const int last = tend - 1;
-      wave_prefetch<T>(plan, a, t, pr, lane, X);
-      wave_prefetch<T>(plan, a, min(t + nwaves, last), pr, lane, Y);
+      wave_prefetch<T, POL>(plan, a, t, pr, lane, X);
+      wave_prefetch<T, POL>(plan, a, min(t + nwaves, last), pr, lane, Y);
       wave_gather<T, KE>(rw, hot, H, X.ci, vX);
       auto step = [&](int tt, TileRegs<T, KE, KP, KR>& P, T (&vP)[KE], TileRegs<T, KE, KP, KR>& G, T (&vG)[KE],
                       TileRegs<T, KE, KP, KR>& F) {
-        wave_prefetch<T>(plan, a, min(tt + 2 * nwaves, last), pr, lane, F);
+        wave_prefetch<T, POL>(plan, a, min(tt + 2 * nwaves, last), pr, lane, F);
         wave_gather<T, KE>(rw, hot, H, G.ci, vG);
         wave_process<T>(plan, a, scr, lane, c, P.td, vP, P.rp, P.xo, P.dv, wval, rho, dm);
       };
@@ -596,7 +599,7 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
     }
   } else {
     TileRegs<T, KE, KP, KR> R;
-    if (t < tend) wave_prefetch<T>(plan, a, t, pr, lane, R);
+    if (t < tend) wave_prefetch<T, POL>(plan, a, t, pr, lane, R);
     for (; t < tend; t += nwaves) {
       T val[KE];
       wave_gather<T, KE>(rw, hot, H, R.ci, val);
@@ -611,7 +614,7 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
         cdv[k] = R.dv[k];
       }
       const int tn = t + nwaves;
-      if (tn < tend) wave_prefetch<T>(plan, a, tn, pr, lane, R);
+      if (tn < tend) wave_prefetch<T, POL>(plan, a, tn, pr, lane, R);
       wave_process<T>(plan, a, scr, lane, c, cur, val, crp, cxo, cdv, wval, rho, dm);
     }
   }
@@ -648,22 +651,32 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
   }
 }
 
+// Gathered vectors larger than the L2 of all XCDs together (32 MiB) read the
+// streams with the nontemporal hint (measured: 3% faster at 134 MB, 2%
+// slower at 17 MB).
+constexpr int64_t WAVE_NT_ABOVE = 32ll << 20;
+
+template <typename T>
+static hipError_t launch_fused_wave_t(const TilePlanDev& plan, const FusedArgs<T>& a, const FusedScratch& scr,
+                                      int grid, int hot_n, const GuardDev* guard, hipStream_t s) {
+  if (grid <= 0) return hipErrorInvalidValue;
+  if ((int64_t)a.ncols * (int64_t)sizeof(T) > WAVE_NT_ABOVE)
+    hipLaunchKernelGGL((fused_wave_kernel<T, CP_NT>), dim3(grid), dim3(WAVE_BLOCK), 0, s, plan, a, scr, hot_n, guard);
+  else
+    hipLaunchKernelGGL((fused_wave_kernel<T, 0>), dim3(grid), dim3(WAVE_BLOCK), 0, s, plan, a, scr, hot_n, guard);
+  return hipGetLastError();
+}
+
 hipError_t launch_fused_wave_f32(const TilePlanDev& plan, const FusedArgs<float>& a,
                                  const FusedScratch& scr, int grid, int hot_n,
                                  const GuardDev* guard, hipStream_t s) {
-  if (grid <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fused_wave_kernel<float>, dim3(grid), dim3(WAVE_BLOCK), 0, s, plan, a, scr,
-                     hot_n, guard);
-  return hipGetLastError();
+  return launch_fused_wave_t<float>(plan, a, scr, grid, hot_n, guard, s);
 }
 
 hipError_t launch_fused_wave_f64(const TilePlanDev& plan, const FusedArgs<double>& a,
                                  const FusedScratch& scr, int grid, int hot_n,
                                  const GuardDev* guard, hipStream_t s) {
-  if (grid <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fused_wave_kernel<double>, dim3(grid), dim3(WAVE_BLOCK), 0, s, plan, a, scr,
-                     hot_n, guard);
-  return hipGetLastError();
+  return launch_fused_wave_t<double>(plan, a, scr, grid, hot_n, guard, s);
 }
 
 int wave_hot_max(int type) { return type == T_FP32 ? WaveLds<float>::HMAX : WaveLds<double>::HMAX; }
