@@ -165,3 +165,34 @@ def test_scale25_fp32_fused_matches_oracle(gpu, oracle_mod):
         assert abs(x.sum() - 1.0) <= 1e-5
     finally:
         g.free()
+
+
+def test_scale23_fp64_batch_takes_the_wide_kernel(gpu, oracle_mod):
+    """64 FP64 columns on R-MAT scale 23: each n x k operand is 4.3 GB, past
+    what 32-bit buffer offsets address, so the pass runs the 64-bit
+    addressed kernel.  Sampled columns against the oracle at the same pass
+    count (relative L1 1e-12), every column's mass 1."""
+    from paper_2509_14211_amd import api
+    oracle_mod.set_threads(_threads())
+    print("scale-23 graph on the GPU", flush=True)
+    g = api.rmat_graph(23)
+    try:
+        assert g.n * 64 * 8 > 0xFFFFFF00
+        sets = [s.tolist() for s in synthetic.ppr_seed_sets(g.n, 64, seed=23)]
+        X = torch.empty(g.n * 64, dtype=torch.float64, device="cuda")
+        it, col_it, col_res = gpu.GrM_ppr_batch(X, gpu.builtin("GrB_FP64"), sets, g.AT, g.outdeg, D, 1e-9, 200)
+        print("scale 23 fp64 batch: %d passes" % it, flush=True)
+        X = X.reshape(g.n, 64)
+        sums = X.sum(dim=0).cpu().numpy()
+        assert np.all(np.abs(sums - 1.0) <= 1e-9)
+        assert col_res.max() <= 1e-9
+        cols = [0, 31, 63]
+        Xs = X[:, cols].cpu().numpy()
+        del X
+        print("scale-23 graph in the oracle", flush=True)
+        og = oracle_mod.rmat_graph(23)
+        for j, q in enumerate(cols):
+            ref = oracle_mod.ppr(og, sets[q], D, fixed_iters=it)
+            assert np.abs(Xs[:, j] - ref.x).sum() / np.abs(ref.x).sum() <= 1e-12, q
+    finally:
+        g.free()
