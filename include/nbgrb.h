@@ -125,7 +125,7 @@ extern GrB_BinaryOp GrM_ABSDIFF_FP32, GrM_ABSDIFF_FP64; /* |x - y| */
 
 extern GrB_Monoid GrB_PLUS_MONOID_FP32, GrB_PLUS_MONOID_FP64;
 
-/* Semirings accepted by GrB_mxv / GrB_mxm.  The matrices built by this
+/* Semirings accepted by GrB_mxv.  The matrices built by this
  * library are patterns whose stored values are all 1 (iso-valued), so
  * plus-times and plus-second compute the same product. */
 extern GrB_Semiring GrB_PLUS_TIMES_SEMIRING_FP32, GrB_PLUS_TIMES_SEMIRING_FP64;

@@ -42,8 +42,9 @@ void require_init() {
 
 void* raw_alloc(size_t bytes) {
   Ctx& c = g_ctx;
-  if (c.fail_after > 0) {
-    if (--c.fail_after == 0) return nullptr;
+  if (c.fail_after > 0 && --c.fail_after == 0) {
+    c.fail_after = -1;  // the test hook fired: the caller must not retry
+    return nullptr;
   }
   void* p = nullptr;
   if (c.alloc) {
@@ -85,6 +86,7 @@ BufP dev_alloc(size_t bytes) {
         for (void* q : kv.second) raw_release(q);
       c.cache.clear();
       if (c.fail_after == 0) p = raw_alloc(rb);
+      if (c.fail_after < 0) c.fail_after = 0;  // one failure per arming of the hook
       if (!p) fail(GrB_OUT_OF_MEMORY, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
   }
