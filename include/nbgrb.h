@@ -686,8 +686,11 @@ GrB_Info GrM_gnn_predict_x0(GrB_Vector x0, GrM_GNN net, GrB_Matrix A, GrB_Matrix
 GrB_Info GrM_stream_copy(void *dst_dev, const void *src_dev, size_t bytes);
 
 /* Per-launch timing of fused PageRank kernels (HIP events recorded around
- * every fused launch on the library stream while enabled).  Reading the
- * total synchronises. */
+ * every fused launch on the library stream while enabled).  GrM_timing_read
+ * synchronises, returns the summed duration and the number of launches
+ * recorded since the previous read, and drops those records.  The count
+ * includes passes the device loop guard turned into no-ops (a driver
+ * enqueues check_every passes between host checks). */
 GrB_Info GrM_timing_enable(bool on);
 GrB_Info GrM_timing_read(double *total_ms, int64_t *launches);
 

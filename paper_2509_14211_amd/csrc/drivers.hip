@@ -110,7 +110,8 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
   std::vector<NodeP> hist{x.node};
   int64_t base = 0;
   GuardDev hg{};
-  int batch = check_every;
+  // no pass beyond itermax is enqueued (the guard would only skip it)
+  int batch = check_every < itermax ? check_every : itermax;
   for (;;) {
     for (int j = 0; j < batch; ++j) {
       GB_Vector_opaque w{MAGIC_VEC, T, n, nullptr}, s{MAGIC_VEC, T, n, nullptr};
