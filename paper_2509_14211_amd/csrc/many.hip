@@ -7,12 +7,14 @@
 // vertices are numbered by decreasing out-degree, so the leading slice of
 // the gathered vector -- all of it for graphs up to the LDS capacity -- is
 // kept in LDS and refreshed after every pass.  Rows are reduced by groups of
-// lanes (a power of two per graph from its mean degree) with shuffles; the
-// residual and the dangling mass are summed in FP64 in a fixed order.
+// lanes (a power of two per graph from its mean degree) with shuffles, rows
+// longer than MANY_LONG_ROW by one wavefront each; the residual and the
+// dangling mass are summed in FP64 in a fixed order.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
+#include "device_util.h"
 #include "kernels.h"
 
 namespace nbgrb {
@@ -60,9 +62,9 @@ __device__ __forceinline__ double bsum(double v, double* red, double* out) {
 template <typename T>
 __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
   constexpr int HM = ManyLds<T>::H;
+  constexpr int RPG = sizeof(T) == 4 ? 8 : 4;  // rows per lane group and step (register budget)
   __shared__ T hot[HM];
   __shared__ double red[MNW];
-  __shared__ T redT[MNW];
   __shared__ double bcast;
   __shared__ int sq;
   const int tid = threadIdx.x;
@@ -111,56 +113,97 @@ __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
       const double cd = (1.0 - p.damping) / (double)n + (p.uniform ? p.damping * D / (double)n : 0.0);
       const T c = (T)cd;
       double rl = 0.0, dn = 0.0;
-      for (int base = 0; base < n; base += groups) {
-        const int row = base + grp;
-        T s = 0;
-        bool mine = row < n;
-        if (mine) {
-          const int e0 = rp[row], e1 = rp[row + 1];
-          mine = e1 - e0 <= MANY_LONG_ROW;  // long rows: second phase
-          if (mine)
-            for (int e = e0 + sub; e < e1; e += lpr) {
-              const int j = col[e];
-              s += j < H ? hot[j] : wc[j];
-            }
+      // RPG rows per lane group and step: their row bounds, old ranks and
+      // degrees, then their column indices and gathers, are issued together
+      // (out-of-range lanes load nothing), so one step waits for a few
+      // memory latencies instead of a few per row
+      const __amdgpu_buffer_rsrc_t rrp = buf_rsrc(rp, (unsigned)(n + 1) * 4u);
+      const __amdgpu_buffer_rsrc_t rcol = buf_rsrc(col, (unsigned)G.m * 4u);
+      const __amdgpu_buffer_rsrc_t rw = buf_rsrc(wc, (unsigned)n * (unsigned)sizeof(T));
+      const __amdgpu_buffer_rsrc_t rx = buf_rsrc(xc, (unsigned)n * (unsigned)sizeof(T));
+      const __amdgpu_buffer_rsrc_t rdg = buf_rsrc(deg, (unsigned)n * 4u);
+      for (int base = 0; base < n; base += groups * RPG) {
+        int lo[RPG], len[RPG], dg[RPG];
+        T xo[RPG], s[RPG];
+#pragma unroll
+        for (int k = 0; k < RPG; ++k) {
+          const int row = base + grp + k * groups;
+          const unsigned off = row < n ? (unsigned)row * 4u : BUF_SKIP;
+          lo[k] = buf_load<int>(rrp, off);
+          len[k] = buf_load<int>(rrp, off, 4u);
+          dg[k] = buf_load<int>(rdg, off);
+          xo[k] = buf_load<T>(rx, row < n ? (unsigned)row * (unsigned)sizeof(T) : BUF_SKIP);
         }
-        for (int o = lpr >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (sub == 0 && mine) {
-          const T r = c + s;
-          const T xo = xc[row];
-          const int dg = deg[row];
-          const T dv = dg > 0 ? dmp * ((T)1 / (T)dg) : (T)0;
-          xn[row] = r;
-          wn[row] = r * dv;
-          rl += fabs((double)xo - (double)r);
-          if (dg == 0) dn += (double)r;
+        int maxlen = 0;
+#pragma unroll
+        for (int k = 0; k < RPG; ++k) {
+          len[k] -= lo[k];
+          // long rows: second phase
+          if (base + grp + k * groups >= n || len[k] > MANY_LONG_ROW) len[k] = -1;
+          maxlen = len[k] > maxlen ? len[k] : maxlen;
+          s[k] = 0;
+        }
+        for (int t = sub; t < maxlen; t += lpr) {
+          int j[RPG];
+#pragma unroll
+          for (int k = 0; k < RPG; ++k) j[k] = buf_load<int>(rcol, t < len[k] ? (unsigned)(lo[k] + t) * 4u : BUF_SKIP);
+#pragma unroll
+          for (int k = 0; k < RPG; ++k) {
+            const bool v = t < len[k];
+            const bool h = j[k] < H;
+            const T g = buf_load<T>(rw, v && !h ? (unsigned)j[k] * (unsigned)sizeof(T) : BUF_SKIP);
+            const T hv = hot[h ? j[k] : 0];
+            if (v) s[k] += h ? hv : g;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < RPG; ++k) {
+          T sk = s[k];
+          for (int o = lpr >> 1; o > 0; o >>= 1) sk += __shfl_xor(sk, o, 64);
+          const int row = base + grp + k * groups;
+          if (sub == 0 && len[k] >= 0) {
+            const T r = c + sk;
+            const T dv = dg[k] > 0 ? dmp * ((T)1 / (T)dg[k]) : (T)0;
+            xn[row] = r;
+            wn[row] = r * dv;
+            rl += fabs((double)xo[k] - (double)r);
+            if (dg[k] == 0) dn += (double)r;
+          }
         }
       }
-      // long rows: every thread takes a strided share, fixed tree after
-      for (int q = 0; q < G.nlong; ++q) {
-        const int row = p.longrows[G.loff + q];
-        const int e1 = rp[row + 1];
-        T s = 0;
-        for (int e = rp[row] + tid; e < e1; e += MB) {
-          const int j = col[e];
-          s += j < H ? hot[j] : wc[j];
+      // long rows: one wavefront per row, sixteen rows at a time, four
+      // loads per lane in flight; the row's sum is a fixed tree
+      {
+        const int wv = tid >> 6, lane = tid & 63;
+        for (int q = wv; q < G.nlong; q += MNW) {
+          const int row = p.longrows[G.loff + q];
+          const int e0 = rp[row], e1 = rp[row + 1];
+          T sl = 0;
+          for (int e = e0 + lane; e < e1; e += 256) {
+            int j[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) j[k] = buf_load<int>(rcol, e + 64 * k < e1 ? (unsigned)(e + 64 * k) * 4u : BUF_SKIP);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const bool v = e + 64 * k < e1;
+              const bool h = j[k] < H;
+              const T g = buf_load<T>(rw, v && !h ? (unsigned)j[k] * (unsigned)sizeof(T) : BUF_SKIP);
+              const T hv = hot[h ? j[k] : 0];
+              if (v) sl += h ? hv : g;
+            }
+          }
+          sl = wsum(sl);
+          if (lane == 0) {
+            const T r = c + sl;
+            const T xo = xc[row];
+            const int dg = deg[row];
+            const T dv = dg > 0 ? dmp * ((T)1 / (T)dg) : (T)0;
+            xn[row] = r;
+            wn[row] = r * dv;
+            rl += fabs((double)xo - (double)r);
+            if (dg == 0) dn += (double)r;
+          }
         }
-        s = wsum(s);
-        if ((tid & 63) == 0) redT[tid >> 6] = s;
-        __syncthreads();
-        if (tid == 0) {
-          T t = 0;
-          for (int w = 0; w < MNW; ++w) t += redT[w];
-          const T r = c + t;
-          const T xo = xc[row];
-          const int dg = deg[row];
-          const T dv = dg > 0 ? dmp * ((T)1 / (T)dg) : (T)0;
-          xn[row] = r;
-          wn[row] = r * dv;
-          rl += fabs((double)xo - (double)r);
-          if (dg == 0) dn += (double)r;
-        }
-        __syncthreads();
       }
       __syncthreads();  // every row of the pass is written
       rho = bsum(rl, red, &bcast);
