@@ -547,9 +547,15 @@ GrB_Info GrM_ppr_stream(void *X, GrB_Type type, int nsets, const int32_t *seed_p
  * X (device, total vertices entries of `type`) receives the ranks of graph
  * g at offsets voff[g] .. voff[g+1] in the graph's original numbering;
  * iters / resid (host arrays of ngraphs, may be NULL) receive each graph's
- * passes and last residual (reading them synchronises).
+ * passes and last residual (reading them synchronises, and reports
+ * GrB_PANIC if a team of workgroups gave up waiting for a member).
+ *
+ * Graphs much larger than the mean share of one compute unit are solved
+ * by a team of up to GrM_set_many_team_max workgroups (default 8; 1 solves
+ * every graph with one workgroup), sized when the multigraph is created.
  * ---------------------------------------------------------------------- */
 typedef struct GB_Multigraph_opaque *GrM_Multigraph;
+GrB_Info GrM_set_many_team_max(int max_team);
 GrB_Info GrM_Multigraph_new(GrM_Multigraph *mg, int ngraphs, const GrB_Matrix *AT);
 GrB_Info GrM_Multigraph_free(GrM_Multigraph *mg);
 /* voff: host array of ngraphs + 1 vertex offsets. */

@@ -623,7 +623,8 @@ struct GB_Multigraph_opaque {
   int ngraphs;
   int64_t nv, ne;
   std::vector<int64_t> voff;
-  BufP graphs, queue, qnext, rowptr, col, deg, inv, longrows, xa, xb, wa, wb, iters, resid;
+  int nslots = 0;
+  BufP graphs, queue, qnext, rowptr, col, deg, inv, longrows, xa, xb, wa, wb, iters, resid, team_bar, team_part, team_err;
   std::vector<std::shared_ptr<MatData>> keep;  // relabeled copies stay alive
   struct Exec {
     int type;
@@ -675,6 +676,8 @@ GrB_Info GrM_Multigraph_new(GrM_Multigraph* mg, int ngraphs, const GrB_Matrix* A
     G.lpr = lpr;
     G.nlong = 0;
     G.loff = 0;
+    G.team = 1;
+    G.pad_ = 0;
     G.voff = nv;
     G.eoff = ne;
     G.roff = nr;
@@ -733,14 +736,38 @@ GrB_Info GrM_Multigraph_new(GrM_Multigraph* mg, int ngraphs, const GrB_Matrix* A
   std::vector<int> order((size_t)ngraphs);
   for (int g = 0; g < ngraphs; ++g) order[(size_t)g] = g;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return gs[(size_t)a].m > gs[(size_t)b].m; });
-  m->queue = dev_alloc(sizeof(int) * order.size());
+  // Teams: a graph gets about one workgroup per mean per-CU share of all
+  // edges (at most many_team_max).  Team slots lead the queue and number at
+  // most the grid (one workgroup per compute unit), so every member of
+  // every team starts at once.
+  {
+    const double share = std::max(1.0, (double)ne / (double)c.cus);
+    int used = 0;
+    for (int g : order) {
+      ManyGraph& G = gs[(size_t)g];
+      int t = (int)std::llround((double)G.m / share);
+      t = std::max(1, std::min(t, std::min(c.many_team_max, MANY_MAX_TEAM)));
+      if (t > 1 && used + t > c.cus) t = 1;
+      if (t > 1) used += t;
+      G.team = t;
+    }
+  }
+  std::stable_partition(order.begin(), order.end(), [&](int g) { return gs[(size_t)g].team > 1; });
+  std::vector<int> slots;
+  for (int g : order)
+    for (int k = 0; k < gs[(size_t)g].team; ++k) slots.push_back(g * MANY_MAX_TEAM + k);
+  m->nslots = (int)slots.size();
+  m->team_bar = dev_alloc(sizeof(unsigned) * (size_t)ngraphs);
+  m->team_part = dev_alloc(sizeof(double) * 4 * MANY_MAX_TEAM * (size_t)ngraphs);
+  m->team_err = dev_alloc(sizeof(int));
+  m->queue = dev_alloc(sizeof(int) * slots.size());
   m->longrows = dev_alloc(sizeof(int) * std::max<size_t>(longrows.size(), 1));
   if (!longrows.empty())
     hip_check(hipMemcpyAsync(m->longrows->p, longrows.data(), sizeof(int) * longrows.size(), hipMemcpyHostToDevice,
                              c.stream), "upload");
   hip_check(hipMemcpyAsync(m->graphs->p, gs.data(), sizeof(ManyGraph) * gs.size(), hipMemcpyHostToDevice, c.stream),
             "upload");
-  hip_check(hipMemcpyAsync(m->queue->p, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, c.stream),
+  hip_check(hipMemcpyAsync(m->queue->p, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice, c.stream),
             "upload");
   hip_check(hipStreamSynchronize(c.stream), "sync");
   hip_check(hipStreamCreateWithFlags(&m->aux, hipStreamNonBlocking), "stream");
@@ -813,6 +840,10 @@ GrB_Info GrM_pagerank_many(void* X, GrB_Type type, GrM_Multigraph mg, double dam
     a.queue = (const int*)mg->queue->p;
     a.queue_next = (int*)mg->qnext->p;
     a.ngraphs = mg->ngraphs;
+    a.nslots = mg->nslots;
+    a.team_bar = (unsigned*)mg->team_bar->p;
+    a.team_part = (double*)mg->team_part->p;
+    a.team_err = (int*)mg->team_err->p;
     a.rowptr = (const int*)mg->rowptr->p;
     a.col = (const int*)mg->col->p;
     a.deg = (const int*)mg->deg->p;
@@ -855,7 +886,19 @@ GrB_Info GrM_pagerank_many(void* X, GrB_Type type, GrM_Multigraph mg, double dam
     hip_check(hipMemcpyAsync(resid, mg->resid->p, sizeof(double) * (size_t)mg->ngraphs, hipMemcpyDeviceToHost,
                              c.stream),
               "copy");
+  int team_err = 0;
+  if (iters || resid)
+    hip_check(hipMemcpyAsync(&team_err, mg->team_err->p, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy");
   if (iters || resid) hip_check(hipStreamSynchronize(c.stream), "sync");
+  if (team_err) fail(GrB_PANIC, "a team of workgroups gave up waiting for a member");
+  API_END
+}
+
+GrB_Info GrM_set_many_team_max(int max_team) {
+  API_BEGIN
+  require_init();
+  if (max_team < 1 || max_team > MANY_MAX_TEAM) fail(GrB_INVALID_VALUE, "max_team must be 1..8");
+  ctx().many_team_max = max_team;
   API_END
 }
 

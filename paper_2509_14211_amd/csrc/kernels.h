@@ -265,15 +265,22 @@ hipError_t launch_rows_permute(const void* in, int type, const int* idx, void* o
 struct ManyGraph {
   int n, m, lpr, nlong;   // nlong rows longer than MANY_LONG_ROW entries
   int64_t voff, eoff, roff, loff;
+  int team;               // workgroups solving this graph together, 1..MANY_MAX_TEAM
+  int pad_;
 };
+constexpr int MANY_MAX_TEAM = 8;
 // Rows with more entries are summed by the whole workgroup, not by one
 // lane group, so no lane accumulates more than this many terms serially.
 constexpr int MANY_LONG_ROW = 256;
 struct ManyArgs {
   const ManyGraph* graphs;
-  const int* queue;   // graph indices, largest first
+  const int* queue;   // graph * MANY_MAX_TEAM + member: teams first, then single graphs, largest first
   int* queue_next;    // reset to 0 by the launch
+  unsigned* team_bar;   // per graph: team arrivals, reset to 0 by the launch
+  double* team_part;    // per graph: [barrier parity][member][residual, dangling]
+  int* team_err;        // set when a team member waited too long (reset by the launch)
   int ngraphs;
+  int nslots;         // queue entries: one per team member, one per single graph
   const int* rowptr;
   const int* col;
   const int* deg;     // out-degree per vertex (execution numbering)
@@ -289,7 +296,8 @@ struct ManyArgs {
   double damping, tol;
   int itermax, uniform;
 };
-// Queue reset + the persistent kernel (grid workgroups of 1024 threads).
+// Queue, barrier and error reset + the persistent kernel (grid workgroups of
+// 1024 threads; the team slots at the head of the queue must number at most grid).
 hipError_t launch_pr_many(const ManyArgs& a, int type, int grid, hipStream_t s);
 
 // ------------------------------------------------------------ graph build

@@ -1,15 +1,24 @@
 // Many independent PageRank problems in one persistent launch.
 //
-// Every workgroup (1024 threads, one per compute unit) takes whole graphs
-// from a queue ordered by decreasing size and runs the fused pass on each
-// until its own residual reaches the tolerance: no workgroup ever waits for
-// another, and each exits when the queue is empty.  Inside a graph the
-// vertices are numbered by decreasing out-degree, so the leading slice of
-// the gathered vector -- all of it for graphs up to the LDS capacity -- is
-// kept in LDS and refreshed after every pass.  Rows are reduced by groups of
-// lanes (a power of two per graph from its mean degree) with shuffles, rows
-// longer than MANY_LONG_ROW by one wavefront each; the residual and the
-// dangling mass are summed in FP64 in a fixed order.
+// Every workgroup (1024 threads, one per compute unit) takes work from a
+// queue: first the graphs large enough to be solved by a team of
+// workgroups (one queue slot per member), then whole graphs, largest first.
+// A single workgroup runs the fused pass on its graph until the graph's own
+// residual reaches the tolerance and never waits for another workgroup.
+// The members of a team split the rows of every pass between them and meet
+// at a barrier of their own after it: they publish their residual and
+// dangling partial sums, wait until every member has arrived, and add the
+// partials in member order, so every member takes the same loop decision.
+// Team slots come first and number at most the grid, so every member is
+// running when the first barrier is reached; a wait still gives up after
+// about ten seconds and flags the launch as failed instead of hanging.
+// Inside a graph the vertices are numbered by decreasing out-degree, so the
+// leading slice of the gathered vector -- all of it for graphs up to the LDS
+// capacity -- is kept in LDS and refreshed after every pass.  Rows are
+// reduced by groups of lanes (a power of two per graph from its mean
+// degree) with shuffles, rows longer than MANY_LONG_ROW by one wavefront
+// each; the residual and the dangling mass are summed in FP64 in a fixed
+// order.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -59,14 +68,47 @@ __device__ __forceinline__ double bsum(double v, double* red, double* out) {
   return r;
 }
 
+constexpr uint64_t TEAM_WAIT_TICKS = 1000000000ull;  // about 10 s of the 100 MHz wall clock
+
+// Thread 0: wait until *bar reaches target; false, with *err set, when the
+// wait runs out.
+__device__ bool team_wait(unsigned* bar, unsigned target, int* err) {
+  const uint64_t t0 = wall_clock64();
+  while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (wall_clock64() - t0 > TEAM_WAIT_TICKS) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+// Team barrier (every thread calls it): this workgroup's global writes are
+// released, its arrival counted, and once all members have arrived their
+// writes are acquired (which also drops this compute unit's stale cached
+// lines of the shared vectors).  False when the wait ran out.
+__device__ bool team_sync(unsigned* bar, unsigned target, int* err, int* sflag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    *sflag = team_wait(bar, target, err) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool ok = *sflag != 0;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
+}
+
 template <typename T>
 __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
   constexpr int HM = ManyLds<T>::H;
-  constexpr int RPG = sizeof(T) == 4 ? 8 : 4;  // rows per lane group and step (register budget)
+  constexpr int RPG = 4;  // rows per lane group and step (register budget)
   __shared__ T hot[HM];
   __shared__ double red[MNW];
   __shared__ double bcast;
-  __shared__ int sq;
+  __shared__ int sq, sflag;
   const int tid = threadIdx.x;
 
   for (;;) {
@@ -74,8 +116,13 @@ __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
     __syncthreads();
     const int q = sq;
     __syncthreads();
-    if (q >= p.ngraphs) break;
-    const ManyGraph G = p.graphs[p.queue[q]];
+    if (q >= p.nslots) break;
+    const int gi = p.queue[q] / MANY_MAX_TEAM, mk = p.queue[q] % MANY_MAX_TEAM;
+    const ManyGraph G = p.graphs[gi];
+    const int team = G.team;
+    unsigned* bar = p.team_bar + gi;
+    double* part = p.team_part + (int64_t)gi * (4 * MANY_MAX_TEAM);
+    unsigned gen = 0;
     const int n = G.n;
     const int* rp = p.rowptr + G.roff;
     const int* col = p.col + G.eoff;
@@ -90,19 +137,23 @@ __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
     const int grp = tid / lpr, sub = tid & (lpr - 1);
     const T dmp = (T)p.damping;
 
-    // start: x = 1/n, w = x .* d, D = mass on dangling vertices
+    // start: x = 1/n, w = x .* d, D = mass on dangling vertices (every
+    // member computes D and its slice itself, and stores its share of x, w)
     double dl = 0.0;
     const T x0 = (T)(1.0 / (double)n);
     for (int i = tid; i < n; i += MB) {
       const int dg = deg[i];
       const T dv = dg > 0 ? dmp * ((T)1 / (T)dg) : (T)0;
-      xa[i] = x0;
       const T wv = x0 * dv;
-      wa[i] = wv;
+      if ((i / MB) % team == mk) {
+        xa[i] = x0;
+        wa[i] = wv;
+      }
       if (i < H) hot[i] = wv;
       if (dg == 0) dl += (double)x0;
     }
     double D = bsum(dl, red, &bcast);
+    if (team > 1 && !team_sync(bar, ++gen * (unsigned)team, p.team_err, &sflag)) return;
     double rho = 1.0;
     int it = 0;
     T* xc = xa;
@@ -122,7 +173,7 @@ __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
       const __amdgpu_buffer_rsrc_t rw = buf_rsrc(wc, (unsigned)n * (unsigned)sizeof(T));
       const __amdgpu_buffer_rsrc_t rx = buf_rsrc(xc, (unsigned)n * (unsigned)sizeof(T));
       const __amdgpu_buffer_rsrc_t rdg = buf_rsrc(deg, (unsigned)n * 4u);
-      for (int base = 0; base < n; base += groups * RPG) {
+      for (int base = mk * groups * RPG; base < n; base += team * groups * RPG) {
         int lo[RPG], len[RPG], dg[RPG];
         T xo[RPG], s[RPG];
 #pragma unroll
@@ -175,8 +226,8 @@ __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
       // loads per lane in flight; the row's sum is a fixed tree
       {
         const int wv = tid >> 6, lane = tid & 63;
-        for (int q = wv; q < G.nlong; q += MNW) {
-          const int row = p.longrows[G.loff + q];
+        for (int lq = wv + MNW * mk; lq < G.nlong; lq += MNW * team) {
+          const int row = p.longrows[G.loff + lq];
           const int e0 = rp[row], e1 = rp[row + 1];
           T sl = 0;
           for (int e = e0 + lane; e < e1; e += 256) {
@@ -206,8 +257,28 @@ __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
         }
       }
       __syncthreads();  // every row of the pass is written
-      rho = bsum(rl, red, &bcast);
-      D = bsum(dn, red, &bcast);
+      const double brl = bsum(rl, red, &bcast);
+      const double bdn = bsum(dn, red, &bcast);
+      if (team == 1) {
+        rho = brl;
+        D = bdn;
+      } else {
+        // partials in the slot of this barrier's parity: a member can only
+        // overwrite it after every member has read it (two barriers later)
+        double* pp = part + (int64_t)((gen + 1) & 1) * (2 * MANY_MAX_TEAM);
+        if (tid == 0) {
+          publish(&pp[2 * mk], brl);
+          publish(&pp[2 * mk + 1], bdn);
+        }
+        if (!team_sync(bar, ++gen * (unsigned)team, p.team_err, &sflag)) return;
+        double a0 = 0.0, a1 = 0.0;
+        for (int u = 0; u < team; ++u) {
+          a0 += consume(&pp[2 * u]);
+          a1 += consume(&pp[2 * u + 1]);
+        }
+        rho = a0;
+        D = a1;
+      }
       ++it;
       // the next pass gathers the new pre-scaled vector
       for (int i = tid; i < H; i += MB) hot[i] = wn[i];
@@ -222,22 +293,30 @@ __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
     // ranks back in the graph's original numbering
     T* out = (T*)p.out + G.voff;
     const int* inv = p.inv + G.voff;
-    for (int v = tid; v < n; v += MB) out[v] = xc[inv[v]];
-    if (tid == 0) {
-      p.iters[p.queue[q]] = it;
-      p.resid[p.queue[q]] = rho;
+    for (int v = tid; v < n; v += MB)
+      if ((v / MB) % team == mk) out[v] = xc[inv[v]];
+    if (tid == 0 && mk == 0) {
+      p.iters[gi] = it;
+      p.resid[gi] = rho;
     }
     __syncthreads();
   }
 }
 
-__global__ void queue_reset_kernel(int* q) { *q = 0; }
+__global__ void queue_reset_kernel(int* q, unsigned* bar, int ngraphs, int* err) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ngraphs; i += gridDim.x * blockDim.x) bar[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *q = 0;
+    *err = 0;
+  }
+}
 
 }  // namespace
 
 hipError_t launch_pr_many(const ManyArgs& a, int type, int grid, hipStream_t s) {
   if (grid <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, s, a.queue_next);
+  hipLaunchKernelGGL(queue_reset_kernel, dim3((a.ngraphs + 255) / 256), dim3(256), 0, s, a.queue_next, a.team_bar,
+                     a.ngraphs, a.team_err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (type == T_FP32)

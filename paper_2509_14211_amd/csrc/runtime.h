@@ -265,6 +265,8 @@ struct Ctx {
   // also fused into generated kernels
   int fusion = 1;
   int format_policy = FP_ESTIMATE;
+  // largest team of workgroups per graph in the many-graph launch
+  int many_team_max = 8;
   // plan configuration override chosen by the autotuner (per matrix id)
   std::map<std::pair<uint64_t, int>, PlanConfig> tuned;
 };

@@ -109,6 +109,7 @@ _FUNCS = {
     "GrB_Vector_assign_INT32": [vp, vp, vp, i32, vp, u64, vp],
     "GrM_Vector_format": [ctypes.POINTER(i32), vp],
     "GrM_set_format_policy": [i32],
+    "GrM_set_many_team_max": [i32],
     "GrM_code_cache_clear": [],
     "GrB_Scalar_new": [PV, vp],
     "GrB_Scalar_free": [PV],
@@ -363,6 +364,11 @@ def GrM_Vector_format(v) -> int:
 
 def GrM_set_format_policy(policy: int):
     _call("GrM_set_format_policy", policy)
+
+
+def GrM_set_many_team_max(max_team: int):
+    """Largest team of workgroups per graph in later GrM_Multigraph_new calls (1..8)."""
+    _call("GrM_set_many_team_max", max_team)
 
 
 def GrM_error() -> str:

@@ -1,6 +1,7 @@
 """Many independent graphs in one persistent, graph-captured launch: every
-graph's ranks against the FP64 oracle at that graph's own pass count, and
-replays of the captured launch reproduce the first run bit for bit."""
+graph's ranks against the FP64 oracle at that graph's own pass count, with
+and without teams of workgroups per graph, and replays of the captured
+launch reproduce the first run bit for bit."""
 import numpy as np
 import pytest
 import torch
@@ -27,11 +28,19 @@ def _graphs(oracle_mod):
     return gs, ogs
 
 
+@pytest.mark.parametrize("team", [8, 1])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_many_matches_oracle(nonblocking, oracle_mod, mode):
+def test_many_matches_oracle(nonblocking, oracle_mod, mode, team):
+    """team 8: every graph with edges is solved by a team of workgroups (the
+    graphs are small next to the per-CU share of all edges); team 1: one
+    workgroup per graph."""
     grb = nonblocking
     gs, ogs = _graphs(oracle_mod)
-    mg = grb.GrM_Multigraph_new([g.AT for g in gs])
+    grb.GrM_set_many_team_max(team)
+    try:
+        mg = grb.GrM_Multigraph_new([g.AT for g in gs])
+    finally:
+        grb.GrM_set_many_team_max(8)
     off = grb.GrM_Multigraph_offsets(mg, len(gs))
     assert off[-1] == sum(g.n for g in gs)
     for dtype, tol, bound in ((torch.float64, 1e-10, None), (torch.float32, 1e-6, 1e-5)):
@@ -83,6 +92,9 @@ def test_many_rmat_workload_sample(nonblocking, oracle_mod):
 
 def test_many_errors(nonblocking):
     grb = nonblocking
+    for bad in (0, 9):
+        with pytest.raises(grb.GrBError):
+            grb.GrM_set_many_team_max(bad)
     with pytest.raises(grb.GrBError):
         grb.GrM_Multigraph_new([])
     A = grb.GrB_Matrix_new(grb.builtin("GrB_FP32"), 3, 4)
