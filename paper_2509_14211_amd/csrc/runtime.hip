@@ -436,6 +436,11 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
   }
   hipError_t e;
   const bool wave = plan->cfg.kernel == K_WAVE;
+  // no more workgroups than there is tile work: the block kernel takes tiles
+  // per workgroup, the wave kernel per wavefront (16 per workgroup); a small
+  // matrix would otherwise pay for dispatching thousands of idle workgroups
+  const int ntl = std::max(1, plan->dev.ntiles);
+  const int grid = std::max(1, std::min(plan->cfg.grid, wave ? (ntl + 15) / 16 : ntl));
   if (f.type == T_FP32) {
     FusedArgs<float> a{};
     a.rowptr = (const int*)A->rowptr->p;
@@ -459,8 +464,8 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     a.c = f.c;
     a.rho_out = f.rho;
     a.D_out = f.D;
-    e = wave ? launch_fused_wave_f32(plan->dev, a, scr, plan->cfg.grid, plan->cfg.hot, c.guard, c.stream)
-             : launch_fused_f32(plan->dev, a, scr, plan->cfg.grid, plan->cfg.lds_entries,
+    e = wave ? launch_fused_wave_f32(plan->dev, a, scr, grid, plan->cfg.hot, c.guard, c.stream)
+             : launch_fused_f32(plan->dev, a, scr, grid, plan->cfg.lds_entries,
                                 plan->cfg.lds_rows, c.guard, c.stream);
   } else {
     FusedArgs<double> a{};
@@ -485,8 +490,8 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     a.c = f.c;
     a.rho_out = f.rho;
     a.D_out = f.D;
-    e = wave ? launch_fused_wave_f64(plan->dev, a, scr, plan->cfg.grid, plan->cfg.hot, c.guard, c.stream)
-             : launch_fused_f64(plan->dev, a, scr, plan->cfg.grid, plan->cfg.lds_entries,
+    e = wave ? launch_fused_wave_f64(plan->dev, a, scr, grid, plan->cfg.hot, c.guard, c.stream)
+             : launch_fused_f64(plan->dev, a, scr, grid, plan->cfg.lds_entries,
                                 plan->cfg.lds_rows, c.guard, c.stream);
   }
   hip_check(e, "fused pass launch");
