@@ -69,10 +69,25 @@ __device__ __forceinline__ bool allowed(const MaskView& m, int64_t i) {
   return a != (m.comp != 0);
 }
 
-// Adds the number of lanes with f set to *cnt (one atomic per wavefront).
-__device__ __forceinline__ void count_flags(bool f, unsigned long long* cnt) {
-  const unsigned long long b = __ballot(f);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(cnt, (unsigned long long)__popcll(b));
+// Counts are kept in COUNT_SLOTS counters, one per 128-byte line, and
+// summed when read.
+constexpr int COUNT_SLOTS = 64, COUNT_STRIDE = 16;
+
+// Adds the counts of all threads of the block to its counter slot with one
+// atomic per block (every thread of the block calls it, once, at the end of
+// the kernel): counting per wavefront and loop step on one address
+// serialised tens of thousands of atomics.
+__device__ __forceinline__ void count_add(unsigned long long mine, unsigned long long* cnt) {
+  __shared__ unsigned long long part[SV_BLOCK / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < SV_BLOCK / 64; ++w) t += part[w];
+    if (t) atomicAdd(cnt + (blockIdx.x % COUNT_SLOTS) * COUNT_STRIDE, t);
+  }
 }
 
 enum SvMode : int { SV_MULT = 0, SV_ADD = 1, SV_UNARY = 2, SV_BIND1 = 3, SV_BIND2 = 4, SV_COPY = 5 };
@@ -92,6 +107,7 @@ __device__ __forceinline__ T sv_value(int mode, int op, T x, T y, T k) {
 template <typename T>
 __global__ void sv_range_kernel(int64_t n, int mode, int op, VView a, VView b, ScalarArg s, int out_type, void* out,
                                 uint8_t* obits, unsigned long long* cnt) {
+  unsigned long long mine = 0;
   const T k = (T)scalar_value(s);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -117,8 +133,9 @@ __global__ void sv_range_kernel(int64_t n, int mode, int op, VView a, VView b, S
       store_as<T>(out, out_type, i, v);
       obits[i] = p ? 1 : 0;
     }
-    count_flags(p, cnt);
+    mine += p ? 1ull : 0ull;
   }
+  count_add(mine, cnt);
 }
 
 // Loop over the nnz entries (positions idx, values aval) of a sparse input:
@@ -162,6 +179,7 @@ template <typename T, int GROUP>
 __global__ void sv_mxv_pull_kernel(int64_t nrows, const int* __restrict__ rowptr, const int* __restrict__ col,
                                    VView u, int u_full, MaskView m, VView old, int keep_old, T* out, uint8_t* obits,
                                    unsigned long long* cnt) {
+  unsigned long long mine = 0;
   const int lane = threadIdx.x & (GROUP - 1);
   const int64_t groups = (int64_t)gridDim.x * (blockDim.x / GROUP);
   const int64_t g0 = (int64_t)blockIdx.x * (blockDim.x / GROUP) + threadIdx.x / GROUP;
@@ -200,8 +218,9 @@ __global__ void sv_mxv_pull_kernel(int64_t nrows, const int* __restrict__ rowptr
       }
       obits[i] = p ? 1 : 0;
     }
-    count_flags(p, cnt);
+    mine += p ? 1ull : 0ull;
   }
+  count_add(mine, cnt);
 }
 
 // Push mxv: one wavefront per present u(j) adds it into the rows i of
@@ -229,6 +248,7 @@ __global__ void sv_mxv_push_kernel(int64_t nnz, const int* __restrict__ uidx, Op
 template <typename T>
 __global__ void sv_keep_old_kernel(int64_t n, MaskView m, VView old, int keep_old, T* out, uint8_t* obits,
                                    unsigned long long* cnt) {
+  unsigned long long mine = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
     const int64_t i = i0 + threadIdx.x;
@@ -241,14 +261,16 @@ __global__ void sv_keep_old_kernel(int64_t n, MaskView m, VView old, int keep_ol
       }
       p = obits[i] != 0;
     }
-    count_flags(p, cnt);
+    mine += p ? 1ull : 0ull;
   }
+  count_add(mine, cnt);
 }
 
 // w(i) = x where the mask allows, else the old entry unless replace.
 template <typename T>
 __global__ void sv_assign_kernel(int64_t n, double x, MaskView m, VView old, int keep_old, int out_type, void* out,
                                  uint8_t* obits, unsigned long long* cnt) {
+  unsigned long long mine = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
     const int64_t i = i0 + threadIdx.x;
@@ -265,8 +287,9 @@ __global__ void sv_assign_kernel(int64_t n, double x, MaskView m, VView old, int
       store_as<T>(out, out_type, i, v);
       obits[i] = p ? 1 : 0;
     }
-    count_flags(p, cnt);
+    mine += p ? 1ull : 0ull;
   }
+  count_add(mine, cnt);
 }
 
 // sparse -> bitset: out and bits must start zeroed.
@@ -298,18 +321,22 @@ struct Held {
 
 BufP alloc_bytes(size_t b) { return dev_alloc(b < 4 ? 4 : b); }
 
+constexpr size_t COUNT_BYTES = sizeof(unsigned long long) * COUNT_SLOTS * COUNT_STRIDE;
+
 unsigned long long* new_counter(BufP& holder) {
-  holder = alloc_bytes(sizeof(unsigned long long));
-  hip_check(launch_zero(holder->p, sizeof(unsigned long long), ctx().stream), "zero counter");
+  holder = alloc_bytes(COUNT_BYTES);
+  hip_check(launch_zero(holder->p, COUNT_BYTES, ctx().stream), "zero counter");
   launch_mark(false);
   return (unsigned long long*)holder->p;
 }
 
 int64_t read_counter(const BufP& holder) {
-  unsigned long long h = 0;
-  hip_check(hipMemcpyAsync(&h, holder->p, sizeof(h), hipMemcpyDeviceToHost, ctx().stream), "copy count");
+  unsigned long long h[COUNT_SLOTS * COUNT_STRIDE];
+  hip_check(hipMemcpyAsync(h, holder->p, COUNT_BYTES, hipMemcpyDeviceToHost, ctx().stream), "copy count");
   hip_check(hipStreamSynchronize(ctx().stream), "sync");
-  return (int64_t)h;
+  unsigned long long t = 0;
+  for (int k = 0; k < COUNT_SLOTS; ++k) t += h[k * COUNT_STRIDE];
+  return (int64_t)t;
 }
 
 // Bitset storage (values of `type` and presence bytes) of the sparse node x.
