@@ -556,6 +556,12 @@ GrB_Info GrM_ppr_stream(void *X, GrB_Type type, int nsets, const int32_t *seed_p
  * ---------------------------------------------------------------------- */
 typedef struct GB_Multigraph_opaque *GrM_Multigraph;
 GrB_Info GrM_set_many_team_max(int max_team);
+/* Test hook for the failure path, for callers that test error handling: a
+ * team member gives up a barrier wait after `ticks` of the 100 MHz wall
+ * clock (default 1e9, ten seconds), flags the launch and exits; the next
+ * GrM_pagerank_many that reads iters or resid then returns GrB_PANIC.  The
+ * limit is part of the captured launch's key. */
+GrB_Info GrM_set_many_team_wait(unsigned long long ticks);
 GrB_Info GrM_Multigraph_new(GrM_Multigraph *mg, int ngraphs, const GrB_Matrix *AT);
 GrB_Info GrM_Multigraph_free(GrM_Multigraph *mg);
 /* voff: host array of ngraphs + 1 vertex offsets. */

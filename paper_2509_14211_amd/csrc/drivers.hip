@@ -631,6 +631,7 @@ struct GB_Multigraph_opaque {
     double damping, tol;
     int itermax, uniform;
     void* out;
+    unsigned long long wait_ticks;
     hipGraph_t graph;
     hipGraphExec_t exec;
   };
@@ -832,7 +833,7 @@ GrB_Info GrM_pagerank_many(void* X, GrB_Type type, GrM_Multigraph mg, double dam
   GB_Multigraph_opaque::Exec* ex = nullptr;
   for (auto& e : mg->execs)
     if (e.type == T && e.damping == damping && e.tol == tol && e.itermax == itermax && e.uniform == uniform &&
-        e.out == X)
+        e.out == X && e.wait_ticks == c.many_wait_ticks)
       ex = &e;
   if (!ex) {
     ManyArgs a{};
@@ -844,6 +845,7 @@ GrB_Info GrM_pagerank_many(void* X, GrB_Type type, GrM_Multigraph mg, double dam
     a.team_bar = (unsigned*)mg->team_bar->p;
     a.team_part = (double*)mg->team_part->p;
     a.team_err = (int*)mg->team_err->p;
+    a.team_wait_ticks = c.many_wait_ticks;
     a.rowptr = (const int*)mg->rowptr->p;
     a.col = (const int*)mg->col->p;
     a.deg = (const int*)mg->deg->p;
@@ -860,7 +862,7 @@ GrB_Info GrM_pagerank_many(void* X, GrB_Type type, GrM_Multigraph mg, double dam
     a.tol = tol;
     a.itermax = itermax;
     a.uniform = uniform;
-    GB_Multigraph_opaque::Exec e{T, damping, tol, itermax, uniform, X, nullptr, nullptr};
+    GB_Multigraph_opaque::Exec e{T, damping, tol, itermax, uniform, X, c.many_wait_ticks, nullptr, nullptr};
     hip_check(hipStreamBeginCapture(mg->aux, hipStreamCaptureModeThreadLocal), "begin capture");
     hipError_t le = launch_pr_many(a, T, c.cus, mg->aux);
     hipGraph_t gph = nullptr;
@@ -891,6 +893,13 @@ GrB_Info GrM_pagerank_many(void* X, GrB_Type type, GrM_Multigraph mg, double dam
     hip_check(hipMemcpyAsync(&team_err, mg->team_err->p, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy");
   if (iters || resid) hip_check(hipStreamSynchronize(c.stream), "sync");
   if (team_err) fail(GrB_PANIC, "a team of workgroups gave up waiting for a member");
+  API_END
+}
+
+GrB_Info GrM_set_many_team_wait(unsigned long long ticks) {
+  API_BEGIN
+  require_init();
+  ctx().many_wait_ticks = ticks;
   API_END
 }
 

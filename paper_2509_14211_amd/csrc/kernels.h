@@ -279,6 +279,7 @@ struct ManyArgs {
   unsigned* team_bar;   // per graph: team arrivals, reset to 0 by the launch
   double* team_part;    // per graph: [barrier parity][member][residual, dangling]
   int* team_err;        // set when a team member waited too long (reset by the launch)
+  unsigned long long team_wait_ticks;  // give-up limit of a team wait, in 100 MHz wall-clock ticks
   int ngraphs;
   int nslots;         // queue entries: one per team member, one per single graph
   const int* rowptr;

@@ -10,8 +10,9 @@
 // dangling partial sums, wait until every member has arrived, and add the
 // partials in member order, so every member takes the same loop decision.
 // Team slots come first and number at most the grid, so every member is
-// running when the first barrier is reached; a wait still gives up after
-// about ten seconds and flags the launch as failed instead of hanging.
+// running when the first barrier is reached; a wait still gives up after a
+// bounded time (ten seconds unless set lower) and flags the launch as
+// failed instead of hanging.
 // Inside a graph the vertices are numbered by decreasing out-degree, so the
 // leading slice of the gathered vector -- all of it for graphs up to the LDS
 // capacity -- is kept in LDS and refreshed after every pass.  Rows are
@@ -68,14 +69,12 @@ __device__ __forceinline__ double bsum(double v, double* red, double* out) {
   return r;
 }
 
-constexpr uint64_t TEAM_WAIT_TICKS = 1000000000ull;  // about 10 s of the 100 MHz wall clock
-
 // Thread 0: wait until *bar reaches target; false, with *err set, when the
-// wait runs out.
-__device__ bool team_wait(unsigned* bar, unsigned target, int* err) {
+// wait runs out (after `ticks` of the 100 MHz wall clock).
+__device__ bool team_wait(unsigned* bar, unsigned target, int* err, uint64_t ticks) {
   const uint64_t t0 = wall_clock64();
   while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    if (wall_clock64() - t0 > TEAM_WAIT_TICKS) {
+    if (wall_clock64() - t0 > ticks) {
       __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
@@ -88,12 +87,12 @@ __device__ bool team_wait(unsigned* bar, unsigned target, int* err) {
 // released, its arrival counted, and once all members have arrived their
 // writes are acquired (which also drops this compute unit's stale cached
 // lines of the shared vectors).  False when the wait ran out.
-__device__ bool team_sync(unsigned* bar, unsigned target, int* err, int* sflag) {
+__device__ bool team_sync(unsigned* bar, unsigned target, int* err, uint64_t ticks, int* sflag) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    *sflag = team_wait(bar, target, err) ? 1 : 0;
+    *sflag = team_wait(bar, target, err, ticks) ? 1 : 0;
   }
   __syncthreads();
   const bool ok = *sflag != 0;
@@ -153,7 +152,7 @@ __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
       if (dg == 0) dl += (double)x0;
     }
     double D = bsum(dl, red, &bcast);
-    if (team > 1 && !team_sync(bar, ++gen * (unsigned)team, p.team_err, &sflag)) return;
+    if (team > 1 && !team_sync(bar, ++gen * (unsigned)team, p.team_err, p.team_wait_ticks, &sflag)) return;
     double rho = 1.0;
     int it = 0;
     T* xc = xa;
@@ -270,7 +269,7 @@ __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
           publish(&pp[2 * mk], brl);
           publish(&pp[2 * mk + 1], bdn);
         }
-        if (!team_sync(bar, ++gen * (unsigned)team, p.team_err, &sflag)) return;
+        if (!team_sync(bar, ++gen * (unsigned)team, p.team_err, p.team_wait_ticks, &sflag)) return;
         double a0 = 0.0, a1 = 0.0;
         for (int u = 0; u < team; ++u) {
           a0 += consume(&pp[2 * u]);

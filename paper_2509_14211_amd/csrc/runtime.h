@@ -267,6 +267,8 @@ struct Ctx {
   int format_policy = FP_ESTIMATE;
   // largest team of workgroups per graph in the many-graph launch
   int many_team_max = 8;
+  // give-up limit of a team barrier wait (100 MHz wall-clock ticks)
+  unsigned long long many_wait_ticks = 1000000000ull;
   // plan configuration override chosen by the autotuner (per matrix id)
   std::map<std::pair<uint64_t, int>, PlanConfig> tuned;
 };

@@ -110,6 +110,7 @@ _FUNCS = {
     "GrM_Vector_format": [ctypes.POINTER(i32), vp],
     "GrM_set_format_policy": [i32],
     "GrM_set_many_team_max": [i32],
+    "GrM_set_many_team_wait": [ctypes.c_ulonglong],
     "GrM_code_cache_clear": [],
     "GrB_Scalar_new": [PV, vp],
     "GrB_Scalar_free": [PV],
@@ -369,6 +370,11 @@ def GrM_set_format_policy(policy: int):
 def GrM_set_many_team_max(max_team: int):
     """Largest team of workgroups per graph in later GrM_Multigraph_new calls (1..8)."""
     _call("GrM_set_many_team_max", max_team)
+
+
+def GrM_set_many_team_wait(ticks: int):
+    """Give-up limit of a team barrier wait in 100 MHz ticks (a test hook)."""
+    _call("GrM_set_many_team_wait", ticks)
 
 
 def GrM_error() -> str:

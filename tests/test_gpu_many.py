@@ -102,3 +102,31 @@ def test_many_errors(nonblocking):
         grb.GrM_Multigraph_new([A])
     assert e.value.info == -6
     grb.GrB_Matrix_free(A)
+
+
+def test_many_team_wait_give_up_is_reported(nonblocking, oracle_mod):
+    """Failure path of the team barrier, forced from the host with a zero
+    wait limit: members give up and exit instead of waiting, the launch
+    still completes, GrM_pagerank_many reports GrB_PANIC, and the same
+    multigraph then solves correctly with the normal limit."""
+    grb = nonblocking
+    gs, ogs = _graphs(oracle_mod)
+    mg = grb.GrM_Multigraph_new([g.AT for g in gs])
+    off = grb.GrM_Multigraph_offsets(mg, len(gs))
+    t = grb.builtin("GrB_FP64")
+    X = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
+    grb.GrM_set_many_team_wait(0)
+    try:
+        with pytest.raises(grb.GrBError) as e:
+            grb.GrM_pagerank_many(X, t, mg, len(gs), D, 1e-10, 1000, 1)
+        assert e.value.info == grb.GrB_PANIC
+    finally:
+        grb.GrM_set_many_team_wait(10 ** 9)
+    its, res = grb.GrM_pagerank_many(X, t, mg, len(gs), D, 1e-10, 1000, 1)
+    x = X.cpu().numpy()
+    for i, og in enumerate(ogs):
+        ref = oracle_mod.pagerank(og, D, fixed_iters=int(its[i]), mode=1)
+        assert np.abs(x[off[i]:off[i + 1]] - ref.x).sum() / np.abs(ref.x).sum() <= 1e-12, i
+    grb.GrM_Multigraph_free(mg)
+    for g in gs:
+        g.free()
