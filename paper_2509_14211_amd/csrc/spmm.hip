@@ -429,13 +429,16 @@ __global__ void spmm_init_kernel(SpmmArgs p, const int* __restrict__ by_col_ptr,
   if (p.hit) p.hit[c] = -1;
 }
 
+// Clears the selected columns of two n x k row-major blocks: one wavefront
+// per row, lane c owns column c (k <= 64), so no lane divides an index.
 __global__ void zero_columns_kernel(void* __restrict__ x, void* __restrict__ w, int type, int64_t n, int k,
                                     uint64_t cols) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t total = n * k;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
-    const int c = (int)(q % k);
-    if (!((cols >> c) & 1ull)) continue;
+  const int lane = threadIdx.x & 63;
+  const bool mine = lane < k && ((cols >> lane) & 1ull);
+  const int64_t per_step = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < n; i += per_step) {
+    if (!mine) continue;
+    const int64_t q = i * k + lane;
     if (type == T_FP32) {
       ((float*)x)[q] = 0.f;
       ((float*)w)[q] = 0.f;
@@ -446,8 +449,8 @@ __global__ void zero_columns_kernel(void* __restrict__ x, void* __restrict__ w, 
   }
 }
 
-// 64 rows per workgroup: the rows (k values each, read whole) go through
-// LDS, then each selected column leaves as 64 consecutive values.
+// 64 rows per workgroup: the selected columns of the rows go through LDS,
+// then each leaves as 64 consecutive values.
 template <typename T>
 __global__ __launch_bounds__(256) void columns_out_kernel(const T* __restrict__ in, const int* __restrict__ idx,
                                                           int64_t n, int k, uint64_t cols, ColumnOutputs outs) {
@@ -456,7 +459,7 @@ __global__ __launch_bounds__(256) void columns_out_kernel(const T* __restrict__ 
   for (int q = threadIdx.x; q < 64 * 64; q += 256) {
     const int r = q >> 6, c = q & 63;
     const int64_t i = r0 + r;
-    if (i < n && c < k) tile[r][c] = in[(idx ? (int64_t)idx[i] : i) * k + c];
+    if (i < n && c < k && ((cols >> c) & 1ull)) tile[r][c] = in[(idx ? (int64_t)idx[i] : i) * k + c];
   }
   __syncthreads();
   for (int q = threadIdx.x; q < 64 * 64; q += 256) {
@@ -517,8 +520,8 @@ hipError_t launch_spmm_init(const SpmmArgs& a, int type, const int* by_col_ptr, 
 }
 
 hipError_t launch_spmm_zero_columns(void* x, void* w, int type, int64_t n, int k, uint64_t cols, hipStream_t s) {
-  if (n <= 0 || !cols) return hipSuccess;
-  int64_t g = (n * k + 1023) / 1024;
+  if (n <= 0 || !cols || k < 1 || k > 64) return n <= 0 || !cols ? hipSuccess : hipErrorInvalidValue;
+  int64_t g = (n + 3) / 4;  // four rows per 256-thread workgroup and step
   if (g > 16384) g = 16384;
   hipLaunchKernelGGL(zero_columns_kernel, dim3((int)g), dim3(256), 0, s, x, w, type, n, k, cols);
   return hipGetLastError();
