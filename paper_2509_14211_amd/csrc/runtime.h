@@ -67,6 +67,8 @@ struct MatData {
   std::map<std::tuple<int, int, int, int, int, int, int>, std::shared_ptr<Plan>> plans;
   std::shared_ptr<Relabeled> relabeled;
   std::shared_ptr<MatData> transposed;  // built on demand for push-style mxv
+  BufP long_rows;                       // rows longer than SV_LONG_ROW, for the pull mxv (on demand)
+  int64_t nlong = -1;                   // their count; -1 until computed
 };
 
 // Kernel family of a plan.

@@ -40,6 +40,7 @@ namespace {
 constexpr int SV_BLOCK = 256;
 constexpr double SPARSE_BELOW = 1.0 / 16;  // estimated fill below which outputs are stored sparse
 constexpr double PUSH_BELOW = 1.0 / 32;    // fill of a sparse u below which mxv is driven by u
+constexpr int SV_LONG_ROW = 2048;          // pull mxv: longer rows get a workgroup of their own
 
 int sv_grid(int64_t n) {
   int64_t g = (n + SV_BLOCK * 4 - 1) / (SV_BLOCK * 4);
@@ -188,7 +189,8 @@ __global__ void sv_mxv_pull_kernel(int64_t nrows, const int* __restrict__ rowptr
   const int64_t rounds = (nrows + groups - 1) / groups;
   for (int64_t r = 0; r < rounds; ++r) {
     const int64_t i = g0 + r * groups;
-    const bool row_ok = i < nrows;
+    // rows longer than SV_LONG_ROW belong to sv_mxv_pull_long_kernel
+    const bool row_ok = i < nrows && rowptr[i + 1] - rowptr[i] <= SV_LONG_ROW;
     const bool allow = row_ok && allowed(m, i);
     T s = (T)0;
     bool hit = false;
@@ -221,6 +223,66 @@ __global__ void sv_mxv_pull_kernel(int64_t nrows, const int* __restrict__ rowptr
     mine += p ? 1ull : 0ull;
   }
   count_add(mine, cnt);
+}
+
+// Pull mxv of the rows longer than SV_LONG_ROW (list `rows`): one
+// workgroup per row, four loads in flight per thread, the sum and the
+// presence combined in a fixed order, the rest as in the pull kernel.
+template <typename T>
+__global__ __launch_bounds__(SV_BLOCK) void sv_mxv_pull_long_kernel(const int* __restrict__ rows,
+                                                                    const int* __restrict__ rowptr,
+                                                                    const int* __restrict__ col, VView u, int u_full,
+                                                                    MaskView m, VView old, int keep_old, T* out,
+                                                                    uint8_t* obits, unsigned long long* cnt) {
+  __shared__ T ssum[SV_BLOCK / 64];
+  __shared__ int shit[SV_BLOCK / 64];
+  const int64_t i = rows[blockIdx.x];
+  const bool allow = allowed(m, i);
+  T s = (T)0;
+  int hit = 0;
+  if (allow) {
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += 4 * SV_BLOCK) {
+      int j[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) j[k] = col[min(e + k * SV_BLOCK, e1 - 1)];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (e + k * SV_BLOCK < e1 && present(u, j[k])) {
+          s += load_as<T>(u.val, j[k]);
+          hit = 1;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o, 64);
+    hit |= __shfl_xor(hit, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    ssum[threadIdx.x >> 6] = s;
+    shit[threadIdx.x >> 6] = hit;
+  }
+  __syncthreads();
+  bool p = false;
+  if (threadIdx.x == 0) {
+    T t = (T)0;
+    int h = 0;
+    for (int w = 0; w < SV_BLOCK / 64; ++w) {
+      t += ssum[w];
+      h |= shit[w];
+    }
+    if (allow) {
+      p = h || u_full;
+      out[i] = p ? t : (T)0;
+    } else {
+      p = keep_old && present(old, i);
+      out[i] = p ? load_as<T>(old.val, i) : (T)0;
+    }
+    obits[i] = p ? 1 : 0;
+  }
+  count_add(p ? 1ull : 0ull, cnt);
 }
 
 // Push mxv: one wavefront per present u(j) adds it into the rows i of
@@ -544,6 +606,28 @@ void exec_ewise(Node& n) {
   finish(n, vals, bits, count);
 }
 
+// Rows of A longer than SV_LONG_ROW (computed once per matrix, on the host
+// from its row pointers).
+int64_t long_rows_of(const MatP& A) {
+  if (A->nlong >= 0) return A->nlong;
+  Ctx& c = ctx();
+  std::vector<int> rp((size_t)A->nrows + 1);
+  hip_check(hipMemcpyAsync(rp.data(), A->rowptr->p, sizeof(int) * rp.size(), hipMemcpyDeviceToHost, c.stream),
+            "copy row pointers");
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+  std::vector<int> rows;
+  for (int64_t i = 0; i < A->nrows; ++i)
+    if (rp[(size_t)i + 1] - rp[(size_t)i] > SV_LONG_ROW) rows.push_back((int)i);
+  A->long_rows = alloc_bytes(sizeof(int) * std::max<size_t>(rows.size(), 1));
+  if (!rows.empty()) {
+    hip_check(hipMemcpyAsync(A->long_rows->p, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, c.stream),
+              "upload long rows");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+  }
+  A->nlong = (int64_t)rows.size();
+  return A->nlong;
+}
+
 void exec_mxv(Node& n) {
   Ctx& c = ctx();
   const NodeP& U = n.a;
@@ -582,10 +666,15 @@ void exec_mxv(Node& n) {
     const int u_full = U->fmt == F_FULL ? 1 : 0;
     const int* rp = (const int*)A->rowptr->p;
     const int* col = A->col ? (const int*)A->col->p : nullptr;
+    const int64_t nlong = long_rows_of(A);
     by_type(n.type, [&](auto z) {
       using T = decltype(z);
       hipLaunchKernelGGL((sv_mxv_pull_kernel<T, 8>), dim3(sv_grid(n.n * 8)), dim3(SV_BLOCK), 0, c.stream, n.n, rp,
                          col, hu.v, u_full, hm.m, hold.v, keep_old ? 1 : 0, (T*)vals->p, (uint8_t*)bits->p, cnt);
+      if (nlong > 0)
+        hipLaunchKernelGGL(sv_mxv_pull_long_kernel<T>, dim3((unsigned)nlong), dim3(SV_BLOCK), 0, c.stream,
+                           (const int*)A->long_rows->p, rp, col, hu.v, u_full, hm.m, hold.v, keep_old ? 1 : 0,
+                           (T*)vals->p, (uint8_t*)bits->p, cnt);
     });
     hip_check(hipGetLastError(), "mxv pull");
   }
