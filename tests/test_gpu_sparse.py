@@ -191,6 +191,66 @@ def test_masked_mxv_against_oracle(policy, g10, fill, mask, replace):
         grb.GrB_Vector_free(h)
 
 
+@pytest.fixture(scope="module")
+def g_long(gpu, oracle_mod):
+    """Rows of A^T longer than the pull mxv's per-group limit (2048 entries,
+    summed by a workgroup each): in-hubs 0 and 1 with 5999 and 3000 links,
+    among 20,000 random links."""
+    from paper_2509_14211_amd import api
+    n = 6000
+    rng = np.random.default_rng(77)
+    src = np.concatenate([np.arange(1, n), np.arange(2, 3002), rng.integers(0, n, 20000)]).astype(np.uint32)
+    dst = np.concatenate([np.zeros(n - 1), np.ones(3000), rng.integers(0, n, 20000)]).astype(np.uint32)
+    g = api.graph_from_edges(n, src, dst)
+    og = oracle_mod.graph_from_edges(n, src, dst)
+    assert og.rowptrT[1] - og.rowptrT[0] > 2048 and og.rowptrT[2] - og.rowptrT[1] > 2048
+    yield g, og
+    g.free()
+
+
+@pytest.mark.parametrize("fill", [0.2, 1.0])
+@pytest.mark.parametrize("mask", [None, "value", "struct_comp"])
+@pytest.mark.parametrize("replace", [True, False])
+def test_pull_mxv_long_rows_against_oracle(policy, g_long, fill, mask, replace):
+    """Pull mxv with rows past the per-group limit: hub 0 lies inside the
+    mask and hub 1 outside it (both have old entries), so every mask mode
+    sends one long row through the allowed path and one through the
+    kept-or-dropped path.  Integer-valued operands: exact in any order."""
+    grb = policy
+    g, og = g_long
+    n = g.n
+    rng = np.random.default_rng(int(fill * 10) + (0 if mask is None else len(mask)) + 2 * replace)
+    u = _rand(rng, n, fill) if fill < 1 else S.SVec.full(rng.integers(-4, 5, n).astype(float))
+    gu = _from_svec(grb, u)
+    old = _rand(rng, n, 0.3)
+    keep = (old.idx != 0) & (old.idx != 1)
+    old = S.SVec(n, np.concatenate([[0, 1], old.idx[keep]]), np.concatenate([[3.0, -2.0], old.vals[keep]]))
+    order = np.argsort(old.idx)
+    old = S.SVec(n, old.idx[order], old.vals[order])
+    w = _from_svec(grb, old)
+    m = _rand(rng, n, 0.4)
+    mk = (m.idx != 0) & (m.idx != 1)
+    m = S.SVec(n, np.concatenate([[0], m.idx[mk]]), np.concatenate([[1.0], m.vals[mk]]))
+    order = np.argsort(m.idx)
+    m = S.SVec(n, m.idx[order], m.vals[order])
+    gm = _from_svec(grb, m) if mask else None
+    comp = mask == "struct_comp"
+    struct = mask == "struct_comp"
+    desc = None
+    if mask and (replace or struct or comp):
+        desc = grb.builtin("GrB_DESC_" + ("R" if replace else "") + ("S" if struct else "") + ("C" if comp else ""))
+    grb.GrM_reset_stats()
+    grb.GrB_mxv(w, gm, None, grb.builtin("GrM_PLUS_SECOND_SEMIRING_FP64"), g.AT, gu, desc)
+    got = _to_svec(grb, w, n)
+    want = S.mxv(og.rowptrT, og.colT, u, m if mask else None, comp, struct, replace or not mask,
+                 old if (mask and not replace) else None)
+    assert _same(got, want)
+    if mask or fill < 1:  # (a full u with no mask takes the dense pass)
+        assert grb.GrM_get_stats()["mxv_pull"] == 1
+    for h in (gu, w) + ((gm,) if gm else ()):
+        grb.GrB_Vector_free(h)
+
+
 def test_format_policies_give_identical_results(policy, g10):
     """The estimates only choose storage and loop drivers (Section III-D):
     a chain of operations gives the same entries under every policy."""
