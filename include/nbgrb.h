@@ -227,6 +227,8 @@ GrB_Info GrB_Scalar_setElement_FP64(GrB_Scalar s, double x);
 /* Forces the scalar and copies its value to *x (synchronises).
  * GrB_NO_VALUE if the scalar has never been assigned. */
 GrB_Info GrB_Scalar_extractElement_FP64(double *x, GrB_Scalar s);
+/* Complete s (as GrB_Vector_wait; Section III: reading a scalar's value,
+ * as Fig. 6 does with the residual in its loop test, also forces it). */
 GrB_Info GrB_Scalar_wait(GrB_Scalar s, GrB_WaitMode mode);
 /* out = alpha * in + beta, recorded like any other operation (project
  * extension: it expresses the teleport constant (1-d)/n + d*D/n from the
@@ -245,6 +247,11 @@ GrB_Info GrB_Vector_free(GrB_Vector *v);
 GrB_Info GrB_Vector_dup(GrB_Vector *w, GrB_Vector u);
 GrB_Info GrB_Vector_size(GrB_Index *n, GrB_Vector v);
 GrB_Info GrM_Vector_type(GrB_Type *t, GrB_Vector v);
+/* Complete v: run whatever pending work it depends on (nonblocking mode).
+ * Defined by: the wait method that materialises an object (Section III,
+ * and Section III-C: the point where the pending method tree is matched,
+ * looked up in the cache by its signature and run); Fig. 6 calls it on the
+ * new rank vector every iteration.  In blocking mode a no-op. */
 GrB_Info GrB_Vector_wait(GrB_Vector v, GrB_WaitMode mode);
 
 /* Every entry := value (the paper's GrBVector(n, value) constructor,
@@ -291,6 +298,38 @@ GrB_Info GrM_Matrix_export_CSR(int32_t *rowptr_dev, int32_t *col_dev, GrB_Matrix
 GrB_Info GrM_Matrix_build_edges(GrB_Matrix A, const uint32_t *src_dev,
                                 const uint32_t *dst_dev, GrB_Index nedges,
                                 bool drop_self);
+
+/* Dense matrices (the second operand and the result of GrB_mxm).  A
+ * matrix made by GrB_Matrix_new(type FP32 or FP64, nrows, ncols) becomes
+ * dense by this import: nrows x ncols values of A's type, row-major (row i
+ * at src_dev + i*ncols), copied from device memory.  nrows and ncols must
+ * be A's (GrB_DIMENSION_MISMATCH otherwise).  A dense matrix is accepted
+ * only by GrB_mxm (as B, and as C, which it overwrites), the export below,
+ * GrB_Matrix_free / nrows / ncols / nvals / wait and the pattern imports
+ * that replace its content; every other call that takes a matrix rejects
+ * it with GrB_INVALID_VALUE.
+ * Defined by: the matrix operand of the GraphBLAS operations the paper
+ * records (Section II); the paper itself only multiplies by vectors. */
+GrB_Info GrM_Matrix_import_dense(GrB_Matrix A, const void *src_dev, GrB_Index nrows, GrB_Index ncols);
+/* Copy a dense matrix's nrows x ncols values (row-major, its type) to
+ * device memory.  GrB_INVALID_VALUE if A holds a pattern. */
+GrB_Info GrM_Matrix_export_dense(void *dst_dev, GrB_Matrix A);
+
+/* C := A (+.*) B with A a CSR pattern (nrows x ncols) and B dense
+ * (ncols x k, 1 <= k <= 64): C(i, c) = sum over the entries j of row i of
+ * B(j, c), every row of B read as one k-wide vector.  C becomes dense
+ * nrows x k (C must have been made nrows x k); the types of B, C and the
+ * semiring must agree (FP32 or FP64).  Mask, accum and desc must be NULL
+ * (GrB_NOT_IMPLEMENTED otherwise), as must k > 64; semirings are
+ * plus-times or plus-second (equal on a pattern).  Runs at once in both
+ * modes: no vector operation is pending on matrices.  Empty rows give 0.
+ * Defined by: the GraphBLAS mxm operation (Section II's operations on
+ * matrix objects), restricted to the sparse x dense product that batches k
+ * right-hand sides of the mxv of Fig. 6 -- the product behind batched
+ * personalised PageRank (GrM_ppr_batch fuses the same product with its
+ * epilogue and never materialises it). */
+GrB_Info GrB_mxm(GrB_Matrix C, GrB_Matrix Mask, GrB_BinaryOp accum, GrB_Semiring op,
+                 GrB_Matrix A, GrB_Matrix B, GrB_Descriptor desc);
 
 /* C := A^T (GraphBLAS transpose with no mask and no accumulator; mask and
  * accum must be NULL).  C must be ncols(A) x nrows(A).  Each row of C lists
@@ -426,12 +465,22 @@ GrB_Info GrM_set_format_policy(int policy);
 /* w<mask> = A (+.*) u.  A is nrows x ncols, u has ncols entries, w nrows.
  * With every entry of u present an empty row gives the monoid identity 0;
  * otherwise see "Vectors with missing entries".  mask may be NULL; accum
- * must be NULL. */
+ * must be NULL.
+ * Defined by: the paper's mxv method (Section III-A, Fig. 3: identity,
+ * add and multiply operators over a matrix and a vector) as the PageRank
+ * loop uses it (Fig. 6: identity 0, add +, multiply "second" over the
+ * transposed adjacency).  On a pattern matrix plus-second and plus-times
+ * agree.  In nonblocking mode this is the anchor the matcher fuses with the
+ * elementwise operations around it (Section II, Section IV). */
 GrB_Info GrB_mxv(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
                  GrB_Semiring op, GrB_Matrix A, GrB_Vector u, GrB_Descriptor desc);
 
 /* w(i) = op(u(i), v(i)).  For full vectors the union (eWiseAdd) and the
- * intersection (eWiseMult) of the patterns coincide. */
+ * intersection (eWiseMult) of the patterns coincide.
+ * Defined by: ewise_mult of Figs. 1 and 2 (the elementwise product whose
+ * generated loop the paper shows) and the ewise_mult / ewise_add calls of
+ * the PageRank loop (Fig. 6: the division by the degree vector, the
+ * teleport addition and the absolute difference behind the residual). */
 GrB_Info GrB_Vector_eWiseMult_BinaryOp(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
                                        GrB_BinaryOp op, GrB_Vector u, GrB_Vector v,
                                        GrB_Descriptor desc);
@@ -439,7 +488,9 @@ GrB_Info GrB_Vector_eWiseAdd_BinaryOp(GrB_Vector w, GrB_Vector mask, GrB_BinaryO
                                       GrB_BinaryOp op, GrB_Vector u, GrB_Vector v,
                                       GrB_Descriptor desc);
 
-/* w(i) = op(u(i)). */
+/* w(i) = op(u(i)).
+ * Defined by: the apply method (Fig. 2's inner apply, Fig. 4's iterator
+ * form of it, Section III-B). */
 GrB_Info GrB_Vector_apply(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
                           GrB_UnaryOp op, GrB_Vector u, GrB_Descriptor desc);
 /* w(i) = op(s, u(i)) and w(i) = op(u(i), s) with a host scalar s. */
@@ -455,7 +506,11 @@ GrB_Info GrB_Vector_apply_BinaryOp2nd_Scalar(GrB_Vector w, GrB_Vector mask, GrB_
                                              GrB_Descriptor desc);
 
 /* s = sum of u (plus monoid only), accumulated in FP64.  The _Scalar form
- * is recorded lazily; the _FP64 form forces and synchronises. */
+ * is recorded lazily; the _FP64 form forces and synchronises.
+ * Defined by: the reduce of the PageRank loop (Fig. 6: the plus reduction
+ * of the absolute differences that gives the residual, read through the
+ * scalar in the loop test).  The paper accumulates in FP32; this library
+ * accumulates in FP64. */
 GrB_Info GrB_Vector_reduce_Monoid_Scalar(GrB_Scalar s, GrB_BinaryOp accum, GrB_Monoid monoid,
                                          GrB_Vector u, GrB_Descriptor desc);
 GrB_Info GrB_Vector_reduce_FP64(double *s, GrB_BinaryOp accum, GrB_Monoid monoid,

@@ -101,9 +101,17 @@ GB_Scalar_opaque* nbgrb::sca(GrB_Scalar s, const char* what) {
   return s;
 }
 
-GB_Matrix_opaque* nbgrb::mat(GrB_Matrix A, const char* what) {
+GB_Matrix_opaque* nbgrb::mat_any(GrB_Matrix A, const char* what) {
   need(A, what);
   if (A->magic != MAGIC_MAT) fail(GrB_UNINITIALIZED_OBJECT, std::string(what) + " is not a matrix");
+  return A;
+}
+
+GB_Matrix_opaque* nbgrb::mat(GrB_Matrix A, const char* what) {
+  mat_any(A, what);
+  if (A->data && A->data->dense)
+    fail(GrB_INVALID_VALUE, std::string(what) + " holds dense values; only GrB_mxm's second operand and output, "
+                                                "GrM_Matrix_export_dense and the size queries take a dense matrix");
   return A;
 }
 
@@ -639,7 +647,7 @@ GrB_Info GrB_Matrix_new(GrB_Matrix* A, GrB_Type type, GrB_Index nrows, GrB_Index
 GrB_Info GrB_Matrix_free(GrB_Matrix* A) {
   API_BEGIN
   if (!A || !*A) return GrB_SUCCESS;
-  GB_Matrix_opaque* o = mat(*A, "matrix");
+  GB_Matrix_opaque* o = mat_any(*A, "matrix");
   o->data.reset();
   o->magic = MAGIC_FREED;
   delete o;
@@ -650,28 +658,62 @@ GrB_Info GrB_Matrix_free(GrB_Matrix* A) {
 GrB_Info GrB_Matrix_nrows(GrB_Index* n, GrB_Matrix A) {
   API_BEGIN
   need(n, "n");
-  *n = (GrB_Index)mat(A, "A")->nrows;
+  *n = (GrB_Index)mat_any(A, "A")->nrows;
   API_END
 }
 
 GrB_Info GrB_Matrix_ncols(GrB_Index* n, GrB_Matrix A) {
   API_BEGIN
   need(n, "n");
-  *n = (GrB_Index)mat(A, "A")->ncols;
+  *n = (GrB_Index)mat_any(A, "A")->ncols;
   API_END
 }
 
 GrB_Info GrB_Matrix_nvals(GrB_Index* nvals, GrB_Matrix A) {
   API_BEGIN
   need(nvals, "nvals");
-  *nvals = (GrB_Index)mat(A, "A")->data->nnz;
+  GB_Matrix_opaque* o = mat_any(A, "A");
+  *nvals = o->data->dense ? (GrB_Index)(o->nrows * o->ncols) : (GrB_Index)o->data->nnz;
+  API_END
+}
+
+GrB_Info GrM_Matrix_import_dense(GrB_Matrix A, const void* src, GrB_Index nrows, GrB_Index ncols) {
+  API_BEGIN
+  require_init();
+  GB_Matrix_opaque* o = mat_any(A, "A");
+  need(src, "src");
+  float_type(o->type, "A");
+  if ((int64_t)nrows != o->nrows || (int64_t)ncols != o->ncols)
+    fail(GrB_DIMENSION_MISMATCH, "dense import must fill the whole matrix (nrows x ncols of GrB_Matrix_new)");
+  Ctx& c = ctx();
+  auto m = std::make_shared<MatData>();
+  m->id = c.next_id++;
+  m->nrows = o->nrows;
+  m->ncols = o->ncols;
+  m->nnz = 0;
+  m->dense_type = o->type;
+  const size_t bytes = type_size(o->type) * (size_t)o->nrows * (size_t)o->ncols;
+  m->dense = dev_alloc(bytes);
+  hip_check(hipMemcpyAsync(m->dense->p, src, bytes, hipMemcpyDeviceToDevice, c.stream), "import dense");
+  o->data = m;
+  API_END
+}
+
+GrB_Info GrM_Matrix_export_dense(void* dst, GrB_Matrix A) {
+  API_BEGIN
+  require_init();
+  GB_Matrix_opaque* o = mat_any(A, "A");
+  need(dst, "dst");
+  if (!o->data->dense) fail(GrB_INVALID_VALUE, "A holds a pattern, not dense values");
+  const size_t bytes = type_size(o->data->dense_type) * (size_t)o->nrows * (size_t)o->ncols;
+  hip_check(hipMemcpyAsync(dst, o->data->dense->p, bytes, hipMemcpyDeviceToDevice, ctx().stream), "export dense");
   API_END
 }
 
 GrB_Info GrB_Matrix_wait(GrB_Matrix A, GrB_WaitMode mode) {
   API_BEGIN
   require_init();
-  mat(A, "A");
+  mat_any(A, "A");
   if (mode != GrB_COMPLETE && mode != GrB_MATERIALIZE) fail(GrB_INVALID_VALUE, "wait mode");
   API_END
 }
@@ -679,7 +721,7 @@ GrB_Info GrB_Matrix_wait(GrB_Matrix A, GrB_WaitMode mode) {
 GrB_Info GrM_Matrix_import_CSR(GrB_Matrix A, const int32_t* rowptr, const int32_t* col, GrB_Index nnz) {
   API_BEGIN
   require_init();
-  GB_Matrix_opaque* o = mat(A, "A");
+  GB_Matrix_opaque* o = mat_any(A, "A");
   need(rowptr, "rowptr");
   if (nnz > 0) need(col, "col");
   if (nnz > (GrB_Index)INT32_MAX) fail(GrB_INVALID_VALUE, "nnz must be < 2^31");
@@ -731,7 +773,7 @@ GrB_Info GrM_Matrix_build_edges(GrB_Matrix A, const uint32_t* src, const uint32_
                                 bool drop_self) {
   API_BEGIN
   require_init();
-  GB_Matrix_opaque* o = mat(A, "A");
+  GB_Matrix_opaque* o = mat_any(A, "A");
   if (o->nrows != o->ncols) fail(GrB_DIMENSION_MISMATCH, "edge lists build square matrices");
   if (nedges > 0) {
     need(src, "src");

@@ -15,7 +15,10 @@ std::string& api_error();
 void need(const void* p, const char* what);
 GB_Vector_opaque* vec(GrB_Vector v, const char* what);
 GB_Scalar_opaque* sca(GrB_Scalar s, const char* what);
+// A pattern (CSR) matrix; a dense one is GrB_INVALID_VALUE.
 GB_Matrix_opaque* mat(GrB_Matrix A, const char* what);
+// Any matrix handle, pattern or dense.
+GB_Matrix_opaque* mat_any(GrB_Matrix A, const char* what);
 void no_mask_accum(const void* mask, const void* accum);
 void float_type(int t, const char* what);
 bool desc_comp(GrB_Descriptor d);

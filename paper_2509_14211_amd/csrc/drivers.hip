@@ -172,6 +172,7 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
     if (next < 1) next = 1;
     batch = next;
   }
+  if (hg.bad) fail(GrB_PANIC, "pagerank: a residual or dangling mass was not finite (NaN or Inf in the iterate)");
   const int64_t idx = (int64_t)hg.iters - base;
   if (idx < 0 || idx >= (int64_t)hist.size()) fail(GrB_PANIC, "loop guard out of step");
   c.guard = saved_guard;
@@ -286,6 +287,8 @@ struct PprColumns {
     wp.chunk = WAVE_TILE_ENTRIES;
     wp.grid = c.cus * 2;
     plan = get_plan(A_exec, wp);
+    // the SpMM kernels assume wavefront tiles (at most 256 rows, 512 entries)
+    if (plan->cfg.kernel != K_WAVE) fail(GrB_NOT_IMPLEMENTED, "batched PPR: too many vertices for the wavefront tile plan");
     grid = plan->cfg.grid;
 
     // d = damping ./ outdeg (0 for dangling), in execution order
@@ -472,6 +475,7 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
     batch = next;
   }
   c.guard = saved_guard;
+  if (hg.bad) fail(GrB_PANIC, "ppr_batch: a column's residual or dangling mass was not finite");
   const BufP& res = pc.Xb[hg.iters & 1];
   if (pc.rl)
     hip_check(launch_rows_permute(res->p, T, (const int*)pc.rl->inv->p, X, n, k, c.stream), "unpermute");
@@ -572,7 +576,10 @@ GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_p
     for (int j = 0; j < std::max(batch, 1); ++j) pc.run_pass(++pass);
     hip_check(hipMemcpyAsync(hh.data(), pc.hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
     hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+    GuardDev hg{};
+    hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
     hip_check(hipStreamSynchronize(c.stream), "sync");
+    if (hg.bad) fail(GrB_PANIC, "ppr_stream: a column's residual or dangling mass was not finite");
     const int cur = pass & 1;
     uint64_t retired = 0;
     ColumnOutputs outs{};
@@ -614,6 +621,83 @@ GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_p
     return GrB_PANIC;
   }
   return GrB_SUCCESS;
+}
+
+// ------------------------------------------------------------ sparse x dense
+
+GrB_Info GrB_mxm(GrB_Matrix C, GrB_Matrix Mask, GrB_BinaryOp accum, GrB_Semiring op, GrB_Matrix A, GrB_Matrix B,
+                 GrB_Descriptor desc) {
+  API_BEGIN
+  require_init();
+  GB_Matrix_opaque* co = mat_any(C, "C");
+  GB_Matrix_opaque* ao = mat(A, "A");
+  GB_Matrix_opaque* bo = mat_any(B, "B");
+  need(op, "semiring");
+  if (Mask) fail(GrB_NOT_IMPLEMENTED, "GrB_mxm: masks are not supported");
+  if (accum) fail(GrB_NOT_IMPLEMENTED, "GrB_mxm: accumulators are not supported");
+  if (desc) fail(GrB_NOT_IMPLEMENTED, "GrB_mxm: descriptors are not supported");
+  if (!bo->data->dense) fail(GrB_NOT_IMPLEMENTED, "GrB_mxm: B must be dense (GrM_Matrix_import_dense)");
+  if (op->add != B_PLUS || (op->mul != B_TIMES && op->mul != B_SECOND))
+    fail(GrB_NOT_IMPLEMENTED, "GrB_mxm: only plus-times / plus-second semirings");
+  const int T = op->type;
+  float_type(T, "semiring");
+  if (bo->data->dense_type != T || co->type != T) fail(GrB_DOMAIN_MISMATCH, "GrB_mxm: B, C and the semiring differ in type");
+  if (ao->ncols != bo->nrows || co->nrows != ao->nrows || co->ncols != bo->ncols)
+    fail(GrB_DIMENSION_MISMATCH, "GrB_mxm dimensions");
+  const int64_t n = ao->nrows;
+  const int k = (int)bo->ncols;
+  if (k < 1 || k > 64) fail(GrB_NOT_IMPLEMENTED, "GrB_mxm: B may have at most 64 columns");
+  Ctx& c = ctx();
+  const MatP& Am = ao->data;
+
+  // the wavefront tile plan of A (lane c of a wavefront owns column c)
+  PlanConfig wp;
+  wp.kernel = K_WAVE;
+  wp.lds_entries = WAVE_TILE_ENTRIES;
+  wp.lds_rows = WAVE_TILE_ROWS;
+  wp.long_row = WAVE_TILE_ENTRIES;
+  wp.chunk = WAVE_TILE_ENTRIES;
+  wp.grid = c.cus * 2;
+  auto plan = get_plan(Am, wp);
+  if (plan->cfg.kernel != K_WAVE)
+    fail(GrB_NOT_IMPLEMENTED, "GrB_mxm: A has too many columns for the wavefront tile plan (2^29 or more)");
+
+  auto m = std::make_shared<MatData>();
+  m->id = c.next_id++;
+  m->nrows = n;
+  m->ncols = k;
+  m->dense_type = T;
+  const size_t obytes = type_size(T) * (size_t)n * (size_t)k;
+  m->dense = dev_alloc(obytes);
+  const size_t bbytes = type_size(T) * (size_t)bo->nrows * (size_t)k;
+  BufP hub_sum = dev_alloc(sizeof(double) * 64 * (size_t)std::max(plan->nparts, 1));
+  BufP hub_cnt = dev_alloc(sizeof(int) * (size_t)std::max(plan->nhubs, 1));
+  BufP hub_red = dev_alloc(sizeof(double) * 128 * (size_t)std::max(plan->nhubs, 1));
+  hip_check(launch_zero(hub_cnt->p, sizeof(int) * (size_t)std::max(plan->nhubs, 1), c.stream), "zero");
+  launch_mark(false);
+  SpmmArgs a{};
+  a.rowptr = (const int*)Am->rowptr->p;
+  a.col = Am->col ? (const int*)Am->col->p : nullptr;
+  a.k = k;
+  a.w = bo->data->dense->p;
+  // the buffer-addressed pass needs every operand below 4 GiB
+  a.w_bytes = std::max(bbytes, obytes) < 0xFFFFFF00ull ? (unsigned)std::max(bbytes, obytes) : 0u;
+  a.x_new = m->dense->p;
+  a.hub_sum = (double*)hub_sum->p;
+  a.hub_cnt = (int*)hub_cnt->p;
+  a.hub_red = (double*)hub_red->p;
+  a.plain = 1;
+  // no more workgroups than tiles can use (16 wavefronts each)
+  const int grid = std::max(1, std::min(plan->cfg.grid, (std::max(plan->dev.ntiles, 1) + 15) / 16));
+  if (plan->dev.ntiles > 0) {
+    hip_check(launch_spmm_ppr(plan->dev, a, T, grid, nullptr, c.stream), "mxm");
+    launch_mark(false);
+  } else {
+    hip_check(launch_zero(m->dense->p, obytes, c.stream), "zero");
+    launch_mark(false);
+  }
+  co->data = m;
+  API_END
 }
 
 // ------------------------------------------------------------ many graphs
@@ -892,7 +976,8 @@ GrB_Info GrM_pagerank_many(void* X, GrB_Type type, GrM_Multigraph mg, double dam
   if (iters || resid)
     hip_check(hipMemcpyAsync(&team_err, mg->team_err->p, sizeof(int), hipMemcpyDeviceToHost, c.stream), "copy");
   if (iters || resid) hip_check(hipStreamSynchronize(c.stream), "sync");
-  if (team_err) fail(GrB_PANIC, "a team of workgroups gave up waiting for a member");
+  if (team_err & 1) fail(GrB_PANIC, "a team of workgroups gave up waiting for a member");
+  if (team_err & 2) fail(GrB_PANIC, "pagerank_many: a graph's residual was not finite");
   API_END
 }
 

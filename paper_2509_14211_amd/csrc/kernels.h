@@ -37,7 +37,7 @@ struct GuardDev {
   double rho_prev;  // the one before (lets the host predict how many more)
   double tol;
   int itermax;
-  int pad;
+  int bad;          // set when a residual or dangling mass was not finite
 };
 
 // Scalar operand: value = dev ? alpha * (*dev) + beta : beta.
@@ -236,6 +236,10 @@ struct SpmmArgs {
   double* hub_red;
   double* wg_part;
   unsigned* ticket;
+  // plain product (GrB_mxm): x_new = A (+.second) W and nothing else -- no
+  // teleport, pre-scaled copy, residual or dangling mass; x_old, dvec,
+  // seeds, tile_seed, the reductions and the guard are not used
+  int plain;
 };
 constexpr int SPMM_BLOCK = 1024;
 hipError_t launch_spmm_ppr(const TilePlanDev& plan, const SpmmArgs& a, int type, int grid,
@@ -278,7 +282,7 @@ struct ManyArgs {
   int* queue_next;    // reset to 0 by the launch
   unsigned* team_bar;   // per graph: team arrivals, reset to 0 by the launch
   double* team_part;    // per graph: [barrier parity][member][residual, dangling]
-  int* team_err;        // set when a team member waited too long (reset by the launch)
+  int* team_err;        // bit 0: a team member waited too long; bit 1: a residual was not finite (reset by the launch)
   unsigned long long team_wait_ticks;  // give-up limit of a team wait, in 100 MHz wall-clock ticks
   int ngraphs;
   int nslots;         // queue entries: one per team member, one per single graph

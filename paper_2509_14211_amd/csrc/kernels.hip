@@ -56,13 +56,19 @@ __device__ __forceinline__ V block_sum(V v, V* red) {
   return r;
 }
 
-// Called by thread 0 of the block that produced a guarded residual.
-__device__ __forceinline__ void guard_advance(GuardDev* g, double rho) {
+// Called by thread 0 of the block that produced a guarded residual (and,
+// for the fused pass, the dangling mass of the same pass, 0 when none is
+// computed).  A residual or mass that is not finite ends the loop and marks
+// the guard bad, which the drivers report as an execution error: a NaN
+// compares false with the tolerance and would otherwise read as converged.
+__device__ __forceinline__ void guard_advance(GuardDev* g, double rho, double D = 0.0) {
   g->rho_prev = g->rho;
   g->rho = rho;
   const int it = g->iters + 1;
   g->iters = it;
-  g->active = (rho > g->tol && it < g->itermax) ? 1 : 0;
+  const bool finite = __builtin_isfinite(rho) && __builtin_isfinite(D);
+  if (!finite) g->bad = 1;
+  g->active = (finite && rho > g->tol && it < g->itermax) ? 1 : 0;
 }
 
 // ---------------------------------------------------------- fused PR pass
@@ -310,7 +316,7 @@ __global__ __launch_bounds__(FUSED_BLOCK) void fused_pr_kernel(TilePlanDev plan,
   if (tid == 0) {
     if (a.rho_out.out) *a.rho_out.out = tr;
     if (a.D_out.out) *a.D_out.out = tdm;
-    if (a.rho_out.guard) guard_advance(a.rho_out.guard, tr);
+    if (a.rho_out.guard) guard_advance(a.rho_out.guard, tr, a.do_D ? tdm : 0.0);
     publish(scr.ticket, 0u);
   }
 }
@@ -510,6 +516,11 @@ __device__ __forceinline__ void wave_process(const TilePlanDev& plan, const Fuse
         publish(&scr.hub_red[2 * h], hr);
         publish(&scr.hub_red[2 * h + 1], hd);
         publish(&scr.hub_cnt[h], 0);
+        // Any wavefront of the workgroup may finish a hub, but only thread
+        // 0 waits for its own stores before the workgroup takes its ticket:
+        // the hub row's partials must be complete before this wavefront
+        // reaches the workgroup barrier that precedes the ticket.
+        wait_stores();
       }
     }
   }
@@ -646,7 +657,7 @@ __global__ __launch_bounds__(WAVE_BLOCK) void fused_wave_kernel(TilePlanDev plan
   if (tid == 0) {
     if (a.rho_out.out) *a.rho_out.out = tr;
     if (a.D_out.out) *a.D_out.out = tdm;
-    if (a.rho_out.guard) guard_advance(a.rho_out.guard, tr);
+    if (a.rho_out.guard) guard_advance(a.rho_out.guard, tr, a.do_D ? tdm : 0.0);
     publish(scr.ticket, 0u);
   }
 }
@@ -875,7 +886,7 @@ __global__ void guard_init_kernel(GuardDev* g, int active, double tol, int iterm
   g->rho_prev = 0.0;
   g->tol = tol;
   g->itermax = itermax;
-  g->pad = 0;
+  g->bad = 0;
 }
 
 hipError_t launch_guard_init(GuardDev* g, int active, double tol, int itermax, hipStream_t s) {

@@ -75,7 +75,7 @@ __device__ bool team_wait(unsigned* bar, unsigned target, int* err, uint64_t tic
   const uint64_t t0 = wall_clock64();
   while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     if (wall_clock64() - t0 > ticks) {
-      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
     __builtin_amdgcn_s_sleep(2);
@@ -297,6 +297,9 @@ __global__ __launch_bounds__(MB) void pr_many_kernel(ManyArgs p) {
     if (tid == 0 && mk == 0) {
       p.iters[gi] = it;
       p.resid[gi] = rho;
+      // a residual that is not finite ended this graph's loop (a NaN
+      // compares false with the tolerance): flag it (bit 1) for the driver
+      if (!__builtin_isfinite(rho)) __hip_atomic_fetch_or(p.team_err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
   }

@@ -69,6 +69,10 @@ struct MatData {
   std::shared_ptr<MatData> transposed;  // built on demand for push-style mxv
   BufP long_rows;                       // rows longer than SV_LONG_ROW, for the pull mxv (on demand)
   int64_t nlong = -1;                   // their count; -1 until computed
+  // A dense matrix (the operand and result of GrB_mxm) holds nrows x ncols
+  // values of type dense_type, row-major, in `dense`, and no pattern.
+  BufP dense;
+  int dense_type = -1;
 };
 
 // Kernel family of a plan.

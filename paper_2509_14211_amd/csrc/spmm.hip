@@ -38,6 +38,10 @@ __device__ __forceinline__ void spmm_finish(const SpmmArgs& p, int i, T s, int l
   }
   if (!on) return;
   const int64_t at = (int64_t)i * p.k + lane;
+  if (p.plain) {
+    __builtin_nontemporal_store(s, (T*)p.x_new + at);
+    return;
+  }
   const T r = s + tele;
   __builtin_nontemporal_store(r, (T*)p.x_new + at);
   ((T*)p.w_new)[at] = r * dv;
@@ -47,8 +51,16 @@ __device__ __forceinline__ void spmm_finish(const SpmmArgs& p, int i, T s, int l
 
 template <typename T>
 __device__ __forceinline__ T load_xo(const SpmmArgs& p, int i, int lane, bool on) {
-  return on ? __builtin_nontemporal_load((const T*)p.x_old + (int64_t)i * p.k + lane) : (T)0;
+  return (on && !p.plain) ? __builtin_nontemporal_load((const T*)p.x_old + (int64_t)i * p.k + lane) : (T)0;
 }
+
+template <typename T>
+__device__ __forceinline__ T load_dv(const SpmmArgs& p, int i) {
+  return p.plain ? (T)0 : ((const T*)p.dvec)[i];
+}
+
+// First vertex-sorted seed of tile t (no seeds in a plain product).
+__device__ __forceinline__ int first_seed(const SpmmArgs& p, int t) { return p.nseeds > 0 ? p.tile_seed[t] : 0; }
 
 // Hub row h: once every chunk has published its k-wide partial sum, the
 // wavefront that finished last adds them in chunk order and runs the
@@ -76,8 +88,8 @@ __device__ void spmm_hub_finish(const SpmmArgs& p, int4 hub, int h, int chunk, i
   int sp = sp0;
   int nsv = sp < p.nseeds ? p.seed_v[sp] : 0x7fffffff;
   double hr = 0.0, hd = 0.0;
-  spmm_finish<T>(p, hub.x, s, lane, on, cfac, load_xo<T>(p, hub.x, lane, on), ((const T*)p.dvec)[hub.x], sp, nsv,
-                 hr, hd);
+  spmm_finish<T>(p, hub.x, s, lane, on, cfac, load_xo<T>(p, hub.x, lane, on), load_dv<T>(p, hub.x), sp, nsv, hr,
+                 hd);
   publish(&p.hub_red[(int64_t)h * 128 + lane], hr);
   publish(&p.hub_red[(int64_t)h * 128 + 64 + lane], hd);
   if (lane == 0) publish(&p.hub_cnt[h], 0);
@@ -140,19 +152,24 @@ __device__ void spmm_reduce(const TilePlanDev& plan, const SpmmArgs& p, double r
   __syncthreads();
   if (tid == 0) {
     double mx = 0.0;
+    bool finite = true;
     const int it = p.guard ? p.guard->iters + 1 : 0;
     for (int c = 0; c < p.k; ++c) {
       p.rho_out[c] = sr[0][c];
       p.d_out[c] = sd[0][c];
       if (sr[0][c] > mx) mx = sr[0][c];
+      finite = finite && __builtin_isfinite(sr[0][c]) && __builtin_isfinite(sd[0][c]);
       if (p.hit && p.hit[c] < 0 && p.guard && sr[0][c] <= p.hit_tol) p.hit[c] = it;
     }
     if (p.guard) {
+      // a column whose residual or dangling mass is not finite ends the
+      // loop and marks the guard bad (reported as an execution error)
       GuardDev* g = p.guard;
       g->rho_prev = g->rho;
-      g->rho = mx;
+      g->rho = finite ? mx : __builtin_nan("");
       g->iters = it;
-      g->active = (mx > g->tol && it < g->itermax) ? 1 : 0;
+      if (!finite) g->bad = 1;
+      g->active = (finite && mx > g->tol && it < g->itermax) ? 1 : 0;
     }
     publish(p.ticket, 0u);
   }
@@ -179,8 +196,12 @@ __device__ __forceinline__ void spmm_finish_b(const SpmmArgs& p, const RowBufs& 
     nsv = sp < p.nseeds ? wave_uniform(p.seed_v[sp]) : 0x7fffffff;
   }
   if (!on) return;
-  const T r = s + tele;
   const int so = row_off(b, i);
+  if (p.plain) {
+    buf_store<T, CP_NT>(b.xn, s, b.voff, so);
+    return;
+  }
+  const T r = s + tele;
   buf_store<T, CP_NT>(b.xn, r, b.voff, so);
   buf_store<T, 0>(b.wn, r * dv, b.voff, so);
   rho += fabs((double)xo - (double)r);
@@ -213,6 +234,7 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
   __shared__ int sflag;
   const int tid = threadIdx.x, wv = wave_uniform(tid >> 6), lane = tid & 63;
   const bool on = lane < p.k;
+  const bool plain = p.plain != 0;
   RowBufs b;
   b.row_bytes = (unsigned)p.k * (unsigned)sizeof(T);
   b.voff = on ? lane * (int)sizeof(T) : 0;
@@ -236,13 +258,13 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      int sp = wave_uniform(p.tile_seed[t]);
+      int sp = wave_uniform(first_seed(p, t));
       int nsv = sp < p.nseeds ? wave_uniform(p.seed_v[sp]) : 0x7fffffff;
       int r = 0;
       int rend = wave_uniform(wrp[1]);
       T acc = 0;
-      T xo = buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0));
-      T dv = wave_uniform(((const T*)p.dvec)[row0]);
+      T xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0));
+      T dv = wave_uniform(load_dv<T>(p, row0));
       for (int c0 = 0; c0 < ne; c0 += 64) {
         const int cn = c0 + 64 + lane;
         const int coln = cn < ne ? p.col[e0 + cn] : 0;
@@ -262,8 +284,8 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
                 acc = 0;
                 ++r;
                 rend = wave_uniform(wrp[r + 1]);
-                xo = buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
-                dv = wave_uniform(((const T*)p.dvec)[row0 + r]);
+                xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
+                dv = wave_uniform(load_dv<T>(p, row0 + r));
               }
               acc += v[u];
             }
@@ -276,8 +298,8 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
         acc = 0;
         ++r;
         if (r < nr) {
-          xo = buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
-          dv = wave_uniform(((const T*)p.dvec)[row0 + r]);
+          xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
+          dv = wave_uniform(load_dv<T>(p, row0 + r));
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -301,10 +323,11 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
         }
         colv = coln;
       }
-      spmm_hub_finish<T>(p, wave_uniform(plan.hubs[h]), h, td.x, wave_uniform(p.tile_seed[t]), acc, lane, on, cfac);
+      spmm_hub_finish<T>(p, wave_uniform(plan.hubs[h]), h, td.x, wave_uniform(first_seed(p, t)), acc, lane, on,
+                         cfac);
     }
   }
-  spmm_reduce(plan, p, rho, dm, sr, sd, &sflag);
+  if (!plain) spmm_reduce(plan, p, rho, dm, sr, sd, &sflag);
 }
 
 // The same pass with 64-bit addressing, for operands of 4 GiB or more: the
@@ -338,12 +361,12 @@ __global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArg
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     T acc = 0;
-    int r = 0, sp = p.tile_seed[t];
+    int r = 0, sp = first_seed(p, t);
     int nsv = sp < p.nseeds ? p.seed_v[sp] : 0x7fffffff;
     const int row0 = td.x, nr = td.y;
     int rend = td.y > 0 ? wrp[1] : 0x7fffffff;
     T xo = td.y > 0 ? load_xo<T>(p, row0, lane, on) : (T)0;
-    T dv = td.y > 0 ? ((const T*)p.dvec)[row0] : (T)0;
+    T dv = td.y > 0 ? load_dv<T>(p, row0) : (T)0;
     for (int base = 0; base < ne; base += U) {
       int cj[U];
 #pragma unroll
@@ -367,7 +390,7 @@ __global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArg
             ++r;
             rend = wrp[r + 1];
             xo = load_xo<T>(p, row0 + r, lane, on);
-            dv = ((const T*)p.dvec)[row0 + r];
+            dv = load_dv<T>(p, row0 + r);
           }
           acc += v[u];
         }
@@ -380,7 +403,7 @@ __global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArg
         ++r;
         if (r < nr) {
           xo = load_xo<T>(p, row0 + r, lane, on);
-          dv = ((const T*)p.dvec)[row0 + r];
+          dv = load_dv<T>(p, row0 + r);
         }
       }
     } else {
@@ -390,7 +413,7 @@ __global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArg
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();  // the next tile rewrites wcol / wrp
   }
-  spmm_reduce(plan, p, rho, dm, sr, sd, &sflag);
+  if (!p.plain) spmm_reduce(plan, p, rho, dm, sr, sd, &sflag);
 }
 
 // First seed (in vertex order) at or after the first row of each tile.
@@ -487,7 +510,8 @@ __global__ void rows_permute_kernel(const void* __restrict__ in, int type, const
 
 hipError_t launch_spmm_ppr(const TilePlanDev& plan, const SpmmArgs& a, int type, int grid,
                            const GuardDev* guard, hipStream_t s) {
-  if (grid <= 0 || a.k < 1 || a.k > 64 || !a.tile_seed) return hipErrorInvalidValue;
+  if (grid <= 0 || a.k < 1 || a.k > 64 || (a.nseeds > 0 && !a.tile_seed)) return hipErrorInvalidValue;
+  if (!a.plain && (!a.x_old || !a.dvec || !a.w_new || !a.rho_out || !a.d_out)) return hipErrorInvalidValue;
   const bool wide = a.w_bytes == 0;  // operand of 4 GiB or more
   if (type == T_FP32) {
     if (wide)

@@ -138,6 +138,9 @@ _FUNCS = {
     "GrM_Matrix_export_CSR": [vp, vp, vp],
     "GrM_Matrix_build_edges": [vp, vp, vp, u64, ctypes.c_bool],
     "GrB_transpose": [vp, vp, vp, vp, vp],
+    "GrM_Matrix_import_dense": [vp, vp, u64, u64],
+    "GrM_Matrix_export_dense": [vp, vp],
+    "GrB_mxm": [vp, vp, vp, vp, vp, vp, vp],
     "GrM_Matrix_row_degree": [vp, vp],
     "GrM_rmat_edges": [vp, vp, i32, u64, u64, dbl, dbl, dbl],
     "GrM_web_edges": [vp, vp, u64, ctypes.POINTER(u64), u64, u64, ctypes.c_void_p],
@@ -511,6 +514,18 @@ def GrM_Matrix_export_CSR(rowptr, col, A):
 
 def GrM_Matrix_build_edges(A, src, dst, nedges: int, drop_self: bool = True):
     _call("GrM_Matrix_build_edges", A, _addr(src), _addr(dst), nedges, drop_self)
+
+
+def GrM_Matrix_import_dense(A, src, nrows: int, ncols: int):
+    _call("GrM_Matrix_import_dense", A, _addr(src), nrows, ncols)
+
+
+def GrM_Matrix_export_dense(dst, A):
+    _call("GrM_Matrix_export_dense", _addr(dst), A)
+
+
+def GrB_mxm(C, Mask, accum, op, A, B, desc=None):
+    _call("GrB_mxm", C, Mask, accum, op, A, B, desc)
 
 
 def GrB_transpose(C, Mask, accum, A, desc=None):

@@ -115,11 +115,21 @@ def random_vector(n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.nd
     return lo + (hi - lo) * rng.random(n)
 
 
+def _splitmix64_first(seed: int) -> int:
+    """First output of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014)
+    seeded with `seed`: one increment of the state, then the mix."""
+    m = (1 << 64) - 1
+    z = (seed + 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
 def many_graph_specs(count: int = 256, base_seed: int = 3000, smin: int = 10,
                      smax: int = 16):
     """(scale, seed) of each graph of the many-small-graphs workload: graph
-    i has seed base_seed + i and a scale drawn uniformly from smin..smax by a
-    numpy generator seeded with base_seed."""
-    rng = np.random.default_rng(base_seed)
-    scales = rng.integers(smin, smax + 1, count)
-    return [(int(scales[i]), base_seed + i) for i in range(count)]
+    i has seed base_seed + i and scale smin + (SplitMix64(base_seed + i) mod
+    (smax - smin + 1)), the first draw of the generator seeded with the
+    graph's seed."""
+    k = smax - smin + 1
+    return [(smin + _splitmix64_first(base_seed + i) % k, base_seed + i) for i in range(count)]

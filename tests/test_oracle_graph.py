@@ -31,6 +31,19 @@ def test_splitmix64_published_vector(oracle_mod):
         assert oracle_mod.splitmix64(1234567, k) == v
 
 
+def test_many_graph_scales_follow_the_stated_rule():
+    """Graph i of the many-graph workload has scale 10 + (first SplitMix64
+    draw of seed 3000 + i) mod 7; the first draw is pinned by the published
+    vector, and the scales cover 10..16."""
+    pairs = _golden_pairs("splitmix64_seed1234567.txt")
+    assert synthetic._splitmix64_first(1234567) == dict(pairs)[0]
+    specs = synthetic.many_graph_specs(256)
+    assert [s for _, s in specs] == list(range(3000, 3256))
+    for scale, seed in specs:
+        assert scale == 10 + synthetic._splitmix64_first(seed) % 7
+    assert {sc for sc, _ in specs} == set(range(10, 17))
+
+
 @pytest.mark.parametrize("scale,seed", [(10, 10), (12, 99)])
 def test_rmat_quadrant_frequencies(oracle_mod, scale, seed):
     """Each level picks quadrant a/b/c/d with probability .57/.19/.19/.05:
