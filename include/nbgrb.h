@@ -200,6 +200,7 @@ typedef struct {
   int64_t out_sparse;       /* ... stored sparse */
   int64_t index_loops;      /* elementwise loops driven by a sparse input's entries */
   int64_t range_loops;      /* ... over the whole index range */
+  int64_t device_allocs;    /* device buffers handed out, from the cache or the allocator */
 } GrM_Stats;
 GrB_Info GrM_get_stats(GrM_Stats *stats);
 GrB_Info GrM_reset_stats(void);
@@ -760,6 +761,29 @@ GrB_Info GrM_stream_copy(void *dst_dev, const void *src_dev, size_t bytes);
  * enqueues check_every passes between host checks). */
 GrB_Info GrM_timing_enable(bool on);
 GrB_Info GrM_timing_read(double *total_ms, int64_t *launches);
+
+/* ------------------------------------------------------------------------
+ * Allocation-free sum, for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, hosts that forbid allocation).
+ *
+ * *sum_dev = the sum of x_dev[0:n) in FP64, enqueued on the library stream.
+ * Same kernel, grid and summation order as GrB_Vector_reduce_FP64 on a full
+ * vector holding the same n values, so the two give bit-identical sums.
+ *   sum_dev  device, one double, written (not accumulated into);
+ *   x_dev    device, n values of `type` (GrB_FP32 or GrB_FP64), read only;
+ *            may be NULL when n == 0 (the sum is then 0);
+ *   n        at most GRM_NOALLOC_MAX_N.
+ * The call allocates nothing and does not synchronise.  Its scratch (one
+ * FP64 partial per workgroup, at most 1024, and a completion ticket: 8.4 KB)
+ * is a static device array that every call on a device shares; GrB_init
+ * locates this device's copy.  Two calls that overlap on one device (other
+ * streams or host threads) race on it and give wrong sums; calls in stream
+ * order are safe.  Errors: GrB_NULL_POINTER (sum_dev, type, or x_dev with
+ * n > 0), GrB_DOMAIN_MISMATCH (type not FP32/FP64), GrB_INVALID_VALUE
+ * (n > GRM_NOALLOC_MAX_N), GrB_PANIC (launch failure).
+ * ---------------------------------------------------------------------- */
+#define GRM_NOALLOC_MAX_N (1ull << 40)
+GrB_Info GrM_reduce_dense_noalloc(double *sum_dev, const void *x_dev, GrB_Type type, GrB_Index n);
 
 #ifdef __cplusplus
 }

@@ -291,6 +291,7 @@ GrB_Info GrB_init(GrB_Mode mode) {
   c.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   c.mode = mode;
   c.stream = nullptr;
+  noalloc_setup(c.device, nullptr);
   c.stats = Stats{};
   c.init = true;
   API_END
@@ -407,6 +408,7 @@ GrB_Info GrM_get_stats(GrM_Stats* s) {
   s->out_sparse = t.out_sparse;
   s->index_loops = t.index_loops;
   s->range_loops = t.range_loops;
+  s->device_allocs = t.device_allocs;
   API_END
 }
 

@@ -242,6 +242,7 @@ struct Stats {
   int64_t mxv_push = 0, mxv_pull = 0;        // sparse-path mxv by loop driver
   int64_t out_full = 0, out_bitset = 0, out_sparse = 0;  // sparse-path output formats
   int64_t index_loops = 0, range_loops = 0;  // sparse-path elementwise loop drivers
+  int64_t device_allocs = 0;  // device buffers handed out (cache hits included)
 };
 
 struct Ctx {
@@ -300,6 +301,9 @@ ScalarArg scalar_arg(const NodeP& s);
 Operand operand_of(const NodeP& v);
 
 void launch_mark(bool fused);
+// Finds this device's copy of the allocation-free entry point's static
+// scratch array (the device must be current); once per device.
+void noalloc_setup(int device, hipStream_t s);
 
 // Scratch of the deterministic reduction kernel on the context stream.
 RedScratch reduce_scratch();

@@ -72,6 +72,7 @@ static size_t round_bytes(size_t b) {
 
 BufP dev_alloc(size_t bytes) {
   Ctx& c = g_ctx;
+  c.stats.device_allocs++;
   const size_t rb = round_bytes(bytes);
   auto it = c.cache.find(rb);
   void* p = nullptr;

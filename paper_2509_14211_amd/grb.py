@@ -81,7 +81,7 @@ class GrM_Stats(ctypes.Structure):
                 ("ewise_fused", i64), ("ewise_ops", i64), ("jit_compiles", i64),
                 ("jit_disk_hits", i64), ("jit_memory_hits", i64), ("mxv_push", i64), ("mxv_pull", i64),
                 ("out_full", i64), ("out_bitset", i64), ("out_sparse", i64), ("index_loops", i64),
-                ("range_loops", i64)]
+                ("range_loops", i64), ("device_allocs", i64)]
 
 
 # name -> (restype, argtypes).  All return GrB_Info unless noted.
@@ -182,6 +182,7 @@ _FUNCS = {
     "GrM_stream_copy": [vp, vp, ctypes.c_size_t],
     "GrM_timing_enable": [ctypes.c_bool],
     "GrM_timing_read": [ctypes.POINTER(dbl), ctypes.POINTER(i64)],
+    "GrM_reduce_dense_noalloc": [vp, vp, vp, u64],
 }
 
 _lib = None
@@ -714,6 +715,11 @@ def GrM_pagerank_many(X, type_, mg, ngraphs: int, damping, tol, itermax,
 
 def GrM_stream_copy(dst, src, nbytes: int):
     _call("GrM_stream_copy", _addr(dst), _addr(src), nbytes)
+
+
+def GrM_reduce_dense_noalloc(sum_dev, x_dev, type_, n: int):
+    """*sum_dev = sum of x_dev[0:n) (device pointers or tensors), allocating nothing."""
+    _call("GrM_reduce_dense_noalloc", _addr(sum_dev), _addr(x_dev) if x_dev is not None else None, type_, n)
 
 
 def GrM_timing_enable(on: bool):
