@@ -46,27 +46,34 @@ def blocking_bytes_per_pass(n: int, m: int, b: int) -> int:
 
 
 COPY_BYTES = 1 << 30  # bytes read and written by one launch of the copy probe
-PROFILE_MD = os.path.join(ROOT, "profiles", "fused_wave_kernel_rmat22.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_14211_amd", "csrc", f)
-                  for f in ("kernels.hip", "kernels.h", "device_util.h", "ops_device.h")]
+# fused FP32 kernel of each plan kind: name, committed profile summary of
+# the scale-22 pass, sources whose hash the summary records
+FUSED_KERNELS = {
+    0: ("fused_pr_kernel<float, ...>", None, ("kernels.hip",)),
+    1: ("fused_wave_kernel<float, ...>", "fused_wave_kernel_rmat22.md", ("kernels.hip",)),
+    2: ("fused_stripe_kernel", "fused_stripe_kernel_rmat22.md", ("stripe.hip",)),
+}
+TRAFFIC_KERNELS = {"fused_wave_kernel<float": 1, "fused_stripe_kernel": 2}
 
 
-def kernel_source_sha() -> str:
-    """sha256 over the sources that define the fused kernels."""
+def kernel_source_sha(kind: int = 1) -> str:
+    """sha256 over the sources that define the fused kernel of a plan kind."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
+    for f in FUSED_KERNELS[kind][2] + ("kernels.h", "device_util.h", "ops_device.h"):
+        with open(os.path.join(ROOT, "paper_2509_14211_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """HBM-side bytes per launch of the fused FP32 kernel as recorded in the
-    committed profile summary, or None when the summary is missing or the
-    kernel sources changed since the counters were taken."""
+def recorded_traffic(kind: int):
+    """HBM-side bytes per launch of the fused FP32 kernel of a plan kind as
+    recorded in the committed profile summary, or None when the summary is
+    missing or the kernel sources changed since the counters were taken."""
+    if FUSED_KERNELS[kind][1] is None:
+        return None
     try:
-        text = open(PROFILE_MD).read()
+        text = open(os.path.join(ROOT, "profiles", FUSED_KERNELS[kind][1])).read()
     except OSError:
         return None
     kv = {}
@@ -74,7 +81,7 @@ def recorded_traffic():
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != kernel_source_sha():
+    if kv.get("source_sha256") != kernel_source_sha(kind):
         return None
     try:
         return int(kv["traffic_bytes_per_launch"])
@@ -161,8 +168,8 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float", min
         if len(keep) != len(wv):
             print("- launches_counted: %d of %d (WRITE_SIZE >= %.0f KiB)" % (len(keep), len(wv), min_write_kib))
         print("- traffic_bytes_per_launch: %d" % int(round(traffic)))
-        if traffic_kernel == "fused_wave_kernel<float":
-            print("- source_sha256: %s" % kernel_source_sha())
+        if traffic_kernel in TRAFFIC_KERNELS:
+            print("- source_sha256: %s" % kernel_source_sha(TRAFFIC_KERNELS[traffic_kernel]))
         print()
 
 
@@ -175,8 +182,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=16.0,
-                    help="target length of the CPU oracle sample (whole passes)")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="target length of the one-thread CPU oracle sample (whole solves)")
     ap.add_argument("--ppr-k", type=int, default=64, help="seed sets of the batched PPR leg")
     ap.add_argument("--ppr-stream", type=int, default=512,
                     help="seed sets streamed through the ppr-k column slots (0: skip)")
@@ -290,17 +297,16 @@ def main():
         log("fused fp32: %d iterations, %.3f ms/solve, %.1f GTEPS" % (it32, ms32, gteps))
 
         # ---- roofline of the fused pass
+        kind32 = tuned["GrB_FP32"]["kernel"]
         avg_us = pass_time_us(torch.float32)
         bpp = fused_bytes_per_pass(n, m, 4)
         achieved = bpp / (avg_us * 1e-6) / 1e9
         log("fused pass: %.2f us, %.1f GB/s algorithmic" % (avg_us, achieved))
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                           # the committed counters cover the wave kernel on the scale-22 graph only
-                           "traffic": recorded_traffic() if args.scale == 22 and tuned["GrB_FP32"]["kernel"] == 1
-                           else None,
-                           "kernel": "fused_wave_kernel<float, ...>" if tuned["GrB_FP32"]["kernel"] == 1
-                           else "fused_pr_kernel<float, ...>",
+                           # the committed counters cover the scale-22 graph only
+                           "traffic": recorded_traffic(kind32) if args.scale == 22 else None,
+                           "kernel": FUSED_KERNELS[kind32][0],
                            "bytes_per_launch": bpp, "avg_launch_us": round(avg_us, 3)}
         if out["roofline"]["traffic"]:
             # fabric-side rate of the same pass: counter bytes over the pass time
@@ -713,8 +719,9 @@ def main():
                                  "ms_per_query_teleport": round(ev["ms_teleport"], 3),
                                  "fallbacks": ev["fallbacks"]}
 
-        # ---- CPU oracle on a bounded sample: the same graph, a fixed number
-        # of passes, and the GPU error against it at that pass count.
+        # ---- CPU oracle: solves to the same tolerance on the same graph, 1
+        # warm-up + 16 timed at the host's thread count and a bounded sample
+        # at one thread; the GPU error against it at the same pass count.
         if not args.no_cpu_baseline:
             import oracle
             threads = min(16, os.cpu_count() or 1)
@@ -722,22 +729,24 @@ def main():
             t0 = time.perf_counter()
             og = oracle.rmat_graph(args.scale)
             build_s = time.perf_counter() - t0
-            oracle.pagerank(og, DAMPING, fixed_iters=2)  # warm-up
+            ref = oracle.pagerank(og, DAMPING, tol=args.tol)  # warm-up
+            runs = 16
             t0 = time.perf_counter()
-            oracle.pagerank(og, DAMPING, fixed_iters=8)  # pass time estimate
-            per_pass = (time.perf_counter() - t0) / 8
-            k = max(8, int(args.cpu_seconds / max(per_pass, 1e-6)))
-            t0 = time.perf_counter()
-            ref = oracle.pagerank(og, DAMPING, fixed_iters=k)
-            cpu_s = time.perf_counter() - t0
-            cpu_gteps = og.m * k / cpu_s / 1e9
-            # one thread, a few passes (the oracle's result does not depend on
-            # the thread count)
+            for _ in range(runs):
+                ref = oracle.pagerank(og, DAMPING, tol=args.tol)
+            cpu_s = (time.perf_counter() - t0) / runs
+            cpu_gteps = og.m * ref.iters / cpu_s / 1e9
+            # one thread: solves to tolerance until about cpu_seconds have
+            # passed (at least one; the result does not depend on the thread
+            # count)
             oracle.set_threads(1)
-            k1 = 8
-            t0 = time.perf_counter()
-            oracle.pagerank(og, DAMPING, fixed_iters=k1)
-            cpu1_s = time.perf_counter() - t0
+            runs1, t1 = 0, 0.0
+            while runs1 == 0 or (t1 < args.cpu_seconds and runs1 < 16):
+                t0 = time.perf_counter()
+                r1 = oracle.pagerank(og, DAMPING, tol=args.tol)
+                t1 += time.perf_counter() - t0
+                runs1 += 1
+            cpu1_s = t1 / runs1
             oracle.set_threads(threads)
             model = ""
             try:
@@ -745,16 +754,21 @@ def main():
                     model = next((ln.split(":", 1)[1].strip() for ln in f_ if ln.startswith("model name")), "")
             except OSError:
                 pass
+            k = ref.iters
             xk, itk, _ = api.pagerank(g, torch.float32, DAMPING, 0.0, k, grb.GrM_DANGLING_UNIFORM, None, 8)
             errk = float(np.abs(xk.double().cpu().numpy() - ref.x).sum())
-            log("oracle: %d passes in %.2fs on %d threads (%.3f GTEPS); graph build %.1fs; "
-                "GPU fp32 L1 error at %d passes: %.3e" % (k, cpu_s, threads, cpu_gteps, build_s, k, errk))
+            log("oracle: %d passes to tol %g, %.3fs per solve on %d threads (%.3f GTEPS), %.2fs on one; "
+                "graph build %.1fs; GPU fp32 L1 error at %d passes: %.3e"
+                % (k, args.tol, cpu_s, threads, cpu_gteps, cpu1_s, build_s, k, errk))
             out["cpu_baseline"] = {"value": round(cpu_gteps, 4), "unit": "GTEPS", "cores": threads,
                                    "kind": "oracle",
-                                   "sample": "%d blocking FP64 passes on the same R-MAT scale-%d graph "
-                                             "(%.1f s)" % (k, args.scale, cpu_s),
-                                   "one_thread_value": round(og.m * k1 / cpu1_s / 1e9, 4),
-                                   "one_thread_sample": "%d passes (%.1f s)" % (k1, cpu1_s),
+                                   "sample": "blocking FP64 solves of the same R-MAT scale-%d graph to L1 %g "
+                                             "(%d passes): 1 warm-up + %d timed, %.3f s each"
+                                             % (args.scale, args.tol, k, runs, cpu_s),
+                                   "seconds_to_tol": round(cpu_s, 4),
+                                   "one_thread_value": round(og.m * r1.iters / cpu1_s / 1e9, 4),
+                                   "one_thread_seconds_to_tol": round(cpu1_s, 3),
+                                   "one_thread_sample": "%d solves to L1 %g, no warm-up" % (runs1, args.tol),
                                    "host_cpus": os.cpu_count(), "host_model": model}
             out["l1_fp32_vs_oracle_fixed_passes"] = errk
         g.free()

@@ -494,14 +494,21 @@ GrB_Info GrB_Vector_eWiseAdd_BinaryOp(GrB_Vector w, GrB_Vector mask, GrB_BinaryO
  * form of it, Section III-B). */
 GrB_Info GrB_Vector_apply(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
                           GrB_UnaryOp op, GrB_Vector u, GrB_Descriptor desc);
-/* w(i) = op(s, u(i)) and w(i) = op(u(i), s) with a host scalar s. */
+/* w(i) = op(s, u(i)) and w(i) = op(u(i), s) with a host scalar s.
+ * Defined by: an elementwise operation with an iso-valued vector (Section
+ * III-B: vectors whose entries all hold one value); Fig. 6 builds the
+ * teleport term as such a vector and adds it with ewise_add. */
 GrB_Info GrB_Vector_apply_BinaryOp1st_FP64(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
                                            GrB_BinaryOp op, double s, GrB_Vector u,
                                            GrB_Descriptor desc);
 GrB_Info GrB_Vector_apply_BinaryOp2nd_FP64(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
                                            GrB_BinaryOp op, GrB_Vector u, double s,
                                            GrB_Descriptor desc);
-/* w(i) = op(u(i), s) with s a (possibly pending) GrB_Scalar. */
+/* w(i) = op(u(i), s) with s a (possibly pending) GrB_Scalar.
+ * Defined by: the same iso-vector form with the value held by a scalar
+ * object (Fig. 6 keeps the residual in a GraphBLAS scalar); a pending
+ * scalar stays on the device, so the dangling share of the uniform
+ * PageRank variant never goes through the host. */
 GrB_Info GrB_Vector_apply_BinaryOp2nd_Scalar(GrB_Vector w, GrB_Vector mask, GrB_BinaryOp accum,
                                              GrB_BinaryOp op, GrB_Vector u, GrB_Scalar s,
                                              GrB_Descriptor desc);
@@ -629,8 +636,9 @@ GrB_Info GrM_pagerank_many(void *X, GrB_Type type, GrM_Multigraph mg, double dam
  * Tile plans.  The row-parallel kernels (mxv and the fused PageRank pass)
  * walk a plan of row tiles built once per matrix and configuration on the
  * host (the analogue of the paper's compiled-kernel cache keyed by a method
- * signature, Section III-C):
- *   kernel       0: one workgroup per tile; 1: one wavefront per tile
+ * signasignature, Section III-C):
+ *   kernel       0: one workgroup per tile; 1: one wavefront per tile;
+ *                2: stripes of rows (kernel 2 below)
  *   lds_entries  entries a tile stages in LDS (kernel 0: 1024, 2048 or 4096;
  *                kernel 1: 512)
  *   lds_rows     rows per tile (kernel 0: 512 with 1024 entries, else 1024;
@@ -641,18 +649,35 @@ GrB_Info GrM_pagerank_many(void *X, GrB_Type type, GrM_Multigraph mg, double dam
  *                of this size reduced by several workgroups
  *                (long_row <= chunk <= lds_entries)
  *   grid         persistent workgroups (0: 8 per compute unit)
+ * Kernel 2 (FP32 ranks only; other types run kernel 1) cuts the rows into
+ * stripes of at most 8064 rows whose sums stay in LDS while the columns
+ * are visited in blocks of 12288: a stripe loads the leading blocks into
+ * LDS one at a time (at most hot/12288 of them, and only blocks holding at
+ * least long_row of its entries, 512 when long_row is 0) and gathers its
+ * other entries from memory.
+ * Row sums are exact 64-bit fixed-point sums of the FP32 terms scaled by
+ * 2^F, F = 62 - ceil(log2(longest row * max|w|)), rounded once to FP32, so
+ * they do not depend on the order of accumulation; the truncation of each
+ * term to the fixed-point grid adds at most (row length) * 2^-F to a row
+ * sum.  lds_entries, lds_rows, chunk and xcd_split are ignored; grid is the
+ * number of workgroups (0: one per compute unit).  Matrices with 2^30 or
+ * more columns or 2^31 or more entries run kernel 1 instead.
  * The choice never changes results beyond floating-point reassociation.
  * ---------------------------------------------------------------------- */
 typedef struct {
   int32_t kernel;   /* 0: workgroup tiles; 1: wavefront tiles (lds_entries 512,
-                       lds_rows 256, 1024-thread workgroups) */
+                       lds_rows 256, 1024-thread workgroups); 2: row stripes
+                       with the leading columns in LDS blocks (FP32 only; see
+                       below) */
   int32_t lds_entries;
   int32_t lds_rows;
   int32_t long_row;
   int32_t chunk;
   int32_t grid;
   int32_t hot;      /* kernel 1: leading entries of the gathered vector kept in
-                       LDS (clamped to what fits) */
+                       LDS (clamped to what fits); kernel 2: leading columns
+                       that may be held in LDS blocks (whole blocks of 12288,
+                       0: 32 blocks) */
   int32_t relabel;  /* GrM_pagerank: 1 runs on a copy of the matrix with the
                        vertices renumbered by decreasing out-degree (built once
                        and cached with the matrix), so the most gathered values

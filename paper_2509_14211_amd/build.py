@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnbgrb.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "graph_build.hip", "runtime.hip", "abi.hip", "drivers.hip", "autotune.hip", "spmm.hip", "many.hip", "gnn.hip", "jit.hip", "webgen.hip", "sparse.hip", "noalloc.hip"]
+SOURCES = ["kernels.hip", "graph_build.hip", "runtime.hip", "abi.hip", "drivers.hip", "autotune.hip", "spmm.hip", "many.hip", "gnn.hip", "jit.hip", "webgen.hip", "sparse.hip", "noalloc.hip", "stripe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

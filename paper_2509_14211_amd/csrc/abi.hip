@@ -1033,9 +1033,11 @@ GrB_Info GrM_Vector_reduce_masked_Scalar(GrB_Scalar s, GrB_Vector mask, GrB_Mono
 
 // ------------------------------------------------------------ plans
 
-static bool plan_geometry_ok(const GrM_PlanConfig& c) {
-  if (c.kernel != K_BLOCK && c.kernel != K_WAVE) return false;
+static bool plan_geometry_ok(const GrM_PlanConfig& c, int type) {
+  if (c.kernel != K_BLOCK && c.kernel != K_WAVE && c.kernel != K_STRIPE) return false;
   if (c.hot < 0 || (c.relabel != 0 && c.relabel != 1) || (c.xcd_split != 0 && c.xcd_split != 1)) return false;
+  if (c.kernel == K_STRIPE)  // fixed geometry; FP32 ranks only
+    return type == T_FP32 && c.long_row >= 0 && c.grid >= 0 && c.grid <= (1 << 20);
   const bool lds_ok = c.kernel == K_WAVE
                           ? (c.lds_entries == WAVE_TILE_ENTRIES && c.lds_rows == WAVE_TILE_ROWS)
                           : ((c.lds_entries == 1024 && c.lds_rows == 512) ||
@@ -1055,7 +1057,7 @@ GrB_Info GrM_Matrix_plan_set(GrB_Matrix A, GrB_Type type, const GrM_PlanConfig* 
   if (!cfg) {
     ctx().tuned.erase(key);
   } else {
-    if (!plan_geometry_ok(*cfg)) fail(GrB_INVALID_VALUE, "unsupported tile plan geometry");
+    if (!plan_geometry_ok(*cfg, type->code)) fail(GrB_INVALID_VALUE, "unsupported tile plan geometry");
     PlanConfig pc;
     pc.kernel = cfg->kernel;
     pc.hot = cfg->hot;

@@ -114,6 +114,11 @@ GrB_Info GrM_autotune_pagerank(GrM_PlanConfig* chosen, double* us_per_pass, GrB_
       cands.push_back({1, 512, 256, 512, 512, 0, hmax, relabel, 0});
       cands.push_back({1, 512, 256, 512, 512, 0, hmax, relabel, 1});
       cands.push_back({1, 512, 256, 128, 512, 0, hmax, relabel, 0});
+      // stripe plans (FP32 ranks; the layout addresses < 2^30 columns and < 2^31 entries)
+      if (T == T_FP32 && A->ncols < ((int64_t)1 << 30) && A->nnz < ((int64_t)1 << 31)) {
+        cands.push_back({2, 0, 0, 512, 0, 0, 0, relabel, 0});
+        cands.push_back({2, 0, 0, 1024, 0, 0, 16 * STRIPE_HB, relabel, 0});
+      }
     }
     // Time k1 and k2 fused passes in one batch each (tol 0, no early stop);
     // the difference divided by k2 - k1 is the time of one pass.

@@ -84,8 +84,10 @@ __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, u
     return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, AUX));
   else if constexpr (sizeof(V) == 4)
     return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX));
-  else
+  else if constexpr (sizeof(V) == 8)
     return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, AUX));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, AUX));
 }
 
 template <typename V, int AUX = 0>

@@ -161,6 +161,54 @@ hipError_t launch_fused_wave_f64(const TilePlanDev& plan, const FusedArgs<double
                                  const GuardDev* guard, hipStream_t s);
 int wave_hot_max(int type);
 
+// Stripe-blocked fused pass (FP32 only).  Rows of the pattern are cut into
+// stripes of at most STRIPE_RMAX rows, one workgroup of STRIPE_BLOCK threads
+// per stripe at a time, row sums in LDS as 64-bit fixed point; columns into
+// blocks of STRIPE_HB values of the gathered vector, the leading `nb` blocks
+// of each stripe loaded into LDS in turn.
+//   hot words   : (row in stripe + 1) << 16 | column in the block, one
+//                 segment per (stripe, LDS block), sorted by row, padded to
+//                 a multiple of 8 with zero words;
+//   cold pairs  : column (uint32) and row in stripe + 1 (uint16) of the
+//                 stripe's other entries, sorted by row, padded the same way.
+// Row slot 0 takes the padding entries and is never read.
+constexpr int STRIPE_BLOCK = 1024;
+constexpr int STRIPE_RMAX = 8064;
+constexpr int STRIPE_HB = 12288;
+constexpr int STRIPE_NBMAX = 32;
+constexpr int STRIPE_K = 8;  // consecutive entries per lane
+
+struct StripeDesc {
+  int r0, nrows, nb, cold_n;    // rows [r0, r0 + nrows); LDS blocks; padded cold entries
+  long long hot_base, cold_base;  // first hot word / cold pair of the stripe
+  int seg[STRIPE_NBMAX + 1];    // hot segment of block b: [seg[b], seg[b+1]) after hot_base
+  int pad[7];
+};
+static_assert(sizeof(StripeDesc) == 192, "stripe descriptor layout");
+
+struct StripePlanDev {
+  const StripeDesc* desc;
+  const unsigned* hot;
+  const unsigned* cold_col;
+  const unsigned short* cold_row;
+  const int* wg_off;   // workgroup g runs wg_list[wg_off[g] .. wg_off[g+1])
+  const int* wg_list;
+  unsigned* wg_max;    // per-workgroup max |w'| (scratch)
+  int nstripes;
+  int maxlen;          // longest row
+};
+
+// The fused pass over a stripe plan.  wmax_in: IEEE bits of max|w| of the
+// gathered vector (sets the fixed-point scale; a non-finite value makes every
+// row sum NaN).  wmax_out (may be null): receives max|w'| of the pre-scaled
+// copy written.  grid must be the plan's workgroup count.
+hipError_t launch_fused_stripe_f32(const StripePlanDev& p, const FusedArgs<float>& a, const unsigned* wmax_in,
+                                   unsigned* wmax_out, const FusedScratch& scr, int grid, const GuardDev* guard,
+                                   hipStream_t s);
+// *out = IEEE bits of max |x[i]| (deterministic; NaN above every finite value).
+hipError_t launch_absmax_f32(const float* x, int64_t n, unsigned* out, RedScratch scr, const GuardDev* guard,
+                             hipStream_t s);
+
 // Elementwise: out[i] = f(a[i], b[i]) computed in `ct` (T_FP32 / T_FP64).
 //   kind 0: binary op(a, b); 1: unary op(a); 2: op(s, a); 3: op(a, s)
 enum EwKind : int { EW_BINARY = 0, EW_UNARY = 1, EW_BIND1ST = 2, EW_BIND2ND = 3 };

@@ -42,6 +42,21 @@ __device__ __forceinline__ void store_as(void* p, int type, int64_t i, T v) {
   }
 }
 
+// Called by thread 0 of the block that produced a guarded residual (and,
+// for the fused pass, the dangling mass of the same pass, 0 when none is
+// computed).  A residual or mass that is not finite ends the loop and marks
+// the guard bad, which the drivers report as an execution error: a NaN
+// compares false with the tolerance and would otherwise read as converged.
+__device__ __forceinline__ void guard_advance(GuardDev* g, double rho, double D = 0.0) {
+  g->rho_prev = g->rho;
+  g->rho = rho;
+  const int it = g->iters + 1;
+  g->iters = it;
+  const bool finite = __builtin_isfinite(rho) && __builtin_isfinite(D);
+  if (!finite) g->bad = 1;
+  g->active = (finite && rho > g->tol && it < g->itermax) ? 1 : 0;
+}
+
 // alpha * s + beta with one rounding (generated kernels use the same form).
 __device__ __forceinline__ double scalar_value(const ScalarArg& s) {
   return s.dev ? fma(s.alpha, *s.dev, s.beta) : s.beta;

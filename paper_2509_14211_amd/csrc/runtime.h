@@ -76,17 +76,19 @@ struct MatData {
 };
 
 // Kernel family of a plan.
-enum KernelKind : int { K_BLOCK = 0, K_WAVE = 1 };
+enum KernelKind : int { K_BLOCK = 0, K_WAVE = 1, K_STRIPE = 2 };
 
 // Tile plan of one matrix for the row-parallel kernels.
 struct PlanConfig {
   int kernel = K_BLOCK;    // block-tiled or wave-tiled pass
   int lds_entries = 2048;  // STREAM tile entry budget
   int lds_rows = 1024;     // STREAM tile row budget
-  int long_row = 2048;     // rows longer than this get a tile of their own
+  int long_row = 2048;     // rows longer than this get a tile of their own;
+                           // stripe kernel: fewest entries that make a stripe load a block
   int chunk = 2048;        // rows longer than this are split in chunks (<= lds_entries)
   int grid = 0;            // persistent workgroups (0: from the device)
-  int hot = 0;             // wave kernel: leading gathered entries kept in LDS
+  int hot = 0;             // wave kernel: leading gathered entries kept in LDS;
+                           // stripe kernel: leading columns in LDS blocks (0: all 32 blocks)
   int relabel = 0;         // drivers: run on the degree-renumbered copy
   int xcd = 0;             // tiles split into one contiguous range per XCD
 };
@@ -97,7 +99,16 @@ struct Plan {
   int nstream = 0, nlong = 0, nchunk = 0;
   BufP tiles, hubs, hub_sum, hub_cnt, hub_red;
   TilePlanDev dev{};
+  // stripe plan (K_STRIPE)
+  BufP st_desc, st_hot, st_ccol, st_crow, st_wgoff, st_wglist, st_wgmax, st_mass;
+  int st_nstripes = 0;
+  int64_t st_hot_entries = 0, st_cold_entries = 0;  // padded
+  StripePlanDev st_dev{};
 };
+
+// Builds the stripe layout of A into plan (plan.cfg set; rp = A's row
+// pointers on the host).
+void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp);
 
 std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg);
 PlanConfig default_plan_config(const MatP& A, int value_type);
@@ -172,6 +183,7 @@ struct Node {
   // Pre-scaled copy of this vector (value .* dvec or ./ dvec) produced as a
   // side output by the fused pass, keyed by operator and dvec node id.
   BufP memo;
+  BufP memo_max;  // max|memo| as IEEE bits, when the pass that wrote the memo computed it
   int memo_op = -1;
   uint64_t memo_dvec = 0;
 

@@ -280,22 +280,42 @@ std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
     cfg.grid = 0;
     cfg.hot = 0;
   }
+  if (cfg.kernel == K_STRIPE && (A->ncols >= ((int64_t)1 << 30) || A->nnz >= ((int64_t)1 << 31))) {
+    // beyond the stripe layout's 32-bit offsets: the wave plan
+    cfg.kernel = K_WAVE;
+    cfg.hot = wave_hot_max(T_FP32);
+    cfg.long_row = WAVE_TILE_ENTRIES;
+    cfg.chunk = WAVE_TILE_ENTRIES;
+    cfg.grid = 0;
+  }
   if (cfg.kernel == K_WAVE) {
     cfg.lds_entries = WAVE_TILE_ENTRIES;
     cfg.lds_rows = WAVE_TILE_ROWS;
   }
-  if (cfg.grid <= 0) cfg.grid = cfg.kernel == K_WAVE ? device_cus() : device_cus() * 8;
+  const bool stripe = cfg.kernel == K_STRIPE;
+  if (stripe) {
+    // geometry is fixed by the kernel; hot caps the LDS blocks, long_row is
+    // the fewest entries that make a stripe load a block
+    cfg.lds_entries = 0;
+    cfg.lds_rows = 0;
+    cfg.chunk = 0;
+    cfg.xcd = 0;
+    if (cfg.hot <= 0 || cfg.hot > STRIPE_NBMAX * STRIPE_HB) cfg.hot = STRIPE_NBMAX * STRIPE_HB;
+    cfg.hot = std::max(1, cfg.hot / STRIPE_HB) * STRIPE_HB;
+    if (cfg.long_row <= 0) cfg.long_row = 512;
+  }
+  if (cfg.grid <= 0) cfg.grid = (cfg.kernel == K_WAVE || stripe) ? device_cus() : device_cus() * 8;
   if (cfg.grid % 8 != 0) cfg.xcd = 0;
-  auto key = std::make_tuple(cfg.kernel, cfg.lds_entries, cfg.lds_rows, cfg.long_row, cfg.chunk,
-                             cfg.grid, cfg.xcd);
+  auto key = std::make_tuple(cfg.kernel, stripe ? cfg.hot : cfg.lds_entries, cfg.lds_rows, cfg.long_row,
+                             cfg.chunk, cfg.grid, cfg.xcd);
   auto it = A->plans.find(key);
   if (it != A->plans.end()) {
     g_ctx.stats.plan_hits++;
     return it->second;
   }
   g_ctx.stats.plan_misses++;
-  if (cfg.long_row < 1 || cfg.chunk < cfg.long_row || cfg.chunk > cfg.lds_entries ||
-      cfg.lds_rows < 1)
+  if (!stripe && (cfg.long_row < 1 || cfg.chunk < cfg.long_row || cfg.chunk > cfg.lds_entries ||
+                  cfg.lds_rows < 1))
     fail(GrB_INVALID_VALUE, "bad tile plan configuration");
   Ctx& c = g_ctx;
   const int64_t n = A->nrows;
@@ -307,6 +327,11 @@ std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
 
   auto plan = std::make_shared<Plan>();
   plan->cfg = cfg;
+  if (stripe) {
+    build_stripe_plan(A, *plan, rp);
+    A->plans[key] = plan;
+    return plan;
+  }
   std::vector<int4> tiles;
   std::vector<int4> hubs;
   int nparts = 0;
@@ -398,6 +423,10 @@ struct FusedSpec {
   ScalarArg c{nullptr, 0.0, 0.0};
   ReduceOut rho{nullptr, nullptr};
   ReduceOut D{nullptr, nullptr};
+  // stripe plans: max|w| of the gathered vector if known (IEEE bits), and
+  // where to put max|w_out|
+  const unsigned* wmax_in = nullptr;
+  unsigned* wmax_out = nullptr;
 };
 
 static hipEvent_t pooled_event() {
@@ -412,15 +441,27 @@ static hipEvent_t pooled_event() {
   return e;
 }
 
-static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_override = nullptr) {
+// Returns whether f.wmax_out was written.
+static bool run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_override = nullptr) {
   Ctx& c = g_ctx;
-  const PlanConfig cfg = cfg_override ? *cfg_override : default_plan_config(A, f.type);
+  PlanConfig cfg = cfg_override ? *cfg_override : default_plan_config(A, f.type);
+  if (cfg.kernel == K_STRIPE && f.type != T_FP32) {
+    // the stripe kernel's fixed-point sums serve FP32 ranks only
+    cfg.kernel = K_WAVE;
+    cfg.hot = wave_hot_max(f.type);
+    cfg.long_row = WAVE_TILE_ENTRIES;
+    cfg.chunk = WAVE_TILE_ENTRIES;
+    cfg.grid = 0;
+  }
   auto plan = get_plan(A, cfg);
-  // the hot slice is w[0, hot): never more than the gathered vector holds
-  int64_t hot = cfg.hot < 0 ? 0 : cfg.hot;
-  if (hot > A->ncols) hot = A->ncols;
-  if (hot > wave_hot_max(f.type)) hot = wave_hot_max(f.type);
-  plan->cfg.hot = (int)hot;
+  const bool stripe = plan->cfg.kernel == K_STRIPE;
+  if (!stripe) {
+    // the hot slice is w[0, hot): never more than the gathered vector holds
+    int64_t hot = cfg.hot < 0 ? 0 : cfg.hot;
+    if (hot > A->ncols) hot = A->ncols;
+    if (hot > wave_hot_max(f.type)) hot = wave_hot_max(f.type);
+    plan->cfg.hot = (int)hot;
+  }
   fused_scratch_ensure(plan->cfg.grid);
   FusedScratch scr{};
   scr.wg_part = (double*)c.fused_part->p;
@@ -436,6 +477,7 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     hip_check(hipEventRecord(e0, c.stream), "event record");
   }
   hipError_t e;
+  bool wrote_wmax = false;
   const bool wave = plan->cfg.kernel == K_WAVE;
   // no more workgroups than there is tile work: the block kernel takes tiles
   // per workgroup, the wave kernel per wavefront (16 per workgroup); a small
@@ -465,9 +507,24 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     a.c = f.c;
     a.rho_out = f.rho;
     a.D_out = f.D;
-    e = wave ? launch_fused_wave_f32(plan->dev, a, scr, grid, plan->cfg.hot, c.guard, c.stream)
-             : launch_fused_f32(plan->dev, a, scr, grid, plan->cfg.lds_entries,
-                                plan->cfg.lds_rows, c.guard, c.stream);
+    if (stripe) {
+      const unsigned* wmax_in = f.wmax_in;
+      unsigned* mass = (unsigned*)plan->st_mass->p;
+      if (!wmax_in) {
+        // no bound carried over from the pass that wrote w: measure it
+        hip_check(launch_absmax_f32(a.w, A->ncols, mass, reduce_scratch(), c.guard, c.stream), "max |w|");
+        launch_mark(false);
+        wmax_in = mass;
+        // the pass timer covers the fused kernel alone
+        if (timed) hip_check(hipEventRecord(e0, c.stream), "event record");
+      }
+      e = launch_fused_stripe_f32(plan->st_dev, a, wmax_in, f.wmax_out, scr, plan->cfg.grid, c.guard, c.stream);
+      wrote_wmax = f.wmax_out != nullptr && a.w_out != nullptr;
+    } else {
+      e = wave ? launch_fused_wave_f32(plan->dev, a, scr, grid, plan->cfg.hot, c.guard, c.stream)
+               : launch_fused_f32(plan->dev, a, scr, grid, plan->cfg.lds_entries,
+                                  plan->cfg.lds_rows, c.guard, c.stream);
+    }
   } else {
     FusedArgs<double> a{};
     a.rowptr = (const int*)A->rowptr->p;
@@ -501,6 +558,7 @@ static void run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     c.events.push_back({e0, e1});
   }
   launch_mark(f.mode == EPI_PR);
+  return wrote_wmax;
 }
 
 // Plain (blocking) mxv: s = A (+.*) w.
@@ -518,7 +576,7 @@ void mxv_now(const MatP& A, int type, const void* w, void* s_out) { run_mxv_plai
 // Public hook for the autotuner and tests: one fused pass with an explicit
 // plan configuration.
 void run_fused_with(const MatP& A, const FusedSpec& f, const PlanConfig& cfg) {
-  run_fused(A, f, &cfg);
+  (void)run_fused(A, f, &cfg);
 }
 
 // ------------------------------------------------------------ single nodes
@@ -956,6 +1014,7 @@ static void run_pr_group(PRMatch& m, const Consumers& cons) {
   }
   if (memo_hit) {
     f.w = X->memo->p;
+    if (X->memo_max) f.wmax_in = (const unsigned*)X->memo_max->p;
     W->done = true;  // elided: never written
     release_inputs(*W);
   } else {
@@ -964,11 +1023,13 @@ static void run_pr_group(PRMatch& m, const Consumers& cons) {
     f.w = W->buf->p;
   }
   // side output for the next pass: r .* dv (or ./ dv)
-  BufP memo;
+  BufP memo, memo_max;
   if (DV) {
     memo = dev_alloc(type_size(T) * (size_t)E->n);
+    memo_max = dev_alloc(sizeof(unsigned));
     f.dvec = DV->buf->p;
     f.w_out = memo->p;
+    f.wmax_out = (unsigned*)memo_max->p;
     f.memo_div = wop == B_DIV ? 1 : 0;
   }
   // E is stored when a handle or a node outside the group reads it
@@ -992,7 +1053,7 @@ static void run_pr_group(PRMatch& m, const Consumers& cons) {
       f.mask = operand_of(m.DR->mask);
     }
   }
-  run_fused(M->A, f);
+  const bool wrote_max = run_fused(M->A, f);
   // bookkeeping
   M->done = true;
   release_inputs(*M);
@@ -1001,6 +1062,7 @@ static void run_pr_group(PRMatch& m, const Consumers& cons) {
   E->iso = false;
   if (DV) {
     E->memo = memo;
+    E->memo_max = wrote_max ? memo_max : nullptr;
     E->memo_op = wop;
     E->memo_dvec = DV->id;
   }

@@ -1,0 +1,772 @@
+// Stripe-blocked fused PageRank pass (FP32 ranks), the plan kind for graphs
+// whose gathered vector is far larger than LDS.
+//
+// The pass computes the same thing as the other fused kernels (paper,
+// Fig. 6: the pre-scaled operand w gathered by the mxv over A^T, the
+// teleport/dangling add, the L1 residual and the dangling mass), but it
+// reorganises the mxv so that most gathers read LDS instead of memory:
+//
+//   * Rows of A^T are cut into stripes of at most STRIPE_RMAX rows.  A
+//     workgroup keeps the stripe's row sums in LDS.
+//   * Columns (sources) are cut into blocks of STRIPE_HB.  With vertices
+//     renumbered by decreasing out-degree the leading blocks hold the most
+//     gathered values (at R-MAT scale 22 the first 8 blocks draw 80% of all
+//     gathers).  For each of its leading blocks the stripe stores the
+//     entries that fall in it as packed words (row in the stripe << 16 |
+//     column in the block), sorted by row; the workgroup loads the block of
+//     w into LDS once and every such entry reads LDS.
+//   * The stripe's remaining entries (columns past its LDS blocks) are
+//     stored as (column, row in the stripe) pairs and gathered from memory
+//     while the next block loads.
+//   * Row sums are accumulated exactly in 64-bit fixed point with LDS
+//     integer atomics: w values are scaled by 2^F, where 2^(62-F) bounds
+//     (longest row) * max|w|, so no partial sum can overflow, and integer
+//     addition makes the sum independent of the order in which lanes and
+//     wavefronts add.  Each lane first adds runs of equal rows among its
+//     own entries in registers.  The row sum is then rounded once to FP32;
+//     its error is at most (row length) * 2^-F, far below FP32 rounding of
+//     the ranks it is added to.
+//   * Per row the epilogue is the usual one; it also publishes max|w'| of
+//     the pre-scaled copy it writes, which the next pass uses for its scale.
+//
+// The layout is built on the GPU once per matrix and plan: counts of each
+// stripe's entries per column block, a choice of how many leading blocks a
+// stripe loads (a block is loaded only when enough of the stripe's entries
+// fall in it to pay for reading it), a stable radix sort of the entries by
+// (stripe, block), and a scatter into the packed arrays.  Stripes are
+// assigned to workgroups by longest-processing-time-first on an estimate of
+// their cost, so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <queue>
+#include <rocprim/rocprim.hpp>
+#include <vector>
+
+#include "device_util.h"
+#include "ops_device.h"
+#include "runtime.h"
+
+namespace nbgrb {
+
+namespace {
+
+constexpr int NCLS = STRIPE_NBMAX + 1;  // column classes of a stripe: the LDS blocks, then the rest
+constexpr int CHUNK = 64 * STRIPE_K;    // entries one wavefront takes at a time
+
+template <typename V>
+__device__ __forceinline__ V wave_sum64(V v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename V, int B>
+__device__ __forceinline__ V block_sum_st(V v, V* red) {
+  v = wave_sum64(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  V r = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < B / 64; ++i) r += red[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ unsigned block_max_st(unsigned v, unsigned* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o, 64));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  unsigned r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < STRIPE_BLOCK / 64; ++i) r = max(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// v * 2^F as a two's-complement 64-bit integer, truncated toward zero, with
+// kshift = 188 - F.  v = mant * 2^(E - 150) (E the biased exponent, 1 for
+// subnormals), so v * 2^F = (mant << 38) >> (188 - F - E); the scale
+// guarantees a non-negative shift for every |v| <= max|w|.
+__device__ __forceinline__ long long fixed_of(float v, int kshift) {
+  const unsigned b = __float_as_uint(v);
+  const int E = (int)((b >> 23) & 0xFFu);
+  const unsigned mant = (b & 0x7FFFFFu) | (E ? 0x800000u : 0u);
+  int sh = kshift - (E ? E : 1);
+  sh = sh < 0 ? 0 : (sh > 63 ? 63 : sh);
+  const unsigned long long q = ((unsigned long long)mant << 38) >> sh;
+  return (b >> 31) ? -(long long)q : (long long)q;
+}
+
+// Adds a lane's entries (rows sorted ascending, padding rows 0 at the end)
+// into the LDS row sums: runs of equal rows are summed in registers first.
+// When the whole wavefront holds one row (a long row), one lane adds the
+// wavefront's total.
+template <int K>
+__device__ __forceinline__ void add_runs(unsigned long long* acc, const int (&row)[K], const float (&v)[K],
+                                         int kshift) {
+  const int first = lane_value(row[0], 0);
+  const int last = lane_value(row[K - 1], 63);
+  if (first == last) {
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) s += fixed_of(v[k], kshift);
+    s = wave_sum64(s);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&acc[first], (unsigned long long)s);
+    return;
+  }
+  int cur = row[0];
+  long long s = fixed_of(v[0], kshift);
+#pragma unroll
+  for (int k = 1; k < K; ++k) {
+    if (row[k] != cur) {
+      atomicAdd(&acc[cur], (unsigned long long)s);
+      cur = row[k];
+      s = 0;
+    }
+    s += fixed_of(v[k], kshift);
+  }
+  atomicAdd(&acc[cur], (unsigned long long)s);
+}
+
+// The workgroup's LDS block after block b of the stripe at list position
+// si: the next block of the same stripe, else block 0 of the next stripe in
+// the list that loads any (b = -1: the first block of stripe si or later).
+// Returns false when there is none.
+__device__ __forceinline__ bool next_block(const StripePlanDev& p, int si, int s_end, int b, int& nsi, int& nb_) {
+  if (si < s_end && b + 1 < wave_uniform(p.desc[wave_uniform(p.wg_list[si])].nb)) {
+    nsi = si;
+    nb_ = b + 1;
+    return true;
+  }
+  for (int k = si + 1; k < s_end; ++k) {
+    const int t = wave_uniform(p.wg_list[k]);
+    if (wave_uniform(p.desc[t].nb) > 0) {
+      nsi = k;
+      nb_ = 0;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Block b of the gathered vector into registers: piece t + j * nt of the
+// block's 16-byte pieces for j < HV, t = this thread's index among the nt
+// loading threads (the same thread stores them).
+template <int HV>
+__device__ __forceinline__ void load_block(const float* w, int ncols, int b, int t, int nt, int hv,
+                                           uint4 (&R)[HV]) {
+  const int b0 = b * STRIPE_HB;
+  const int cnt = min(STRIPE_HB, ncols - b0);
+  const __amdgpu_buffer_rsrc_t rb = buf_rsrc(w + b0, (unsigned)(cnt > 0 ? cnt : 0) * 4u);
+#pragma unroll
+  for (int j = 0; j < HV; ++j)
+    if (j < hv) R[j] = buf_load<uint4>(rb, (unsigned)(t + j * nt) * 16u);
+}
+
+template <int HV>
+__device__ __forceinline__ void store_block(float* buf, int t, int nt, int hv, const uint4 (&R)[HV]) {
+#pragma unroll
+  for (int j = 0; j < HV; ++j)
+    if (j < hv) ((uint4*)buf)[t + j * nt] = R[j];
+}
+
+// Hot item (phase b, chunk j) of a hot wavefront within a stripe: chunks
+// h, h + nh, ... of each LDS block's segment in turn (h = its index among
+// the nh hot wavefronts).  Segment starts come from a register holding
+// seg[lane] in lane `lane`, read with v_readlane: a scalar memory load here
+// would wait for the wavefront's LDS operations too (one counter tracks
+// both).
+struct HotCursor {
+  int b, j;
+};
+
+__device__ __forceinline__ int seg_at(int segv, int b) { return __builtin_amdgcn_readlane(segv, b); }
+
+__device__ __forceinline__ void hot_settle(int segv, int nb, int h, HotCursor& c) {
+  while (c.b < nb && c.j * CHUNK >= seg_at(segv, c.b + 1) - seg_at(segv, c.b)) {
+    ++c.b;
+    c.j = h;
+  }
+}
+
+__device__ __forceinline__ void hot_words(const unsigned* hot_seg0, int segv, const HotCursor& c, int lane,
+                                          uint4& wa, uint4& wb) {
+  const int sb0 = seg_at(segv, c.b), sb1 = seg_at(segv, c.b + 1);
+  const __amdgpu_buffer_rsrc_t rh = buf_rsrc(hot_seg0 + sb0, (unsigned)(sb1 - sb0) * 4u);
+  const unsigned e = (unsigned)(c.j * CHUNK + lane * STRIPE_K);
+  wa = buf_load<uint4>(rh, e * 4u);
+  wb = buf_load<uint4>(rh, e * 4u + 16u);
+}
+
+// Registers of one chunk of gathered entries: column indices, rows in the
+// stripe (16 bits each) and the gathered values.
+struct ColdRegs {
+  uint4 ca, cb, rr;
+  float v[STRIPE_K];
+};
+
+// Indices of chunk `ch` (past the end the loads return zeros: column 0,
+// row slot 0).
+__device__ __forceinline__ void cold_indices(__amdgpu_buffer_rsrc_t rcc, __amdgpu_buffer_rsrc_t rcr, int ch,
+                                             int lane, ColdRegs& R) {
+  const unsigned e = (unsigned)(ch * CHUNK + lane * STRIPE_K);
+  R.ca = buf_load<uint4>(rcc, e * 4u);
+  R.cb = buf_load<uint4>(rcc, e * 4u + 16u);
+  R.rr = buf_load<uint4>(rcr, e * 2u);
+}
+
+__device__ __forceinline__ void cold_gather(__amdgpu_buffer_rsrc_t rw, ColdRegs& R) {
+  const unsigned col[STRIPE_K] = {R.ca.x, R.ca.y, R.ca.z, R.ca.w, R.cb.x, R.cb.y, R.cb.z, R.cb.w};
+#pragma unroll
+  for (int k = 0; k < STRIPE_K; ++k) R.v[k] = buf_load<float>(rw, col[k] * 4u);
+}
+
+__device__ __forceinline__ void cold_add(unsigned long long* acc, const ColdRegs& R, int kshift) {
+  const int row[STRIPE_K] = {(int)(R.rr.x & 0xFFFFu), (int)(R.rr.x >> 16), (int)(R.rr.y & 0xFFFFu),
+                             (int)(R.rr.y >> 16),     (int)(R.rr.z & 0xFFFFu), (int)(R.rr.z >> 16),
+                             (int)(R.rr.w & 0xFFFFu), (int)(R.rr.w >> 16)};
+  add_runs<STRIPE_K>(acc, row, R.v, kshift);
+}
+
+}  // namespace
+
+// One workgroup per compute unit; workgroup g runs stripes
+// wg_list[wg_off[g] .. wg_off[g+1]) one after the other.  Per stripe, all
+// wavefronts first gather the entries outside the LDS blocks (software-
+// pipelined), then add the entries of each LDS block in turn.  The LDS
+// blocks of all the workgroup's stripes form one sequence: block k sits in
+// buffer k mod 2 while block k+2 is in flight into registers; block k+1,
+// loaded during the previous phase, goes into the other buffer at the end
+// of the phase (one workgroup barrier per block).
+__global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDev p, FusedArgs<float> a,
+                                                                    const unsigned* wmax_in, unsigned* wmax_out,
+                                                                    FusedScratch scr, const GuardDev* guard) {
+  constexpr int B = STRIPE_BLOCK;
+  constexpr int NW = B / 64;
+  constexpr int HV = STRIPE_HB / (4 * B);        // 16-byte pieces of a block per thread
+  constexpr int ER = (STRIPE_RMAX + B - 1) / B;  // epilogue rows per thread
+  static_assert(STRIPE_HB % (4 * B) == 0, "blocks are loaded in whole 16-byte pieces per thread");
+  if (guard && guard->active == 0) return;
+
+  __shared__ unsigned long long acc[STRIPE_RMAX + 1];  // slot 0 takes the padding entries
+  __shared__ __attribute__((aligned(16))) float hot[2][STRIPE_HB];
+  __shared__ double sred[NW];
+  __shared__ unsigned smax[NW];
+  __shared__ int sflag;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = wave_uniform(tid >> 6);
+  const bool pr = a.mode == EPI_PR;
+  float c = 0.0f;
+  if (pr) c = (float)scalar_value(a.c);
+
+  // fixed-point scale: 2^(62-F) >= maxlen * max|w|
+  const float wmax = __uint_as_float(*wmax_in & 0x7FFFFFFFu);
+  const bool finite = __builtin_isfinite(wmax);
+  const double bound = (double)p.maxlen * (double)wmax;
+  int F = 62;
+  if (finite && bound > 0.0) {
+    int k = 0;
+    (void)frexp(bound, &k);  // bound < 2^k
+    F = 62 - k;
+  }
+  const int kshift = 188 - F;
+  const double unscale = ldexp(1.0, -F);
+
+  const __amdgpu_buffer_rsrc_t rw = buf_rsrc(a.w, (unsigned)a.ncols * 4u);
+  double rho = 0.0, dm = 0.0;
+  unsigned wmx = 0u;
+
+  const int g = blockIdx.x;
+  const int s_begin = p.wg_off[g], s_end = p.wg_off[g + 1];
+
+  for (int i = tid; i <= STRIPE_RMAX; i += B) acc[i] = 0ull;
+  // LDS block sequence: (bsi, bb) is the block after the one in flight
+  int kblk = 0;  // blocks consumed so far: the next one sits in hot[kblk & 1]
+  int bsi = s_begin, bb = -1;
+  bool have1 = false;  // block kblk + 1 is in registers R1 / R2 (by parity)
+  uint4 R1[HV], R2[HV];
+  {
+    if (s_begin < s_end && next_block(p, bsi, s_end, bb, bsi, bb)) {
+      uint4 R[HV];
+      load_block<HV>(a.w, a.ncols, bb, tid, B, HV, R);
+      store_block<HV>(hot[0], tid, B, HV, R);
+      if (next_block(p, bsi, s_end, bb, bsi, bb)) {
+        load_block<HV>(a.w, a.ncols, bb, tid, B, HV, R1);
+        have1 = true;
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int si = s_begin; si < s_end; ++si) {
+    const int s = wave_uniform(p.wg_list[si]);
+    const StripeDesc* dp = p.desc + s;
+    const int r0 = wave_uniform(dp->r0), nrows = wave_uniform(dp->nrows);
+    const int nb = wave_uniform(dp->nb), cold_n = wave_uniform(dp->cold_n);
+    const long long hot_base = dp->hot_base, cold_base = dp->cold_base;
+    const int ncold = (cold_n + CHUNK - 1) / CHUNK;
+    const __amdgpu_buffer_rsrc_t rcc = buf_rsrc(p.cold_col + cold_base, (unsigned)cold_n * 4u);
+    const __amdgpu_buffer_rsrc_t rcr = buf_rsrc(p.cold_row + cold_base, (unsigned)cold_n * 2u);
+    const int segv = lane <= nb ? dp->seg[lane] : 0;
+    const unsigned* hot_seg0 = p.hot + hot_base;
+
+    // Entries outside the LDS blocks, gathered from memory first: this
+    // wavefront's chunks wv, wv + 16, ...  Three register sets rotate so the
+    // indices of chunk i+2 and the gathers of chunk i+1 are in flight while
+    // chunk i is added (unrolled by three: no set is ever copied, which
+    // would wait for its loads).
+    {
+      const int nk = ncold > wv ? (ncold - wv + NW - 1) / NW : 0;
+      if (nk > 0) {
+        ColdRegs X, Y, Z;
+        cold_indices(rcc, rcr, wv, lane, X);
+        cold_indices(rcc, rcr, wv + NW, lane, Y);
+        cold_gather(rw, X);
+        auto step = [&](int i, ColdRegs& P, ColdRegs& G, ColdRegs& F) {
+          cold_indices(rcc, rcr, wv + (i + 2) * NW, lane, F);
+          cold_gather(rw, G);
+          cold_add(acc, P, kshift);
+        };
+        for (int i = 0;;) {
+          step(i, X, Y, Z);
+          if (++i >= nk) break;
+          step(i, Y, Z, X);
+          if (++i >= nk) break;
+          step(i, Z, X, Y);
+          if (++i >= nk) break;
+        }
+      }
+    }
+
+    // entries in the LDS blocks, one block per phase
+    HotCursor cur{0, wv};
+    hot_settle(segv, nb, wv, cur);
+    uint4 wa = make_uint4(0, 0, 0, 0), wb = make_uint4(0, 0, 0, 0);
+    if (cur.b < nb) hot_words(hot_seg0, segv, cur, lane, wa, wb);
+    for (int b = 0; b < nb; ++b) {
+      // block kblk + 2 of the sequence into the free register set
+      const bool more2 = have1 && next_block(p, bsi, s_end, bb, bsi, bb);
+      if (more2) {
+        if (kblk & 1)
+          load_block<HV>(a.w, a.ncols, bb, tid, B, HV, R1);
+        else
+          load_block<HV>(a.w, a.ncols, bb, tid, B, HV, R2);
+      }
+      const float* hbuf = hot[kblk & 1];
+      while (cur.b == b) {
+        const uint4 ca = wa, cb = wb;
+        HotCursor nx{cur.b, cur.j + NW};
+        hot_settle(segv, nb, wv, nx);
+        if (nx.b < nb) hot_words(hot_seg0, segv, nx, lane, wa, wb);
+        const unsigned wd[STRIPE_K] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+        int row[STRIPE_K];
+        float v[STRIPE_K];
+#pragma unroll
+        for (int k = 0; k < STRIPE_K; ++k) {
+          row[k] = (int)(wd[k] >> 16);
+          v[k] = hbuf[wd[k] & 0xFFFFu];
+        }
+        add_runs<STRIPE_K>(acc, row, v, kshift);
+        cur = nx;
+      }
+      // block kblk + 1 (loaded during the previous phase) into the other
+      // buffer, last read in the previous phase before its barrier
+      if (have1) {
+        if (kblk & 1)
+          store_block<HV>(hot[0], tid, B, HV, R2);
+        else
+          store_block<HV>(hot[1], tid, B, HV, R1);
+      }
+      have1 = more2;
+      __syncthreads();
+      ++kblk;
+    }
+    if (nb == 0) __syncthreads();  // every gathered entry added
+
+    // epilogue: rows of the stripe (all loads issued first); each slot is
+    // cleared for the next stripe
+    float xo[ER], dv[ER];
+#pragma unroll
+    for (int k = 0; k < ER; ++k) {
+      const int r = tid + k * B;
+      xo[k] = (r < nrows && pr && a.x_old) ? __builtin_nontemporal_load(a.x_old + r0 + r) : 0.0f;
+      dv[k] = (r < nrows && pr && a.dvec) ? __builtin_nontemporal_load(a.dvec + r0 + r) : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < ER; ++k) {
+      const int r = tid + k * B;
+      if (r >= nrows) continue;
+      const int i = r0 + r;
+      const long long q = (long long)acc[r + 1];
+      acc[r + 1] = 0ull;
+      const float sv = finite ? (float)((double)q * unscale) : __builtin_nanf("");
+      if (!pr) {
+        a.s_out[i] = sv;
+        continue;
+      }
+      const float tele = a.tele_vec ? (a.tele_scaled ? a.tele_vec[i] * c : a.tele_vec[i]) : c;
+      const float rv = tele + sv;
+      if (a.r_out) __builtin_nontemporal_store(rv, a.r_out + i);
+      if (a.x_old) rho += fabs((double)xo[k] - (double)rv);
+      if (a.w_out) {
+        const float wn = a.memo_div ? rv / dv[k] : rv * dv[k];
+        a.w_out[i] = wn;
+        wmx = max(wmx, __float_as_uint(wn) & 0x7FFFFFFFu);
+      }
+      if (a.do_D) {
+        const bool m = a.mask_is_dvec ? (dv[k] != 0.0f) : nonzero_at(a.mask, i);
+        if (m != (a.mask_comp != 0)) dm += (double)rv;
+      }
+    }
+    if (tid == 0) acc[0] = 0ull;
+    __syncthreads();  // slots are clear before the next stripe adds into them
+  }
+
+  const bool reduce = (pr && (a.rho_out.out || a.D_out.out || a.rho_out.guard)) || wmax_out;
+  if (!reduce) return;
+  const double br = block_sum_st<double, B>(rho, sred);
+  const double bd = block_sum_st<double, B>(dm, sred);
+  const unsigned bm = block_max_st(wmx, smax);
+  if (tid == 0) {
+    publish(&scr.wg_part[2 * g], br);
+    publish(&scr.wg_part[2 * g + 1], bd);
+    publish(&p.wg_max[g], bm);
+    wait_stores();
+    sflag = ticket_add(scr.ticket) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!sflag) return;
+  double pr_ = 0.0, pd = 0.0;
+  unsigned pm = 0u;
+  for (int k = tid; k < (int)gridDim.x; k += B) {
+    pr_ += consume(&scr.wg_part[2 * k]);
+    pd += consume(&scr.wg_part[2 * k + 1]);
+    pm = max(pm, consume(&p.wg_max[k]));
+  }
+  const double tr = block_sum_st<double, B>(pr_, sred);
+  const double tdm = block_sum_st<double, B>(pd, sred);
+  const unsigned tm = block_max_st(pm, smax);
+  if (tid == 0) {
+    if (pr) {
+      if (a.rho_out.out) *a.rho_out.out = tr;
+      if (a.D_out.out) *a.D_out.out = tdm;
+      if (a.rho_out.guard) guard_advance(a.rho_out.guard, tr, a.do_D ? tdm : 0.0);
+    }
+    if (wmax_out) *wmax_out = tm;
+    publish(scr.ticket, 0u);
+  }
+}
+
+hipError_t launch_fused_stripe_f32(const StripePlanDev& p, const FusedArgs<float>& a, const unsigned* wmax_in,
+                                   unsigned* wmax_out, const FusedScratch& scr, int grid, const GuardDev* guard,
+                                   hipStream_t s) {
+  if (grid <= 0 || !wmax_in) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fused_stripe_kernel, dim3(grid), dim3(STRIPE_BLOCK), 0, s, p, a, wmax_in, wmax_out, scr,
+                     guard);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ max |x|
+
+// Deterministic two-level max of |x| (as IEEE bits; NaN above every finite
+// value) into *out.
+__global__ __launch_bounds__(256) void absmax_kernel(const float* x, int64_t n, unsigned* out, RedScratch scr,
+                                                      const GuardDev* guard) {
+  if (guard && guard->active == 0) return;
+  __shared__ unsigned red[4];
+  __shared__ int sflag;
+  unsigned m = 0u;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+    m = max(m, __float_as_uint(x[i]) & 0x7FFFFFFFu);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = max(max(red[0], red[1]), max(red[2], red[3]));
+    publish(&scr.partials[blockIdx.x], (double)m);
+    wait_stores();
+    sflag = ticket_add(scr.ticket) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!sflag || threadIdx.x != 0) return;
+  unsigned t = 0u;
+  for (int k = 0; k < (int)gridDim.x; ++k) t = max(t, (unsigned)consume(&scr.partials[k]));
+  *out = t;
+  publish(scr.ticket, 0u);
+}
+
+hipError_t launch_absmax_f32(const float* x, int64_t n, unsigned* out, RedScratch scr, const GuardDev* guard,
+                             hipStream_t s) {
+  int64_t g = (n + 256 * 8 - 1) / (256 * 8);
+  if (g < 1) g = 1;
+  if (g > REDUCE_GRID) g = REDUCE_GRID;
+  hipLaunchKernelGGL(absmax_kernel, dim3((int)g), dim3(256), 0, s, x, n, out, scr, guard);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ layout build
+
+namespace {
+
+// cnt[s][cls] = entries of stripe s whose column falls in block cls
+// (classes past STRIPE_NBMAX - 1 are merged into the last one).  One
+// workgroup per stripe.
+__global__ __launch_bounds__(256) void st_count_kernel(const int* rowptr, const int* col, const int* sr0,
+                                                        int* cnt) {
+  __shared__ int h[NCLS];
+  const int s = blockIdx.x;
+  if (threadIdx.x < NCLS) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int e0 = rowptr[sr0[s]], e1 = rowptr[sr0[s + 1]];
+  for (int e = e0 + threadIdx.x; e < e1; e += 256) atomicAdd(&h[min(col[e] / STRIPE_HB, STRIPE_NBMAX)], 1);
+  __syncthreads();
+  if (threadIdx.x < NCLS) cnt[s * NCLS + threadIdx.x] = h[threadIdx.x];
+}
+
+// key = (segment << 32) | entry, segment = s * NCLS + min(block, nb[s]).
+__global__ __launch_bounds__(256) void st_key_kernel(const int* rowptr, const int* col, const int* sr0,
+                                                      const int* nbs, uint64_t* keys) {
+  const int s = blockIdx.x;
+  const int e0 = rowptr[sr0[s]], e1 = rowptr[sr0[s + 1]];
+  const int nb = nbs[s];
+  for (int e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int cls = min(col[e] / STRIPE_HB, nb);
+    keys[e] = ((uint64_t)(unsigned)(s * NCLS + cls) << 32) | (uint64_t)(unsigned)e;
+  }
+}
+
+// Sorted position q holds entry e of segment seg: its row is found by a
+// binary search over the stripe's rows; it goes to position
+// obase[seg] + (q - ustart[seg]) of the packed hot words or cold pairs.
+__global__ __launch_bounds__(256) void st_scatter_kernel(const uint64_t* keys, int64_t m, const int* rowptr,
+                                                          const int* col, const int* sr0, const int* nbs,
+                                                          const int64_t* ustart, const int64_t* obase,
+                                                          unsigned* hot, unsigned* ccol, unsigned short* crow) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < m; q += stride) {
+    const uint64_t k = keys[q];
+    const int seg = (int)(k >> 32);
+    const int e = (int)(unsigned)(k & 0xFFFFFFFFull);
+    const int s = seg / NCLS, cls = seg % NCLS;
+    int lo = sr0[s], hi = sr0[s + 1];  // row r with rowptr[r] <= e < rowptr[r+1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (rowptr[mid] <= e) lo = mid; else hi = mid;
+    }
+    const unsigned rl = (unsigned)(lo - sr0[s] + 1);
+    const int64_t dst = obase[seg] + (q - ustart[seg]);
+    const int cc = col[e];
+    if (cls < nbs[s]) {
+      hot[dst] = (rl << 16) | (unsigned)(cc - cls * STRIPE_HB);
+    } else {
+      ccol[dst] = (unsigned)cc;
+      crow[dst] = (unsigned short)rl;
+    }
+  }
+}
+
+int64_t pad8(int64_t x) { return (x + 7) & ~(int64_t)7; }
+
+}  // namespace
+
+void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
+  Ctx& c = ctx();
+  const PlanConfig& cfg = plan.cfg;
+  const int64_t n = A->nrows, m = A->nnz;
+  if (A->ncols >= (int64_t)1 << 30) fail(GrB_INVALID_VALUE, "the stripe plan addresses at most 2^30 columns");
+  if (m >= (int64_t)1 << 31) fail(GrB_INVALID_VALUE, "the stripe plan holds fewer than 2^31 entries");
+  const int G = cfg.grid;
+  int maxlen = 0;
+  for (int64_t i = 0; i < n; ++i) maxlen = std::max(maxlen, rp[i + 1] - rp[i]);
+
+  // stripes: at most STRIPE_RMAX rows, about m / (2G) entries
+  const int64_t emax = std::max<int64_t>(4096, (m + 2 * (int64_t)G - 1) / (2 * (int64_t)G));
+  std::vector<int> sr0{0};
+  {
+    int64_t r0 = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t ecur = rp[i] - rp[r0];
+      if (i - r0 >= STRIPE_RMAX || (ecur > 0 && ecur + (rp[i + 1] - rp[i]) > emax)) {
+        sr0.push_back((int)i);
+        r0 = i;
+      }
+    }
+    if (sr0.back() != (int)n || n == 0) sr0.push_back((int)n);
+  }
+  const int S = (int)sr0.size() - 1;
+
+  BufP d_sr0 = dev_alloc(sizeof(int) * (size_t)(S + 1));
+  hip_check(hipMemcpyAsync(d_sr0->p, sr0.data(), sizeof(int) * (S + 1), hipMemcpyHostToDevice, c.stream), "upload");
+  BufP d_cnt = dev_alloc(sizeof(int) * (size_t)S * NCLS);
+  const int* rowptr = (const int*)A->rowptr->p;
+  const int* col = A->col ? (const int*)A->col->p : nullptr;
+  if (S > 0 && m > 0) {
+    hipLaunchKernelGGL(st_count_kernel, dim3(S), dim3(256), 0, c.stream, rowptr, col, (const int*)d_sr0->p,
+                       (int*)d_cnt->p);
+    hip_check(hipGetLastError(), "stripe count");
+  } else if (S > 0) {
+    hip_check(launch_zero(d_cnt->p, sizeof(int) * (size_t)S * NCLS, c.stream), "zero counts");
+  }
+  std::vector<int> cnt((size_t)S * NCLS);
+  if (S > 0)
+    hip_check(hipMemcpyAsync(cnt.data(), d_cnt->p, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost, c.stream),
+              "download counts");
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+
+  // LDS blocks of each stripe: leading blocks with enough entries
+  const int nb_cap = std::min<int64_t>(STRIPE_NBMAX, cfg.hot > 0 ? std::max(1, cfg.hot / STRIPE_HB) : STRIPE_NBMAX);
+  const int ncolblk = (int)((A->ncols + STRIPE_HB - 1) / STRIPE_HB);
+  const int min_entries = cfg.long_row > 0 ? cfg.long_row : 512;
+  std::vector<int> nbs(S);
+  std::vector<StripeDesc> desc(S);
+  std::vector<int64_t> ustart((size_t)S * NCLS, 0), obase((size_t)S * NCLS, 0);
+  std::vector<double> cost(S);
+  int64_t hot_total = 0, cold_total = 0, sorted = 0;
+  for (int s = 0; s < S; ++s) {
+    const int* cs = &cnt[(size_t)s * NCLS];
+    int nb = 0;
+    while (nb < nb_cap && nb < ncolblk && nb < STRIPE_NBMAX && cs[nb] >= min_entries) ++nb;
+    nbs[s] = nb;
+    StripeDesc& d = desc[s];
+    std::memset(&d, 0, sizeof(d));
+    d.r0 = sr0[s];
+    d.nrows = sr0[s + 1] - sr0[s];
+    d.nb = nb;
+    d.hot_base = hot_total;
+    int64_t off = 0, hot_e = 0;
+    for (int b = 0; b < nb; ++b) {
+      d.seg[b] = (int)off;
+      ustart[(size_t)s * NCLS + b] = sorted;
+      obase[(size_t)s * NCLS + b] = hot_total + off;
+      sorted += cs[b];
+      off += pad8(cs[b]);
+      hot_e += cs[b];
+    }
+    d.seg[nb] = (int)off;
+    hot_total += off;
+    int64_t cold = 0;
+    for (int b = nb; b < NCLS; ++b) cold += cs[b];
+    ustart[(size_t)s * NCLS + nb] = sorted;
+    obase[(size_t)s * NCLS + nb] = cold_total;
+    sorted += cold;
+    d.cold_base = cold_total;
+    d.cold_n = (int)pad8(cold);
+    cold_total += pad8(cold);
+    // estimated cycles of one compute unit: entries added from LDS (about 2
+    // per cycle, plus a block load and barrier per LDS block), entries
+    // gathered from memory (about 0.3 per cycle), rows of the epilogue
+    cost[s] = (double)hot_e / 2.0 + nb * 700.0 + (double)cold / 0.3 + d.nrows / 4.0 + 2000.0;
+  }
+  if (sorted != m) fail(GrB_PANIC, "stripe plan: entry counts do not add up");
+  if (hot_total >= ((int64_t)1 << 32) || cold_total >= ((int64_t)1 << 32))
+    fail(GrB_INVALID_VALUE, "stripe plan too large");
+
+  // packed arrays (padding entries are zero: they add w[0] to the dump slot)
+  plan.st_hot = dev_alloc(sizeof(unsigned) * (size_t)std::max<int64_t>(hot_total, 8));
+  plan.st_ccol = dev_alloc(sizeof(unsigned) * (size_t)std::max<int64_t>(cold_total, 8));
+  plan.st_crow = dev_alloc(sizeof(unsigned short) * (size_t)std::max<int64_t>(cold_total, 8));
+  hip_check(launch_zero(plan.st_hot->p, plan.st_hot->bytes, c.stream), "zero");
+  hip_check(launch_zero(plan.st_ccol->p, plan.st_ccol->bytes, c.stream), "zero");
+  hip_check(launch_zero(plan.st_crow->p, plan.st_crow->bytes, c.stream), "zero");
+  if (m > 0) {
+    BufP d_nb = dev_alloc(sizeof(int) * (size_t)S);
+    BufP d_us = dev_alloc(sizeof(int64_t) * ustart.size());
+    BufP d_ob = dev_alloc(sizeof(int64_t) * obase.size());
+    hip_check(hipMemcpyAsync(d_nb->p, nbs.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.stream), "upload");
+    hip_check(hipMemcpyAsync(d_us->p, ustart.data(), sizeof(int64_t) * ustart.size(), hipMemcpyHostToDevice,
+                             c.stream),
+              "upload");
+    hip_check(hipMemcpyAsync(d_ob->p, obase.data(), sizeof(int64_t) * obase.size(), hipMemcpyHostToDevice,
+                             c.stream),
+              "upload");
+    BufP k0 = dev_alloc(sizeof(uint64_t) * (size_t)m), k1 = dev_alloc(sizeof(uint64_t) * (size_t)m);
+    hipLaunchKernelGGL(st_key_kernel, dim3(S), dim3(256), 0, c.stream, rowptr, col, (const int*)d_sr0->p,
+                       (const int*)d_nb->p, (uint64_t*)k0->p);
+    hip_check(hipGetLastError(), "stripe keys");
+    unsigned end_bit = 32;
+    while (end_bit < 64 && ((uint64_t)S * NCLS) > ((uint64_t)1 << (end_bit - 32))) ++end_bit;
+    size_t tb = 0;
+    hip_check(rocprim::radix_sort_keys(nullptr, tb, (uint64_t*)k0->p, (uint64_t*)k1->p, (size_t)m, 0u, end_bit,
+                                       c.stream),
+              "sort size");
+    BufP tmp = dev_alloc(tb + 256);
+    hip_check(rocprim::radix_sort_keys(tmp->p, tb, (uint64_t*)k0->p, (uint64_t*)k1->p, (size_t)m, 0u, end_bit,
+                                       c.stream),
+              "sort");
+    const int grid = (int)std::min<int64_t>((m + 255) / 256, 8192);
+    hipLaunchKernelGGL(st_scatter_kernel, dim3(grid), dim3(256), 0, c.stream, (const uint64_t*)k1->p, m, rowptr,
+                       col, (const int*)d_sr0->p, (const int*)d_nb->p, (const int64_t*)d_us->p,
+                       (const int64_t*)d_ob->p, (unsigned*)plan.st_hot->p, (unsigned*)plan.st_ccol->p,
+                       (unsigned short*)plan.st_crow->p);
+    hip_check(hipGetLastError(), "stripe scatter");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+  }
+
+  // stripes to workgroups: longest estimated cost first onto the least loaded
+  std::vector<int> ord(S);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<std::vector<int>> per(G);
+  using Slot = std::pair<double, int>;
+  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> q;
+  for (int k = 0; k < G; ++k) q.push({0.0, k});
+  for (int s : ord) {
+    Slot t = q.top();
+    q.pop();
+    per[t.second].push_back(s);
+    q.push({t.first + cost[s], t.second});
+  }
+  std::vector<int> wg_off(G + 1, 0), wg_list;
+  wg_list.reserve(S);
+  for (int k = 0; k < G; ++k) {
+    std::sort(per[k].begin(), per[k].end());
+    wg_off[k] = (int)wg_list.size();
+    wg_list.insert(wg_list.end(), per[k].begin(), per[k].end());
+  }
+  wg_off[G] = (int)wg_list.size();
+
+  plan.st_desc = dev_alloc(sizeof(StripeDesc) * (size_t)std::max(S, 1));
+  plan.st_wgoff = dev_alloc(sizeof(int) * (size_t)(G + 1));
+  plan.st_wglist = dev_alloc(sizeof(int) * (size_t)std::max(S, 1));
+  plan.st_wgmax = dev_alloc(sizeof(unsigned) * (size_t)G);
+  plan.st_mass = dev_alloc(sizeof(unsigned) * 2);
+  if (S > 0) {
+    hip_check(hipMemcpyAsync(plan.st_desc->p, desc.data(), sizeof(StripeDesc) * S, hipMemcpyHostToDevice, c.stream),
+              "upload");
+    hip_check(hipMemcpyAsync(plan.st_wglist->p, wg_list.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.stream),
+              "upload");
+  }
+  hip_check(hipMemcpyAsync(plan.st_wgoff->p, wg_off.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice, c.stream),
+            "upload");
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+
+  plan.st_nstripes = S;
+  plan.st_hot_entries = hot_total;
+  plan.st_cold_entries = cold_total;
+  StripePlanDev& d = plan.st_dev;
+  d.desc = (const StripeDesc*)plan.st_desc->p;
+  d.hot = (const unsigned*)plan.st_hot->p;
+  d.cold_col = (const unsigned*)plan.st_ccol->p;
+  d.cold_row = (const unsigned short*)plan.st_crow->p;
+  d.wg_off = (const int*)plan.st_wgoff->p;
+  d.wg_list = (const int*)plan.st_wglist->p;
+  d.wg_max = (unsigned*)plan.st_wgmax->p;
+  d.nstripes = S;
+  d.maxlen = maxlen;
+}
+
+}  // namespace nbgrb

@@ -1,8 +1,10 @@
 """Generated fusion of elementwise trees (nonblocking mode): random trees of
 eWiseAdd / eWiseMult / apply (bound constants and bound device scalars)
-over FP32, FP64 and INT32 vectors give bit-for-bit the results of the
-per-operation kernels (blocking mode), run as one kernel, and reuse the
-compiled code from memory and from the code cache directory."""
+over FP32, FP64 and INT32 vectors give bit for bit the values the oracle's
+one-operation-at-a-time evaluation gives (each operation rounded in its own
+type, oracle/ewise.py), and the results of the per-operation kernels
+(blocking mode); they run as one kernel, and reuse the compiled code from
+memory and from the code cache directory."""
 import os
 
 import numpy as np
@@ -37,23 +39,27 @@ class Builder:
         return self.grb.GrB_Vector_new(self.grb.builtin("GrB_" + t), n)
 
     def leaf(self, t):
-        hs = [h for h, lt in self.leaves if lt == t]
-        return hs[self.rng.integers(len(hs))]
+        ks = [k for k, (_, lt) in enumerate(self.leaves) if lt == t]
+        k = ks[self.rng.integers(len(ks))]
+        return self.leaves[k][0], ("leaf", k)
 
     def build(self, depth, n, t):
-        """Returns (handle, owned) of a random expression of type t (binary
-        operations and binds take operands of their own type; a unary apply
-        may convert from FP32, FP64 or INT32)."""
+        """Returns (handle, owned, expression) of a random expression of type
+        t (binary operations and binds take operands of their own type; a
+        unary apply may convert from FP32, FP64 or INT32); the expression is
+        the tree in oracle/ewise.py's notation."""
         g, rng = self.grb, self.rng
         if depth == 0 or rng.random() < 0.2:
-            return self.leaf(t), False
+            h, e = self.leaf(t)
+            return h, False, e
         kind = rng.integers(5)
         out = self.vec(t, n)
         self.nops += 1
         if kind <= 1:
-            a, oa = self.build(depth - 1, n, t)
-            b, ob = self.build(depth - 1, n, t)
-            op = g.builtin(_opname("b", BIN_M[rng.integers(len(BIN_M))], t))
+            a, oa, ea = self.build(depth - 1, n, t)
+            b, ob, eb = self.build(depth - 1, n, t)
+            name = BIN_M[rng.integers(len(BIN_M))]
+            op = g.builtin(_opname("b", name, t))
             if kind == 0:
                 g.GrB_Vector_eWiseMult_BinaryOp(out, None, None, op, a, b)
             else:
@@ -61,44 +67,68 @@ class Builder:
             for h, o in ((a, oa), (b, ob)):
                 if o:
                     g.GrB_Vector_free(h)
-            return out, True
+            return out, True, ("ewise", t, name, ea, eb)
         if kind == 2:
             ct = ["FP32", "FP64", "INT32"][rng.integers(3)]
-            a, oa = (self.leaf(ct), False) if ct == "INT32" else self.build(depth - 1, n, ct)
-            g.GrB_Vector_apply(out, None, None, g.builtin(_opname("u", UN[rng.integers(len(UN))], t)), a)
+            if ct == "INT32":
+                a, ea = self.leaf(ct)
+                oa = False
+            else:
+                a, oa, ea = self.build(depth - 1, n, ct)
+            name = UN[rng.integers(len(UN))]
+            g.GrB_Vector_apply(out, None, None, g.builtin(_opname("u", name, t)), a)
+            e = ("unary", t, name, ea)
         else:
-            a, oa = self.build(depth - 1, n, t)
-            op = g.builtin(_opname("b", BIN[rng.integers(len(BIN))], t))
+            a, oa, ea = self.build(depth - 1, n, t)
+            name = BIN[rng.integers(len(BIN))]
+            op = g.builtin(_opname("b", name, t))
             if kind == 3:
                 k = float(rng.uniform(0.5, 2.0))
                 if rng.random() < 0.5:
                     g.GrB_Vector_apply_BinaryOp1st_FP64(out, None, None, op, k, a)
+                    e = ("bind1st", t, name, k, ea)
                 else:
                     g.GrB_Vector_apply_BinaryOp2nd_FP64(out, None, None, op, a, k)
+                    e = ("bind2nd", t, name, ea, k)
             else:
-                s = self.scalars[rng.integers(len(self.scalars))]
-                g.GrB_Vector_apply_BinaryOp2nd_Scalar(out, None, None, op, a, s)
+                j = int(rng.integers(len(self.scalars)))
+                g.GrB_Vector_apply_BinaryOp2nd_Scalar(out, None, None, op, a, self.scalars[j])
+                e = ("bind2nd_scalar", t, name, ea, j)
         if oa:
             g.GrB_Vector_free(a)
-        return out, True
+        return out, True, e
 
 
-def _leaves(grb, n, seed):
-    from paper_2509_14211_amd import api
+def _leaf_values(n, seed):
+    """Host values of the leaves (numpy, in the leaf's type) and the type
+    names: FP32 and FP64 random values, small integers, two iso vectors,
+    and FP64 multiples of 1/256 (their sum is exact in any order)."""
     rng = np.random.default_rng(seed)
-    x32 = torch.tensor(rng.uniform(0.5, 2.0, n), dtype=torch.float32, device="cuda")
-    x64 = torch.tensor(rng.uniform(-2.0, 2.0, n), dtype=torch.float64, device="cuda")
-    xi = torch.tensor(rng.integers(0, 5, n), dtype=torch.int32, device="cuda")
-    iso64 = grb.GrB_Vector_new(grb.builtin("GrB_FP64"), n)
-    grb.GrM_Vector_fill(iso64, 1.5)
-    iso32 = grb.GrB_Vector_new(grb.builtin("GrB_FP32"), n)
-    grb.GrM_Vector_fill(iso32, 0.25)
-    return [(api.vector_from_tensor(x32), "FP32"), (api.vector_from_tensor(x64), "FP64"),
-            (api.vector_from_tensor(xi), "INT32"), (iso64, "FP64"), (iso32, "FP32")]
+    vals = [rng.uniform(0.5, 2.0, n).astype(np.float32), rng.uniform(-2.0, 2.0, n),
+            rng.integers(0, 5, n).astype(np.int32), np.full(n, 1.5), np.full(n, 0.25, np.float32),
+            rng.integers(-512, 513, n) / 256.0]
+    return vals, ["FP32", "FP64", "INT32", "FP64", "FP32", "FP64"]
+
+
+ISO_LEAVES = (3, 4)  # held as iso-valued vectors
+
+
+def _leaves(grb, vals, types):
+    from paper_2509_14211_amd import api
+    out = []
+    for k, (v, t) in enumerate(zip(vals, types)):
+        if k in ISO_LEAVES:
+            h = grb.GrB_Vector_new(grb.builtin("GrB_" + t), len(v))
+            grb.GrM_Vector_fill(h, float(v[0]))
+        else:
+            h = api.vector_from_tensor(torch.from_numpy(v).cuda())
+        out.append((h, t))
+    return out
 
 
 def _scalars(grb, leaf):
-    """A host-set scalar and a pending reduction (folded as a device value)."""
+    """A host-set scalar, a pending reduction of the dyadic leaf (folded as a
+    device value) and an affine map of it."""
     s1 = grb.GrB_Scalar_new(grb.builtin("GrB_FP64"))
     grb.GrB_Scalar_setElement_FP64(s1, 0.75)
     s2 = grb.GrB_Scalar_new(grb.builtin("GrB_FP64"))
@@ -109,16 +139,21 @@ def _scalars(grb, leaf):
 
 
 def _run(grb, mode, n, seed, t):
+    """(result, operations, expression, leaf values, scalar values) of the
+    random tree of this seed, recorded in the given mode."""
     from paper_2509_14211_amd import api
+    from oracle import ewise
     grb.GrM_set_mode(mode)
-    leaves = _leaves(grb, n, seed)
-    scalars = _scalars(grb, leaves[1][0])
+    vals, types = _leaf_values(n, seed)
+    leaves = _leaves(grb, vals, types)
+    scalars = _scalars(grb, leaves[5][0])
     b = Builder(grb, leaves, scalars, seed)
-    root, owned = b.build(4, n, t)
+    root, owned, expr = b.build(4, n, t)
     if not owned:
         root2 = grb.GrB_Vector_new(grb.builtin("GrB_" + t), n)
         grb.GrB_Vector_apply(root2, None, None, grb.builtin(_opname("u", "IDENTITY", t)), root)
         root = root2
+        expr = ("unary", t, "IDENTITY", expr)
     out = api.tensor_from_vector(root, torch.float32 if t == "FP32" else torch.float64).cpu()
     for h, _ in leaves:
         grb.GrB_Vector_free(h)
@@ -126,22 +161,37 @@ def _run(grb, mode, n, seed, t):
         grb.GrB_Scalar_free(s)
     grb.GrB_Vector_free(root)
     grb.GrM_set_mode(grb.GrB_NONBLOCKING)
-    return out, b.nops
+    s2 = float(np.sum(vals[5]))  # exact: multiples of 1/256 far below 2^53
+    svals = [0.75, s2, ewise.fma_double(1e-6, s2, 0.25)]
+    return out, b.nops, expr, vals, svals
 
 
-@pytest.mark.parametrize("seed", list(range(12)))
-def test_random_trees_equal_per_op_kernels(gpu, seed):
+def _bits_equal(got, ref, t):
+    """Bit for bit, NaN where ref has NaN."""
+    got, ref = torch.as_tensor(got), torch.as_tensor(ref)
+    if not torch.equal(torch.isnan(got), torch.isnan(ref)):
+        return False
+    m = ~torch.isnan(ref)
+    it = torch.int64 if t == "FP64" else torch.int32
+    return torch.equal(got[m].view(it), ref[m].view(it))
+
+
+@pytest.mark.parametrize("seed", list(range(24)))
+def test_random_trees_match_oracle_and_per_op_kernels(gpu, seed):
+    from oracle import ewise
     n = 50001 + seed
     t = "FP32" if seed % 2 else "FP64"
-    ref, nops = _run(gpu, gpu.GrB_BLOCKING, n, seed, t)
+    ref, nops, expr, vals, svals = _run(gpu, gpu.GrB_BLOCKING, n, seed, t)
     gpu.GrM_reset_stats()
-    got, _ = _run(gpu, gpu.GrB_NONBLOCKING, n, seed, t)
+    got, _, expr2, _, _ = _run(gpu, gpu.GrB_NONBLOCKING, n, seed, t)
     st = gpu.GrM_get_stats()
-    # bit for bit, NaN where the per-op kernels give NaN
-    assert torch.equal(torch.isnan(got), torch.isnan(ref))
-    m = ~torch.isnan(ref)
-    assert torch.equal(got[m].view(torch.int64 if t == "FP64" else torch.int32),
-                       ref[m].view(torch.int64 if t == "FP64" else torch.int32)), seed
+    assert expr2 == expr
+    want = ewise.evaluate(expr, vals, svals, n)
+    assert want.dtype == (np.float32 if t == "FP32" else np.float64)
+    # the generated kernel against the oracle's definition, then against the
+    # per-operation kernels
+    assert _bits_equal(got, torch.from_numpy(want), t), (seed, expr)
+    assert _bits_equal(got, ref, t), seed
     if nops >= 2:
         assert st["ewise_fused"] >= 1 and st["ewise_ops"] >= 2
 
@@ -232,13 +282,13 @@ def test_code_cache_directory(gpu, tmp_path):
     try:
         gpu.GrM_code_cache_clear()
         gpu.GrM_reset_stats()
-        a, _ = _run(gpu, gpu.GrB_NONBLOCKING, 4099, 101, "FP64")
+        a = _run(gpu, gpu.GrB_NONBLOCKING, 4099, 101, "FP64")[0]
         s1 = gpu.GrM_get_stats()
         assert s1["jit_compiles"] >= 1 and s1["jit_disk_hits"] == 0
         assert any(p.suffix == ".co" for p in tmp_path.iterdir())
         gpu.GrM_code_cache_clear()
         gpu.GrM_reset_stats()
-        b, _ = _run(gpu, gpu.GrB_NONBLOCKING, 4099, 101, "FP64")
+        b = _run(gpu, gpu.GrB_NONBLOCKING, 4099, 101, "FP64")[0]
         s2 = gpu.GrM_get_stats()
         assert s2["jit_compiles"] == 0 and s2["jit_disk_hits"] == s1["jit_compiles"]
         assert torch.equal(torch.nan_to_num(a), torch.nan_to_num(b))

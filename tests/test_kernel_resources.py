@@ -38,6 +38,7 @@ def _resources(src, tmp_path):
     ("kernels.hip", ("fused_wave_kernel", "fused_pr_kernel")),
     ("spmm.hip", ("spmm_ppr_kernel",)),
     ("many.hip", ("pr_many_kernel",)),
+    ("stripe.hip", ("fused_stripe_kernel",)),
 ])
 def test_hot_kernels_use_no_scratch(tmp_path, src, kernels):
     res = _resources(src, tmp_path)
