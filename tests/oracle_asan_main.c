@@ -127,6 +127,79 @@ static int run_pagerank(const graph *g) {
   return it;
 }
 
+
+/* Dense solve of M x = b by Gaussian elimination with partial pivoting
+ * (M is n x n, row-major, overwritten; b becomes x). */
+static void dense_solve(int n, double *M, double *b) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(M[(size_t)i * n + k]) > fabs(M[(size_t)piv * n + k])) piv = i;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) {
+        double t = M[(size_t)k * n + j];
+        M[(size_t)k * n + j] = M[(size_t)piv * n + j];
+        M[(size_t)piv * n + j] = t;
+      }
+      double t = b[k];
+      b[k] = b[piv];
+      b[piv] = t;
+    }
+    for (int i = k + 1; i < n; ++i) {
+      double f = M[(size_t)i * n + k] / M[(size_t)k * n + k];
+      for (int j = k; j < n; ++j) M[(size_t)i * n + j] -= f * M[(size_t)k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int j = i + 1; j < n; ++j) s -= M[(size_t)i * n + j] * b[j];
+    b[i] = s / M[(size_t)i * n + i];
+  }
+}
+
+/* The PageRank fixed point from the raw edge list, without the oracle's
+ * CSR: x = (1-d) v + d P x [+ d (sum of x over dangling j) v], with
+ * P[i][j] = 1/outdeg_j for each distinct edge j -> i, j != i.  Returns the
+ * L1 distance of the oracle's 400-pass iterate from it, relative to its L1
+ * norm. */
+static double lu_pin(int n, int64_t ne, const uint32_t *src, const uint32_t *dst, int mode) {
+  double *A = (double *)calloc((size_t)n * n, sizeof(double));
+  for (int64_t e = 0; e < ne; ++e)
+    if (src[e] != dst[e]) A[(size_t)src[e] * n + dst[e]] = 1.0;
+  double *outdeg = (double *)calloc((size_t)n, sizeof(double));
+  for (int s = 0; s < n; ++s)
+    for (int t = 0; t < n; ++t) outdeg[s] += A[(size_t)s * n + t];
+  double *M = (double *)xmalloc((size_t)n * n * sizeof(double));
+  double *b = (double *)xmalloc((size_t)n * sizeof(double));
+  for (int i = 0; i < n; ++i) {
+    b[i] = (1.0 - 0.85) / n;
+    for (int j = 0; j < n; ++j) {
+      double p = outdeg[j] > 0 ? A[(size_t)j * n + i] / outdeg[j] : 0.0;
+      if (mode == 1 && outdeg[j] == 0) p = 1.0 / n;
+      M[(size_t)i * n + j] = (i == j ? 1.0 : 0.0) - 0.85 * p;
+    }
+  }
+  dense_solve(n, M, b);
+  graph g = make_graph(n, ne, src, dst);
+  double *x = (double *)xmalloc((size_t)n * sizeof(double));
+  int it = oracle_pagerank(n, g.rowptrT, g.colT, g.outdeg, 0.85, 0.0, 1, 400, mode, NULL, NULL, x,
+                           NULL, NULL, NULL);
+  CHECK(it == 400);
+  double err = 0.0, norm = 0.0;
+  for (int i = 0; i < n; ++i) {
+    err += fabs(x[i] - b[i]);
+    norm += fabs(b[i]);
+  }
+  free_graph(&g);
+  free(A);
+  free(outdeg);
+  free(M);
+  free(b);
+  free(x);
+  return err / norm;
+}
+
 int main(void) {
   oracle_set_threads(4);
 
@@ -192,6 +265,43 @@ int main(void) {
                     NULL, NULL, NULL);
     for (int i = 0; i < N; ++i) CHECK(fabs(x[i] - 1.0 / N) < 1e-15);
     free_graph(&cyc);
+  }
+
+  /* dense LU pins: R-MAT at scales 3, 5, 7, both dangling modes */
+  for (int scale = 3; scale <= 7; scale += 2) {
+    const int n = 1 << scale;
+    const int64_t ne = 16 * (int64_t)n;
+    uint32_t *src = (uint32_t *)xmalloc((size_t)ne * sizeof(uint32_t));
+    uint32_t *dst = (uint32_t *)xmalloc((size_t)ne * sizeof(uint32_t));
+    oracle_rmat_edges(scale, ne, 100u + (uint64_t)scale, 0.57, 0.76, 0.95, src, dst);
+    for (int mode = 0; mode <= 1; ++mode) CHECK(lu_pin(n, ne, src, dst, mode) <= 1e-12);
+    free(src);
+    free(dst);
+  }
+
+  /* closed forms: star inward (m leaves -> centre) and outward (centre ->
+   * m leaves), uniform dangling mass */
+  {
+    enum { M = 40 };
+    const double d = 0.85;
+    uint32_t a[M], b[M];
+    for (uint32_t i = 0; i < M; ++i) {
+      a[i] = i + 1;
+      b[i] = 0;
+    }
+    graph in = make_graph(M + 1, M, a, b);
+    graph out = make_graph(M + 1, M, b, a);
+    double x[M + 1];
+    oracle_pagerank(M + 1, in.rowptrT, in.colT, in.outdeg, d, 1e-15, 1000, 0, 1, NULL, NULL, x,
+                    NULL, NULL, NULL);
+    CHECK(fabs(x[0] - (1 + M * d) / (M + 1 + M * d)) < 1e-14);
+    for (int i = 1; i <= M; ++i) CHECK(fabs(x[i] - 1 / (M + 1 + M * d)) < 1e-14);
+    oracle_pagerank(M + 1, out.rowptrT, out.colT, out.outdeg, d, 1e-15, 1000, 0, 1, NULL, NULL, x,
+                    NULL, NULL, NULL);
+    CHECK(fabs(x[0] - 1 / (M + 1 + d)) < 1e-14);
+    for (int i = 1; i <= M; ++i) CHECK(fabs(x[i] - (M + d) / (M * (M + 1 + d))) < 1e-14);
+    free_graph(&in);
+    free_graph(&out);
   }
 
   /* the empty graph */
