@@ -387,16 +387,21 @@ def main():
                 grb.GrB_Vector_free(vv)
             grb.GrB_Vector_free(r)
             seq_per_query = seq_ms / nseq
-            bpp = 4 * (n + 1) + 4 * m + 4 * n + 4 * n * len(sets) * 4
+            # algorithmic bytes: the pattern and d once per pass, and per
+            # column-pass the gathered w, x_old, x_new and w_new (columns
+            # stop at their own converged pass; the product narrows)
+            col_passes = int(np.sum(col_it[col_it > 0])) + int(np.sum(col_it <= 0)) * pit
+            alg_bytes = (4 * (n + 1) + 4 * m + 4 * n) * pit + 4 * n * 4 * col_passes
             del X
             log("ppr batch: %d sets, %d passes, %.2f ms -> %.1f queries/s; sequential %.2f ms/query "
                 "(%.1f queries/s)" % (len(sets), pit, batch_ms, len(sets) / batch_ms * 1e3,
                                       seq_per_query, 1e3 / seq_per_query))
             out["ppr"] = {"queries_per_s": round(len(sets) / batch_ms * 1e3, 1), "k": len(sets),
-                          "passes": pit, "ms_per_batch": round(batch_ms, 3),
+                          "passes": pit, "column_passes": col_passes,
+                          "ms_per_batch": round(batch_ms, 3),
                           "sequential_queries_per_s": round(1e3 / seq_per_query, 1),
                           "batch_vs_sequential_speedup": round(seq_per_query * len(sets) / batch_ms, 2),
-                          "algorithmic_gbs": round(bpp * pit / (batch_ms * 1e-3) / 1e9, 1),
+                          "algorithmic_gbs": round(alg_bytes / (batch_ms * 1e-3) / 1e9, 1),
                           "max_col_resid": float(col_res.max())}
             # a stream of seed sets through the same 64 column slots: a
             # converged column is written out and restarts with the next set
@@ -717,7 +722,12 @@ def main():
                                  "mean_iters_teleport": ev["mean_iters_teleport"],
                                  "ms_per_query_warm": round(ev["ms_warm"], 3),
                                  "ms_per_query_teleport": round(ev["ms_teleport"], 3),
-                                 "fallbacks": ev["fallbacks"]}
+                                 "ms_per_query_features": round(ev["ms_features"], 3),
+                                 "fallbacks": ev["fallbacks"],
+                                 "pays_in_wall_time": ev["pays"],
+                                 "result": ("the learned start is faster in wall time" if ev["pays"] else
+                                            "negative: features and prediction cost more wall time than "
+                                            "the passes the learned start saves")}
 
         # ---- CPU oracle: solves to the same tolerance on the same graph, 1
         # warm-up + 16 timed at the host's thread count and a bounded sample

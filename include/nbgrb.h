@@ -571,28 +571,38 @@ GrB_Info GrM_ppr(GrB_Vector r, int *iters, double *resid, GrB_Matrix AT, GrB_Vec
  * distinct vertices in [0, n)); its teleport vector is 1/|S_q| on the set.
  * Column q follows GrM_ppr exactly (start = teleport vector, the dangling
  * mass returns to the seeds in GrM_DANGLING_UNIFORM), with the residual and
- * dangling mass of every column in FP64.  All columns iterate until the
- * largest column residual is <= tol (or itermax passes).  X (device,
- * n x k row-major, `type` FP32 or FP64) receives the ranks; *iters the
- * passes performed; col_iters[q] (host, may be NULL) the first pass at
- * which column q's residual was <= tol (-1 if never); col_resid[q] (host,
- * may be NULL) its last residual. */
+ * dangling mass of every column in FP64, and stops where GrM_ppr would:
+ * at the first pass whose residual is <= tol, or after itermax passes.  A
+ * stopped column is frozen (no longer written), and once at most half the
+ * columns are still running the product narrows to them, so the passes of
+ * the slowest sets cost less than full-width passes.  X (device, n x k
+ * row-major, `type` FP32 or FP64) receives in column q the ranks of the
+ * pass column q stopped at; *iters the passes of the longest-running
+ * column; col_iters[q] (host, may be NULL) the pass at which column q's
+ * residual first was <= tol (-1 if never within itermax); col_resid[q]
+ * (host, may be NULL) column q's residual at its last pass (1 when no
+ * pass ran).
+ * Defined by: the loop of Fig. 6 with the mxv over one vector replaced by
+ * the product with k of them (one per seed set). */
 GrB_Info GrM_ppr_batch(void *X, GrB_Type type, int k, const int32_t *seed_ptr,
                        const int32_t *seed_vtx, GrB_Matrix AT, GrB_Vector outdeg, double damping,
                        double tol, int itermax, GrM_Dangling dangling, int check_every, int *iters,
                        int *col_iters, double *col_resid);
 
 /* Personalised PageRank of nsets seed sets through k column slots
- * (1 <= k <= 64) of the batched pass: the first k sets start together, and
- * whenever a column's residual has reached tol (checked every check_every
- * passes) or it has run itermax passes, its ranks are written out and the
- * column restarts with the next set, so one pass always serves k queries.
+ * (1 <= k <= 64) of the batched pass: the first k sets start together; a
+ * column stops at the first pass whose residual is <= tol (frozen there)
+ * or after itermax passes, and at the next check (every check_every
+ * passes) its ranks are written out and the column restarts with the next
+ * set, so one pass serves up to k queries.  Once no set is waiting and at
+ * most half the columns still run, the product narrows to them.
  * Seed sets as in GrM_ppr_batch.  X (device, nsets x n of `type` FP32 or
  * FP64) receives set q's ranks at X + q n in the original numbering;
- * set_iters[q] (host, may be NULL) the first pass at which its residual was
- * <= tol (-1 if never), set_passes[q] the passes it ran (its ranks are that
- * iterate), set_resid[q] its last residual.  Each set's ranks equal
- * GrM_ppr's after set_passes[q] passes. */
+ * set_iters[q] (host, may be NULL) the pass at which its residual first
+ * was <= tol (-1 if never within itermax), set_passes[q] the passes it ran
+ * (its ranks are that iterate: set_iters[q] when it converged, else
+ * itermax), set_resid[q] its residual at that pass.  Each set's ranks
+ * equal GrM_ppr's after set_passes[q] passes. */
 GrB_Info GrM_ppr_stream(void *X, GrB_Type type, int nsets, const int32_t *seed_ptr,
                         const int32_t *seed_vtx, GrB_Matrix AT, GrB_Vector outdeg, double damping,
                         double tol, int itermax, GrM_Dangling dangling, int k, int check_every,
@@ -653,10 +663,10 @@ GrB_Info GrM_pagerank_many(void *X, GrB_Type type, GrM_Multigraph mg, double dam
  * stripes of at most 8064 rows whose sums stay in LDS while the columns
  * are visited in blocks of 12288: a stripe loads the leading blocks into
  * LDS one at a time (at most hot/12288 of them, and only blocks holding at
- * least long_row of its entries, 512 when long_row is 0) and gathers its
+ * least long_row of its entries, 1024 when long_row is 0) and gathers its
  * other entries from memory.
  * Row sums are exact 64-bit fixed-point sums of the FP32 terms scaled by
- * 2^F, F = 62 - ceil(log2(longest row * max|w|)), rounded once to FP32, so
+ * 2^F, F = 62 - ceil(log2(sum |w|)), rounded once to FP32, so
  * they do not depend on the order of accumulation; the truncation of each
  * term to the fixed-point grid adds at most (row length) * 2^-F to a row
  * sum.  lds_entries, lds_rows, chunk and xcd_split are ignored; grid is the

@@ -116,8 +116,8 @@ GrB_Info GrM_autotune_pagerank(GrM_PlanConfig* chosen, double* us_per_pass, GrB_
       cands.push_back({1, 512, 256, 128, 512, 0, hmax, relabel, 0});
       // stripe plans (FP32 ranks; the layout addresses < 2^30 columns and < 2^31 entries)
       if (T == T_FP32 && A->ncols < ((int64_t)1 << 30) && A->nnz < ((int64_t)1 << 31)) {
-        cands.push_back({2, 0, 0, 512, 0, 0, 0, relabel, 0});
-        cands.push_back({2, 0, 0, 1024, 0, 0, 16 * STRIPE_HB, relabel, 0});
+        cands.push_back({2, 0, 0, 1024, 0, 0, 0, relabel, 0});
+        cands.push_back({2, 0, 0, 2048, 0, 0, 0, relabel, 0});
       }
     }
     // Time k1 and k2 fused passes in one batch each (tol 0, no early stop);
@@ -161,6 +161,16 @@ GrB_Info GrM_autotune_pagerank(GrM_PlanConfig* chosen, double* us_per_pass, GrB_
     GrB_Vector_free(&rv);
     if (info != GrB_SUCCESS) return info;
     c.tuned[{A->id, T}] = to_plan(best);
+    // The candidates' tile plans and layouts stay cached with the matrix
+    // (some are as large as the matrix itself); drop them, and the
+    // renumbered copy when the choice does not use it.  The chosen plan is
+    // rebuilt on first use.
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    A->plans.clear();
+    if (A->relabeled) {
+      A->relabeled->A->plans.clear();
+      if (!best.relabel) A->relabeled.reset();
+    }
     if (cache_path && *cache_path) append_cache(cache_path, key, best, best_us);
     *chosen = best;
     if (us_per_pass) *us_per_pass = best_us;

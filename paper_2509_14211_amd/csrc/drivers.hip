@@ -403,6 +403,41 @@ struct PprColumns {
     launch_mark(false);
   }
 
+  // Columns `cols` to their outputs: column c of the iterate from buffer
+  // set 1 when bit c of from1 is set, else from set 0 (a converged column
+  // is frozen in the buffer of the pass it converged in), in vertex order.
+  void output(uint64_t cols, uint64_t from1, const ColumnOutputs& outs) {
+    if (!cols) return;
+    hip_check(launch_spmm_columns_out(Xb[0]->p, Xb[1]->p, from1, T, rl ? (const int*)rl->inv->p : nullptr, n, k,
+                                      cols, outs, ctx().stream),
+              "columns out");
+    launch_mark(false);
+  }
+
+  // Narrows the iterate after pass `pass` to k2 columns: new column j is old
+  // column keep[j] (j < keep.size()), the rest are empty and frozen.  The
+  // product's cost follows k, so once most columns have converged the
+  // remaining passes gather k2-wide rows instead of k-wide ones.  The
+  // caller renumbers the seed table.
+  void narrow(int pass, const std::vector<int>& keep, int k2) {
+    const int cur = pass & 1;
+    ColumnMap map;
+    for (int j = 0; j < 64; ++j) map.c[j] = j < (int)keep.size() ? keep[(size_t)j] : -1;
+    hip_check(launch_spmm_compact(Xb[cur]->p, Wb[cur]->p, (const double*)Db[cur]->p, Xb[cur ^ 1]->p,
+                                  Wb[cur ^ 1]->p, (double*)Db[cur ^ 1]->p, (int*)hit->p, T, n, k, k2, map,
+                                  ctx().stream),
+              "narrow columns");
+    launch_mark(false);
+    // the narrowed copy becomes the iterate of pass `pass`
+    std::swap(Xb[0], Xb[1]);
+    std::swap(Wb[0], Wb[1]);
+    std::swap(Db[0], Db[1]);
+    k = k2;
+    a.k = k2;
+    const size_t used = type_size(T) * (size_t)n * (size_t)k2;
+    a.w_bytes = used < 0xFFFFFF00ull ? (unsigned)used : 0u;
+  }
+
   // One pass from buffer set (pass-1)&1 into pass&1.
   void run_pass(int pass) {
     Ctx& c = ctx();
@@ -458,38 +493,89 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
   c.guard = (GuardDev*)pc.gbuf->p;
   pc.a.guard = c.guard;
 
+  // col_set[c]: the seed set in column c (-1: converged and written out).
+  // Each column stops at the pass its own residual first reaches tol (the
+  // pass kernel freezes it there), so column q ends where a single-vector
+  // solve of set q would.  Converged columns are written to X at each
+  // check; once at most half the columns are live the rest are narrowed.
+  std::vector<int> col_set((size_t)k);
+  for (int q = 0; q < k; ++q) col_set[(size_t)q] = q;
+  int live = k;
+  ColumnOutputs outs{};
+  outs.ld = k;
+  auto out_of = [&](uint64_t cols, uint64_t from1) {
+    for (int col = 0; col < pc.k; ++col)
+      if ((cols >> col) & 1ull) outs.out[col] = (char*)X + type_size(T) * (size_t)col_set[(size_t)col];
+    pc.output(cols, from1, outs);
+  };
+  std::vector<int> hh(64, -1);
+  std::vector<double> rr(64, 1.0);
   GuardDev hg{};
   int pass = 0, batch = check_every;
   for (;;) {
     for (int j = 0; j < batch; ++j) pc.run_pass(++pass);
+    hip_check(hipMemcpyAsync(hh.data(), pc.hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+    hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
     hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
     hip_check(hipStreamSynchronize(c.stream), "sync");
+    if (hg.bad) break;
+    uint64_t done = 0, from1 = 0;
+    for (int col = 0; col < pc.k; ++col) {
+      const int q = col_set[(size_t)col];
+      if (q < 0 || hh[(size_t)col] < 0) continue;
+      done |= 1ull << col;
+      if (hh[(size_t)col] & 1) from1 |= 1ull << col;
+      if (col_iters) col_iters[q] = hh[(size_t)col];
+      if (col_resid) col_resid[q] = rr[(size_t)col];
+      --live;
+    }
+    out_of(done, from1);
+    for (int col = 0; col < pc.k; ++col)
+      if ((done >> col) & 1ull) col_set[(size_t)col] = -1;
     if (!hg.active) break;
+    if (live > 0 && live <= pc.k / 2) {
+      int k2 = 1;
+      while (k2 < live) k2 <<= 1;
+      std::vector<int> keep, newpos((size_t)pc.k, -1), set2((size_t)k2, -1);
+      for (int col = 0; col < pc.k; ++col)
+        if (col_set[(size_t)col] >= 0) {
+          newpos[(size_t)col] = (int)keep.size();
+          set2[keep.size()] = col_set[(size_t)col];
+          keep.push_back(col);
+        }
+      std::vector<PprSeed> kept;
+      for (const PprSeed& sd : seeds)
+        if (newpos[(size_t)sd.c] >= 0) kept.push_back({sd.v, newpos[(size_t)sd.c], sd.w});
+      pc.narrow(hg.iters, keep, k2);
+      seeds.swap(kept);
+      pc.set_seeds(seeds);
+      col_set.swap(set2);
+    }
     int next = check_every;
     if (hg.rho_prev > 0.0 && hg.rho > 0.0 && hg.rho < hg.rho_prev && tol > 0.0) {
       const double need_passes = std::log(tol / hg.rho) / std::log(hg.rho / hg.rho_prev);
       if (need_passes > 0.0 && need_passes < 1e6) next = (int)std::ceil(need_passes);
     }
+    // once columns start to converge, check often enough to narrow soon
+    if (live < k && next > 2) next = 2;
     if (next > itermax - hg.iters) next = itermax - hg.iters;
     if (next < 1) next = 1;
     batch = next;
   }
   c.guard = saved_guard;
   if (hg.bad) fail(GrB_PANIC, "ppr_batch: a column's residual or dangling mass was not finite");
-  const BufP& res = pc.Xb[hg.iters & 1];
-  if (pc.rl)
-    hip_check(launch_rows_permute(res->p, T, (const int*)pc.rl->inv->p, X, n, k, c.stream), "unpermute");
-  else
-    hip_check(hipMemcpyAsync(X, res->p, pc.vbytes, hipMemcpyDeviceToDevice, c.stream), "copy out");
-  std::vector<int> hh(64);
-  std::vector<double> rr(64);
-  hip_check(hipMemcpyAsync(hh.data(), pc.hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
-  hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+  // columns that did not converge within itermax (or ran no pass): their
+  // current iterate
+  uint64_t rest = 0;
+  for (int col = 0; col < pc.k; ++col) {
+    const int q = col_set[(size_t)col];
+    if (q < 0) continue;
+    rest |= 1ull << col;
+    if (col_iters) col_iters[q] = -1;
+    if (col_resid) col_resid[q] = hg.iters == 0 ? 1.0 : rr[(size_t)col];
+  }
+  out_of(rest, (hg.iters & 1) ? rest : 0ull);
   hip_check(hipStreamSynchronize(c.stream), "sync");
-  if (col_iters)
-    for (int q = 0; q < k; ++q) col_iters[q] = hg.iters == 0 ? -1 : hh[q];
-  if (col_resid)
-    for (int q = 0; q < k; ++q) col_resid[q] = hg.iters == 0 ? 1.0 : rr[q];
   *iters = hg.iters;
   }
   catch (const GrbError& e) {
@@ -538,7 +624,13 @@ GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_p
   c.guard = (GuardDev*)pc.gbuf->p;
   pc.a.guard = c.guard;
 
-  std::vector<int> slot_set(k, -1), slot_start(k, 0);
+  // slot_set[c]: the set in column c (-1: free), started after slot_start[c]
+  // passes.  A column stops at the pass its residual first reaches tol (the
+  // pass kernel freezes it there) or after itermax passes; it is written out
+  // at the next check and the column restarts with the next set.  Once no
+  // set is waiting and at most half the columns are live, the rest are
+  // narrowed.
+  std::vector<int> slot_set((size_t)k, -1), slot_start((size_t)k, 0);
   std::vector<PprSeed> active;  // seeds of the columns in use
   int next_set = 0, pass = 0, live = 0;
   auto set_seeds_of = [&](int q, int col, std::vector<PprSeed>& out) {
@@ -548,14 +640,15 @@ GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_p
   // fill the free slots with the next sets, starting them in buffer set `cur`
   auto refill = [&](int cur, uint64_t freed) {
     // drop the seeds of retired columns, then hand free columns the next sets
-    active.erase(std::remove_if(active.begin(), active.end(), [&](const PprSeed& s) { return slot_set[s.c] < 0; }),
+    active.erase(std::remove_if(active.begin(), active.end(),
+                                [&](const PprSeed& sd) { return slot_set[(size_t)sd.c] < 0; }),
                  active.end());
     uint64_t cols = 0;
     std::vector<PprSeed> fresh;
-    for (int col = 0; col < k && next_set < nsets; ++col) {
-      if (slot_set[col] >= 0) continue;
-      slot_set[col] = next_set;
-      slot_start[col] = pass;
+    for (int col = 0; col < pc.k && next_set < nsets; ++col) {
+      if (slot_set[(size_t)col] >= 0) continue;
+      slot_set[(size_t)col] = next_set;
+      slot_start[(size_t)col] = pass;
       set_seeds_of(next_set, col, fresh);
       cols |= 1ull << col;
       ++next_set;
@@ -568,11 +661,13 @@ GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_p
   refill(0, 0);
   std::vector<int> hh(64);
   std::vector<double> rr(64);
+  ColumnOutputs outs{};
+  outs.ld = 1;
   while (live > 0) {
     // up to check_every passes, never past a column's itermax
     int batch = check_every;
-    for (int col = 0; col < k; ++col)
-      if (slot_set[col] >= 0) batch = std::min(batch, itermax - (pass - slot_start[col]));
+    for (int col = 0; col < pc.k; ++col)
+      if (slot_set[(size_t)col] >= 0) batch = std::min(batch, itermax - (pass - slot_start[(size_t)col]));
     for (int j = 0; j < std::max(batch, 1); ++j) pc.run_pass(++pass);
     hip_check(hipMemcpyAsync(hh.data(), pc.hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
     hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
@@ -581,30 +676,47 @@ GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_p
     hip_check(hipStreamSynchronize(c.stream), "sync");
     if (hg.bad) fail(GrB_PANIC, "ppr_stream: a column's residual or dangling mass was not finite");
     const int cur = pass & 1;
-    uint64_t retired = 0;
-    ColumnOutputs outs{};
-    for (int col = 0; col < k; ++col) {
-      const int q = slot_set[col];
+    uint64_t retired = 0, from1 = 0;
+    for (int col = 0; col < pc.k; ++col) {
+      const int q = slot_set[(size_t)col];
       if (q < 0) continue;
-      const int done = pass - slot_start[col];
-      const bool conv = hh[col] >= 0;
+      const int done = pass - slot_start[(size_t)col];
+      const int h = hh[(size_t)col];
+      const bool conv = h >= 0;
       if (!conv && done < itermax) continue;
-      // retire: the column's current iterate goes to set q's output
+      // retire: the iterate of the pass it converged in (frozen since), or
+      // after itermax passes the current one
       retired |= 1ull << col;
+      if ((conv ? h : pass) & 1) from1 |= 1ull << col;
       outs.out[col] = (char*)X + type_size(T) * (size_t)n * (size_t)q;
-      if (set_iters) set_iters[q] = conv ? hh[col] - slot_start[col] : -1;
-      if (set_passes) set_passes[q] = done;
-      if (set_resid) set_resid[q] = rr[col];
-      slot_set[col] = -1;
+      if (set_iters) set_iters[q] = conv ? h - slot_start[(size_t)col] : -1;
+      if (set_passes) set_passes[q] = conv ? h - slot_start[(size_t)col] : done;
+      if (set_resid) set_resid[q] = rr[(size_t)col];
+      slot_set[(size_t)col] = -1;
       --live;
     }
-    if (retired) {
-      hip_check(launch_spmm_columns_out(pc.Xb[cur]->p, T, pc.rl ? (const int*)pc.rl->inv->p : nullptr, n, k, retired,
-                                        outs, c.stream),
-                "columns out");
-      launch_mark(false);
-      // freed columns stop contributing (zeroed) or restart with new sets
-      refill(cur, retired);
+    pc.output(retired, from1, outs);
+    // freed columns restart with new sets (or are zeroed) while sets wait
+    if (retired && next_set < nsets) refill(cur, retired);
+    if (next_set >= nsets && live > 0 && live <= pc.k / 2) {
+      int k2 = 1;
+      while (k2 < live) k2 <<= 1;
+      std::vector<int> keep, newpos((size_t)pc.k, -1), set2((size_t)k2, -1), start2((size_t)k2, 0);
+      for (int col = 0; col < pc.k; ++col)
+        if (slot_set[(size_t)col] >= 0) {
+          newpos[(size_t)col] = (int)keep.size();
+          set2[keep.size()] = slot_set[(size_t)col];
+          start2[keep.size()] = slot_start[(size_t)col];
+          keep.push_back(col);
+        }
+      std::vector<PprSeed> kept;
+      for (const PprSeed& sd : active)
+        if (newpos[(size_t)sd.c] >= 0) kept.push_back({sd.v, newpos[(size_t)sd.c], sd.w});
+      pc.narrow(pass, keep, k2);
+      active.swap(kept);
+      pc.set_seeds(active);
+      slot_set.swap(set2);
+      slot_start.swap(start2);
     }
   }
   c.guard = saved_guard;

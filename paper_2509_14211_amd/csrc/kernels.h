@@ -193,20 +193,20 @@ struct StripePlanDev {
   const unsigned short* cold_row;
   const int* wg_off;   // workgroup g runs wg_list[wg_off[g] .. wg_off[g+1])
   const int* wg_list;
-  unsigned* wg_max;    // per-workgroup max |w'| (scratch)
+  double* wg_sum;      // per-workgroup sum |w'| (scratch)
   int nstripes;
   int maxlen;          // longest row
 };
 
-// The fused pass over a stripe plan.  wmax_in: IEEE bits of max|w| of the
-// gathered vector (sets the fixed-point scale; a non-finite value makes every
-// row sum NaN).  wmax_out (may be null): receives max|w'| of the pre-scaled
-// copy written.  grid must be the plan's workgroup count.
-hipError_t launch_fused_stripe_f32(const StripePlanDev& p, const FusedArgs<float>& a, const unsigned* wmax_in,
-                                   unsigned* wmax_out, const FusedScratch& scr, int grid, const GuardDev* guard,
+// The fused pass over a stripe plan.  wsum_in: sum |w| of the gathered
+// vector (sets the fixed-point scale; a non-finite value makes every row sum
+// NaN).  wsum_out (may be null): receives sum |w'| of the pre-scaled copy
+// written.  grid must be the plan's workgroup count.
+hipError_t launch_fused_stripe_f32(const StripePlanDev& p, const FusedArgs<float>& a, const double* wsum_in,
+                                   double* wsum_out, const FusedScratch& scr, int grid, const GuardDev* guard,
                                    hipStream_t s);
-// *out = IEEE bits of max |x[i]| (deterministic; NaN above every finite value).
-hipError_t launch_absmax_f32(const float* x, int64_t n, unsigned* out, RedScratch scr, const GuardDev* guard,
+// *out = sum |x[i]| in FP64 (deterministic).
+hipError_t launch_abssum_f32(const float* x, int64_t n, double* out, RedScratch scr, const GuardDev* guard,
                              hipStream_t s);
 
 // Elementwise: out[i] = f(a[i], b[i]) computed in `ct` (T_FP32 / T_FP64).
@@ -299,13 +299,23 @@ hipError_t launch_spmm_init(const SpmmArgs& a, int type, const int* by_col_ptr, 
                             const double* by_col_w, uint64_t cols, hipStream_t s);
 // Zero columns `cols` (bit mask) of the n x k arrays x and w.
 hipError_t launch_spmm_zero_columns(void* x, void* w, int type, int64_t n, int k, uint64_t cols, hipStream_t s);
-// For every column c with bit c of `cols` set: out[c][i] = in[(idx ? idx[i]
-// : i) * k + c], i < n (columns of the n x k array in vertex order).
+// For every column c with bit c of `cols` set: out[c][i * ld] =
+// in[(idx ? idx[i] : i) * k + c], i < n (columns of the n x k array in
+// vertex order), with in = in1 when bit c of from1 is set, else in0.
 struct ColumnOutputs {
   void* out[64];
+  int64_t ld;
 };
-hipError_t launch_spmm_columns_out(const void* in, int type, const int* idx, int64_t n, int k, uint64_t cols,
-                                   const ColumnOutputs& outs, hipStream_t s);
+hipError_t launch_spmm_columns_out(const void* in0, const void* in1, uint64_t from1, int type, const int* idx,
+                                   int64_t n, int k, uint64_t cols, const ColumnOutputs& outs, hipStream_t s);
+// New column j < k2 of the n x k2 arrays x2, w2 = column map.c[j] of the
+// n x k arrays x, w (map.c[j] < 0: zeros); d2[j] = d[map.c[j]] (0 when
+// empty); hit[j] = -1 for a mapped column, 0 (frozen) otherwise, j < 64.
+struct ColumnMap {
+  int c[64];
+};
+hipError_t launch_spmm_compact(const void* x, const void* w, const double* d, void* x2, void* w2, double* d2,
+                               int* hit, int type, int64_t n, int k, int k2, const ColumnMap& map, hipStream_t s);
 // out row i = in row idx[i] (n rows of k values).
 hipError_t launch_rows_permute(const void* in, int type, const int* idx, void* out, int64_t n, int k,
                                hipStream_t s);

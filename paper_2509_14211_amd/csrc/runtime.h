@@ -100,7 +100,7 @@ struct Plan {
   BufP tiles, hubs, hub_sum, hub_cnt, hub_red;
   TilePlanDev dev{};
   // stripe plan (K_STRIPE)
-  BufP st_desc, st_hot, st_ccol, st_crow, st_wgoff, st_wglist, st_wgmax, st_mass;
+  BufP st_desc, st_hot, st_ccol, st_crow, st_wgoff, st_wglist, st_wgsum, st_mass;
   int st_nstripes = 0;
   int64_t st_hot_entries = 0, st_cold_entries = 0;  // padded
   StripePlanDev st_dev{};
@@ -183,7 +183,7 @@ struct Node {
   // Pre-scaled copy of this vector (value .* dvec or ./ dvec) produced as a
   // side output by the fused pass, keyed by operator and dvec node id.
   BufP memo;
-  BufP memo_max;  // max|memo| as IEEE bits, when the pass that wrote the memo computed it
+  BufP memo_sum;  // sum |memo| (FP64), when the pass that wrote the memo computed it
   int memo_op = -1;
   uint64_t memo_dvec = 0;
 

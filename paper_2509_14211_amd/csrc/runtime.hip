@@ -98,11 +98,16 @@ BufP dev_alloc(size_t bytes) {
   return b;
 }
 
+// Buffers of 2 GiB or more (one-off temporaries of the large builders)
+// go straight back to the allocator instead of the size-keyed cache, which
+// would keep them for an exact-size reuse that rarely comes.
+constexpr size_t CACHE_MAX_BYTES = (size_t)2 << 30;
+
 DevBuf::~DevBuf() {
   if (!p) return;
   Ctx& c = g_ctx;
   c.live_bytes -= (int64_t)bytes;
-  if (c.init)
+  if (c.init && bytes < CACHE_MAX_BYTES)
     c.cache[bytes].push_back(p);  // reused in stream order
   else
     raw_release(p);
@@ -302,7 +307,7 @@ std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
     cfg.xcd = 0;
     if (cfg.hot <= 0 || cfg.hot > STRIPE_NBMAX * STRIPE_HB) cfg.hot = STRIPE_NBMAX * STRIPE_HB;
     cfg.hot = std::max(1, cfg.hot / STRIPE_HB) * STRIPE_HB;
-    if (cfg.long_row <= 0) cfg.long_row = 512;
+    if (cfg.long_row <= 0) cfg.long_row = 1024;
   }
   if (cfg.grid <= 0) cfg.grid = (cfg.kernel == K_WAVE || stripe) ? device_cus() : device_cus() * 8;
   if (cfg.grid % 8 != 0) cfg.xcd = 0;
@@ -423,10 +428,10 @@ struct FusedSpec {
   ScalarArg c{nullptr, 0.0, 0.0};
   ReduceOut rho{nullptr, nullptr};
   ReduceOut D{nullptr, nullptr};
-  // stripe plans: max|w| of the gathered vector if known (IEEE bits), and
-  // where to put max|w_out|
-  const unsigned* wmax_in = nullptr;
-  unsigned* wmax_out = nullptr;
+  // stripe plans: sum |w| of the gathered vector if known, and where to
+  // put sum |w_out|
+  const double* wsum_in = nullptr;
+  double* wsum_out = nullptr;
 };
 
 static hipEvent_t pooled_event() {
@@ -441,7 +446,7 @@ static hipEvent_t pooled_event() {
   return e;
 }
 
-// Returns whether f.wmax_out was written.
+// Returns whether f.wsum_out was written.
 static bool run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_override = nullptr) {
   Ctx& c = g_ctx;
   PlanConfig cfg = cfg_override ? *cfg_override : default_plan_config(A, f.type);
@@ -477,7 +482,7 @@ static bool run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     hip_check(hipEventRecord(e0, c.stream), "event record");
   }
   hipError_t e;
-  bool wrote_wmax = false;
+  bool wrote_wsum = false;
   const bool wave = plan->cfg.kernel == K_WAVE;
   // no more workgroups than there is tile work: the block kernel takes tiles
   // per workgroup, the wave kernel per wavefront (16 per workgroup); a small
@@ -508,18 +513,18 @@ static bool run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     a.rho_out = f.rho;
     a.D_out = f.D;
     if (stripe) {
-      const unsigned* wmax_in = f.wmax_in;
-      unsigned* mass = (unsigned*)plan->st_mass->p;
-      if (!wmax_in) {
+      const double* wsum_in = f.wsum_in;
+      double* mass = (double*)plan->st_mass->p;
+      if (!wsum_in) {
         // no bound carried over from the pass that wrote w: measure it
-        hip_check(launch_absmax_f32(a.w, A->ncols, mass, reduce_scratch(), c.guard, c.stream), "max |w|");
+        hip_check(launch_abssum_f32(a.w, A->ncols, mass, reduce_scratch(), c.guard, c.stream), "sum |w|");
         launch_mark(false);
-        wmax_in = mass;
+        wsum_in = mass;
         // the pass timer covers the fused kernel alone
         if (timed) hip_check(hipEventRecord(e0, c.stream), "event record");
       }
-      e = launch_fused_stripe_f32(plan->st_dev, a, wmax_in, f.wmax_out, scr, plan->cfg.grid, c.guard, c.stream);
-      wrote_wmax = f.wmax_out != nullptr && a.w_out != nullptr;
+      e = launch_fused_stripe_f32(plan->st_dev, a, wsum_in, f.wsum_out, scr, plan->cfg.grid, c.guard, c.stream);
+      wrote_wsum = f.wsum_out != nullptr && a.w_out != nullptr;
     } else {
       e = wave ? launch_fused_wave_f32(plan->dev, a, scr, grid, plan->cfg.hot, c.guard, c.stream)
                : launch_fused_f32(plan->dev, a, scr, grid, plan->cfg.lds_entries,
@@ -558,7 +563,7 @@ static bool run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     c.events.push_back({e0, e1});
   }
   launch_mark(f.mode == EPI_PR);
-  return wrote_wmax;
+  return wrote_wsum;
 }
 
 // Plain (blocking) mxv: s = A (+.*) w.
@@ -1014,7 +1019,7 @@ static void run_pr_group(PRMatch& m, const Consumers& cons) {
   }
   if (memo_hit) {
     f.w = X->memo->p;
-    if (X->memo_max) f.wmax_in = (const unsigned*)X->memo_max->p;
+    if (X->memo_sum) f.wsum_in = (const double*)X->memo_sum->p;
     W->done = true;  // elided: never written
     release_inputs(*W);
   } else {
@@ -1023,13 +1028,13 @@ static void run_pr_group(PRMatch& m, const Consumers& cons) {
     f.w = W->buf->p;
   }
   // side output for the next pass: r .* dv (or ./ dv)
-  BufP memo, memo_max;
+  BufP memo, memo_sum;
   if (DV) {
     memo = dev_alloc(type_size(T) * (size_t)E->n);
-    memo_max = dev_alloc(sizeof(unsigned));
+    memo_sum = dev_alloc(sizeof(double));
     f.dvec = DV->buf->p;
     f.w_out = memo->p;
-    f.wmax_out = (unsigned*)memo_max->p;
+    f.wsum_out = (double*)memo_sum->p;
     f.memo_div = wop == B_DIV ? 1 : 0;
   }
   // E is stored when a handle or a node outside the group reads it
@@ -1053,7 +1058,7 @@ static void run_pr_group(PRMatch& m, const Consumers& cons) {
       f.mask = operand_of(m.DR->mask);
     }
   }
-  const bool wrote_max = run_fused(M->A, f);
+  const bool wrote_sum = run_fused(M->A, f);
   // bookkeeping
   M->done = true;
   release_inputs(*M);
@@ -1062,7 +1067,7 @@ static void run_pr_group(PRMatch& m, const Consumers& cons) {
   E->iso = false;
   if (DV) {
     E->memo = memo;
-    E->memo_max = wrote_max ? memo_max : nullptr;
+    E->memo_sum = wrote_sum ? memo_sum : nullptr;
     E->memo_op = wop;
     E->memo_dvec = DV->id;
   }

@@ -59,6 +59,14 @@ __device__ __forceinline__ T load_dv(const SpmmArgs& p, int i) {
   return p.plain ? (T)0 : ((const T*)p.dvec)[i];
 }
 
+// Column c takes part in this pass: it exists and has not converged yet.  A
+// converged column is frozen: no lane writes it again, so its iterate of
+// the pass it converged in stays in that pass's buffer, and its residual
+// and dangling mass stay those of that pass.
+__device__ __forceinline__ bool column_live(const SpmmArgs& p, int c) {
+  return c < p.k && !(p.hit && p.hit[c] >= 0);
+}
+
 // First vertex-sorted seed of tile t (no seeds in a plain product).
 __device__ __forceinline__ int first_seed(const SpmmArgs& p, int t) { return p.nseeds > 0 ? p.tile_seed[t] : 0; }
 
@@ -97,8 +105,9 @@ __device__ void spmm_hub_finish(const SpmmArgs& p, int4 hub, int h, int chunk, i
 
 // Per-column residual and dangling mass of the pass: wavefronts in order,
 // then workgroups in order, then hub rows; the last workgroup to arrive
-// writes rho_out / d_out and advances the loop guard on the largest column
-// residual.
+// writes rho_out / d_out of the live columns, marks the ones whose residual
+// reached hit_tol, and advances the loop guard on the largest residual of
+// the columns that were live in this pass.
 __device__ void spmm_reduce(const TilePlanDev& plan, const SpmmArgs& p, double rho, double dm,
                             double (*sr)[64], double (*sd)[64], int* sflag) {
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -155,6 +164,7 @@ __device__ void spmm_reduce(const TilePlanDev& plan, const SpmmArgs& p, double r
     bool finite = true;
     const int it = p.guard ? p.guard->iters + 1 : 0;
     for (int c = 0; c < p.k; ++c) {
+      if (!column_live(p, c)) continue;  // frozen: keeps its values
       p.rho_out[c] = sr[0][c];
       p.d_out[c] = sd[0][c];
       if (sr[0][c] > mx) mx = sr[0][c];
@@ -233,7 +243,7 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
   __shared__ int srp[SNW][TR + 1];
   __shared__ int sflag;
   const int tid = threadIdx.x, wv = wave_uniform(tid >> 6), lane = tid & 63;
-  const bool on = lane < p.k;
+  const bool on = column_live(p, lane);
   const bool plain = p.plain != 0;
   RowBufs b;
   b.row_bytes = (unsigned)p.k * (unsigned)sizeof(T);
@@ -342,7 +352,7 @@ __global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArg
   __shared__ int srp[SNW][TR + 1];
   __shared__ int sflag;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const bool on = lane < p.k;
+  const bool on = column_live(p, lane);
   const T* W = (const T*)p.w;
   T cfac = (T)0;
   if (on) cfac = (T)(p.c_beta + (p.d_prev ? p.c_alpha * p.d_prev[lane] : 0.0));
@@ -472,23 +482,52 @@ __global__ void zero_columns_kernel(void* __restrict__ x, void* __restrict__ w, 
   }
 }
 
-// 64 rows per workgroup: the selected columns of the rows go through LDS,
-// then each leaves as 64 consecutive values.
+// 64 rows per workgroup: the selected columns of the rows go through LDS
+// (column c read from in1 when bit c of from1 is set, else from in0), then
+// each leaves as 64 values at stride outs.ld.
 template <typename T>
-__global__ __launch_bounds__(256) void columns_out_kernel(const T* __restrict__ in, const int* __restrict__ idx,
-                                                          int64_t n, int k, uint64_t cols, ColumnOutputs outs) {
+__global__ __launch_bounds__(256) void columns_out_kernel(const T* __restrict__ in0, const T* __restrict__ in1,
+                                                          uint64_t from1, const int* __restrict__ idx, int64_t n,
+                                                          int k, uint64_t cols, ColumnOutputs outs) {
   __shared__ T tile[64][65];
   const int64_t r0 = (int64_t)blockIdx.x * 64;
   for (int q = threadIdx.x; q < 64 * 64; q += 256) {
     const int r = q >> 6, c = q & 63;
     const int64_t i = r0 + r;
-    if (i < n && c < k && ((cols >> c) & 1ull)) tile[r][c] = in[(idx ? (int64_t)idx[i] : i) * k + c];
+    if (i < n && c < k && ((cols >> c) & 1ull)) {
+      const T* in = ((from1 >> c) & 1ull) ? in1 : in0;
+      tile[r][c] = in[(idx ? (int64_t)idx[i] : i) * k + c];
+    }
   }
   __syncthreads();
   for (int q = threadIdx.x; q < 64 * 64; q += 256) {
     const int c = q >> 6, r = q & 63;
     const int64_t i = r0 + r;
-    if (i < n && c < k && ((cols >> c) & 1ull)) ((T*)outs.out[c])[i] = tile[r][c];
+    if (i < n && c < k && ((cols >> c) & 1ull)) ((T*)outs.out[c])[i * outs.ld] = tile[r][c];
+  }
+}
+
+// Columns map[j] (j < k2; map[j] < 0: an empty column) of the n x k arrays
+// x, w into the n x k2 arrays x2, w2, with their dangling masses; hit of
+// the new columns: -1 for a live one, 0 (frozen) for an empty one.  One
+// wavefront per row, lane j owns new column j.
+template <typename T>
+__global__ __launch_bounds__(256) void compact_columns_kernel(const T* __restrict__ x, const T* __restrict__ w,
+                                                              const double* __restrict__ d, T* __restrict__ x2,
+                                                              T* __restrict__ w2, double* __restrict__ d2,
+                                                              int* __restrict__ hit, int64_t n, int k, int k2,
+                                                              ColumnMap map) {
+  const int lane = threadIdx.x & 63;
+  const int src = lane < k2 ? map.c[lane] : -1;
+  if (blockIdx.x == 0 && threadIdx.x < 64) {
+    if (lane < k2) d2[lane] = src >= 0 ? d[src] : 0.0;
+    hit[lane] = (lane < k2 && src >= 0) ? -1 : 0;
+  }
+  if (lane >= k2) return;
+  const int64_t per_step = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < n; i += per_step) {
+    x2[i * k2 + lane] = src >= 0 ? x[i * k + src] : (T)0;
+    w2[i * k2 + lane] = src >= 0 ? w[i * k + src] : (T)0;
   }
 }
 
@@ -551,15 +590,34 @@ hipError_t launch_spmm_zero_columns(void* x, void* w, int type, int64_t n, int k
   return hipGetLastError();
 }
 
-hipError_t launch_spmm_columns_out(const void* in, int type, const int* idx, int64_t n, int k, uint64_t cols,
-                                   const ColumnOutputs& outs, hipStream_t s) {
+hipError_t launch_spmm_columns_out(const void* in0, const void* in1, uint64_t from1, int type, const int* idx,
+                                   int64_t n, int k, uint64_t cols, const ColumnOutputs& outs, hipStream_t s) {
   if (n <= 0 || !cols) return hipSuccess;
+  if (k < 1 || k > 64 || outs.ld < 1) return hipErrorInvalidValue;
   const int g = (int)((n + 63) / 64);
   if (type == T_FP32)
-    hipLaunchKernelGGL(columns_out_kernel<float>, dim3(g), dim3(256), 0, s, (const float*)in, idx, n, k, cols, outs);
+    hipLaunchKernelGGL(columns_out_kernel<float>, dim3(g), dim3(256), 0, s, (const float*)in0, (const float*)in1,
+                       from1, idx, n, k, cols, outs);
   else
-    hipLaunchKernelGGL(columns_out_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)in, idx, n, k, cols,
-                       outs);
+    hipLaunchKernelGGL(columns_out_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)in0,
+                       (const double*)in1, from1, idx, n, k, cols, outs);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_compact(const void* x, const void* w, const double* d, void* x2, void* w2, double* d2,
+                               int* hit, int type, int64_t n, int k, int k2, const ColumnMap& map, hipStream_t s) {
+  if (k < 1 || k > 64 || k2 < 1 || k2 > 64) return hipErrorInvalidValue;
+  for (int j = 0; j < k2; ++j)
+    if (map.c[j] >= k) return hipErrorInvalidValue;
+  int64_t g = (n + 3) / 4;  // four rows per 256-thread workgroup and step
+  if (g > 16384) g = 16384;
+  if (g < 1) g = 1;
+  if (type == T_FP32)
+    hipLaunchKernelGGL(compact_columns_kernel<float>, dim3((int)g), dim3(256), 0, s, (const float*)x,
+                       (const float*)w, d, (float*)x2, (float*)w2, d2, hit, n, k, k2, map);
+  else
+    hipLaunchKernelGGL(compact_columns_kernel<double>, dim3((int)g), dim3(256), 0, s, (const double*)x,
+                       (const double*)w, d, (double*)x2, (double*)w2, d2, hit, n, k, k2, map);
   return hipGetLastError();
 }
 

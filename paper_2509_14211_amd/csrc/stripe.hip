@@ -20,20 +20,21 @@
 //     while the next block loads.
 //   * Row sums are accumulated exactly in 64-bit fixed point with LDS
 //     integer atomics: w values are scaled by 2^F, where 2^(62-F) bounds
-//     (longest row) * max|w|, so no partial sum can overflow, and integer
-//     addition makes the sum independent of the order in which lanes and
-//     wavefronts add.  Each lane first adds runs of equal rows among its
-//     own entries in registers.  The row sum is then rounded once to FP32;
-//     its error is at most (row length) * 2^-F, far below FP32 rounding of
-//     the ranks it is added to.
-//   * Per row the epilogue is the usual one; it also publishes max|w'| of
-//     the pre-scaled copy it writes, which the next pass uses for its scale.
+//     sum |w| -- a row adds distinct entries of w, so no partial sum can
+//     overflow -- and integer addition makes the sum independent of the
+//     order in which lanes and wavefronts add.  Each lane first adds runs
+//     of equal rows among its own entries in registers.  Each term is
+//     truncated to the 2^-F grid (at most 2^-62 sum |w| per term) and the
+//     exact sum is rounded once to FP32.
+//   * Per row the epilogue is the usual one; it also publishes sum |w'| of
+//     the pre-scaled copy it writes (FP64), which the next pass uses for its
+//     scale.
 //
 // The layout is built on the GPU once per matrix and plan: counts of each
 // stripe's entries per column block, a choice of how many leading blocks a
 // stripe loads (a block is loaded only when enough of the stripe's entries
-// fall in it to pay for reading it), a stable radix sort of the entries by
-// (stripe, block), and a scatter into the packed arrays.  Stripes are
+// fall in it to pay for reading it), and a stable partition of each
+// stripe's entries into its segments (no sort, no temporary arrays).  Stripes are
 // assigned to workgroups by longest-processing-time-first on an estimate of
 // their cost, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
@@ -44,7 +45,6 @@
 #include <cstring>
 #include <numeric>
 #include <queue>
-#include <rocprim/rocprim.hpp>
 #include <vector>
 
 #include "device_util.h"
@@ -80,23 +80,10 @@ __device__ __forceinline__ V block_sum_st(V v, V* red) {
   return r;
 }
 
-__device__ __forceinline__ unsigned block_max_st(unsigned v, unsigned* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o, 64));
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  if (l == 0) red[w] = v;
-  __syncthreads();
-  unsigned r = 0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < STRIPE_BLOCK / 64; ++i) r = max(r, red[i]);
-  __syncthreads();
-  return r;
-}
-
 // v * 2^F as a two's-complement 64-bit integer, truncated toward zero, with
 // kshift = 188 - F.  v = mant * 2^(E - 150) (E the biased exponent, 1 for
 // subnormals), so v * 2^F = (mant << 38) >> (188 - F - E); the scale
-// guarantees a non-negative shift for every |v| <= max|w|.
+// guarantees a non-negative shift for every |v| <= sum |w|.
 __device__ __forceinline__ long long fixed_of(float v, int kshift) {
   const unsigned b = __float_as_uint(v);
   const int E = (int)((b >> 23) & 0xFFu);
@@ -249,7 +236,7 @@ __device__ __forceinline__ void cold_add(unsigned long long* acc, const ColdRegs
 // loaded during the previous phase, goes into the other buffer at the end
 // of the phase (one workgroup barrier per block).
 __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDev p, FusedArgs<float> a,
-                                                                    const unsigned* wmax_in, unsigned* wmax_out,
+                                                                    const double* wsum_in, double* wsum_out,
                                                                     FusedScratch scr, const GuardDev* guard) {
   constexpr int B = STRIPE_BLOCK;
   constexpr int NW = B / 64;
@@ -261,7 +248,6 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
   __shared__ unsigned long long acc[STRIPE_RMAX + 1];  // slot 0 takes the padding entries
   __shared__ __attribute__((aligned(16))) float hot[2][STRIPE_HB];
   __shared__ double sred[NW];
-  __shared__ unsigned smax[NW];
   __shared__ int sflag;
 
   const int tid = threadIdx.x;
@@ -271,14 +257,14 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
   float c = 0.0f;
   if (pr) c = (float)scalar_value(a.c);
 
-  // fixed-point scale: 2^(62-F) >= maxlen * max|w|
-  const float wmax = __uint_as_float(*wmax_in & 0x7FFFFFFFu);
-  const bool finite = __builtin_isfinite(wmax);
-  const double bound = (double)p.maxlen * (double)wmax;
+  // fixed-point scale: 2^(62-F) >= sum |w|.  Every partial sum of a row
+  // adds distinct entries of w, so its magnitude is at most sum |w|.
+  const double wsum = *wsum_in;
+  const bool finite = __builtin_isfinite(wsum);
   int F = 62;
-  if (finite && bound > 0.0) {
+  if (finite && wsum > 0.0) {
     int k = 0;
-    (void)frexp(bound, &k);  // bound < 2^k
+    (void)frexp(wsum, &k);  // wsum < 2^k
     F = 62 - k;
   }
   const int kshift = 188 - F;
@@ -286,7 +272,7 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
 
   const __amdgpu_buffer_rsrc_t rw = buf_rsrc(a.w, (unsigned)a.ncols * 4u);
   double rho = 0.0, dm = 0.0;
-  unsigned wmx = 0u;
+  double wsm = 0.0;  // sum |w'| of this thread's rows
 
   const int g = blockIdx.x;
   const int s_begin = p.wg_off[g], s_end = p.wg_off[g + 1];
@@ -423,7 +409,7 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
       if (a.w_out) {
         const float wn = a.memo_div ? rv / dv[k] : rv * dv[k];
         a.w_out[i] = wn;
-        wmx = max(wmx, __float_as_uint(wn) & 0x7FFFFFFFu);
+        wsm += fabs((double)wn);
       }
       if (a.do_D) {
         const bool m = a.mask_is_dvec ? (dv[k] != 0.0f) : nonzero_at(a.mask, i);
@@ -434,87 +420,84 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
     __syncthreads();  // slots are clear before the next stripe adds into them
   }
 
-  const bool reduce = (pr && (a.rho_out.out || a.D_out.out || a.rho_out.guard)) || wmax_out;
+  const bool reduce = (pr && (a.rho_out.out || a.D_out.out || a.rho_out.guard)) || wsum_out;
   if (!reduce) return;
   const double br = block_sum_st<double, B>(rho, sred);
   const double bd = block_sum_st<double, B>(dm, sred);
-  const unsigned bm = block_max_st(wmx, smax);
+  const double bw = block_sum_st<double, B>(wsm, sred);
   if (tid == 0) {
     publish(&scr.wg_part[2 * g], br);
     publish(&scr.wg_part[2 * g + 1], bd);
-    publish(&p.wg_max[g], bm);
+    publish(&p.wg_sum[g], bw);
     wait_stores();
     sflag = ticket_add(scr.ticket) == gridDim.x - 1;
   }
   __syncthreads();
   if (!sflag) return;
-  double pr_ = 0.0, pd = 0.0;
-  unsigned pm = 0u;
+  double pr_ = 0.0, pd = 0.0, pw = 0.0;
   for (int k = tid; k < (int)gridDim.x; k += B) {
     pr_ += consume(&scr.wg_part[2 * k]);
     pd += consume(&scr.wg_part[2 * k + 1]);
-    pm = max(pm, consume(&p.wg_max[k]));
+    pw += consume(&p.wg_sum[k]);
   }
   const double tr = block_sum_st<double, B>(pr_, sred);
   const double tdm = block_sum_st<double, B>(pd, sred);
-  const unsigned tm = block_max_st(pm, smax);
+  const double tw = block_sum_st<double, B>(pw, sred);
   if (tid == 0) {
     if (pr) {
       if (a.rho_out.out) *a.rho_out.out = tr;
       if (a.D_out.out) *a.D_out.out = tdm;
       if (a.rho_out.guard) guard_advance(a.rho_out.guard, tr, a.do_D ? tdm : 0.0);
     }
-    if (wmax_out) *wmax_out = tm;
+    if (wsum_out) *wsum_out = tw;
     publish(scr.ticket, 0u);
   }
 }
 
-hipError_t launch_fused_stripe_f32(const StripePlanDev& p, const FusedArgs<float>& a, const unsigned* wmax_in,
-                                   unsigned* wmax_out, const FusedScratch& scr, int grid, const GuardDev* guard,
+hipError_t launch_fused_stripe_f32(const StripePlanDev& p, const FusedArgs<float>& a, const double* wsum_in,
+                                   double* wsum_out, const FusedScratch& scr, int grid, const GuardDev* guard,
                                    hipStream_t s) {
-  if (grid <= 0 || !wmax_in) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fused_stripe_kernel, dim3(grid), dim3(STRIPE_BLOCK), 0, s, p, a, wmax_in, wmax_out, scr,
+  if (grid <= 0 || !wsum_in) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fused_stripe_kernel, dim3(grid), dim3(STRIPE_BLOCK), 0, s, p, a, wsum_in, wsum_out, scr,
                      guard);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------ max |x|
 
-// Deterministic two-level max of |x| (as IEEE bits; NaN above every finite
-// value) into *out.
-__global__ __launch_bounds__(256) void absmax_kernel(const float* x, int64_t n, unsigned* out, RedScratch scr,
+// Deterministic two-level FP64 sum of |x| into *out: per-workgroup sums,
+// then the last workgroup adds them in workgroup order.
+__global__ __launch_bounds__(256) void abssum_kernel(const float* x, int64_t n, double* out, RedScratch scr,
                                                       const GuardDev* guard) {
   if (guard && guard->active == 0) return;
-  __shared__ unsigned red[4];
+  __shared__ double red[4];
   __shared__ int sflag;
-  unsigned m = 0u;
+  double a = 0.0;
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
-    m = max(m, __float_as_uint(x[i]) & 0x7FFFFFFFu);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) a += fabs((double)x[i]);
+  a = block_sum_st<double, 256>(a, red);
   if (threadIdx.x == 0) {
-    m = max(max(red[0], red[1]), max(red[2], red[3]));
-    publish(&scr.partials[blockIdx.x], (double)m);
+    publish(&scr.partials[blockIdx.x], a);
     wait_stores();
     sflag = ticket_add(scr.ticket) == gridDim.x - 1;
   }
   __syncthreads();
-  if (!sflag || threadIdx.x != 0) return;
-  unsigned t = 0u;
-  for (int k = 0; k < (int)gridDim.x; ++k) t = max(t, (unsigned)consume(&scr.partials[k]));
-  *out = t;
-  publish(scr.ticket, 0u);
+  if (!sflag) return;
+  double t = 0.0;
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += 256) t += consume(&scr.partials[k]);
+  t = block_sum_st<double, 256>(t, red);
+  if (threadIdx.x == 0) {
+    *out = t;
+    publish(scr.ticket, 0u);
+  }
 }
 
-hipError_t launch_absmax_f32(const float* x, int64_t n, unsigned* out, RedScratch scr, const GuardDev* guard,
+hipError_t launch_abssum_f32(const float* x, int64_t n, double* out, RedScratch scr, const GuardDev* guard,
                              hipStream_t s) {
   int64_t g = (n + 256 * 8 - 1) / (256 * 8);
   if (g < 1) g = 1;
   if (g > REDUCE_GRID) g = REDUCE_GRID;
-  hipLaunchKernelGGL(absmax_kernel, dim3((int)g), dim3(256), 0, s, x, n, out, scr, guard);
+  hipLaunchKernelGGL(abssum_kernel, dim3((int)g), dim3(256), 0, s, x, n, out, scr, guard);
   return hipGetLastError();
 }
 
@@ -537,45 +520,64 @@ __global__ __launch_bounds__(256) void st_count_kernel(const int* rowptr, const 
   if (threadIdx.x < NCLS) cnt[s * NCLS + threadIdx.x] = h[threadIdx.x];
 }
 
-// key = (segment << 32) | entry, segment = s * NCLS + min(block, nb[s]).
-__global__ __launch_bounds__(256) void st_key_kernel(const int* rowptr, const int* col, const int* sr0,
-                                                      const int* nbs, uint64_t* keys) {
+// Stable partition of each stripe's entries (in CSR order, so by row) into
+// its segments, one workgroup of 256 per stripe.  The entries go in chunks
+// of 256; each wavefront ranks its lanes among the lanes of the same class
+// with ballots, the four wavefronts' counts are combined in LDS, and the
+// running count of each class places the entry in its segment.  Row of an
+// entry: binary search over the stripe's row pointers.
+__global__ __launch_bounds__(256) void st_partition_kernel(const int* rowptr, const int* col, const int* sr0,
+                                                          const int* nbs, const int64_t* obase, unsigned* hot,
+                                                          unsigned* ccol, unsigned short* crow) {
+  __shared__ int run[NCLS];       // entries of each class placed so far
+  __shared__ int wcnt[4][NCLS];   // entries of each class per wavefront in this chunk
   const int s = blockIdx.x;
-  const int e0 = rowptr[sr0[s]], e1 = rowptr[sr0[s + 1]];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int r0 = sr0[s], r1 = sr0[s + 1];
+  const int e0 = rowptr[r0], e1 = rowptr[r1];
   const int nb = nbs[s];
-  for (int e = e0 + threadIdx.x; e < e1; e += 256) {
-    const int cls = min(col[e] / STRIPE_HB, nb);
-    keys[e] = ((uint64_t)(unsigned)(s * NCLS + cls) << 32) | (uint64_t)(unsigned)e;
-  }
-}
-
-// Sorted position q holds entry e of segment seg: its row is found by a
-// binary search over the stripe's rows; it goes to position
-// obase[seg] + (q - ustart[seg]) of the packed hot words or cold pairs.
-__global__ __launch_bounds__(256) void st_scatter_kernel(const uint64_t* keys, int64_t m, const int* rowptr,
-                                                          const int* col, const int* sr0, const int* nbs,
-                                                          const int64_t* ustart, const int64_t* obase,
-                                                          unsigned* hot, unsigned* ccol, unsigned short* crow) {
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < m; q += stride) {
-    const uint64_t k = keys[q];
-    const int seg = (int)(k >> 32);
-    const int e = (int)(unsigned)(k & 0xFFFFFFFFull);
-    const int s = seg / NCLS, cls = seg % NCLS;
-    int lo = sr0[s], hi = sr0[s + 1];  // row r with rowptr[r] <= e < rowptr[r+1]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (rowptr[mid] <= e) lo = mid; else hi = mid;
+  if (t < NCLS) run[t] = 0;
+  for (int c0 = e0; c0 < e1; c0 += 256) {
+    if (t < 4 * NCLS) (&wcnt[0][0])[t] = 0;
+    __syncthreads();
+    const int e = c0 + t;
+    const bool ok = e < e1;
+    int cls = 0, cc = 0;
+    if (ok) {
+      cc = col[e];
+      cls = min(cc / STRIPE_HB, nb);
     }
-    const unsigned rl = (unsigned)(lo - sr0[s] + 1);
-    const int64_t dst = obase[seg] + (q - ustart[seg]);
-    const int cc = col[e];
-    if (cls < nbs[s]) {
-      hot[dst] = (rl << 16) | (unsigned)(cc - cls * STRIPE_HB);
-    } else {
-      ccol[dst] = (unsigned)cc;
-      crow[dst] = (unsigned short)rl;
+    int rank = 0;
+    unsigned long long todo = __ballot(ok);
+    while (todo) {
+      const int lead = __ffsll((long long)todo) - 1;
+      const int k = __shfl(cls, lead, 64);
+      const unsigned long long m = __ballot(ok && cls == k);
+      if (ok && cls == k) rank = __popcll(m & ((1ull << lane) - 1ull));
+      if (lane == 0) wcnt[w][k] = __popcll(m);
+      todo &= ~m;
     }
+    __syncthreads();
+    if (ok) {
+      int before = run[cls] + rank;
+      for (int v = 0; v < w; ++v) before += wcnt[v][cls];
+      int lo = r0, hi = r1;  // row r with rowptr[r] <= e < rowptr[r+1]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rowptr[mid] <= e) lo = mid; else hi = mid;
+      }
+      const unsigned rl = (unsigned)(lo - r0 + 1);
+      const int64_t dst = obase[(int64_t)s * NCLS + cls] + before;
+      if (cls < nb) {
+        hot[dst] = (rl << 16) | (unsigned)(cc - cls * STRIPE_HB);
+      } else {
+        ccol[dst] = (unsigned)cc;
+        crow[dst] = (unsigned short)rl;
+      }
+    }
+    __syncthreads();
+    if (t < NCLS) run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    __syncthreads();  // the counts are read before the next chunk clears them
   }
 }
 
@@ -630,12 +632,12 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
   // LDS blocks of each stripe: leading blocks with enough entries
   const int nb_cap = std::min<int64_t>(STRIPE_NBMAX, cfg.hot > 0 ? std::max(1, cfg.hot / STRIPE_HB) : STRIPE_NBMAX);
   const int ncolblk = (int)((A->ncols + STRIPE_HB - 1) / STRIPE_HB);
-  const int min_entries = cfg.long_row > 0 ? cfg.long_row : 512;
+  const int min_entries = cfg.long_row > 0 ? cfg.long_row : 1024;
   std::vector<int> nbs(S);
   std::vector<StripeDesc> desc(S);
-  std::vector<int64_t> ustart((size_t)S * NCLS, 0), obase((size_t)S * NCLS, 0);
+  std::vector<int64_t> obase((size_t)S * NCLS, 0);
   std::vector<double> cost(S);
-  int64_t hot_total = 0, cold_total = 0, sorted = 0;
+  int64_t hot_total = 0, cold_total = 0, counted = 0;
   for (int s = 0; s < S; ++s) {
     const int* cs = &cnt[(size_t)s * NCLS];
     int nb = 0;
@@ -650,9 +652,8 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
     int64_t off = 0, hot_e = 0;
     for (int b = 0; b < nb; ++b) {
       d.seg[b] = (int)off;
-      ustart[(size_t)s * NCLS + b] = sorted;
       obase[(size_t)s * NCLS + b] = hot_total + off;
-      sorted += cs[b];
+      counted += cs[b];
       off += pad8(cs[b]);
       hot_e += cs[b];
     }
@@ -660,9 +661,8 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
     hot_total += off;
     int64_t cold = 0;
     for (int b = nb; b < NCLS; ++b) cold += cs[b];
-    ustart[(size_t)s * NCLS + nb] = sorted;
     obase[(size_t)s * NCLS + nb] = cold_total;
-    sorted += cold;
+    counted += cold;
     d.cold_base = cold_total;
     d.cold_n = (int)pad8(cold);
     cold_total += pad8(cold);
@@ -671,7 +671,7 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
     // gathered from memory (about 0.3 per cycle), rows of the epilogue
     cost[s] = (double)hot_e / 2.0 + nb * 700.0 + (double)cold / 0.3 + d.nrows / 4.0 + 2000.0;
   }
-  if (sorted != m) fail(GrB_PANIC, "stripe plan: entry counts do not add up");
+  if (counted != m) fail(GrB_PANIC, "stripe plan: entry counts do not add up");
   if (hot_total >= ((int64_t)1 << 32) || cold_total >= ((int64_t)1 << 32))
     fail(GrB_INVALID_VALUE, "stripe plan too large");
 
@@ -684,35 +684,15 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
   hip_check(launch_zero(plan.st_crow->p, plan.st_crow->bytes, c.stream), "zero");
   if (m > 0) {
     BufP d_nb = dev_alloc(sizeof(int) * (size_t)S);
-    BufP d_us = dev_alloc(sizeof(int64_t) * ustart.size());
     BufP d_ob = dev_alloc(sizeof(int64_t) * obase.size());
     hip_check(hipMemcpyAsync(d_nb->p, nbs.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.stream), "upload");
-    hip_check(hipMemcpyAsync(d_us->p, ustart.data(), sizeof(int64_t) * ustart.size(), hipMemcpyHostToDevice,
-                             c.stream),
-              "upload");
     hip_check(hipMemcpyAsync(d_ob->p, obase.data(), sizeof(int64_t) * obase.size(), hipMemcpyHostToDevice,
                              c.stream),
               "upload");
-    BufP k0 = dev_alloc(sizeof(uint64_t) * (size_t)m), k1 = dev_alloc(sizeof(uint64_t) * (size_t)m);
-    hipLaunchKernelGGL(st_key_kernel, dim3(S), dim3(256), 0, c.stream, rowptr, col, (const int*)d_sr0->p,
-                       (const int*)d_nb->p, (uint64_t*)k0->p);
-    hip_check(hipGetLastError(), "stripe keys");
-    unsigned end_bit = 32;
-    while (end_bit < 64 && ((uint64_t)S * NCLS) > ((uint64_t)1 << (end_bit - 32))) ++end_bit;
-    size_t tb = 0;
-    hip_check(rocprim::radix_sort_keys(nullptr, tb, (uint64_t*)k0->p, (uint64_t*)k1->p, (size_t)m, 0u, end_bit,
-                                       c.stream),
-              "sort size");
-    BufP tmp = dev_alloc(tb + 256);
-    hip_check(rocprim::radix_sort_keys(tmp->p, tb, (uint64_t*)k0->p, (uint64_t*)k1->p, (size_t)m, 0u, end_bit,
-                                       c.stream),
-              "sort");
-    const int grid = (int)std::min<int64_t>((m + 255) / 256, 8192);
-    hipLaunchKernelGGL(st_scatter_kernel, dim3(grid), dim3(256), 0, c.stream, (const uint64_t*)k1->p, m, rowptr,
-                       col, (const int*)d_sr0->p, (const int*)d_nb->p, (const int64_t*)d_us->p,
-                       (const int64_t*)d_ob->p, (unsigned*)plan.st_hot->p, (unsigned*)plan.st_ccol->p,
-                       (unsigned short*)plan.st_crow->p);
-    hip_check(hipGetLastError(), "stripe scatter");
+    hipLaunchKernelGGL(st_partition_kernel, dim3(S), dim3(256), 0, c.stream, rowptr, col, (const int*)d_sr0->p,
+                       (const int*)d_nb->p, (const int64_t*)d_ob->p, (unsigned*)plan.st_hot->p,
+                       (unsigned*)plan.st_ccol->p, (unsigned short*)plan.st_crow->p);
+    hip_check(hipGetLastError(), "stripe partition");
     hip_check(hipStreamSynchronize(c.stream), "sync");
   }
 
@@ -742,8 +722,8 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
   plan.st_desc = dev_alloc(sizeof(StripeDesc) * (size_t)std::max(S, 1));
   plan.st_wgoff = dev_alloc(sizeof(int) * (size_t)(G + 1));
   plan.st_wglist = dev_alloc(sizeof(int) * (size_t)std::max(S, 1));
-  plan.st_wgmax = dev_alloc(sizeof(unsigned) * (size_t)G);
-  plan.st_mass = dev_alloc(sizeof(unsigned) * 2);
+  plan.st_wgsum = dev_alloc(sizeof(double) * (size_t)G);
+  plan.st_mass = dev_alloc(sizeof(double));
   if (S > 0) {
     hip_check(hipMemcpyAsync(plan.st_desc->p, desc.data(), sizeof(StripeDesc) * S, hipMemcpyHostToDevice, c.stream),
               "upload");
@@ -764,7 +744,7 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
   d.cold_row = (const unsigned short*)plan.st_crow->p;
   d.wg_off = (const int*)plan.st_wgoff->p;
   d.wg_list = (const int*)plan.st_wglist->p;
-  d.wg_max = (unsigned*)plan.st_wgmax->p;
+  d.wg_sum = (double*)plan.st_wgsum->p;
   d.nstripes = S;
   d.maxlen = maxlen;
 }

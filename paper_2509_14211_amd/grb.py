@@ -276,14 +276,33 @@ _FREE_T = ctypes.CFUNCTYPE(None, vp, vp)
 _keep = []
 
 
+def allocator_thunks(alloc, release):
+    """C callbacks for GrM_set_allocator around Python callables.  A Python
+    exception must not cross into C: ctypes would print it and hand the
+    library an undefined (non-null) pointer.  A failed allocation returns
+    NULL instead, which the library reports as GrB_OUT_OF_MEMORY."""
+    def _alloc(n, ctx):
+        try:
+            return alloc(n) or None
+        except Exception:
+            return None
+
+    def _release(p, ctx):
+        try:
+            release(p)
+        except Exception:
+            pass
+
+    return _ALLOC_T(_alloc), _FREE_T(_release)
+
+
 def GrM_set_allocator(alloc=None, release=None):
     """alloc(nbytes) -> int address, release(address) -> None (Python
     callables), or both None for hipMalloc / hipFree."""
     if alloc is None:
         _call("GrM_set_allocator", None, None, None)
         return
-    ca = _ALLOC_T(lambda n, ctx: alloc(n) or None)
-    cf = _FREE_T(lambda p, ctx: release(p))
+    ca, cf = allocator_thunks(alloc, release)
     _keep.append((ca, cf))
     _call("GrM_set_allocator", ctypes.cast(ca, vp), ctypes.cast(cf, vp), None)
 
@@ -645,8 +664,10 @@ def GrM_ppr(r, AT, outdeg, teleport, damping, tol, itermax, dangling=GrM_DANGLIN
 def GrM_ppr_batch(X, type_, seed_sets, AT, outdeg, damping, tol, itermax,
                   dangling=GrM_DANGLING_UNIFORM, check_every=8):
     """seed_sets: list of k integer sequences.  X: device buffer (tensor or
-    address) of n*k entries of type_.  Returns (passes, per-column first
-    converged pass, per-column last residual)."""
+    address) of n*k entries of type_ (n x k row-major).  Each column stops
+    at its own converged pass.  Returns (passes of the longest-running
+    column, per-column converged pass (-1: not within itermax), per-column
+    residual at its last pass)."""
     import numpy as np
     k = len(seed_sets)
     ptr = np.zeros(k + 1, dtype=np.int32)

@@ -89,3 +89,25 @@ def test_product_path_does_not_touch_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "liboracle" not in text, f
                 assert "from oracle" not in text, f
+
+
+def test_allocator_exception_becomes_null():
+    """An allocator callable that raises (torch's out-of-memory error) makes
+    the C callback return NULL, which the library turns into
+    GrB_OUT_OF_MEMORY; without the guard ctypes returns an undefined
+    non-null pointer that kernels would then write to."""
+    import ctypes
+    from paper_2509_14211_amd import grb
+
+    def oom(n):
+        raise MemoryError("out of memory")
+
+    freed = []
+    ca, cf = grb.allocator_thunks(oom, freed.append)
+    assert ca(1 << 40, None) is None
+    ok, _ = grb.allocator_thunks(lambda n: 4096, freed.append)
+    assert ok(16, None) == 4096
+    cf(4096, None)
+    assert freed == [4096]
+    _, bad_free = grb.allocator_thunks(oom, oom)
+    bad_free(4096, None)  # an exception in release is swallowed as well

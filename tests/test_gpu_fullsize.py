@@ -1,8 +1,9 @@
 """Parity at the workload sizes, in the launch configuration the benchmark
-times (autotuned plan: wave tiles, LDS hot slice, degree relabeling): the
-R-MAT scale-22 and scale-25 solves against the full FP64 oracle, the 64-set
-batched PPR on sampled columns, all 256 graphs of the many-graph workload,
-and the warm-start network on sampled vertices of the scale-22 graph."""
+times (autotuned plan): the R-MAT scale-22 and scale-25 solves against the
+full FP64 oracle (L1 and per vertex), the stripe-blocked plan forced at
+scale 22, every column of the 64-set batched PPR and every set of a
+128-set PPR stream, all 256 graphs of the many-graph workload, and the
+warm-start network on sampled vertices of the scale-22 graph."""
 import os
 
 import numpy as np
@@ -102,8 +103,11 @@ def test_scale22_fp64_fused_matches_oracle(gpu, oracle_mod, g22):
     assert abs(res - ref.resid) <= 4 * np.abs(x - ref.x).sum() + 1e-16
 
 
-def test_scale22_ppr_batch_sampled_columns(gpu, oracle_mod, g22):
-    """64 seed sets (sizes 1..16, seed 7) as one SpMM solve to 1e-6."""
+def test_scale22_ppr_batch_all_columns(gpu, oracle_mod, g22):
+    """64 seed sets (sizes 1..16, seed 7) as one SpMM solve to 1e-6: every
+    column against the single-vector oracle after its own pass count (a
+    column stops where its residual first reaches the tolerance), in L1 and
+    per vertex."""
     g, og = g22
     sets = [s.tolist() for s in synthetic.ppr_seed_sets(g.n, 64, seed=7)]
     X = torch.empty(g.n * 64, dtype=torch.float32, device="cuda")
@@ -111,9 +115,29 @@ def test_scale22_ppr_batch_sampled_columns(gpu, oracle_mod, g22):
     X = X.reshape(g.n, 64).cpu().numpy().astype(np.float64)
     assert col_res.max() <= 1e-6
     assert np.all(np.abs(X.sum(axis=0) - 1.0) <= 1e-5)
-    for q in (0, 17, 40, 63):
-        ref = oracle_mod.ppr(og, sets[q], D, fixed_iters=it)
+    assert it == col_it.max() and col_it.min() >= 1
+    for q in range(64):
+        print("ppr batch column %d (%d passes)" % (q, col_it[q]), flush=True)
+        ref = oracle_mod.ppr(og, sets[q], D, fixed_iters=int(col_it[q]))
         assert np.abs(X[:, q] - ref.x).sum() <= 1e-5, q
+        _per_vertex(X[:, q], ref.x)
+
+
+def test_scale22_ppr_stream_128_sets(gpu, oracle_mod, g22):
+    """128 seed sets streamed through 64 columns (converged columns retire
+    and restart with the next set): every set against the single-vector
+    oracle after the passes it ran, in L1 and per vertex."""
+    g, og = g22
+    sets = [s.tolist() for s in synthetic.ppr_seed_sets(g.n, 128, seed=8)]
+    X = torch.empty(g.n * 128, dtype=torch.float32, device="cuda")
+    first, ran, res = gpu.GrM_ppr_stream(X, gpu.builtin("GrB_FP32"), sets, g.AT, g.outdeg, D, 1e-6, 1000)
+    X = X.reshape(128, g.n).cpu().numpy().astype(np.float64)
+    assert res.max() <= 1e-6
+    for q in range(128):
+        print("ppr stream set %d (%d passes)" % (q, int(ran[q])), flush=True)
+        ref = oracle_mod.ppr(og, sets[q], D, fixed_iters=int(ran[q]))
+        assert np.abs(X[q] - ref.x).sum() <= 1e-5, q
+        _per_vertex(X[q], ref.x)
 
 
 def test_scale22_warm_start_sampled_vertices(gpu, oracle_mod, g22):
@@ -171,6 +195,45 @@ def test_many_graphs_full_workload(gpu, oracle_mod):
             x_.free()
 
 
+def test_scale25_stripe_mxv_exact_on_integers(gpu):
+    """The stripe layout at scale 25 (about 4,200 stripes of up to 8064
+    rows, 2,731 column blocks): with integer-valued FP32 operands every
+    fixed-point term and row sum is exact, so GrB_mxv on the stripe plan
+    equals the exact product bit for bit -- each entry is placed exactly
+    once, in its own row, with and without the degree renumbering."""
+    from paper_2509_14211_amd import api
+    print("scale-25 graph on the GPU (integer mxv)", flush=True)
+    g = api.rmat_graph(25)
+    t = gpu.builtin("GrB_FP32")
+    try:
+        rp, col = api.csr_of(g.AT)
+        rows = torch.repeat_interleave(torch.arange(g.n, device="cuda"), (rp[1:] - rp[:-1]).long())
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(5)
+        u = torch.randint(-8, 9, (g.n,), device="cuda", generator=gen).float()
+        exact = torch.zeros(g.n, dtype=torch.float64, device="cuda").index_add_(0, rows, u[col.long()].double())
+        del rows, rp, col
+        gpu.GrM_set_mode(gpu.GrB_BLOCKING)
+        for relabel in (0, 1):
+            gpu.GrM_Matrix_plan_set(g.AT, t, dict(kernel=2, lds_entries=0, lds_rows=0, long_row=1024, chunk=0,
+                                                  grid=0, hot=0, relabel=relabel))
+            uv = api.vector_from_tensor(u)
+            w = gpu.GrB_Vector_new(t, g.n)
+            try:
+                gpu.GrB_mxv(w, None, None, gpu.builtin("GrB_PLUS_TIMES_SEMIRING_FP32"), g.AT, uv)
+                got = api.tensor_from_vector(w, torch.float32).double()
+            finally:
+                gpu.GrB_Vector_free(uv)
+                gpu.GrB_Vector_free(w)
+                gpu.GrM_Matrix_plan_set(g.AT, t, None)
+            bad = (got != exact).nonzero().flatten()
+            print("relabel %d: %d rows differ" % (relabel, bad.numel()), flush=True)
+            assert bad.numel() == 0, (relabel, bad[:10].tolist())
+    finally:
+        gpu.GrM_set_mode(gpu.GrB_NONBLOCKING)
+        g.free()
+
+
 def test_scale25_fp32_fused_matches_oracle(gpu, oracle_mod):
     """The HBM-bound size: graph bit-exact and the FP32 solve within 1e-5 L1
     of the full FP64 oracle (about a minute of oracle work)."""
@@ -194,6 +257,7 @@ def test_scale25_fp32_fused_matches_oracle(gpu, oracle_mod):
         err = np.abs(x - ref.x).sum()
         print("scale 25 fp32: %d passes, L1 error %.3e" % (it, err), flush=True)
         assert err <= 1e-5 and res <= 1e-6
+        _per_vertex(x, ref.x)
         assert abs(x.sum() - 1.0) <= 1e-5
     finally:
         g.free()
@@ -224,7 +288,7 @@ def test_scale23_fp64_batch_takes_the_wide_kernel(gpu, oracle_mod):
         print("scale-23 graph in the oracle", flush=True)
         og = oracle_mod.rmat_graph(23)
         for j, q in enumerate(cols):
-            ref = oracle_mod.ppr(og, sets[q], D, fixed_iters=it)
+            ref = oracle_mod.ppr(og, sets[q], D, fixed_iters=int(col_it[q]))
             assert np.abs(Xs[:, j] - ref.x).sum() / np.abs(ref.x).sum() <= 1e-12, q
     finally:
         g.free()

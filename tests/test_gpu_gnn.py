@@ -278,6 +278,14 @@ def test_warm_start_saves_iterations_on_unseen_seed_sets(gpu, oracle_mod):
         res = ws.evaluate(test_g, sets, tol=1e-6, graph_seed=2000)
         assert res["fallbacks"] == 0
         assert res["mean_iters_warm"] < res["mean_iters_teleport"], res
+        # the wall-time figure of the warm start includes its features and
+        # prediction; whether it pays is decided on wall time
+        assert 0.0 < res["ms_features"] < res["ms_warm"], res
+        assert res["ms_teleport"] > 0.0
+        assert res["pays"] == (res["ms_warm"] < res["ms_teleport"])
+        print("warm start at scale 12: %.2f vs %.2f iterations, %.3f vs %.3f ms per query (%.3f ms features)"
+              % (res["mean_iters_warm"], res["mean_iters_teleport"], res["ms_warm"], res["ms_teleport"],
+                 res["ms_features"]), flush=True)
         og = oracle_mod.rmat_graph(12, seed=2000)
         for q in range(3):
             xv = ws.predict_vector(test_g, sets[q], graph_seed=2000, index=q)

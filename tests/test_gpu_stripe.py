@@ -122,7 +122,7 @@ def test_stripe_hub_and_edge_graphs(nonblocking, cfg):
         g.free()
 
 
-@pytest.mark.parametrize("scale", [9, 17])
+@pytest.mark.parametrize("scale", [9, 17, 21])
 def test_stripe_mxv_exact_on_integers(blocking, scale):
     """Blocking-mode GrB_mxv on the stripe plan: with integer-valued FP32
     operands (|sums| < 2^24) every fixed-point term and row sum is exact, so
