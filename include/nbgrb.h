@@ -646,7 +646,7 @@ GrB_Info GrM_pagerank_many(void *X, GrB_Type type, GrM_Multigraph mg, double dam
  * Tile plans.  The row-parallel kernels (mxv and the fused PageRank pass)
  * walk a plan of row tiles built once per matrix and configuration on the
  * host (the analogue of the paper's compiled-kernel cache keyed by a method
- * signasignature, Section III-C):
+ * signature, Section III-C):
  *   kernel       0: one workgroup per tile; 1: one wavefront per tile;
  *                2: stripes of rows (kernel 2 below)
  *   lds_entries  entries a tile stages in LDS (kernel 0: 1024, 2048 or 4096;
@@ -661,10 +661,11 @@ GrB_Info GrM_pagerank_many(void *X, GrB_Type type, GrM_Multigraph mg, double dam
  *   grid         persistent workgroups (0: 8 per compute unit)
  * Kernel 2 (FP32 ranks only; other types run kernel 1) cuts the rows into
  * stripes of at most 8064 rows whose sums stay in LDS while the columns
- * are visited in blocks of 12288: a stripe loads the leading blocks into
- * LDS one at a time (at most hot/12288 of them, and only blocks holding at
- * least long_row of its entries, 1024 when long_row is 0) and gathers its
- * other entries from memory.
+ * are visited in blocks of 12288: a stripe loads the blocks holding the
+ * most of its entries into LDS one at a time (at most hot/12288 of them,
+ * only blocks holding at least long_row of its entries, 1024 when long_row
+ * is 0, and only among the first 16383 blocks when there are more than
+ * 16384) and gathers its other entries from memory.
  * Row sums are exact 64-bit fixed-point sums of the FP32 terms scaled by
  * 2^F, F = 62 - ceil(log2(sum |w|)), rounded once to FP32, so
  * they do not depend on the order of accumulation; the truncation of each
@@ -677,17 +678,17 @@ GrB_Info GrM_pagerank_many(void *X, GrB_Type type, GrM_Multigraph mg, double dam
 typedef struct {
   int32_t kernel;   /* 0: workgroup tiles; 1: wavefront tiles (lds_entries 512,
                        lds_rows 256, 1024-thread workgroups); 2: row stripes
-                       with the leading columns in LDS blocks (FP32 only; see
-                       below) */
+                       with their densest column blocks in LDS (FP32 only;
+                       see below) */
   int32_t lds_entries;
   int32_t lds_rows;
   int32_t long_row;
   int32_t chunk;
   int32_t grid;
   int32_t hot;      /* kernel 1: leading entries of the gathered vector kept in
-                       LDS (clamped to what fits); kernel 2: leading columns
-                       that may be held in LDS blocks (whole blocks of 12288,
-                       0: 32 blocks) */
+                       LDS (clamped to what fits); kernel 2: columns a
+                       stripe may hold in LDS (whole blocks of 12288, 0: 32
+                       blocks) */
   int32_t relabel;  /* GrM_pagerank: 1 runs on a copy of the matrix with the
                        vertices renumbered by decreasing out-degree (built once
                        and cached with the matrix), so the most gathered values

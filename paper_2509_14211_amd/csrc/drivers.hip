@@ -222,6 +222,10 @@ struct PprSeed {
   double w;
 };
 
+// A batch with at most this many columns still running finishes them as
+// single-vector solves.
+constexpr int PPR_TAIL_COLUMNS = 16;
+
 // Seed sets seed_vtx[seed_ptr[q] : seed_ptr[q+1]], q < nsets: non-empty,
 // distinct vertices in [0, n).
 void check_seed_sets(int nsets, const int32_t* seed_ptr, const int32_t* seed_vtx, int64_t n) {
@@ -493,14 +497,17 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
   c.guard = (GuardDev*)pc.gbuf->p;
   pc.a.guard = c.guard;
 
-  // col_set[c]: the seed set in column c (-1: converged and written out).
-  // Each column stops at the pass its own residual first reaches tol (the
-  // pass kernel freezes it there), so column q ends where a single-vector
-  // solve of set q would.  Converged columns are written to X at each
-  // check; once at most half the columns are live the rest are narrowed.
+  // col_set[c]: the seed set in column c (-1: none).  Each column stops at
+  // the pass its own residual first reaches tol (the pass kernel freezes it
+  // there, in the buffer of that pass), so column q ends where a
+  // single-vector solve of set q would.  Converged columns are written to
+  // X when the product narrows (before their buffers are reused) and at the
+  // end: once at most half the columns are live, the rest are narrowed.
   std::vector<int> col_set((size_t)k);
   for (int q = 0; q < k; ++q) col_set[(size_t)q] = q;
   int live = k;
+  uint64_t frozen = 0, frozen1 = 0;  // converged, not yet written; from buffer set 1
+  bool tail = false;
   ColumnOutputs outs{};
   outs.ld = k;
   auto out_of = [&](uint64_t cols, uint64_t from1) {
@@ -519,23 +526,28 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
     hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
     hip_check(hipStreamSynchronize(c.stream), "sync");
     if (hg.bad) break;
-    uint64_t done = 0, from1 = 0;
     for (int col = 0; col < pc.k; ++col) {
       const int q = col_set[(size_t)col];
-      if (q < 0 || hh[(size_t)col] < 0) continue;
-      done |= 1ull << col;
-      if (hh[(size_t)col] & 1) from1 |= 1ull << col;
+      if (q < 0 || ((frozen >> col) & 1ull) || hh[(size_t)col] < 0) continue;
+      frozen |= 1ull << col;
+      if (hh[(size_t)col] & 1) frozen1 |= 1ull << col;
       if (col_iters) col_iters[q] = hh[(size_t)col];
       if (col_resid) col_resid[q] = rr[(size_t)col];
       --live;
     }
-    out_of(done, from1);
-    for (int col = 0; col < pc.k; ++col)
-      if ((done >> col) & 1ull) col_set[(size_t)col] = -1;
     if (!hg.active) break;
-    if (live > 0 && live <= pc.k / 2) {
-      int k2 = 1;
-      while (k2 < live) k2 <<= 1;
+    if (live <= PPR_TAIL_COLUMNS) {
+      tail = true;
+      break;
+    }
+    // narrow to the live columns rounded up to 16 (rows of whole 64-byte
+    // sectors in FP32) once that is narrower
+    const int k2 = (live + 15) / 16 * 16;
+    if (k2 < pc.k) {
+      out_of(frozen, frozen1);
+      for (int col = 0; col < pc.k; ++col)
+        if ((frozen >> col) & 1ull) col_set[(size_t)col] = -1;
+      frozen = frozen1 = 0;
       std::vector<int> keep, newpos((size_t)pc.k, -1), set2((size_t)k2, -1);
       for (int col = 0; col < pc.k; ++col)
         if (col_set[(size_t)col] >= 0) {
@@ -551,12 +563,14 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
       pc.set_seeds(seeds);
       col_set.swap(set2);
     }
+    // at most check_every passes between checks (fewer when the slowest
+    // column is predicted to finish sooner); once columns start to
+    // converge, every second pass, so the product narrows soon after
     int next = check_every;
     if (hg.rho_prev > 0.0 && hg.rho > 0.0 && hg.rho < hg.rho_prev && tol > 0.0) {
       const double need_passes = std::log(tol / hg.rho) / std::log(hg.rho / hg.rho_prev);
-      if (need_passes > 0.0 && need_passes < 1e6) next = (int)std::ceil(need_passes);
+      if (need_passes > 0.0 && need_passes < (double)next) next = (int)std::ceil(need_passes);
     }
-    // once columns start to converge, check often enough to narrow soon
     if (live < k && next > 2) next = 2;
     if (next > itermax - hg.iters) next = itermax - hg.iters;
     if (next < 1) next = 1;
@@ -564,19 +578,80 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
   }
   c.guard = saved_guard;
   if (hg.bad) fail(GrB_PANIC, "ppr_batch: a column's residual or dangling mass was not finite");
-  // columns that did not converge within itermax (or ran no pass): their
-  // current iterate
+  // the converged columns not yet written
+  out_of(frozen, frozen1);
   uint64_t rest = 0;
-  for (int col = 0; col < pc.k; ++col) {
-    const int q = col_set[(size_t)col];
-    if (q < 0) continue;
-    rest |= 1ull << col;
-    if (col_iters) col_iters[q] = -1;
-    if (col_resid) col_resid[q] = hg.iters == 0 ? 1.0 : rr[(size_t)col];
+  for (int col = 0; col < pc.k; ++col)
+    if (col_set[(size_t)col] >= 0 && !((frozen >> col) & 1ull)) rest |= 1ull << col;
+  const int done_passes = hg.iters;
+  int max_passes = hg.iters;
+  if (tail && itermax > done_passes) {
+    // The few columns still running continue one by one as single-vector
+    // solves (GrM_ppr) from their current iterate: that pass costs a small
+    // fraction of even a one-column SpMM pass.  Their iterate, teleport
+    // vector and dangling mass define the next pass completely, so column q
+    // still ends where a single-vector solve of set q from the start would.
+    const size_t vb = type_size(T) * (size_t)n;
+    for (int col = 0; col < pc.k; ++col) {
+      if (!((rest >> col) & 1ull)) continue;
+      const int q = col_set[(size_t)col];
+      GB_Vector_opaque xv{MAGIC_VEC, T, n, nullptr}, tv{MAGIC_VEC, T, n, nullptr}, rv{MAGIC_VEC, T, n, nullptr};
+      NodeP xn = new_node(N_DENSE, T, n, false), tn = new_node(N_DENSE, T, n, false);
+      xn->buf = dev_alloc(vb);
+      tn->buf = dev_alloc(vb);
+      ColumnOutputs one{};
+      one.ld = 1;
+      one.out[col] = xn->buf->p;
+      pc.output(1ull << col, (done_passes & 1) ? (1ull << col) : 0ull, one);
+      hip_check(launch_zero(tn->buf->p, vb, c.stream), "zero");
+      const int ns = seed_ptr[q + 1] - seed_ptr[q];
+      BufP sidx = pc.upload(seed_vtx + seed_ptr[q], sizeof(int) * (size_t)ns);
+      hip_check(launch_scatter_value(tn->buf->p, T, (const int*)sidx->p, ns, 1.0 / (double)ns, c.stream), "seeds");
+      launch_mark(false);
+      xn->done = tn->done = true;
+      set_vec(&xv, xn);
+      set_vec(&tv, tn);
+      int it = 0;
+      double res = 1.0;
+      c.guard = saved_guard;
+      const GrB_Info info = pagerank_impl((GrB_Vector)&rv, &it, &res, AT, outdeg, (GrB_Vector)&tv, damping, tol,
+                                          itermax - done_passes, dangling, (GrB_Vector)&xv, check_every);
+      if (info != GrB_SUCCESS) {
+        set_vec(&xv, nullptr);
+        set_vec(&tv, nullptr);
+        set_vec(&rv, nullptr);
+        fail(info, "ppr_batch: " + api_error());
+      }
+      materialize(rv.node);
+      require_full(rv.node, "a batched PPR column");
+      ColumnOutputs to{};
+      to.ld = k;
+      to.out[0] = (char*)X + type_size(T) * (size_t)q;
+      hip_check(launch_spmm_columns_out(rv.node->buf->p, rv.node->buf->p, 0, T, nullptr, n, 1, 1ull, to, c.stream),
+                "column out");
+      launch_mark(false);
+      const bool conv = res <= tol;
+      if (col_iters) col_iters[q] = conv ? done_passes + it : -1;
+      if (col_resid) col_resid[q] = res;
+      max_passes = std::max(max_passes, done_passes + it);
+      hip_check(hipStreamSynchronize(c.stream), "sync");
+      set_vec(&xv, nullptr);
+      set_vec(&tv, nullptr);
+      set_vec(&rv, nullptr);
+    }
+  } else {
+    // columns that did not converge within itermax (or ran no pass): their
+    // current iterate
+    for (int col = 0; col < pc.k; ++col) {
+      if (!((rest >> col) & 1ull)) continue;
+      const int q = col_set[(size_t)col];
+      if (col_iters) col_iters[q] = -1;
+      if (col_resid) col_resid[q] = hg.iters == 0 ? 1.0 : rr[(size_t)col];
+    }
+    out_of(rest, (hg.iters & 1) ? rest : 0ull);
   }
-  out_of(rest, (hg.iters & 1) ? rest : 0ull);
   hip_check(hipStreamSynchronize(c.stream), "sync");
-  *iters = hg.iters;
+  *iters = max_passes;
   }
   catch (const GrbError& e) {
     c.guard = saved_guard;

@@ -164,8 +164,10 @@ int wave_hot_max(int type);
 // Stripe-blocked fused pass (FP32 only).  Rows of the pattern are cut into
 // stripes of at most STRIPE_RMAX rows, one workgroup of STRIPE_BLOCK threads
 // per stripe at a time, row sums in LDS as 64-bit fixed point; columns into
-// blocks of STRIPE_HB values of the gathered vector, the leading `nb` blocks
-// of each stripe loaded into LDS in turn.
+// blocks of STRIPE_HB values of the gathered vector, the `nb` blocks that
+// hold most of a stripe's entries (listed ascending in blk) loaded into LDS
+// in turn.  Blocks at or past STRIPE_MAXBLK - 1 are never loaded (one bin
+// counts them all when the layout is built).
 //   hot words   : (row in stripe + 1) << 16 | column in the block, one
 //                 segment per (stripe, LDS block), sorted by row, padded to
 //                 a multiple of 8 with zero words;
@@ -177,14 +179,16 @@ constexpr int STRIPE_RMAX = 8064;
 constexpr int STRIPE_HB = 12288;
 constexpr int STRIPE_NBMAX = 32;
 constexpr int STRIPE_K = 8;  // consecutive entries per lane
+constexpr int STRIPE_MAXBLK = 16384;
 
 struct StripeDesc {
   int r0, nrows, nb, cold_n;    // rows [r0, r0 + nrows); LDS blocks; padded cold entries
   long long hot_base, cold_base;  // first hot word / cold pair of the stripe
-  int seg[STRIPE_NBMAX + 1];    // hot segment of block b: [seg[b], seg[b+1]) after hot_base
+  int seg[STRIPE_NBMAX + 1];    // hot segment of LDS block b: [seg[b], seg[b+1]) after hot_base
+  int blk[STRIPE_NBMAX];        // column block of LDS block b (ascending)
   int pad[7];
 };
-static_assert(sizeof(StripeDesc) == 192, "stripe descriptor layout");
+static_assert(sizeof(StripeDesc) == 320, "stripe descriptor layout");
 
 struct StripePlanDev {
   const StripeDesc* desc;
@@ -316,6 +320,8 @@ struct ColumnMap {
 };
 hipError_t launch_spmm_compact(const void* x, const void* w, const double* d, void* x2, void* w2, double* d2,
                                int* hit, int type, int64_t n, int k, int k2, const ColumnMap& map, hipStream_t s);
+// x[idx[j]] = v for j < cnt (x of `type` FP32 or FP64).
+hipError_t launch_scatter_value(void* x, int type, const int* idx, int cnt, double v, hipStream_t s);
 // out row i = in row idx[i] (n rows of k values).
 hipError_t launch_rows_permute(const void* in, int type, const int* idx, void* out, int64_t n, int k,
                                hipStream_t s);

@@ -531,6 +531,16 @@ __global__ __launch_bounds__(256) void compact_columns_kernel(const T* __restric
   }
 }
 
+__global__ void scatter_value_kernel(void* __restrict__ x, int type, const int* __restrict__ idx, int cnt,
+                                     double v) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt) return;
+  if (type == T_FP32)
+    ((float*)x)[idx[j]] = (float)v;
+  else
+    ((double*)x)[idx[j]] = v;
+}
+
 __global__ void rows_permute_kernel(const void* __restrict__ in, int type, const int* __restrict__ idx,
                                     void* __restrict__ out, int64_t n, int k) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -618,6 +628,12 @@ hipError_t launch_spmm_compact(const void* x, const void* w, const double* d, vo
   else
     hipLaunchKernelGGL(compact_columns_kernel<double>, dim3((int)g), dim3(256), 0, s, (const double*)x,
                        (const double*)w, d, (double*)x2, (double*)w2, d2, hit, n, k, k2, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_value(void* x, int type, const int* idx, int cnt, double v, hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_value_kernel, dim3((cnt + 255) / 256), dim3(256), 0, s, x, type, idx, cnt, v);
   return hipGetLastError();
 }
 

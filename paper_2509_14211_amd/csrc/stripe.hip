@@ -8,14 +8,16 @@
 //
 //   * Rows of A^T are cut into stripes of at most STRIPE_RMAX rows.  A
 //     workgroup keeps the stripe's row sums in LDS.
-//   * Columns (sources) are cut into blocks of STRIPE_HB.  With vertices
-//     renumbered by decreasing out-degree the leading blocks hold the most
-//     gathered values (at R-MAT scale 22 the first 8 blocks draw 80% of all
-//     gathers).  For each of its leading blocks the stripe stores the
+//   * Columns (sources) are cut into blocks of STRIPE_HB.  Each stripe
+//     loads the blocks that hold most of its entries: with vertices
+//     renumbered by decreasing out-degree these are the leading blocks (at
+//     R-MAT scale 22 the first 8 blocks draw 80% of all gathers); on a
+//     graph whose links are mostly local they are the blocks around the
+//     stripe's own rows.  For each of its LDS blocks the stripe stores the
 //     entries that fall in it as packed words (row in the stripe << 16 |
 //     column in the block), sorted by row; the workgroup loads the block of
 //     w into LDS once and every such entry reads LDS.
-//   * The stripe's remaining entries (columns past its LDS blocks) are
+//   * The stripe's remaining entries (columns outside its LDS blocks) are
 //     stored as (column, row in the stripe) pairs and gathered from memory
 //     while the next block loads.
 //   * Row sums are accumulated exactly in 64-bit fixed point with LDS
@@ -31,8 +33,8 @@
 //     scale.
 //
 // The layout is built on the GPU once per matrix and plan: counts of each
-// stripe's entries per column block, a choice of how many leading blocks a
-// stripe loads (a block is loaded only when enough of the stripe's entries
+// stripe's entries per column block, the choice of the blocks a stripe
+// loads (those with the most of its entries, each only when enough of them
 // fall in it to pay for reading it), and a stable partition of each
 // stripe's entries into its segments (no sort, no temporary arrays).  Stripes are
 // assigned to workgroups by longest-processing-time-first on an estimate of
@@ -125,21 +127,27 @@ __device__ __forceinline__ void add_runs(unsigned long long* acc, const int (&ro
   atomicAdd(&acc[cur], (unsigned long long)s);
 }
 
-// The workgroup's LDS block after block b of the stripe at list position
-// si: the next block of the same stripe, else block 0 of the next stripe in
-// the list that loads any (b = -1: the first block of stripe si or later).
-// Returns false when there is none.
-__device__ __forceinline__ bool next_block(const StripePlanDev& p, int si, int s_end, int b, int& nsi, int& nb_) {
-  if (si < s_end && b + 1 < wave_uniform(p.desc[wave_uniform(p.wg_list[si])].nb)) {
-    nsi = si;
-    nb_ = b + 1;
-    return true;
+// The workgroup's LDS block after LDS block b of the stripe at list
+// position si: the next one of the same stripe, else the first of the next
+// stripe in the list that loads any (b = -1: the first of stripe si or
+// later), and its column block.  Returns false when there is none.
+__device__ __forceinline__ bool next_block(const StripePlanDev& p, int si, int s_end, int b, int& nsi, int& nb_,
+                                           int& col_blk) {
+  if (si < s_end) {
+    const StripeDesc* d = p.desc + wave_uniform(p.wg_list[si]);
+    if (b + 1 < wave_uniform(d->nb)) {
+      nsi = si;
+      nb_ = b + 1;
+      col_blk = wave_uniform(d->blk[b + 1]);
+      return true;
+    }
   }
   for (int k = si + 1; k < s_end; ++k) {
-    const int t = wave_uniform(p.wg_list[k]);
-    if (wave_uniform(p.desc[t].nb) > 0) {
+    const StripeDesc* d = p.desc + wave_uniform(p.wg_list[k]);
+    if (wave_uniform(d->nb) > 0) {
       nsi = k;
       nb_ = 0;
+      col_blk = wave_uniform(d->blk[0]);
       return true;
     }
   }
@@ -280,16 +288,16 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
   for (int i = tid; i <= STRIPE_RMAX; i += B) acc[i] = 0ull;
   // LDS block sequence: (bsi, bb) is the block after the one in flight
   int kblk = 0;  // blocks consumed so far: the next one sits in hot[kblk & 1]
-  int bsi = s_begin, bb = -1;
+  int bsi = s_begin, bb = -1, bcol = 0;
   bool have1 = false;  // block kblk + 1 is in registers R1 / R2 (by parity)
   uint4 R1[HV], R2[HV];
   {
-    if (s_begin < s_end && next_block(p, bsi, s_end, bb, bsi, bb)) {
+    if (s_begin < s_end && next_block(p, bsi, s_end, bb, bsi, bb, bcol)) {
       uint4 R[HV];
-      load_block<HV>(a.w, a.ncols, bb, tid, B, HV, R);
+      load_block<HV>(a.w, a.ncols, bcol, tid, B, HV, R);
       store_block<HV>(hot[0], tid, B, HV, R);
-      if (next_block(p, bsi, s_end, bb, bsi, bb)) {
-        load_block<HV>(a.w, a.ncols, bb, tid, B, HV, R1);
+      if (next_block(p, bsi, s_end, bb, bsi, bb, bcol)) {
+        load_block<HV>(a.w, a.ncols, bcol, tid, B, HV, R1);
         have1 = true;
       }
     }
@@ -343,12 +351,12 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
     if (cur.b < nb) hot_words(hot_seg0, segv, cur, lane, wa, wb);
     for (int b = 0; b < nb; ++b) {
       // block kblk + 2 of the sequence into the free register set
-      const bool more2 = have1 && next_block(p, bsi, s_end, bb, bsi, bb);
+      const bool more2 = have1 && next_block(p, bsi, s_end, bb, bsi, bb, bcol);
       if (more2) {
         if (kblk & 1)
-          load_block<HV>(a.w, a.ncols, bb, tid, B, HV, R1);
+          load_block<HV>(a.w, a.ncols, bcol, tid, B, HV, R1);
         else
-          load_block<HV>(a.w, a.ncols, bb, tid, B, HV, R2);
+          load_block<HV>(a.w, a.ncols, bcol, tid, B, HV, R2);
       }
       const float* hbuf = hot[kblk & 1];
       while (cur.b == b) {
@@ -505,47 +513,122 @@ hipError_t launch_abssum_f32(const float* x, int64_t n, double* out, RedScratch 
 
 namespace {
 
-// cnt[s][cls] = entries of stripe s whose column falls in block cls
-// (classes past STRIPE_NBMAX - 1 are merged into the last one).  One
-// workgroup per stripe.
-__global__ __launch_bounds__(256) void st_count_kernel(const int* rowptr, const int* col, const int* sr0,
-                                                        int* cnt) {
-  __shared__ int h[NCLS];
-  const int s = blockIdx.x;
-  if (threadIdx.x < NCLS) h[threadIdx.x] = 0;
+// The LDS blocks of stripe s: entries per column block counted in an LDS
+// histogram (blocks at or past nbins - 1 share the last bin when
+// `merged`, and that bin is never chosen), then up to nb_cap rounds pick
+// the bin with the most entries (ties: the lower block) while it holds at
+// least min_entries.  Writes nbs[s], the chosen blocks ascending in
+// blk[s][..] with their entry counts in hcnt[s][..], and cold[s] = the
+// stripe's other entries.  One workgroup per stripe.
+__global__ __launch_bounds__(1024) void st_select_kernel(const int* rowptr, const int* col, const int* sr0,
+                                                         int nbins, int merged, int nb_cap, int min_entries,
+                                                         int* nbs, int* blk, int* hcnt, int* cold) {
+  __shared__ int h[STRIPE_MAXBLK];
+  __shared__ unsigned long long red[16];
+  __shared__ unsigned long long pick;
+  __shared__ int sb[STRIPE_NBMAX], sc[STRIPE_NBMAX];
+  const int s = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int i = t; i < nbins; i += 1024) h[i] = 0;
   __syncthreads();
   const int e0 = rowptr[sr0[s]], e1 = rowptr[sr0[s + 1]];
-  for (int e = e0 + threadIdx.x; e < e1; e += 256) atomicAdd(&h[min(col[e] / STRIPE_HB, STRIPE_NBMAX)], 1);
+  for (int e = e0 + t; e < e1; e += 1024) atomicAdd(&h[min(col[e] / STRIPE_HB, nbins - 1)], 1);
   __syncthreads();
-  if (threadIdx.x < NCLS) cnt[s * NCLS + threadIdx.x] = h[threadIdx.x];
+  const int choosable = merged ? nbins - 1 : nbins;
+  int k = 0;
+  for (; k < nb_cap; ++k) {
+    // key: count in the high half, ~bin in the low half (larger count, then
+    // lower bin, wins)
+    unsigned long long best = 0;
+    for (int i = t; i < choosable; i += 1024) {
+      const int c = h[i];
+      if (c > 0) {
+        const unsigned long long key = ((unsigned long long)(unsigned)c << 32) | (unsigned)(~(unsigned)i);
+        best = key > best ? key : best;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long other = __shfl_xor(best, o, 64);
+      best = other > best ? other : best;
+    }
+    if (lane == 0) red[w] = best;
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long b = 0;
+      for (int i = 0; i < 16; ++i) b = red[i] > b ? red[i] : b;
+      pick = b;
+      const int c = (int)(b >> 32);
+      if (c >= min_entries && c > 0) {
+        const int bin = (int)~(unsigned)(b & 0xFFFFFFFFull);
+        sb[k] = bin;
+        sc[k] = c;
+        h[bin] = 0;
+      }
+    }
+    __syncthreads();
+    const int c = (int)(pick >> 32);
+    if (c < min_entries || c == 0) break;
+  }
+  if (t == 0) {
+    // ascending block order (insertion sort of at most 32)
+    for (int i = 1; i < k; ++i) {
+      const int b = sb[i], c = sc[i];
+      int j = i - 1;
+      while (j >= 0 && sb[j] > b) {
+        sb[j + 1] = sb[j];
+        sc[j + 1] = sc[j];
+        --j;
+      }
+      sb[j + 1] = b;
+      sc[j + 1] = c;
+    }
+    int hot = 0;
+    for (int i = 0; i < k; ++i) {
+      blk[s * STRIPE_NBMAX + i] = sb[i];
+      hcnt[s * STRIPE_NBMAX + i] = sc[i];
+      hot += sc[i];
+    }
+    nbs[s] = k;
+    cold[s] = (e1 - e0) - hot;
+  }
 }
 
 // Stable partition of each stripe's entries (in CSR order, so by row) into
-// its segments, one workgroup of 256 per stripe.  The entries go in chunks
-// of 256; each wavefront ranks its lanes among the lanes of the same class
-// with ballots, the four wavefronts' counts are combined in LDS, and the
-// running count of each class places the entry in its segment.  Row of an
-// entry: binary search over the stripe's row pointers.
+// its segments, one workgroup of 256 per stripe.  The class of an entry is
+// the position of its column block in the stripe's block list (binary
+// search), or nb for the rest.  The entries go in chunks of 256; each
+// wavefront ranks its lanes among the lanes of the same class with
+// ballots, the four wavefronts' counts are combined in LDS, and the running
+// count of each class places the entry in its segment.  Row of an entry:
+// binary search over the stripe's row pointers.
 __global__ __launch_bounds__(256) void st_partition_kernel(const int* rowptr, const int* col, const int* sr0,
-                                                          const int* nbs, const int64_t* obase, unsigned* hot,
-                                                          unsigned* ccol, unsigned short* crow) {
+                                                          const int* nbs, const int* blk, const int64_t* obase,
+                                                          unsigned* hot, unsigned* ccol, unsigned short* crow) {
   __shared__ int run[NCLS];       // entries of each class placed so far
   __shared__ int wcnt[4][NCLS];   // entries of each class per wavefront in this chunk
+  __shared__ int sblk[STRIPE_NBMAX];
   const int s = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r0 = sr0[s], r1 = sr0[s + 1];
   const int e0 = rowptr[r0], e1 = rowptr[r1];
   const int nb = nbs[s];
   if (t < NCLS) run[t] = 0;
+  if (t < nb) sblk[t] = blk[s * STRIPE_NBMAX + t];
   for (int c0 = e0; c0 < e1; c0 += 256) {
     if (t < 4 * NCLS) (&wcnt[0][0])[t] = 0;
     __syncthreads();
     const int e = c0 + t;
     const bool ok = e < e1;
-    int cls = 0, cc = 0;
+    int cls = 0, cc = 0, cb = 0;
     if (ok) {
       cc = col[e];
-      cls = min(cc / STRIPE_HB, nb);
+      cb = cc / STRIPE_HB;
+      int lo = 0, hi = nb;  // first listed block >= cb
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sblk[mid] < cb) lo = mid + 1; else hi = mid;
+      }
+      cls = (lo < nb && sblk[lo] == cb) ? lo : nb;
     }
     int rank = 0;
     unsigned long long todo = __ballot(ok);
@@ -569,7 +652,7 @@ __global__ __launch_bounds__(256) void st_partition_kernel(const int* rowptr, co
       const unsigned rl = (unsigned)(lo - r0 + 1);
       const int64_t dst = obase[(int64_t)s * NCLS + cls] + before;
       if (cls < nb) {
-        hot[dst] = (rl << 16) | (unsigned)(cc - cls * STRIPE_HB);
+        hot[dst] = (rl << 16) | (unsigned)(cc - cb * STRIPE_HB);
       } else {
         ccol[dst] = (unsigned)cc;
         crow[dst] = (unsigned short)rl;
@@ -613,36 +696,42 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
 
   BufP d_sr0 = dev_alloc(sizeof(int) * (size_t)(S + 1));
   hip_check(hipMemcpyAsync(d_sr0->p, sr0.data(), sizeof(int) * (S + 1), hipMemcpyHostToDevice, c.stream), "upload");
-  BufP d_cnt = dev_alloc(sizeof(int) * (size_t)S * NCLS);
+  // LDS blocks of each stripe: the blocks with the most entries, each with
+  // at least min_entries of them
+  const int nb_cap = std::min<int64_t>(STRIPE_NBMAX, cfg.hot > 0 ? std::max(1, cfg.hot / STRIPE_HB) : STRIPE_NBMAX);
+  const int64_t ncolblk = (A->ncols + STRIPE_HB - 1) / STRIPE_HB;
+  const int nbins = (int)std::max<int64_t>(1, std::min<int64_t>(ncolblk, STRIPE_MAXBLK));
+  const int merged = ncolblk > STRIPE_MAXBLK ? 1 : 0;
+  const int min_entries = cfg.long_row > 0 ? cfg.long_row : 1024;
+  const size_t S1 = (size_t)std::max(S, 1);
+  BufP d_nb = dev_alloc(sizeof(int) * S1), d_cold = dev_alloc(sizeof(int) * S1);
+  BufP d_blk = dev_alloc(sizeof(int) * S1 * STRIPE_NBMAX), d_hc = dev_alloc(sizeof(int) * S1 * STRIPE_NBMAX);
   const int* rowptr = (const int*)A->rowptr->p;
   const int* col = A->col ? (const int*)A->col->p : nullptr;
+  std::vector<int> nbs(S), cold_cnt(S), blk((size_t)S * STRIPE_NBMAX), hcnt((size_t)S * STRIPE_NBMAX);
   if (S > 0 && m > 0) {
-    hipLaunchKernelGGL(st_count_kernel, dim3(S), dim3(256), 0, c.stream, rowptr, col, (const int*)d_sr0->p,
-                       (int*)d_cnt->p);
-    hip_check(hipGetLastError(), "stripe count");
-  } else if (S > 0) {
-    hip_check(launch_zero(d_cnt->p, sizeof(int) * (size_t)S * NCLS, c.stream), "zero counts");
+    hipLaunchKernelGGL(st_select_kernel, dim3(S), dim3(1024), 0, c.stream, rowptr, col, (const int*)d_sr0->p, nbins,
+                       merged, nb_cap, min_entries, (int*)d_nb->p, (int*)d_blk->p, (int*)d_hc->p, (int*)d_cold->p);
+    hip_check(hipGetLastError(), "stripe block choice");
+    hip_check(hipMemcpyAsync(nbs.data(), d_nb->p, sizeof(int) * S, hipMemcpyDeviceToHost, c.stream), "download");
+    hip_check(hipMemcpyAsync(cold_cnt.data(), d_cold->p, sizeof(int) * S, hipMemcpyDeviceToHost, c.stream),
+              "download");
+    hip_check(hipMemcpyAsync(blk.data(), d_blk->p, sizeof(int) * blk.size(), hipMemcpyDeviceToHost, c.stream),
+              "download");
+    hip_check(hipMemcpyAsync(hcnt.data(), d_hc->p, sizeof(int) * hcnt.size(), hipMemcpyDeviceToHost, c.stream),
+              "download");
   }
-  std::vector<int> cnt((size_t)S * NCLS);
-  if (S > 0)
-    hip_check(hipMemcpyAsync(cnt.data(), d_cnt->p, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost, c.stream),
-              "download counts");
   hip_check(hipStreamSynchronize(c.stream), "sync");
 
-  // LDS blocks of each stripe: leading blocks with enough entries
-  const int nb_cap = std::min<int64_t>(STRIPE_NBMAX, cfg.hot > 0 ? std::max(1, cfg.hot / STRIPE_HB) : STRIPE_NBMAX);
-  const int ncolblk = (int)((A->ncols + STRIPE_HB - 1) / STRIPE_HB);
-  const int min_entries = cfg.long_row > 0 ? cfg.long_row : 1024;
-  std::vector<int> nbs(S);
   std::vector<StripeDesc> desc(S);
   std::vector<int64_t> obase((size_t)S * NCLS, 0);
   std::vector<double> cost(S);
   int64_t hot_total = 0, cold_total = 0, counted = 0;
   for (int s = 0; s < S; ++s) {
-    const int* cs = &cnt[(size_t)s * NCLS];
-    int nb = 0;
-    while (nb < nb_cap && nb < ncolblk && nb < STRIPE_NBMAX && cs[nb] >= min_entries) ++nb;
-    nbs[s] = nb;
+    const int nb = nbs[(size_t)s];
+    if (nb < 0 || nb > nb_cap) fail(GrB_PANIC, "stripe plan: bad block count");
+    const int* bs = &blk[(size_t)s * STRIPE_NBMAX];
+    const int* cs = &hcnt[(size_t)s * STRIPE_NBMAX];
     StripeDesc& d = desc[s];
     std::memset(&d, 0, sizeof(d));
     d.r0 = sr0[s];
@@ -651,6 +740,9 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
     d.hot_base = hot_total;
     int64_t off = 0, hot_e = 0;
     for (int b = 0; b < nb; ++b) {
+      if (bs[b] < 0 || bs[b] >= ncolblk || (b > 0 && bs[b] <= bs[b - 1]))
+        fail(GrB_PANIC, "stripe plan: bad block list");
+      d.blk[b] = bs[b];
       d.seg[b] = (int)off;
       obase[(size_t)s * NCLS + b] = hot_total + off;
       counted += cs[b];
@@ -659,8 +751,7 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
     }
     d.seg[nb] = (int)off;
     hot_total += off;
-    int64_t cold = 0;
-    for (int b = nb; b < NCLS; ++b) cold += cs[b];
+    const int64_t cold = cold_cnt[(size_t)s];
     obase[(size_t)s * NCLS + nb] = cold_total;
     counted += cold;
     d.cold_base = cold_total;
@@ -682,16 +773,14 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
   hip_check(launch_zero(plan.st_hot->p, plan.st_hot->bytes, c.stream), "zero");
   hip_check(launch_zero(plan.st_ccol->p, plan.st_ccol->bytes, c.stream), "zero");
   hip_check(launch_zero(plan.st_crow->p, plan.st_crow->bytes, c.stream), "zero");
-  if (m > 0) {
-    BufP d_nb = dev_alloc(sizeof(int) * (size_t)S);
+  if (m > 0 && S > 0) {
     BufP d_ob = dev_alloc(sizeof(int64_t) * obase.size());
-    hip_check(hipMemcpyAsync(d_nb->p, nbs.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.stream), "upload");
     hip_check(hipMemcpyAsync(d_ob->p, obase.data(), sizeof(int64_t) * obase.size(), hipMemcpyHostToDevice,
                              c.stream),
               "upload");
     hipLaunchKernelGGL(st_partition_kernel, dim3(S), dim3(256), 0, c.stream, rowptr, col, (const int*)d_sr0->p,
-                       (const int*)d_nb->p, (const int64_t*)d_ob->p, (unsigned*)plan.st_hot->p,
-                       (unsigned*)plan.st_ccol->p, (unsigned short*)plan.st_crow->p);
+                       (const int*)d_nb->p, (const int*)d_blk->p, (const int64_t*)d_ob->p,
+                       (unsigned*)plan.st_hot->p, (unsigned*)plan.st_ccol->p, (unsigned short*)plan.st_crow->p);
     hip_check(hipGetLastError(), "stripe partition");
     hip_check(hipStreamSynchronize(c.stream), "sync");
   }

@@ -180,3 +180,99 @@ def test_stripe_plan_only_for_fp32(nonblocking):
         grb.GrM_Matrix_plan_set(g.AT, grb.builtin("GrB_FP64"), stripe_cfg())
     assert e.value.info == -3
     g.free()
+
+
+def _mxv_fp32(grb, A, u):
+    from paper_2509_14211_amd import api
+    t = grb.builtin("GrB_FP32")
+    uv = api.vector_from_tensor(u)
+    w = grb.GrB_Vector_new(t, grb.GrB_Matrix_nrows(A))
+    try:
+        grb.GrB_mxv(w, None, None, grb.builtin("GrB_PLUS_TIMES_SEMIRING_FP32"), A, uv)
+        return api.tensor_from_vector(w, torch.float32)
+    finally:
+        grb.GrB_Vector_free(uv)
+        grb.GrB_Vector_free(w)
+
+
+def _exact(rowptr, col, u):
+    rows = torch.repeat_interleave(torch.arange(rowptr.numel() - 1, device="cuda"),
+                                   (rowptr[1:] - rowptr[:-1]).long())
+    return torch.zeros(rowptr.numel() - 1, dtype=torch.float64, device="cuda").index_add_(
+        0, rows, u[col.long()].double())
+
+
+def test_stripe_loads_the_dense_blocks_of_a_banded_graph(nonblocking, oracle_mod):
+    """Links only to nearby vertices: each stripe's entries sit in the one
+    or two column blocks around its own rows, not in the leading blocks.
+    The layout picks those blocks (so most entries read LDS) and the
+    results are exact on integers and match the oracle per vertex."""
+    from paper_2509_14211_amd import api
+    n = 150000
+    i = np.repeat(np.arange(n), 6)
+    d = np.tile(np.array([-3000, -700, -1, 1, 500, 2500]), n)
+    src = i.astype(np.uint32)
+    dst = ((i + d) % n).astype(np.uint32)
+    g = api.graph_from_edges(n, src, dst)
+    og = oracle_mod.graph_from_edges(n, src, dst)
+    grb = nonblocking
+    t = grb.builtin("GrB_FP32")
+    cfg = stripe_cfg(relabel=0, long_row=256)
+    # integer mxv, bit for bit
+    grb.GrM_set_mode(grb.GrB_BLOCKING)
+    grb.GrM_Matrix_plan_set(g.AT, t, cfg)
+    try:
+        rp, cl = api.csr_of(g.AT)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(3)
+        u = torch.randint(-8, 9, (n,), device="cuda", generator=gen).float()
+        got = _mxv_fp32(grb, g.AT, u).double()
+        assert torch.equal(got, _exact(rp, cl, u))
+    finally:
+        grb.GrM_Matrix_plan_set(g.AT, t, None)
+        grb.GrM_set_mode(grb.GrB_NONBLOCKING)
+    x, it, _ = _run(nonblocking, g, cfg, tol=1e-7)
+    ref = oracle_mod.pagerank(og, D, fixed_iters=it)
+    _check_fp32(x, ref.x)
+    g.free()
+
+
+def test_stripe_with_more_column_blocks_than_the_layout_tells_apart(blocking):
+    """205M columns (16,685 blocks of 12,288, more than the 16,384 the
+    layout counts one by one): blocks from 16,383 on share one bin that is
+    never loaded, so their entries are gathered; a dense low block is still
+    loaded.  Integer operands, exact."""
+    from paper_2509_14211_amd import api
+    grb = blocking
+    nrows, ncols = 16128, 205_000_000
+    hb = 12288
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(9)
+    per = 48
+    # per row: 24 distinct columns in block 3, 12 in blocks >= 16383, 12 anywhere
+    lo = 3 * hb + torch.stack([torch.randperm(hb, device="cuda", generator=gen)[:24] for _ in range(4)])
+    lo = lo[torch.arange(nrows, device="cuda") % 4]
+    hi = 16383 * hb + torch.randint(0, ncols - 16383 * hb, (nrows, 12), device="cuda", generator=gen)
+    anyc = torch.randint(0, ncols, (nrows, 12), device="cuda", generator=gen)
+    cols = torch.cat([lo, hi, anyc], dim=1)
+    cols, _ = torch.sort(cols, dim=1)
+    keep = torch.ones_like(cols, dtype=torch.bool)
+    keep[:, 1:] = cols[:, 1:] != cols[:, :-1]
+    counts = keep.sum(dim=1)
+    rowptr = torch.zeros(nrows + 1, dtype=torch.int32, device="cuda")
+    rowptr[1:] = torch.cumsum(counts, 0).int()
+    col = cols[keep].int().contiguous()
+    assert col.numel() == int(rowptr[-1]) and per * nrows >= col.numel()
+    A = grb.GrB_Matrix_new(grb.builtin("GrB_FP32"), nrows, ncols)
+    t = grb.builtin("GrB_FP32")
+    try:
+        grb.GrM_Matrix_import_CSR(A, rowptr, col, col.numel())
+        u = torch.randint(-8, 9, (ncols,), device="cuda", generator=gen).float()
+        want = _exact(rowptr, col, u)
+        for cfg in (stripe_cfg(relabel=0, long_row=1000), stripe_cfg(relabel=0, long_row=1)):
+            grb.GrM_Matrix_plan_set(A, t, cfg)
+            got = _mxv_fp32(grb, A, u).double()
+            grb.GrM_Matrix_plan_set(A, t, None)
+            assert torch.equal(got, want), cfg
+    finally:
+        grb.GrB_Matrix_free(A)
