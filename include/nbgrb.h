@@ -687,7 +687,7 @@ typedef struct {
   int32_t grid;
   int32_t hot;      /* kernel 1: leading entries of the gathered vector kept in
                        LDS (clamped to what fits); kernel 2: columns a
-                       stripe may hold in LDS (whole blocks of 12288, 0: 32
+                       stripe may hold in LDS (whole blocks of 12288, 0: 63
                        blocks) */
   int32_t relabel;  /* GrM_pagerank: 1 runs on a copy of the matrix with the
                        vertices renumbered by decreasing out-degree (built once

@@ -177,7 +177,7 @@ int wave_hot_max(int type);
 constexpr int STRIPE_BLOCK = 1024;
 constexpr int STRIPE_RMAX = 8064;
 constexpr int STRIPE_HB = 12288;
-constexpr int STRIPE_NBMAX = 32;
+constexpr int STRIPE_NBMAX = 63;  // segment starts 0..nb sit one per lane of a wavefront
 constexpr int STRIPE_K = 8;  // consecutive entries per lane
 constexpr int STRIPE_MAXBLK = 16384;
 
@@ -186,9 +186,9 @@ struct StripeDesc {
   long long hot_base, cold_base;  // first hot word / cold pair of the stripe
   int seg[STRIPE_NBMAX + 1];    // hot segment of LDS block b: [seg[b], seg[b+1]) after hot_base
   int blk[STRIPE_NBMAX];        // column block of LDS block b (ascending)
-  int pad[7];
+  int pad[1];
 };
-static_assert(sizeof(StripeDesc) == 320, "stripe descriptor layout");
+static_assert(sizeof(StripeDesc) == 544, "stripe descriptor layout");
 
 struct StripePlanDev {
   const StripeDesc* desc;

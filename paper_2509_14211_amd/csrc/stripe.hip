@@ -570,7 +570,7 @@ __global__ __launch_bounds__(1024) void st_select_kernel(const int* rowptr, cons
     if (c < min_entries || c == 0) break;
   }
   if (t == 0) {
-    // ascending block order (insertion sort of at most 32)
+    // ascending block order (insertion sort of at most STRIPE_NBMAX)
     for (int i = 1; i < k; ++i) {
       const int b = sb[i], c = sc[i];
       int j = i - 1;
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(256) void st_partition_kernel(const int* rowptr, co
   if (t < NCLS) run[t] = 0;
   if (t < nb) sblk[t] = blk[s * STRIPE_NBMAX + t];
   for (int c0 = e0; c0 < e1; c0 += 256) {
-    if (t < 4 * NCLS) (&wcnt[0][0])[t] = 0;
+    for (int i = t; i < 4 * NCLS; i += 256) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int e = c0 + t;
     const bool ok = e < e1;

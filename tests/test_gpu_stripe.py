@@ -78,13 +78,14 @@ def test_stripe_rmat_matches_oracle(nonblocking, oracle_mod, cfg, scale):
 
 
 def test_stripe_many_blocks_and_cold_entries(nonblocking, oracle_mod):
-    """Scale 19: 524,288 columns = 42.7 blocks of 12,288, so stripes load up
-    to 32 blocks and gather the rest; at least 66 stripes of at most 8064
+    """Scale 19: 524,288 columns = 42.7 blocks of 12,288, so with every
+    block eligible a stripe loads up to 43 of them, and with at most 32
+    (hot cap) it gathers the rest; at least 66 stripes of at most 8064
     rows each."""
     from paper_2509_14211_amd import api
     g = api.rmat_graph(19)
     og = oracle_mod.rmat_graph(19)
-    for cfg in (stripe_cfg(long_row=1), stripe_cfg(relabel=0, long_row=1)):
+    for cfg in (stripe_cfg(long_row=1), stripe_cfg(relabel=0, long_row=1), stripe_cfg(long_row=1, hot=32 * HB)):
         x, it, _ = _run(nonblocking, g, cfg, tol=1e-6)
         ref = oracle_mod.pagerank(og, D, fixed_iters=it)
         _check_fp32(x, ref.x)
