@@ -670,8 +670,10 @@ GrB_Info GrM_pagerank_many(void *X, GrB_Type type, GrM_Multigraph mg, double dam
  * 2^F, F = 62 - ceil(log2(sum |w|)), rounded once to FP32, so
  * they do not depend on the order of accumulation; the truncation of each
  * term to the fixed-point grid adds at most (row length) * 2^-F to a row
- * sum.  lds_entries, lds_rows, chunk and xcd_split are ignored; grid is the
- * number of workgroups (0: one per compute unit).  Matrices with 2^30 or
+ * sum.  chunk 1 reads a stripe's packed entries with the nontemporal cache
+ * hint (any other value: the default policy); lds_entries, lds_rows and
+ * xcd_split are ignored; grid is the number of workgroups (0: one per
+ * compute unit).  Matrices with 2^30 or
  * more columns or 2^31 or more entries run kernel 1 instead.
  * The choice never changes results beyond floating-point reassociation.
  * ---------------------------------------------------------------------- */

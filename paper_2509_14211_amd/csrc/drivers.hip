@@ -592,53 +592,73 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
     // vector and dangling mass define the next pass completely, so column q
     // still ends where a single-vector solve of set q from the start would.
     const size_t vb = type_size(T) * (size_t)n;
-    for (int col = 0; col < pc.k; ++col) {
-      if (!((rest >> col) & 1ull)) continue;
-      const int q = col_set[(size_t)col];
-      GB_Vector_opaque xv{MAGIC_VEC, T, n, nullptr}, tv{MAGIC_VEC, T, n, nullptr}, rv{MAGIC_VEC, T, n, nullptr};
-      NodeP xn = new_node(N_DENSE, T, n, false), tn = new_node(N_DENSE, T, n, false);
-      xn->buf = dev_alloc(vb);
-      tn->buf = dev_alloc(vb);
-      ColumnOutputs one{};
-      one.ld = 1;
-      one.out[col] = xn->buf->p;
-      pc.output(1ull << col, (done_passes & 1) ? (1ull << col) : 0ull, one);
-      hip_check(launch_zero(tn->buf->p, vb, c.stream), "zero");
-      const int ns = seed_ptr[q + 1] - seed_ptr[q];
-      BufP sidx = pc.upload(seed_vtx + seed_ptr[q], sizeof(int) * (size_t)ns);
-      hip_check(launch_scatter_value(tn->buf->p, T, (const int*)sidx->p, ns, 1.0 / (double)ns, c.stream), "seeds");
-      launch_mark(false);
-      xn->done = tn->done = true;
-      set_vec(&xv, xn);
-      set_vec(&tv, tn);
-      int it = 0;
-      double res = 1.0;
-      c.guard = saved_guard;
-      const GrB_Info info = pagerank_impl((GrB_Vector)&rv, &it, &res, AT, outdeg, (GrB_Vector)&tv, damping, tol,
-                                          itermax - done_passes, dangling, (GrB_Vector)&xv, check_every);
-      if (info != GrB_SUCCESS) {
-        set_vec(&xv, nullptr);
-        set_vec(&tv, nullptr);
-        set_vec(&rv, nullptr);
-        fail(info, "ppr_batch: " + api_error());
+    std::vector<int> tcols;
+    for (int col = 0; col < pc.k; ++col)
+      if ((rest >> col) & 1ull) tcols.push_back(col);
+    const int nt = (int)tcols.size();
+    // every tail column's current iterate, in the original numbering, in
+    // one sweep over the operand
+    std::vector<GB_Vector_opaque> xv((size_t)nt, GB_Vector_opaque{MAGIC_VEC, T, n, nullptr});
+    std::vector<GB_Vector_opaque> rv((size_t)nt, GB_Vector_opaque{MAGIC_VEC, T, n, nullptr});
+    auto release = [&]() {
+      for (int i = 0; i < nt; ++i) {
+        set_vec(&xv[(size_t)i], nullptr);
+        set_vec(&rv[(size_t)i], nullptr);
       }
-      materialize(rv.node);
-      require_full(rv.node, "a batched PPR column");
-      ColumnOutputs to{};
-      to.ld = k;
-      to.out[0] = (char*)X + type_size(T) * (size_t)q;
-      hip_check(launch_spmm_columns_out(rv.node->buf->p, rv.node->buf->p, 0, T, nullptr, n, 1, 1ull, to, c.stream),
-                "column out");
+    };
+    try {
+      ColumnOutputs xo{};
+      xo.ld = 1;
+      for (int i = 0; i < nt; ++i) {
+        NodeP xn = new_node(N_DENSE, T, n, false);
+        xn->buf = dev_alloc(vb);
+        xn->done = true;
+        xo.out[tcols[(size_t)i]] = xn->buf->p;
+        set_vec(&xv[(size_t)i], xn);
+      }
+      pc.output(rest, (done_passes & 1) ? rest : 0ull, xo);
+      ColumnInputs ins{};
+      ins.ld = k;
+      for (int i = 0; i < nt; ++i) {
+        const int q = col_set[(size_t)tcols[(size_t)i]];
+        GB_Vector_opaque tv{MAGIC_VEC, T, n, nullptr};
+        NodeP tn = new_node(N_DENSE, T, n, false);
+        tn->buf = dev_alloc(vb);
+        hip_check(launch_zero(tn->buf->p, vb, c.stream), "zero");
+        const int ns = seed_ptr[q + 1] - seed_ptr[q];
+        BufP sidx = pc.upload(seed_vtx + seed_ptr[q], sizeof(int) * (size_t)ns);
+        hip_check(launch_scatter_value(tn->buf->p, T, (const int*)sidx->p, ns, 1.0 / (double)ns, c.stream),
+                  "seeds");
+        launch_mark(false);
+        tn->done = true;
+        set_vec(&tv, tn);
+        int it = 0;
+        double res = 1.0;
+        c.guard = saved_guard;
+        const GrB_Info info = pagerank_impl((GrB_Vector)&rv[(size_t)i], &it, &res, AT, outdeg, (GrB_Vector)&tv,
+                                            damping, tol, itermax - done_passes, dangling,
+                                            (GrB_Vector)&xv[(size_t)i], check_every);
+        set_vec(&tv, nullptr);
+        if (info != GrB_SUCCESS) fail(info, "ppr_batch: " + api_error());
+        set_vec(&xv[(size_t)i], nullptr);  // its start vector is no longer needed
+        materialize(rv[(size_t)i].node);
+        require_full(rv[(size_t)i].node, "a batched PPR column");
+        ins.in[i] = rv[(size_t)i].node->buf->p;
+        ins.dst[i] = q;
+        const bool conv = res <= tol;
+        if (col_iters) col_iters[q] = conv ? done_passes + it : -1;
+        if (col_resid) col_resid[q] = res;
+        max_passes = std::max(max_passes, done_passes + it);
+      }
+      // all tail columns into X in one sweep
+      hip_check(launch_columns_in(ins, nt, T, n, X, c.stream), "columns in");
       launch_mark(false);
-      const bool conv = res <= tol;
-      if (col_iters) col_iters[q] = conv ? done_passes + it : -1;
-      if (col_resid) col_resid[q] = res;
-      max_passes = std::max(max_passes, done_passes + it);
       hip_check(hipStreamSynchronize(c.stream), "sync");
-      set_vec(&xv, nullptr);
-      set_vec(&tv, nullptr);
-      set_vec(&rv, nullptr);
+    } catch (...) {
+      release();
+      throw;
     }
+    release();
   } else {
     // columns that did not converge within itermax (or ran no pass): their
     // current iterate

@@ -205,10 +205,13 @@ struct StripePlanDev {
 // The fused pass over a stripe plan.  wsum_in: sum |w| of the gathered
 // vector (sets the fixed-point scale; a non-finite value makes every row sum
 // NaN).  wsum_out (may be null): receives sum |w'| of the pre-scaled copy
-// written.  grid must be the plan's workgroup count.
+// written.  grid must be the plan's workgroup count.  nt_streams: the
+// packed entries (LDS-block words, gathered columns and rows) are read with
+// the nontemporal hint, which keeps them from displacing the gathered
+// vector in the caches.
 hipError_t launch_fused_stripe_f32(const StripePlanDev& p, const FusedArgs<float>& a, const double* wsum_in,
-                                   double* wsum_out, const FusedScratch& scr, int grid, const GuardDev* guard,
-                                   hipStream_t s);
+                                   double* wsum_out, const FusedScratch& scr, int grid, bool nt_streams,
+                                   const GuardDev* guard, hipStream_t s);
 // *out = sum |x[i]| in FP64 (deterministic).
 hipError_t launch_abssum_f32(const float* x, int64_t n, double* out, RedScratch scr, const GuardDev* guard,
                              hipStream_t s);
@@ -312,6 +315,14 @@ struct ColumnOutputs {
 };
 hipError_t launch_spmm_columns_out(const void* in0, const void* in1, uint64_t from1, int type, const int* idx,
                                    int64_t n, int k, uint64_t cols, const ColumnOutputs& outs, hipStream_t s);
+// Vector c < nc (n values at ins.in[c]) into column ins.dst[c] of the
+// n-row array `out` whose rows are ins.ld values apart (0 <= dst < ld).
+struct ColumnInputs {
+  const void* in[64];
+  int64_t dst[64];
+  int64_t ld;
+};
+hipError_t launch_columns_in(const ColumnInputs& ins, int nc, int type, int64_t n, void* out, hipStream_t s);
 // New column j < k2 of the n x k2 arrays x2, w2 = column map.c[j] of the
 // n x k arrays x, w (map.c[j] < 0: zeros); d2[j] = d[map.c[j]] (0 when
 // empty); hit[j] = -1 for a mapped column, 0 (frozen) otherwise, j < 64.

@@ -300,10 +300,11 @@ std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
   const bool stripe = cfg.kernel == K_STRIPE;
   if (stripe) {
     // geometry is fixed by the kernel; hot caps the LDS blocks, long_row is
-    // the fewest entries that make a stripe load a block
+    // the fewest entries that make a stripe load a block, chunk 1 reads the
+    // packed entries with the nontemporal hint
     cfg.lds_entries = 0;
     cfg.lds_rows = 0;
-    cfg.chunk = 0;
+    cfg.chunk = cfg.chunk == 1 ? 1 : 0;
     cfg.xcd = 0;
     if (cfg.hot <= 0 || cfg.hot > STRIPE_NBMAX * STRIPE_HB) cfg.hot = STRIPE_NBMAX * STRIPE_HB;
     cfg.hot = std::max(1, cfg.hot / STRIPE_HB) * STRIPE_HB;
@@ -523,7 +524,8 @@ static bool run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
         // the pass timer covers the fused kernel alone
         if (timed) hip_check(hipEventRecord(e0, c.stream), "event record");
       }
-      e = launch_fused_stripe_f32(plan->st_dev, a, wsum_in, f.wsum_out, scr, plan->cfg.grid, c.guard, c.stream);
+      e = launch_fused_stripe_f32(plan->st_dev, a, wsum_in, f.wsum_out, scr, plan->cfg.grid, plan->cfg.chunk == 1,
+                                  c.guard, c.stream);
       wrote_wsum = f.wsum_out != nullptr && a.w_out != nullptr;
     } else {
       e = wave ? launch_fused_wave_f32(plan->dev, a, scr, grid, plan->cfg.hot, c.guard, c.stream)

@@ -507,6 +507,24 @@ __global__ __launch_bounds__(256) void columns_out_kernel(const T* __restrict__ 
   }
 }
 
+// The reverse of columns_out: vector c < nc (n values) into column
+// ins.dst[c] of the n-row array `out` (row stride ins.ld).  64 rows per
+// workgroup go through LDS, so each vector is read in whole lines.
+template <typename T>
+__global__ __launch_bounds__(256) void columns_in_kernel(ColumnInputs ins, int nc, int64_t n, T* __restrict__ out) {
+  __shared__ T tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  for (int q = threadIdx.x; q < 64 * 64; q += 256) {
+    const int c = q >> 6, r = q & 63;
+    if (c < nc && r0 + r < n) tile[r][c] = ((const T*)ins.in[c])[r0 + r];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 64 * 64; q += 256) {
+    const int r = q >> 6, c = q & 63;
+    if (c < nc && r0 + r < n) out[(r0 + r) * ins.ld + ins.dst[c]] = tile[r][c];
+  }
+}
+
 // Columns map[j] (j < k2; map[j] < 0: an empty column) of the n x k arrays
 // x, w into the n x k2 arrays x2, w2, with their dangling masses; hit of
 // the new columns: -1 for a live one, 0 (frozen) for an empty one.  One
@@ -611,6 +629,19 @@ hipError_t launch_spmm_columns_out(const void* in0, const void* in1, uint64_t fr
   else
     hipLaunchKernelGGL(columns_out_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)in0,
                        (const double*)in1, from1, idx, n, k, cols, outs);
+  return hipGetLastError();
+}
+
+hipError_t launch_columns_in(const ColumnInputs& ins, int nc, int type, int64_t n, void* out, hipStream_t s) {
+  if (n <= 0 || nc <= 0) return hipSuccess;
+  if (nc > 64 || ins.ld < 1) return hipErrorInvalidValue;
+  for (int c = 0; c < nc; ++c)
+    if (!ins.in[c] || ins.dst[c] < 0 || ins.dst[c] >= ins.ld) return hipErrorInvalidValue;
+  const int g = (int)((n + 63) / 64);
+  if (type == T_FP32)
+    hipLaunchKernelGGL(columns_in_kernel<float>, dim3(g), dim3(256), 0, s, ins, nc, n, (float*)out);
+  else
+    hipLaunchKernelGGL(columns_in_kernel<double>, dim3(g), dim3(256), 0, s, ins, nc, n, (double*)out);
   return hipGetLastError();
 }
 

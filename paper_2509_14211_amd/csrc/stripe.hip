@@ -194,13 +194,14 @@ __device__ __forceinline__ void hot_settle(int segv, int nb, int h, HotCursor& c
   }
 }
 
+template <int SP>
 __device__ __forceinline__ void hot_words(const unsigned* hot_seg0, int segv, const HotCursor& c, int lane,
                                           uint4& wa, uint4& wb) {
   const int sb0 = seg_at(segv, c.b), sb1 = seg_at(segv, c.b + 1);
   const __amdgpu_buffer_rsrc_t rh = buf_rsrc(hot_seg0 + sb0, (unsigned)(sb1 - sb0) * 4u);
   const unsigned e = (unsigned)(c.j * CHUNK + lane * STRIPE_K);
-  wa = buf_load<uint4>(rh, e * 4u);
-  wb = buf_load<uint4>(rh, e * 4u + 16u);
+  wa = buf_load<uint4, SP>(rh, e * 4u);
+  wb = buf_load<uint4, SP>(rh, e * 4u + 16u);
 }
 
 // Registers of one chunk of gathered entries: column indices, rows in the
@@ -212,12 +213,13 @@ struct ColdRegs {
 
 // Indices of chunk `ch` (past the end the loads return zeros: column 0,
 // row slot 0).
+template <int SP>
 __device__ __forceinline__ void cold_indices(__amdgpu_buffer_rsrc_t rcc, __amdgpu_buffer_rsrc_t rcr, int ch,
                                              int lane, ColdRegs& R) {
   const unsigned e = (unsigned)(ch * CHUNK + lane * STRIPE_K);
-  R.ca = buf_load<uint4>(rcc, e * 4u);
-  R.cb = buf_load<uint4>(rcc, e * 4u + 16u);
-  R.rr = buf_load<uint4>(rcr, e * 2u);
+  R.ca = buf_load<uint4, SP>(rcc, e * 4u);
+  R.cb = buf_load<uint4, SP>(rcc, e * 4u + 16u);
+  R.rr = buf_load<uint4, SP>(rcr, e * 2u);
 }
 
 __device__ __forceinline__ void cold_gather(__amdgpu_buffer_rsrc_t rw, ColdRegs& R) {
@@ -243,6 +245,7 @@ __device__ __forceinline__ void cold_add(unsigned long long* acc, const ColdRegs
 // buffer k mod 2 while block k+2 is in flight into registers; block k+1,
 // loaded during the previous phase, goes into the other buffer at the end
 // of the phase (one workgroup barrier per block).
+template <int SP>
 __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDev p, FusedArgs<float> a,
                                                                     const double* wsum_in, double* wsum_out,
                                                                     FusedScratch scr, const GuardDev* guard) {
@@ -325,11 +328,11 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
       const int nk = ncold > wv ? (ncold - wv + NW - 1) / NW : 0;
       if (nk > 0) {
         ColdRegs X, Y, Z;
-        cold_indices(rcc, rcr, wv, lane, X);
-        cold_indices(rcc, rcr, wv + NW, lane, Y);
+        cold_indices<SP>(rcc, rcr, wv, lane, X);
+        cold_indices<SP>(rcc, rcr, wv + NW, lane, Y);
         cold_gather(rw, X);
         auto step = [&](int i, ColdRegs& P, ColdRegs& G, ColdRegs& F) {
-          cold_indices(rcc, rcr, wv + (i + 2) * NW, lane, F);
+          cold_indices<SP>(rcc, rcr, wv + (i + 2) * NW, lane, F);
           cold_gather(rw, G);
           cold_add(acc, P, kshift);
         };
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
     HotCursor cur{0, wv};
     hot_settle(segv, nb, wv, cur);
     uint4 wa = make_uint4(0, 0, 0, 0), wb = make_uint4(0, 0, 0, 0);
-    if (cur.b < nb) hot_words(hot_seg0, segv, cur, lane, wa, wb);
+    if (cur.b < nb) hot_words<SP>(hot_seg0, segv, cur, lane, wa, wb);
     for (int b = 0; b < nb; ++b) {
       // block kblk + 2 of the sequence into the free register set
       const bool more2 = have1 && next_block(p, bsi, s_end, bb, bsi, bb, bcol);
@@ -363,7 +366,7 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
         const uint4 ca = wa, cb = wb;
         HotCursor nx{cur.b, cur.j + NW};
         hot_settle(segv, nb, wv, nx);
-        if (nx.b < nb) hot_words(hot_seg0, segv, nx, lane, wa, wb);
+        if (nx.b < nb) hot_words<SP>(hot_seg0, segv, nx, lane, wa, wb);
         const unsigned wd[STRIPE_K] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
         int row[STRIPE_K];
         float v[STRIPE_K];
@@ -463,11 +466,15 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
 }
 
 hipError_t launch_fused_stripe_f32(const StripePlanDev& p, const FusedArgs<float>& a, const double* wsum_in,
-                                   double* wsum_out, const FusedScratch& scr, int grid, const GuardDev* guard,
-                                   hipStream_t s) {
+                                   double* wsum_out, const FusedScratch& scr, int grid, bool nt_streams,
+                                   const GuardDev* guard, hipStream_t s) {
   if (grid <= 0 || !wsum_in) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fused_stripe_kernel, dim3(grid), dim3(STRIPE_BLOCK), 0, s, p, a, wsum_in, wsum_out, scr,
-                     guard);
+  if (nt_streams)
+    hipLaunchKernelGGL(fused_stripe_kernel<CP_NT>, dim3(grid), dim3(STRIPE_BLOCK), 0, s, p, a, wsum_in, wsum_out,
+                       scr, guard);
+  else
+    hipLaunchKernelGGL(fused_stripe_kernel<0>, dim3(grid), dim3(STRIPE_BLOCK), 0, s, p, a, wsum_in, wsum_out, scr,
+                       guard);
   return hipGetLastError();
 }
 

@@ -18,8 +18,8 @@ D = 0.85
 HB = 12288
 
 
-def stripe_cfg(relabel=1, long_row=1024, hot=0, grid=0):
-    return dict(kernel=2, lds_entries=0, lds_rows=0, long_row=long_row, chunk=0, grid=grid, hot=hot,
+def stripe_cfg(relabel=1, long_row=1024, hot=0, grid=0, chunk=0):
+    return dict(kernel=2, lds_entries=0, lds_rows=0, long_row=long_row, chunk=chunk, grid=grid, hot=hot,
                 relabel=relabel)
 
 
@@ -30,11 +30,12 @@ CONFIGS = [
     stripe_cfg(long_row=1 << 30),         # no block is loaded: every entry gathered
     stripe_cfg(hot=HB, grid=3),           # one LDS block at most, three workgroups
     stripe_cfg(hot=2 * HB, long_row=64, grid=13),
+    stripe_cfg(chunk=1),                  # packed entries read with the nontemporal hint
 ]
 
 
 def _ids(c):
-    return "r%d-l%d-h%d-g%d" % (c["relabel"], c["long_row"], c["hot"], c["grid"])
+    return "r%d-l%d-h%d-g%d-c%d" % (c["relabel"], c["long_row"], c["hot"], c["grid"], c["chunk"])
 
 
 def _run(grb, g, cfg, dtype=torch.float32, **kw):
