@@ -89,7 +89,8 @@ def recorded_traffic(kind: int):
         return None
 
 
-def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float", min_write_kib: float = 0.0) -> None:
+def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float", min_write_kib: float = 0.0,
+                      min_launch_us: float = 20.0) -> None:
     """Kernel statistics (from --kernel-trace --stats) and per-dispatch PMC
     counters (from --pmc runs) found under the given directories, as
     Markdown tables; with FETCH_SIZE and WRITE_SIZE runs that include the
@@ -97,7 +98,9 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float", min
     With min_write_kib, only the traffic kernel's launches whose WRITE_SIZE
     reaches it are counted (matched by launch order between the two runs):
     the fused passes, when plain mxv launches of the same kernel (blocking
-    mode) share the profile."""
+    mode) share the profile.  min_launch_us: the trace table also averages
+    the launches at least this long (the passes of the larger graph when
+    two graphs share a profile)."""
     import collections
     import csv
     import glob
@@ -119,11 +122,11 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float", min
             for r in csv.DictReader(open(p)):
                 dur[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
             print("### launches of the fused kernels (%s)\n" % os.path.basename(p))
-            print("| kernel | launches | mean (us) | launches > 20 us | their mean (us) |")
+            print("| kernel | launches | mean (us) | launches > %g us | their mean (us) |" % min_launch_us)
             print("|---|---|---|---|---|")
             for k, v in dur.items():
                 if "fused" in k or traffic_kernel in k:
-                    act = [x for x in v if x > 20.0]
+                    act = [x for x in v if x > min_launch_us]
                     print("| %s | %d | %.2f | %d | %.2f |" % (k[:90], len(v), sum(v) / len(v), len(act),
                                                             sum(act) / max(len(act), 1)))
             print()
@@ -200,11 +203,13 @@ def main():
                     help="kernel (name substring) whose calibrated traffic --summarize-rocprof reports")
     ap.add_argument("--min-write-kib", type=float, default=0.0,
                     help="with --summarize-rocprof: count only traffic-kernel launches writing at least this")
+    ap.add_argument("--min-launch-us", type=float, default=20.0,
+                    help="with --summarize-rocprof: also average the fused launches at least this long")
     ap.add_argument("--summarize-rocprof", metavar="DIR", nargs="+",
                     help="print a text summary of the rocprofv3 CSV files under the DIRs and exit")
     args = ap.parse_args()
     if args.summarize_rocprof:
-        summarize_rocprof(args.summarize_rocprof, args.traffic_kernel, args.min_write_kib)
+        summarize_rocprof(args.summarize_rocprof, args.traffic_kernel, args.min_write_kib, args.min_launch_us)
         return
 
     legs = {"blocking", "m0", "ppr", "many", "fusion", "bfs", "scale25", "web", "warm"} if args.legs == "all" else (
