@@ -52,8 +52,9 @@ FUSED_KERNELS = {
     0: ("fused_pr_kernel<float, ...>", None, ("kernels.hip",)),
     1: ("fused_wave_kernel<float, ...>", "fused_wave_kernel_rmat22.md", ("kernels.hip",)),
     2: ("fused_stripe_kernel", "fused_stripe_kernel_rmat22.md", ("stripe.hip",)),
+    3: ("cold_fill_kernel+fused_stripe_kernel", "fused_stripe_kernel_twophase_rmat22.md", ("stripe.hip",)),
 }
-TRAFFIC_KERNELS = {"fused_wave_kernel<float": 1, "fused_stripe_kernel": 2}
+TRAFFIC_KERNELS = {"fused_wave_kernel<float": 1, "fused_stripe_kernel": 2, "cold_fill_kernel+fused_stripe_kernel": 3}
 
 
 def kernel_source_sha(kind: int = 1) -> str:
@@ -104,6 +105,7 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float", min
     import collections
     import csv
     import glob
+    parts = traffic_kernel.split("+")  # a pass of several kernels: their traffic adds up
     counters = collections.defaultdict(list)
     for d in dirs:
         stats = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
@@ -125,7 +127,7 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float", min
             print("| kernel | launches | mean (us) | launches > %g us | their mean (us) |" % min_launch_us)
             print("|---|---|---|---|---|")
             for k, v in dur.items():
-                if "fused" in k or traffic_kernel in k:
+                if "fused" in k or any(part in k for part in parts):
                     act = [x for x in v if x > min_launch_us]
                     print("| %s | %d | %.2f | %d | %.2f |" % (k[:90], len(v), sum(v) / len(v), len(act),
                                                             sum(act) / max(len(act), 1)))
@@ -139,51 +141,58 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float", min
             print("| kernel | counter | dispatches | mean | max |")
             print("|---|---|---|---|---|")
             for (k, c), v in sorted(vals.items()):
-                if "fused" in k or "stream_copy" in k or traffic_kernel in k:
+                if "fused" in k or "stream_copy" in k or any(part in k for part in parts):
                     print("| %s | %s | %d | %.1f | %.1f |" % (k[:90], c, len(v), sum(v) / len(v), max(v)))
                     counters[(k, c)] = v
             print()
     copy = [k for (k, c) in counters if "stream_copy" in k]
-    fused = sorted({k for (k, c) in counters if traffic_kernel in k})
-    if copy and fused:
-        ck = copy[0]
-        f_copy = sum(counters[(ck, "FETCH_SIZE")]) / len(counters[(ck, "FETCH_SIZE")])
-        w_copy = sum(counters[(ck, "WRITE_SIZE")]) / len(counters[(ck, "WRITE_SIZE")])
-        f_scale = COPY_BYTES / (f_copy * 1024.0)
-        w_scale = COPY_BYTES / (w_copy * 1024.0)
+    if not copy:
+        return
+    ck = copy[0]
+    f_copy = sum(counters[(ck, "FETCH_SIZE")]) / max(len(counters[(ck, "FETCH_SIZE")]), 1)
+    w_copy = sum(counters[(ck, "WRITE_SIZE")]) / max(len(counters[(ck, "WRITE_SIZE")]), 1)
+    if not f_copy or not w_copy:
+        return
+    f_scale = COPY_BYTES / (f_copy * 1024.0)
+    w_scale = COPY_BYTES / (w_copy * 1024.0)
+    picked = []
+    for part in parts:
         # the matching kernel (template instance) with the most launches
         # that pass the write filter
         best = None
-        for k in fused:
+        for k in sorted({k for (k, c) in counters if part in k}):
             fv, wv = counters.get((k, "FETCH_SIZE"), []), counters.get((k, "WRITE_SIZE"), [])
             if not fv or len(fv) != len(wv):
                 continue
-            keep = [i for i, w in enumerate(wv) if w >= min_write_kib]
+            keep = [i for i, w in enumerate(wv) if w >= min_write_kib] if part == parts[-1] else list(
+                range(len(wv)))
             if keep and (best is None or len(keep) > len(best[3])):
                 best = (k, fv, wv, keep)
         if best is None:
-            print("### calibrated traffic of %s: no launch passes the filters\n" % traffic_kernel)
+            print("### calibrated traffic of %s: no launch of %s passes the filters\n" % (traffic_kernel, part))
             return
-        k, fv, wv, keep = best
+        picked.append(best)
+    print("### calibrated traffic of %s\n" % traffic_kernel)
+    print("The copy probe reads and writes %d bytes per launch; its counters give the scale of each "
+          "counter (bytes per KiB reported).\n" % COPY_BYTES)
+    print("- copy_fetch_kib: %.1f" % f_copy)
+    print("- copy_write_kib: %.1f" % w_copy)
+    print("- fetch_scale: %.4f" % (f_scale * 1.0))
+    print("- write_scale: %.4f" % (w_scale * 1.0))
+    traffic = 0.0
+    for k, fv, wv, keep in picked:
         f_k = sum(fv[i] for i in keep) / len(keep)
         w_k = sum(wv[i] for i in keep) / len(keep)
-        traffic = f_k * 1024.0 * f_scale + w_k * 1024.0 * w_scale
-        print("### calibrated traffic of %s\n" % traffic_kernel)
-        print("The copy probe reads and writes %d bytes per launch; its counters give the scale of each "
-              "counter (bytes per KiB reported).\n" % COPY_BYTES)
-        print("- copy_fetch_kib: %.1f" % f_copy)
-        print("- copy_write_kib: %.1f" % w_copy)
-        print("- fetch_scale: %.4f" % (f_scale * 1.0))
-        print("- write_scale: %.4f" % (w_scale * 1.0))
+        traffic += f_k * 1024.0 * f_scale + w_k * 1024.0 * w_scale
         print("- kernel: %s" % k[:90])
         print("- kernel_fetch_kib_per_launch: %.1f" % f_k)
         print("- kernel_write_kib_per_launch: %.1f" % w_k)
         if len(keep) != len(wv):
             print("- launches_counted: %d of %d (WRITE_SIZE >= %.0f KiB)" % (len(keep), len(wv), min_write_kib))
-        print("- traffic_bytes_per_launch: %d" % int(round(traffic)))
-        if traffic_kernel in TRAFFIC_KERNELS:
-            print("- source_sha256: %s" % kernel_source_sha(TRAFFIC_KERNELS[traffic_kernel]))
-        print()
+    print("- traffic_bytes_per_launch: %d" % int(round(traffic)))
+    if traffic_kernel in TRAFFIC_KERNELS:
+        print("- source_sha256: %s" % kernel_source_sha(TRAFFIC_KERNELS[traffic_kernel]))
+    print()
 
 
 def main():

@@ -648,7 +648,8 @@ GrB_Info GrM_pagerank_many(void *X, GrB_Type type, GrM_Multigraph mg, double dam
  * host (the analogue of the paper's compiled-kernel cache keyed by a method
  * signature, Section III-C):
  *   kernel       0: one workgroup per tile; 1: one wavefront per tile;
- *                2: stripes of rows (kernel 2 below)
+ *                2: stripes of rows (kernel 2 below); 3: the same stripes
+ *                in two phases (kernel 3 below)
  *   lds_entries  entries a tile stages in LDS (kernel 0: 1024, 2048 or 4096;
  *                kernel 1: 512)
  *   lds_rows     rows per tile (kernel 0: 512 with 1024 entries, else 1024;
@@ -675,22 +676,29 @@ GrB_Info GrM_pagerank_many(void *X, GrB_Type type, GrM_Multigraph mg, double dam
  * xcd_split are ignored; grid is the number of workgroups (0: one per
  * compute unit).  Matrices with 2^30 or
  * more columns or 2^31 or more entries run kernel 1 instead.
+ * Kernel 3 is kernel 2 with the gathers replaced by a first phase: a list
+ * of the stripes' other entries ordered by column block streams each block
+ * of the vector through LDS and writes every entry's value into its slot,
+ * and the pass then reads those values in sequence.  Same parameters, same
+ * exact sums (bit-identical results to kernel 2), two launches per pass,
+ * and 10 more bytes per gathered entry held with the plan (its slot and
+ * its column within the block, in place of its column).
  * The choice never changes results beyond floating-point reassociation.
  * ---------------------------------------------------------------------- */
 typedef struct {
   int32_t kernel;   /* 0: workgroup tiles; 1: wavefront tiles (lds_entries 512,
                        lds_rows 256, 1024-thread workgroups); 2: row stripes
                        with their densest column blocks in LDS (FP32 only;
-                       see below) */
+                       see below); 3: kernel 2 in two phases */
   int32_t lds_entries;
   int32_t lds_rows;
   int32_t long_row;
   int32_t chunk;
   int32_t grid;
   int32_t hot;      /* kernel 1: leading entries of the gathered vector kept in
-                       LDS (clamped to what fits); kernel 2: columns a
-                       stripe may hold in LDS (whole blocks of 12288, 0: 63
-                       blocks) */
+                       LDS (clamped to what fits); kernels 2 and 3: columns
+                       a stripe may hold in LDS (whole blocks of 12288, 0:
+                       63 blocks) */
   int32_t relabel;  /* GrM_pagerank: 1 runs on a copy of the matrix with the
                        vertices renumbered by decreasing out-degree (built once
                        and cached with the matrix), so the most gathered values

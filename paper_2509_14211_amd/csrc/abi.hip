@@ -1034,9 +1034,9 @@ GrB_Info GrM_Vector_reduce_masked_Scalar(GrB_Scalar s, GrB_Vector mask, GrB_Mono
 // ------------------------------------------------------------ plans
 
 static bool plan_geometry_ok(const GrM_PlanConfig& c, int type) {
-  if (c.kernel != K_BLOCK && c.kernel != K_WAVE && c.kernel != K_STRIPE) return false;
+  if (c.kernel != K_BLOCK && c.kernel != K_WAVE && !is_stripe(c.kernel)) return false;
   if (c.hot < 0 || (c.relabel != 0 && c.relabel != 1) || (c.xcd_split != 0 && c.xcd_split != 1)) return false;
-  if (c.kernel == K_STRIPE)  // fixed geometry; FP32 ranks only
+  if (is_stripe(c.kernel))  // fixed geometry; FP32 ranks only
     return type == T_FP32 && c.long_row >= 0 && c.grid >= 0 && c.grid <= (1 << 20);
   const bool lds_ok = c.kernel == K_WAVE
                           ? (c.lds_entries == WAVE_TILE_ENTRIES && c.lds_rows == WAVE_TILE_ROWS)

@@ -121,6 +121,13 @@ GrB_Info GrM_autotune_pagerank(GrM_PlanConfig* chosen, double* us_per_pass, GrB_
         // past the L2 of all XCDs (32 MiB of gathered values), also with the
         // packed entries read nontemporally
         if (A->ncols * 4 > ((int64_t)32 << 20)) cands.push_back({2, 0, 0, 1024, 1, 0, 0, relabel, 0});
+        // two-phase: the entries outside the LDS blocks are filled by a
+        // streaming phase instead of gathered
+        cands.push_back({3, 0, 0, 1024, 0, 0, 0, relabel, 0});
+        cands.push_back({3, 0, 0, 1024, 1, 0, 0, relabel, 0});
+        cands.push_back({3, 0, 0, 2048, 0, 0, 0, relabel, 0});
+        cands.push_back({3, 0, 0, 2048, 1, 0, 0, relabel, 0});
+        cands.push_back({3, 0, 0, 4096, 0, 0, 0, relabel, 0});
       }
     }
     // Time k1 and k2 fused passes in one batch each (tol 0, no early stop);

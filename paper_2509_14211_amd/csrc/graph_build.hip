@@ -268,6 +268,21 @@ hipError_t degree_order(int64_t n, const int* col, int64_t nnz, int* order, int*
   return hipStreamSynchronize(s);  // scoped temporaries are released on return
 }
 
+hipError_t sort_pairs_u64_u16(const uint64_t* keys_in, uint64_t* keys_out, const uint16_t* vals_in,
+                              uint16_t* vals_out, int64_t n, unsigned end_bit, AllocFn alloc,
+                              ReleaseFn release, void* actx, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  size_t tb = 0;
+  hipError_t e = rocprim::radix_sort_pairs(nullptr, tb, keys_in, keys_out, vals_in, vals_out, (size_t)n, 0u,
+                                           end_bit, s);
+  if (e != hipSuccess) return e;
+  Scoped tmp(alloc, release, actx, tb + 256);
+  if (!tmp.ok(1)) return hipErrorOutOfMemory;
+  e = rocprim::radix_sort_pairs(tmp.p, tb, keys_in, keys_out, vals_in, vals_out, (size_t)n, 0u, end_bit, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);  // the scoped temporary is released on return
+}
+
 hipError_t permute_csr(int64_t n, const int* rowptr, const int* col, int64_t nnz, const int* inv,
                        int* rowptr2, int* col2, AllocFn alloc, ReleaseFn release, void* actx,
                        hipStream_t s) {

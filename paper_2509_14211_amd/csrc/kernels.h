@@ -193,7 +193,8 @@ static_assert(sizeof(StripeDesc) == 544, "stripe descriptor layout");
 struct StripePlanDev {
   const StripeDesc* desc;
   const unsigned* hot;
-  const unsigned* cold_col;
+  const unsigned* cold_col;       // gathered plan: column of each gathered entry
+  const float* cold_val;          // two-phase plan: its value, filled before the pass
   const unsigned short* cold_row;
   const int* wg_off;   // workgroup g runs wg_list[wg_off[g] .. wg_off[g+1])
   const int* wg_list;
@@ -202,6 +203,26 @@ struct StripePlanDev {
   int maxlen;          // longest row
 };
 
+// Two-phase stripe plan: the stripes' gathered entries, listed by column
+// block and then by their slot in the stripes' arrays.  Chunk c covers list
+// entries [start, end) of column block blk; entry e's value is
+// w[blk * STRIPE_HB + src[e]] and goes to val[pos[e]].
+struct ColdChunk {
+  int blk;
+  unsigned start, end, pad;
+};
+struct ColdFillDev {
+  const unsigned* pos;
+  const unsigned short* src;
+  const ColdChunk* chunk;
+  float* val;
+  int nchunks;
+};
+// Fills val for the pass that gathers w (ncols values).  Skipped when the
+// guard is inactive.
+hipError_t launch_cold_fill_f32(const ColdFillDev& f, const float* w, int ncols, const GuardDev* guard,
+                                hipStream_t s);
+
 // The fused pass over a stripe plan.  wsum_in: sum |w| of the gathered
 // vector (sets the fixed-point scale; a non-finite value makes every row sum
 // NaN).  wsum_out (may be null): receives sum |w'| of the pre-scaled copy
@@ -209,9 +230,11 @@ struct StripePlanDev {
 // packed entries (LDS-block words, gathered columns and rows) are read with
 // the nontemporal hint, which keeps them from displacing the gathered
 // vector in the caches.
+// prefilled: the plan is two-phase (values of the gathered entries are
+// read from p.cold_val, filled by launch_cold_fill_f32 for this pass).
 hipError_t launch_fused_stripe_f32(const StripePlanDev& p, const FusedArgs<float>& a, const double* wsum_in,
                                    double* wsum_out, const FusedScratch& scr, int grid, bool nt_streams,
-                                   const GuardDev* guard, hipStream_t s);
+                                   bool prefilled, const GuardDev* guard, hipStream_t s);
 // *out = sum |x[i]| in FP64 (deterministic).
 hipError_t launch_abssum_f32(const float* x, int64_t n, double* out, RedScratch scr, const GuardDev* guard,
                              hipStream_t s);
@@ -409,6 +432,11 @@ hipError_t degree_order(int64_t n, const int* col, int64_t nnz, int* order, int*
 hipError_t permute_csr(int64_t n, const int* rowptr, const int* col, int64_t nnz, const int* inv,
                        int* rowptr2, int* col2, AllocFn alloc, ReleaseFn release, void* actx,
                        hipStream_t s);
+// Sorts n (key, value) pairs by key bits [0, end_bit) (stable); the inputs
+// are left as they were.  Synchronises `s`.
+hipError_t sort_pairs_u64_u16(const uint64_t* keys_in, uint64_t* keys_out, const uint16_t* vals_in,
+                              uint16_t* vals_out, int64_t n, unsigned end_bit, AllocFn alloc,
+                              ReleaseFn release, void* actx, hipStream_t s);
 // out[k] = in[idx[k]] for k < n, storage type `type`.
 hipError_t launch_permute(const void* in, int type, const int* idx, void* out, int64_t n, hipStream_t s);
 

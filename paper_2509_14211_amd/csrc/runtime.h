@@ -76,7 +76,8 @@ struct MatData {
 };
 
 // Kernel family of a plan.
-enum KernelKind : int { K_BLOCK = 0, K_WAVE = 1, K_STRIPE = 2 };
+enum KernelKind : int { K_BLOCK = 0, K_WAVE = 1, K_STRIPE = 2, K_STRIPE2 = 3 };
+inline bool is_stripe(int kernel) { return kernel == K_STRIPE || kernel == K_STRIPE2; }
 
 // Tile plan of one matrix for the row-parallel kernels.
 struct PlanConfig {
@@ -99,11 +100,15 @@ struct Plan {
   int nstream = 0, nlong = 0, nchunk = 0;
   BufP tiles, hubs, hub_sum, hub_cnt, hub_red;
   TilePlanDev dev{};
-  // stripe plan (K_STRIPE)
+  // stripe plan (K_STRIPE, K_STRIPE2)
   BufP st_desc, st_hot, st_ccol, st_crow, st_wgoff, st_wglist, st_wgsum, st_mass;
   int st_nstripes = 0;
   int64_t st_hot_entries = 0, st_cold_entries = 0;  // padded
   StripePlanDev st_dev{};
+  // two-phase stripe plan (K_STRIPE2): the gathered entries' values, and
+  // the list that fills them block by block
+  BufP st_cval, st_papos, st_pasrc, st_pachunk;
+  ColdFillDev st_fill{};
 };
 
 // Builds the stripe layout of A into plan (plan.cfg set; rp = A's row

@@ -285,7 +285,7 @@ std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
     cfg.grid = 0;
     cfg.hot = 0;
   }
-  if (cfg.kernel == K_STRIPE && (A->ncols >= ((int64_t)1 << 30) || A->nnz >= ((int64_t)1 << 31))) {
+  if (is_stripe(cfg.kernel) && (A->ncols >= ((int64_t)1 << 30) || A->nnz >= ((int64_t)1 << 31))) {
     // beyond the stripe layout's 32-bit offsets: the wave plan
     cfg.kernel = K_WAVE;
     cfg.hot = wave_hot_max(T_FP32);
@@ -297,7 +297,7 @@ std::shared_ptr<Plan> get_plan(const MatP& A, const PlanConfig& cfg0) {
     cfg.lds_entries = WAVE_TILE_ENTRIES;
     cfg.lds_rows = WAVE_TILE_ROWS;
   }
-  const bool stripe = cfg.kernel == K_STRIPE;
+  const bool stripe = is_stripe(cfg.kernel);
   if (stripe) {
     // geometry is fixed by the kernel; hot caps the LDS blocks, long_row is
     // the fewest entries that make a stripe load a block, chunk 1 reads the
@@ -451,7 +451,7 @@ static hipEvent_t pooled_event() {
 static bool run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_override = nullptr) {
   Ctx& c = g_ctx;
   PlanConfig cfg = cfg_override ? *cfg_override : default_plan_config(A, f.type);
-  if (cfg.kernel == K_STRIPE && f.type != T_FP32) {
+  if (is_stripe(cfg.kernel) && f.type != T_FP32) {
     // the stripe kernel's fixed-point sums serve FP32 ranks only
     cfg.kernel = K_WAVE;
     cfg.hot = wave_hot_max(f.type);
@@ -460,7 +460,7 @@ static bool run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
     cfg.grid = 0;
   }
   auto plan = get_plan(A, cfg);
-  const bool stripe = plan->cfg.kernel == K_STRIPE;
+  const bool stripe = is_stripe(plan->cfg.kernel);
   if (!stripe) {
     // the hot slice is w[0, hot): never more than the gathered vector holds
     int64_t hot = cfg.hot < 0 ? 0 : cfg.hot;
@@ -524,8 +524,15 @@ static bool run_fused(const MatP& A, const FusedSpec& f, const PlanConfig* cfg_o
         // the pass timer covers the fused kernel alone
         if (timed) hip_check(hipEventRecord(e0, c.stream), "event record");
       }
+      const bool two_phase = plan->cfg.kernel == K_STRIPE2;
+      if (two_phase) {
+        // phase one: the values of the stripes' gathered entries, streamed
+        // block by block
+        hip_check(launch_cold_fill_f32(plan->st_fill, a.w, a.ncols, c.guard, c.stream), "fill gathered values");
+        launch_mark(false);
+      }
       e = launch_fused_stripe_f32(plan->st_dev, a, wsum_in, f.wsum_out, scr, plan->cfg.grid, plan->cfg.chunk == 1,
-                                  c.guard, c.stream);
+                                  two_phase, c.guard, c.stream);
       wrote_wsum = f.wsum_out != nullptr && a.w_out != nullptr;
     } else {
       e = wave ? launch_fused_wave_f32(plan->dev, a, scr, grid, plan->cfg.hot, c.guard, c.stream)

@@ -96,16 +96,25 @@ __device__ __forceinline__ long long fixed_of(float v, int kshift) {
   return (b >> 31) ? -(long long)q : (long long)q;
 }
 
-// Adds a lane's entries (rows sorted ascending, padding rows 0 at the end)
-// into the LDS row sums: runs of equal rows are summed in registers first.
-// When the whole wavefront holds one row (a long row), one lane adds the
-// wavefront's total.
-template <int K>
+// Adds a lane's entries into the LDS row sums: runs of equal rows are
+// summed in registers first.  When the whole wavefront holds one row (a
+// long row), one lane adds the wavefront's total.  SORTED: the wavefront's
+// rows ascend across lanes (padding rows 0 at the end), so the first and
+// the last row decide that; otherwise every row is compared.
+template <int K, bool SORTED>
 __device__ __forceinline__ void add_runs(unsigned long long* acc, const int (&row)[K], const float (&v)[K],
                                          int kshift) {
   const int first = lane_value(row[0], 0);
-  const int last = lane_value(row[K - 1], 63);
-  if (first == last) {
+  bool one_row;
+  if constexpr (SORTED) {
+    one_row = first == lane_value(row[K - 1], 63);
+  } else {
+    bool mine = true;
+#pragma unroll
+    for (int k = 0; k < K; ++k) mine = mine && row[k] == first;
+    one_row = __ballot(mine) == ~0ull;
+  }
+  if (one_row) {
     long long s = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) s += fixed_of(v[k], kshift);
@@ -228,11 +237,22 @@ __device__ __forceinline__ void cold_gather(__amdgpu_buffer_rsrc_t rw, ColdRegs&
   for (int k = 0; k < STRIPE_K; ++k) R.v[k] = buf_load<float>(rw, col[k] * 4u);
 }
 
+// PF: the chunk's values were loaded in place of its columns (two-phase
+// plan, entries grouped by column block, rows ascending only within a
+// group); otherwise they were gathered into R.v.
+template <bool PF>
 __device__ __forceinline__ void cold_add(unsigned long long* acc, const ColdRegs& R, int kshift) {
   const int row[STRIPE_K] = {(int)(R.rr.x & 0xFFFFu), (int)(R.rr.x >> 16), (int)(R.rr.y & 0xFFFFu),
                              (int)(R.rr.y >> 16),     (int)(R.rr.z & 0xFFFFu), (int)(R.rr.z >> 16),
                              (int)(R.rr.w & 0xFFFFu), (int)(R.rr.w >> 16)};
-  add_runs<STRIPE_K>(acc, row, R.v, kshift);
+  if constexpr (PF) {
+    const float v[STRIPE_K] = {__uint_as_float(R.ca.x), __uint_as_float(R.ca.y), __uint_as_float(R.ca.z),
+                               __uint_as_float(R.ca.w), __uint_as_float(R.cb.x), __uint_as_float(R.cb.y),
+                               __uint_as_float(R.cb.z), __uint_as_float(R.cb.w)};
+    add_runs<STRIPE_K, false>(acc, row, v, kshift);
+  } else {
+    add_runs<STRIPE_K, true>(acc, row, R.v, kshift);
+  }
 }
 
 }  // namespace
@@ -245,7 +265,7 @@ __device__ __forceinline__ void cold_add(unsigned long long* acc, const ColdRegs
 // buffer k mod 2 while block k+2 is in flight into registers; block k+1,
 // loaded during the previous phase, goes into the other buffer at the end
 // of the phase (one workgroup barrier per block).
-template <int SP>
+template <int SP, bool PF>
 __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDev p, FusedArgs<float> a,
                                                                     const double* wsum_in, double* wsum_out,
                                                                     FusedScratch scr, const GuardDev* guard) {
@@ -314,7 +334,9 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
     const int nb = wave_uniform(dp->nb), cold_n = wave_uniform(dp->cold_n);
     const long long hot_base = dp->hot_base, cold_base = dp->cold_base;
     const int ncold = (cold_n + CHUNK - 1) / CHUNK;
-    const __amdgpu_buffer_rsrc_t rcc = buf_rsrc(p.cold_col + cold_base, (unsigned)cold_n * 4u);
+    // the gathered entries' columns, or in a two-phase plan their values
+    const __amdgpu_buffer_rsrc_t rcc =
+        PF ? buf_rsrc(p.cold_val + cold_base, (unsigned)cold_n * 4u) : buf_rsrc(p.cold_col + cold_base, (unsigned)cold_n * 4u);
     const __amdgpu_buffer_rsrc_t rcr = buf_rsrc(p.cold_row + cold_base, (unsigned)cold_n * 2u);
     const int segv = lane <= nb ? dp->seg[lane] : 0;
     const unsigned* hot_seg0 = p.hot + hot_base;
@@ -330,11 +352,11 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
         ColdRegs X, Y, Z;
         cold_indices<SP>(rcc, rcr, wv, lane, X);
         cold_indices<SP>(rcc, rcr, wv + NW, lane, Y);
-        cold_gather(rw, X);
+        if constexpr (!PF) cold_gather(rw, X);
         auto step = [&](int i, ColdRegs& P, ColdRegs& G, ColdRegs& F) {
           cold_indices<SP>(rcc, rcr, wv + (i + 2) * NW, lane, F);
-          cold_gather(rw, G);
-          cold_add(acc, P, kshift);
+          if constexpr (!PF) cold_gather(rw, G);
+          cold_add<PF>(acc, P, kshift);
         };
         for (int i = 0;;) {
           step(i, X, Y, Z);
@@ -375,7 +397,7 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
           row[k] = (int)(wd[k] >> 16);
           v[k] = hbuf[wd[k] & 0xFFFFu];
         }
-        add_runs<STRIPE_K>(acc, row, v, kshift);
+        add_runs<STRIPE_K, true>(acc, row, v, kshift);
         cur = nx;
       }
       // block kblk + 1 (loaded during the previous phase) into the other
@@ -467,14 +489,58 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
 
 hipError_t launch_fused_stripe_f32(const StripePlanDev& p, const FusedArgs<float>& a, const double* wsum_in,
                                    double* wsum_out, const FusedScratch& scr, int grid, bool nt_streams,
-                                   const GuardDev* guard, hipStream_t s) {
-  if (grid <= 0 || !wsum_in) return hipErrorInvalidValue;
-  if (nt_streams)
-    hipLaunchKernelGGL(fused_stripe_kernel<CP_NT>, dim3(grid), dim3(STRIPE_BLOCK), 0, s, p, a, wsum_in, wsum_out,
-                       scr, guard);
-  else
-    hipLaunchKernelGGL(fused_stripe_kernel<0>, dim3(grid), dim3(STRIPE_BLOCK), 0, s, p, a, wsum_in, wsum_out, scr,
-                       guard);
+                                   bool prefilled, const GuardDev* guard, hipStream_t s) {
+  if (grid <= 0 || !wsum_in || (prefilled && !p.cold_val) || (!prefilled && !p.cold_col && p.nstripes > 0))
+    return hipErrorInvalidValue;
+  const dim3 g(grid), b(STRIPE_BLOCK);
+  if (prefilled) {
+    if (nt_streams)
+      hipLaunchKernelGGL((fused_stripe_kernel<CP_NT, true>), g, b, 0, s, p, a, wsum_in, wsum_out, scr, guard);
+    else
+      hipLaunchKernelGGL((fused_stripe_kernel<0, true>), g, b, 0, s, p, a, wsum_in, wsum_out, scr, guard);
+  } else {
+    if (nt_streams)
+      hipLaunchKernelGGL((fused_stripe_kernel<CP_NT, false>), g, b, 0, s, p, a, wsum_in, wsum_out, scr, guard);
+    else
+      hipLaunchKernelGGL((fused_stripe_kernel<0, false>), g, b, 0, s, p, a, wsum_in, wsum_out, scr, guard);
+  }
+  return hipGetLastError();
+}
+
+namespace {
+
+// Phase one of a two-phase pass: chunks of the fill list in turn; the
+// chunk's column block of w goes to LDS, then each entry's value to its
+// slot (the list is ordered by slot within a block, so the writes run
+// along each stripe's group of entries from that block).
+__global__ __launch_bounds__(512) void cold_fill_kernel(ColdFillDev f, const float* __restrict__ w, int ncols,
+                                                        const GuardDev* guard) {
+  if (guard && guard->active == 0) return;
+  __shared__ __attribute__((aligned(16))) float win[STRIPE_HB];
+  for (int c = blockIdx.x; c < f.nchunks; c += gridDim.x) {
+    const ColdChunk ch = f.chunk[c];
+    const int b0 = ch.blk * STRIPE_HB;
+    const int cnt = min(STRIPE_HB, ncols - b0);
+    __syncthreads();  // the previous chunk's reads of win are done
+    if (cnt == STRIPE_HB && ((uintptr_t)(w + b0) & 15u) == 0) {
+      for (int i = threadIdx.x; i < STRIPE_HB / 4; i += blockDim.x)
+        ((float4*)win)[i] = ((const float4*)(w + b0))[i];
+    } else {
+      for (int i = threadIdx.x; i < cnt; i += blockDim.x) win[i] = w[b0 + i];
+    }
+    __syncthreads();
+    for (unsigned e = ch.start + threadIdx.x; e < ch.end; e += blockDim.x) f.val[f.pos[e]] = win[f.src[e]];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_cold_fill_f32(const ColdFillDev& f, const float* w, int ncols, const GuardDev* guard,
+                                hipStream_t s) {
+  if (f.nchunks <= 0) return hipSuccess;
+  if (!f.pos || !f.src || !f.chunk || !f.val || !w) return hipErrorInvalidValue;
+  const int grid = std::min(f.nchunks, std::max(1, ctx().cus) * 3);
+  hipLaunchKernelGGL(cold_fill_kernel, dim3(grid), dim3(512), 0, s, f, w, ncols, guard);
   return hipGetLastError();
 }
 
@@ -671,7 +737,201 @@ __global__ __launch_bounds__(256) void st_partition_kernel(const int* rowptr, co
   }
 }
 
+// Exclusive prefix of v over the 1024 threads of the workgroup (ws: 16
+// ints of LDS).
+__device__ int block_excl_scan_1024(int v, int* ws) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) ws[w] = incl;
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int i = 0; i < 16; ++i) {
+      const int x = ws[i];
+      ws[i] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  const int r = ws[w] + incl - v;
+  __syncthreads();
+  return r;
+}
+
+// Two-phase plans: each stripe's gathered entries (real ones, not the
+// padding) regrouped by column block, into tcol / trow at the same slots;
+// the order inside a group is arbitrary (the fixed-point sums do not depend
+// on it).  One workgroup of 1024 per stripe; nbins <= STRIPE_MAXBLK.
+__global__ __launch_bounds__(1024) void st_group_kernel(const unsigned* ccol, const unsigned short* crow,
+                                                        const StripeDesc* desc, const int* ncold, int nbins,
+                                                        unsigned* tcol, unsigned short* trow) {
+  __shared__ int cnt[STRIPE_MAXBLK];
+  __shared__ int ws[16];
+  const int s = blockIdx.x, t = threadIdx.x;
+  const int64_t base = desc[s].cold_base;
+  const int nc = ncold[s];
+  for (int i = t; i < nbins; i += 1024) cnt[i] = 0;
+  __syncthreads();
+  for (int e = t; e < nc; e += 1024) atomicAdd(&cnt[min((int)(ccol[base + e] / STRIPE_HB), nbins - 1)], 1);
+  __syncthreads();
+  // thread t owns bins [16 t, 16 t + 16)
+  int own = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int i = t * 16 + k;
+    own += i < nbins ? cnt[i] : 0;
+  }
+  int run = block_excl_scan_1024(own, ws);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int i = t * 16 + k;
+    if (i < nbins) {
+      const int c = cnt[i];
+      cnt[i] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < nc; e += 1024) {
+    const unsigned c = ccol[base + e];
+    const int at = atomicAdd(&cnt[min((int)(c / STRIPE_HB), nbins - 1)], 1);
+    tcol[base + at] = c;
+    trow[base + at] = crow[base + e];
+  }
+}
+
+// Fill-list keys of the stripes' real gathered entries: (column block << 32
+// | slot), the column inside its block as the value; entry e of stripe s
+// goes to list position off[s] + e.
+__global__ __launch_bounds__(256) void st_fill_keys_kernel(const unsigned* ccol, const StripeDesc* desc,
+                                                           const int* ncold, const int64_t* off, uint64_t* keys,
+                                                           uint16_t* vals) {
+  const int s = blockIdx.x;
+  const int64_t base = desc[s].cold_base, o = off[s];
+  const int nc = ncold[s];
+  for (int e = threadIdx.x; e < nc; e += 256) {
+    const unsigned c = ccol[base + e];
+    const unsigned b = c / STRIPE_HB;
+    keys[o + e] = ((uint64_t)b << 32) | (uint64_t)(base + e);
+    vals[o + e] = (uint16_t)(c - b * STRIPE_HB);
+  }
+}
+
+// Slots from the sorted keys, and the first list position of each column
+// block (first[b] stays 0xFFFFFFFF for a block without entries).
+__global__ void st_fill_finish_kernel(const uint64_t* keys, int64_t n, unsigned* pos, unsigned* first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k = keys[i];
+  pos[i] = (unsigned)(k & 0xFFFFFFFFull);
+  const unsigned b = (unsigned)(k >> 32);
+  if (i == 0 || (unsigned)(keys[i - 1] >> 32) != b) first[b] = (unsigned)i;
+}
+
 int64_t pad8(int64_t x) { return (x + 7) & ~(int64_t)7; }
+
+}  // namespace
+
+namespace {
+
+constexpr unsigned FILL_CHUNK = 32768;  // fill-list entries per chunk at most
+
+// The two-phase part of a stripe plan: each stripe's gathered entries
+// regrouped by column block, the fill list (entries by column block, then
+// by slot) cut into chunks, and the zeroed value array.  The columns are
+// not kept: the pass reads values instead.
+void build_fill(const MatP& A, Plan& plan, const std::vector<int>& ncold) {
+  Ctx& c = ctx();
+  const int S = plan.st_nstripes;
+  const int64_t ncolblk = (A->ncols + STRIPE_HB - 1) / STRIPE_HB;
+  const int nbins = (int)std::max<int64_t>(1, std::min<int64_t>(ncolblk, STRIPE_MAXBLK));
+  std::vector<int64_t> off((size_t)S + 1, 0);
+  for (int s = 0; s < S; ++s) off[(size_t)s + 1] = off[(size_t)s] + ncold[(size_t)s];
+  const int64_t N = off[(size_t)S];
+  const size_t slots = (size_t)std::max<int64_t>(plan.st_cold_entries, 8);
+  plan.st_cval = dev_alloc(sizeof(float) * slots);
+  hip_check(launch_zero(plan.st_cval->p, plan.st_cval->bytes, c.stream), "zero");
+  std::vector<ColdChunk> chunks;
+  if (N > 0) {
+    BufP d_nc = dev_alloc(sizeof(int) * (size_t)S), d_off = dev_alloc(sizeof(int64_t) * (size_t)S);
+    hip_check(hipMemcpyAsync(d_nc->p, ncold.data(), sizeof(int) * (size_t)S, hipMemcpyHostToDevice, c.stream),
+              "upload");
+    hip_check(hipMemcpyAsync(d_off->p, off.data(), sizeof(int64_t) * (size_t)S, hipMemcpyHostToDevice, c.stream),
+              "upload");
+    // regroup each stripe's entries by column block
+    BufP tcol = dev_alloc(plan.st_ccol->bytes), trow = dev_alloc(plan.st_crow->bytes);
+    hip_check(launch_zero(tcol->p, tcol->bytes, c.stream), "zero");
+    hip_check(launch_zero(trow->p, trow->bytes, c.stream), "zero");
+    hipLaunchKernelGGL(st_group_kernel, dim3(S), dim3(1024), 0, c.stream, (const unsigned*)plan.st_ccol->p,
+                       (const unsigned short*)plan.st_crow->p, (const StripeDesc*)plan.st_desc->p,
+                       (const int*)d_nc->p, nbins, (unsigned*)tcol->p, (unsigned short*)trow->p);
+    hip_check(hipGetLastError(), "group gathered entries");
+    plan.st_ccol = tcol;
+    plan.st_crow = trow;
+    // the fill list: (block, slot) keys sorted
+    BufP kin = dev_alloc(sizeof(uint64_t) * (size_t)N), kout = dev_alloc(sizeof(uint64_t) * (size_t)N);
+    BufP vin = dev_alloc(sizeof(uint16_t) * (size_t)N);
+    plan.st_pasrc = dev_alloc(sizeof(uint16_t) * (size_t)N);
+    hipLaunchKernelGGL(st_fill_keys_kernel, dim3(S), dim3(256), 0, c.stream, (const unsigned*)plan.st_ccol->p,
+                       (const StripeDesc*)plan.st_desc->p, (const int*)d_nc->p, (const int64_t*)d_off->p,
+                       (uint64_t*)kin->p, (uint16_t*)vin->p);
+    hip_check(hipGetLastError(), "fill keys");
+    unsigned end_bit = 32;
+    while (end_bit < 64 && ((uint64_t)1 << (end_bit - 32)) < (uint64_t)ncolblk) ++end_bit;
+    hip_check(sort_pairs_u64_u16((const uint64_t*)kin->p, (uint64_t*)kout->p, (const uint16_t*)vin->p,
+                                 (uint16_t*)plan.st_pasrc->p, N, end_bit, cache_alloc, cache_release, nullptr,
+                                 c.stream),
+              "sort fill list");
+    kin.reset();
+    vin.reset();
+    plan.st_papos = dev_alloc(sizeof(unsigned) * (size_t)N);
+    BufP first = dev_alloc(sizeof(unsigned) * (size_t)ncolblk);
+    hip_check(launch_fill(first->p, T_INT32, ncolblk, -1.0, c.stream), "fill");
+    const int64_t g = (N + 255) / 256;
+    hipLaunchKernelGGL(st_fill_finish_kernel, dim3((unsigned)g), dim3(256), 0, c.stream, (const uint64_t*)kout->p,
+                       N, (unsigned*)plan.st_papos->p, (unsigned*)first->p);
+    hip_check(hipGetLastError(), "fill list");
+    std::vector<unsigned> hfirst((size_t)ncolblk);
+    hip_check(hipMemcpyAsync(hfirst.data(), first->p, sizeof(unsigned) * (size_t)ncolblk, hipMemcpyDeviceToHost,
+                             c.stream),
+              "download");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    // chunks of at most FILL_CHUNK entries of one block
+    int64_t prev_b = -1;
+    for (int64_t b = 0; b <= ncolblk; ++b) {
+      if (b < ncolblk && hfirst[(size_t)b] == 0xFFFFFFFFu) continue;
+      if (prev_b >= 0) {
+        const unsigned st = hfirst[(size_t)prev_b];
+        const unsigned en = b < ncolblk ? hfirst[(size_t)b] : (unsigned)N;
+        if (en < st) fail(GrB_PANIC, "stripe plan: fill list out of order");
+        for (unsigned x = st; x < en; x += FILL_CHUNK)
+          chunks.push_back(ColdChunk{(int)prev_b, x, std::min(en, x + FILL_CHUNK), 0u});
+      }
+      prev_b = b;
+    }
+  }
+  plan.st_pachunk = dev_alloc(sizeof(ColdChunk) * std::max<size_t>(chunks.size(), 1));
+  if (!chunks.empty())
+    hip_check(hipMemcpyAsync(plan.st_pachunk->p, chunks.data(), sizeof(ColdChunk) * chunks.size(),
+                             hipMemcpyHostToDevice, c.stream),
+              "upload");
+  hip_check(hipStreamSynchronize(c.stream), "sync");
+  plan.st_ccol.reset();  // the pass reads values, not columns
+  plan.st_dev.cold_col = nullptr;
+  plan.st_dev.cold_row = (const unsigned short*)plan.st_crow->p;
+  plan.st_dev.cold_val = (const float*)plan.st_cval->p;
+  ColdFillDev& f = plan.st_fill;
+  f.pos = plan.st_papos ? (const unsigned*)plan.st_papos->p : nullptr;
+  f.src = plan.st_pasrc ? (const unsigned short*)plan.st_pasrc->p : nullptr;
+  f.chunk = (const ColdChunk*)plan.st_pachunk->p;
+  f.val = (float*)plan.st_cval->p;
+  f.nchunks = (int)chunks.size();
+}
 
 }  // namespace
 
@@ -841,8 +1101,10 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
   d.wg_off = (const int*)plan.st_wgoff->p;
   d.wg_list = (const int*)plan.st_wglist->p;
   d.wg_sum = (double*)plan.st_wgsum->p;
+  d.cold_val = nullptr;
   d.nstripes = S;
   d.maxlen = maxlen;
+  if (cfg.kernel == K_STRIPE2) build_fill(A, plan, cold_cnt);
 }
 
 }  // namespace nbgrb

@@ -70,16 +70,17 @@ def _per_vertex(x, ref_x):
     assert not bad.any(), (np.flatnonzero(bad)[:10], e[bad][:10])
 
 
-@pytest.mark.parametrize("relabel", [1, 0])
-def test_scale22_stripe_plan_matches_oracle(gpu, oracle_mod, g22, relabel):
-    """The stripe-blocked pass (row sums in LDS, leading column blocks in
-    LDS, 64-bit fixed-point sums) at the headline size."""
+@pytest.mark.parametrize("kernel,relabel", [(2, 1), (2, 0), (3, 1), (3, 0)])
+def test_scale22_stripe_plan_matches_oracle(gpu, oracle_mod, g22, kernel, relabel):
+    """The stripe-blocked pass (row sums in LDS, dense column blocks in LDS,
+    64-bit fixed-point sums), gathered (kernel 2) or two-phase (kernel 3),
+    at the headline size."""
     from paper_2509_14211_amd import api
     g, og = g22
     t = gpu.builtin("GrB_FP32")
     saved = gpu.GrM_Matrix_plan_get(g.AT, t)
-    gpu.GrM_Matrix_plan_set(g.AT, t, dict(kernel=2, lds_entries=0, lds_rows=0, long_row=1024, chunk=0, grid=0,
-                                          hot=0, relabel=relabel))
+    gpu.GrM_Matrix_plan_set(g.AT, t, dict(kernel=kernel, lds_entries=0, lds_rows=0, long_row=1024, chunk=0,
+                                          grid=0, hot=0, relabel=relabel))
     try:
         x, it, res = api.pagerank(g, torch.float32, D, 1e-6)
     finally:
@@ -87,7 +88,8 @@ def test_scale22_stripe_plan_matches_oracle(gpu, oracle_mod, g22, relabel):
     x = x.cpu().numpy().astype(np.float64)
     ref = oracle_mod.pagerank(og, D, fixed_iters=it)
     err = np.abs(x - ref.x).sum()
-    print("scale 22 stripe relabel %d: %d passes, L1 error %.3e" % (relabel, it, err), flush=True)
+    print("scale 22 stripe kernel %d relabel %d: %d passes, L1 error %.3e" % (kernel, relabel, it, err),
+          flush=True)
     assert err <= 1e-5
     _per_vertex(x, ref.x)
     assert res <= 1e-6 and abs(res - ref.resid) <= 4 * err + 1e-7
@@ -214,9 +216,9 @@ def test_scale25_stripe_mxv_exact_on_integers(gpu):
         exact = torch.zeros(g.n, dtype=torch.float64, device="cuda").index_add_(0, rows, u[col.long()].double())
         del rows, rp, col
         gpu.GrM_set_mode(gpu.GrB_BLOCKING)
-        for relabel in (0, 1):
-            gpu.GrM_Matrix_plan_set(g.AT, t, dict(kernel=2, lds_entries=0, lds_rows=0, long_row=1024, chunk=0,
-                                                  grid=0, hot=0, relabel=relabel))
+        for kernel, relabel in ((2, 0), (2, 1), (3, 0), (3, 1)):
+            gpu.GrM_Matrix_plan_set(g.AT, t, dict(kernel=kernel, lds_entries=0, lds_rows=0, long_row=1024,
+                                                  chunk=0, grid=0, hot=0, relabel=relabel))
             uv = api.vector_from_tensor(u)
             w = gpu.GrB_Vector_new(t, g.n)
             try:
@@ -227,8 +229,8 @@ def test_scale25_stripe_mxv_exact_on_integers(gpu):
                 gpu.GrB_Vector_free(w)
                 gpu.GrM_Matrix_plan_set(g.AT, t, None)
             bad = (got != exact).nonzero().flatten()
-            print("relabel %d: %d rows differ" % (relabel, bad.numel()), flush=True)
-            assert bad.numel() == 0, (relabel, bad[:10].tolist())
+            print("kernel %d relabel %d: %d rows differ" % (kernel, relabel, bad.numel()), flush=True)
+            assert bad.numel() == 0, (kernel, relabel, bad[:10].tolist())
     finally:
         gpu.GrM_set_mode(gpu.GrB_NONBLOCKING)
         g.free()

@@ -18,8 +18,8 @@ D = 0.85
 HB = 12288
 
 
-def stripe_cfg(relabel=1, long_row=1024, hot=0, grid=0, chunk=0):
-    return dict(kernel=2, lds_entries=0, lds_rows=0, long_row=long_row, chunk=chunk, grid=grid, hot=hot,
+def stripe_cfg(relabel=1, long_row=1024, hot=0, grid=0, chunk=0, kernel=2):
+    return dict(kernel=kernel, lds_entries=0, lds_rows=0, long_row=long_row, chunk=chunk, grid=grid, hot=hot,
                 relabel=relabel)
 
 
@@ -31,11 +31,16 @@ CONFIGS = [
     stripe_cfg(hot=HB, grid=3),           # one LDS block at most, three workgroups
     stripe_cfg(hot=2 * HB, long_row=64, grid=13),
     stripe_cfg(chunk=1),                  # packed entries read with the nontemporal hint
+    # two-phase: the entries outside the LDS blocks are filled block by block
+    stripe_cfg(kernel=3),
+    stripe_cfg(kernel=3, relabel=0, chunk=1),
+    stripe_cfg(kernel=3, long_row=1 << 30),  # no LDS block: every entry filled
+    stripe_cfg(kernel=3, hot=HB, grid=3),
 ]
 
 
 def _ids(c):
-    return "r%d-l%d-h%d-g%d-c%d" % (c["relabel"], c["long_row"], c["hot"], c["grid"], c["chunk"])
+    return "k%d-r%d-l%d-h%d-g%d-c%d" % (c["kernel"], c["relabel"], c["long_row"], c["hot"], c["grid"], c["chunk"])
 
 
 def _run(grb, g, cfg, dtype=torch.float32, **kw):
@@ -86,7 +91,8 @@ def test_stripe_many_blocks_and_cold_entries(nonblocking, oracle_mod):
     from paper_2509_14211_amd import api
     g = api.rmat_graph(19)
     og = oracle_mod.rmat_graph(19)
-    for cfg in (stripe_cfg(long_row=1), stripe_cfg(relabel=0, long_row=1), stripe_cfg(long_row=1, hot=32 * HB)):
+    for cfg in (stripe_cfg(long_row=1), stripe_cfg(relabel=0, long_row=1), stripe_cfg(long_row=1, hot=32 * HB),
+                stripe_cfg(kernel=3, long_row=1), stripe_cfg(kernel=3, relabel=0, long_row=2048)):
         x, it, _ = _run(nonblocking, g, cfg, tol=1e-6)
         ref = oracle_mod.pagerank(og, D, fixed_iters=it)
         _check_fp32(x, ref.x)
@@ -141,7 +147,8 @@ def test_stripe_mxv_exact_on_integers(blocking, scale):
     exact = np.zeros(g.n, np.float64)
     np.add.at(exact, rows, u[cl].astype(np.float64))
     t = grb.builtin("GrB_FP32")
-    for cfg in (stripe_cfg(relabel=0), stripe_cfg(relabel=0, long_row=1 << 30), stripe_cfg(relabel=0, grid=5)):
+    for cfg in (stripe_cfg(relabel=0), stripe_cfg(relabel=0, long_row=1 << 30), stripe_cfg(relabel=0, grid=5),
+                stripe_cfg(relabel=0, kernel=3), stripe_cfg(relabel=0, kernel=3, long_row=1 << 30)):
         grb.GrM_Matrix_plan_set(g.AT, t, cfg)
         uv = api.vector_from_tensor(torch.from_numpy(u).cuda())
         w = grb.GrB_Vector_new(t, g.n)
@@ -178,9 +185,27 @@ def test_stripe_plan_only_for_fp32(nonblocking):
     from paper_2509_14211_amd import api
     grb = nonblocking
     g = api.rmat_graph(8)
-    with pytest.raises(grb.GrBError) as e:
-        grb.GrM_Matrix_plan_set(g.AT, grb.builtin("GrB_FP64"), stripe_cfg())
-    assert e.value.info == -3
+    for kernel in (2, 3):
+        with pytest.raises(grb.GrBError) as e:
+            grb.GrM_Matrix_plan_set(g.AT, grb.builtin("GrB_FP64"), stripe_cfg(kernel=kernel))
+        assert e.value.info == -3
+    g.free()
+
+
+def test_two_phase_stripe_is_deterministic_and_matches_gathered(nonblocking):
+    """The two-phase plan regroups entries with atomics (their order inside
+    a block group varies from build to build), yet its fixed-point sums are
+    exact: two builds give the same bits, and integer products equal the
+    gathered plan's."""
+    from paper_2509_14211_amd import api
+    g = api.rmat_graph(16)
+    a, ita, ra = _run(nonblocking, g, stripe_cfg(kernel=3), tol=1e-7)
+    g.free()
+    g = api.rmat_graph(16)
+    b, itb, rb = _run(nonblocking, g, stripe_cfg(kernel=3), tol=1e-7)
+    c, itc, rc = _run(nonblocking, g, stripe_cfg(kernel=2), tol=1e-7)
+    assert ita == itb and ra == rb and np.array_equal(a, b)
+    assert itc == ita and np.array_equal(a, c)
     g.free()
 
 
@@ -219,23 +244,23 @@ def test_stripe_loads_the_dense_blocks_of_a_banded_graph(nonblocking, oracle_mod
     og = oracle_mod.graph_from_edges(n, src, dst)
     grb = nonblocking
     t = grb.builtin("GrB_FP32")
-    cfg = stripe_cfg(relabel=0, long_row=256)
-    # integer mxv, bit for bit
-    grb.GrM_set_mode(grb.GrB_BLOCKING)
-    grb.GrM_Matrix_plan_set(g.AT, t, cfg)
-    try:
-        rp, cl = api.csr_of(g.AT)
-        gen = torch.Generator(device="cuda")
-        gen.manual_seed(3)
-        u = torch.randint(-8, 9, (n,), device="cuda", generator=gen).float()
-        got = _mxv_fp32(grb, g.AT, u).double()
-        assert torch.equal(got, _exact(rp, cl, u))
-    finally:
-        grb.GrM_Matrix_plan_set(g.AT, t, None)
-        grb.GrM_set_mode(grb.GrB_NONBLOCKING)
-    x, it, _ = _run(nonblocking, g, cfg, tol=1e-7)
-    ref = oracle_mod.pagerank(og, D, fixed_iters=it)
-    _check_fp32(x, ref.x)
+    for cfg in (stripe_cfg(relabel=0, long_row=256), stripe_cfg(relabel=0, long_row=256, kernel=3)):
+        # integer mxv, bit for bit
+        grb.GrM_set_mode(grb.GrB_BLOCKING)
+        grb.GrM_Matrix_plan_set(g.AT, t, cfg)
+        try:
+            rp, cl = api.csr_of(g.AT)
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(3)
+            u = torch.randint(-8, 9, (n,), device="cuda", generator=gen).float()
+            got = _mxv_fp32(grb, g.AT, u).double()
+            assert torch.equal(got, _exact(rp, cl, u)), _ids(cfg)
+        finally:
+            grb.GrM_Matrix_plan_set(g.AT, t, None)
+            grb.GrM_set_mode(grb.GrB_NONBLOCKING)
+        x, it, _ = _run(nonblocking, g, cfg, tol=1e-7)
+        ref = oracle_mod.pagerank(og, D, fixed_iters=it)
+        _check_fp32(x, ref.x)
     g.free()
 
 
@@ -271,7 +296,8 @@ def test_stripe_with_more_column_blocks_than_the_layout_tells_apart(blocking):
         grb.GrM_Matrix_import_CSR(A, rowptr, col, col.numel())
         u = torch.randint(-8, 9, (ncols,), device="cuda", generator=gen).float()
         want = _exact(rowptr, col, u)
-        for cfg in (stripe_cfg(relabel=0, long_row=1000), stripe_cfg(relabel=0, long_row=1)):
+        for cfg in (stripe_cfg(relabel=0, long_row=1000), stripe_cfg(relabel=0, long_row=1),
+                    stripe_cfg(relabel=0, long_row=1000, kernel=3)):
             grb.GrM_Matrix_plan_set(A, t, cfg)
             got = _mxv_fp32(grb, A, u).double()
             grb.GrM_Matrix_plan_set(A, t, None)

@@ -109,7 +109,7 @@ def test_plan_config_validation(nonblocking):
     grb = nonblocking
     g = api.rmat_graph(8)
     t = grb.builtin("GrB_FP32")
-    bad = [dict(kernel=3, lds_entries=2048, lds_rows=1024, long_row=2048, chunk=2048),
+    bad = [dict(kernel=4, lds_entries=2048, lds_rows=1024, long_row=2048, chunk=2048),
            dict(kernel=0, lds_entries=3000, lds_rows=1024, long_row=2048, chunk=2048),
            dict(kernel=1, lds_entries=2048, lds_rows=1024, long_row=512, chunk=512),
            dict(kernel=0, lds_entries=2048, lds_rows=1024, long_row=4096, chunk=2048),
