@@ -164,8 +164,7 @@ def summarize_rocprof(dirs, traffic_kernel: str = "fused_wave_kernel<float", min
             fv, wv = counters.get((k, "FETCH_SIZE"), []), counters.get((k, "WRITE_SIZE"), [])
             if not fv or len(fv) != len(wv):
                 continue
-            keep = [i for i, w in enumerate(wv) if w >= min_write_kib] if part == parts[-1] else list(
-                range(len(wv)))
+            keep = [i for i, w in enumerate(wv) if w >= min_write_kib]
             if keep and (best is None or len(keep) > len(best[3])):
                 best = (k, fv, wv, keep)
         if best is None:
