@@ -140,6 +140,15 @@ GrB_Info GrM_autotune_pagerank(GrM_PlanConfig* chosen, double* us_per_pass, GrB_
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
     double best_us = 1e300;
+    bool any = false;
+    // Each candidate's plan (some are as large as the matrix) is dropped
+    // once it is timed, so only one is held at a time; a candidate whose
+    // layout does not fit in memory is skipped.
+    auto drop_plans = [&]() {
+      hip_check(hipStreamSynchronize(c.stream), "sync");
+      A->plans.clear();
+      if (A->relabeled) A->relabeled->A->plans.clear();
+    };
     for (const GrM_PlanConfig& cand : cands) {
       c.tuned[{A->id, T}] = to_plan(cand);
       double t[2] = {0, 0};
@@ -147,8 +156,7 @@ GrB_Info GrM_autotune_pagerank(GrM_PlanConfig* chosen, double* us_per_pass, GrB_
       double res = 0;
       // warm-up builds the plan (and the relabeled copy) outside the timing
       info = GrM_pagerank(rv, &it, &res, AT, outdeg, 0.85, 0.0, 2, GrM_DANGLING_UNIFORM, nullptr, 2);
-      if (info != GrB_SUCCESS) break;
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < 2 && info == GrB_SUCCESS; ++j) {
         const int k = j == 0 ? k1 : k2;
         hip_check(hipEventRecord(e0, c.stream), "record");
         info = GrM_pagerank(rv, &it, &res, AT, outdeg, 0.85, 0.0, k, GrM_DANGLING_UNIFORM, nullptr, k);
@@ -159,12 +167,22 @@ GrB_Info GrM_autotune_pagerank(GrM_PlanConfig* chosen, double* us_per_pass, GrB_
         hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
         t[j] = ms;
       }
+      drop_plans();
+      if (info == GrB_OUT_OF_MEMORY) {
+        info = GrB_SUCCESS;
+        continue;
+      }
       if (info != GrB_SUCCESS) break;
       const double us = (t[1] - t[0]) * 1e3 / (k2 - k1);
-      if (us < best_us) {
+      if (!any || us < best_us) {
         best_us = us;
         best = cand;
+        any = true;
       }
+    }
+    if (info == GrB_SUCCESS && !any) {
+      info = GrB_OUT_OF_MEMORY;
+      set_error_text("no candidate plan fits in memory");
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
