@@ -573,9 +573,11 @@ GrB_Info GrM_ppr(GrB_Vector r, int *iters, double *resid, GrB_Matrix AT, GrB_Vec
  * mass returns to the seeds in GrM_DANGLING_UNIFORM), with the residual and
  * dangling mass of every column in FP64, and stops where GrM_ppr would:
  * at the first pass whose residual is <= tol, or after itermax passes.  A
- * stopped column is frozen (no longer written), and once at most half the
- * columns are still running the product narrows to them, so the passes of
- * the slowest sets cost less than full-width passes.  X (device, n x k
+ * stopped column keeps the ranks of that pass (later passes carry them
+ * forward unchanged); as columns stop, the product narrows to the running
+ * ones (multiples of 16 columns), and the last eight or fewer finish as
+ * single-vector solves, so the passes of the slowest sets cost less than
+ * full-width passes.  X (device, n x k
  * row-major, `type` FP32 or FP64) receives in column q the ranks of the
  * pass column q stopped at; *iters the passes of the longest-running
  * column; col_iters[q] (host, may be NULL) the pass at which column q's

@@ -223,8 +223,14 @@ struct PprSeed {
 };
 
 // A batch with at most this many columns still running finishes them as
-// single-vector solves.
-constexpr int PPR_TAIL_COLUMNS = 16;
+// single-vector solves.  A gathered row narrower than a 128-byte cache line
+// costs a whole line, so a product pass of 8 columns costs about as much as
+// one of 16 and more than 8 single-vector passes.
+constexpr int PPR_TAIL_COLUMNS = 8;
+
+// Width of the product once `live` columns still run: whole 64-byte FP32
+// row sectors, at least 16 columns (gathered four entries per load).
+inline int ppr_narrow_width(int live) { return live > 16 ? (live + 15) / 16 * 16 : 16; }
 
 // Seed sets seed_vtx[seed_ptr[q] : seed_ptr[q+1]], q < nsets: non-empty,
 // distinct vertices in [0, n).
@@ -262,6 +268,9 @@ struct PprColumns {
   SpmmArgs a{};
   int grid = 0;
   bool uniform = true;
+  // the next pass stores every row: after a start or a narrowing, the
+  // output buffers do not yet hold zeros in the rows the pass may skip
+  bool full_next = true;
 
   ~PprColumns() { set_vec(&dinv, nullptr); }
 
@@ -405,6 +414,7 @@ struct PprColumns {
               "ppr init");
     launch_mark(false);
     launch_mark(false);
+    full_next = true;
   }
 
   // Columns `cols` to their outputs: column c of the iterate from buffer
@@ -440,6 +450,7 @@ struct PprColumns {
     a.k = k2;
     const size_t used = type_size(T) * (size_t)n * (size_t)k2;
     a.w_bytes = used < 0xFFFFFF00ull ? (unsigned)used : 0u;
+    full_next = true;
   }
 
   // One pass from buffer set (pass-1)&1 into pass&1.
@@ -452,6 +463,10 @@ struct PprColumns {
     a.w_new = Wb[out]->p;
     a.d_prev = uniform ? (const double*)Db[in]->p : nullptr;
     a.d_out = (double*)Db[out]->p;
+    // rows with no entries and no seed stay zero in both buffer sets once a
+    // pass has stored every row of the current layout and seeds
+    a.skip_empty = full_next ? 0 : 1;
+    full_next = false;
     hip_check(launch_spmm_ppr(plan->dev, a, T, grid, a.guard, c.stream), "ppr pass");
     launch_mark(true);
   }
@@ -499,21 +514,25 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
 
   // col_set[c]: the seed set in column c (-1: none).  Each column stops at
   // the pass its own residual first reaches tol (the pass kernel freezes it
-  // there, in the buffer of that pass), so column q ends where a
-  // single-vector solve of set q would.  Converged columns are written to
-  // X when the product narrows (before their buffers are reused) and at the
-  // end: once at most half the columns are live, the rest are narrowed.
+  // there and every later pass carries its ranks forward unchanged, so the
+  // buffer set of the last pass holds every column), and column q ends
+  // where a single-vector solve of set q would.  Finished columns go to a
+  // column-major staging copy (set q at stage + q n, vertex order), written
+  // in whole lines, when the product narrows and at the end; X is written
+  // once, whole rows at a time, at the very end.
+  const size_t vb = type_size(T) * (size_t)n;
+  BufP stage = dev_alloc(vb * (size_t)k);
   std::vector<int> col_set((size_t)k);
   for (int q = 0; q < k; ++q) col_set[(size_t)q] = q;
   int live = k;
-  uint64_t frozen = 0, frozen1 = 0;  // converged, not yet written; from buffer set 1
+  uint64_t frozen = 0;  // converged, not yet staged
   bool tail = false;
   ColumnOutputs outs{};
-  outs.ld = k;
-  auto out_of = [&](uint64_t cols, uint64_t from1) {
+  outs.ld = 1;
+  auto out_of = [&](uint64_t cols, int at_pass) {
     for (int col = 0; col < pc.k; ++col)
-      if ((cols >> col) & 1ull) outs.out[col] = (char*)X + type_size(T) * (size_t)col_set[(size_t)col];
-    pc.output(cols, from1, outs);
+      if ((cols >> col) & 1ull) outs.out[col] = (char*)stage->p + vb * (size_t)col_set[(size_t)col];
+    pc.output(cols, (at_pass & 1) ? cols : 0ull, outs);
   };
   std::vector<int> hh(64, -1);
   std::vector<double> rr(64, 1.0);
@@ -530,7 +549,6 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
       const int q = col_set[(size_t)col];
       if (q < 0 || ((frozen >> col) & 1ull) || hh[(size_t)col] < 0) continue;
       frozen |= 1ull << col;
-      if (hh[(size_t)col] & 1) frozen1 |= 1ull << col;
       if (col_iters) col_iters[q] = hh[(size_t)col];
       if (col_resid) col_resid[q] = rr[(size_t)col];
       --live;
@@ -540,14 +558,13 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
       tail = true;
       break;
     }
-    // narrow to the live columns rounded up to 16 (rows of whole 64-byte
-    // sectors in FP32) once that is narrower
-    const int k2 = (live + 15) / 16 * 16;
+    // narrow to the live columns once that is narrower
+    const int k2 = ppr_narrow_width(live);
     if (k2 < pc.k) {
-      out_of(frozen, frozen1);
+      out_of(frozen, hg.iters);
       for (int col = 0; col < pc.k; ++col)
         if ((frozen >> col) & 1ull) col_set[(size_t)col] = -1;
-      frozen = frozen1 = 0;
+      frozen = 0;
       std::vector<int> keep, newpos((size_t)pc.k, -1), set2((size_t)k2, -1);
       for (int col = 0; col < pc.k; ++col)
         if (col_set[(size_t)col] >= 0) {
@@ -578,35 +595,42 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
   }
   c.guard = saved_guard;
   if (hg.bad) fail(GrB_PANIC, "ppr_batch: a column's residual or dangling mass was not finite");
-  // the converged columns not yet written
-  out_of(frozen, frozen1);
+  // the converged columns not yet staged
+  out_of(frozen, hg.iters);
   uint64_t rest = 0;
   for (int col = 0; col < pc.k; ++col)
     if (col_set[(size_t)col] >= 0 && !((frozen >> col) & 1ull)) rest |= 1ull << col;
   const int done_passes = hg.iters;
   int max_passes = hg.iters;
-  if (tail && itermax > done_passes) {
-    // The few columns still running continue one by one as single-vector
-    // solves (GrM_ppr) from their current iterate: that pass costs a small
-    // fraction of even a one-column SpMM pass.  Their iterate, teleport
-    // vector and dangling mass define the next pass completely, so column q
-    // still ends where a single-vector solve of set q from the start would.
-    const size_t vb = type_size(T) * (size_t)n;
-    std::vector<int> tcols;
+  // source of every column of X: its staged copy, or a tail solve's result
+  ColumnInputs ins{};
+  ins.ld = k;
+  for (int q = 0; q < k; ++q) {
+    ins.in[q] = (const char*)stage->p + vb * (size_t)q;
+    ins.dst[q] = q;
+  }
+  std::vector<int> tcols;
+  if (tail && itermax > done_passes)
     for (int col = 0; col < pc.k; ++col)
       if ((rest >> col) & 1ull) tcols.push_back(col);
-    const int nt = (int)tcols.size();
-    // every tail column's current iterate, in the original numbering, in
-    // one sweep over the operand
-    std::vector<GB_Vector_opaque> xv((size_t)nt, GB_Vector_opaque{MAGIC_VEC, T, n, nullptr});
-    std::vector<GB_Vector_opaque> rv((size_t)nt, GB_Vector_opaque{MAGIC_VEC, T, n, nullptr});
-    auto release = [&]() {
-      for (int i = 0; i < nt; ++i) {
-        set_vec(&xv[(size_t)i], nullptr);
-        set_vec(&rv[(size_t)i], nullptr);
-      }
-    };
-    try {
+  const int nt = (int)tcols.size();
+  std::vector<GB_Vector_opaque> xv((size_t)nt, GB_Vector_opaque{MAGIC_VEC, T, n, nullptr});
+  std::vector<GB_Vector_opaque> rv((size_t)nt, GB_Vector_opaque{MAGIC_VEC, T, n, nullptr});
+  auto release = [&]() {
+    for (int i = 0; i < nt; ++i) {
+      set_vec(&xv[(size_t)i], nullptr);
+      set_vec(&rv[(size_t)i], nullptr);
+    }
+  };
+  try {
+    if (nt > 0) {
+      // The few columns still running continue one by one as single-vector
+      // solves (GrM_ppr) from their current iterate: that pass costs a small
+      // fraction of even a one-column SpMM pass.  Their iterate, teleport
+      // vector and dangling mass define the next pass completely, so column
+      // q still ends where a single-vector solve of set q from the start
+      // would.  Every tail column's current iterate, in the original
+      // numbering, comes out in one sweep over the operand.
       ColumnOutputs xo{};
       xo.ld = 1;
       for (int i = 0; i < nt; ++i) {
@@ -617,8 +641,6 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
         set_vec(&xv[(size_t)i], xn);
       }
       pc.output(rest, (done_passes & 1) ? rest : 0ull, xo);
-      ColumnInputs ins{};
-      ins.ld = k;
       for (int i = 0; i < nt; ++i) {
         const int q = col_set[(size_t)tcols[(size_t)i]];
         GB_Vector_opaque tv{MAGIC_VEC, T, n, nullptr};
@@ -643,34 +665,32 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
         set_vec(&xv[(size_t)i], nullptr);  // its start vector is no longer needed
         materialize(rv[(size_t)i].node);
         require_full(rv[(size_t)i].node, "a batched PPR column");
-        ins.in[i] = rv[(size_t)i].node->buf->p;
-        ins.dst[i] = q;
+        ins.in[q] = rv[(size_t)i].node->buf->p;
         const bool conv = res <= tol;
         if (col_iters) col_iters[q] = conv ? done_passes + it : -1;
         if (col_resid) col_resid[q] = res;
         max_passes = std::max(max_passes, done_passes + it);
       }
-      // all tail columns into X in one sweep
-      hip_check(launch_columns_in(ins, nt, T, n, X, c.stream), "columns in");
-      launch_mark(false);
-      hip_check(hipStreamSynchronize(c.stream), "sync");
-    } catch (...) {
-      release();
-      throw;
+    } else {
+      // columns that did not converge within itermax (or ran no pass):
+      // their current iterate
+      for (int col = 0; col < pc.k; ++col) {
+        if (!((rest >> col) & 1ull)) continue;
+        const int q = col_set[(size_t)col];
+        if (col_iters) col_iters[q] = -1;
+        if (col_resid) col_resid[q] = hg.iters == 0 ? 1.0 : rr[(size_t)col];
+      }
+      out_of(rest, hg.iters);
     }
+    // every column into X, whole rows at a time
+    hip_check(launch_columns_in(ins, k, T, n, X, c.stream), "columns in");
+    launch_mark(false);
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+  } catch (...) {
     release();
-  } else {
-    // columns that did not converge within itermax (or ran no pass): their
-    // current iterate
-    for (int col = 0; col < pc.k; ++col) {
-      if (!((rest >> col) & 1ull)) continue;
-      const int q = col_set[(size_t)col];
-      if (col_iters) col_iters[q] = -1;
-      if (col_resid) col_resid[q] = hg.iters == 0 ? 1.0 : rr[(size_t)col];
-    }
-    out_of(rest, (hg.iters & 1) ? rest : 0ull);
+    throw;
   }
-  hip_check(hipStreamSynchronize(c.stream), "sync");
+  release();
   *iters = max_passes;
   }
   catch (const GrbError& e) {

@@ -318,6 +318,10 @@ struct SpmmArgs {
   // teleport, pre-scaled copy, residual or dangling mass; x_old, dvec,
   // seeds, tile_seed, the reductions and the guard are not used
   int plain;
+  // the buffer-addressed pass leaves rows with no entries and no seed
+  // untouched; the caller guarantees their x and w are zero in both the
+  // input and the output buffers (every column)
+  int skip_empty;
 };
 constexpr int SPMM_BLOCK = 1024;
 hipError_t launch_spmm_ppr(const TilePlanDev& plan, const SpmmArgs& a, int type, int grid,

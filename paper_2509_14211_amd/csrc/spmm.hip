@@ -26,32 +26,38 @@ constexpr int SNW = SB / 64;
 
 // Epilogue of row i with its inputs already loaded (xo = x_old row entry,
 // dv = d_i).  Seeds are consumed in vertex order: sp is the next unread
-// seed, nsv its vertex.
+// seed, nsv its vertex.  Lane `lane` owns an existing column when `have`,
+// one still iterating when `live`.  A frozen column (have, not live) copies
+// its value forward, so both buffer sets hold it and every row is stored
+// whole: a row store with masked lanes leaves partly written lines in HBM,
+// which cost the memory system more than full ones.
 template <typename T>
-__device__ __forceinline__ void spmm_finish(const SpmmArgs& p, int i, T s, int lane, bool on, T cfac, T xo,
-                                            T dv, int& sp, int& nsv, double& rho, double& dm) {
+__device__ __forceinline__ void spmm_finish(const SpmmArgs& p, int i, T s, int lane, bool have, bool live, T cfac,
+                                            T xo, T dv, int& sp, int& nsv, double& rho, double& dm) {
   T tele = 0;
   while (nsv == i) {
     if (p.seed_c[sp] == lane) tele += (T)p.seed_w[sp] * cfac;
     ++sp;
     nsv = sp < p.nseeds ? p.seed_v[sp] : 0x7fffffff;
   }
-  if (!on) return;
+  if (!have) return;
   const int64_t at = (int64_t)i * p.k + lane;
   if (p.plain) {
     __builtin_nontemporal_store(s, (T*)p.x_new + at);
     return;
   }
-  const T r = s + tele;
+  const T r = live ? s + tele : xo;
   __builtin_nontemporal_store(r, (T*)p.x_new + at);
   ((T*)p.w_new)[at] = r * dv;
-  rho += fabs((double)xo - (double)r);
-  if (dv == (T)0) dm += (double)r;
+  if (live) {
+    rho += fabs((double)xo - (double)r);
+    if (dv == (T)0) dm += (double)r;
+  }
 }
 
 template <typename T>
-__device__ __forceinline__ T load_xo(const SpmmArgs& p, int i, int lane, bool on) {
-  return (on && !p.plain) ? __builtin_nontemporal_load((const T*)p.x_old + (int64_t)i * p.k + lane) : (T)0;
+__device__ __forceinline__ T load_xo(const SpmmArgs& p, int i, int lane, bool have) {
+  return (have && !p.plain) ? __builtin_nontemporal_load((const T*)p.x_old + (int64_t)i * p.k + lane) : (T)0;
 }
 
 template <typename T>
@@ -74,8 +80,9 @@ __device__ __forceinline__ int first_seed(const SpmmArgs& p, int t) { return p.n
 // wavefront that finished last adds them in chunk order and runs the
 // epilogue; the row's residual and dangling terms go to hub_red[h].
 template <typename T>
-__device__ void spmm_hub_finish(const SpmmArgs& p, int4 hub, int h, int chunk, int sp0, T acc, int lane, bool on,
-                                T cfac) {
+__device__ void spmm_hub_finish(const SpmmArgs& p, int4 hub, int h, int chunk, int sp0, T acc, int lane, bool have,
+                                bool live, T cfac) {
+  const bool on = live;  // frozen columns need no sum
   if (on) publish(&p.hub_sum[(int64_t)(hub.z + chunk) * 64 + lane], (double)acc);
   wait_stores();
   int last = 0;
@@ -96,8 +103,8 @@ __device__ void spmm_hub_finish(const SpmmArgs& p, int4 hub, int h, int chunk, i
   int sp = sp0;
   int nsv = sp < p.nseeds ? p.seed_v[sp] : 0x7fffffff;
   double hr = 0.0, hd = 0.0;
-  spmm_finish<T>(p, hub.x, s, lane, on, cfac, load_xo<T>(p, hub.x, lane, on), load_dv<T>(p, hub.x), sp, nsv, hr,
-                 hd);
+  spmm_finish<T>(p, hub.x, s, lane, have, live, cfac, load_xo<T>(p, hub.x, lane, have), load_dv<T>(p, hub.x), sp,
+                 nsv, hr, hd);
   publish(&p.hub_red[(int64_t)h * 128 + lane], hr);
   publish(&p.hub_red[(int64_t)h * 128 + 64 + lane], hd);
   if (lane == 0) publish(&p.hub_cnt[h], 0);
@@ -197,25 +204,28 @@ __device__ __forceinline__ int row_off(const RowBufs& b, int i) { return (int)((
 
 // spmm_finish with buffer-addressed rows.
 template <typename T>
-__device__ __forceinline__ void spmm_finish_b(const SpmmArgs& p, const RowBufs& b, int i, T s, int lane, bool on,
-                                              T cfac, T xo, T dv, int& sp, int& nsv, double& rho, double& dm) {
+__device__ __forceinline__ void spmm_finish_b(const SpmmArgs& p, const RowBufs& b, int i, T s, int lane, bool have,
+                                              bool live, T cfac, T xo, T dv, int& sp, int& nsv, double& rho,
+                                              double& dm) {
   T tele = 0;
   while (nsv == i) {
     if (wave_uniform(p.seed_c[sp]) == lane) tele += (T)wave_uniform(p.seed_w[sp]) * cfac;
     ++sp;
     nsv = sp < p.nseeds ? wave_uniform(p.seed_v[sp]) : 0x7fffffff;
   }
-  if (!on) return;
+  if (!have) return;
   const int so = row_off(b, i);
   if (p.plain) {
     buf_store<T, CP_NT>(b.xn, s, b.voff, so);
     return;
   }
-  const T r = s + tele;
+  const T r = live ? s + tele : xo;
   buf_store<T, CP_NT>(b.xn, r, b.voff, so);
   buf_store<T, 0>(b.wn, r * dv, b.voff, so);
-  rho += fabs((double)xo - (double)r);
-  if (dv == (T)0) dm += (double)r;
+  if (live) {
+    rho += fabs((double)xo - (double)r);
+    if (dv == (T)0) dm += (double)r;
+  }
 }
 
 template <typename T>
@@ -231,7 +241,10 @@ struct GatherDepth<double> {
 // time; the tile's column indices are read 64 at a time into one register
 // (lane q holds entry q of the chunk) and broadcast with readlane, so every
 // gathered row costs one scalar offset and one vector load, with U rows in
-// flight.  The tile's row pointers sit in wave-private LDS.
+// flight.  The tile's row pointers sit in wave-private LDS.  With
+// p.skip_empty, a row with no entries and no seed is not touched: its x and
+// w are zero in both buffer sets (the caller keeps them so), and it adds
+// nothing to the residual or the dangling mass.
 template <typename T>
 __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void spmm_ppr_kernel(
     TilePlanDev plan, SpmmArgs p, const GuardDev* guard) {
@@ -243,17 +256,19 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
   __shared__ int srp[SNW][TR + 1];
   __shared__ int sflag;
   const int tid = threadIdx.x, wv = wave_uniform(tid >> 6), lane = tid & 63;
-  const bool on = column_live(p, lane);
+  const bool have = lane < p.k;
+  const bool live = column_live(p, lane);
   const bool plain = p.plain != 0;
+  const bool skip = p.skip_empty != 0 && !plain;
   RowBufs b;
   b.row_bytes = (unsigned)p.k * (unsigned)sizeof(T);
-  b.voff = on ? lane * (int)sizeof(T) : 0;
+  b.voff = have ? lane * (int)sizeof(T) : 0;
   b.w = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.w), (short)0, (int)p.w_bytes, 0x00020000);
   b.xo = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.x_old), (short)0, (int)p.w_bytes, 0x00020000);
   b.xn = __builtin_amdgcn_make_buffer_rsrc(p.x_new, (short)0, (int)p.w_bytes, 0x00020000);
   b.wn = __builtin_amdgcn_make_buffer_rsrc(p.w_new, (short)0, (int)p.w_bytes, 0x00020000);
   T cfac = (T)0;
-  if (on) cfac = (T)(p.c_beta + (p.d_prev ? p.c_alpha * p.d_prev[lane] : 0.0));
+  if (live) cfac = (T)(p.c_beta + (p.d_prev ? p.c_alpha * p.d_prev[lane] : 0.0));
   double rho = 0.0, dm = 0.0;
   int* wrp = srp[wv];
 
@@ -261,20 +276,26 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
   for (int t = (int)blockIdx.x * SNW + wv; t < plan.ntiles; t += nwaves) {
     const int4 td = wave_uniform(plan.tiles[t]);
     const int e0 = td.z, ne = td.w;
-    int colv = lane < ne ? p.col[e0 + lane] : 0;
     if (td.y > 0) {
       const int row0 = td.x, nr = td.y;
+      int sp = wave_uniform(first_seed(p, t));
+      int nsv = sp < p.nseeds ? wave_uniform(p.seed_v[sp]) : 0x7fffffff;
+      if (skip && ne == 0 && nsv >= row0 + nr) continue;  // rows without entries or seeds
+      int colv = lane < ne ? p.col[e0 + lane] : 0;
       for (int q = lane; q <= nr; q += 64) wrp[q] = p.rowptr[row0 + q] - e0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      int sp = wave_uniform(first_seed(p, t));
-      int nsv = sp < p.nseeds ? wave_uniform(p.seed_v[sp]) : 0x7fffffff;
       int r = 0;
       int rend = wave_uniform(wrp[1]);
+      // row r is left untouched: no entries, no seed
+      bool idle = skip && rend == 0 && nsv != row0;
       T acc = 0;
-      T xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0));
-      T dv = wave_uniform(load_dv<T>(p, row0));
+      T xo = (T)0, dv = (T)0;
+      if (!idle) {
+        xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0));
+        dv = wave_uniform(load_dv<T>(p, row0));
+      }
       for (int c0 = 0; c0 < ne; c0 += 64) {
         const int cn = c0 + 64 + lane;
         const int coln = cn < ne ? p.col[e0 + cn] : 0;
@@ -290,12 +311,16 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
             const int e = base + u;
             if (e < ne) {
               while (e == rend) {
-                spmm_finish_b<T>(p, b, row0 + r, acc, lane, on, cfac, xo, dv, sp, nsv, rho, dm);
+                if (!idle) spmm_finish_b<T>(p, b, row0 + r, acc, lane, have, live, cfac, xo, dv, sp, nsv, rho, dm);
                 acc = 0;
                 ++r;
+                const int rbeg = rend;
                 rend = wave_uniform(wrp[r + 1]);
-                xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
-                dv = wave_uniform(load_dv<T>(p, row0 + r));
+                idle = skip && rend == rbeg && nsv != row0 + r;
+                if (!idle) {
+                  xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
+                  dv = wave_uniform(load_dv<T>(p, row0 + r));
+                }
               }
               acc += v[u];
             }
@@ -304,18 +329,23 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
         colv = coln;
       }
       while (r < nr) {  // last row with entries, then empty rows
-        spmm_finish_b<T>(p, b, row0 + r, acc, lane, on, cfac, xo, dv, sp, nsv, rho, dm);
+        if (!idle) spmm_finish_b<T>(p, b, row0 + r, acc, lane, have, live, cfac, xo, dv, sp, nsv, rho, dm);
         acc = 0;
         ++r;
         if (r < nr) {
-          xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
-          dv = wave_uniform(load_dv<T>(p, row0 + r));
+          // every row from here on has no entries
+          idle = skip && nsv != row0 + r;
+          if (!idle) {
+            xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
+            dv = wave_uniform(load_dv<T>(p, row0 + r));
+          }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();  // the next tile rewrites wrp
     } else {
       const int h = -td.y - 1;
+      int colv = lane < ne ? p.col[e0 + lane] : 0;
       T acc = 0;
       for (int c0 = 0; c0 < ne; c0 += 64) {
         const int cn = c0 + 64 + lane;
@@ -333,15 +363,162 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void sp
         }
         colv = coln;
       }
-      spmm_hub_finish<T>(p, wave_uniform(plan.hubs[h]), h, td.x, wave_uniform(first_seed(p, t)), acc, lane, on,
-                         cfac);
+      spmm_hub_finish<T>(p, wave_uniform(plan.hubs[h]), h, td.x, wave_uniform(first_seed(p, t)), acc, lane, have,
+                         live, cfac);
+    }
+  }
+  if (!plain) spmm_reduce(plan, p, rho, dm, sr, sd, &sflag);
+}
+
+// Sum of v over the G = 64 / KP lane groups of a wavefront: every lane ends
+// with the sum for its column c = lane % KP.
+template <int KP, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = KP; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// The buffer-addressed pass for k <= KP columns (KP = 4, 8 or 16): the
+// wavefront splits into G = 64 / KP lane groups of KP lanes, lane (g, c)
+// owning column c of entry g of each group of G consecutive entries, so
+// one vector load gathers G rows of W.  A row's partial sums are added
+// across the groups when it ends; group 0 then runs the epilogue, exactly
+// as lane c of the one-entry-per-load pass would (same stores, residual,
+// seeds and hub handling).  Narrow column counts would otherwise leave
+// most lanes of every gathering load idle.
+template <typename T, int KP>
+__global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void spmm_packed_kernel(
+    TilePlanDev plan, SpmmArgs p, const GuardDev* guard) {
+  constexpr int TR = WAVE_TILE_ROWS, G = 64 / KP, STEPS = 64 / G;  // STEPS groups of G entries per chunk
+  constexpr int UNR = (sizeof(T) == 8 && STEPS > 8) ? 4 : STEPS;     // gathers in flight
+  static_assert(KP == 4 || KP == 8 || KP == 16, "lane group width");
+  if (guard && guard->active == 0) return;
+  __shared__ double sr[SNW][64];
+  __shared__ double sd[SNW][64];
+  __shared__ int srp[SNW][TR + 1];
+  __shared__ int sflag;
+  const int tid = threadIdx.x, wv = wave_uniform(tid >> 6), lane = tid & 63;
+  const int grp = lane / KP, c = lane % KP;
+  const bool gather = c < p.k;                  // lane loads a real column
+  const bool have = grp == 0 && c < p.k;        // lane owns column c in the epilogue
+  const bool live = grp == 0 && column_live(p, c);
+  const bool plain = p.plain != 0;
+  const bool skip = p.skip_empty != 0 && !plain;
+  RowBufs b;
+  b.row_bytes = (unsigned)p.k * (unsigned)sizeof(T);
+  b.voff = have ? lane * (int)sizeof(T) : 0;    // lane == c in group 0
+  const unsigned coff = gather ? (unsigned)c * (unsigned)sizeof(T) : 0u;
+  b.w = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.w), (short)0, (int)p.w_bytes, 0x00020000);
+  b.xo = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.x_old), (short)0, (int)p.w_bytes, 0x00020000);
+  b.xn = __builtin_amdgcn_make_buffer_rsrc(p.x_new, (short)0, (int)p.w_bytes, 0x00020000);
+  b.wn = __builtin_amdgcn_make_buffer_rsrc(p.w_new, (short)0, (int)p.w_bytes, 0x00020000);
+  T cfac = (T)0;
+  if (live) cfac = (T)(p.c_beta + (p.d_prev ? p.c_alpha * p.d_prev[c] : 0.0));
+  double rho = 0.0, dm = 0.0;
+  int* wrp = srp[wv];
+
+  const int nwaves = (int)gridDim.x * SNW;
+  for (int t = (int)blockIdx.x * SNW + wv; t < plan.ntiles; t += nwaves) {
+    const int4 td = wave_uniform(plan.tiles[t]);
+    const int e0 = td.z, ne = td.w;
+    const bool rows = td.y > 0;
+    const int row0 = td.x, nr = td.y;
+    int sp = wave_uniform(first_seed(p, t));
+    int nsv = sp < p.nseeds ? wave_uniform(p.seed_v[sp]) : 0x7fffffff;
+    if (rows && skip && ne == 0 && nsv >= row0 + nr) continue;  // rows without entries or seeds
+    int colv = lane < ne ? p.col[e0 + lane] : 0;
+    int r = 0, rend = 0x7fffffff;
+    bool idle = false;
+    T xo = (T)0, dv = (T)0;
+    if (rows) {
+      for (int q = lane; q <= nr; q += 64) wrp[q] = p.rowptr[row0 + q] - e0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      rend = wave_uniform(wrp[1]);
+      idle = skip && rend == 0 && nsv != row0;
+      if (!idle) {
+        xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0));
+        dv = wave_uniform(load_dv<T>(p, row0));
+      }
+    }
+    T acc = 0;
+    for (int c0 = 0; c0 < ne; c0 += 64) {
+      const int cn = c0 + 64 + lane;
+      const int coln = cn < ne ? p.col[e0 + cn] : 0;
+#pragma unroll
+      for (int s0 = 0; s0 < STEPS; s0 += UNR) {
+      if (c0 + s0 * G >= ne) break;
+      T v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        // entry c0 + s*G + grp, its column index taken from lane s*G + grp
+        const int q = (s0 + u) * G + grp;
+        const int cj = __builtin_amdgcn_ds_bpermute(q * 4, colv);
+        const unsigned off = (c0 + q < ne) ? (unsigned)cj * b.row_bytes + coff : BUF_SKIP;
+        v[u] = buf_load<T, 0>(b.w, off);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int eb = c0 + (s0 + u) * G;  // first entry of this group of G
+        if (eb >= ne) break;
+        T val = v[u];
+        // rows that end inside this group, before the tile's last entry
+        // (the last row with entries is finished after the loop): their
+        // entries are the ones below rend
+        const int lim = min(eb + G, ne);
+        while (rend < lim) {
+          const bool mine = eb + grp < rend;
+          acc += mine ? val : (T)0;
+          val = mine ? (T)0 : val;
+          const int rbeg = wave_uniform(wrp[r]);
+          const T tot = rend == rbeg ? (T)0 : group_sum<KP>(acc);
+          if (!idle) spmm_finish_b<T>(p, b, row0 + r, tot, lane, have, live, cfac, xo, dv, sp, nsv, rho, dm);
+          acc = 0;
+          ++r;
+          const int nb = rend;
+          rend = wave_uniform(wrp[r + 1]);
+          idle = skip && rend == nb && nsv != row0 + r;
+          if (!idle) {
+            xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
+            dv = wave_uniform(load_dv<T>(p, row0 + r));
+          }
+        }
+        acc += val;
+      }
+      }
+      colv = coln;
+    }
+    if (rows) {
+      while (r < nr) {  // last row with entries, then empty rows
+        const T tot = wave_uniform(wrp[r + 1]) == wave_uniform(wrp[r]) ? (T)0 : group_sum<KP>(acc);
+        if (!idle) spmm_finish_b<T>(p, b, row0 + r, tot, lane, have, live, cfac, xo, dv, sp, nsv, rho, dm);
+        acc = 0;
+        ++r;
+        if (r < nr) {
+          idle = skip && nsv != row0 + r;  // every row from here on has no entries
+          if (!idle) {
+            xo = plain ? (T)0 : buf_load<T, CP_NT>(b.xo, b.voff, row_off(b, row0 + r));
+            dv = wave_uniform(load_dv<T>(p, row0 + r));
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();  // the next tile rewrites wrp
+    } else {
+      const int h = -td.y - 1;
+      acc = group_sum<KP>(acc);
+      spmm_hub_finish<T>(p, wave_uniform(plan.hubs[h]), h, td.x, sp, acc, lane, have, live, cfac);
     }
   }
   if (!plain) spmm_reduce(plan, p, rho, dm, sr, sd, &sflag);
 }
 
 // The same pass with 64-bit addressing, for operands of 4 GiB or more: the
-// tile's column indices are staged in wave-private LDS.
+// tile's column indices are staged in wave-private LDS.  It stores every
+// row (p.skip_empty is not used), which leaves the zero rows the
+// buffer-addressed pass relies on in place.
 template <typename T>
 __global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArgs p, const GuardDev* guard) {
   constexpr int TE = WAVE_TILE_ENTRIES, TR = WAVE_TILE_ROWS, U = 16;
@@ -352,10 +529,11 @@ __global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArg
   __shared__ int srp[SNW][TR + 1];
   __shared__ int sflag;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const bool on = column_live(p, lane);
+  const bool have = lane < p.k;
+  const bool live = column_live(p, lane);
   const T* W = (const T*)p.w;
   T cfac = (T)0;
-  if (on) cfac = (T)(p.c_beta + (p.d_prev ? p.c_alpha * p.d_prev[lane] : 0.0));
+  if (live) cfac = (T)(p.c_beta + (p.d_prev ? p.c_alpha * p.d_prev[lane] : 0.0));
   double rho = 0.0, dm = 0.0;
   int* wcol = scol[wv];
   int* wrp = srp[wv];
@@ -375,7 +553,7 @@ __global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArg
     int nsv = sp < p.nseeds ? p.seed_v[sp] : 0x7fffffff;
     const int row0 = td.x, nr = td.y;
     int rend = td.y > 0 ? wrp[1] : 0x7fffffff;
-    T xo = td.y > 0 ? load_xo<T>(p, row0, lane, on) : (T)0;
+    T xo = td.y > 0 ? load_xo<T>(p, row0, lane, have) : (T)0;
     T dv = td.y > 0 ? load_dv<T>(p, row0) : (T)0;
     for (int base = 0; base < ne; base += U) {
       int cj[U];
@@ -389,17 +567,17 @@ __global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArg
       }
       T v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = (on && base + u < ne) ? W[(int64_t)cj[u] * p.k + lane] : (T)0;
+      for (int u = 0; u < U; ++u) v[u] = (live && base + u < ne) ? W[(int64_t)cj[u] * p.k + lane] : (T)0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = base + u;
         if (e < ne) {
           while (e == rend) {
-            spmm_finish<T>(p, row0 + r, acc, lane, on, cfac, xo, dv, sp, nsv, rho, dm);
+            spmm_finish<T>(p, row0 + r, acc, lane, have, live, cfac, xo, dv, sp, nsv, rho, dm);
             acc = 0;
             ++r;
             rend = wrp[r + 1];
-            xo = load_xo<T>(p, row0 + r, lane, on);
+            xo = load_xo<T>(p, row0 + r, lane, have);
             dv = load_dv<T>(p, row0 + r);
           }
           acc += v[u];
@@ -408,17 +586,17 @@ __global__ __launch_bounds__(SB) void spmm_wide_kernel(TilePlanDev plan, SpmmArg
     }
     if (td.y > 0) {
       while (r < nr) {
-        spmm_finish<T>(p, row0 + r, acc, lane, on, cfac, xo, dv, sp, nsv, rho, dm);
+        spmm_finish<T>(p, row0 + r, acc, lane, have, live, cfac, xo, dv, sp, nsv, rho, dm);
         acc = 0;
         ++r;
         if (r < nr) {
-          xo = load_xo<T>(p, row0 + r, lane, on);
+          xo = load_xo<T>(p, row0 + r, lane, have);
           dv = load_dv<T>(p, row0 + r);
         }
       }
     } else {
       const int h = -td.y - 1;
-      spmm_hub_finish<T>(p, plan.hubs[h], h, td.x, sp, acc, lane, on, cfac);
+      spmm_hub_finish<T>(p, plan.hubs[h], h, td.x, sp, acc, lane, have, live, cfac);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();  // the next tile rewrites wcol / wrp
@@ -580,14 +758,31 @@ hipError_t launch_spmm_ppr(const TilePlanDev& plan, const SpmmArgs& a, int type,
   if (grid <= 0 || a.k < 1 || a.k > 64 || (a.nseeds > 0 && !a.tile_seed)) return hipErrorInvalidValue;
   if (!a.plain && (!a.x_old || !a.dvec || !a.w_new || !a.rho_out || !a.d_out)) return hipErrorInvalidValue;
   const bool wide = a.w_bytes == 0;  // operand of 4 GiB or more
-  if (type == T_FP32) {
-    if (wide)
+  if (wide) {
+    if (type == T_FP32)
       hipLaunchKernelGGL(spmm_wide_kernel<float>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
+    else
+      hipLaunchKernelGGL(spmm_wide_kernel<double>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
+    return hipGetLastError();
+  }
+  // k <= 16 columns: several entries per gathering load
+  const int kp = a.k <= 4 ? 4 : a.k <= 8 ? 8 : a.k <= 16 ? 16 : 64;
+  if (type == T_FP32) {
+    if (kp == 4)
+      hipLaunchKernelGGL((spmm_packed_kernel<float, 4>), dim3(grid), dim3(SB), 0, s, plan, a, guard);
+    else if (kp == 8)
+      hipLaunchKernelGGL((spmm_packed_kernel<float, 8>), dim3(grid), dim3(SB), 0, s, plan, a, guard);
+    else if (kp == 16)
+      hipLaunchKernelGGL((spmm_packed_kernel<float, 16>), dim3(grid), dim3(SB), 0, s, plan, a, guard);
     else
       hipLaunchKernelGGL(spmm_ppr_kernel<float>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
   } else {
-    if (wide)
-      hipLaunchKernelGGL(spmm_wide_kernel<double>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
+    if (kp == 4)
+      hipLaunchKernelGGL((spmm_packed_kernel<double, 4>), dim3(grid), dim3(SB), 0, s, plan, a, guard);
+    else if (kp == 8)
+      hipLaunchKernelGGL((spmm_packed_kernel<double, 8>), dim3(grid), dim3(SB), 0, s, plan, a, guard);
+    else if (kp == 16)
+      hipLaunchKernelGGL((spmm_packed_kernel<double, 16>), dim3(grid), dim3(SB), 0, s, plan, a, guard);
     else
       hipLaunchKernelGGL(spmm_ppr_kernel<double>, dim3(grid), dim3(SB), 0, s, plan, a, guard);
   }

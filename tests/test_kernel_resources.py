@@ -36,7 +36,7 @@ def _resources(src, tmp_path):
 @pytest.mark.skipif(not shutil.which(HIPCC) and not os.path.exists(HIPCC), reason="hipcc not found")
 @pytest.mark.parametrize("src,kernels", [
     ("kernels.hip", ("fused_wave_kernel", "fused_pr_kernel")),
-    ("spmm.hip", ("spmm_ppr_kernel",)),
+    ("spmm.hip", ("spmm_ppr_kernel", "spmm_packed_kernel")),
     ("many.hip", ("pr_many_kernel",)),
     ("stripe.hip", ("fused_stripe_kernel",)),
 ])
