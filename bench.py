@@ -208,6 +208,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
                     help="target length of the one-thread CPU oracle sample (whole solves)")
     ap.add_argument("--ppr-k", type=int, default=64, help="seed sets of the batched PPR leg")
+    ap.add_argument("--ppr-itermax", type=int, default=1000,
+                    help="pass limit of the batched and sequential PPR solves (with --tol 0 every column "
+                         "runs this many passes at full width: a fixed-width run for profiling)")
     ap.add_argument("--ppr-stream", type=int, default=512,
                     help="seed sets streamed through the ppr-k column slots (0: skip)")
     ap.add_argument("--many", type=int, default=256, help="graphs of the many-graph leg")
@@ -383,7 +386,7 @@ def main():
             sets = [s.tolist() for s in synthetic.ppr_seed_sets(n, args.ppr_k, seed=7)]
             f32 = grb.builtin("GrB_FP32")
             X = torch.empty(n * len(sets), dtype=torch.float32, device="cuda")
-            grb.GrM_ppr_batch(X, f32, sets, g.AT, g.outdeg, DAMPING, args.tol, 1000)  # warm-up
+            grb.GrM_ppr_batch(X, f32, sets, g.AT, g.outdeg, DAMPING, args.tol, args.ppr_itermax)  # warm-up
             torch.cuda.synchronize()
             reps = 3
             e0 = torch.cuda.Event(enable_timing=True)
@@ -391,7 +394,7 @@ def main():
             e0.record(stream)
             for _ in range(reps):
                 pit, col_it, col_res = grb.GrM_ppr_batch(X, f32, sets, g.AT, g.outdeg, DAMPING,
-                                                         args.tol, 1000)
+                                                         args.tol, args.ppr_itermax)
             e1.record(stream)
             torch.cuda.synchronize()
             batch_ms = e0.elapsed_time(e1) / reps
@@ -405,7 +408,7 @@ def main():
                 vv = api.vector_from_tensor(v)
                 torch.cuda.synchronize()
                 e0.record(stream)
-                grb.GrM_ppr(r, g.AT, g.outdeg, vv, DAMPING, args.tol, 1000)
+                grb.GrM_ppr(r, g.AT, g.outdeg, vv, DAMPING, args.tol, args.ppr_itermax)
                 e1.record(stream)
                 torch.cuda.synchronize()
                 seq_ms += e0.elapsed_time(e1)

@@ -391,9 +391,11 @@ struct PprColumns {
 
   // Start columns `cols` (their seeds listed by column in seeds_by_col) in
   // buffer set `cur`: x = v, w = v .* d, D = dangling seed mass, hit = -1.
-  void start_columns(uint64_t cols, int cur, const std::vector<PprSeed>& seeds_by_col) {
+  // `zeroed`: those columns of set `cur` are zero already (set 0 is, right
+  // after setup).
+  void start_columns(uint64_t cols, int cur, const std::vector<PprSeed>& seeds_by_col, bool zeroed = false) {
     Ctx& c = ctx();
-    hip_check(launch_spmm_zero_columns(Xb[cur]->p, Wb[cur]->p, T, n, k, cols, c.stream), "zero columns");
+    if (!zeroed) hip_check(launch_spmm_zero_columns(Xb[cur]->p, Wb[cur]->p, T, n, k, cols, c.stream), "zero columns");
     std::vector<int> ptr(k + 1, 0), v;
     std::vector<double> w;
     for (int col = 0; col < k; ++col) {
@@ -437,7 +439,7 @@ struct PprColumns {
     const int cur = pass & 1;
     ColumnMap map;
     for (int j = 0; j < 64; ++j) map.c[j] = j < (int)keep.size() ? keep[(size_t)j] : -1;
-    hip_check(launch_spmm_compact(Xb[cur]->p, Wb[cur]->p, (const double*)Db[cur]->p, Xb[cur ^ 1]->p,
+    hip_check(launch_spmm_compact(Xb[cur]->p, a.dvec, (const double*)Db[cur]->p, Xb[cur ^ 1]->p,
                                   Wb[cur ^ 1]->p, (double*)Db[cur ^ 1]->p, (int*)hit->p, T, n, k, k2, map,
                                   ctx().stream),
               "narrow columns");
@@ -505,7 +507,7 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
     for (int e = seed_ptr[q]; e < seed_ptr[q + 1]; ++e) seeds.push_back({pc.exec_vertex(seed_vtx[e]), q, w});
   }
   pc.set_seeds(seeds);
-  pc.start_columns(k == 64 ? ~0ull : ((1ull << k) - 1ull), 0, seeds);
+  pc.start_columns(k == 64 ? ~0ull : ((1ull << k) - 1ull), 0, seeds, true);
   hip_check(launch_guard_init((GuardDev*)pc.gbuf->p, (1.0 > tol && itermax > 0) ? 1 : 0, tol, itermax, c.stream),
             "guard init");
   launch_mark(false);

@@ -350,13 +350,14 @@ struct ColumnInputs {
   int64_t ld;
 };
 hipError_t launch_columns_in(const ColumnInputs& ins, int nc, int type, int64_t n, void* out, hipStream_t s);
-// New column j < k2 of the n x k2 arrays x2, w2 = column map.c[j] of the
-// n x k arrays x, w (map.c[j] < 0: zeros); d2[j] = d[map.c[j]] (0 when
-// empty); hit[j] = -1 for a mapped column, 0 (frozen) otherwise, j < 64.
+// New column j < k2 of the n x k2 array x2 = column map.c[j] of the n x k
+// array x (map.c[j] < 0: zeros), w2 = x2 .* dvec (dvec: n entries of the
+// same type); d2[j] = d[map.c[j]] (0 when empty); hit[j] = -1 for a mapped
+// column, 0 (frozen) otherwise, j < 64.
 struct ColumnMap {
   int c[64];
 };
-hipError_t launch_spmm_compact(const void* x, const void* w, const double* d, void* x2, void* w2, double* d2,
+hipError_t launch_spmm_compact(const void* x, const void* dvec, const double* d, void* x2, void* w2, double* d2,
                                int* hit, int type, int64_t n, int k, int k2, const ColumnMap& map, hipStream_t s);
 // x[idx[j]] = v for j < cnt (x of `type` FP32 or FP64).
 hipError_t launch_scatter_value(void* x, int type, const int* idx, int cnt, double v, hipStream_t s);

@@ -662,20 +662,31 @@ __global__ void zero_columns_kernel(void* __restrict__ x, void* __restrict__ w, 
 
 // 64 rows per workgroup: the selected columns of the rows go through LDS
 // (column c read from in1 when bit c of from1 is set, else from in0), then
-// each leaves as 64 values at stride outs.ld.
+// each leaves as 64 values at stride outs.ld.  Each thread issues its 16
+// loads before it stores any of them, so a workgroup has its whole tile in
+// flight.
 template <typename T>
 __global__ __launch_bounds__(256) void columns_out_kernel(const T* __restrict__ in0, const T* __restrict__ in1,
                                                           uint64_t from1, const int* __restrict__ idx, int64_t n,
                                                           int k, uint64_t cols, ColumnOutputs outs) {
   __shared__ T tile[64][65];
   const int64_t r0 = (int64_t)blockIdx.x * 64;
-  for (int q = threadIdx.x; q < 64 * 64; q += 256) {
-    const int r = q >> 6, c = q & 63;
+  T v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int q = (int)threadIdx.x + 256 * j;
+    const int r = q >> 6, c = q & 63;  // one row per wavefront and step
     const int64_t i = r0 + r;
+    v[j] = (T)0;
     if (i < n && c < k && ((cols >> c) & 1ull)) {
       const T* in = ((from1 >> c) & 1ull) ? in1 : in0;
-      tile[r][c] = in[(idx ? (int64_t)idx[i] : i) * k + c];
+      v[j] = in[(idx ? (int64_t)idx[i] : i) * k + c];
     }
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int q = (int)threadIdx.x + 256 * j;
+    tile[q >> 6][q & 63] = v[j];
   }
   __syncthreads();
   for (int q = threadIdx.x; q < 64 * 64; q += 256) {
@@ -687,14 +698,23 @@ __global__ __launch_bounds__(256) void columns_out_kernel(const T* __restrict__ 
 
 // The reverse of columns_out: vector c < nc (n values) into column
 // ins.dst[c] of the n-row array `out` (row stride ins.ld).  64 rows per
-// workgroup go through LDS, so each vector is read in whole lines.
+// workgroup go through LDS, so each vector is read in whole lines and,
+// when nc = ins.ld, each row of `out` is written whole.
 template <typename T>
 __global__ __launch_bounds__(256) void columns_in_kernel(ColumnInputs ins, int nc, int64_t n, T* __restrict__ out) {
   __shared__ T tile[64][65];
   const int64_t r0 = (int64_t)blockIdx.x * 64;
-  for (int q = threadIdx.x; q < 64 * 64; q += 256) {
-    const int c = q >> 6, r = q & 63;
-    if (c < nc && r0 + r < n) tile[r][c] = ((const T*)ins.in[c])[r0 + r];
+  T v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int q = (int)threadIdx.x + 256 * j;
+    const int c = q >> 6, r = q & 63;  // one vector per wavefront and step
+    v[j] = (c < nc && r0 + r < n) ? ((const T*)ins.in[c])[r0 + r] : (T)0;
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int q = (int)threadIdx.x + 256 * j;
+    tile[q & 63][q >> 6] = v[j];
   }
   __syncthreads();
   for (int q = threadIdx.x; q < 64 * 64; q += 256) {
@@ -703,16 +723,19 @@ __global__ __launch_bounds__(256) void columns_in_kernel(ColumnInputs ins, int n
   }
 }
 
-// Columns map[j] (j < k2; map[j] < 0: an empty column) of the n x k arrays
-// x, w into the n x k2 arrays x2, w2, with their dangling masses; hit of
-// the new columns: -1 for a live one, 0 (frozen) for an empty one.  One
-// wavefront per row, lane j owns new column j.
+// Columns map[j] (j < k2; map[j] < 0: an empty column) of the n x k
+// iterate x into the n x k2 arrays x2 and w2 = x2 .* d (the product the
+// pass stores, so w2 equals the pre-scaled copy it replaces), with the
+// dangling masses; hit of the new columns: -1 for a live one, 0 (frozen)
+// for an empty one.  One wavefront per row and four rows in flight, lane j
+// owns new column j.
 template <typename T>
-__global__ __launch_bounds__(256) void compact_columns_kernel(const T* __restrict__ x, const T* __restrict__ w,
+__global__ __launch_bounds__(256) void compact_columns_kernel(const T* __restrict__ x, const T* __restrict__ dvec,
                                                               const double* __restrict__ d, T* __restrict__ x2,
                                                               T* __restrict__ w2, double* __restrict__ d2,
                                                               int* __restrict__ hit, int64_t n, int k, int k2,
                                                               ColumnMap map) {
+  constexpr int R = 4;
   const int lane = threadIdx.x & 63;
   const int src = lane < k2 ? map.c[lane] : -1;
   if (blockIdx.x == 0 && threadIdx.x < 64) {
@@ -720,10 +743,23 @@ __global__ __launch_bounds__(256) void compact_columns_kernel(const T* __restric
     hit[lane] = (lane < k2 && src >= 0) ? -1 : 0;
   }
   if (lane >= k2) return;
-  const int64_t per_step = (int64_t)gridDim.x * (blockDim.x / 64);
-  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < n; i += per_step) {
-    x2[i * k2 + lane] = src >= 0 ? x[i * k + src] : (T)0;
-    w2[i * k2 + lane] = src >= 0 ? w[i * k + src] : (T)0;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t i0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * R; i0 < n; i0 += waves * R) {
+    T v[R], dv[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = i0 + u;
+      v[u] = (i < n && src >= 0) ? x[i * k + src] : (T)0;
+      dv[u] = i < n ? dvec[i] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = i0 + u;
+      if (i < n) {
+        x2[i * k2 + lane] = v[u];
+        w2[i * k2 + lane] = v[u] * dv[u];
+      }
+    }
   }
 }
 
@@ -840,20 +876,20 @@ hipError_t launch_columns_in(const ColumnInputs& ins, int nc, int type, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_spmm_compact(const void* x, const void* w, const double* d, void* x2, void* w2, double* d2,
+hipError_t launch_spmm_compact(const void* x, const void* dvec, const double* d, void* x2, void* w2, double* d2,
                                int* hit, int type, int64_t n, int k, int k2, const ColumnMap& map, hipStream_t s) {
   if (k < 1 || k > 64 || k2 < 1 || k2 > 64) return hipErrorInvalidValue;
   for (int j = 0; j < k2; ++j)
     if (map.c[j] >= k) return hipErrorInvalidValue;
-  int64_t g = (n + 3) / 4;  // four rows per 256-thread workgroup and step
+  int64_t g = (n + 15) / 16;  // four wavefronts of four rows per 256-thread workgroup and step
   if (g > 16384) g = 16384;
   if (g < 1) g = 1;
   if (type == T_FP32)
     hipLaunchKernelGGL(compact_columns_kernel<float>, dim3((int)g), dim3(256), 0, s, (const float*)x,
-                       (const float*)w, d, (float*)x2, (float*)w2, d2, hit, n, k, k2, map);
+                       (const float*)dvec, d, (float*)x2, (float*)w2, d2, hit, n, k, k2, map);
   else
     hipLaunchKernelGGL(compact_columns_kernel<double>, dim3((int)g), dim3(256), 0, s, (const double*)x,
-                       (const double*)w, d, (double*)x2, (double*)w2, d2, hit, n, k, k2, map);
+                       (const double*)dvec, d, (double*)x2, (double*)w2, d2, hit, n, k, k2, map);
   return hipGetLastError();
 }
 
