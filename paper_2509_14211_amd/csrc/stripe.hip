@@ -163,26 +163,24 @@ __device__ __forceinline__ bool next_block(const StripePlanDev& p, int si, int s
   return false;
 }
 
-// Block b of the gathered vector into registers: piece t + j * nt of the
-// block's 16-byte pieces for j < HV, t = this thread's index among the nt
-// loading threads (the same thread stores them).
-template <int HV>
-__device__ __forceinline__ void load_block(const float* w, int ncols, int b, int t, int nt, int hv,
-                                           uint4 (&R)[HV]) {
+// Block b of the gathered vector straight into LDS buffer `buf` (no
+// registers): wavefront wv of nw writes the block's 1 KiB pieces wv,
+// wv + nw, ..., 16 bytes per lane, with memory-to-LDS loads.  Past the end
+// of the vector the loads return zeros.  The writes are complete once the
+// wavefront's vector-memory counter reaches zero (wait_block).
+__device__ __forceinline__ void dma_block(const float* w, int ncols, int b, float* buf, int wv, int nw, int lane) {
+  constexpr int PIECES = STRIPE_HB * 4 / 1024;
   const int b0 = b * STRIPE_HB;
   const int cnt = min(STRIPE_HB, ncols - b0);
   const __amdgpu_buffer_rsrc_t rb = buf_rsrc(w + b0, (unsigned)(cnt > 0 ? cnt : 0) * 4u);
-#pragma unroll
-  for (int j = 0; j < HV; ++j)
-    if (j < hv) R[j] = buf_load<uint4>(rb, (unsigned)(t + j * nt) * 16u);
+  for (int q = wv; q < PIECES; q += nw)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (__attribute__((address_space(3))) void*)(buf + q * 256), 16,
+                                             (unsigned)(q * 1024 + lane * 16), 0, 0, 0);
 }
 
-template <int HV>
-__device__ __forceinline__ void store_block(float* buf, int t, int nt, int hv, const uint4 (&R)[HV]) {
-#pragma unroll
-  for (int j = 0; j < HV; ++j)
-    if (j < hv) ((uint4*)buf)[t + j * nt] = R[j];
-}
+// This wavefront's memory-to-LDS loads (and every other load it issued)
+// have completed.
+__device__ __forceinline__ void wait_block() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Hot item (phase b, chunk j) of a hot wavefront within a stripe: chunks
 // h, h + nh, ... of each LDS block's segment in turn (h = its index among
@@ -261,19 +259,17 @@ __device__ __forceinline__ void cold_add(unsigned long long* acc, const ColdRegs
 // wg_list[wg_off[g] .. wg_off[g+1]) one after the other.  Per stripe, all
 // wavefronts first gather the entries outside the LDS blocks (software-
 // pipelined), then add the entries of each LDS block in turn.  The LDS
-// blocks of all the workgroup's stripes form one sequence: block k sits in
-// buffer k mod 2 while block k+2 is in flight into registers; block k+1,
-// loaded during the previous phase, goes into the other buffer at the end
-// of the phase (one workgroup barrier per block).
+// blocks of all the workgroup's stripes form one sequence: while block k
+// is read from buffer k mod 2, block k+1 streams from memory straight into
+// the other buffer (one workgroup barrier per block).
 template <int SP, bool PF>
 __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDev p, FusedArgs<float> a,
                                                                     const double* wsum_in, double* wsum_out,
                                                                     FusedScratch scr, const GuardDev* guard) {
   constexpr int B = STRIPE_BLOCK;
   constexpr int NW = B / 64;
-  constexpr int HV = STRIPE_HB / (4 * B);        // 16-byte pieces of a block per thread
   constexpr int ER = (STRIPE_RMAX + B - 1) / B;  // epilogue rows per thread
-  static_assert(STRIPE_HB % (4 * B) == 0, "blocks are loaded in whole 16-byte pieces per thread");
+  static_assert(STRIPE_HB % 256 == 0, "blocks are loaded in whole 1 KiB pieces");
   if (guard && guard->active == 0) return;
 
   __shared__ unsigned long long acc[STRIPE_RMAX + 1];  // slot 0 takes the padding entries
@@ -309,22 +305,12 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
   const int s_begin = p.wg_off[g], s_end = p.wg_off[g + 1];
 
   for (int i = tid; i <= STRIPE_RMAX; i += B) acc[i] = 0ull;
-  // LDS block sequence: (bsi, bb) is the block after the one in flight
+  // LDS block sequence: (bsi, bb) is the last block requested
   int kblk = 0;  // blocks consumed so far: the next one sits in hot[kblk & 1]
   int bsi = s_begin, bb = -1, bcol = 0;
-  bool have1 = false;  // block kblk + 1 is in registers R1 / R2 (by parity)
-  uint4 R1[HV], R2[HV];
-  {
-    if (s_begin < s_end && next_block(p, bsi, s_end, bb, bsi, bb, bcol)) {
-      uint4 R[HV];
-      load_block<HV>(a.w, a.ncols, bcol, tid, B, HV, R);
-      store_block<HV>(hot[0], tid, B, HV, R);
-      if (next_block(p, bsi, s_end, bb, bsi, bb, bcol)) {
-        load_block<HV>(a.w, a.ncols, bcol, tid, B, HV, R1);
-        have1 = true;
-      }
-    }
-  }
+  bool more = s_begin < s_end && next_block(p, bsi, s_end, bb, bsi, bb, bcol);
+  if (more) dma_block(a.w, a.ncols, bcol, hot[0], wv, NW, lane);
+  wait_block();
   __syncthreads();
 
   for (int si = s_begin; si < s_end; ++si) {
@@ -340,6 +326,12 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
     const __amdgpu_buffer_rsrc_t rcr = buf_rsrc(p.cold_row + cold_base, (unsigned)cold_n * 2u);
     const int segv = lane <= nb ? dp->seg[lane] : 0;
     const unsigned* hot_seg0 = p.hot + hot_base;
+    // the first chunk of this wavefront's LDS-block entries is requested
+    // now, so its latency overlaps the gathered entries below
+    HotCursor cur{0, wv};
+    hot_settle(segv, nb, wv, cur);
+    uint4 wa = make_uint4(0, 0, 0, 0), wb = make_uint4(0, 0, 0, 0);
+    if (cur.b < nb) hot_words<SP>(hot_seg0, segv, cur, lane, wa, wb);
 
     // Entries outside the LDS blocks, gathered from memory first: this
     // wavefront's chunks wv, wv + 16, ...  Three register sets rotate so the
@@ -370,19 +362,11 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
     }
 
     // entries in the LDS blocks, one block per phase
-    HotCursor cur{0, wv};
-    hot_settle(segv, nb, wv, cur);
-    uint4 wa = make_uint4(0, 0, 0, 0), wb = make_uint4(0, 0, 0, 0);
-    if (cur.b < nb) hot_words<SP>(hot_seg0, segv, cur, lane, wa, wb);
     for (int b = 0; b < nb; ++b) {
-      // block kblk + 2 of the sequence into the free register set
-      const bool more2 = have1 && next_block(p, bsi, s_end, bb, bsi, bb, bcol);
-      if (more2) {
-        if (kblk & 1)
-          load_block<HV>(a.w, a.ncols, bcol, tid, B, HV, R1);
-        else
-          load_block<HV>(a.w, a.ncols, bcol, tid, B, HV, R2);
-      }
+      // block kblk + 1 of the sequence into the other buffer, whose last
+      // readers (phase kblk - 1) passed the barrier that ended their phase
+      more = more && next_block(p, bsi, s_end, bb, bsi, bb, bcol);
+      if (more) dma_block(a.w, a.ncols, bcol, hot[(kblk + 1) & 1], wv, NW, lane);
       const float* hbuf = hot[kblk & 1];
       while (cur.b == b) {
         const uint4 ca = wa, cb = wb;
@@ -400,15 +384,7 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
         add_runs<STRIPE_K, true>(acc, row, v, kshift);
         cur = nx;
       }
-      // block kblk + 1 (loaded during the previous phase) into the other
-      // buffer, last read in the previous phase before its barrier
-      if (have1) {
-        if (kblk & 1)
-          store_block<HV>(hot[0], tid, B, HV, R2);
-        else
-          store_block<HV>(hot[1], tid, B, HV, R1);
-      }
-      have1 = more2;
+      wait_block();  // this wavefront's part of block kblk + 1 is in LDS
       __syncthreads();
       ++kblk;
     }
@@ -1024,10 +1000,17 @@ void build_stripe_plan(const MatP& A, Plan& plan, const std::vector<int>& rp) {
     d.cold_base = cold_total;
     d.cold_n = (int)pad8(cold);
     cold_total += pad8(cold);
-    // estimated cycles of one compute unit: entries added from LDS (about 2
-    // per cycle, plus a block load and barrier per LDS block), entries
-    // gathered from memory (about 0.3 per cycle), rows of the epilogue
-    cost[s] = (double)hot_e / 2.0 + nb * 700.0 + (double)cold / 0.3 + d.nrows / 4.0 + 2000.0;
+    // estimated time on one compute unit.  Gathered plan (cycles): entries
+    // added from LDS (about 2 per cycle, plus a block load and barrier per
+    // LDS block), entries gathered from memory (about 0.3 per cycle), rows
+    // of the epilogue.  Two-phase plan (ns, a least-squares fit of measured
+    // per-stripe times at R-MAT scale 22, R^2 0.996): 0.16 per LDS-block
+    // entry, 0.45 per filled entry, 820 per LDS block, 0.8 per row and
+    // 3,300 per stripe.
+    if (cfg.kernel == K_STRIPE2)
+      cost[s] = 0.163 * (double)hot_e + 0.446 * (double)cold + 823.0 * nb + 0.793 * d.nrows + 3260.0;
+    else
+      cost[s] = (double)hot_e / 2.0 + nb * 700.0 + (double)cold / 0.3 + d.nrows / 4.0 + 2000.0;
   }
   if (counted != m) fail(GrB_PANIC, "stripe plan: entry counts do not add up");
   if (hot_total >= ((int64_t)1 << 32) || cold_total >= ((int64_t)1 << 32))
