@@ -5,6 +5,7 @@
 #include <cstring>
 #include <hip/hip_runtime.h>
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 #include <rocprim/device/device_select.hpp>
 
 #include "kernels.h"
@@ -266,6 +267,19 @@ hipError_t degree_order(int64_t n, const int* col, int64_t nnz, int* order, int*
   hipLaunchKernelGGL(order_from_keys_kernel, dim3(gb_grid(n)), dim3(GB_BLOCK), 0, s, out, n, order, inv);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipStreamSynchronize(s);  // scoped temporaries are released on return
+}
+
+hipError_t scan_u32_inclusive(const unsigned* in, unsigned* out, int64_t n, AllocFn alloc, ReleaseFn release,
+                              void* actx, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  size_t tb = 0;
+  hipError_t e = rocprim::inclusive_scan(nullptr, tb, in, out, (size_t)n, rocprim::plus<unsigned>(), s);
+  if (e != hipSuccess) return e;
+  Scoped tmp(alloc, release, actx, tb + 256);
+  if (!tmp.ok(1)) return hipErrorOutOfMemory;
+  e = rocprim::inclusive_scan(tmp.p, tb, in, out, (size_t)n, rocprim::plus<unsigned>(), s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);  // the scoped temporary is released on return
 }
 
 hipError_t sort_pairs_u64_u16(const uint64_t* keys_in, uint64_t* keys_out, const uint16_t* vals_in,

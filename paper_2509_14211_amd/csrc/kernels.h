@@ -206,14 +206,21 @@ struct StripePlanDev {
 // Two-phase stripe plan: the stripes' gathered entries, listed by column
 // block and then by their slot in the stripes' arrays.  Chunk c covers list
 // entries [start, end) of column block blk; entry e's value is
-// w[blk * STRIPE_HB + src[e]] and goes to val[pos[e]].
+// w[blk * STRIPE_HB + (src[e] & 0x3FFF)] and goes to slot pos(e).  Slots
+// are stored per run: a run is a stretch of the list whose slots are
+// consecutive; bit 15 of src[e] marks the first entry of a run, and run r
+// starts at slot run_pos[r].  Chunks are cut into sub-chunks of
+// FILL_SUB entries, each starting a run; sub-chunk j of chunk c has run
+// index sub_run[c.sub0 + j] at its first entry.
+constexpr unsigned FILL_SUB = 4096;
 struct ColdChunk {
   int blk;
-  unsigned start, end, pad;
+  unsigned start, end, sub0;
 };
 struct ColdFillDev {
-  const unsigned* pos;
   const unsigned short* src;
+  const unsigned* run_pos;
+  const unsigned* sub_run;
   const ColdChunk* chunk;
   float* val;
   int nchunks;
@@ -437,6 +444,9 @@ hipError_t degree_order(int64_t n, const int* col, int64_t nnz, int* order, int*
 hipError_t permute_csr(int64_t n, const int* rowptr, const int* col, int64_t nnz, const int* inv,
                        int* rowptr2, int* col2, AllocFn alloc, ReleaseFn release, void* actx,
                        hipStream_t s);
+// out[i] = in[0] + ... + in[i] for i < n (unsigned, wrapping).  Synchronises `s`.
+hipError_t scan_u32_inclusive(const unsigned* in, unsigned* out, int64_t n, AllocFn alloc, ReleaseFn release,
+                              void* actx, hipStream_t s);
 // Sorts n (key, value) pairs by key bits [0, end_bit) (stable); the inputs
 // are left as they were.  Synchronises `s`.
 hipError_t sort_pairs_u64_u16(const uint64_t* keys_in, uint64_t* keys_out, const uint16_t* vals_in,

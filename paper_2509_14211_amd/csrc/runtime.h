@@ -107,7 +107,7 @@ struct Plan {
   StripePlanDev st_dev{};
   // two-phase stripe plan (K_STRIPE2): the gathered entries' values, and
   // the list that fills them block by block
-  BufP st_cval, st_papos, st_pasrc, st_pachunk;
+  BufP st_cval, st_pasrc, st_prun, st_psub, st_pachunk;
   ColdFillDev st_fill{};
 };
 

@@ -491,8 +491,11 @@ namespace {
 // along each stripe's group of entries from that block).
 __global__ __launch_bounds__(512) void cold_fill_kernel(ColdFillDev f, const float* __restrict__ w, int ncols,
                                                         const GuardDev* guard) {
+  constexpr int NWF = 512 / 64;
   if (guard && guard->active == 0) return;
   __shared__ __attribute__((aligned(16))) float win[STRIPE_HB];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long le = (2ull << lane) - 1ull;  // lanes up to and including this one
   for (int c = blockIdx.x; c < f.nchunks; c += gridDim.x) {
     const ColdChunk ch = f.chunk[c];
     const int b0 = ch.blk * STRIPE_HB;
@@ -505,7 +508,41 @@ __global__ __launch_bounds__(512) void cold_fill_kernel(ColdFillDev f, const flo
       for (int i = threadIdx.x; i < cnt; i += blockDim.x) win[i] = w[b0 + i];
     }
     __syncthreads();
-    for (unsigned e = ch.start + threadIdx.x; e < ch.end; e += blockDim.x) f.val[f.pos[e]] = win[f.src[e]];
+    // one wavefront per sub-chunk: an entry's run is the last run start at
+    // or before it (a ballot over the wavefront, carried between steps)
+    const unsigned nsub = (ch.end - ch.start + FILL_SUB - 1) / FILL_SUB;
+    for (unsigned j = wv; j < nsub; j += NWF) {
+      const unsigned s0 = ch.start + j * FILL_SUB, s1 = min(s0 + FILL_SUB, ch.end);
+      unsigned run = f.sub_run[ch.sub0 + j] - 1u;  // s0 starts a run
+      unsigned first = s0;
+      // U groups of 64 entries at a time: their loads are in flight together
+      constexpr int U = 8;
+      for (unsigned g0 = s0; g0 < s1; g0 += 64 * U) {
+        unsigned word[U], my_run[U], my_first[U], rp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const unsigned e = g0 + 64u * u + lane;
+          word[u] = e < s1 ? (unsigned)f.src[e] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const unsigned e0 = g0 + 64u * u;
+          const unsigned long long bw = __ballot(e0 + lane < s1 && (word[u] & 0x8000u));
+          const unsigned long long m = bw & le;
+          my_run[u] = run + (unsigned)__popcll(m);
+          my_first[u] = m ? e0 + (63u - (unsigned)__clzll(m)) : first;
+          run += (unsigned)__popcll(bw);
+          if (bw) first = e0 + (63u - (unsigned)__clzll(bw));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) rp[u] = g0 + 64u * u + lane < s1 ? f.run_pos[my_run[u]] : 0u;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const unsigned e = g0 + 64u * u + lane;
+          if (e < s1) f.val[rp[u] + (e - my_first[u])] = win[word[u] & 0x3FFFu];
+        }
+      }
+    }
   }
 }
 
@@ -514,7 +551,7 @@ __global__ __launch_bounds__(512) void cold_fill_kernel(ColdFillDev f, const flo
 hipError_t launch_cold_fill_f32(const ColdFillDev& f, const float* w, int ncols, const GuardDev* guard,
                                 hipStream_t s) {
   if (f.nchunks <= 0) return hipSuccess;
-  if (!f.pos || !f.src || !f.chunk || !f.val || !w) return hipErrorInvalidValue;
+  if (!f.src || !f.run_pos || !f.sub_run || !f.chunk || !f.val || !w) return hipErrorInvalidValue;
   const int grid = std::min(f.nchunks, std::max(1, ctx().cus) * 3);
   hipLaunchKernelGGL(cold_fill_kernel, dim3(grid), dim3(512), 0, s, f, w, ncols, guard);
   return hipGetLastError();
@@ -800,11 +837,40 @@ __global__ __launch_bounds__(256) void st_fill_keys_kernel(const unsigned* ccol,
 
 // Slots from the sorted keys, and the first list position of each column
 // block (first[b] stays 0xFFFFFFFF for a block without entries).
-__global__ void st_fill_finish_kernel(const uint64_t* keys, int64_t n, unsigned* pos, unsigned* first) {
+// Run starts of the sorted fill list: an entry whose slot does not follow
+// its predecessor's (or whose block differs) starts a run.
+__global__ void st_run_flags_kernel(const uint64_t* keys, int64_t n, unsigned* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  flag[i] = (i == 0 || keys[i] != keys[i - 1] + 1ull) ? 1u : 0u;
+}
+
+// Every sub-chunk starts a run.
+__global__ void st_sub_flags_kernel(const unsigned* sub_start, int nsub, unsigned* flag) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nsub) flag[sub_start[k]] = 1u;
+}
+
+// Run r = rank[i] - 1 of run-start entry i begins at slot pos[i]; the entry
+// carries the run-start mark.
+__global__ void st_runs_kernel(const unsigned* flag, const unsigned* rank, const uint64_t* keys, int64_t n,
+                               unsigned* run_pos, unsigned short* src) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  run_pos[rank[i] - 1u] = (unsigned)(keys[i] & 0xFFFFFFFFull);
+  src[i] = (unsigned short)(src[i] | 0x8000u);
+}
+
+// Run index at each sub-chunk's first entry.
+__global__ void st_sub_runs_kernel(const unsigned* sub_start, int nsub, const unsigned* rank, unsigned* sub_run) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nsub) sub_run[k] = rank[sub_start[k]] - 1u;
+}
+
+__global__ void st_fill_finish_kernel(const uint64_t* keys, int64_t n, unsigned* first) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint64_t k = keys[i];
-  pos[i] = (unsigned)(k & 0xFFFFFFFFull);
   const unsigned b = (unsigned)(k >> 32);
   if (i == 0 || (unsigned)(keys[i - 1] >> 32) != b) first[b] = (unsigned)i;
 }
@@ -865,19 +931,20 @@ void build_fill(const MatP& A, Plan& plan, const std::vector<int>& ncold) {
               "sort fill list");
     kin.reset();
     vin.reset();
-    plan.st_papos = dev_alloc(sizeof(unsigned) * (size_t)N);
     BufP first = dev_alloc(sizeof(unsigned) * (size_t)ncolblk);
     hip_check(launch_fill(first->p, T_INT32, ncolblk, -1.0, c.stream), "fill");
     const int64_t g = (N + 255) / 256;
     hipLaunchKernelGGL(st_fill_finish_kernel, dim3((unsigned)g), dim3(256), 0, c.stream, (const uint64_t*)kout->p,
-                       N, (unsigned*)plan.st_papos->p, (unsigned*)first->p);
+                       N, (unsigned*)first->p);
     hip_check(hipGetLastError(), "fill list");
     std::vector<unsigned> hfirst((size_t)ncolblk);
     hip_check(hipMemcpyAsync(hfirst.data(), first->p, sizeof(unsigned) * (size_t)ncolblk, hipMemcpyDeviceToHost,
                              c.stream),
               "download");
     hip_check(hipStreamSynchronize(c.stream), "sync");
-    // chunks of at most FILL_CHUNK entries of one block
+    // chunks of at most FILL_CHUNK entries of one block, cut into
+    // sub-chunks of FILL_SUB
+    std::vector<unsigned> sub_start;
     int64_t prev_b = -1;
     for (int64_t b = 0; b <= ncolblk; ++b) {
       if (b < ncolblk && hfirst[(size_t)b] == 0xFFFFFFFFu) continue;
@@ -885,11 +952,51 @@ void build_fill(const MatP& A, Plan& plan, const std::vector<int>& ncold) {
         const unsigned st = hfirst[(size_t)prev_b];
         const unsigned en = b < ncolblk ? hfirst[(size_t)b] : (unsigned)N;
         if (en < st) fail(GrB_PANIC, "stripe plan: fill list out of order");
-        for (unsigned x = st; x < en; x += FILL_CHUNK)
-          chunks.push_back(ColdChunk{(int)prev_b, x, std::min(en, x + FILL_CHUNK), 0u});
+        for (unsigned x = st; x < en; x += FILL_CHUNK) {
+          const unsigned xe = std::min(en, x + FILL_CHUNK);
+          chunks.push_back(ColdChunk{(int)prev_b, x, xe, (unsigned)sub_start.size()});
+          for (unsigned y = x; y < xe; y += FILL_SUB) sub_start.push_back(y);
+        }
       }
       prev_b = b;
     }
+    // runs of consecutive slots: each starts at an entry whose slot does
+    // not follow its predecessor's, or at a sub-chunk
+    const int nsub = (int)sub_start.size();
+    BufP flag = dev_alloc(sizeof(unsigned) * (size_t)N), rank = dev_alloc(sizeof(unsigned) * (size_t)N);
+    BufP d_sub = dev_alloc(sizeof(unsigned) * (size_t)std::max(nsub, 1));
+    if (nsub > 0)
+      hip_check(hipMemcpyAsync(d_sub->p, sub_start.data(), sizeof(unsigned) * (size_t)nsub, hipMemcpyHostToDevice,
+                               c.stream),
+                "upload");
+    hipLaunchKernelGGL(st_run_flags_kernel, dim3((unsigned)g), dim3(256), 0, c.stream, (const uint64_t*)kout->p, N,
+                       (unsigned*)flag->p);
+    hip_check(hipGetLastError(), "run starts");
+    if (nsub > 0) {
+      hipLaunchKernelGGL(st_sub_flags_kernel, dim3((nsub + 255) / 256), dim3(256), 0, c.stream,
+                         (const unsigned*)d_sub->p, nsub, (unsigned*)flag->p);
+      hip_check(hipGetLastError(), "sub-chunk starts");
+    }
+    hip_check(scan_u32_inclusive((const unsigned*)flag->p, (unsigned*)rank->p, N, cache_alloc, cache_release,
+                                 nullptr, c.stream),
+              "run ranks");
+    unsigned nruns = 0;
+    hip_check(hipMemcpyAsync(&nruns, (const unsigned*)rank->p + (N - 1), sizeof(unsigned), hipMemcpyDeviceToHost,
+                             c.stream),
+              "download");
+    hip_check(hipStreamSynchronize(c.stream), "sync");
+    plan.st_prun = dev_alloc(sizeof(unsigned) * (size_t)std::max(nruns, 1u));
+    plan.st_psub = dev_alloc(sizeof(unsigned) * (size_t)std::max(nsub, 1));
+    hipLaunchKernelGGL(st_runs_kernel, dim3((unsigned)g), dim3(256), 0, c.stream, (const unsigned*)flag->p,
+                       (const unsigned*)rank->p, (const uint64_t*)kout->p, N, (unsigned*)plan.st_prun->p,
+                       (unsigned short*)plan.st_pasrc->p);
+    hip_check(hipGetLastError(), "runs");
+    if (nsub > 0) {
+      hipLaunchKernelGGL(st_sub_runs_kernel, dim3((nsub + 255) / 256), dim3(256), 0, c.stream,
+                         (const unsigned*)d_sub->p, nsub, (const unsigned*)rank->p, (unsigned*)plan.st_psub->p);
+      hip_check(hipGetLastError(), "sub-chunk runs");
+    }
+    hip_check(hipStreamSynchronize(c.stream), "sync");
   }
   plan.st_pachunk = dev_alloc(sizeof(ColdChunk) * std::max<size_t>(chunks.size(), 1));
   if (!chunks.empty())
@@ -902,8 +1009,9 @@ void build_fill(const MatP& A, Plan& plan, const std::vector<int>& ncold) {
   plan.st_dev.cold_row = (const unsigned short*)plan.st_crow->p;
   plan.st_dev.cold_val = (const float*)plan.st_cval->p;
   ColdFillDev& f = plan.st_fill;
-  f.pos = plan.st_papos ? (const unsigned*)plan.st_papos->p : nullptr;
   f.src = plan.st_pasrc ? (const unsigned short*)plan.st_pasrc->p : nullptr;
+  f.run_pos = plan.st_prun ? (const unsigned*)plan.st_prun->p : nullptr;
+  f.sub_run = plan.st_psub ? (const unsigned*)plan.st_psub->p : nullptr;
   f.chunk = (const ColdChunk*)plan.st_pachunk->p;
   f.val = (float*)plan.st_cval->p;
   f.nchunks = (int)chunks.size();

@@ -48,7 +48,9 @@ def _check(got, ref, mag, rowlen, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-@pytest.mark.parametrize("k", [1, 7, 64])
+# k <= 16 runs the packed pass (lane groups of 4, 8 or 16 columns, several
+# entries per load): each group width at and past its edge
+@pytest.mark.parametrize("k", [1, 4, 5, 7, 8, 9, 16, 17, 64])
 def test_mxm_rmat_against_oracle(nonblocking, oracle_mod, dtype, k):
     from paper_2509_14211_amd import api
     grb = nonblocking
