@@ -535,8 +535,10 @@ GrB_Info GrM_Vector_reduce_masked_Scalar(GrB_Scalar s, GrB_Vector mask, GrB_Mono
  * PageRank drivers.  They issue the operations above (so the nonblocking
  * matcher and the plan cache are on their path) and add device-side loop
  * control so the host reads the residual only every `check_every`
- * iterations; iterations past convergence are skipped on the device, so
- * the iteration count is the same as with a check after every pass.
+ * iterations (GrM_pagerank and GrM_ppr queue two more iterations behind
+ * each read, so the device keeps working while the host decides);
+ * iterations past convergence are skipped on the device, so the iteration
+ * count is the same as with a check after every pass.
  * ---------------------------------------------------------------------- */
 
 typedef enum { GrM_DANGLING_DROP = 0, GrM_DANGLING_UNIFORM = 1 } GrM_Dangling;

@@ -316,6 +316,12 @@ GrB_Info GrB_finalize(void) {
   c.events.clear();
   for (auto e : c.event_pool) (void)hipEventDestroy(e);
   c.event_pool.clear();
+  for (auto& e : c.guard_snap_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+  if (c.guard_snap) (void)hipHostFree(c.guard_snap);
+  c.guard_snap = nullptr;
   c.tuned.clear();
   c.init = false;
   for (auto& kv : c.cache)

@@ -18,6 +18,19 @@ extern "C" {
 
 // ------------------------------------------------------------ PageRank
 
+// The context's two pinned guard-copy slots and their events.
+static GuardDev* guard_snapshots() {
+  Ctx& c = ctx();
+  if (!c.guard_snap) {
+    void* p = nullptr;
+    hip_check(hipHostMalloc(&p, 2 * sizeof(GuardDev), hipHostMallocDefault), "pinned guard slots");
+    c.guard_snap = (GuardDev*)p;
+  }
+  for (auto& e : c.guard_snap_ev)
+    if (!e) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  return c.guard_snap;
+}
+
 static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matrix AT, GrB_Vector outdeg,
                               GrB_Vector teleport, double damping, double tol, int itermax,
                               GrM_Dangling dangling, GrB_Vector x0, int check_every) {
@@ -107,13 +120,13 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
   launch_mark(false);
   c.guard = (GuardDev*)gbuf->p;
 
+  // hist[i]: the iterate after pass base + i
   std::vector<NodeP> hist{x.node};
   int64_t base = 0;
   GuardDev hg{};
-  // no pass beyond itermax is enqueued (the guard would only skip it)
-  int batch = check_every < itermax ? check_every : itermax;
-  for (;;) {
-    for (int j = 0; j < batch; ++j) {
+  int enq = 0;  // passes enqueued (never beyond itermax: the guard would only skip them)
+  auto enqueue = [&](int count) {
+    for (int j = 0; j < count; ++j) {
       GB_Vector_opaque w{MAGIC_VEC, T, n, nullptr}, s{MAGIC_VEC, T, n, nullptr};
       GB_Vector_opaque rn{MAGIC_VEC, T, n, nullptr}, t{MAGIC_VEC, T, n, nullptr};
       GB_Scalar_opaque cs{MAGIC_SCA, T_FP64, nullptr}, rho{MAGIC_SCA, T_FP64, nullptr};
@@ -152,25 +165,50 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
       set_sca(&rho, nullptr);
       set_sca(&Dn, nullptr);
     }
-    hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
-    hip_check(hipStreamSynchronize(c.stream), "sync");
+    enq += count;
+  };
+  // The guard is copied to pinned host memory after each batch, and a few
+  // more passes are queued behind the copy before the host waits for it:
+  // the device works through them while the host reads the guard and
+  // queues the next batch, instead of waiting for the host.  Passes queued
+  // past convergence are skipped by the guard.
+  constexpr int AHEAD = 2;
+  GuardDev* snap = guard_snapshots();
+  int slot = 0;
+  auto snapshot = [&]() {
+    hip_check(hipMemcpyAsync(&snap[slot], c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream),
+              "read guard");
+    hip_check(hipEventRecord(c.guard_snap_ev[slot], c.stream), "event record");
+  };
+  enqueue(check_every < itermax ? check_every : itermax);
+  snapshot();
+  for (;;) {
+    enqueue(std::min(AHEAD, itermax - enq));
+    hip_check(hipEventSynchronize(c.guard_snap_ev[slot]), "wait for the guard");
+    hg = snap[slot];
     if (!hg.active) break;
-    base += (int64_t)hist.size() - 1;
-    NodeP last = hist.back();
-    hist.assign(1, last);
+    // passes before hg.iters are done with
+    const int64_t drop = (int64_t)hg.iters - base;
+    if (drop > 0 && drop < (int64_t)hist.size()) {
+      hist.erase(hist.begin(), hist.begin() + drop);
+      base = hg.iters;
+    }
     // The residual contracts about geometrically: predict the passes still
     // needed from the last two residuals (at least 1, at most what itermax
     // allows); an underestimate only costs one more check.
-    int next = check_every;
+    int need = check_every;
     if (hg.rho_prev > 0.0 && hg.rho > 0.0 && hg.rho < hg.rho_prev && tol > 0.0) {
       const double q = hg.rho / hg.rho_prev;
-      const double need = std::log(tol / hg.rho) / std::log(q);
-      if (need > 0.0 && need < 1e6) next = (int)std::ceil(need);
-      if (next < 1) next = 1;
+      const double pn = std::log(tol / hg.rho) / std::log(q);
+      if (pn > 0.0 && pn < 1e6) need = (int)std::ceil(pn);
+      if (need < 1) need = 1;
     }
-    if (next > itermax - hg.iters) next = itermax - hg.iters;
-    if (next < 1) next = 1;
-    batch = next;
+    // beyond the passes already queued after hg.iters
+    int next = need - (enq - hg.iters);
+    if (next > itermax - enq) next = itermax - enq;
+    if (next > 0) enqueue(next);
+    slot ^= 1;
+    snapshot();
   }
   if (hg.bad) fail(GrB_PANIC, "pagerank: a residual or dangling mass was not finite (NaN or Inf in the iterate)");
   const int64_t idx = (int64_t)hg.iters - base;

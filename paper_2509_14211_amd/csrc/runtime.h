@@ -295,6 +295,10 @@ struct Ctx {
   unsigned long long many_wait_ticks = 1000000000ull;
   // plan configuration override chosen by the autotuner (per matrix id)
   std::map<std::pair<uint64_t, int>, PlanConfig> tuned;
+  // two pinned host slots for copies of the loop guard, each with the event
+  // that marks its copy done (created on first use)
+  GuardDev* guard_snap = nullptr;
+  hipEvent_t guard_snap_ev[2] = {nullptr, nullptr};
 };
 
 Ctx& ctx();
