@@ -323,6 +323,7 @@ GrB_Info GrB_finalize(void) {
   if (c.guard_snap) (void)hipHostFree(c.guard_snap);
   c.guard_snap = nullptr;
   c.tuned.clear();
+  c.dinv_cache.clear();
   c.init = false;
   for (auto& kv : c.cache)
     for (void* p : kv.second) raw_release(p);

@@ -18,6 +18,35 @@ extern "C" {
 
 // ------------------------------------------------------------ PageRank
 
+// d = damping ./ outdeg (0 where outdeg = 0) in the execution order of
+// A_exec (the out-degree vector permuted by rl when the plan renumbers),
+// materialised.  Solves on the same matrix, out-degree vector, damping and
+// type share it: the context keeps the last few.
+static NodeP damping_over_outdeg(const MatP& A_exec, const std::shared_ptr<Relabeled>& rl,
+                                 GB_Vector_opaque* dego, int T, double damping) {
+  Ctx& c = ctx();
+  uint64_t dbits = 0;
+  std::memcpy(&dbits, &damping, sizeof dbits);
+  const auto key = std::make_tuple(A_exec->id, dego->node->id, dbits, T);
+  auto it = c.dinv_cache.find(key);
+  if (it != c.dinv_cache.end()) return it->second;
+  const int64_t n = dego->n;
+  GB_Vector_opaque deg_exec{MAGIC_VEC, dego->type, n, nullptr};
+  set_vec(&deg_exec, rl ? permuted(dego->node, rl->order) : dego->node);
+  GB_Vector_opaque dinv{MAGIC_VEC, T, n, nullptr};
+  rec_unop(&dinv, U_MINV_OR_ZERO, &deg_exec);
+  rec_bind(&dinv, B_TIMES, &dinv, damping, true);
+  set_vec(&deg_exec, nullptr);
+  materialize(dinv.node);
+  require_full(dinv.node, "the PageRank out-degree vector");
+  store_if_iso(dinv.node);
+  NodeP d = dinv.node;
+  set_vec(&dinv, nullptr);
+  if (c.dinv_cache.size() >= 4) c.dinv_cache.erase(c.dinv_cache.begin());
+  c.dinv_cache[key] = d;
+  return d;
+}
+
 // The context's two pinned guard-copy slots and their events.
 static GuardDev* guard_snapshots() {
   Ctx& c = ctx();
@@ -73,17 +102,9 @@ static GrB_Info pagerank_impl(GrB_Vector r, int* iters, double* resid, GrB_Matri
     c.tuned[{rl->A->id, T}] = sub;
   }
 
-  GB_Vector_opaque deg_exec{MAGIC_VEC, dego->type, n, nullptr};
-  set_vec(&deg_exec, rl ? permuted(dego->node, rl->order) : dego->node);
-
   // d = damping ./ outdeg (0 where outdeg = 0)
   GB_Vector_opaque dinv{MAGIC_VEC, T, n, nullptr};
-  rec_unop(&dinv, U_MINV_OR_ZERO, &deg_exec);
-  rec_bind(&dinv, B_TIMES, &dinv, damping, true);
-  set_vec(&deg_exec, nullptr);
-  materialize(dinv.node);
-  require_full(dinv.node, "the PageRank out-degree vector");
-  store_if_iso(dinv.node);
+  set_vec(&dinv, damping_over_outdeg(A_exec.data, rl, dego, T, damping));
 
   // personalised teleport distribution (permuted like every vector)
   GB_Vector_opaque v{MAGIC_VEC, T, n, nullptr};
@@ -343,16 +364,9 @@ struct PprColumns {
     grid = plan->cfg.grid;
 
     // d = damping ./ outdeg (0 for dangling), in execution order
-    GB_Vector_opaque deg_exec{MAGIC_VEC, dego->type, n, nullptr};
-    set_vec(&deg_exec, rl ? permuted(dego->node, rl->order) : dego->node);
     dinv.type = T;
     dinv.n = n;
-    rec_unop(&dinv, U_MINV_OR_ZERO, &deg_exec);
-    rec_bind(&dinv, B_TIMES, &dinv, damping, true);
-    set_vec(&deg_exec, nullptr);
-    materialize(dinv.node);
-    require_full(dinv.node, "the PageRank out-degree vector");
-    store_if_iso(dinv.node);
+    set_vec(&dinv, damping_over_outdeg(A_exec, rl, dego, T, damping));
 
     vbytes = type_size(T) * (size_t)n * (size_t)k;
     for (int i = 0; i < 2; ++i) {

@@ -299,6 +299,9 @@ struct Ctx {
   // that marks its copy done (created on first use)
   GuardDev* guard_snap = nullptr;
   hipEvent_t guard_snap_ev[2] = {nullptr, nullptr};
+  // damping ./ outdeg in execution order, per (execution matrix, out-degree
+  // vector node, damping bits, type)
+  std::map<std::tuple<uint64_t, uint64_t, uint64_t, int>, NodeP> dinv_cache;
 };
 
 Ctx& ctx();
