@@ -151,3 +151,33 @@ def test_autotune_cache_roundtrip(nonblocking, tmp_path):
         grb.GrM_Matrix_plan_set(h.AT, f64, None)
         h.free()
     assert os.path.exists(path)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_guard_reads_do_not_change_the_solve(nonblocking, oracle_mod, dtype):
+    """The drivers read the loop guard every check_every passes and keep two
+    passes queued behind each read; those passes are skipped on the device
+    once the residual reached tol or itermax passes ran.  Every cadence
+    gives the same pass count, residual and ranks as checking once at the
+    end, the ranks are those of the oracle after that many passes, and no
+    more than itermax passes run."""
+    from paper_2509_14211_amd import api
+    grb = nonblocking
+    g = api.rmat_graph(11)
+    og = oracle_mod.rmat_graph(11)
+    tol = 1e-6 if dtype == torch.float32 else 1e-10
+    for itermax in (0, 1, 2, 3, 7, 1000):
+        ref_x, ref_it, ref_res = api.pagerank(g, dtype, tol=tol, itermax=itermax, check_every=1000)
+        assert ref_it <= itermax
+        # no pass: the start vector (every entry 1/n)
+        want = (oracle_mod.pagerank(og, 0.85, fixed_iters=ref_it, mode=1).x if ref_it > 0
+                else np.full(g.n, 1.0 / g.n))
+        ref_np = ref_x.cpu().numpy().astype(np.float64)
+        bound = 1e-5 if dtype == torch.float32 else 1e-12
+        assert np.abs(ref_np - want).sum() <= bound * max(1.0, np.abs(want).sum())
+        for check_every in (1, 2, 3, 5, 8):
+            print("itermax", itermax, "check_every", check_every, dtype, flush=True)
+            x, it, res = api.pagerank(g, dtype, tol=tol, itermax=itermax, check_every=check_every)
+            assert it == ref_it and res == ref_res
+            assert torch.equal(x, ref_x)
+    g.free()
