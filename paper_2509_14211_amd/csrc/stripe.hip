@@ -515,15 +515,20 @@ __global__ __launch_bounds__(512) void cold_fill_kernel(ColdFillDev f, const flo
       const unsigned s0 = ch.start + j * FILL_SUB, s1 = min(s0 + FILL_SUB, ch.end);
       unsigned run = f.sub_run[ch.sub0 + j] - 1u;  // s0 starts a run
       unsigned first = s0;
-      // U groups of 64 entries at a time: their loads are in flight together
+      // U groups of 64 entries at a time: their loads are in flight
+      // together, and the next U groups' columns load while these groups'
+      // run slots are read and their values stored (two register sets
+      // alternate, so neither is copied while its loads are in flight)
       constexpr int U = 8;
-      for (unsigned g0 = s0; g0 < s1; g0 += 64 * U) {
-        unsigned word[U], my_run[U], my_first[U], rp[U];
+      auto load_words = [&](unsigned g0, unsigned (&word)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const unsigned e = g0 + 64u * u + lane;
           word[u] = e < s1 ? (unsigned)f.src[e] : 0u;
         }
+      };
+      auto place = [&](unsigned g0, const unsigned (&word)[U]) {
+        unsigned my_run[U], my_first[U], rp[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const unsigned e0 = g0 + 64u * u;
@@ -541,6 +546,16 @@ __global__ __launch_bounds__(512) void cold_fill_kernel(ColdFillDev f, const flo
           const unsigned e = g0 + 64u * u + lane;
           if (e < s1) f.val[rp[u] + (e - my_first[u])] = win[word[u] & 0x3FFFu];
         }
+      };
+      constexpr unsigned GS = 64u * U;
+      unsigned wa[U], wb[U];
+      load_words(s0, wa);
+      for (unsigned g0 = s0; g0 < s1; g0 += 2 * GS) {
+        if (g0 + GS < s1) load_words(g0 + GS, wb);
+        place(g0, wa);
+        if (g0 + GS >= s1) break;
+        if (g0 + 2 * GS < s1) load_words(g0 + 2 * GS, wa);
+        place(g0 + GS, wb);
       }
     }
   }
