@@ -212,7 +212,7 @@ struct StripePlanDev {
 // starts at slot run_pos[r].  Chunks are cut into sub-chunks of
 // FILL_SUB entries, each starting a run; sub-chunk j of chunk c has run
 // index sub_run[c.sub0 + j] at its first entry.
-constexpr unsigned FILL_SUB = 4096;
+constexpr unsigned FILL_SUB = 2048;
 struct ColdChunk {
   int blk;
   unsigned start, end, sub0;

@@ -896,7 +896,7 @@ int64_t pad8(int64_t x) { return (x + 7) & ~(int64_t)7; }
 
 namespace {
 
-constexpr unsigned FILL_CHUNK = 32768;  // fill-list entries per chunk at most
+constexpr unsigned FILL_CHUNK = 16384;  // fill-list entries per chunk at most
 
 // The two-phase part of a stripe plan: each stripe's gathered entries
 // regrouped by column block, the fill list (entries by column block, then
