@@ -322,6 +322,10 @@ GrB_Info GrB_finalize(void) {
   }
   if (c.guard_snap) (void)hipHostFree(c.guard_snap);
   c.guard_snap = nullptr;
+  if (c.ppr_snap_ev) (void)hipEventDestroy(c.ppr_snap_ev);
+  c.ppr_snap_ev = nullptr;
+  if (c.ppr_snap) (void)hipHostFree(c.ppr_snap);
+  c.ppr_snap = nullptr;
   c.tuned.clear();
   c.dinv_cache.clear();
   c.init = false;

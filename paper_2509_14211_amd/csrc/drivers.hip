@@ -524,6 +524,32 @@ struct PprColumns {
     hip_check(launch_spmm_ppr(plan->dev, a, T, grid, a.guard, c.stream), "ppr pass");
     launch_mark(true);
   }
+
+  // The per-column converged pass and residual and the guard after the
+  // passes queued so far: copied into pinned host memory with one wait.
+  void read_state(std::vector<int>& hh, std::vector<double>& rr, GuardDev& hg) {
+    struct Snap {
+      int hit[64];
+      double rho[64];
+      GuardDev g;
+    };
+    Ctx& c = ctx();
+    if (!c.ppr_snap) {
+      void* p = nullptr;
+      hip_check(hipHostMalloc(&p, sizeof(Snap), hipHostMallocDefault), "pinned check slot");
+      c.ppr_snap = p;
+    }
+    if (!c.ppr_snap_ev) hip_check(hipEventCreateWithFlags(&c.ppr_snap_ev, hipEventDisableTiming), "event");
+    Snap* sn = (Snap*)c.ppr_snap;
+    hip_check(hipMemcpyAsync(sn->hit, hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+    hip_check(hipMemcpyAsync(sn->rho, rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
+    hip_check(hipMemcpyAsync(&sn->g, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
+    hip_check(hipEventRecord(c.ppr_snap_ev, c.stream), "event record");
+    hip_check(hipEventSynchronize(c.ppr_snap_ev), "wait for the check");
+    hh.assign(sn->hit, sn->hit + 64);
+    rr.assign(sn->rho, sn->rho + 64);
+    hg = sn->g;
+  }
 };
 
 }  // namespace
@@ -594,10 +620,7 @@ GrB_Info GrM_ppr_batch(void* X, GrB_Type type, int k, const int32_t* seed_ptr, c
   int pass = 0, batch = check_every;
   for (;;) {
     for (int j = 0; j < batch; ++j) pc.run_pass(++pass);
-    hip_check(hipMemcpyAsync(hh.data(), pc.hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
-    hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
-    hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
-    hip_check(hipStreamSynchronize(c.stream), "sync");
+    pc.read_state(hh, rr, hg);
     if (hg.bad) break;
     for (int col = 0; col < pc.k; ++col) {
       const int q = col_set[(size_t)col];
@@ -838,11 +861,8 @@ GrB_Info GrM_ppr_stream(void* X, GrB_Type type, int nsets, const int32_t* seed_p
     for (int col = 0; col < pc.k; ++col)
       if (slot_set[(size_t)col] >= 0) batch = std::min(batch, itermax - (pass - slot_start[(size_t)col]));
     for (int j = 0; j < std::max(batch, 1); ++j) pc.run_pass(++pass);
-    hip_check(hipMemcpyAsync(hh.data(), pc.hit->p, sizeof(int) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
-    hip_check(hipMemcpyAsync(rr.data(), pc.rho->p, sizeof(double) * 64, hipMemcpyDeviceToHost, c.stream), "copy");
     GuardDev hg{};
-    hip_check(hipMemcpyAsync(&hg, c.guard, sizeof(GuardDev), hipMemcpyDeviceToHost, c.stream), "read guard");
-    hip_check(hipStreamSynchronize(c.stream), "sync");
+    pc.read_state(hh, rr, hg);
     if (hg.bad) fail(GrB_PANIC, "ppr_stream: a column's residual or dangling mass was not finite");
     const int cur = pass & 1;
     uint64_t retired = 0, from1 = 0;

@@ -299,6 +299,10 @@ struct Ctx {
   // that marks its copy done (created on first use)
   GuardDev* guard_snap = nullptr;
   hipEvent_t guard_snap_ev[2] = {nullptr, nullptr};
+  // pinned host copy of a batched PPR check (per-column hit pass and
+  // residual, and the guard) and the event that marks it done
+  void* ppr_snap = nullptr;
+  hipEvent_t ppr_snap_ev = nullptr;
   // damping ./ outdeg in execution order, per (execution matrix, out-degree
   // vector node, damping bits, type)
   std::map<std::tuple<uint64_t, uint64_t, uint64_t, int>, NodeP> dinv_cache;
