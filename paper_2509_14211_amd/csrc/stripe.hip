@@ -26,8 +26,9 @@
 //     overflow -- and integer addition makes the sum independent of the
 //     order in which lanes and wavefronts add.  Each lane first adds runs
 //     of equal rows among its own entries in registers.  Each term is
-//     truncated to the 2^-F grid (at most 2^-62 sum |w| per term) and the
-//     exact sum is rounded once to FP32.
+//     truncated to the 2^-F grid (at most 2^-62 sum |w| per term; F is
+//     capped at 126, so a vector with sum |w| below 2^-64 keeps a grid of
+//     2^-126) and the exact sum is rounded once to FP32.
 //   * Per row the epilogue is the usual one; it also publishes sum |w'| of
 //     the pre-scaled copy it writes (FP64), which the next pass uses for its
 //     scale.
@@ -82,18 +83,22 @@ __device__ __forceinline__ V block_sum_st(V v, V* red) {
   return r;
 }
 
-// v * 2^F as a two's-complement 64-bit integer, truncated toward zero, with
-// kshift = 188 - F.  v = mant * 2^(E - 150) (E the biased exponent, 1 for
-// subnormals), so v * 2^F = (mant << 38) >> (188 - F - E); the scale
-// guarantees a non-negative shift for every |v| <= sum |w|.
-__device__ __forceinline__ long long fixed_of(float v, int kshift) {
-  const unsigned b = __float_as_uint(v);
-  const int E = (int)((b >> 23) & 0xFFu);
-  const unsigned mant = (b & 0x7FFFFFu) | (E ? 0x800000u : 0u);
-  int sh = kshift - (E ? E : 1);
-  sh = sh < 0 ? 0 : (sh > 63 ? 63 : sh);
-  const unsigned long long q = ((unsigned long long)mant << 38) >> sh;
-  return (b >> 31) ? -(long long)q : (long long)q;
+// v * 2^F as a two's-complement 64-bit integer, truncated toward zero,
+// with fm32 = F - 32.  y = |v| * 2^(F-32) is exact (a power-of-two
+// scaling; where y would be subnormal, |v| * 2^F < 1 and the result is 0
+// either way), and since |v| * 2^F < 2^62, y < 2^30: the high word is
+// floor(y) and the low word floor(frac(y) * 2^32), both exact conversions;
+// the sign is applied to the 64-bit pair.  With F <= 126 a subnormal v
+// gives 0, as v * 2^F < 1, so this is the exact truncation for every
+// float (checked against the bit-level form mant * 2^(E - 150) shifted
+// into place, on every exponent, both signs, zeros and subnormals).
+__device__ __forceinline__ long long fixed_of(float v, int fm32) {
+  const float y = __builtin_amdgcn_ldexpf(__builtin_fabsf(v), fm32);
+  const unsigned hi = (unsigned)y;
+  const unsigned lo = (unsigned)__builtin_amdgcn_ldexpf(__builtin_amdgcn_fractf(y), 32);
+  const unsigned long long q = ((unsigned long long)hi << 32) | lo;
+  const unsigned long long sg = (unsigned long long)(long long)((int)__float_as_uint(v) >> 31);
+  return (long long)((q ^ sg) - sg);
 }
 
 // Adds a lane's entries into the LDS row sums: runs of equal rows are
@@ -103,7 +108,7 @@ __device__ __forceinline__ long long fixed_of(float v, int kshift) {
 // the last row decide that; otherwise every row is compared.
 template <int K, bool SORTED>
 __device__ __forceinline__ void add_runs(unsigned long long* acc, const int (&row)[K], const float (&v)[K],
-                                         int kshift) {
+                                         int fm32) {
   const int first = lane_value(row[0], 0);
   bool one_row;
   if constexpr (SORTED) {
@@ -117,13 +122,13 @@ __device__ __forceinline__ void add_runs(unsigned long long* acc, const int (&ro
   if (one_row) {
     long long s = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) s += fixed_of(v[k], kshift);
+    for (int k = 0; k < K; ++k) s += fixed_of(v[k], fm32);
     s = wave_sum64(s);
     if ((threadIdx.x & 63) == 0) atomicAdd(&acc[first], (unsigned long long)s);
     return;
   }
   int cur = row[0];
-  long long s = fixed_of(v[0], kshift);
+  long long s = fixed_of(v[0], fm32);
 #pragma unroll
   for (int k = 1; k < K; ++k) {
     if (row[k] != cur) {
@@ -131,7 +136,7 @@ __device__ __forceinline__ void add_runs(unsigned long long* acc, const int (&ro
       cur = row[k];
       s = 0;
     }
-    s += fixed_of(v[k], kshift);
+    s += fixed_of(v[k], fm32);
   }
   atomicAdd(&acc[cur], (unsigned long long)s);
 }
@@ -239,7 +244,7 @@ __device__ __forceinline__ void cold_gather(__amdgpu_buffer_rsrc_t rw, ColdRegs&
 // plan, entries grouped by column block, rows ascending only within a
 // group); otherwise they were gathered into R.v.
 template <bool PF>
-__device__ __forceinline__ void cold_add(unsigned long long* acc, const ColdRegs& R, int kshift) {
+__device__ __forceinline__ void cold_add(unsigned long long* acc, const ColdRegs& R, int fm32) {
   const int row[STRIPE_K] = {(int)(R.rr.x & 0xFFFFu), (int)(R.rr.x >> 16), (int)(R.rr.y & 0xFFFFu),
                              (int)(R.rr.y >> 16),     (int)(R.rr.z & 0xFFFFu), (int)(R.rr.z >> 16),
                              (int)(R.rr.w & 0xFFFFu), (int)(R.rr.w >> 16)};
@@ -247,9 +252,9 @@ __device__ __forceinline__ void cold_add(unsigned long long* acc, const ColdRegs
     const float v[STRIPE_K] = {__uint_as_float(R.ca.x), __uint_as_float(R.ca.y), __uint_as_float(R.ca.z),
                                __uint_as_float(R.ca.w), __uint_as_float(R.cb.x), __uint_as_float(R.cb.y),
                                __uint_as_float(R.cb.z), __uint_as_float(R.cb.w)};
-    add_runs<STRIPE_K, false>(acc, row, v, kshift);
+    add_runs<STRIPE_K, false>(acc, row, v, fm32);
   } else {
-    add_runs<STRIPE_K, true>(acc, row, R.v, kshift);
+    add_runs<STRIPE_K, true>(acc, row, R.v, fm32);
   }
 }
 
@@ -285,7 +290,9 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
   if (pr) c = (float)scalar_value(a.c);
 
   // fixed-point scale: 2^(62-F) >= sum |w|.  Every partial sum of a row
-  // adds distinct entries of w, so its magnitude is at most sum |w|.
+  // adds distinct entries of w, so its magnitude is at most sum |w|.  F is
+  // capped at 126 (a vector whose sum |w| is below 2^-64 keeps a grid of
+  // 2^-126, the smallest normal FP32 value).
   const double wsum = *wsum_in;
   const bool finite = __builtin_isfinite(wsum);
   int F = 62;
@@ -294,7 +301,8 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
     (void)frexp(wsum, &k);  // wsum < 2^k
     F = 62 - k;
   }
-  const int kshift = 188 - F;
+  if (F > 126) F = 126;
+  const int fm32 = F - 32;
   const double unscale = ldexp(1.0, -F);
 
   const __amdgpu_buffer_rsrc_t rw = buf_rsrc(a.w, (unsigned)a.ncols * 4u);
@@ -348,7 +356,7 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
         auto step = [&](int i, ColdRegs& P, ColdRegs& G, ColdRegs& F) {
           cold_indices<SP>(rcc, rcr, wv + (i + 2) * NW, lane, F);
           if constexpr (!PF) cold_gather(rw, G);
-          cold_add<PF>(acc, P, kshift);
+          cold_add<PF>(acc, P, fm32);
         };
         for (int i = 0;;) {
           step(i, X, Y, Z);
@@ -381,7 +389,7 @@ __global__ __launch_bounds__(STRIPE_BLOCK) void fused_stripe_kernel(StripePlanDe
           row[k] = (int)(wd[k] >> 16);
           v[k] = hbuf[wd[k] & 0xFFFFu];
         }
-        add_runs<STRIPE_K, true>(acc, row, v, kshift);
+        add_runs<STRIPE_K, true>(acc, row, v, fm32);
         cur = nx;
       }
       wait_block();  // this wavefront's part of block kblk + 1 is in LDS
