@@ -497,6 +497,15 @@ namespace {
 // chunk's column block of w goes to LDS, then each entry's value to its
 // slot (the list is ordered by slot within a block, so the writes run
 // along each stripe's group of entries from that block).
+//
+// Consecutive chunks mostly share a column block.  Workgroup g runs on XCD
+// g mod 8, so with a grid that is a multiple of 8·FILL_GROUP each round of
+// gridDim.x chunks is dealt out in groups of FILL_GROUP consecutive chunks,
+// group i to the workgroups of XCD i mod 8: a block then comes from memory
+// into one or two XCDs' L2 instead of into most of them.  Any assignment
+// gives the same values (each chunk writes only its own slots).
+constexpr int FILL_GROUP = 8;
+
 __global__ __launch_bounds__(512) void cold_fill_kernel(ColdFillDev f, const float* __restrict__ w, int ncols,
                                                         const GuardDev* guard) {
   constexpr int NWF = 512 / 64;
@@ -504,7 +513,12 @@ __global__ __launch_bounds__(512) void cold_fill_kernel(ColdFillDev f, const flo
   __shared__ __attribute__((aligned(16))) float win[STRIPE_HB];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const unsigned long long le = (2ull << lane) - 1ull;  // lanes up to and including this one
-  for (int c = blockIdx.x; c < f.nchunks; c += gridDim.x) {
+  int c0 = blockIdx.x;
+  if ((gridDim.x % (8 * FILL_GROUP)) == 0) {
+    const int x = blockIdx.x & 7, k = blockIdx.x >> 3;  // XCD, and rank among its workgroups
+    c0 = ((k / FILL_GROUP) * 8 + x) * FILL_GROUP + k % FILL_GROUP;
+  }
+  for (int c = c0; c < f.nchunks; c += gridDim.x) {
     const ColdChunk ch = f.chunk[c];
     const int b0 = ch.blk * STRIPE_HB;
     const int cnt = min(STRIPE_HB, ncols - b0);
